@@ -575,17 +575,32 @@ def test_golden_storage_and_cases():
 
 def test_swirl_direction_matches_analytic_field(O):
     """u = (sin^2(pi x) sin(2 pi y), -sin^2(pi y) sin(2 pi x)) cos(pi t / T):
-    a narrow blob at (0.25, 0.25) starts moving along (0.5, -0.5)."""
+    the centroid of a narrow blob follows the characteristic of that field
+    (integrated here with RK4), within 5% of its displacement."""
     L = S.uniform_leaves(3)
     mx = 16
     q0 = S.sample_on_leaves(lambda x, y: np.exp(-((x - 0.25) ** 2 + (y - 0.25) ** 2) / 0.03 ** 2), L, mx)
     o = O.Oracle(L, mx=mx, velocity="swirl", vel_params=(1.0, 0, 0))
     o.set_interior(q0)
     dt = 0.9 / 128
-    for s in range(10):
+    nst = 10
+    for s in range(nst):
         o.coarse_step(s * dt, dt)
     x, y = centres(L, mx)
     q = o.interior()
-    cx, cy = (q * x).sum() / q.sum(), (q * y).sum() / q.sum()
-    T = 10 * dt
-    assert abs((cx - 0.25) / T - 0.5) < 0.05 and abs((cy - 0.25) / T + 0.5) < 0.05
+    c = np.array([(q * x).sum() / q.sum(), (q * y).sum() / q.sum()])
+
+    def vel(t, p):
+        X, Y = p
+        f = np.cos(np.pi * t)
+        return np.array([np.sin(np.pi * X) ** 2 * np.sin(2 * np.pi * Y) * f,
+                         -np.sin(np.pi * Y) ** 2 * np.sin(2 * np.pi * X) * f])
+    p = np.array([0.25, 0.25])
+    hs = nst * dt / 100
+    for k in range(100):
+        t = k * hs
+        k1 = vel(t, p); k2 = vel(t + hs / 2, p + hs / 2 * k1)
+        k3 = vel(t + hs / 2, p + hs / 2 * k2); k4 = vel(t + hs, p + hs * k3)
+        p = p + hs / 6 * (k1 + 2 * k2 + 2 * k3 + k4)
+    disp = np.linalg.norm(p - 0.25)
+    assert np.linalg.norm(c - p) < 0.05 * disp, (c, p)
