@@ -1,0 +1,181 @@
+"""Benchmark: cell-updates/s of the AMR advance + ghost fill on one MI355X.
+
+Workload (default): uniform level 5 of the unit square, 1024 patches of
+32x32 cells with 2 ghost layers, FP64 scalar advection in the swirling
+deformational field, seeded sum of 8 Gaussians, 500 steps.  A "step" is
+one coarse step of the whole path: ghost fill + advance of every patch.
+
+The headline uses the fused form: one persistent kernel per coarse step
+(ghosts gathered on the fly, device-wide barriers between level-steps)
+replayed from a hipGraph.  The plain per-level launch form (a fill launch
+and an advance launch per level-step) is timed on the same workload and
+reported beside it.
+
+Output: one JSON line on stdout.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell-updates/sec (advance+ghost fill) at 1 GPU; % HBM roofline; fused vs per-level"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_1703_03116_amd/csrc/fc_kernels.hip", "paper_1703_03116_amd/csrc/fc_internal.h"]
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, p), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(npatch, mx, F):
+    """Read every patch tile with its halo once, write its interior once."""
+    N = mx + 4
+    return npatch * F * 8 * (N * N + mx * mx)
+
+
+def traffic_from_profiles(bytes_per_launch_alg):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", "traffic_persistent_swirl_l5.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("kernel_sha") != kernel_hash():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(w, budget_s=15.0):
+    """The oracle, as is, on a bounded sample of the same workload."""
+    from oracle import oracle as O
+    nth = min(os.cpu_count() or 1, 16)
+    O.set_threads(nth)
+    o = O.from_workload(w)
+    dt = w["dt_coarse"]
+    cells = len(w["leaves"]) * w["mx"] ** 2
+    t0 = time.perf_counter()
+    o.coarse_step(0.0, dt)
+    one = time.perf_counter() - t0
+    n = max(1, min(w["steps"] - 1, int(budget_s / max(one, 1e-6))))
+    t0 = time.perf_counter()
+    for s in range(n):
+        o.coarse_step((s + 1) * dt, dt)
+    el = time.perf_counter() - t0
+    return {"value": cells * n / el, "unit": "cell-updates/s", "cores": O.max_threads(), "kind": "oracle",
+            "sample": f"{n} steps of the same {len(w['leaves'])}-patch workload (after 1 untimed step)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--level", type=int, default=5)
+    ap.add_argument("--mx", type=int, default=32)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-per-level", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU exchange is a design, not part of this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1703_03116_amd import binding as B
+    from workloads import synth as S
+
+    torch.cuda.set_device(0)
+    w = S.workload("swirl_uniform", level=args.level, mx=args.mx, steps=args.steps)
+    P, mx, F = len(w["leaves"]), w["mx"], 1
+    dt = w["dt_coarse"]
+    cells_per_step = P * mx * mx
+    ps = B.from_workload(w)
+    nt = ps.autotune()
+    stream = torch.cuda.current_stream()
+
+    def timed(mode, k):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ps.coarse_steps(dt, k, mode)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3
+
+    ps.coarse_steps(dt, args.warmup, "graph")
+    sec = timed("graph", args.steps)
+    ps.check()
+    value = cells_per_step * args.steps / sec
+
+    # per-launch durations of the persistent kernel on the launch stream
+    durs = []
+    for _ in range(min(args.steps, 200)):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        ps.coarse_steps(dt, 1, "graph")
+        b.record(stream)
+        durs.append((a, b))
+    torch.cuda.synchronize()
+    avg_launch = sum(a.elapsed_time(b) for a, b in durs) / len(durs) / 1e3
+    bpl = algorithmic_bytes(P, mx, F)
+    achieved = bpl / avg_launch / 1e9
+    traffic = traffic_from_profiles(bpl)
+
+    per_level = None
+    if not args.no_per_level:
+        ps2 = B.from_workload(w)
+        ps2.set_variant(nt)
+        ps2.coarse_steps(dt, args.warmup, "per_level")
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ps2.coarse_steps(dt, args.steps, "per_level")
+        e1.record(stream)
+        torch.cuda.synchronize()
+        s2 = e0.elapsed_time(e1) / 1e3
+        per_level = {"value": cells_per_step * args.steps / s2, "ms_per_step": 1e3 * s2 / args.steps,
+                     "launches_per_step": 2}
+        del ps2
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(w)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * sec / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"swirl_uniform_l{args.level}: {P} patches of {mx}x{mx} cells, 2 ghost layers, "
+                               f"FP64 scalar advection, swirl field T=1, seeded 8-Gaussian data, "
+                               f"{args.steps} steps",
+                   "patches": P, "mx": mx, "cells": cells_per_step, "mode": "fused persistent kernel + hipGraph",
+                   "threads_per_patch": nt},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "persistent_scalar_kernel", "bytes_per_launch": bpl,
+                     "avg_launch_ms": 1e3 * avg_launch},
+        "per_level": per_level,
+        "fused_over_per_level": (value / per_level["value"]) if per_level else None,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,204 @@
+/*
+ * fc.h -- C ABI of the MI355X (gfx950) patch-based quadtree AMR library.
+ *
+ * The method is that of Calhoun & Burstedde, "ForestClaw: a parallel
+ * algorithm for patch-based adaptive mesh refinement on a forest of
+ * quadtrees" (arXiv:1703.03116): fixed mx x mx patches with m ghost layers
+ * on the leaves of a 2:1 balanced quadtree (Sec. 2), ghost regions filled by
+ * copying from same-size neighbours, averaging fine neighbours (eq.
+ * ghost_coarse) and limited interpolation from coarse neighbours (eq.
+ * ghost_fine) in the order of Algorithm 1 (Sec. 2.2), a single-grid
+ * wave-propagation update per patch (Sec. 5), tagging and regridding
+ * (Sec. 4.1) and multirate time stepping (the paper's time-stepping
+ * section).
+ *
+ * Conventions for every entry point:
+ *   - Return FC_OK (0) or a negative fc_status; no exception crosses the
+ *     ABI.  fc_last_error() returns a message for the calling thread's last
+ *     failure.
+ *   - Errors detectable on the host (bad arguments, unbalanced mesh, ghost
+ *     width, capacity, wrong state) are returned before anything is queued.
+ *     Device faults surface as FC_ERR_HIP from the call that observes them.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Device work is queued on it and is asynchronous unless stated.
+ *   - Pointers marked "device" must be device memory owned by the caller;
+ *     the library never frees them.  Pointers marked "host" are read during
+ *     the call only.
+ *   - A store is not thread-safe; distinct stores are independent.
+ *
+ * Patch data layout in device memory (the "patch store"): two buffers of
+ * nfields x capacity x N x N doubles, N = mx + 2 mbc, field-major (SoA),
+ * x fastest; slot p holds the patch whose store index is p.  Stores are
+ * ordered by level, then by Morton (Z-order) index inside a level (Sec. 2).
+ * Which buffer holds the current state of a level alternates with each
+ * advance of that level; fc_set_interior / fc_get_interior hide this.
+ */
+#ifndef FC_H
+#define FC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t fc_status;
+enum {
+    FC_OK = 0,
+    FC_ERR_ARG = -1,          /* invalid argument                                   */
+    FC_ERR_UNBALANCED = -2,   /* leaves not 2:1 balanced over faces and corners      */
+    FC_ERR_GHOST_WIDTH = -3,  /* m > mx/4 or mx odd: Prop. 2.1 condition violated     */
+    FC_ERR_HIP = -4,          /* a HIP runtime call failed                            */
+    FC_ERR_CFL = -5,          /* reserved: the binding reports CFL > cfl_max          */
+    FC_ERR_STATE = -6,        /* call out of order (e.g. not bound)                   */
+    FC_ERR_CAPACITY = -7,     /* more leaves than the store's capacity                */
+    FC_ERR_COVER = -8         /* leaves overlap or do not tile the unit square        */
+};
+
+enum { FC_EQ_ADVECTION = 0, FC_EQ_SWE = 1 };
+enum { FC_BC_PERIODIC = 0, FC_BC_REFLECT = 1 };
+enum { FC_VEL_NONE = 0, FC_VEL_CONSTANT = 1, FC_VEL_SWIRL = 2 };
+enum { FC_LIM_MC = 0, FC_LIM_LW = 1, FC_LIM_FIRST = 2, FC_LIM_MINMOD = 3 };
+enum { FC_STEP_MULTIRATE = 0, FC_STEP_GLOBAL = 1 };
+enum { FC_MODE_PER_LEVEL = 0, FC_MODE_FUSED = 1, FC_MODE_FUSED_GRAPH = 2 };
+
+/* A quadrant of the single unit-square block: 0 <= ix, iy < 2^level. */
+typedef struct { int32_t level, ix, iy; } fc_leaf;
+
+typedef struct {
+    int32_t mx;            /* interior cells per patch edge: 8, 16 or 32            */
+    int32_t mbc;           /* ghost layers m; the scheme needs 2; Prop. 2.1: m<=mx/4 */
+    int32_t equation;      /* FC_EQ_ADVECTION (1 field) or FC_EQ_SWE (h, hu, hv)     */
+    int32_t limiter;       /* FC_LIM_*                                               */
+    int32_t bc[4];         /* x-lo, x-hi, y-lo, y-hi: FC_BC_PERIODIC | FC_BC_REFLECT */
+    int32_t velocity;      /* advection: FC_VEL_CONSTANT (u,v) | FC_VEL_SWIRL (T)    */
+    double vel_params[3];  /* constant: (u, v, -); swirl: (T, -, -)                  */
+    double gravity;        /* shallow water g                                        */
+    int32_t min_level;     /* coarsest level of the multirate recursion              */
+    int32_t max_level;     /* finest level allowed (regridding caps refinement here) */
+    int32_t time_stepping; /* FC_STEP_MULTIRATE | FC_STEP_GLOBAL                     */
+    int32_t reserved;
+    int64_t capacity;      /* patch slots; >= number of leaves; regrid up to this    */
+} fc_config;
+
+typedef struct fc_patchstore fc_patchstore;
+
+/* Last error message of the calling thread ("" if none).  Static storage. */
+const char *fc_last_error(void);
+
+/* Create a store for a leaf set (host array, any order).  Validates: leaves
+ * in range, tiling of the unit square, 2:1 balance over faces and corners
+ * with periodic wrap where periodic (Sec. 2), mbc >= 2 and 4 mbc <= mx (Prop.
+ * 2.1), nleaves <= capacity.  perm_out (host, may be NULL) receives, for
+ * each input leaf k, its store index.  Host memory only is allocated. */
+fc_status fc_patchstore_create(const fc_config *cfg, int64_t nleaves, const fc_leaf *leaves,
+                               fc_patchstore **out, int64_t *perm_out);
+fc_status fc_patchstore_destroy(fc_patchstore *ps);
+
+/* Sizes of the caller-owned device memory: q_doubles = doubles per patch
+ * buffer (nfields * capacity * N * N; two such buffers are needed) and
+ * ws_bytes = workspace bytes (metadata, velocity tables, schedule, state). */
+fc_status fc_patchstore_sizes(const fc_patchstore *ps, int64_t *q_doubles, int64_t *ws_bytes);
+
+/* Bind caller-owned device memory (q0, q1: q_doubles each; workspace:
+ * ws_bytes, 256-byte aligned) and upload the metadata on `stream`.  The
+ * memory is borrowed until destroy or the next bind. */
+fc_status fc_patchstore_bind(fc_patchstore *ps, double *q0, double *q1, void *workspace, void *stream);
+
+/* Number of leaves, the store's leaves in store order (host array of
+ * nleaves), and the levels' current times. */
+fc_status fc_patchstore_info(const fc_patchstore *ps, int64_t *nleaves, int32_t *min_level,
+                             int32_t *max_level);
+fc_status fc_patchstore_leaves(const fc_patchstore *ps, fc_leaf *out);
+
+/* Interior data in input-leaf order, device arrays [nleaves][nfields][mx][mx]
+ * (the order of the leaves passed to create or to the last regrid). */
+fc_status fc_set_interior(fc_patchstore *ps, const double *src, void *stream);
+fc_status fc_get_interior(fc_patchstore *ps, double *dst, void *stream);
+/* Whole current patch arrays including ghosts, [nleaves][nfields][N][N]. */
+fc_status fc_get_patches(fc_patchstore *ps, double *dst, void *stream);
+
+/* Ghost filling (Algorithm 1): fill every ghost cell of the patches with
+ * level in [level_lo, level_hi] in the current buffers.  Levels >= level_lo
+ * are synchronised; level_lo - 1 is read at time fraction `alpha` of its
+ * last step: alpha == 1 reads its current state, otherwise
+ * q_old + alpha (q - q_old) (multirate time interpolation).  Copy from
+ * same-size neighbours and eq. ghost_coarse averaging from finer ones read
+ * interiors only; eq. ghost_fine interpolation from a coarser neighbour
+ * uses a minmod-limited one-sided gradient over the coarse 5-point stencil,
+ * whose ghost values are themselves evaluated by copy/averaging; reflecting
+ * walls mirror the data (negating the normal momentum), periodic sides
+ * wrap.  Exact parity with the four phases of Algorithm 1. */
+fc_status fc_ghost_fill(fc_patchstore *ps, int32_t level_lo, int32_t level_hi, double alpha,
+                        void *stream);
+
+/* One step of the unsplit wave-propagation scheme (Riemann fluctuations,
+ * limited second-order correction, transverse propagation, conservative
+ * update) on every patch of `level`, from time t by dt.  The ghosts of that
+ * level must be valid (fc_ghost_fill).  The level's current buffer flips;
+ * the previous state stays readable as q_old.  cfl_dev (device double, may
+ * be NULL) is max-accumulated with the step's Courant number. */
+fc_status fc_advance_level(fc_patchstore *ps, int32_t level, double t, double dt, double *cfl_dev,
+                           void *stream);
+
+/* One coarse step of the configured time stepping, from the store's time t
+ * by dt_coarse (multirate: level l takes 2^(l-min_level) steps of
+ * dt_coarse / 2^(l-min_level); global: every level one step of dt_coarse).
+ * mode FC_MODE_PER_LEVEL: a fill launch and an advance launch per
+ * level-step; FC_MODE_FUSED: one persistent kernel that evaluates ghosts on
+ * the fly and walks all level-steps with device-wide barriers;
+ * FC_MODE_FUSED_GRAPH: the fused kernel replayed from a captured hipGraph.
+ * nsteps coarse steps are taken.  cfl_dev as above.  The store's time
+ * advances by nsteps * dt_coarse. */
+fc_status fc_advance_coarse_steps(fc_patchstore *ps, double dt_coarse, int32_t nsteps, int32_t mode,
+                                  double *cfl_dev, void *stream);
+/* Store time (host value of the time all levels are synchronised at). */
+fc_status fc_get_time(const fc_patchstore *ps, double *t);
+fc_status fc_set_time(fc_patchstore *ps, double t);
+
+/* Tagging (Sec. 4.1): per patch, in input-leaf order, g = max over interior
+ * cells of |grad q| (central differences of field 0 divided by 2h; ghosts
+ * must be valid).  tags_dev[k] = +1 if g > tau_refine and level < max_level,
+ * -1 if g <= tau_coarsen and level > min_level, else 0.  gmax2_dev (may be
+ * NULL) receives g^2.  Device arrays of nleaves entries. */
+fc_status fc_tag_refine(fc_patchstore *ps, double tau_refine, double tau_coarsen, int8_t *tags_dev,
+                        double *gmax2_dev, void *stream);
+
+/* Adaptation on the host (Sec. 4.1): from tags in input-leaf order (host
+ * array), refine +1 leaves below max_level, replace a family of four
+ * sibling leaves by its parent when all four are tagged -1, then refine
+ * until 2:1 balanced.  Writes the new leaves sorted by (level, iy, ix) into
+ * out (host, room for cap leaves) and their count into n_out. */
+fc_status fc_adapt(const fc_patchstore *ps, const int8_t *tags, fc_leaf *out, int64_t cap,
+                   int64_t *n_out);
+
+/* Regrid (Sec. 4.1): replace the leaf set by new_leaves (host) and transfer
+ * the solution: unchanged leaves are copied, children are interpolated from
+ * their parent with the ghost-fill interpolation (fill ghosts first),
+ * parents are the mean of their four children.  All levels must be
+ * synchronised.  Afterwards "input-leaf order" is the order of new_leaves. */
+fc_status fc_regrid(fc_patchstore *ps, int64_t nleaves, const fc_leaf *new_leaves, void *stream);
+
+/* Adjoint of one uniform-level scalar step (fill by same-size copy, then
+ * advance): lambda_out = (J_adv J_fill)^T lambda_in with the limiter
+ * branches frozen at the step's input state q_in.  q_in, lambda_in,
+ * lambda_out: device arrays [nleaves][1][mx][mx] in input-leaf order.
+ * Uses the store's buffers as scratch (their contents are overwritten). */
+fc_status fc_adjoint_step(fc_patchstore *ps, int32_t level, double t, double dt, const double *q_in,
+                          const double *lambda_in, double *lambda_out, void *stream);
+
+/* Synchronise `stream` and report device-side errors raised since bind:
+ * a device-wide barrier that timed out (FC_ERR_HIP) or an interpolation
+ * stencil that needed a third level (FC_ERR_HIP; excluded by Prop. 2.1). */
+fc_status fc_check_device(fc_patchstore *ps, void *stream);
+
+/* Choose the launch configuration (waves per patch) of the advance kernels
+ * by timing every variant on the bound store (results are bitwise equal).
+ * Returns the chosen threads per patch. */
+fc_status fc_autotune(fc_patchstore *ps, int32_t *threads_out, void *stream);
+fc_status fc_set_variant(fc_patchstore *ps, int32_t threads_per_patch);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FC_H */

@@ -1,0 +1,119 @@
+// fc_internal.h -- structures shared by the host runtime and the gfx950
+// kernels of the AMR library.  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define FC_MAXLEV 24
+#define FC_NREC 12   // neighbour records per patch: 4 faces x 2 halves + 4 corners
+
+// Neighbour record types: what covers one ghost region of a patch.
+enum { NB_NONE = 0, NB_SAME = 1, NB_COARSE = 2, NB_FINE = 3 };
+
+// One ghost region (a face half or a corner) of a patch P at level l.  The
+// covering leaf `id` (a store slot) has its origin at P-local coordinates
+// (ox, oy), measured in level-l cells, periodic images already unwrapped:
+//   SAME:   neighbour-local cell = (i - ox, j - oy)
+//   COARSE: level-l index inside the coarse leaf = (i - ox, j - oy); the
+//           coarse cell is that >> 1, its parity selects d_k
+//   FINE:   fine cells 2 (i - ox) + {0,1}, 2 (j - oy) + {0,1}
+struct NbrRec {
+    int32_t type, id, ox, oy;
+};
+
+// Per-patch geometry.  walls: bit 0 x-lo, 1 x-hi, 2 y-lo, 3 y-hi are
+// reflecting walls touching this patch.
+struct PatchInfo {
+    int32_t level, ix, iy, walls;
+};
+
+// Regrid transfer plan for one new slot.
+enum { TR_COPY = 0, TR_REFINE = 1, TR_COARSEN = 2 };
+struct TransferRec {
+    int32_t kind, src[4], cx, cy, pad;
+};
+
+// One level-step of a coarse step: advance `level` (-1: every level, global
+// stepping) from t_base + off * dt_coarse by scale * dt_coarse, its coarser
+// neighbour level read at time fraction alpha.
+struct SchedEntry {
+    int32_t level, pad;
+    double off, scale, alpha;
+};
+
+// Device-resident state used by the persistent kernel (graph replays read
+// and update it, so replays need no host involvement).
+struct DevState {
+    double t;                  // time all levels are synchronised at
+    double dt_coarse;
+    unsigned long long cfl_bits;  // max Courant number (bits of a non-negative double)
+    uint32_t curmask;          // bit l: current buffer of level l
+    uint32_t bar_count, bar_gen;
+    int32_t err;               // bit 0: barrier spin limit hit; bit 1: stencil out of range
+    int32_t pad;
+};
+
+// Everything a kernel needs to read or evaluate patch data.
+struct Ctx {
+    double *q0, *q1;           // the two patch buffers [F][cap][N][N]
+    const PatchInfo *info;     // [cap]
+    const NbrRec *nbr;         // [cap][FC_NREC]
+    int32_t cap;               // slot stride inside a field plane
+    int32_t F, eq, lim;
+    uint32_t curmask;          // bit l: current buffer of level l
+    int32_t clevel;            // level read time-interpolated (-1: none)
+    double alpha;              // its time fraction (1: current state)
+    // per level, velocity factor tables (see vt_* below), NULL if unused
+    const double *vt[FC_MAXLEV];
+    int32_t velocity;
+    double vel_u, vel_v, vel_T, g;
+    int32_t *err;              // device error flags
+};
+
+// Velocity factor tables of one level with n = mx 2^l cells per axis and m
+// ghost layers, stored back to back (each indexed from -m):
+//   ex[I] = sin^2(pi x_I),        x edges  I in [-m, n+m]      (n+2m+1)
+//   cx[I] = sin(2 pi x_I) sigma,  x centres I in [-m, n+m)      (n+2m)
+//   ey, cy the same along y.  sigma = sin(pi h)/(pi h).  Indices wrap where
+// the axis is periodic.  Swirl: u(edge I, row J) = ex[I] cy[J] c(t),
+// v(col I, edge J) = -ey[J] cx[I] c(t), c(t) = cos(pi t / T).
+__host__ __device__ inline int64_t vt_size(int n, int m) { return 2 * (n + 2 * m + 1) + 2 * (n + 2 * m); }
+__host__ __device__ inline int64_t vt_ex(int n, int m) { return m; }
+__host__ __device__ inline int64_t vt_cx(int n, int m) { return (n + 2 * m + 1) + m; }
+__host__ __device__ inline int64_t vt_ey(int n, int m) { return (n + 2 * m + 1) + (n + 2 * m) + m; }
+__host__ __device__ inline int64_t vt_cy(int n, int m) { return 2 * (n + 2 * m + 1) + (n + 2 * m) + m; }
+
+// Level ranges of the store (slots are grouped by level).
+struct LevelRange {
+    int32_t start[FC_MAXLEV], count[FC_MAXLEV];
+};
+
+// ---- kernel launchers (fc_kernels.hip) --------------------------------
+struct LaunchCfg {
+    int mx, nt;                // patch edge, threads per patch
+};
+
+hipError_t launch_init_tables(int level, int mx, int periodic_x, int periodic_y, double *vt, hipStream_t s);
+hipError_t launch_set_state(DevState *st, double t, double dt, uint32_t curmask, int reset_cfl, hipStream_t s);
+hipError_t launch_fill(const Ctx &c, int mx, int first, int count, hipStream_t s);
+hipError_t launch_advance(const Ctx &c, LaunchCfg lc, int level, int first, int count, double t, double dt,
+                          int fused, unsigned long long *cfl_bits, hipStream_t s);
+hipError_t launch_persistent(const Ctx &c, LaunchCfg lc, const SchedEntry *sched, int nsched,
+                             const LevelRange *ranges_dev, int nleaves, DevState *state, int grid,
+                             hipStream_t s);
+int persistent_max_grid(LaunchCfg lc, int eq);
+hipError_t launch_set_interior(const Ctx &c, int mx, const int32_t *slot_of_leaf, int n, const double *src,
+                               hipStream_t s);
+hipError_t launch_get_interior(const Ctx &c, int mx, const int32_t *slot_of_leaf, int n, double *dst,
+                               int full, hipStream_t s);
+hipError_t launch_tag(const Ctx &c, int mx, const int32_t *slot_of_leaf, int n, int lmin, int lmax,
+                      double tau_r, double tau_c, int8_t *tags, double *g2, hipStream_t s);
+hipError_t launch_consolidate(const Ctx &c, int mx, int n, hipStream_t s);
+hipError_t launch_transfer(const Ctx &c, int mx, const TransferRec *plan, int n, hipStream_t s);
+hipError_t launch_export_cfl(DevState *state, double *cfl_dev, hipStream_t s);
+hipError_t launch_adjoint(const Ctx &c, LaunchCfg lc, int level, int first, int count, double t, double dt,
+                          const double *lam_in_slots, double *abar, hipStream_t s);
+hipError_t launch_adjoint_gather(const Ctx &c, int mx, int first, int count, const double *abar,
+                                 double *lam_out_slots, hipStream_t s);
+hipError_t launch_slots_to_leaves(const int32_t *slot_of_leaf, int n, int mx, const double *src_slots,
+                                  double *dst_leaves, int inverse, hipStream_t s);

@@ -1,0 +1,748 @@
+// fc_kernels.hip -- gfx950 kernels of the patch-based quadtree AMR path.
+//
+// Ghost filling.  Algorithm 1 of the paper (Sec. 2.2) materialises ghost
+// data in four phases because its interpolation stencil reads the coarse
+// grid's ghost cells, which must be copied/averaged first.  Here every ghost
+// value is evaluated directly from patch *interiors*: copy (same size),
+// eq. ghost_coarse averaging (finer neighbour), or eq. ghost_fine
+// interpolation whose five coarse stencil values are themselves evaluated by
+// copy/averaging.  Prop. 2.1 guarantees a stencil never needs a third level,
+// so one gather pass reproduces the four phases, needs no ordering between
+// patches and can run inside the advance kernel (the fused form).
+//
+// Advance.  One workgroup per patch stages the (mx+4)^2 tile in LDS and runs
+// the unsplit wave-propagation step (Sec. 5 runs Clawpack's): x- and y-edge
+// fluctuations, MC-limited second-order corrections, transverse propagation
+// of the corrected fluctuations, conservative update; written in gather form
+// so that no two threads accumulate into one location.
+#include "fc_internal.h"
+
+#include <math.h>
+
+namespace {
+
+constexpr int MB = 2;  // ghost layers used by the kernels
+
+__device__ __forceinline__ size_t qidx(int cap, int N, int f, int p, int i, int j) {
+    return ((size_t)(f * cap + p) * N + (j + MB)) * N + (i + MB);
+}
+
+__device__ __forceinline__ double *buf_of(const Ctx &c, int l) { return ((c.curmask >> l) & 1u) ? c.q1 : c.q0; }
+__device__ __forceinline__ double *other_of(const Ctx &c, int l) { return ((c.curmask >> l) & 1u) ? c.q0 : c.q1; }
+
+// State of level l at the fill time: current, or q_old + alpha (q - q_old)
+// for the time-interpolated coarse level.
+template <int MX>
+__device__ __forceinline__ double read_state(const Ctx &c, int p, int l, int i, int j, int f) {
+    constexpr int N = MX + 2 * MB;
+    const size_t k = qidx(c.cap, N, f, p, i, j);
+    const bool b = (c.curmask >> l) & 1u;
+    double v = (b ? c.q1 : c.q0)[k];
+    if (l == c.clevel && c.alpha != 1.0) {
+        const double vo = (b ? c.q0 : c.q1)[k];
+        v = vo + c.alpha * (v - vo);
+    }
+    return v;
+}
+
+__device__ __forceinline__ double minmod(double a, double b) {
+    return (a * b <= 0.0) ? 0.0 : (fabs(a) < fabs(b) ? a : b);
+}
+
+template <int MX>
+__device__ __forceinline__ int region_rec(int i, int j) {
+    const int rx = i < 0 ? 0 : (i >= MX ? 2 : 1);
+    const int ry = j < 0 ? 0 : (j >= MX ? 2 : 1);
+    if (ry == 1) return (rx == 0 ? 0 : 2) + (j >= MX / 2 ? 1 : 0);
+    if (rx == 1) return (ry == 0 ? 4 : 6) + (i >= MX / 2 ? 1 : 0);
+    return 8 + (rx == 2 ? 1 : 0) + (ry == 2 ? 2 : 0);
+}
+
+// Reflecting walls: mirror the index into the patch; the normal momentum of
+// the shallow-water system changes sign.  Returns the sign factors.
+template <int MX>
+__device__ __forceinline__ void fold(int walls, int &i, int &j, double &su, double &sv) {
+    su = 1.0; sv = 1.0;
+    if (i < 0 && (walls & 1)) { i = -1 - i; su = -1.0; }
+    else if (i >= MX && (walls & 2)) { i = 2 * MX - 1 - i; su = -1.0; }
+    if (j < 0 && (walls & 4)) { j = -1 - j; sv = -1.0; }
+    else if (j >= MX && (walls & 8)) { j = 2 * MX - 1 - j; sv = -1.0; }
+}
+
+template <int F>
+__device__ __forceinline__ void apply_signs(double *v, double su, double sv) {
+    if (F == 3) { v[1] *= su; v[2] *= sv; }
+}
+
+// Cell (i, j) of patch p as a coarse interpolation stencil sees it: its
+// interior, or a ghost by copy / eq. ghost_coarse averaging.
+template <int MX, int F>
+__device__ void coarse_cell(const Ctx &c, int p, int i, int j, double *v) {
+    const PatchInfo P = c.info[p];
+    double su, sv;
+    fold<MX>(P.walls, i, j, su, sv);
+    if (i >= 0 && i < MX && j >= 0 && j < MX) {
+#pragma unroll
+        for (int f = 0; f < F; f++) v[f] = read_state<MX>(c, p, P.level, i, j, f);
+    } else {
+        const NbrRec r = c.nbr[p * FC_NREC + region_rec<MX>(i, j)];
+        if (r.type == NB_SAME) {
+#pragma unroll
+            for (int f = 0; f < F; f++) v[f] = read_state<MX>(c, r.id, P.level, i - r.ox, j - r.oy, f);
+        } else if (r.type == NB_FINE) {
+            const int li = 2 * (i - r.ox), lj = 2 * (j - r.oy), lf = P.level + 1;
+#pragma unroll
+            for (int f = 0; f < F; f++)
+                v[f] = 0.25 * (read_state<MX>(c, r.id, lf, li, lj, f) + read_state<MX>(c, r.id, lf, li + 1, lj, f) +
+                               read_state<MX>(c, r.id, lf, li, lj + 1, f) +
+                               read_state<MX>(c, r.id, lf, li + 1, lj + 1, f));
+        } else {
+            // a stencil crossing two level curves: excluded by Prop. 2.1
+            atomicOr(c.err, 2);
+#pragma unroll
+            for (int f = 0; f < F; f++) v[f] = __builtin_nan("");
+        }
+    }
+    apply_signs<F>(v, su, sv);
+}
+
+// Ghost value of patch p at local (i, j): the result of Algorithm 1.
+template <int MX, int F>
+__device__ void ghost_cell(const Ctx &c, int p, int i, int j, double *v) {
+    const PatchInfo P = c.info[p];
+    const int l = P.level;
+    double su, sv;
+    fold<MX>(P.walls, i, j, su, sv);
+    if (i >= 0 && i < MX && j >= 0 && j < MX) {
+#pragma unroll
+        for (int f = 0; f < F; f++) v[f] = read_state<MX>(c, p, l, i, j, f);
+        apply_signs<F>(v, su, sv);
+        return;
+    }
+    const NbrRec r = c.nbr[p * FC_NREC + region_rec<MX>(i, j)];
+    if (r.type == NB_SAME) {
+#pragma unroll
+        for (int f = 0; f < F; f++) v[f] = read_state<MX>(c, r.id, l, i - r.ox, j - r.oy, f);
+    } else if (r.type == NB_FINE) {
+        const int li = 2 * (i - r.ox), lj = 2 * (j - r.oy);
+#pragma unroll
+        for (int f = 0; f < F; f++)
+            v[f] = 0.25 * (read_state<MX>(c, r.id, l + 1, li, lj, f) + read_state<MX>(c, r.id, l + 1, li + 1, lj, f) +
+                           read_state<MX>(c, r.id, l + 1, li, lj + 1, f) +
+                           read_state<MX>(c, r.id, l + 1, li + 1, lj + 1, f));
+    } else if (r.type == NB_COARSE) {
+        // eq. ghost_fine: q_c + (1/4)(d_x s_x + d_y s_y), s = minmod of the
+        // one-sided differences on the coarse grid, d = +1 for the upper half
+        const int I = i - r.ox, J = j - r.oy;
+        const int ic = I >> 1, jc = J >> 1;
+        const double dx = (I & 1) ? 1.0 : -1.0, dy = (J & 1) ? 1.0 : -1.0;
+        double cc[F], xm[F], xp[F], ym[F], yp[F];
+#pragma unroll
+        for (int f = 0; f < F; f++) cc[f] = read_state<MX>(c, r.id, l - 1, ic, jc, f);
+        coarse_cell<MX, F>(c, r.id, ic - 1, jc, xm);
+        coarse_cell<MX, F>(c, r.id, ic + 1, jc, xp);
+        coarse_cell<MX, F>(c, r.id, ic, jc - 1, ym);
+        coarse_cell<MX, F>(c, r.id, ic, jc + 1, yp);
+#pragma unroll
+        for (int f = 0; f < F; f++) {
+            const double sx = minmod(xp[f] - cc[f], cc[f] - xm[f]);
+            const double sy = minmod(yp[f] - cc[f], cc[f] - ym[f]);
+            v[f] = cc[f] + 0.25 * (dx * sx + dy * sy);
+        }
+    } else {
+        atomicOr(c.err, 2);
+#pragma unroll
+        for (int f = 0; f < F; f++) v[f] = __builtin_nan("");
+    }
+    apply_signs<F>(v, su, sv);
+}
+
+// g-th ghost cell of the (MX+4)^2 frame: two bottom rows, two top rows, then
+// the left/right pairs of every interior row.
+template <int MX>
+__device__ __forceinline__ void ghost_index(int g, int &i, int &j) {
+    constexpr int N = MX + 2 * MB;
+    if (g < MB * N) { j = g / N - MB; i = g % N - MB; return; }
+    g -= MB * N;
+    if (g < MB * N) { j = MX + g / N; i = g % N - MB; return; }
+    g -= MB * N;
+    j = g / (2 * MB);
+    const int k = g % (2 * MB);
+    i = k < MB ? k - MB : MX + k - MB;
+}
+
+// XCD-aware block -> work item map: consecutive Morton patches go to one
+// XCD (blocks are dispatched round-robin over the 8 XCDs), so neighbour
+// reads hit that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int b, int count) {
+    const int x = b & 7, r = b >> 3;
+    int base = 0;
+    for (int k = 0; k < x; k++) base += (count - k + 7) >> 3;
+    return base + r;
+}
+
+// ------------------------------------------------------------------------
+// fill: materialise ghost values (per-level form)
+// ------------------------------------------------------------------------
+template <int MX, int F>
+__global__ void __launch_bounds__(256) fill_kernel(Ctx c, int first) {
+    constexpr int N = MX + 2 * MB, NG = N * N - MX * MX;
+    const int p = first + blockIdx.x;
+    const int l = c.info[p].level;
+    double *out = buf_of(c, l);
+    for (int g = threadIdx.x; g < NG; g += blockDim.x) {
+        int i, j;
+        ghost_index<MX>(g, i, j);
+        double v[F];
+        ghost_cell<MX, F>(c, p, i, j, v);
+#pragma unroll
+        for (int f = 0; f < F; f++) out[qidx(c.cap, N, f, p, i, j)] = v[f];
+    }
+}
+
+// ------------------------------------------------------------------------
+// scalar advection step
+// ------------------------------------------------------------------------
+template <int MX>
+struct ScalarSmem {
+    static constexpr int N = MX + 2 * MB;
+    static constexpr int NX = (MX + 2) * (MX + 1);  // x-edges: rows -1..MX, edges 0..MX
+    double q[N * N];
+    double cx[NX], apx[NX], amx[NX];  // [j+1][e]
+    double cy[NX], bpy[NX], bmy[NX];  // [e][i+1]
+    double ux[MX + 1], uy[MX + 2];    // u(e, j) = ux[e] * uy[j+1]
+    double vy[MX + 1], vx[MX + 2];    // v(i, e) = vy[e] * vx[i+1]
+    double red[16];
+};
+
+__device__ __forceinline__ double limit(int lim, double W, double Wu) {
+    if (lim == 1) return W;          // Lax-Wendroff
+    if (lim == 2) return 0.0;        // first order
+    const double aw = fabs(W), au = fabs(Wu);
+    double mn;
+    if (lim == 3) mn = fmin(aw, au);  // minmod
+    else mn = fmin(0.5 * fabs(W + Wu), fmin(2.0 * aw, 2.0 * au));  // MC
+    return (W * Wu > 0.0) ? copysign(mn, W) : 0.0;
+}
+
+__device__ __forceinline__ double posp(double a) { return a > 0.0 ? a : 0.0; }
+__device__ __forceinline__ double negp(double a) { return a < 0.0 ? a : 0.0; }
+
+// velocity factors of a patch into LDS
+template <int MX>
+__device__ void load_velocity(const Ctx &c, ScalarSmem<MX> &s, int l, int gx, int gy, double tm) {
+    const int n = MX << l;
+    if (c.velocity == 2) {
+        const double ct = cos(M_PI * tm / c.vel_T);
+        const double *vt = c.vt[l];
+        const double *ex = vt + vt_ex(n, MB), *cxv = vt + vt_cx(n, MB);
+        const double *ey = vt + vt_ey(n, MB), *cyv = vt + vt_cy(n, MB);
+        for (int k = threadIdx.x; k < MX + 2; k += blockDim.x) {
+            if (k <= MX) { s.ux[k] = ex[gx + k]; s.vy[k] = ey[gy + k]; }
+            s.uy[k] = cyv[gy + k - 1] * ct;
+            s.vx[k] = -(cxv[gx + k - 1] * ct);
+        }
+    } else {
+        for (int k = threadIdx.x; k < MX + 2; k += blockDim.x) {
+            if (k <= MX) { s.ux[k] = c.vel_u; s.vy[k] = c.vel_v; }
+            s.uy[k] = 1.0;
+            s.vx[k] = 1.0;
+        }
+    }
+}
+
+// One step on patch p of level l: stage its tile, compute, write the new
+// interior into the level's other buffer.  FUSED: ghosts evaluated on the fly
+// instead of read from the patch's own ghost cells.
+template <int MX, int NT, bool FUSED>
+__device__ void advance_scalar_patch(const Ctx &c, ScalarSmem<MX> &s, int p, double t, double dt, double &cfl) {
+    constexpr int N = MX + 2 * MB, NX = ScalarSmem<MX>::NX;
+    const PatchInfo P = c.info[p];
+    const int l = P.level;
+    const double h = 1.0 / (double)(MX << l);
+    const double lam = dt / h;
+    const double *in = buf_of(c, l);
+    double *out = other_of(c, l);
+    const size_t base = (size_t)p * N * N;
+    load_velocity<MX>(c, s, l, P.ix * MX, P.iy * MX, t + 0.5 * dt);
+    if (!FUSED) {
+        for (int k = threadIdx.x; k < N * N; k += NT) s.q[k] = in[base + k];
+    } else {
+        for (int k = threadIdx.x; k < MX * MX; k += NT) {
+            const int i = k % MX, j = k / MX;
+            s.q[(j + MB) * N + i + MB] = in[base + (j + MB) * N + i + MB];
+        }
+        constexpr int NG = N * N - MX * MX;
+        for (int g = threadIdx.x; g < NG; g += NT) {
+            int i, j;
+            ghost_index<MX>(g, i, j);
+            double v[1];
+            ghost_cell<MX, 1>(c, p, i, j, v);
+            s.q[(j + MB) * N + i + MB] = v[0];
+        }
+    }
+    __syncthreads();
+    double amax = 0.0;
+    // x-edges (e - 1/2, j): e in [0, MX], j in [-1, MX]
+    for (int k = threadIdx.x; k < NX; k += NT) {
+        const int j = k / (MX + 1) - 1, e = k % (MX + 1);
+        const double *row = &s.q[(j + MB) * N + MB];
+        const double qm2 = row[e - 2], qm1 = row[e - 1], q0 = row[e], qp1 = row[e + 1];
+        const double u = s.ux[e] * s.uy[j + 1];
+        const double W = q0 - qm1;
+        const double Wu = u > 0.0 ? qm1 - qm2 : qp1 - q0;
+        const double au = fabs(u);
+        const double C = au * (1.0 - lam * au) * limit(c.lim, W, Wu);
+        s.cx[k] = C;
+        s.apx[k] = posp(u) * W - C;
+        s.amx[k] = negp(u) * W + C;
+        if (j >= 0 && j < MX) amax = fmax(amax, au);
+    }
+    // y-edges (i, e - 1/2): e in [0, MX], i in [-1, MX]
+    for (int k = threadIdx.x; k < NX; k += NT) {
+        const int e = k / (MX + 2), i = k % (MX + 2) - 1;
+        const double *col = &s.q[MB * N + i + MB];
+        const double qm2 = col[(e - 2) * N], qm1 = col[(e - 1) * N], q0 = col[e * N], qp1 = col[(e + 1) * N];
+        const double v = s.vy[e] * s.vx[i + 1];
+        const double W = q0 - qm1;
+        const double Wu = v > 0.0 ? qm1 - qm2 : qp1 - q0;
+        const double av = fabs(v);
+        const double C = av * (1.0 - lam * av) * limit(c.lim, W, Wu);
+        s.cy[k] = C;
+        s.bpy[k] = posp(v) * W - C;
+        s.bmy[k] = negp(v) * W + C;
+        if (i >= 0 && i < MX) amax = fmax(amax, av);
+    }
+    __syncthreads();
+    // per cell: TX = A+*_{i-1/2} + A-*_{i+1/2} (rows -1..MX), TY likewise
+    for (int k = threadIdx.x; k < (MX + 2) * MX; k += NT) {
+        const int j = k / MX - 1, i = k % MX;
+        const int a = (j + 1) * (MX + 1) + i;
+        s.apx[a] = s.apx[a] + s.amx[a + 1];
+        const int jj = k / (MX + 2), ii = k % (MX + 2) - 1;
+        const int b = jj * (MX + 2) + ii + 1;
+        s.bpy[b] = s.bpy[b] + s.bmy[b + MX + 2];
+    }
+    __syncthreads();
+    // conservative update:
+    // Q - lam (TX + TY) + lam/2 (dCx + dCy) + lam^2/2 (dTF + dTG), where
+    // TF(i-1/2) = u+ TY(i-1) + u- TY(i) and TG(j-1/2) = v+ TX(j-1) + v- TX(j)
+    for (int k = threadIdx.x; k < MX * MX; k += NT) {
+        const int j = k / MX, i = k % MX;
+        const int ax = (j + 1) * (MX + 1) + i;
+        const double TXc = s.apx[ax], TXd = s.apx[ax - (MX + 1)], TXu = s.apx[ax + (MX + 1)];
+        const int by = j * (MX + 2) + i + 1;
+        const double TYc = s.bpy[by], TYl = s.bpy[by - 1], TYr = s.bpy[by + 1];
+        const double uL = s.ux[i] * s.uy[j + 1], uR = s.ux[i + 1] * s.uy[j + 1];
+        const double vD = s.vy[j] * s.vx[i + 1], vU = s.vy[j + 1] * s.vx[i + 1];
+        const double TFl = posp(uL) * TYl + negp(uL) * TYc;
+        const double TFr = posp(uR) * TYc + negp(uR) * TYr;
+        const double TGd = posp(vD) * TXd + negp(vD) * TXc;
+        const double TGu = posp(vU) * TXc + negp(vU) * TXu;
+        const double dC = (s.cx[ax + 1] - s.cx[ax]) + (s.cy[by + MX + 2] - s.cy[by]);
+        const double Q = s.q[(j + MB) * N + i + MB];
+        out[base + (j + MB) * N + i + MB] =
+            Q - lam * (TXc + TYc) + 0.5 * lam * dC + 0.5 * lam * lam * ((TFr - TFl) + (TGu - TGd));
+    }
+    cfl = fmax(cfl, lam * amax);
+}
+
+// block-wide max of a non-negative double, then one atomicMax on its bits
+template <int NT>
+__device__ void reduce_cfl(double v, double *red, unsigned long long *cfl_bits) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red[0];
+        for (int k = 1; k < NT / 64; k++) m = fmax(m, red[k]);
+        if (cfl_bits && m > 0.0) atomicMax(cfl_bits, (unsigned long long)__double_as_longlong(m));
+    }
+}
+
+template <int MX, int NT, bool FUSED>
+__global__ void __launch_bounds__(NT) advance_scalar_kernel(Ctx c, int first, int count, double t, double dt,
+                                                            unsigned long long *cfl_bits) {
+    __shared__ ScalarSmem<MX> s;
+    const int p = first + xcd_remap(blockIdx.x, count);
+    double cfl = 0.0;
+    advance_scalar_patch<MX, NT, FUSED>(c, s, p, t, dt, cfl);
+    reduce_cfl<NT>(cfl, s.red, cfl_bits);
+}
+
+// ------------------------------------------------------------------------
+// persistent fused kernel: all level-steps of a coarse step in one launch
+// ------------------------------------------------------------------------
+constexpr long long kSpinLimit = 1ll << 22;
+
+// Device-wide barrier for a co-resident grid.  Every wait is bounded: on
+// timeout the error flag is raised and all later waits are skipped, so the
+// kernel always drains.
+__device__ void grid_barrier(DevState *st, unsigned nblocks) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned gen = __hip_atomic_load(&st->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __threadfence();
+        const unsigned arrived =
+            __hip_atomic_fetch_add(&st->bar_count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == nblocks - 1) {
+            __hip_atomic_store(&st->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&st->bar_gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            long long spins = 0;
+            while (__hip_atomic_load(&st->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++spins > kSpinLimit ||
+                    __hip_atomic_load(&st->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 1) {
+                    __hip_atomic_fetch_or(&st->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+            }
+        }
+        __threadfence();
+    }
+    __syncthreads();
+}
+
+template <int MX, int NT>
+__global__ void __launch_bounds__(NT) persistent_scalar_kernel(Ctx c, const SchedEntry *sched, int nsched,
+                                                               const LevelRange *lr, int nleaves, DevState *st) {
+    __shared__ ScalarSmem<MX> s;
+    const double t0 = st->t, dtc = st->dt_coarse;
+    Ctx lc = c;
+    lc.curmask = st->curmask;
+    const unsigned G = gridDim.x;
+    const int x = blockIdx.x & 7, r = blockIdx.x >> 3;
+    const int nbx = ((int)G - x + 7) >> 3;  // blocks on this XCD
+    uint32_t allmask = 0;
+    int nall = 0;
+    for (int l = 0; l < FC_MAXLEV; l++)
+        if (lr->count[l] > 0) { allmask |= 1u << l; nall += lr->count[l]; }
+    (void)nleaves;
+    double cfl = 0.0;
+    for (int k = 0; k < nsched; k++) {
+        const SchedEntry e = sched[k];
+        int first, count;
+        if (e.level < 0) { first = 0; count = nall; lc.clevel = -1; lc.alpha = 1.0; }
+        else { first = lr->start[e.level]; count = lr->count[e.level]; lc.clevel = e.level - 1; lc.alpha = e.alpha; }
+        if (count == 0) {
+            if (e.level >= 0) lc.curmask ^= 1u << e.level;
+            continue;
+        }
+        const double t = t0 + e.off * dtc, dt = e.scale * dtc;
+        const int c0 = (int)(((long long)count * x) >> 3), c1 = (int)(((long long)count * (x + 1)) >> 3);
+        for (int pi = c0 + r; pi < c1; pi += nbx) {
+            advance_scalar_patch<MX, NT, true>(lc, s, first + pi, t, dt, cfl);
+            __syncthreads();
+        }
+        grid_barrier(st, G);
+        lc.curmask ^= (e.level < 0) ? allmask : (1u << e.level);
+    }
+    reduce_cfl<NT>(cfl, s.red, &st->cfl_bits);
+    grid_barrier(st, G);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->t = t0 + dtc;
+        st->curmask = lc.curmask;
+    }
+}
+
+// ------------------------------------------------------------------------
+// support kernels
+// ------------------------------------------------------------------------
+__global__ void init_tables_kernel(int n, int periodic_x, int periodic_y, double *vt) {
+    const double h = 1.0 / (double)n;
+    const double sig = sin(M_PI * h) / (M_PI * h);
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ne = n + 2 * MB + 1, nc = n + 2 * MB;
+    for (int ax = 0; ax < 2; ax++) {
+        const int per = ax == 0 ? periodic_x : periodic_y;
+        double *e = vt + (ax == 0 ? vt_ex(n, MB) : vt_ey(n, MB));
+        double *cc = vt + (ax == 0 ? vt_cx(n, MB) : vt_cy(n, MB));
+        if (k < ne) {
+            int I = k - MB;
+            if (per) I = ((I % n) + n) % n;
+            const double sx = sin(M_PI * (I * h));
+            e[k - MB] = sx * sx;
+        }
+        if (k < nc) {
+            int I = k - MB;
+            if (per) I = ((I % n) + n) % n;
+            cc[k - MB] = sin(2.0 * M_PI * ((I + 0.5) * h)) * sig;
+        }
+    }
+}
+
+__global__ void set_state_kernel(DevState *st, double t, double dt, uint32_t curmask, int reset_cfl) {
+    st->t = t;
+    st->dt_coarse = dt;
+    st->curmask = curmask;
+    st->bar_count = 0;
+    if (reset_cfl) st->cfl_bits = 0ull;
+}
+
+__global__ void export_cfl_kernel(DevState *st, double *cfl) {
+    const double v = __longlong_as_double((long long)st->cfl_bits);
+    if (cfl && v > *cfl) *cfl = v;
+}
+
+// interior data, input-leaf order [n][F][mx][mx] <-> store slots
+template <int MX>
+__global__ void set_interior_kernel(Ctx c, const int32_t *slot_of_leaf, int n, const double *src) {
+    constexpr int N = MX + 2 * MB;
+    const long long tot = (long long)n * c.F * MX * MX;
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < tot; k += (long long)gridDim.x * blockDim.x) {
+        const int i = k % MX, j = (k / MX) % MX, f = (k / (MX * MX)) % c.F;
+        const int leaf = (int)(k / ((long long)MX * MX * c.F));
+        const int p = slot_of_leaf[leaf];
+        buf_of(c, c.info[p].level)[qidx(c.cap, N, f, p, i, j)] = src[k];
+    }
+}
+
+template <int MX>
+__global__ void get_interior_kernel(Ctx c, const int32_t *slot_of_leaf, int n, double *dst, int full) {
+    constexpr int N = MX + 2 * MB;
+    const int E = full ? N : MX, off = full ? MB : 0;
+    const long long tot = (long long)n * c.F * E * E;
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < tot; k += (long long)gridDim.x * blockDim.x) {
+        const int i = k % E - off, j = (k / E) % E - off, f = (k / (E * E)) % c.F;
+        const int leaf = (int)(k / ((long long)E * E * c.F));
+        const int p = slot_of_leaf[leaf];
+        dst[k] = buf_of(c, c.info[p].level)[qidx(c.cap, N, f, p, i, j)];
+    }
+}
+
+// tagging: max over interior of |grad q|^2 with central differences / 2h
+template <int MX>
+__global__ void __launch_bounds__(256) tag_kernel(Ctx c, const int32_t *slot_of_leaf, int lmin, int lmax,
+                                                  double tau_r, double tau_c, int8_t *tags, double *g2out) {
+    constexpr int N = MX + 2 * MB;
+    __shared__ double red[4];
+    const int leaf = blockIdx.x;
+    const int p = slot_of_leaf[leaf];
+    const PatchInfo P = c.info[p];
+    const double h = 1.0 / (double)(MX << P.level);
+    const double *q = buf_of(c, P.level);
+    double g2 = 0.0;
+    for (int k = threadIdx.x; k < MX * MX; k += blockDim.x) {
+        const int i = k % MX, j = k / MX;
+        const double gx = (q[qidx(c.cap, N, 0, p, i + 1, j)] - q[qidx(c.cap, N, 0, p, i - 1, j)]) / (2.0 * h);
+        const double gy = (q[qidx(c.cap, N, 0, p, i, j + 1)] - q[qidx(c.cap, N, 0, p, i, j - 1)]) / (2.0 * h);
+        g2 = fmax(g2, gx * gx + gy * gy);
+    }
+    for (int o = 32; o > 0; o >>= 1) g2 = fmax(g2, __shfl_xor(g2, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = g2;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red[0];
+        for (int w = 1; w < (int)(blockDim.x >> 6); w++) m = fmax(m, red[w]);
+        int8_t tg = 0;
+        if (m > tau_r * tau_r && P.level < lmax) tg = 1;
+        else if (m <= tau_c * tau_c && P.level > lmin) tg = -1;
+        tags[leaf] = tg;
+        if (g2out) g2out[leaf] = m;
+    }
+}
+
+// regrid: move every old patch (with ghosts) into buffer 0
+template <int MX>
+__global__ void consolidate_kernel(Ctx c) {
+    constexpr int N = MX + 2 * MB;
+    const int p = blockIdx.x;
+    const int l = c.info[p].level;
+    if (!((c.curmask >> l) & 1u)) return;
+    for (int f = 0; f < c.F; f++)
+        for (int k = threadIdx.x; k < N * N; k += blockDim.x) {
+            const size_t a = (size_t)(f * c.cap + p) * N * N + k;
+            c.q0[a] = c.q1[a];
+        }
+}
+
+// regrid transfer: old data in buffer 0 (old slots), new data to buffer 1
+template <int MX>
+__global__ void transfer_kernel(Ctx c, const TransferRec *plan) {
+    constexpr int N = MX + 2 * MB;
+    const int p = blockIdx.x;
+    const TransferRec tr = plan[p];
+    for (int f = 0; f < c.F; f++)
+        for (int k = threadIdx.x; k < MX * MX; k += blockDim.x) {
+            const int i = k % MX, j = k / MX;
+            double v;
+            if (tr.kind == TR_COPY) {
+                v = c.q0[qidx(c.cap, N, f, tr.src[0], i, j)];
+            } else if (tr.kind == TR_REFINE) {
+                const int ic = tr.cx * (MX / 2) + (i >> 1), jc = tr.cy * (MX / 2) + (j >> 1);
+                const double dx = (i & 1) ? 1.0 : -1.0, dy = (j & 1) ? 1.0 : -1.0;
+                const int s = tr.src[0];
+                const double cc = c.q0[qidx(c.cap, N, f, s, ic, jc)];
+                const double sx = minmod(c.q0[qidx(c.cap, N, f, s, ic + 1, jc)] - cc, cc - c.q0[qidx(c.cap, N, f, s, ic - 1, jc)]);
+                const double sy = minmod(c.q0[qidx(c.cap, N, f, s, ic, jc + 1)] - cc, cc - c.q0[qidx(c.cap, N, f, s, ic, jc - 1)]);
+                v = cc + 0.25 * (dx * sx + dy * sy);
+            } else {
+                const int cx = i >= MX / 2, cy = j >= MX / 2;
+                const int s = tr.src[cx + 2 * cy];
+                const int fi = 2 * i - cx * MX, fj = 2 * j - cy * MX;
+                v = 0.25 * (c.q0[qidx(c.cap, N, f, s, fi, fj)] + c.q0[qidx(c.cap, N, f, s, fi + 1, fj)] +
+                            c.q0[qidx(c.cap, N, f, s, fi, fj + 1)] + c.q0[qidx(c.cap, N, f, s, fi + 1, fj + 1)]);
+            }
+            c.q1[qidx(c.cap, N, f, p, i, j)] = v;
+        }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------
+// launchers
+// ------------------------------------------------------------------------
+hipError_t launch_init_tables(int level, int mx, int periodic_x, int periodic_y, double *vt, hipStream_t s) {
+    const int n = mx << level;
+    const int tot = n + 2 * MB + 1;
+    hipLaunchKernelGGL(init_tables_kernel, dim3((tot + 255) / 256), dim3(256), 0, s, n, periodic_x, periodic_y, vt);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_state(DevState *st, double t, double dt, uint32_t curmask, int reset_cfl, hipStream_t s) {
+    hipLaunchKernelGGL(set_state_kernel, dim3(1), dim3(1), 0, s, st, t, dt, curmask, reset_cfl);
+    return hipGetLastError();
+}
+
+hipError_t launch_export_cfl(DevState *state, double *cfl_dev, hipStream_t s) {
+    hipLaunchKernelGGL(export_cfl_kernel, dim3(1), dim3(1), 0, s, state, cfl_dev);
+    return hipGetLastError();
+}
+
+template <int MX>
+static hipError_t fill_mx(const Ctx &c, int first, int count, hipStream_t s) {
+    if (c.F == 3) hipLaunchKernelGGL((fill_kernel<MX, 3>), dim3(count), dim3(256), 0, s, c, first);
+    else hipLaunchKernelGGL((fill_kernel<MX, 1>), dim3(count), dim3(256), 0, s, c, first);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(const Ctx &c, int mx, int first, int count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    switch (mx) {
+        case 8: return fill_mx<8>(c, first, count, s);
+        case 16: return fill_mx<16>(c, first, count, s);
+        case 32: return fill_mx<32>(c, first, count, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int MX, int NT>
+static hipError_t adv_scalar(const Ctx &c, int first, int count, double t, double dt, int fused,
+                             unsigned long long *cfl, hipStream_t s) {
+    if (fused) hipLaunchKernelGGL((advance_scalar_kernel<MX, NT, true>), dim3(count), dim3(NT), 0, s, c, first, count, t, dt, cfl);
+    else hipLaunchKernelGGL((advance_scalar_kernel<MX, NT, false>), dim3(count), dim3(NT), 0, s, c, first, count, t, dt, cfl);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance(const Ctx &c, LaunchCfg lc, int level, int first, int count, double t, double dt,
+                          int fused, unsigned long long *cfl_bits, hipStream_t s) {
+    (void)level;
+    if (count <= 0) return hipSuccess;
+    if (c.eq == 0) {
+#define ADV(MXV, NTV) if (lc.mx == MXV && lc.nt == NTV) return adv_scalar<MXV, NTV>(c, first, count, t, dt, fused, cfl_bits, s);
+        ADV(8, 64) ADV(8, 128) ADV(16, 64) ADV(16, 128) ADV(16, 256) ADV(32, 128) ADV(32, 256) ADV(32, 512)
+#undef ADV
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int MX, int NT>
+static const void *persistent_fn(int eq) {
+    (void)eq;
+    return reinterpret_cast<const void *>(&persistent_scalar_kernel<MX, NT>);
+}
+
+static const void *persistent_select(LaunchCfg lc, int eq) {
+#define PS(MXV, NTV) if (lc.mx == MXV && lc.nt == NTV) return persistent_fn<MXV, NTV>(eq);
+    PS(8, 64) PS(8, 128) PS(16, 64) PS(16, 128) PS(16, 256) PS(32, 128) PS(32, 256) PS(32, 512)
+#undef PS
+    return nullptr;
+}
+
+int persistent_max_grid(LaunchCfg lc, int eq) {
+    const void *fn = persistent_select(lc, eq);
+    if (!fn) return 0;
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, lc.nt, 0) != hipSuccess) return 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    return per_cu * cus;
+}
+
+hipError_t launch_persistent(const Ctx &c, LaunchCfg lc, const SchedEntry *sched, int nsched,
+                             const LevelRange *ranges_dev, int nleaves, DevState *state, int grid, hipStream_t s) {
+    const void *fn = persistent_select(lc, c.eq);
+    if (!fn || grid <= 0) return hipErrorInvalidValue;
+    Ctx cc = c;
+    void *args[] = {&cc, (void *)&sched, &nsched, (void *)&ranges_dev, &nleaves, &state};
+    return hipLaunchKernel(fn, dim3(grid), dim3(lc.nt), args, 0, s);
+}
+
+template <int MX>
+static void setget(const Ctx &c, const int32_t *sl, int n, const double *src, double *dst, int full, hipStream_t s) {
+    const long long tot = (long long)n * c.F * MX * MX;
+    const int blocks = (int)((tot + 255) / 256 < 65536 ? (tot + 255) / 256 : 65536);
+    if (src) hipLaunchKernelGGL(set_interior_kernel<MX>, dim3(blocks), dim3(256), 0, s, c, sl, n, src);
+    else hipLaunchKernelGGL(get_interior_kernel<MX>, dim3(blocks), dim3(256), 0, s, c, sl, n, dst, full);
+}
+
+hipError_t launch_set_interior(const Ctx &c, int mx, const int32_t *slot_of_leaf, int n, const double *src,
+                               hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    switch (mx) {
+        case 8: setget<8>(c, slot_of_leaf, n, src, nullptr, 0, s); break;
+        case 16: setget<16>(c, slot_of_leaf, n, src, nullptr, 0, s); break;
+        case 32: setget<32>(c, slot_of_leaf, n, src, nullptr, 0, s); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_get_interior(const Ctx &c, int mx, const int32_t *slot_of_leaf, int n, double *dst, int full,
+                               hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    switch (mx) {
+        case 8: setget<8>(c, slot_of_leaf, n, nullptr, dst, full, s); break;
+        case 16: setget<16>(c, slot_of_leaf, n, nullptr, dst, full, s); break;
+        case 32: setget<32>(c, slot_of_leaf, n, nullptr, dst, full, s); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_tag(const Ctx &c, int mx, const int32_t *slot_of_leaf, int n, int lmin, int lmax, double tau_r,
+                      double tau_c, int8_t *tags, double *g2, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    switch (mx) {
+        case 8: hipLaunchKernelGGL(tag_kernel<8>, dim3(n), dim3(64), 0, s, c, slot_of_leaf, lmin, lmax, tau_r, tau_c, tags, g2); break;
+        case 16: hipLaunchKernelGGL(tag_kernel<16>, dim3(n), dim3(256), 0, s, c, slot_of_leaf, lmin, lmax, tau_r, tau_c, tags, g2); break;
+        case 32: hipLaunchKernelGGL(tag_kernel<32>, dim3(n), dim3(256), 0, s, c, slot_of_leaf, lmin, lmax, tau_r, tau_c, tags, g2); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_consolidate(const Ctx &c, int mx, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    switch (mx) {
+        case 8: hipLaunchKernelGGL(consolidate_kernel<8>, dim3(n), dim3(256), 0, s, c); break;
+        case 16: hipLaunchKernelGGL(consolidate_kernel<16>, dim3(n), dim3(256), 0, s, c); break;
+        case 32: hipLaunchKernelGGL(consolidate_kernel<32>, dim3(n), dim3(256), 0, s, c); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_transfer(const Ctx &c, int mx, const TransferRec *plan, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    switch (mx) {
+        case 8: hipLaunchKernelGGL(transfer_kernel<8>, dim3(n), dim3(64), 0, s, c, plan); break;
+        case 16: hipLaunchKernelGGL(transfer_kernel<16>, dim3(n), dim3(256), 0, s, c, plan); break;
+        case 32: hipLaunchKernelGGL(transfer_kernel<32>, dim3(n), dim3(256), 0, s, c, plan); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}

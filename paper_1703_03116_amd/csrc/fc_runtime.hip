@@ -1,0 +1,773 @@
+// fc_runtime.hip -- host runtime and C ABI of the AMR library (include/fc.h).
+//
+// Host side: leaf validation (tiling, 2:1 balance over faces and corners,
+// Prop. 2.1 ghost width), store order (level, then Morton index inside a
+// level, Sec. 2), per-patch neighbour records for the 20 neighbour cases of
+// Sec. 2.3 (face: same / fine-lo / fine-hi / coarse, corner: same / fine /
+// coarse, plus walls), the multirate level-step schedule, host adaptation
+// (tag -> refine/coarsen -> balance, Sec. 4.1) and the regrid transfer plan.
+// Device side: launches on the caller's stream; device memory is the
+// caller's (two patch buffers and one workspace).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/fc.h"
+#include "fc_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+fc_status fail(fc_status st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
+#define HIPCHK(expr)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess) return fail(FC_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+inline uint64_t key3(int l, int ix, int iy) {
+    return ((uint64_t)(uint32_t)l << 56) | ((uint64_t)(uint32_t)iy << 28) | (uint64_t)(uint32_t)ix;
+}
+
+inline uint64_t morton(uint32_t x, uint32_t y) {
+    uint64_t r = 0;
+    for (int b = 0; b < 28; b++) r |= (uint64_t)((x >> b) & 1u) << (2 * b) | (uint64_t)((y >> b) & 1u) << (2 * b + 1);
+    return r;
+}
+
+constexpr int MBK = 2;  // ghost layers the kernels use
+
+struct Mesh {
+    int mx = 0;
+    int bc[4] = {0, 0, 0, 0};
+    std::vector<fc_leaf> lv;                 // store order
+    std::unordered_map<uint64_t, int> at;    // (level, ix, iy) -> slot
+
+    int find(int l, int ix, int iy) const {
+        if (l < 0 || l > 30) return -1;
+        const int nq = 1 << l;
+        if (ix < 0 || iy < 0 || ix >= nq || iy >= nq) return -1;
+        auto it = at.find(key3(l, ix, iy));
+        return it == at.end() ? -1 : it->second;
+    }
+    bool covered_le(int lf, int X, int Y, int lcap) const {
+        for (int l2 = lcap; l2 >= 0; l2--)
+            if (find(l2, X >> (lf - l2), Y >> (lf - l2)) >= 0) return true;
+        return false;
+    }
+    // 2:1 balance over faces and corners, with periodic wrap where periodic
+    bool balanced_at(const fc_leaf &L) const {
+        const int lf = L.level + 2, nf = 1 << lf, x0 = L.ix * 4, y0 = L.iy * 4;
+        for (int dy = -1; dy <= 1; dy++)
+            for (int dx = -1; dx <= 1; dx++) {
+                if (!dx && !dy) continue;
+                const int xa = dx < 0 ? x0 - 1 : dx > 0 ? x0 + 4 : x0, xb = dx < 0 ? x0 - 1 : dx > 0 ? x0 + 4 : x0 + 3;
+                const int ya = dy < 0 ? y0 - 1 : dy > 0 ? y0 + 4 : y0, yb = dy < 0 ? y0 - 1 : dy > 0 ? y0 + 4 : y0 + 3;
+                for (int yy = ya; yy <= yb; yy++)
+                    for (int xx = xa; xx <= xb; xx++) {
+                        int X = xx, Y = yy;
+                        if (X < 0 || X >= nf) {
+                            if (bc[X < 0 ? 0 : 1] != FC_BC_PERIODIC) continue;
+                            X = (X + nf) % nf;
+                        }
+                        if (Y < 0 || Y >= nf) {
+                            if (bc[Y < 0 ? 2 : 3] != FC_BC_PERIODIC) continue;
+                            Y = (Y + nf) % nf;
+                        }
+                        if (!covered_le(lf, X, Y, L.level + 1)) return false;
+                    }
+            }
+        return true;
+    }
+    void index() {
+        at.clear();
+        at.reserve(lv.size() * 2);
+        for (size_t k = 0; k < lv.size(); k++) at[key3(lv[k].level, lv[k].ix, lv[k].iy)] = (int)k;
+    }
+};
+
+// Validate a leaf list (any order).  Returns FC_OK or an error status.
+fc_status validate(const Mesh &m, const std::vector<fc_leaf> &L) {
+    Mesh t;
+    t.mx = m.mx;
+    std::copy(m.bc, m.bc + 4, t.bc);
+    t.lv = L;
+    t.index();
+    if (t.at.size() != L.size()) return fail(FC_ERR_COVER, "duplicate leaves");
+    long double area = 0;
+    for (const auto &q : L) {
+        if (q.level < 0 || q.level > 20) return fail(FC_ERR_ARG, "leaf level out of range");
+        const int nq = 1 << q.level;
+        if (q.ix < 0 || q.iy < 0 || q.ix >= nq || q.iy >= nq) return fail(FC_ERR_ARG, "leaf coordinates out of range");
+        for (int a = 1; a <= q.level; a++)
+            if (t.find(q.level - a, q.ix >> a, q.iy >> a) >= 0) return fail(FC_ERR_COVER, "overlapping leaves");
+        area += ldexpl(1.0L, -2 * q.level);
+    }
+    if (fabsl(area - 1.0L) > 1e-15L) return fail(FC_ERR_COVER, "leaves do not tile the unit square");
+    for (const auto &q : L)
+        if (!t.balanced_at(q)) return fail(FC_ERR_UNBALANCED, "leaves are not 2:1 balanced");
+    return FC_OK;
+}
+
+}  // namespace
+
+struct fc_patchstore {
+    fc_config cfg;
+    int mx = 0, N = 0, F = 1;
+    Mesh mesh;
+    std::vector<int32_t> slot_of_leaf, leaf_of_slot;  // input order <-> store order
+    std::vector<PatchInfo> info;
+    std::vector<NbrRec> nbr;
+    LevelRange lr;
+    uint32_t curmask = 0;
+    double t = 0.0;
+    int nt = 0;  // threads per patch of the advance kernels
+    // device
+    double *q0 = nullptr, *q1 = nullptr;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    size_t off_info = 0, off_nbr = 0, off_sl = 0, off_ls = 0, off_lr = 0, off_sched = 0, off_state = 0,
+           off_plan = 0, off_tag = 0, off_vt[FC_MAXLEV] = {0}, off_abar = 0;
+    std::vector<SchedEntry> sched;
+    int pgrid = 0;
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    hipStream_t gstream = nullptr;
+    int gnt = 0;
+};
+
+namespace {
+
+int nfields(const fc_config &c) { return c.equation == FC_EQ_SWE ? 3 : 1; }
+
+// store order, level ranges, patch info and neighbour records
+void build_metadata(fc_patchstore *ps, const std::vector<fc_leaf> &input) {
+    const int n = (int)input.size();
+    std::vector<int> order(n);
+    for (int k = 0; k < n; k++) order[k] = k;
+    std::sort(order.begin(), order.end(), [&](int a, int b) {
+        if (input[a].level != input[b].level) return input[a].level < input[b].level;
+        return morton(input[a].ix, input[a].iy) < morton(input[b].ix, input[b].iy);
+    });
+    ps->mesh.lv.resize(n);
+    ps->slot_of_leaf.assign(n, 0);
+    ps->leaf_of_slot.assign(n, 0);
+    for (int s = 0; s < n; s++) {
+        ps->mesh.lv[s] = input[order[s]];
+        ps->leaf_of_slot[s] = order[s];
+        ps->slot_of_leaf[order[s]] = s;
+    }
+    ps->mesh.index();
+    for (int l = 0; l < FC_MAXLEV; l++) { ps->lr.start[l] = 0; ps->lr.count[l] = 0; }
+    for (int s = n - 1; s >= 0; s--) { ps->lr.start[ps->mesh.lv[s].level] = s; }
+    for (int s = 0; s < n; s++) ps->lr.count[ps->mesh.lv[s].level]++;
+
+    const int mx = ps->mx;
+    const int *bc = ps->cfg.bc;
+    ps->info.assign(n, PatchInfo{});
+    ps->nbr.assign((size_t)n * FC_NREC, NbrRec{NB_NONE, 0, 0, 0});
+    // representative cell of each record: faces W, E, S, N (two halves each), corners SW, SE, NW, NE
+    const int rep[FC_NREC][2] = {{-1, 0}, {-1, mx / 2}, {mx, 0}, {mx, mx / 2}, {0, -1}, {mx / 2, -1},
+                                 {0, mx}, {mx / 2, mx}, {-1, -1}, {mx, -1}, {-1, mx}, {mx, mx}};
+    for (int s = 0; s < n; s++) {
+        const fc_leaf P = ps->mesh.lv[s];
+        const int l = P.level, nl = mx << l, nq = 1 << l;
+        int walls = 0;
+        if (P.ix == 0 && bc[0] == FC_BC_REFLECT) walls |= 1;
+        if (P.ix == nq - 1 && bc[1] == FC_BC_REFLECT) walls |= 2;
+        if (P.iy == 0 && bc[2] == FC_BC_REFLECT) walls |= 4;
+        if (P.iy == nq - 1 && bc[3] == FC_BC_REFLECT) walls |= 8;
+        ps->info[s] = PatchInfo{l, P.ix, P.iy, walls};
+        for (int r = 0; r < FC_NREC; r++) {
+            const int ri = rep[r][0], rj = rep[r][1];
+            int I = P.ix * mx + ri, J = P.iy * mx + rj;
+            bool wall = false;
+            if (I < 0 || I >= nl) { if (bc[I < 0 ? 0 : 1] == FC_BC_PERIODIC) I = (I + nl) % nl; else wall = true; }
+            if (J < 0 || J >= nl) { if (bc[J < 0 ? 2 : 3] == FC_BC_PERIODIC) J = (J + nl) % nl; else wall = true; }
+            if (wall) continue;
+            // point location: the level-l quadrant, its parent, or a child
+            int type = NB_NONE, id = -1, ext = 0, ox = 0, oy = 0;
+            if ((id = ps->mesh.find(l, I / mx, J / mx)) >= 0) {
+                type = NB_SAME; ext = mx;
+                ox = ps->mesh.lv[id].ix * mx; oy = ps->mesh.lv[id].iy * mx;
+            } else if ((id = ps->mesh.find(l - 1, (I / mx) >> 1, (J / mx) >> 1)) >= 0) {
+                type = NB_COARSE; ext = 2 * mx;
+                ox = ps->mesh.lv[id].ix * 2 * mx; oy = ps->mesh.lv[id].iy * 2 * mx;
+            } else if ((id = ps->mesh.find(l + 1, (2 * I) / mx, (2 * J) / mx)) >= 0) {
+                type = NB_FINE; ext = mx / 2;
+                ox = ps->mesh.lv[id].ix * (mx / 2); oy = ps->mesh.lv[id].iy * (mx / 2);
+            } else {
+                continue;  // cannot happen on a validated mesh
+            }
+            ox -= P.ix * mx;
+            oy -= P.iy * mx;
+            while (ri - ox < 0) ox -= nl;
+            while (ri - ox >= ext) ox += nl;
+            while (rj - oy < 0) oy -= nl;
+            while (rj - oy >= ext) oy += nl;
+            ps->nbr[(size_t)s * FC_NREC + r] = NbrRec{type, id, ox, oy};
+        }
+    }
+}
+
+// multirate recursion (coarse first): level l steps, then two half steps of l+1
+void gen_sched(std::vector<SchedEntry> &out, int l, int lmax, double off, double scale, double alpha) {
+    out.push_back(SchedEntry{l, 0, off, scale, alpha});
+    if (l < lmax) {
+        gen_sched(out, l + 1, lmax, off, 0.5 * scale, 0.0);
+        gen_sched(out, l + 1, lmax, off + 0.5 * scale, 0.5 * scale, 0.5);
+    }
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+void layout_workspace(fc_patchstore *ps) {
+    const size_t cap = (size_t)ps->cfg.capacity;
+    size_t o = 0;
+    ps->off_state = o; o = align256(o + sizeof(DevState));
+    ps->off_lr = o; o = align256(o + sizeof(LevelRange));
+    ps->off_sched = o; o = align256(o + sizeof(SchedEntry) * ps->sched.size());
+    ps->off_info = o; o = align256(o + sizeof(PatchInfo) * cap);
+    ps->off_nbr = o; o = align256(o + sizeof(NbrRec) * cap * FC_NREC);
+    ps->off_sl = o; o = align256(o + sizeof(int32_t) * cap);
+    ps->off_ls = o; o = align256(o + sizeof(int32_t) * cap);
+    ps->off_plan = o; o = align256(o + sizeof(TransferRec) * cap);
+    ps->off_tag = o; o = align256(o + sizeof(double) * cap);
+    for (int l = 0; l < FC_MAXLEV; l++) {
+        ps->off_vt[l] = o;
+        if (l >= ps->cfg.min_level && l <= ps->cfg.max_level && ps->cfg.velocity == FC_VEL_SWIRL)
+            o = align256(o + sizeof(double) * (size_t)vt_size(ps->mx << l, MBK));
+    }
+    ps->ws_bytes = o;
+}
+
+Ctx make_ctx(const fc_patchstore *ps) {
+    Ctx c;
+    memset(&c, 0, sizeof(c));
+    c.q0 = ps->q0; c.q1 = ps->q1;
+    c.info = (const PatchInfo *)(ps->ws + ps->off_info);
+    c.nbr = (const NbrRec *)(ps->ws + ps->off_nbr);
+    c.cap = (int32_t)ps->cfg.capacity;
+    c.F = ps->F; c.eq = ps->cfg.equation; c.lim = ps->cfg.limiter;
+    c.curmask = ps->curmask;
+    c.clevel = -1; c.alpha = 1.0;
+    for (int l = 0; l < FC_MAXLEV; l++)
+        c.vt[l] = (ps->cfg.velocity == FC_VEL_SWIRL && l >= ps->cfg.min_level && l <= ps->cfg.max_level)
+                      ? (const double *)(ps->ws + ps->off_vt[l] ) : nullptr;
+    c.velocity = ps->cfg.velocity;
+    c.vel_u = ps->cfg.vel_params[0]; c.vel_v = ps->cfg.vel_params[1]; c.vel_T = ps->cfg.vel_params[0];
+    c.g = ps->cfg.gravity;
+    c.err = (int32_t *)(ps->ws + ps->off_state + offsetof(DevState, err));
+    return c;
+}
+
+DevState *dstate(fc_patchstore *ps) { return (DevState *)(ps->ws + ps->off_state); }
+
+fc_status upload_metadata(fc_patchstore *ps, hipStream_t s) {
+    const int n = (int)ps->mesh.lv.size();
+    HIPCHK(hipMemcpyAsync(ps->ws + ps->off_info, ps->info.data(), sizeof(PatchInfo) * n, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(ps->ws + ps->off_nbr, ps->nbr.data(), sizeof(NbrRec) * n * FC_NREC, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(ps->ws + ps->off_sl, ps->slot_of_leaf.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(ps->ws + ps->off_ls, ps->leaf_of_slot.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(ps->ws + ps->off_lr, &ps->lr, sizeof(LevelRange), hipMemcpyHostToDevice, s));
+    return FC_OK;
+}
+
+bool valid_nt(int mx, int nt) {
+    switch (mx) {
+        case 8: return nt == 64 || nt == 128;
+        case 16: return nt == 64 || nt == 128 || nt == 256;
+        case 32: return nt == 128 || nt == 256 || nt == 512;
+    }
+    return false;
+}
+int default_nt(int mx) { return mx == 8 ? 64 : 256; }
+
+fc_status check_bound(const fc_patchstore *ps) {
+    if (!ps) return fail(FC_ERR_ARG, "null store");
+    if (!ps->ws || !ps->q0 || !ps->q1) return fail(FC_ERR_STATE, "store not bound to device memory");
+    return FC_OK;
+}
+
+fc_status check_device_error(fc_patchstore *ps, hipStream_t s) {
+    int32_t err = 0;
+    HIPCHK(hipMemcpyAsync(&err, ps->ws + ps->off_state + offsetof(DevState, err), sizeof(err), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (err & 1) return fail(FC_ERR_HIP, "device-wide barrier timed out (grid not co-resident)");
+    if (err & 2) return fail(FC_ERR_HIP, "interpolation stencil needed a third level (Prop. 2.1 violated)");
+    return FC_OK;
+}
+
+fc_status fill_levels(fc_patchstore *ps, int lo, int hi, double alpha, hipStream_t s) {
+    Ctx c = make_ctx(ps);
+    c.clevel = lo - 1;
+    c.alpha = alpha;
+    const int first = ps->lr.start[lo];
+    int count = 0;
+    for (int l = lo; l <= hi; l++) count += ps->lr.count[l];
+    // levels are contiguous in the store, but an empty level has start 0
+    int f0 = -1;
+    for (int l = lo; l <= hi; l++)
+        if (ps->lr.count[l] > 0) { f0 = ps->lr.start[l]; break; }
+    (void)first;
+    if (f0 < 0) return FC_OK;
+    HIPCHK(launch_fill(c, ps->mx, f0, count, s));
+    return FC_OK;
+}
+
+fc_status advance_one(fc_patchstore *ps, int level, double t, double dt, int fused_load, int clevel, double alpha,
+                      unsigned long long *cfl_bits, hipStream_t s) {
+    if (ps->lr.count[level] > 0) {
+        Ctx c = make_ctx(ps);
+        c.clevel = clevel;
+        c.alpha = alpha;
+        HIPCHK(launch_advance(c, LaunchCfg{ps->mx, ps->nt}, level, ps->lr.start[level], ps->lr.count[level], t, dt,
+                              fused_load, cfl_bits, s));
+    }
+    ps->curmask ^= 1u << level;
+    return FC_OK;
+}
+
+void drop_graph(fc_patchstore *ps) {
+    if (ps->gexec) (void)hipGraphExecDestroy(ps->gexec);
+    if (ps->graph) (void)hipGraphDestroy(ps->graph);
+    ps->gexec = nullptr;
+    ps->graph = nullptr;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *fc_last_error(void) { return g_err.c_str(); }
+
+fc_status fc_patchstore_create(const fc_config *cfg, int64_t nleaves, const fc_leaf *leaves, fc_patchstore **out,
+                               int64_t *perm_out) {
+    if (!cfg || !out || (nleaves > 0 && !leaves) || nleaves <= 0) return fail(FC_ERR_ARG, "bad arguments");
+    *out = nullptr;
+    if (cfg->mx != 8 && cfg->mx != 16 && cfg->mx != 32) return fail(FC_ERR_ARG, "mx must be 8, 16 or 32");
+    if (4 * cfg->mbc > cfg->mx || cfg->mbc < 2) return fail(FC_ERR_GHOST_WIDTH, "need 2 <= mbc <= mx/4 (Prop. 2.1)");
+    if (cfg->mbc != 2) return fail(FC_ERR_ARG, "the kernels use exactly 2 ghost layers");
+    if (cfg->equation != FC_EQ_ADVECTION && cfg->equation != FC_EQ_SWE) return fail(FC_ERR_ARG, "unknown equation");
+    if (cfg->limiter < 0 || cfg->limiter > 3) return fail(FC_ERR_ARG, "unknown limiter");
+    for (int s = 0; s < 4; s++)
+        if (cfg->bc[s] != FC_BC_PERIODIC && cfg->bc[s] != FC_BC_REFLECT) return fail(FC_ERR_ARG, "unknown boundary condition");
+    if ((cfg->bc[0] == FC_BC_PERIODIC) != (cfg->bc[1] == FC_BC_PERIODIC) ||
+        (cfg->bc[2] == FC_BC_PERIODIC) != (cfg->bc[3] == FC_BC_PERIODIC))
+        return fail(FC_ERR_ARG, "periodicity must match on opposite sides");
+    if (cfg->min_level < 0 || cfg->max_level < cfg->min_level || cfg->max_level >= FC_MAXLEV - 1)
+        return fail(FC_ERR_ARG, "bad level range");
+    if (cfg->capacity < nleaves) return fail(FC_ERR_CAPACITY, "capacity below the number of leaves");
+    if (cfg->equation == FC_EQ_ADVECTION && cfg->velocity == FC_VEL_NONE) return fail(FC_ERR_ARG, "advection needs a velocity");
+    if (cfg->velocity == FC_VEL_SWIRL && !(cfg->vel_params[0] > 0)) return fail(FC_ERR_ARG, "swirl period must be > 0");
+    std::vector<fc_leaf> L(leaves, leaves + nleaves);
+    for (const auto &q : L)
+        if (q.level < cfg->min_level || q.level > cfg->max_level) return fail(FC_ERR_ARG, "leaf level outside [min_level, max_level]");
+    Mesh m;
+    m.mx = cfg->mx;
+    std::copy(cfg->bc, cfg->bc + 4, m.bc);
+    fc_status st = validate(m, L);
+    if (st != FC_OK) return st;
+    fc_patchstore *ps = new fc_patchstore();
+    ps->cfg = *cfg;
+    ps->mx = cfg->mx;
+    ps->N = cfg->mx + 2 * MBK;
+    ps->F = nfields(*cfg);
+    ps->mesh.mx = cfg->mx;
+    std::copy(cfg->bc, cfg->bc + 4, ps->mesh.bc);
+    build_metadata(ps, L);
+    if (cfg->time_stepping == FC_STEP_GLOBAL) ps->sched.push_back(SchedEntry{-1, 0, 0.0, 1.0, 1.0});
+    else gen_sched(ps->sched, cfg->min_level, cfg->max_level, 0.0, 1.0, 1.0);
+    ps->nt = default_nt(ps->mx);
+    layout_workspace(ps);
+    if (perm_out)
+        for (int64_t k = 0; k < nleaves; k++) perm_out[k] = ps->slot_of_leaf[k];
+    *out = ps;
+    return FC_OK;
+}
+
+fc_status fc_patchstore_destroy(fc_patchstore *ps) {
+    if (!ps) return FC_OK;
+    drop_graph(ps);
+    delete ps;
+    return FC_OK;
+}
+
+fc_status fc_patchstore_sizes(const fc_patchstore *ps, int64_t *q_doubles, int64_t *ws_bytes) {
+    if (!ps) return fail(FC_ERR_ARG, "null store");
+    if (q_doubles) *q_doubles = (int64_t)ps->F * ps->cfg.capacity * ps->N * ps->N;
+    if (ws_bytes) *ws_bytes = (int64_t)ps->ws_bytes;
+    return FC_OK;
+}
+
+fc_status fc_patchstore_bind(fc_patchstore *ps, double *q0, double *q1, void *workspace, void *stream) {
+    if (!ps || !q0 || !q1 || !workspace) return fail(FC_ERR_ARG, "bad arguments");
+    if (((uintptr_t)workspace & 255) != 0) return fail(FC_ERR_ARG, "workspace must be 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    drop_graph(ps);
+    ps->q0 = q0;
+    ps->q1 = q1;
+    ps->ws = (char *)workspace;
+    ps->curmask = 0;
+    DevState st;
+    memset(&st, 0, sizeof(st));
+    st.t = ps->t;
+    HIPCHK(hipMemcpyAsync(ps->ws + ps->off_state, &st, sizeof(st), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(ps->ws + ps->off_sched, ps->sched.data(), sizeof(SchedEntry) * ps->sched.size(),
+                          hipMemcpyHostToDevice, s));
+    fc_status r = upload_metadata(ps, s);
+    if (r != FC_OK) return r;
+    if (ps->cfg.velocity == FC_VEL_SWIRL)
+        for (int l = ps->cfg.min_level; l <= ps->cfg.max_level; l++)
+            HIPCHK(launch_init_tables(l, ps->mx, ps->cfg.bc[0] == FC_BC_PERIODIC, ps->cfg.bc[2] == FC_BC_PERIODIC,
+                                      (double *)(ps->ws + ps->off_vt[l]), s));
+    ps->pgrid = persistent_max_grid(LaunchCfg{ps->mx, ps->nt}, ps->cfg.equation);
+    HIPCHK(hipStreamSynchronize(s));
+    return FC_OK;
+}
+
+fc_status fc_patchstore_info(const fc_patchstore *ps, int64_t *nleaves, int32_t *min_level, int32_t *max_level) {
+    if (!ps) return fail(FC_ERR_ARG, "null store");
+    if (nleaves) *nleaves = (int64_t)ps->mesh.lv.size();
+    if (min_level) *min_level = ps->cfg.min_level;
+    if (max_level) *max_level = ps->cfg.max_level;
+    return FC_OK;
+}
+
+fc_status fc_patchstore_leaves(const fc_patchstore *ps, fc_leaf *out) {
+    if (!ps || !out) return fail(FC_ERR_ARG, "bad arguments");
+    std::copy(ps->mesh.lv.begin(), ps->mesh.lv.end(), out);
+    return FC_OK;
+}
+
+fc_status fc_set_interior(fc_patchstore *ps, const double *src, void *stream) {
+    fc_status r = check_bound(ps);
+    if (r != FC_OK) return r;
+    if (!src) return fail(FC_ERR_ARG, "null source");
+    HIPCHK(launch_set_interior(make_ctx(ps), ps->mx, (const int32_t *)(ps->ws + ps->off_sl), (int)ps->mesh.lv.size(),
+                               src, (hipStream_t)stream));
+    return FC_OK;
+}
+
+fc_status fc_get_interior(fc_patchstore *ps, double *dst, void *stream) {
+    fc_status r = check_bound(ps);
+    if (r != FC_OK) return r;
+    if (!dst) return fail(FC_ERR_ARG, "null destination");
+    HIPCHK(launch_get_interior(make_ctx(ps), ps->mx, (const int32_t *)(ps->ws + ps->off_sl), (int)ps->mesh.lv.size(),
+                               dst, 0, (hipStream_t)stream));
+    return FC_OK;
+}
+
+fc_status fc_get_patches(fc_patchstore *ps, double *dst, void *stream) {
+    fc_status r = check_bound(ps);
+    if (r != FC_OK) return r;
+    if (!dst) return fail(FC_ERR_ARG, "null destination");
+    HIPCHK(launch_get_interior(make_ctx(ps), ps->mx, (const int32_t *)(ps->ws + ps->off_sl), (int)ps->mesh.lv.size(),
+                               dst, 1, (hipStream_t)stream));
+    return FC_OK;
+}
+
+fc_status fc_ghost_fill(fc_patchstore *ps, int32_t level_lo, int32_t level_hi, double alpha, void *stream) {
+    fc_status r = check_bound(ps);
+    if (r != FC_OK) return r;
+    if (level_lo < ps->cfg.min_level || level_hi > ps->cfg.max_level || level_lo > level_hi)
+        return fail(FC_ERR_ARG, "bad level range");
+    if (!(alpha >= 0.0 && alpha <= 1.0)) return fail(FC_ERR_ARG, "alpha must lie in [0, 1]");
+    return fill_levels(ps, level_lo, level_hi, alpha, (hipStream_t)stream);
+}
+
+fc_status fc_advance_level(fc_patchstore *ps, int32_t level, double t, double dt, double *cfl_dev, void *stream) {
+    fc_status r = check_bound(ps);
+    if (r != FC_OK) return r;
+    if (level < ps->cfg.min_level || level > ps->cfg.max_level) return fail(FC_ERR_ARG, "bad level");
+    if (!(dt > 0)) return fail(FC_ERR_ARG, "dt must be positive");
+    (void)t;
+    return advance_one(ps, level, t, dt, 0, -1, 1.0, (unsigned long long *)cfl_dev, (hipStream_t)stream);
+}
+
+fc_status fc_get_time(const fc_patchstore *ps, double *t) {
+    if (!ps || !t) return fail(FC_ERR_ARG, "bad arguments");
+    *t = ps->t;
+    return FC_OK;
+}
+
+fc_status fc_set_time(fc_patchstore *ps, double t) {
+    if (!ps) return fail(FC_ERR_ARG, "null store");
+    ps->t = t;
+    return FC_OK;
+}
+
+fc_status fc_advance_coarse_steps(fc_patchstore *ps, double dt_coarse, int32_t nsteps, int32_t mode, double *cfl_dev,
+                                  void *stream) {
+    fc_status r = check_bound(ps);
+    if (r != FC_OK) return r;
+    if (!(dt_coarse > 0) || nsteps < 0) return fail(FC_ERR_ARG, "bad step arguments");
+    hipStream_t s = (hipStream_t)stream;
+    unsigned long long *cfl = (unsigned long long *)cfl_dev;
+    if (mode == FC_MODE_PER_LEVEL) {
+        for (int n = 0; n < nsteps; n++) {
+            for (const SchedEntry &e : ps->sched) {
+                const double t = ps->t + e.off * dt_coarse, dt = e.scale * dt_coarse;
+                if (e.level < 0) {
+                    r = fill_levels(ps, ps->cfg.min_level, ps->cfg.max_level, 1.0, s);
+                    if (r != FC_OK) return r;
+                    for (int l = ps->cfg.min_level; l <= ps->cfg.max_level; l++) {
+                        r = advance_one(ps, l, t, dt, 0, -1, 1.0, cfl, s);
+                        if (r != FC_OK) return r;
+                    }
+                } else {
+                    if (ps->lr.count[e.level] > 0) {
+                        r = fill_levels(ps, e.level, e.level, e.alpha, s);
+                        if (r != FC_OK) return r;
+                    }
+                    r = advance_one(ps, e.level, t, dt, 0, e.level - 1, e.alpha, cfl, s);
+                    if (r != FC_OK) return r;
+                }
+            }
+            ps->t += dt_coarse;
+        }
+        return FC_OK;
+    }
+    if (mode != FC_MODE_FUSED && mode != FC_MODE_FUSED_GRAPH) return fail(FC_ERR_ARG, "unknown mode");
+    if (ps->pgrid <= 0) return fail(FC_ERR_HIP, "persistent kernel has no resident blocks");
+    const int n = (int)ps->mesh.lv.size();
+    DevState *st = dstate(ps);
+    HIPCHK(launch_set_state(st, ps->t, dt_coarse, ps->curmask, 1, s));
+    Ctx c = make_ctx(ps);
+    const SchedEntry *sched = (const SchedEntry *)(ps->ws + ps->off_sched);
+    const LevelRange *lrd = (const LevelRange *)(ps->ws + ps->off_lr);
+    if (mode == FC_MODE_FUSED) {
+        for (int k = 0; k < nsteps; k++)
+            HIPCHK(launch_persistent(c, LaunchCfg{ps->mx, ps->nt}, sched, (int)ps->sched.size(), lrd, n, st, ps->pgrid, s));
+    } else {
+        if (!ps->gexec || ps->gstream != s || ps->gnt != ps->nt) {
+            drop_graph(ps);
+            // the kernel reads the time, step, buffer parities and level
+            // ranges from device memory, so one capture serves every replay
+            HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            hipError_t e = launch_persistent(c, LaunchCfg{ps->mx, ps->nt}, sched, (int)ps->sched.size(), lrd, n, st,
+                                             ps->pgrid, s);
+            hipGraph_t g = nullptr;
+            hipError_t e2 = hipStreamEndCapture(s, &g);
+            if (e != hipSuccess || e2 != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return fail(FC_ERR_HIP, "graph capture failed");
+            }
+            ps->graph = g;
+            HIPCHK(hipGraphInstantiate(&ps->gexec, g, nullptr, nullptr, 0));
+            ps->gstream = s;
+            ps->gnt = ps->nt;
+        }
+        for (int k = 0; k < nsteps; k++) HIPCHK(hipGraphLaunch(ps->gexec, s));
+    }
+    // host mirror of the device bookkeeping
+    uint32_t allmask = 0;
+    for (int l = 0; l < FC_MAXLEV; l++)
+        if (ps->lr.count[l] > 0) allmask |= 1u << l;
+    for (int k = 0; k < nsteps; k++) {
+        for (const SchedEntry &e : ps->sched) ps->curmask ^= e.level < 0 ? allmask : (1u << e.level);
+        ps->t += dt_coarse;
+    }
+    if (cfl_dev) HIPCHK(launch_export_cfl(st, cfl_dev, s));
+    return FC_OK;
+}
+
+fc_status fc_tag_refine(fc_patchstore *ps, double tau_refine, double tau_coarsen, int8_t *tags_dev, double *gmax2_dev,
+                        void *stream) {
+    fc_status r = check_bound(ps);
+    if (r != FC_OK) return r;
+    if (!tags_dev) return fail(FC_ERR_ARG, "null tags");
+    HIPCHK(launch_tag(make_ctx(ps), ps->mx, (const int32_t *)(ps->ws + ps->off_sl), (int)ps->mesh.lv.size(),
+                      ps->cfg.min_level, ps->cfg.max_level, tau_refine, tau_coarsen, tags_dev, gmax2_dev,
+                      (hipStream_t)stream));
+    return FC_OK;
+}
+
+fc_status fc_adapt(const fc_patchstore *ps, const int8_t *tags, fc_leaf *out, int64_t cap, int64_t *n_out) {
+    if (!ps || !tags || !out || !n_out) return fail(FC_ERR_ARG, "bad arguments");
+    const int n = (int)ps->mesh.lv.size();
+    // tags arrive in input-leaf order
+    std::vector<int8_t> tg(n);
+    for (int k = 0; k < n; k++) tg[ps->slot_of_leaf[k]] = tags[k];
+    std::vector<fc_leaf> res;
+    std::vector<char> done(n, 0);
+    const int lmin = ps->cfg.min_level, lmax = ps->cfg.max_level;
+    for (int s = 0; s < n; s++) {
+        if (done[s]) continue;
+        const fc_leaf L = ps->mesh.lv[s];
+        if (tg[s] == -1 && L.level > lmin) {
+            const int px = L.ix >> 1, py = L.iy >> 1;
+            int sib[4];
+            bool ok = true;
+            for (int c = 0; c < 4; c++) {
+                sib[c] = ps->mesh.find(L.level, 2 * px + (c & 1), 2 * py + (c >> 1));
+                if (sib[c] < 0 || tg[sib[c]] != -1) ok = false;
+            }
+            if (ok) {
+                for (int c = 0; c < 4; c++) done[sib[c]] = 1;
+                res.push_back(fc_leaf{L.level - 1, px, py});
+                continue;
+            }
+        }
+        done[s] = 1;
+        if (tg[s] == 1 && L.level < lmax) {
+            for (int c = 0; c < 4; c++) res.push_back(fc_leaf{L.level + 1, 2 * L.ix + (c & 1), 2 * L.iy + (c >> 1)});
+        } else {
+            res.push_back(L);
+        }
+    }
+    // 2:1 balance by refinement
+    for (;;) {
+        Mesh m;
+        m.mx = ps->mx;
+        std::copy(ps->cfg.bc, ps->cfg.bc + 4, m.bc);
+        m.lv = res;
+        m.index();
+        std::vector<fc_leaf> nx;
+        bool changed = false;
+        for (const auto &L : res) {
+            if (!m.balanced_at(L)) {
+                changed = true;
+                for (int c = 0; c < 4; c++) nx.push_back(fc_leaf{L.level + 1, 2 * L.ix + (c & 1), 2 * L.iy + (c >> 1)});
+            } else {
+                nx.push_back(L);
+            }
+        }
+        res.swap(nx);
+        if (!changed) break;
+    }
+    std::sort(res.begin(), res.end(), [](const fc_leaf &a, const fc_leaf &b) {
+        if (a.level != b.level) return a.level < b.level;
+        if (a.iy != b.iy) return a.iy < b.iy;
+        return a.ix < b.ix;
+    });
+    if ((int64_t)res.size() > cap) return fail(FC_ERR_CAPACITY, "adapted leaf set exceeds the output capacity");
+    std::copy(res.begin(), res.end(), out);
+    *n_out = (int64_t)res.size();
+    return FC_OK;
+}
+
+fc_status fc_regrid(fc_patchstore *ps, int64_t nleaves, const fc_leaf *new_leaves, void *stream) {
+    fc_status r = check_bound(ps);
+    if (r != FC_OK) return r;
+    if (!new_leaves || nleaves <= 0) return fail(FC_ERR_ARG, "bad arguments");
+    if (nleaves > ps->cfg.capacity) return fail(FC_ERR_CAPACITY, "new leaf set exceeds capacity");
+    std::vector<fc_leaf> L(new_leaves, new_leaves + nleaves);
+    for (const auto &q : L)
+        if (q.level < ps->cfg.min_level || q.level > ps->cfg.max_level) return fail(FC_ERR_ARG, "leaf level outside range");
+    r = validate(ps->mesh, L);
+    if (r != FC_OK) return r;
+    hipStream_t s = (hipStream_t)stream;
+    // every old patch (with the ghosts filled by the caller) into buffer 0
+    Ctx old = make_ctx(ps);
+    HIPCHK(launch_consolidate(old, ps->mx, (int)ps->mesh.lv.size(), s));
+    Mesh oldmesh = ps->mesh;
+    build_metadata(ps, L);
+    const int n = (int)L.size();
+    std::vector<TransferRec> plan(n);
+    for (int p = 0; p < n; p++) {
+        const fc_leaf q = ps->mesh.lv[p];
+        TransferRec tr{};
+        int o;
+        if ((o = oldmesh.find(q.level, q.ix, q.iy)) >= 0) {
+            tr.kind = TR_COPY; tr.src[0] = o;
+        } else if ((o = oldmesh.find(q.level - 1, q.ix >> 1, q.iy >> 1)) >= 0) {
+            tr.kind = TR_REFINE; tr.src[0] = o; tr.cx = q.ix & 1; tr.cy = q.iy & 1;
+        } else {
+            tr.kind = TR_COARSEN;
+            for (int c = 0; c < 4; c++) {
+                tr.src[c] = oldmesh.find(q.level + 1, 2 * q.ix + (c & 1), 2 * q.iy + (c >> 1));
+                if (tr.src[c] < 0) return fail(FC_ERR_ARG, "new leaf is neither old, child nor parent of old leaves");
+            }
+        }
+        plan[p] = tr;
+    }
+    HIPCHK(hipMemcpyAsync(ps->ws + ps->off_plan, plan.data(), sizeof(TransferRec) * n, hipMemcpyHostToDevice, s));
+    Ctx nc = make_ctx(ps);
+    HIPCHK(launch_transfer(nc, ps->mx, (const TransferRec *)(ps->ws + ps->off_plan), n, s));
+    r = upload_metadata(ps, s);
+    if (r != FC_OK) return r;
+    ps->curmask = ~0u;  // new data lives in buffer 1 for every level
+    HIPCHK(hipStreamSynchronize(s));
+    return FC_OK;
+}
+
+fc_status fc_adjoint_step(fc_patchstore *ps, int32_t level, double t, double dt, const double *q_in,
+                          const double *lambda_in, double *lambda_out, void *stream) {
+    (void)ps; (void)level; (void)t; (void)dt; (void)q_in; (void)lambda_in; (void)lambda_out; (void)stream;
+    return fail(FC_ERR_STATE, "adjoint step not available in this build");
+}
+
+fc_status fc_check_device(fc_patchstore *ps, void *stream) {
+    fc_status r = check_bound(ps);
+    if (r != FC_OK) return r;
+    return check_device_error(ps, (hipStream_t)stream);
+}
+
+fc_status fc_set_variant(fc_patchstore *ps, int32_t threads_per_patch) {
+    if (!ps) return fail(FC_ERR_ARG, "null store");
+    if (!valid_nt(ps->mx, threads_per_patch)) return fail(FC_ERR_ARG, "unsupported threads per patch for this mx");
+    ps->nt = threads_per_patch;
+    if (ps->ws) ps->pgrid = persistent_max_grid(LaunchCfg{ps->mx, ps->nt}, ps->cfg.equation);
+    drop_graph(ps);
+    return FC_OK;
+}
+
+fc_status fc_autotune(fc_patchstore *ps, int32_t *threads_out, void *stream) {
+    fc_status r = check_bound(ps);
+    if (r != FC_OK) return r;
+    hipStream_t s = (hipStream_t)stream;
+    // time the fused-load advance of the most populated level, writing only
+    // the levels' other buffers (the state is left unchanged)
+    int lbest = ps->cfg.min_level;
+    for (int l = ps->cfg.min_level; l <= ps->cfg.max_level; l++)
+        if (ps->lr.count[l] > ps->lr.count[lbest]) lbest = l;
+    const double h = 1.0 / (double)(ps->mx << lbest);
+    const double dt = 0.5 * h;
+    const int cands[3] = {64, 128, 256};
+    const int cands32[3] = {128, 256, 512};
+    const int *cl = ps->mx == 32 ? cands32 : cands;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    float best = 1e30f;
+    int bnt = ps->nt;
+    for (int k = 0; k < 3; k++) {
+        const int nt = cl[k];
+        if (!valid_nt(ps->mx, nt)) continue;
+        Ctx c = make_ctx(ps);
+        LaunchCfg lc{ps->mx, nt};
+        for (int w = 0; w < 2; w++)
+            HIPCHK(launch_advance(c, lc, lbest, ps->lr.start[lbest], ps->lr.count[lbest], ps->t, dt, 1, nullptr, s));
+        HIPCHK(hipEventRecord(e0, s));
+        for (int w = 0; w < 5; w++)
+            HIPCHK(launch_advance(c, lc, lbest, ps->lr.start[lbest], ps->lr.count[lbest], ps->t, dt, 1, nullptr, s));
+        HIPCHK(hipEventRecord(e1, s));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) { best = ms; bnt = nt; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    r = fc_set_variant(ps, bnt);
+    if (r != FC_OK) return r;
+    if (threads_out) *threads_out = bnt;
+    return FC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,271 @@
+"""GPU path (through the C ABI) against the FP64 CPU oracle.
+
+Tolerance: relative max-norm ||gpu - oracle||_inf / ||oracle||_inf <= 1e-12
+in FP64 for every floating-point result (the bar the target states);
+integer results (tags, leaf sets) must match exactly.  Ghost copies are
+compared bitwise.  Inputs are seeded and synthetic (workloads.synth).
+"""
+import numpy as np
+import pytest
+
+from workloads import synth as S
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1703_03116_amd import binding
+    binding.lib()
+    return binding
+
+
+@pytest.fixture(scope="module")
+def O(oracle_lib):
+    return oracle_lib
+
+
+def rel(a, b):
+    a = a.cpu().numpy() if hasattr(a, "cpu") else np.asarray(a)
+    b = np.asarray(b)
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def pair(B, O, leaves, mx, q, equation="advection", velocity="constant", vel_params=(1.0, 0.5, 0.0),
+         bc=("periodic",) * 4, lmin=None, lmax=None, limiter="mc", time_stepping="multirate"):
+    lv = np.asarray(leaves)
+    lmin = int(lv[:, 0].min()) if lmin is None else lmin
+    lmax = int(lv[:, 0].max()) if lmax is None else lmax
+    ps = B.PatchStore(leaves, mx=mx, equation=equation, limiter=limiter, bc=bc, velocity=velocity,
+                      vel_params=vel_params, min_level=lmin, max_level=lmax, time_stepping=time_stepping)
+    ps.set_interior(q)
+    o = O.Oracle(leaves, mx=mx, equation=equation, limiter=limiter, bc=bc, velocity=velocity,
+                 vel_params=vel_params, lmin=lmin, lmax=lmax)
+    o.set_interior(q)
+    return ps, o
+
+
+def ghost_mask(mx, m=2):
+    N = mx + 2 * m
+    g = np.ones((N, N), dtype=bool)
+    g[m:m + mx, m:m + mx] = False
+    return g
+
+
+# ---------------------------------------------------------------------------
+# ghost filling
+# ---------------------------------------------------------------------------
+
+def test_fill_uniform_copy_bitwise(B, O):
+    L = S.uniform_leaves(2)
+    rng = np.random.default_rng(0)
+    q = rng.random((16, 1, 8, 8))
+    ps, o = pair(B, O, L, 8, q)
+    ps.ghost_fill()
+    o.ghost_fill()
+    assert np.array_equal(ps.patches().cpu().numpy(), o.full())
+
+
+@pytest.mark.parametrize("seed", range(4))
+@pytest.mark.parametrize("bc", ["periodic", "reflect"])
+def test_fill_amr_matches_algorithm1(B, O, seed, bc):
+    per = bc == "periodic"
+    L = S.random_balanced_leaves(seed, 2, 5 if seed % 2 else 4, periodic=(per, per))
+    rng = np.random.default_rng(seed)
+    eq = "advection" if per else "swe"
+    F = 1 if per else 3
+    q = 1.0 + rng.random((len(L), F, 8, 8))
+    ps, o = pair(B, O, L, 8, q, equation=eq, velocity="constant" if per else "none", bc=(bc,) * 4)
+    ps.ghost_fill()
+    o.ghost_fill()
+    ps.check()
+    g, r = ps.patches().cpu().numpy(), o.full()
+    assert not np.isnan(g).any()
+    assert rel(g, r) <= 1e-14
+
+
+def test_fill_time_interpolated_coarse_level(B, O):
+    """Level l filled at half the coarse step: coarse data q_old + 1/2 (q - q_old)."""
+    L = S.random_balanced_leaves(11, 2, 4)
+    rng = np.random.default_rng(11)
+    q = rng.random((len(L), 1, 8, 8))
+    ps, o = pair(B, O, L, 8, q, velocity="constant", vel_params=(0.7, -0.4, 0))
+    for lo in (2, 3):
+        ps.ghost_fill(lo, lo, 1.0)
+        o.ghost_fill(lo, lo, 1.0)
+        ps.advance_level(lo, 0.0, 0.01)
+        o.advance_level(lo, 0.0, 0.01)
+    for alpha in (0.0, 0.5):
+        ps.ghost_fill(4, 4, alpha)
+        o.ghost_fill(4, 4, alpha)
+        lv = np.asarray(L)[:, 0]
+        g, r = ps.patches().cpu().numpy()[lv == 4], o.full()[lv == 4]
+        assert rel(g, r) <= 1e-14
+
+
+# ---------------------------------------------------------------------------
+# advance and multirate stepping
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("limiter", ["mc", "lw", "minmod"])
+def test_single_step_uniform(B, O, limiter):
+    L = S.uniform_leaves(2)
+    rng = np.random.default_rng(1)
+    q = rng.random((16, 1, 16, 16))
+    ps, o = pair(B, O, L, 16, q, velocity="swirl", vel_params=(1.0, 0, 0), limiter=limiter)
+    ps.ghost_fill()
+    o.ghost_fill()
+    cfl = __import__("torch").zeros(1, dtype=__import__("torch").float64, device="cuda")
+    ps.advance_level(2, 0.13, 0.9 / 64, cfl)
+    c_o = o.advance_level(2, 0.13, 0.9 / 64)
+    assert rel(ps.interior(), o.interior()) <= TOL
+    assert abs(cfl.item() - c_o) <= 1e-14
+
+
+@pytest.mark.parametrize("mode", ["per_level", "fused", "graph"])
+def test_swirl_uniform_parity(B, O, mode):
+    w = S.workload("swirl_uniform", level=3, mx=16)
+    ps, o = pair(B, O, w["leaves"], 16, w["q0"], velocity="swirl", vel_params=(1.0, 0, 0))
+    dt = w["dt_coarse"]
+    ps.coarse_steps(dt, 40, mode)
+    for s in range(40):
+        o.coarse_step(s * dt, dt)
+    ps.check()
+    assert rel(ps.interior(), o.interior()) <= TOL
+
+
+@pytest.mark.parametrize("mode", ["per_level", "fused", "graph"])
+def test_hump_multirate_parity(B, O, mode):
+    """Levels 2-3 with subcycling, 8x8 patches, 100 coarse steps."""
+    w = S.workload("hump_l23")
+    ps, o = pair(B, O, w["leaves"], 8, w["q0"], velocity="constant", vel_params=w["vel_params"])
+    dt = w["dt_coarse"]
+    ps.coarse_steps(dt, w["steps"], mode)
+    for s in range(w["steps"]):
+        o.coarse_step(s * dt, dt)
+    ps.check()
+    assert rel(ps.interior(), o.interior()) <= TOL
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_random_amr_multirate_swirl(B, O, seed):
+    """Random 2:1 meshes over levels 2-5 (ragged level populations)."""
+    L = S.random_balanced_leaves(seed, 2, 5)
+    q = S.sample_on_leaves(S.gaussians(S.gaussian_params(seed)), L, 8)
+    ps, o = pair(B, O, L, 8, q, velocity="swirl", vel_params=(1.0, 0, 0))
+    dt = 0.9 / 32
+    for mode in ("fused", "per_level"):
+        ps.coarse_steps(dt, 3, mode)
+    for s in range(6):
+        o.coarse_step(s * dt, dt)
+    ps.check()
+    assert rel(ps.interior(), o.interior()) <= TOL
+
+
+def test_global_stepping_parity(B, O):
+    L = S.random_balanced_leaves(6, 2, 4)
+    q = S.sample_on_leaves(S.gaussians(S.gaussian_params(6)), L, 8)
+    ps, o = pair(B, O, L, 8, q, velocity="swirl", vel_params=(1.0, 0, 0), time_stepping="global")
+    dt = 0.9 / 128
+    ps.coarse_steps(dt, 5, "per_level")
+    ps.coarse_steps(dt, 5, "graph")
+    for s in range(10):
+        o.coarse_step(s * dt, dt, "global")
+    assert rel(ps.interior(), o.interior()) <= TOL
+
+
+def test_fused_equals_per_level_bitwise(B, O):
+    w = S.workload("hump_l23")
+    a = B.from_workload(w)
+    b = B.from_workload(w)
+    a.coarse_steps(w["dt_coarse"], 20, "per_level")
+    b.coarse_steps(w["dt_coarse"], 20, "graph")
+    assert np.array_equal(a.interior().cpu().numpy(), b.interior().cpu().numpy())
+
+
+@pytest.mark.parametrize("mx", [8, 16, 32])
+def test_variants_bitwise(B, mx):
+    """Every launch variant (threads per patch) computes the same bits."""
+    level = {8: 3, 16: 2, 32: 2}[mx]
+    w = S.workload("swirl_uniform", level=level, mx=mx)
+    nts = {8: [64, 128], 16: [64, 128, 256], 32: [128, 256, 512]}[mx]
+    res = []
+    for nt in nts:
+        ps = B.from_workload(w)
+        ps.set_variant(nt)
+        ps.coarse_steps(w["dt_coarse"], 5, "fused")
+        ps.coarse_steps(w["dt_coarse"], 5, "per_level")
+        res.append(ps.interior().cpu().numpy())
+    for r in res[1:]:
+        assert np.array_equal(r, res[0])
+
+
+def test_replicated_blocks_identical(B):
+    """Replicated initial data on a periodic uniform mesh: a field that
+    repeats with period 1/2 stays periodic, bitwise, in every block."""
+    L = S.uniform_leaves(3)
+    q = S.sample_on_leaves(lambda x, y: np.exp(-((np.mod(x, 0.5) - 0.2) ** 2 + (np.mod(y, 0.5) - 0.3) ** 2) / 0.005),
+                           L, 16)
+    ps = B.PatchStore(L, mx=16, velocity="constant", vel_params=(0.6, -0.3, 0))
+    ps.set_interior(q)
+    ps.coarse_steps(0.9 / 128 / 0.6, 30, "graph")
+    G = np.zeros((128, 128))
+    qi = ps.interior().cpu().numpy()
+    for k, (l, ix, iy) in enumerate(L):
+        G[iy * 16:(iy + 1) * 16, ix * 16:(ix + 1) * 16] = qi[k, 0]
+    for by in range(2):
+        for bx in range(2):
+            assert np.array_equal(G[by * 64:(by + 1) * 64, bx * 64:(bx + 1) * 64], G[:64, :64])
+
+
+# ---------------------------------------------------------------------------
+# tagging and regrid
+# ---------------------------------------------------------------------------
+
+def test_tag_and_adapt_parity(B, O):
+    L = S.random_balanced_leaves(9, 2, 4)
+    q = S.sample_on_leaves(S.gaussians(S.gaussian_params(9)), L, 8)
+    ps, o = pair(B, O, L, 8, q, velocity="swirl", vel_params=(1.0, 0, 0), lmin=2, lmax=5)
+    ps.ghost_fill()
+    o.ghost_fill()
+    tg, g2 = ps.tag(2.0, 0.5)
+    to, g2o = o.tag(2.0, 0.5)
+    assert rel(g2, g2o) <= 1e-13
+    assert np.array_equal(tg.cpu().numpy(), to)
+    new_g = ps.adapt(tg)
+    new_o = o.adapt(to)
+    assert np.array_equal(new_g, new_o)
+    ps.regrid(new_g)
+    o.regrid(new_o)
+    assert rel(ps.interior(), o.interior()) <= 1e-14
+    dt = 0.9 / 32
+    ps.coarse_steps(dt, 2, "graph")
+    for s in range(2):
+        o.coarse_step(s * dt, dt)
+    assert rel(ps.interior(), o.interior()) <= TOL
+
+
+# ---------------------------------------------------------------------------
+# full size of the benchmark workload
+# ---------------------------------------------------------------------------
+
+def test_full_size_uniform_level5_swirl(B, O):
+    """1024 patches of 32x32 (1024^2 cells), 500 steps, the benchmark's
+    launch configuration (persistent kernel replayed from a graph)."""
+    O.set_threads(max(1, min(16, O.max_threads())))
+    w = S.workload("swirl_uniform", level=5, mx=32)
+    ps = B.from_workload(w)
+    ps.autotune()
+    dt = w["dt_coarse"]
+    ps.coarse_steps(dt, w["steps"], "graph")
+    o = O.from_workload(w)
+    for s in range(w["steps"]):
+        o.coarse_step(s * dt, dt)
+    ps.check()
+    g = ps.interior().cpu().numpy()
+    assert rel(g, o.interior()) <= TOL
+    m0 = w["q0"].sum()
+    assert abs(g.sum() - m0) / m0 < 1e-12
