@@ -60,7 +60,7 @@ enum { FC_BC_PERIODIC = 0, FC_BC_REFLECT = 1 };
 enum { FC_VEL_NONE = 0, FC_VEL_CONSTANT = 1, FC_VEL_SWIRL = 2 };
 enum { FC_LIM_MC = 0, FC_LIM_LW = 1, FC_LIM_FIRST = 2, FC_LIM_MINMOD = 3 };
 enum { FC_STEP_MULTIRATE = 0, FC_STEP_GLOBAL = 1 };
-enum { FC_MODE_PER_LEVEL = 0, FC_MODE_FUSED = 1, FC_MODE_FUSED_GRAPH = 2 };
+enum { FC_MODE_PER_LEVEL = 0, FC_MODE_FUSED = 1, FC_MODE_FUSED_GRAPH = 2, FC_MODE_FUSED_LEVELS = 3 };
 
 /* A quadrant of the single unit-square block: 0 <= ix, iy < 2^level. */
 typedef struct { int32_t level, ix, iy; } fc_leaf;
@@ -147,7 +147,9 @@ fc_status fc_advance_level(fc_patchstore *ps, int32_t level, double t, double dt
  * mode FC_MODE_PER_LEVEL: a fill launch and an advance launch per
  * level-step; FC_MODE_FUSED: one persistent kernel that evaluates ghosts on
  * the fly and walks all level-steps with device-wide barriers;
- * FC_MODE_FUSED_GRAPH: the fused kernel replayed from a captured hipGraph.
+ * FC_MODE_FUSED_GRAPH: the fused kernel replayed from a captured hipGraph;
+ * FC_MODE_FUSED_LEVELS: one launch per level-step of the advance kernel
+ * that evaluates its ghosts on the fly (no fill launch, no device barrier).
  * nsteps coarse steps are taken.  cfl_dev as above.  The store's time
  * advances by nsteps * dt_coarse. */
 fc_status fc_advance_coarse_steps(fc_patchstore *ps, double dt_coarse, int32_t nsteps, int32_t mode,
@@ -197,6 +199,10 @@ fc_status fc_check_device(fc_patchstore *ps, void *stream);
  * Returns the chosen threads per patch. */
 fc_status fc_autotune(fc_patchstore *ps, int32_t *threads_out, void *stream);
 fc_status fc_set_variant(fc_patchstore *ps, int32_t threads_per_patch);
+/* Workgroups of the persistent kernel: 0 = as many as can be co-resident
+ * (occupancy x compute units), else min(grid, that).  max_grid (may be
+ * NULL) receives the co-resident maximum. */
+fc_status fc_set_persistent_grid(fc_patchstore *ps, int32_t grid, int32_t *max_grid);
 
 #ifdef __cplusplus
 }

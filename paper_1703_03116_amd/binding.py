@@ -21,7 +21,7 @@ BC = {"periodic": 0, "reflect": 1}
 VEL = {"none": 0, "constant": 1, "swirl": 2}
 LIM = {"mc": 0, "lw": 1, "first": 2, "minmod": 3}
 STEP = {"multirate": 0, "global": 1}
-MODE = {"per_level": 0, "fused": 1, "graph": 2}
+MODE = {"per_level": 0, "fused": 1, "graph": 2, "fused_levels": 3}
 
 FC_ERRORS = {-1: "FC_ERR_ARG", -2: "FC_ERR_UNBALANCED", -3: "FC_ERR_GHOST_WIDTH", -4: "FC_ERR_HIP",
              -5: "FC_ERR_CFL", -6: "FC_ERR_STATE", -7: "FC_ERR_CAPACITY", -8: "FC_ERR_COVER"}
@@ -30,7 +30,7 @@ EXPORTS = ["fc_last_error", "fc_patchstore_create", "fc_patchstore_destroy", "fc
            "fc_patchstore_bind", "fc_patchstore_info", "fc_patchstore_leaves", "fc_set_interior",
            "fc_get_interior", "fc_get_patches", "fc_ghost_fill", "fc_advance_level",
            "fc_advance_coarse_steps", "fc_get_time", "fc_set_time", "fc_tag_refine", "fc_adapt", "fc_regrid",
-           "fc_adjoint_step", "fc_check_device", "fc_autotune", "fc_set_variant"]
+           "fc_adjoint_step", "fc_check_device", "fc_autotune", "fc_set_variant", "fc_set_persistent_grid"]
 
 
 class FcError(RuntimeError):
@@ -83,6 +83,7 @@ def lib():
         L.fc_check_device.argtypes = [vp, vp]
         L.fc_autotune.argtypes = [vp, C.POINTER(C.c_int32), vp]
         L.fc_set_variant.argtypes = [vp, C.c_int32]
+        L.fc_set_persistent_grid.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32)]
         for f in EXPORTS:
             if f != "fc_last_error":
                 getattr(L, f).restype = C.c_int32
@@ -245,6 +246,12 @@ class PatchStore:
 
     def set_variant(self, threads_per_patch):
         _check(lib().fc_set_variant(self._h, int(threads_per_patch)))
+
+    def set_persistent_grid(self, grid=0):
+        """Persistent-kernel workgroups (0: all that fit); returns the maximum."""
+        mg = C.c_int32()
+        _check(lib().fc_set_persistent_grid(self._h, int(grid), C.byref(mg)))
+        return mg.value
 
 
 def from_workload(w, limiter="mc", capacity=None, time_stepping=None):

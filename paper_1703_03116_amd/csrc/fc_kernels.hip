@@ -27,20 +27,35 @@ __device__ __forceinline__ size_t qidx(int cap, int N, int f, int p, int i, int 
     return ((size_t)(f * cap + p) * N + (j + MB)) * N + (i + MB);
 }
 
-__device__ __forceinline__ double *buf_of(const Ctx &c, int l) { return ((c.curmask >> l) & 1u) ? c.q1 : c.q0; }
-__device__ __forceinline__ double *other_of(const Ctx &c, int l) { return ((c.curmask >> l) & 1u) ? c.q0 : c.q1; }
+// The time-dependent part of a kernel's view of the store: which buffer holds
+// each level's current state, and which level is read time-interpolated.
+// Kept apart from the (read-only, kernel-argument) Ctx so that kernels that
+// walk several level-steps never copy Ctx into private memory.
+struct View {
+    uint32_t curmask;
+    int clevel;
+    double alpha;
+};
+
+__device__ __forceinline__ View view_of(const Ctx &c) { return View{c.curmask, c.clevel, c.alpha}; }
+__device__ __forceinline__ double *buf_of(const Ctx &c, const View &v, int l) {
+    return ((v.curmask >> l) & 1u) ? c.q1 : c.q0;
+}
+__device__ __forceinline__ double *other_of(const Ctx &c, const View &v, int l) {
+    return ((v.curmask >> l) & 1u) ? c.q0 : c.q1;
+}
 
 // State of level l at the fill time: current, or q_old + alpha (q - q_old)
 // for the time-interpolated coarse level.
 template <int MX>
-__device__ __forceinline__ double read_state(const Ctx &c, int p, int l, int i, int j, int f) {
+__device__ __forceinline__ double read_state(const Ctx &c, const View &w, int p, int l, int i, int j, int f) {
     constexpr int N = MX + 2 * MB;
     const size_t k = qidx(c.cap, N, f, p, i, j);
-    const bool b = (c.curmask >> l) & 1u;
+    const bool b = (w.curmask >> l) & 1u;
     double v = (b ? c.q1 : c.q0)[k];
-    if (l == c.clevel && c.alpha != 1.0) {
+    if (l == w.clevel && w.alpha != 1.0) {
         const double vo = (b ? c.q0 : c.q1)[k];
-        v = vo + c.alpha * (v - vo);
+        v = vo + w.alpha * (v - vo);
     }
     return v;
 }
@@ -77,25 +92,25 @@ __device__ __forceinline__ void apply_signs(double *v, double su, double sv) {
 // Cell (i, j) of patch p as a coarse interpolation stencil sees it: its
 // interior, or a ghost by copy / eq. ghost_coarse averaging.
 template <int MX, int F>
-__device__ void coarse_cell(const Ctx &c, int p, int i, int j, double *v) {
+__device__ void coarse_cell(const Ctx &c, const View &w, int p, int i, int j, double *v) {
     const PatchInfo P = c.info[p];
     double su, sv;
     fold<MX>(P.walls, i, j, su, sv);
     if (i >= 0 && i < MX && j >= 0 && j < MX) {
 #pragma unroll
-        for (int f = 0; f < F; f++) v[f] = read_state<MX>(c, p, P.level, i, j, f);
+        for (int f = 0; f < F; f++) v[f] = read_state<MX>(c, w, p, P.level, i, j, f);
     } else {
         const NbrRec r = c.nbr[p * FC_NREC + region_rec<MX>(i, j)];
         if (r.type == NB_SAME) {
 #pragma unroll
-            for (int f = 0; f < F; f++) v[f] = read_state<MX>(c, r.id, P.level, i - r.ox, j - r.oy, f);
+            for (int f = 0; f < F; f++) v[f] = read_state<MX>(c, w, r.id, P.level, i - r.ox, j - r.oy, f);
         } else if (r.type == NB_FINE) {
             const int li = 2 * (i - r.ox), lj = 2 * (j - r.oy), lf = P.level + 1;
 #pragma unroll
             for (int f = 0; f < F; f++)
-                v[f] = 0.25 * (read_state<MX>(c, r.id, lf, li, lj, f) + read_state<MX>(c, r.id, lf, li + 1, lj, f) +
-                               read_state<MX>(c, r.id, lf, li, lj + 1, f) +
-                               read_state<MX>(c, r.id, lf, li + 1, lj + 1, f));
+                v[f] = 0.25 * (read_state<MX>(c, w, r.id, lf, li, lj, f) + read_state<MX>(c, w, r.id, lf, li + 1, lj, f) +
+                               read_state<MX>(c, w, r.id, lf, li, lj + 1, f) +
+                               read_state<MX>(c, w, r.id, lf, li + 1, lj + 1, f));
         } else {
             // a stencil crossing two level curves: excluded by Prop. 2.1
             atomicOr(c.err, 2);
@@ -108,28 +123,28 @@ __device__ void coarse_cell(const Ctx &c, int p, int i, int j, double *v) {
 
 // Ghost value of patch p at local (i, j): the result of Algorithm 1.
 template <int MX, int F>
-__device__ void ghost_cell(const Ctx &c, int p, int i, int j, double *v) {
+__device__ void ghost_cell(const Ctx &c, const View &w, int p, int i, int j, double *v) {
     const PatchInfo P = c.info[p];
     const int l = P.level;
     double su, sv;
     fold<MX>(P.walls, i, j, su, sv);
     if (i >= 0 && i < MX && j >= 0 && j < MX) {
 #pragma unroll
-        for (int f = 0; f < F; f++) v[f] = read_state<MX>(c, p, l, i, j, f);
+        for (int f = 0; f < F; f++) v[f] = read_state<MX>(c, w, p, l, i, j, f);
         apply_signs<F>(v, su, sv);
         return;
     }
     const NbrRec r = c.nbr[p * FC_NREC + region_rec<MX>(i, j)];
     if (r.type == NB_SAME) {
 #pragma unroll
-        for (int f = 0; f < F; f++) v[f] = read_state<MX>(c, r.id, l, i - r.ox, j - r.oy, f);
+        for (int f = 0; f < F; f++) v[f] = read_state<MX>(c, w, r.id, l, i - r.ox, j - r.oy, f);
     } else if (r.type == NB_FINE) {
         const int li = 2 * (i - r.ox), lj = 2 * (j - r.oy);
 #pragma unroll
         for (int f = 0; f < F; f++)
-            v[f] = 0.25 * (read_state<MX>(c, r.id, l + 1, li, lj, f) + read_state<MX>(c, r.id, l + 1, li + 1, lj, f) +
-                           read_state<MX>(c, r.id, l + 1, li, lj + 1, f) +
-                           read_state<MX>(c, r.id, l + 1, li + 1, lj + 1, f));
+            v[f] = 0.25 * (read_state<MX>(c, w, r.id, l + 1, li, lj, f) + read_state<MX>(c, w, r.id, l + 1, li + 1, lj, f) +
+                           read_state<MX>(c, w, r.id, l + 1, li, lj + 1, f) +
+                           read_state<MX>(c, w, r.id, l + 1, li + 1, lj + 1, f));
     } else if (r.type == NB_COARSE) {
         // eq. ghost_fine: q_c + (1/4)(d_x s_x + d_y s_y), s = minmod of the
         // one-sided differences on the coarse grid, d = +1 for the upper half
@@ -138,11 +153,11 @@ __device__ void ghost_cell(const Ctx &c, int p, int i, int j, double *v) {
         const double dx = (I & 1) ? 1.0 : -1.0, dy = (J & 1) ? 1.0 : -1.0;
         double cc[F], xm[F], xp[F], ym[F], yp[F];
 #pragma unroll
-        for (int f = 0; f < F; f++) cc[f] = read_state<MX>(c, r.id, l - 1, ic, jc, f);
-        coarse_cell<MX, F>(c, r.id, ic - 1, jc, xm);
-        coarse_cell<MX, F>(c, r.id, ic + 1, jc, xp);
-        coarse_cell<MX, F>(c, r.id, ic, jc - 1, ym);
-        coarse_cell<MX, F>(c, r.id, ic, jc + 1, yp);
+        for (int f = 0; f < F; f++) cc[f] = read_state<MX>(c, w, r.id, l - 1, ic, jc, f);
+        coarse_cell<MX, F>(c, w, r.id, ic - 1, jc, xm);
+        coarse_cell<MX, F>(c, w, r.id, ic + 1, jc, xp);
+        coarse_cell<MX, F>(c, w, r.id, ic, jc - 1, ym);
+        coarse_cell<MX, F>(c, w, r.id, ic, jc + 1, yp);
 #pragma unroll
         for (int f = 0; f < F; f++) {
             const double sx = minmod(xp[f] - cc[f], cc[f] - xm[f]);
@@ -189,12 +204,13 @@ __global__ void __launch_bounds__(256) fill_kernel(Ctx c, int first) {
     constexpr int N = MX + 2 * MB, NG = N * N - MX * MX;
     const int p = first + blockIdx.x;
     const int l = c.info[p].level;
-    double *out = buf_of(c, l);
+    const View w = view_of(c);
+    double *out = buf_of(c, w, l);
     for (int g = threadIdx.x; g < NG; g += blockDim.x) {
         int i, j;
         ghost_index<MX>(g, i, j);
         double v[F];
-        ghost_cell<MX, F>(c, p, i, j, v);
+        ghost_cell<MX, F>(c, w, p, i, j, v);
 #pragma unroll
         for (int f = 0; f < F; f++) out[qidx(c.cap, N, f, p, i, j)] = v[f];
     }
@@ -255,14 +271,15 @@ __device__ void load_velocity(const Ctx &c, ScalarSmem<MX> &s, int l, int gx, in
 // interior into the level's other buffer.  FUSED: ghosts evaluated on the fly
 // instead of read from the patch's own ghost cells.
 template <int MX, int NT, bool FUSED>
-__device__ void advance_scalar_patch(const Ctx &c, ScalarSmem<MX> &s, int p, double t, double dt, double &cfl) {
+__device__ void advance_scalar_patch(const Ctx &c, const View &w, ScalarSmem<MX> &s, int p, double t, double dt,
+                                     double &cfl) {
     constexpr int N = MX + 2 * MB, NX = ScalarSmem<MX>::NX;
     const PatchInfo P = c.info[p];
     const int l = P.level;
     const double h = 1.0 / (double)(MX << l);
     const double lam = dt / h;
-    const double *in = buf_of(c, l);
-    double *out = other_of(c, l);
+    const double *in = buf_of(c, w, l);
+    double *out = other_of(c, w, l);
     const size_t base = (size_t)p * N * N;
     load_velocity<MX>(c, s, l, P.ix * MX, P.iy * MX, t + 0.5 * dt);
     if (!FUSED) {
@@ -277,7 +294,7 @@ __device__ void advance_scalar_patch(const Ctx &c, ScalarSmem<MX> &s, int p, dou
             int i, j;
             ghost_index<MX>(g, i, j);
             double v[1];
-            ghost_cell<MX, 1>(c, p, i, j, v);
+            ghost_cell<MX, 1>(c, w, p, i, j, v);
             s.q[(j + MB) * N + i + MB] = v[0];
         }
     }
@@ -368,7 +385,261 @@ __global__ void __launch_bounds__(NT) advance_scalar_kernel(Ctx c, int first, in
     __shared__ ScalarSmem<MX> s;
     const int p = first + xcd_remap(blockIdx.x, count);
     double cfl = 0.0;
-    advance_scalar_patch<MX, NT, FUSED>(c, s, p, t, dt, cfl);
+    advance_scalar_patch<MX, NT, FUSED>(c, view_of(c), s, p, t, dt, cfl);
+    reduce_cfl<NT>(cfl, s.red, cfl_bits);
+}
+
+// ------------------------------------------------------------------------
+// shallow-water step: Roe solver, Harten-Hyman entropy fix, MC-limited
+// waves, transverse splitting in the Roe eigenbasis (system form of the
+// same unsplit scheme; the paper runs Clawpack's wave-propagation solvers)
+// ------------------------------------------------------------------------
+template <int MX>
+struct SweSmem {
+    static constexpr int N = MX + 2 * MB;
+    static constexpr int NR = (MX + 3) * (MX + 2);  // Riemann problems per direction
+    static constexpr int NC = MX * (MX + 2);        // accumulator cells per direction
+    double q[3][N * N];
+    double R[NR][6];     // alpha_1..3, u_hat, v_hat, c_hat (normal frame)
+    double acc[NC][12];  // per cell: T (3), transverse + (3), transverse - (3), dC (3)
+    double D[3][MX * MX];
+    double red[16];
+};
+
+// Roe linearisation in the frame (h, h u_n, h u_t)
+__device__ __forceinline__ void roe_solve(double g, double hL, double nL, double tL, double hR, double nR, double tR,
+                                          double *r) {
+    const double uL = nL / hL, uR = nR / hR, vL = tL / hL, vR = tR / hR;
+    const double sL = sqrt(hL), sR = sqrt(hR);
+    const double hb = 0.5 * (hL + hR);
+    const double uh = (sL * uL + sR * uR) / (sL + sR);
+    const double vh = (sL * vL + sR * vR) / (sL + sR);
+    const double ch = sqrt(g * hb);
+    const double d0 = hR - hL, d1 = nR - nL, d2 = tR - tL;
+    r[0] = ((uh + ch) * d0 - d1) / (2.0 * ch);
+    r[1] = d2 - vh * d0;
+    r[2] = (d1 - (uh - ch) * d0) / (2.0 * ch);
+    r[3] = uh; r[4] = vh; r[5] = ch;
+}
+
+__device__ __forceinline__ void waves_of(const double *r, double W[3][3], double sp[3]) {
+    const double uh = r[3], vh = r[4], ch = r[5];
+    W[0][0] = r[0]; W[0][1] = r[0] * (uh - ch); W[0][2] = r[0] * vh;
+    W[1][0] = 0.0; W[1][1] = 0.0; W[1][2] = r[1];
+    W[2][0] = r[2]; W[2][1] = r[2] * (uh + ch); W[2][2] = r[2] * vh;
+    sp[0] = uh - ch; sp[1] = uh; sp[2] = uh + ch;
+}
+
+__device__ __forceinline__ double phi_limit(int lim, double th) {
+    if (lim == 1) return 1.0;
+    if (lim == 2) return 0.0;
+    if (lim == 3) return th <= 0 ? 0.0 : (th < 1.0 ? th : 1.0);
+    const double mn = fmin(0.5 * (1.0 + th), fmin(2.0, 2.0 * th));
+    return mn > 0.0 ? mn : 0.0;
+}
+
+// split A (frame h, n, t) into its +t and -t moving parts with the Roe state r
+__device__ __forceinline__ void roe_transverse(const double *r, const double *A, double *bp, double *bm) {
+    const double un = r[3], ut = r[4], c = r[5];
+    const double be[3] = {((ut + c) * A[0] - A[2]) / (2.0 * c), A[1] - un * A[0], (A[2] - (ut - c) * A[0]) / (2.0 * c)};
+    const double mu[3] = {ut - c, ut, ut + c};
+    const double rv[3][3] = {{1.0, un, ut - c}, {0.0, 1.0, 0.0}, {1.0, un, ut + c}};
+#pragma unroll
+    for (int e = 0; e < 3; e++) { bp[e] = 0.0; bm[e] = 0.0; }
+#pragma unroll
+    for (int p = 0; p < 3; p++) {
+        const double mp = mu[p] > 0 ? mu[p] : 0.0, mm = mu[p] < 0 ? mu[p] : 0.0;
+#pragma unroll
+        for (int e = 0; e < 3; e++) { bp[e] += mp * be[p] * rv[p][e]; bm[e] += mm * be[p] * rv[p][e]; }
+    }
+}
+
+// One edge of a sweep (normal frame): fluctuations with the entropy fix,
+// limited second-order correction C, corrected fluctuations and their
+// transverse splits.  qL/qR in the normal frame; rU/rD: Roe data of the
+// neighbouring edges on the two sides (for the upwind waves).
+__device__ __forceinline__ void swe_edge(double g, int lim, double lam, const double *qL, const double *qR,
+                                         const double *r, const double *rlo, const double *rhi, double C[3],
+                                         double Aps[3], double Ams[3], double bpp[3], double bmp[3], double bpm[3],
+                                         double bmm[3], double &smax) {
+    double W[3][3], sp[3];
+    waves_of(r, W, sp);
+    // Harten-Hyman fix on transonic rarefactions of families 1 and 3
+    const double l1L = qL[1] / qL[0] - sqrt(g * qL[0]);
+    const double hm = qL[0] + W[0][0];
+    const double l1R = (qL[1] + W[0][1]) / hm - sqrt(g * hm);
+    const bool fix1 = l1L < 0.0 && l1R > 0.0;
+    const double hm3 = qR[0] - W[2][0];
+    const double l3L = (qR[1] - W[2][1]) / hm3 + sqrt(g * hm3);
+    const double l3R = qR[1] / qR[0] + sqrt(g * qR[0]);
+    const bool fix3 = l3L < 0.0 && l3R > 0.0;
+    double am[3] = {0, 0, 0}, ap[3] = {0, 0, 0};
+#pragma unroll
+    for (int p = 0; p < 3; p++) {
+        double sm, spp;
+        if (p == 0 && fix1) {
+            const double beta = (l1R - sp[0]) / (l1R - l1L);
+            sm = beta * l1L; spp = (1.0 - beta) * l1R;
+        } else if (p == 2 && fix3) {
+            const double beta = (l3R - sp[2]) / (l3R - l3L);
+            sm = beta * l3L; spp = (1.0 - beta) * l3R;
+        } else {
+            sm = sp[p] < 0 ? sp[p] : 0.0;
+            spp = sp[p] > 0 ? sp[p] : 0.0;
+        }
+#pragma unroll
+        for (int e = 0; e < 3; e++) { am[e] += sm * W[p][e]; ap[e] += spp * W[p][e]; }
+    }
+    // MC limiter on each wave against the upwind wave of its family
+    double Wl[3][3], spl[3], Wh[3][3], sph[3];
+    waves_of(rlo, Wl, spl);
+    waves_of(rhi, Wh, sph);
+#pragma unroll
+    for (int e = 0; e < 3; e++) C[e] = 0.0;
+#pragma unroll
+    for (int p = 0; p < 3; p++) {
+        double ww = 0, wu = 0;
+#pragma unroll
+        for (int e = 0; e < 3; e++) {
+            const double wup = sp[p] > 0 ? Wl[p][e] : Wh[p][e];
+            ww += W[p][e] * W[p][e];
+            wu += wup * W[p][e];
+        }
+        const double ph = ww == 0.0 ? 0.0 : phi_limit(lim, wu / ww);
+        const double as = fabs(sp[p]);
+#pragma unroll
+        for (int e = 0; e < 3; e++) C[e] += as * (1.0 - lam * as) * ph * W[p][e];
+        smax = fmax(smax, as);
+    }
+#pragma unroll
+    for (int e = 0; e < 3; e++) { Aps[e] = ap[e] - C[e]; Ams[e] = am[e] + C[e]; }
+    roe_transverse(r, Aps, bpp, bmp);
+    roe_transverse(r, Ams, bpm, bmm);
+}
+
+// One step on a shallow-water patch.  Sweep X then Y; each sweep: Riemann
+// problems into R, then the edges of even and odd index add their
+// contributions to the two adjacent cells (two conflict-free passes), then
+// the cells turn them into their share of the update.
+template <int MX, int NT, bool FUSED>
+__device__ void advance_swe_patch(const Ctx &c, const View &w, SweSmem<MX> &s, int p, double dt, double &cfl) {
+    constexpr int N = MX + 2 * MB, NR = SweSmem<MX>::NR;
+    const PatchInfo P = c.info[p];
+    const int l = P.level;
+    const double h = 1.0 / (double)(MX << l);
+    const double lam = dt / h, g = c.g;
+    const double *in = buf_of(c, w, l);
+    double *out = other_of(c, w, l);
+    if (!FUSED) {
+        for (int f = 0; f < 3; f++)
+            for (int k = threadIdx.x; k < N * N; k += NT) s.q[f][k] = in[(size_t)(f * c.cap + p) * N * N + k];
+    } else {
+        for (int k = threadIdx.x; k < MX * MX; k += NT) {
+            const int i = k % MX, j = k / MX;
+            for (int f = 0; f < 3; f++)
+                s.q[f][(j + MB) * N + i + MB] = in[(size_t)(f * c.cap + p) * N * N + (j + MB) * N + i + MB];
+        }
+        constexpr int NG = N * N - MX * MX;
+        for (int gidx = threadIdx.x; gidx < NG; gidx += NT) {
+            int i, j;
+            ghost_index<MX>(gidx, i, j);
+            double v[3];
+            ghost_cell<MX, 3>(c, w, p, i, j, v);
+            for (int f = 0; f < 3; f++) s.q[f][(j + MB) * N + i + MB] = v[f];
+        }
+    }
+    __syncthreads();
+    double smax = 0.0;
+#define QA(f, i, j) s.q[f][((j) + MB) * N + (i) + MB]
+    for (int dir = 0; dir < 2; dir++) {
+        // normal frame: x sweep (h, hu, hv); y sweep (h, hv, hu)
+        const int fn = dir == 0 ? 1 : 2, ft = dir == 0 ? 2 : 1;
+        // Riemann problems: edge index e in [-1, MX+1] along the sweep, line in [-1, MX]
+        for (int k = threadIdx.x; k < NR; k += NT) {
+            const int ln = k / (MX + 3) - 1, e = k % (MX + 3) - 1;
+            const int iL = dir == 0 ? e - 1 : ln, jL = dir == 0 ? ln : e - 1;
+            const int iR = dir == 0 ? e : ln, jR = dir == 0 ? ln : e;
+            roe_solve(g, QA(0, iL, jL), QA(fn, iL, jL), QA(ft, iL, jL), QA(0, iR, jR), QA(fn, iR, jR),
+                      QA(ft, iR, jR), s.R[k]);
+        }
+        __syncthreads();
+        // edges e in [0, MX] of parity `par`, lines [-1, MX]; cell (e) gets
+        // the right-going part, cell (e-1) the left-going part
+        for (int par = 0; par < 2; par++) {
+            constexpr int NEH = (MX / 2 + 1) * (MX + 2);
+            for (int k = threadIdx.x; k < NEH; k += NT) {
+                const int ln = k / (MX / 2 + 1) - 1, e = 2 * (k % (MX / 2 + 1)) + par;
+                if (e > MX) continue;
+                const int rk = (ln + 1) * (MX + 3) + (e + 1);
+                const int iL = dir == 0 ? e - 1 : ln, jL = dir == 0 ? ln : e - 1;
+                const int iR = dir == 0 ? e : ln, jR = dir == 0 ? ln : e;
+                const double qL[3] = {QA(0, iL, jL), QA(fn, iL, jL), QA(ft, iL, jL)};
+                const double qR[3] = {QA(0, iR, jR), QA(fn, iR, jR), QA(ft, iR, jR)};
+                double C[3], Aps[3], Ams[3], bpp[3], bmp[3], bpm[3], bmm[3];
+                double sm = 0.0;
+                swe_edge(g, c.lim, lam, qL, qR, s.R[rk], s.R[rk - 1], s.R[rk + 1], C, Aps, Ams, bpp, bmp, bpm, bmm, sm);
+                if (ln >= 0 && ln < MX) smax = fmax(smax, sm);
+                // back to (h, hu, hv)
+                const int sw[3] = {0, fn, ft};
+                if (e < MX) {  // cell e along the sweep: right-going part
+                    double *a = dir == 0 ? s.acc[(ln + 1) * MX + e] : s.acc[e * (MX + 2) + (ln + 1)];
+#pragma unroll
+                    for (int f = 0; f < 3; f++) {
+                        const int o = sw[f];
+                        if (par == 0) {
+                            a[o] = Aps[f]; a[3 + o] = bpp[f]; a[6 + o] = bmp[f]; a[9 + o] = -C[f];
+                        } else {
+                            a[o] += Aps[f]; a[3 + o] += bpp[f]; a[6 + o] += bmp[f]; a[9 + o] -= C[f];
+                        }
+                    }
+                }
+                if (e > 0) {  // cell e-1: left-going part
+                    double *a = dir == 0 ? s.acc[(ln + 1) * MX + e - 1] : s.acc[(e - 1) * (MX + 2) + (ln + 1)];
+#pragma unroll
+                    for (int f = 0; f < 3; f++) {
+                        const int o = sw[f];
+                        if (par == 0) {
+                            a[o] = Ams[f]; a[3 + o] = bpm[f]; a[6 + o] = bmm[f]; a[9 + o] = C[f];
+                        } else {
+                            a[o] += Ams[f]; a[3 + o] += bpm[f]; a[6 + o] += bmm[f]; a[9 + o] += C[f];
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        // the sweep's share of the update of interior cell (i, j):
+        // -lam T + lam/2 dC + lam^2/2 (P(i) + M(i+1) - P(i-1) - M(i)) along
+        // the transverse direction
+        for (int k = threadIdx.x; k < MX * MX; k += NT) {
+            const int i = k % MX, j = k / MX;
+            const double *a0, *am_, *ap_;
+            if (dir == 0) {
+                a0 = s.acc[(j + 1) * MX + i]; am_ = s.acc[j * MX + i]; ap_ = s.acc[(j + 2) * MX + i];
+            } else {
+                a0 = s.acc[j * (MX + 2) + i + 1]; am_ = s.acc[j * (MX + 2) + i]; ap_ = s.acc[j * (MX + 2) + i + 2];
+            }
+#pragma unroll
+            for (int f = 0; f < 3; f++) {
+                const double dT = a0[3 + f] + ap_[6 + f] - am_[3 + f] - a0[6 + f];
+                const double part = -lam * a0[f] + 0.5 * lam * a0[9 + f] + 0.5 * lam * lam * dT;
+                if (dir == 0) s.D[f][k] = part;
+                else out[(size_t)(f * c.cap + p) * N * N + (j + MB) * N + i + MB] = QA(f, i, j) + s.D[f][k] + part;
+            }
+        }
+        __syncthreads();
+    }
+#undef QA
+    cfl = fmax(cfl, lam * smax);
+}
+
+template <int MX, int NT, bool FUSED>
+__global__ void __launch_bounds__(NT) advance_swe_kernel(Ctx c, int first, int count, double dt,
+                                                         unsigned long long *cfl_bits) {
+    __shared__ SweSmem<MX> s;
+    const int p = first + xcd_remap(blockIdx.x, count);
+    double cfl = 0.0;
+    advance_swe_patch<MX, NT, FUSED>(c, view_of(c), s, p, dt, cfl);
     reduce_cfl<NT>(cfl, s.red, cfl_bits);
 }
 
@@ -406,13 +677,17 @@ __device__ void grid_barrier(DevState *st, unsigned nblocks) {
     __syncthreads();
 }
 
-template <int MX, int NT>
-__global__ void __launch_bounds__(NT) persistent_scalar_kernel(Ctx c, const SchedEntry *sched, int nsched,
+template <int MX, int EQ>
+struct SmemOf { using type = ScalarSmem<MX>; };
+template <int MX>
+struct SmemOf<MX, 1> { using type = SweSmem<MX>; };
+
+template <int MX, int NT, int EQ>
+__global__ void __launch_bounds__(NT) persistent_kernel(Ctx c, const SchedEntry *sched, int nsched,
                                                                const LevelRange *lr, int nleaves, DevState *st) {
-    __shared__ ScalarSmem<MX> s;
+    __shared__ typename SmemOf<MX, EQ>::type s;
     const double t0 = st->t, dtc = st->dt_coarse;
-    Ctx lc = c;
-    lc.curmask = st->curmask;
+    View w{st->curmask, -1, 1.0};
     const unsigned G = gridDim.x;
     const int x = blockIdx.x & 7, r = blockIdx.x >> 3;
     const int nbx = ((int)G - x + 7) >> 3;  // blocks on this XCD
@@ -425,26 +700,27 @@ __global__ void __launch_bounds__(NT) persistent_scalar_kernel(Ctx c, const Sche
     for (int k = 0; k < nsched; k++) {
         const SchedEntry e = sched[k];
         int first, count;
-        if (e.level < 0) { first = 0; count = nall; lc.clevel = -1; lc.alpha = 1.0; }
-        else { first = lr->start[e.level]; count = lr->count[e.level]; lc.clevel = e.level - 1; lc.alpha = e.alpha; }
+        if (e.level < 0) { first = 0; count = nall; w.clevel = -1; w.alpha = 1.0; }
+        else { first = lr->start[e.level]; count = lr->count[e.level]; w.clevel = e.level - 1; w.alpha = e.alpha; }
         if (count == 0) {
-            if (e.level >= 0) lc.curmask ^= 1u << e.level;
+            if (e.level >= 0) w.curmask ^= 1u << e.level;
             continue;
         }
         const double t = t0 + e.off * dtc, dt = e.scale * dtc;
         const int c0 = (int)(((long long)count * x) >> 3), c1 = (int)(((long long)count * (x + 1)) >> 3);
         for (int pi = c0 + r; pi < c1; pi += nbx) {
-            advance_scalar_patch<MX, NT, true>(lc, s, first + pi, t, dt, cfl);
+            if constexpr (EQ == 0) advance_scalar_patch<MX, NT, true>(c, w, s, first + pi, t, dt, cfl);
+            else advance_swe_patch<MX, NT, true>(c, w, s, first + pi, dt, cfl);
             __syncthreads();
         }
         grid_barrier(st, G);
-        lc.curmask ^= (e.level < 0) ? allmask : (1u << e.level);
+        w.curmask ^= (e.level < 0) ? allmask : (1u << e.level);
     }
     reduce_cfl<NT>(cfl, s.red, &st->cfl_bits);
     grid_barrier(st, G);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->t = t0 + dtc;
-        st->curmask = lc.curmask;
+        st->curmask = w.curmask;
     }
 }
 
@@ -496,7 +772,7 @@ __global__ void set_interior_kernel(Ctx c, const int32_t *slot_of_leaf, int n, c
         const int i = k % MX, j = (k / MX) % MX, f = (k / (MX * MX)) % c.F;
         const int leaf = (int)(k / ((long long)MX * MX * c.F));
         const int p = slot_of_leaf[leaf];
-        buf_of(c, c.info[p].level)[qidx(c.cap, N, f, p, i, j)] = src[k];
+        buf_of(c, view_of(c), c.info[p].level)[qidx(c.cap, N, f, p, i, j)] = src[k];
     }
 }
 
@@ -509,7 +785,7 @@ __global__ void get_interior_kernel(Ctx c, const int32_t *slot_of_leaf, int n, d
         const int i = k % E - off, j = (k / E) % E - off, f = (k / (E * E)) % c.F;
         const int leaf = (int)(k / ((long long)E * E * c.F));
         const int p = slot_of_leaf[leaf];
-        dst[k] = buf_of(c, c.info[p].level)[qidx(c.cap, N, f, p, i, j)];
+        dst[k] = buf_of(c, view_of(c), c.info[p].level)[qidx(c.cap, N, f, p, i, j)];
     }
 }
 
@@ -523,7 +799,7 @@ __global__ void __launch_bounds__(256) tag_kernel(Ctx c, const int32_t *slot_of_
     const int p = slot_of_leaf[leaf];
     const PatchInfo P = c.info[p];
     const double h = 1.0 / (double)(MX << P.level);
-    const double *q = buf_of(c, P.level);
+    const double *q = buf_of(c, view_of(c), P.level);
     double g2 = 0.0;
     for (int k = threadIdx.x; k < MX * MX; k += blockDim.x) {
         const int i = k % MX, j = k / MX;
@@ -637,6 +913,14 @@ static hipError_t adv_scalar(const Ctx &c, int first, int count, double t, doubl
     return hipGetLastError();
 }
 
+template <int MX, int NT>
+static hipError_t adv_swe(const Ctx &c, int first, int count, double dt, int fused, unsigned long long *cfl,
+                          hipStream_t s) {
+    if (fused) hipLaunchKernelGGL((advance_swe_kernel<MX, NT, true>), dim3(count), dim3(NT), 0, s, c, first, count, dt, cfl);
+    else hipLaunchKernelGGL((advance_swe_kernel<MX, NT, false>), dim3(count), dim3(NT), 0, s, c, first, count, dt, cfl);
+    return hipGetLastError();
+}
+
 hipError_t launch_advance(const Ctx &c, LaunchCfg lc, int level, int first, int count, double t, double dt,
                           int fused, unsigned long long *cfl_bits, hipStream_t s) {
     (void)level;
@@ -645,14 +929,19 @@ hipError_t launch_advance(const Ctx &c, LaunchCfg lc, int level, int first, int 
 #define ADV(MXV, NTV) if (lc.mx == MXV && lc.nt == NTV) return adv_scalar<MXV, NTV>(c, first, count, t, dt, fused, cfl_bits, s);
         ADV(8, 64) ADV(8, 128) ADV(16, 64) ADV(16, 128) ADV(16, 256) ADV(32, 128) ADV(32, 256) ADV(32, 512)
 #undef ADV
+    } else {
+#define ADV(MXV, NTV) if (lc.mx == MXV && lc.nt == NTV) return adv_swe<MXV, NTV>(c, first, count, dt, fused, cfl_bits, s);
+        ADV(8, 64) ADV(8, 128) ADV(16, 64) ADV(16, 128) ADV(16, 256)
+#undef ADV
     }
     return hipErrorInvalidValue;
 }
 
 template <int MX, int NT>
 static const void *persistent_fn(int eq) {
-    (void)eq;
-    return reinterpret_cast<const void *>(&persistent_scalar_kernel<MX, NT>);
+    if (eq == 0) return reinterpret_cast<const void *>(&persistent_kernel<MX, NT, 0>);
+    if constexpr (MX <= 16) return reinterpret_cast<const void *>(&persistent_kernel<MX, NT, 1>);
+    return nullptr;
 }
 
 static const void *persistent_select(LaunchCfg lc, int eq) {

@@ -30,10 +30,15 @@ fc_status fail(fc_status st, const std::string &msg) {
     return st;
 }
 
+// A failed HIP call is reported to the caller and the runtime's sticky
+// last-error state is cleared, so the caller's next HIP call does not see it.
 #define HIPCHK(expr)                                                                              \
     do {                                                                                          \
         hipError_t e_ = (expr);                                                                   \
-        if (e_ != hipSuccess) return fail(FC_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+        if (e_ != hipSuccess) {                                                                   \
+            (void)hipGetLastError();                                                              \
+            return fail(FC_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));           \
+        }                                                                                         \
     } while (0)
 
 inline uint64_t key3(int l, int ix, int iy) {
@@ -141,9 +146,10 @@ struct fc_patchstore {
            off_plan = 0, off_tag = 0, off_vt[FC_MAXLEV] = {0}, off_abar = 0;
     std::vector<SchedEntry> sched;
     int pgrid = 0;
+    int pgrid_user = 0;  // grid override of the persistent kernel (0: occupancy)
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
-    hipStream_t gstream = nullptr;
+    hipStream_t cap_stream = nullptr;  // private stream the graph is captured on
     int gnt = 0;
 };
 
@@ -284,7 +290,8 @@ fc_status upload_metadata(fc_patchstore *ps, hipStream_t s) {
     return FC_OK;
 }
 
-bool valid_nt(int mx, int nt) {
+bool valid_nt(int mx, int nt, int eq = 0) {
+    if (eq == FC_EQ_SWE && mx == 32) return false;
     switch (mx) {
         case 8: return nt == 64 || nt == 128;
         case 16: return nt == 64 || nt == 128 || nt == 256;
@@ -363,6 +370,7 @@ fc_status fc_patchstore_create(const fc_config *cfg, int64_t nleaves, const fc_l
     if (4 * cfg->mbc > cfg->mx || cfg->mbc < 2) return fail(FC_ERR_GHOST_WIDTH, "need 2 <= mbc <= mx/4 (Prop. 2.1)");
     if (cfg->mbc != 2) return fail(FC_ERR_ARG, "the kernels use exactly 2 ghost layers");
     if (cfg->equation != FC_EQ_ADVECTION && cfg->equation != FC_EQ_SWE) return fail(FC_ERR_ARG, "unknown equation");
+    if (cfg->equation == FC_EQ_SWE && cfg->mx > 16) return fail(FC_ERR_ARG, "shallow water supports mx = 8 or 16");
     if (cfg->limiter < 0 || cfg->limiter > 3) return fail(FC_ERR_ARG, "unknown limiter");
     for (int s = 0; s < 4; s++)
         if (cfg->bc[s] != FC_BC_PERIODIC && cfg->bc[s] != FC_BC_REFLECT) return fail(FC_ERR_ARG, "unknown boundary condition");
@@ -403,6 +411,7 @@ fc_status fc_patchstore_create(const fc_config *cfg, int64_t nleaves, const fc_l
 fc_status fc_patchstore_destroy(fc_patchstore *ps) {
     if (!ps) return FC_OK;
     drop_graph(ps);
+    if (ps->cap_stream) (void)hipStreamDestroy(ps->cap_stream);
     delete ps;
     return FC_OK;
 }
@@ -542,8 +551,29 @@ fc_status fc_advance_coarse_steps(fc_patchstore *ps, double dt_coarse, int32_t n
         }
         return FC_OK;
     }
+    if (mode == FC_MODE_FUSED_LEVELS) {
+        // one launch per level-step of the kernel that gathers its ghosts
+        for (int n = 0; n < nsteps; n++) {
+            for (const SchedEntry &e : ps->sched) {
+                const double t = ps->t + e.off * dt_coarse, dt = e.scale * dt_coarse;
+                if (e.level < 0) {
+                    Ctx c = make_ctx(ps);
+                    int cnt = (int)ps->mesh.lv.size();
+                    HIPCHK(launch_advance(c, LaunchCfg{ps->mx, ps->nt}, -1, 0, cnt, t, dt, 1, cfl, s));
+                    for (int l = 0; l < FC_MAXLEV; l++)
+                        if (ps->lr.count[l] > 0) ps->curmask ^= 1u << l;
+                } else {
+                    r = advance_one(ps, e.level, t, dt, 1, e.level - 1, e.alpha, cfl, s);
+                    if (r != FC_OK) return r;
+                }
+            }
+            ps->t += dt_coarse;
+        }
+        return FC_OK;
+    }
     if (mode != FC_MODE_FUSED && mode != FC_MODE_FUSED_GRAPH) return fail(FC_ERR_ARG, "unknown mode");
     if (ps->pgrid <= 0) return fail(FC_ERR_HIP, "persistent kernel has no resident blocks");
+    const int grid = ps->pgrid_user > 0 ? std::min(ps->pgrid_user, ps->pgrid) : ps->pgrid;
     const int n = (int)ps->mesh.lv.size();
     DevState *st = dstate(ps);
     HIPCHK(launch_set_state(st, ps->t, dt_coarse, ps->curmask, 1, s));
@@ -552,24 +582,26 @@ fc_status fc_advance_coarse_steps(fc_patchstore *ps, double dt_coarse, int32_t n
     const LevelRange *lrd = (const LevelRange *)(ps->ws + ps->off_lr);
     if (mode == FC_MODE_FUSED) {
         for (int k = 0; k < nsteps; k++)
-            HIPCHK(launch_persistent(c, LaunchCfg{ps->mx, ps->nt}, sched, (int)ps->sched.size(), lrd, n, st, ps->pgrid, s));
+            HIPCHK(launch_persistent(c, LaunchCfg{ps->mx, ps->nt}, sched, (int)ps->sched.size(), lrd, n, st, grid, s));
     } else {
-        if (!ps->gexec || ps->gstream != s || ps->gnt != ps->nt) {
+        if (!ps->gexec || ps->gnt != ps->nt) {
             drop_graph(ps);
-            // the kernel reads the time, step, buffer parities and level
-            // ranges from device memory, so one capture serves every replay
-            HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            // The kernel reads the time, step, buffer parities and level
+            // ranges from device memory, so one capture serves every replay.
+            // Capture happens on a private stream (the null stream cannot be
+            // captured); replays go to the caller's stream.
+            if (!ps->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ps->cap_stream, hipStreamNonBlocking));
+            HIPCHK(hipStreamBeginCapture(ps->cap_stream, hipStreamCaptureModeThreadLocal));
             hipError_t e = launch_persistent(c, LaunchCfg{ps->mx, ps->nt}, sched, (int)ps->sched.size(), lrd, n, st,
-                                             ps->pgrid, s);
+                                             grid, ps->cap_stream);
             hipGraph_t g = nullptr;
-            hipError_t e2 = hipStreamEndCapture(s, &g);
+            hipError_t e2 = hipStreamEndCapture(ps->cap_stream, &g);
             if (e != hipSuccess || e2 != hipSuccess) {
                 if (g) (void)hipGraphDestroy(g);
                 return fail(FC_ERR_HIP, "graph capture failed");
             }
             ps->graph = g;
             HIPCHK(hipGraphInstantiate(&ps->gexec, g, nullptr, nullptr, 0));
-            ps->gstream = s;
             ps->gnt = ps->nt;
         }
         for (int k = 0; k < nsteps; k++) HIPCHK(hipGraphLaunch(ps->gexec, s));
@@ -718,9 +750,19 @@ fc_status fc_check_device(fc_patchstore *ps, void *stream) {
     return check_device_error(ps, (hipStream_t)stream);
 }
 
+fc_status fc_set_persistent_grid(fc_patchstore *ps, int32_t grid, int32_t *max_grid) {
+    if (!ps) return fail(FC_ERR_ARG, "null store");
+    if (grid < 0) return fail(FC_ERR_ARG, "grid must be >= 0");
+    ps->pgrid_user = grid;
+    if (max_grid) *max_grid = ps->pgrid;
+    drop_graph(ps);
+    return FC_OK;
+}
+
 fc_status fc_set_variant(fc_patchstore *ps, int32_t threads_per_patch) {
     if (!ps) return fail(FC_ERR_ARG, "null store");
-    if (!valid_nt(ps->mx, threads_per_patch)) return fail(FC_ERR_ARG, "unsupported threads per patch for this mx");
+    if (!valid_nt(ps->mx, threads_per_patch, ps->cfg.equation))
+        return fail(FC_ERR_ARG, "unsupported threads per patch for this mx");
     ps->nt = threads_per_patch;
     if (ps->ws) ps->pgrid = persistent_max_grid(LaunchCfg{ps->mx, ps->nt}, ps->cfg.equation);
     drop_graph(ps);
@@ -748,7 +790,7 @@ fc_status fc_autotune(fc_patchstore *ps, int32_t *threads_out, void *stream) {
     int bnt = ps->nt;
     for (int k = 0; k < 3; k++) {
         const int nt = cl[k];
-        if (!valid_nt(ps->mx, nt)) continue;
+        if (!valid_nt(ps->mx, nt, ps->cfg.equation)) continue;
         Ctx c = make_ctx(ps);
         LaunchCfg lc{ps->mx, nt};
         for (int w = 0; w < 2; w++)

@@ -90,9 +90,10 @@ def test_fill_amr_matches_algorithm1(B, O, seed, bc):
 def test_fill_time_interpolated_coarse_level(B, O):
     """Level l filled at half the coarse step: coarse data q_old + 1/2 (q - q_old)."""
     L = S.random_balanced_leaves(11, 2, 4)
+    assert (np.asarray(L)[:, 0] == 4).sum() > 0
     rng = np.random.default_rng(11)
     q = rng.random((len(L), 1, 8, 8))
-    ps, o = pair(B, O, L, 8, q, velocity="constant", vel_params=(0.7, -0.4, 0))
+    ps, o = pair(B, O, L, 8, q, velocity="constant", vel_params=(0.7, -0.4, 0), lmin=2, lmax=4)
     for lo in (2, 3):
         ps.ghost_fill(lo, lo, 1.0)
         o.ghost_fill(lo, lo, 1.0)
@@ -269,3 +270,50 @@ def test_full_size_uniform_level5_swirl(B, O):
     assert rel(g, o.interior()) <= TOL
     m0 = w["q0"].sum()
     assert abs(g.sum() - m0) / m0 < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# shallow water (3-field SoA store, reflecting walls, Roe + entropy fix)
+# ---------------------------------------------------------------------------
+
+def swe_pair(B, O, w, mx):
+    return pair(B, O, w["leaves"], mx, w["q0"], equation="swe", velocity="none", bc=("reflect",) * 4,
+                lmin=w["lmin"], lmax=w["lmax"])
+
+
+@pytest.mark.parametrize("mode", ["per_level", "fused", "graph"])
+@pytest.mark.parametrize("mx", [8, 16])
+def test_swe_dam_break_amr_parity(B, O, mode, mx):
+    """Radial dam break on levels 2-4 with subcycling, fixed coarse step
+    (Courant number <= 0.6 on the finest level for |u| + c <= 1.6)."""
+    w = S.workload("dam_break", lmin=2, lmax=4, mx=mx)
+    ps, o = swe_pair(B, O, w, mx)
+    dt = 0.6 / (mx * 4) / 1.6
+    ps.coarse_steps(dt, 6, mode)
+    for s in range(6):
+        o.coarse_step(s * dt, dt)
+    ps.check()
+    assert rel(ps.interior(), o.interior()) <= TOL
+
+
+def test_swe_lake_at_rest_bitwise(B):
+    L = S.random_balanced_leaves(3, 2, 4, periodic=(False, False))
+    q = np.zeros((len(L), 3, 16, 16))
+    q[:, 0] = 1.3
+    ps = B.PatchStore(L, mx=16, equation="swe", velocity="none", bc=("reflect",) * 4)
+    ps.set_interior(q)
+    ps.coarse_steps(0.004, 4, "graph")
+    assert np.array_equal(ps.interior().cpu().numpy(), q)
+
+
+def test_swe_single_step_cfl(B, O):
+    w = S.workload("dam_break", lmin=3, lmax=3, mx=16)
+    ps, o = swe_pair(B, O, w, 16)
+    import torch
+    cfl = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ps.ghost_fill()
+    o.ghost_fill()
+    ps.advance_level(3, 0.0, 0.002, cfl)
+    c_o = o.advance_level(3, 0.0, 0.002)
+    assert rel(ps.interior(), o.interior()) <= TOL
+    assert abs(cfl.item() - c_o) <= 1e-14 * c_o
