@@ -1,0 +1,79 @@
+"""Differentiation of the uniform-level advance + ghost fill.
+
+``AdvanceFill`` is a torch.autograd.Function whose forward runs ``nsteps``
+coarse steps of the GPU path (persistent kernel replayed from a hipGraph)
+from q0 and returns q(T); its backward is the hand-written discrete adjoint
+(fc_adjoint_step: transpose of the limited step with branches frozen at the
+forward state, then transpose of the ghost copy), with checkpoints every
+``checkpoint_every`` steps and the states of one segment recomputed at a
+time.  Shapes: [nleaves][1][mx][mx] float64 on the GPU, in the leaf order the
+store was created with.
+"""
+from __future__ import annotations
+
+import torch
+
+
+def _times(t0, dt, n):
+    """Step start times exactly as the library accumulates them (t += dt)."""
+    out, t = [], float(t0)
+    for _ in range(n):
+        out.append(t)
+        t = t + float(dt)
+    return out
+
+
+class AdvanceFill(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, q0, store, level, dt, nsteps, checkpoint_every=16, t0=0.0):
+        every = max(1, int(checkpoint_every))
+        times = _times(t0, dt, nsteps)
+        store.time = t0
+        store.set_interior(q0.detach())
+        ckpts = [q0.detach().clone()]
+        k = 0
+        while k < nsteps:
+            m = min(every, nsteps - k)
+            store.coarse_steps(dt, m, "graph")
+            k += m
+            if k < nsteps:
+                ckpts.append(store.interior().clone())
+        out = store.interior().clone()
+        ctx.store, ctx.level, ctx.dt, ctx.nsteps, ctx.every = store, level, dt, nsteps, every
+        ctx.times, ctx.ckpts = times, ckpts
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        store, level, dt, n, every = ctx.store, ctx.level, ctx.dt, ctx.nsteps, ctx.every
+        lam = grad_out.detach().to(torch.float64).contiguous()
+        nseg = (n + every - 1) // every
+        for seg in reversed(range(nseg)):
+            a, b = seg * every, min(n, (seg + 1) * every)
+            # recompute the segment's step inputs q^a .. q^(b-1)
+            store.time = ctx.times[a]
+            store.set_interior(ctx.ckpts[seg])
+            states = [ctx.ckpts[seg]]
+            for _ in range(a, b - 1):
+                store.coarse_steps(dt, 1, "graph")
+                states.append(store.interior().clone())
+            for k in reversed(range(a, b)):
+                lam = store.adjoint_step(level, ctx.times[k], dt, states[k - a], lam)
+        return lam, None, None, None, None, None, None
+
+
+def loss_and_grad(store, q0, q_target, level, dt, nsteps, checkpoint_every=16):
+    """L = 1/2 sum (q(T) - q_target)^2 over interior cells and dL/dq0."""
+    q0 = q0.detach().clone().requires_grad_(True)
+    qT = AdvanceFill.apply(q0, store, level, dt, nsteps, checkpoint_every)
+    L = 0.5 * ((qT - q_target) ** 2).sum()
+    L.backward()
+    return L.detach(), q0.grad.detach()
+
+
+def loss(store, q0, q_target, dt, nsteps):
+    """Forward-only loss (for finite differences)."""
+    store.time = 0.0
+    store.set_interior(q0)
+    store.coarse_steps(dt, nsteps, "graph")
+    return 0.5 * ((store.interior() - q_target) ** 2).sum()

@@ -111,9 +111,7 @@ hipError_t launch_tag(const Ctx &c, int mx, const int32_t *slot_of_leaf, int n, 
 hipError_t launch_consolidate(const Ctx &c, int mx, int n, hipStream_t s);
 hipError_t launch_transfer(const Ctx &c, int mx, const TransferRec *plan, int n, hipStream_t s);
 hipError_t launch_export_cfl(DevState *state, double *cfl_dev, hipStream_t s);
-hipError_t launch_adjoint(const Ctx &c, LaunchCfg lc, int level, int first, int count, double t, double dt,
-                          const double *lam_in_slots, double *abar, hipStream_t s);
-hipError_t launch_adjoint_gather(const Ctx &c, int mx, int first, int count, const double *abar,
-                                 double *lam_out_slots, hipStream_t s);
-hipError_t launch_slots_to_leaves(const int32_t *slot_of_leaf, int n, int mx, const double *src_slots,
-                                  double *dst_leaves, int inverse, hipStream_t s);
+hipError_t launch_adjoint(const Ctx &c, int mx, int first, int count, double t, double dt,
+                          const int32_t *leaf_of_slot, const double *lam_in, double *abar, hipStream_t s);
+hipError_t launch_adjoint_gather(const Ctx &c, int mx, int first, int count, const int32_t *leaf_of_slot,
+                                 const double *abar, double *lam_out, hipStream_t s);

@@ -644,6 +644,222 @@ __global__ void __launch_bounds__(NT) advance_swe_kernel(Ctx c, int first, int c
 }
 
 // ------------------------------------------------------------------------
+// adjoint of one uniform-level scalar step (fill by copy, then advance)
+// ------------------------------------------------------------------------
+// The limited step is piecewise linear in Q; its Jacobian is the step with
+// the limiter branches frozen at the forward state.  Branch codes follow the
+// forward limiter's tie order (half-sum, then 2W, then 2Wu).
+__device__ __forceinline__ void limiter_partials(int lim, double W, double Wu, double &dW, double &dWu) {
+    dW = 0.0; dWu = 0.0;
+    if (lim == 1) { dW = 1.0; return; }
+    if (lim == 2) return;
+    if (W * Wu <= 0.0) return;
+    const double aw = fabs(W), au = fabs(Wu);
+    if (lim == 3) { if (aw <= au) dW = 1.0; else dWu = 1.0; return; }
+    const double a = 0.5 * fabs(W + Wu), b = 2.0 * aw, cc = 2.0 * au;
+    int br = 1;
+    double mn = a;
+    if (b < mn) { mn = b; br = 2; }
+    if (cc < mn) br = 3;
+    if (br == 1) { dW = 0.5; dWu = 0.5; }
+    else if (br == 2) dW = 2.0;
+    else dWu = 2.0;
+}
+
+template <int MX>
+struct AdjSmem {
+    static constexpr int N = MX + 2 * MB;
+    static constexpr int NX = (MX + 2) * (MX + 1);  // edges of one direction
+    union {
+        struct {
+            double q[N * N];
+            double tx[(MX + 2) * MX], ty[MX * (MX + 2)];  // adjoints of TX, TY
+        } a;
+        struct {
+            double dx[(MX + 2) * (MX + 3)], dy[(MX + 3) * (MX + 2)];  // total adjoint of each difference
+        } b;
+    } u;
+    double lam[MX * MX];
+    double gx[NX], hx[NX], gy[NX], hy[NX];  // adjoints w.r.t. W and the upwind W
+    double ux[MX + 1], uy[MX + 2], vy[MX + 1], vx[MX + 2];
+};
+
+template <int MX, int NT>
+__global__ void __launch_bounds__(NT) adjoint_kernel(Ctx c, int first, int count, double t, double dt,
+                                                     const int32_t *leaf_of_slot, const double *lam_in,
+                                                     double *abar) {
+    constexpr int N = MX + 2 * MB, NX = AdjSmem<MX>::NX;
+    __shared__ AdjSmem<MX> s;
+    const int p = first + blockIdx.x;
+    const View w = view_of(c);
+    const PatchInfo P = c.info[p];
+    const int l = P.level;
+    const double h = 1.0 / (double)(MX << l), lam = dt / h;
+    const double *in = buf_of(c, w, l);
+    const size_t base = (size_t)p * N * N;
+    // velocities (same factors as the forward step)
+    {
+        const int n = MX << l, gx0 = P.ix * MX, gy0 = P.iy * MX;
+        const double tm = t + 0.5 * dt;
+        if (c.velocity == 2) {
+            const double ct = cos(M_PI * tm / c.vel_T);
+            const double *vt = c.vt[l];
+            const double *ex = vt + vt_ex(n, MB), *cxv = vt + vt_cx(n, MB);
+            const double *ey = vt + vt_ey(n, MB), *cyv = vt + vt_cy(n, MB);
+            for (int k = threadIdx.x; k < MX + 2; k += NT) {
+                if (k <= MX) { s.ux[k] = ex[gx0 + k]; s.vy[k] = ey[gy0 + k]; }
+                s.uy[k] = cyv[gy0 + k - 1] * ct;
+                s.vx[k] = -(cxv[gx0 + k - 1] * ct);
+            }
+        } else {
+            for (int k = threadIdx.x; k < MX + 2; k += NT) {
+                if (k <= MX) { s.ux[k] = c.vel_u; s.vy[k] = c.vel_v; }
+                s.uy[k] = 1.0;
+                s.vx[k] = 1.0;
+            }
+        }
+    }
+    for (int k = threadIdx.x; k < N * N; k += NT) s.u.a.q[k] = in[base + k];
+    const double *li = lam_in + (size_t)leaf_of_slot[p] * MX * MX;
+    for (int k = threadIdx.x; k < MX * MX; k += NT) s.lam[k] = li[k];
+    __syncthreads();
+    auto LN = [&](int i, int j) -> double {
+        return (i >= 0 && i < MX && j >= 0 && j < MX) ? s.lam[j * MX + i] : 0.0;
+    };
+    // adjoint of TX (cells i in [0,MX), rows -1..MX) and TY (cols -1..MX, rows 0..MX-1):
+    // -lam * lambda_n plus the transverse terms that read them
+    for (int k = threadIdx.x; k < (MX + 2) * MX; k += NT) {
+        {
+            const int j = k / MX - 1, i = k % MX;
+            double v = -lam * LN(i, j);
+            if (j + 1 <= MX) {  // y-edge (i, j+1): v+ TX(i, j)
+                const double ve = s.vy[j + 1] * s.vx[i + 1];
+                v += posp(ve) * (0.5 * lam * lam * (LN(i, j) - LN(i, j + 1)));
+            }
+            if (j >= 0) {       // y-edge (i, j): v- TX(i, j)
+                const double ve = s.vy[j] * s.vx[i + 1];
+                v += negp(ve) * (0.5 * lam * lam * (LN(i, j - 1) - LN(i, j)));
+            }
+            s.u.a.tx[k] = v;
+        }
+        {
+            const int j = k / (MX + 2), i = k % (MX + 2) - 1;
+            double v = -lam * LN(i, j);
+            if (i + 1 <= MX) {  // x-edge (i+1, j): u+ TY(i, j)
+                const double ue = s.ux[i + 1] * s.uy[j + 1];
+                v += posp(ue) * (0.5 * lam * lam * (LN(i, j) - LN(i + 1, j)));
+            }
+            if (i >= 0) {       // x-edge (i, j): u- TY(i, j)
+                const double ue = s.ux[i] * s.uy[j + 1];
+                v += negp(ue) * (0.5 * lam * lam * (LN(i - 1, j) - LN(i, j)));
+            }
+            s.u.a.ty[k] = v;
+        }
+    }
+    __syncthreads();
+    // per edge: adjoints w.r.t. its difference W (g) and its upwind difference (h)
+    for (int k = threadIdx.x; k < NX; k += NT) {
+        {   // x-edge (e, j), e in [0, MX], j in [-1, MX]
+            const int j = k / (MX + 1) - 1, e = k % (MX + 1);
+            const double *row = &s.u.a.q[(j + MB) * N + MB];
+            const double u = s.ux[e] * s.uy[j + 1];
+            const double W = row[e] - row[e - 1];
+            const double Wu = u > 0.0 ? row[e - 1] - row[e - 2] : row[e + 1] - row[e];
+            const double apsb = e < MX ? s.u.a.tx[(j + 1) * MX + e] : 0.0;
+            const double amsb = e >= 1 ? s.u.a.tx[(j + 1) * MX + e - 1] : 0.0;
+            const double cxb = (j >= 0 && j < MX) ? 0.5 * lam * (LN(e - 1, j) - LN(e, j)) : 0.0;
+            const double cb = cxb - apsb + amsb;
+            const double au = fabs(u);
+            const double wlb = au * (1.0 - lam * au) * cb;
+            double dW, dWu;
+            limiter_partials(c.lim, W, Wu, dW, dWu);
+            s.gx[k] = posp(u) * apsb + negp(u) * amsb + dW * wlb;
+            s.hx[k] = dWu * wlb;
+        }
+        {   // y-edge (i, e), e in [0, MX], i in [-1, MX]
+            const int e = k / (MX + 2), i = k % (MX + 2) - 1;
+            const double *col = &s.u.a.q[MB * N + i + MB];
+            const double v = s.vy[e] * s.vx[i + 1];
+            const double W = col[e * N] - col[(e - 1) * N];
+            const double Wu = v > 0.0 ? col[(e - 1) * N] - col[(e - 2) * N] : col[(e + 1) * N] - col[e * N];
+            const double bpsb = e < MX ? s.u.a.ty[e * (MX + 2) + i + 1] : 0.0;
+            const double bmsb = e >= 1 ? s.u.a.ty[(e - 1) * (MX + 2) + i + 1] : 0.0;
+            const double cyb = (i >= 0 && i < MX) ? 0.5 * lam * (LN(i, e - 1) - LN(i, e)) : 0.0;
+            const double cb = cyb - bpsb + bmsb;
+            const double av = fabs(v);
+            const double wlb = av * (1.0 - lam * av) * cb;
+            double dW, dWu;
+            limiter_partials(c.lim, W, Wu, dW, dWu);
+            s.gy[k] = posp(v) * bpsb + negp(v) * bmsb + dW * wlb;
+            s.hy[k] = dWu * wlb;
+        }
+    }
+    __syncthreads();
+    // total adjoint of each difference W_e = Q(e) - Q(e-1), e in [-1, MX+1]:
+    // its own edge plus the neighbouring edges that use it as upwind difference
+    for (int k = threadIdx.x; k < (MX + 2) * (MX + 3); k += NT) {
+        {
+            const int j = k / (MX + 3) - 1, e = k % (MX + 3) - 1;
+            const int r = (j + 1) * (MX + 1);
+            double v = (e >= 0 && e <= MX) ? s.gx[r + e] : 0.0;
+            if (e + 1 <= MX && s.ux[e + 1] * s.uy[j + 1] > 0.0) v += s.hx[r + e + 1];
+            if (e - 1 >= 0 && !(s.ux[e - 1] * s.uy[j + 1] > 0.0)) v += s.hx[r + e - 1];
+            s.u.b.dx[k] = v;
+        }
+        {
+            const int e = k / (MX + 2) - 1, i = k % (MX + 2) - 1;
+            double v = (e >= 0 && e <= MX) ? s.gy[e * (MX + 2) + i + 1] : 0.0;
+            if (e + 1 <= MX && s.vy[e + 1] * s.vx[i + 1] > 0.0) v += s.hy[(e + 1) * (MX + 2) + i + 1];
+            if (e - 1 >= 0 && !(s.vy[e - 1] * s.vx[i + 1] > 0.0)) v += s.hy[(e - 1) * (MX + 2) + i + 1];
+            s.u.b.dy[k] = v;
+        }
+    }
+    __syncthreads();
+    // adjoint of every cell of the patch array (interior and ghosts)
+    for (int k = threadIdx.x; k < N * N; k += NT) {
+        const int i = k % N - MB, j = k / N - MB;
+        double v = LN(i, j);
+        if (j >= -1 && j <= MX) {
+            const int r = (j + 1) * (MX + 3);
+            const double a = (i >= -1 && i <= MX + 1) ? s.u.b.dx[r + i + 1] : 0.0;
+            const double b = (i + 1 >= -1 && i + 1 <= MX + 1) ? s.u.b.dx[r + i + 2] : 0.0;
+            v += a - b;
+        }
+        if (i >= -1 && i <= MX) {
+            const double a = (j >= -1 && j <= MX + 1) ? s.u.b.dy[(j + 1) * (MX + 2) + i + 1] : 0.0;
+            const double b = (j + 1 >= -1 && j + 1 <= MX + 1) ? s.u.b.dy[(j + 2) * (MX + 2) + i + 1] : 0.0;
+            v += a - b;
+        }
+        abar[base + k] = v;
+    }
+}
+
+// Transpose of the same-size ghost copy, in gather form: an interior cell
+// collects its own adjoint and that of every ghost cell that copied it.
+template <int MX>
+__global__ void adjoint_gather_kernel(Ctx c, int first, const int32_t *leaf_of_slot, const double *abar,
+                                      double *lam_out) {
+    constexpr int N = MX + 2 * MB;
+    const int p = first + blockIdx.x;
+    // one record per direction: W, E, S, N, SW, SE, NW, NE
+    const int rec[8] = {0, 2, 4, 6, 8, 9, 10, 11};
+    double *lo = lam_out + (size_t)leaf_of_slot[p] * MX * MX;
+    for (int k = threadIdx.x; k < MX * MX; k += blockDim.x) {
+        const int i = k % MX, j = k / MX;
+        double v = abar[(size_t)p * N * N + (j + MB) * N + i + MB];
+        for (int d = 0; d < 8; d++) {
+            const NbrRec r = c.nbr[p * FC_NREC + rec[d]];
+            if (r.type != NB_SAME) continue;
+            const int iN = i - r.ox, jN = j - r.oy;
+            if (iN < -MB || iN >= MX + MB || jN < -MB || jN >= MX + MB) continue;
+            if (iN >= 0 && iN < MX && jN >= 0 && jN < MX) continue;
+            v += abar[(size_t)r.id * N * N + (jN + MB) * N + iN + MB];
+        }
+        lo[k] = v;
+    }
+}
+
+// ------------------------------------------------------------------------
 // persistent fused kernel: all level-steps of a coarse step in one launch
 // ------------------------------------------------------------------------
 constexpr long long kSpinLimit = 1ll << 22;
@@ -1009,6 +1225,30 @@ hipError_t launch_tag(const Ctx &c, int mx, const int32_t *slot_of_leaf, int n, 
         case 8: hipLaunchKernelGGL(tag_kernel<8>, dim3(n), dim3(64), 0, s, c, slot_of_leaf, lmin, lmax, tau_r, tau_c, tags, g2); break;
         case 16: hipLaunchKernelGGL(tag_kernel<16>, dim3(n), dim3(256), 0, s, c, slot_of_leaf, lmin, lmax, tau_r, tau_c, tags, g2); break;
         case 32: hipLaunchKernelGGL(tag_kernel<32>, dim3(n), dim3(256), 0, s, c, slot_of_leaf, lmin, lmax, tau_r, tau_c, tags, g2); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint(const Ctx &c, int mx, int first, int count, double t, double dt,
+                          const int32_t *leaf_of_slot, const double *lam_in, double *abar, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    switch (mx) {
+        case 8: hipLaunchKernelGGL((adjoint_kernel<8, 64>), dim3(count), dim3(64), 0, s, c, first, count, t, dt, leaf_of_slot, lam_in, abar); break;
+        case 16: hipLaunchKernelGGL((adjoint_kernel<16, 256>), dim3(count), dim3(256), 0, s, c, first, count, t, dt, leaf_of_slot, lam_in, abar); break;
+        case 32: hipLaunchKernelGGL((adjoint_kernel<32, 256>), dim3(count), dim3(256), 0, s, c, first, count, t, dt, leaf_of_slot, lam_in, abar); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_gather(const Ctx &c, int mx, int first, int count, const int32_t *leaf_of_slot,
+                                 const double *abar, double *lam_out, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    switch (mx) {
+        case 8: hipLaunchKernelGGL(adjoint_gather_kernel<8>, dim3(count), dim3(64), 0, s, c, first, leaf_of_slot, abar, lam_out); break;
+        case 16: hipLaunchKernelGGL(adjoint_gather_kernel<16>, dim3(count), dim3(256), 0, s, c, first, leaf_of_slot, abar, lam_out); break;
+        case 32: hipLaunchKernelGGL(adjoint_gather_kernel<32>, dim3(count), dim3(256), 0, s, c, first, leaf_of_slot, abar, lam_out); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -740,8 +740,27 @@ fc_status fc_regrid(fc_patchstore *ps, int64_t nleaves, const fc_leaf *new_leave
 
 fc_status fc_adjoint_step(fc_patchstore *ps, int32_t level, double t, double dt, const double *q_in,
                           const double *lambda_in, double *lambda_out, void *stream) {
-    (void)ps; (void)level; (void)t; (void)dt; (void)q_in; (void)lambda_in; (void)lambda_out; (void)stream;
-    return fail(FC_ERR_STATE, "adjoint step not available in this build");
+    fc_status r = check_bound(ps);
+    if (r != FC_OK) return r;
+    if (!q_in || !lambda_in || !lambda_out) return fail(FC_ERR_ARG, "null array");
+    if (ps->cfg.equation != FC_EQ_ADVECTION) return fail(FC_ERR_ARG, "the adjoint covers scalar advection");
+    if (level < ps->cfg.min_level || level > ps->cfg.max_level) return fail(FC_ERR_ARG, "bad level");
+    const int n = (int)ps->mesh.lv.size();
+    if (ps->lr.count[level] != n) return fail(FC_ERR_ARG, "the adjoint needs a uniform mesh at `level`");
+    if (!(dt > 0)) return fail(FC_ERR_ARG, "dt must be positive");
+    hipStream_t s = (hipStream_t)stream;
+    const int32_t *sl = (const int32_t *)(ps->ws + ps->off_sl);
+    const int32_t *ls = (const int32_t *)(ps->ws + ps->off_ls);
+    // forward state with its ghosts in the level's current buffer
+    HIPCHK(launch_set_interior(make_ctx(ps), ps->mx, sl, n, q_in, s));
+    r = fill_levels(ps, level, level, 1.0, s);
+    if (r != FC_OK) return r;
+    // transpose of the advance into the other buffer, then of the copy
+    Ctx c = make_ctx(ps);
+    double *abar = ((ps->curmask >> level) & 1u) ? ps->q0 : ps->q1;
+    HIPCHK(launch_adjoint(c, ps->mx, ps->lr.start[level], n, t, dt, ls, lambda_in, abar, s));
+    HIPCHK(launch_adjoint_gather(c, ps->mx, ps->lr.start[level], n, ls, abar, lambda_out, s));
+    return FC_OK;
 }
 
 fc_status fc_check_device(fc_patchstore *ps, void *stream) {
