@@ -147,7 +147,9 @@ fc_status fc_advance_level(fc_patchstore *ps, int32_t level, double t, double dt
  * mode FC_MODE_PER_LEVEL: a fill launch and an advance launch per
  * level-step; FC_MODE_FUSED: one persistent kernel that evaluates ghosts on
  * the fly and walks all level-steps with device-wide barriers;
- * FC_MODE_FUSED_GRAPH: the fused kernel replayed from a captured hipGraph;
+ * FC_MODE_FUSED_GRAPH: the fused kernel replayed from a captured hipGraph
+ * (one launch covers up to 50 coarse steps; two graphs are kept: 50 steps
+ * and 1 step);
  * FC_MODE_FUSED_LEVELS: one launch per level-step of the advance kernel
  * that evaluates its ghosts on the fly (no fill launch, no device barrier).
  * nsteps coarse steps are taken.  cfl_dev as above.  The store's time

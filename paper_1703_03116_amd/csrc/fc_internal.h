@@ -98,8 +98,9 @@ hipError_t launch_set_state(DevState *st, double t, double dt, uint32_t curmask,
 hipError_t launch_fill(const Ctx &c, int mx, int first, int count, hipStream_t s);
 hipError_t launch_advance(const Ctx &c, LaunchCfg lc, int level, int first, int count, double t, double dt,
                           int fused, unsigned long long *cfl_bits, hipStream_t s);
+// ncoarse coarse steps in one launch (device-wide barrier between level-steps)
 hipError_t launch_persistent(const Ctx &c, LaunchCfg lc, const SchedEntry *sched, int nsched,
-                             const LevelRange *ranges_dev, int nleaves, DevState *state, int grid,
+                             const LevelRange *ranges_dev, int ncoarse, DevState *state, int grid,
                              hipStream_t s);
 int persistent_max_grid(LaunchCfg lc, int eq);
 hipError_t launch_set_interior(const Ctx &c, int mx, const int32_t *slot_of_leaf, int n, const double *src,

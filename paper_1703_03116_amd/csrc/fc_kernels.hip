@@ -900,9 +900,10 @@ struct SmemOf<MX, 1> { using type = SweSmem<MX>; };
 
 template <int MX, int NT, int EQ>
 __global__ void __launch_bounds__(NT) persistent_kernel(Ctx c, const SchedEntry *sched, int nsched,
-                                                               const LevelRange *lr, int nleaves, DevState *st) {
+                                                        const LevelRange *lr, int ncoarse, DevState *st) {
     __shared__ typename SmemOf<MX, EQ>::type s;
-    const double t0 = st->t, dtc = st->dt_coarse;
+    double t0 = st->t;
+    const double dtc = st->dt_coarse;
     View w{st->curmask, -1, 1.0};
     const unsigned G = gridDim.x;
     const int x = blockIdx.x & 7, r = blockIdx.x >> 3;
@@ -911,31 +912,33 @@ __global__ void __launch_bounds__(NT) persistent_kernel(Ctx c, const SchedEntry 
     int nall = 0;
     for (int l = 0; l < FC_MAXLEV; l++)
         if (lr->count[l] > 0) { allmask |= 1u << l; nall += lr->count[l]; }
-    (void)nleaves;
     double cfl = 0.0;
-    for (int k = 0; k < nsched; k++) {
-        const SchedEntry e = sched[k];
-        int first, count;
-        if (e.level < 0) { first = 0; count = nall; w.clevel = -1; w.alpha = 1.0; }
-        else { first = lr->start[e.level]; count = lr->count[e.level]; w.clevel = e.level - 1; w.alpha = e.alpha; }
-        if (count == 0) {
-            if (e.level >= 0) w.curmask ^= 1u << e.level;
-            continue;
+    for (int cs = 0; cs < ncoarse; cs++) {
+        for (int k = 0; k < nsched; k++) {
+            const SchedEntry e = sched[k];
+            int first, count;
+            if (e.level < 0) { first = 0; count = nall; w.clevel = -1; w.alpha = 1.0; }
+            else { first = lr->start[e.level]; count = lr->count[e.level]; w.clevel = e.level - 1; w.alpha = e.alpha; }
+            if (count == 0) {
+                if (e.level >= 0) w.curmask ^= 1u << e.level;
+                continue;
+            }
+            const double t = t0 + e.off * dtc, dt = e.scale * dtc;
+            const int c0 = (int)(((long long)count * x) >> 3), c1 = (int)(((long long)count * (x + 1)) >> 3);
+            for (int pi = c0 + r; pi < c1; pi += nbx) {
+                if constexpr (EQ == 0) advance_scalar_patch<MX, NT, true>(c, w, s, first + pi, t, dt, cfl);
+                else advance_swe_patch<MX, NT, true>(c, w, s, first + pi, dt, cfl);
+                __syncthreads();
+            }
+            grid_barrier(st, G);
+            w.curmask ^= (e.level < 0) ? allmask : (1u << e.level);
         }
-        const double t = t0 + e.off * dtc, dt = e.scale * dtc;
-        const int c0 = (int)(((long long)count * x) >> 3), c1 = (int)(((long long)count * (x + 1)) >> 3);
-        for (int pi = c0 + r; pi < c1; pi += nbx) {
-            if constexpr (EQ == 0) advance_scalar_patch<MX, NT, true>(c, w, s, first + pi, t, dt, cfl);
-            else advance_swe_patch<MX, NT, true>(c, w, s, first + pi, dt, cfl);
-            __syncthreads();
-        }
-        grid_barrier(st, G);
-        w.curmask ^= (e.level < 0) ? allmask : (1u << e.level);
+        t0 = t0 + dtc;  // the same accumulation as the host's time
     }
     reduce_cfl<NT>(cfl, s.red, &st->cfl_bits);
     grid_barrier(st, G);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        st->t = t0 + dtc;
+        st->t = t0;
         st->curmask = w.curmask;
     }
 }
@@ -1178,11 +1181,11 @@ int persistent_max_grid(LaunchCfg lc, int eq) {
 }
 
 hipError_t launch_persistent(const Ctx &c, LaunchCfg lc, const SchedEntry *sched, int nsched,
-                             const LevelRange *ranges_dev, int nleaves, DevState *state, int grid, hipStream_t s) {
+                             const LevelRange *ranges_dev, int ncoarse, DevState *state, int grid, hipStream_t s) {
     const void *fn = persistent_select(lc, c.eq);
-    if (!fn || grid <= 0) return hipErrorInvalidValue;
+    if (!fn || grid <= 0 || ncoarse <= 0) return hipErrorInvalidValue;
     Ctx cc = c;
-    void *args[] = {&cc, (void *)&sched, &nsched, (void *)&ranges_dev, &nleaves, &state};
+    void *args[] = {&cc, (void *)&sched, &nsched, (void *)&ranges_dev, &ncoarse, &state};
     return hipLaunchKernel(fn, dim3(grid), dim3(lc.nt), args, 0, s);
 }
 

@@ -147,8 +147,10 @@ struct fc_patchstore {
     std::vector<SchedEntry> sched;
     int pgrid = 0;
     int pgrid_user = 0;  // grid override of the persistent kernel (0: occupancy)
-    hipGraphExec_t gexec = nullptr;
-    hipGraph_t graph = nullptr;
+    // captured graphs: [0] one coarse step per launch, [1] `chunk` coarse steps
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    int chunk = 0;
     hipStream_t cap_stream = nullptr;  // private stream the graph is captured on
     int gnt = 0;
 };
@@ -347,10 +349,36 @@ fc_status advance_one(fc_patchstore *ps, int level, double t, double dt, int fus
 }
 
 void drop_graph(fc_patchstore *ps) {
-    if (ps->gexec) (void)hipGraphExecDestroy(ps->gexec);
-    if (ps->graph) (void)hipGraphDestroy(ps->graph);
-    ps->gexec = nullptr;
-    ps->graph = nullptr;
+    for (int k = 0; k < 2; k++) {
+        if (ps->gexec[k]) (void)hipGraphExecDestroy(ps->gexec[k]);
+        if (ps->graph[k]) (void)hipGraphDestroy(ps->graph[k]);
+        ps->gexec[k] = nullptr;
+        ps->graph[k] = nullptr;
+    }
+}
+
+// Capture one persistent launch of `ncoarse` coarse steps.  The kernel reads
+// the time, step, buffer parities and level ranges from device memory, so one
+// capture serves every replay.  Capture runs on a private stream (the null
+// stream cannot be captured); replays go to the caller's stream.
+fc_status capture(fc_patchstore *ps, int which, int ncoarse, int grid) {
+    if (!ps->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ps->cap_stream, hipStreamNonBlocking));
+    Ctx c = make_ctx(ps);
+    const SchedEntry *sched = (const SchedEntry *)(ps->ws + ps->off_sched);
+    const LevelRange *lrd = (const LevelRange *)(ps->ws + ps->off_lr);
+    HIPCHK(hipStreamBeginCapture(ps->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = launch_persistent(c, LaunchCfg{ps->mx, ps->nt}, sched, (int)ps->sched.size(), lrd, ncoarse,
+                                     dstate(ps), grid, ps->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(ps->cap_stream, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        return fail(FC_ERR_HIP, "graph capture failed");
+    }
+    ps->graph[which] = g;
+    HIPCHK(hipGraphInstantiate(&ps->gexec[which], g, nullptr, nullptr, 0));
+    return FC_OK;
 }
 
 }  // namespace
@@ -574,37 +602,34 @@ fc_status fc_advance_coarse_steps(fc_patchstore *ps, double dt_coarse, int32_t n
     if (mode != FC_MODE_FUSED && mode != FC_MODE_FUSED_GRAPH) return fail(FC_ERR_ARG, "unknown mode");
     if (ps->pgrid <= 0) return fail(FC_ERR_HIP, "persistent kernel has no resident blocks");
     const int grid = ps->pgrid_user > 0 ? std::min(ps->pgrid_user, ps->pgrid) : ps->pgrid;
-    const int n = (int)ps->mesh.lv.size();
     DevState *st = dstate(ps);
     HIPCHK(launch_set_state(st, ps->t, dt_coarse, ps->curmask, 1, s));
     Ctx c = make_ctx(ps);
     const SchedEntry *sched = (const SchedEntry *)(ps->ws + ps->off_sched);
     const LevelRange *lrd = (const LevelRange *)(ps->ws + ps->off_lr);
+    // coarse steps per launch: all levels' level-steps of up to `kChunk`
+    // coarse steps run inside one persistent launch
+    const int kChunk = 50;
     if (mode == FC_MODE_FUSED) {
-        for (int k = 0; k < nsteps; k++)
-            HIPCHK(launch_persistent(c, LaunchCfg{ps->mx, ps->nt}, sched, (int)ps->sched.size(), lrd, n, st, grid, s));
-    } else {
-        if (!ps->gexec || ps->gnt != ps->nt) {
-            drop_graph(ps);
-            // The kernel reads the time, step, buffer parities and level
-            // ranges from device memory, so one capture serves every replay.
-            // Capture happens on a private stream (the null stream cannot be
-            // captured); replays go to the caller's stream.
-            if (!ps->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ps->cap_stream, hipStreamNonBlocking));
-            HIPCHK(hipStreamBeginCapture(ps->cap_stream, hipStreamCaptureModeThreadLocal));
-            hipError_t e = launch_persistent(c, LaunchCfg{ps->mx, ps->nt}, sched, (int)ps->sched.size(), lrd, n, st,
-                                             grid, ps->cap_stream);
-            hipGraph_t g = nullptr;
-            hipError_t e2 = hipStreamEndCapture(ps->cap_stream, &g);
-            if (e != hipSuccess || e2 != hipSuccess) {
-                if (g) (void)hipGraphDestroy(g);
-                return fail(FC_ERR_HIP, "graph capture failed");
-            }
-            ps->graph = g;
-            HIPCHK(hipGraphInstantiate(&ps->gexec, g, nullptr, nullptr, 0));
-            ps->gnt = ps->nt;
+        for (int k = 0; k < nsteps; k += kChunk) {
+            const int m = std::min(kChunk, nsteps - k);
+            HIPCHK(launch_persistent(c, LaunchCfg{ps->mx, ps->nt}, sched, (int)ps->sched.size(), lrd, m, st, grid, s));
         }
-        for (int k = 0; k < nsteps; k++) HIPCHK(hipGraphLaunch(ps->gexec, s));
+    } else {
+        if (ps->gnt != ps->nt || ps->chunk != kChunk) {
+            drop_graph(ps);
+            ps->gnt = ps->nt;
+            ps->chunk = kChunk;
+        }
+        int k = 0;
+        if (nsteps >= kChunk) {
+            if (!ps->gexec[1]) { r = capture(ps, 1, kChunk, grid); if (r != FC_OK) return r; }
+            for (; k + kChunk <= nsteps; k += kChunk) HIPCHK(hipGraphLaunch(ps->gexec[1], s));
+        }
+        if (k < nsteps) {
+            if (!ps->gexec[0]) { r = capture(ps, 0, 1, grid); if (r != FC_OK) return r; }
+            for (; k < nsteps; k++) HIPCHK(hipGraphLaunch(ps->gexec[0], s));
+        }
     }
     // host mirror of the device bookkeeping
     uint32_t allmask = 0;
