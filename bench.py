@@ -85,6 +85,8 @@ def main():
     ap.add_argument("--mx", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-level", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -96,6 +98,14 @@ def main():
     from workloads import synth as S
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        # a plain copy kernel of known size: reads 256 MiB, writes 256 MiB
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = S.workload("swirl_uniform", level=args.level, mx=args.mx, steps=args.steps)
     P, mx, F = len(w["leaves"]), w["mx"], 1
     dt = w["dt_coarse"]
