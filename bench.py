@@ -83,6 +83,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--level", type=int, default=5)
     ap.add_argument("--mx", type=int, default=32)
+    ap.add_argument("--workload", default="swirl_uniform",
+                    choices=["swirl_uniform", "swirl_amr", "dam_break"],
+                    help="swirl_uniform (default; --level sets its size), swirl_amr (levels 3-7, regrid "
+                         "every 2 coarse steps), dam_break (shallow water, levels 2-6, 16x16)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-level", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -106,6 +110,8 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.workload != "swirl_uniform":
+        return other_workload(args)
     w = S.workload("swirl_uniform", level=args.level, mx=args.mx, steps=args.steps)
     P, mx, F = len(w["leaves"]), w["mx"], 1
     dt = w["dt_coarse"]
@@ -186,6 +192,53 @@ def main():
         "fused_over_per_level": (value / per_level["value"]) if per_level else None,
         "cpu_baseline": cpu,
     }
+    print(json.dumps(out), flush=True)
+
+
+def other_workload(args):
+    """Adaptive workloads: cell updates over advance + fill time (regrid timed
+    apart), fused graph form and per-level form, one JSON line."""
+    import numpy as np
+    import torch
+    from paper_1703_03116_amd import binding as B
+    from paper_1703_03116_amd.amr import run_adaptive
+    from workloads import synth as S
+
+    res = {}
+    for mode in ("graph", "per_level"):
+        if args.workload == "swirl_amr":
+            w = S.workload("swirl_amr")
+            ps = B.from_workload(w, capacity=4 ** w["lmax"])
+            nt = ps.autotune()
+            tm = {}
+            run_adaptive(ps, w["dt_coarse"], 2, regrid_every=2, mode=mode)  # warm-up
+            cells = run_adaptive(ps, w["dt_coarse"], args.steps, regrid_every=2, mode=mode, timings=tm)
+            res[mode] = {"value": cells / tm["advance"], "advance_s": tm["advance"],
+                         "regrid_s": tm.get("regrid", 0.0), "patches_end": ps.nleaves}
+        else:
+            w = S.workload("dam_break")
+            ps = B.from_workload(w)
+            nt = ps.autotune()
+            lv = np.asarray(w["leaves"])[:, 0]
+            dt = 0.6 / (w["mx"] << w["lmin"]) / 2.5   # finest-level Courant number <= 0.6 for speeds <= 2.5
+            per_step = sum(int((lv == l).sum()) * w["mx"] ** 2 * (1 << (l - w["lmin"])) for l in np.unique(lv))
+            ps.coarse_steps(dt, 2, mode)
+            torch.cuda.synchronize()
+            stream = torch.cuda.current_stream()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            ps.coarse_steps(dt, args.steps, mode)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            sec = e0.elapsed_time(e1) / 1e3
+            ps.check()
+            res[mode] = {"value": per_step * args.steps / sec, "ms_per_coarse_step": 1e3 * sec / args.steps,
+                         "patches": len(lv)}
+    out = {"metric": METRIC, "value": res["graph"]["value"], "unit": "cell-updates/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": 2, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64", "data": "synthetic", "config": {"workload": args.workload, "threads_per_patch": nt},
+           "fused_graph": res["graph"], "per_level": res["per_level"],
+           "fused_over_per_level": res["graph"]["value"] / res["per_level"]["value"]}
     print(json.dumps(out), flush=True)
 
 

@@ -222,14 +222,24 @@ __global__ void __launch_bounds__(256) fill_kernel(Ctx c, int first) {
 template <int MX>
 struct ScalarSmem {
     static constexpr int N = MX + 2 * MB;
+    static constexpr int NP = N + 1;                 // odd row stride: column sweeps avoid bank conflicts
     static constexpr int NX = (MX + 2) * (MX + 1);  // x-edges: rows -1..MX, edges 0..MX
-    double q[N * N];
+    double q[N * NP];
     double cx[NX], apx[NX], amx[NX];  // [j+1][e]
     double cy[NX], bpy[NX], bmy[NX];  // [e][i+1]
     double ux[MX + 1], uy[MX + 2];    // u(e, j) = ux[e] * uy[j+1]
     double vy[MX + 1], vx[MX + 2];    // v(i, e) = vy[e] * vx[i+1]
     double red[16];
 };
+
+// Edges per thread in the edge sweeps: the smallest segment length with
+// (MX+2) lines x ceil((MX+1)/seg) segments <= NT.
+template <int MX, int NT>
+constexpr int edge_seg() {
+    int sg = 1;
+    while ((MX + 2) * ((MX + 1 + sg - 1) / sg) > NT) sg++;
+    return sg;
+}
 
 __device__ __forceinline__ double limit(int lim, double W, double Wu) {
     if (lim == 1) return W;          // Lax-Wendroff
@@ -270,10 +280,14 @@ __device__ void load_velocity(const Ctx &c, ScalarSmem<MX> &s, int l, int gx, in
 // One step on patch p of level l: stage its tile, compute, write the new
 // interior into the level's other buffer.  FUSED: ghosts evaluated on the fly
 // instead of read from the patch's own ghost cells.
+//   x-edges are swept along rows and y-edges along columns, each thread
+//   keeping the four cells of the limiter stencil in registers; the update
+//   sweeps a band of rows per interior column.
 template <int MX, int NT, bool FUSED>
 __device__ void advance_scalar_patch(const Ctx &c, const View &w, ScalarSmem<MX> &s, int p, double t, double dt,
                                      double &cfl) {
-    constexpr int N = MX + 2 * MB, NX = ScalarSmem<MX>::NX;
+    constexpr int N = MX + 2 * MB, NP = ScalarSmem<MX>::NP;
+    constexpr int SEG = edge_seg<MX, NT>(), NSEG = (MX + 1 + SEG - 1) / SEG;
     const PatchInfo P = c.info[p];
     const int l = P.level;
     const double h = 1.0 / (double)(MX << l);
@@ -283,11 +297,11 @@ __device__ void advance_scalar_patch(const Ctx &c, const View &w, ScalarSmem<MX>
     const size_t base = (size_t)p * N * N;
     load_velocity<MX>(c, s, l, P.ix * MX, P.iy * MX, t + 0.5 * dt);
     if (!FUSED) {
-        for (int k = threadIdx.x; k < N * N; k += NT) s.q[k] = in[base + k];
+        for (int k = threadIdx.x; k < N * N; k += NT) s.q[(k / N) * NP + k % N] = in[base + k];
     } else {
         for (int k = threadIdx.x; k < MX * MX; k += NT) {
             const int i = k % MX, j = k / MX;
-            s.q[(j + MB) * N + i + MB] = in[base + (j + MB) * N + i + MB];
+            s.q[(j + MB) * NP + i + MB] = in[base + (j + MB) * N + i + MB];
         }
         constexpr int NG = N * N - MX * MX;
         for (int g = threadIdx.x; g < NG; g += NT) {
@@ -295,40 +309,54 @@ __device__ void advance_scalar_patch(const Ctx &c, const View &w, ScalarSmem<MX>
             ghost_index<MX>(g, i, j);
             double v[1];
             ghost_cell<MX, 1>(c, w, p, i, j, v);
-            s.q[(j + MB) * N + i + MB] = v[0];
+            s.q[(j + MB) * NP + i + MB] = v[0];
         }
     }
     __syncthreads();
     double amax = 0.0;
-    // x-edges (e - 1/2, j): e in [0, MX], j in [-1, MX]
-    for (int k = threadIdx.x; k < NX; k += NT) {
-        const int j = k / (MX + 1) - 1, e = k % (MX + 1);
-        const double *row = &s.q[(j + MB) * N + MB];
-        const double qm2 = row[e - 2], qm1 = row[e - 1], q0 = row[e], qp1 = row[e + 1];
-        const double u = s.ux[e] * s.uy[j + 1];
-        const double W = q0 - qm1;
-        const double Wu = u > 0.0 ? qm1 - qm2 : qp1 - q0;
-        const double au = fabs(u);
-        const double C = au * (1.0 - lam * au) * limit(c.lim, W, Wu);
-        s.cx[k] = C;
-        s.apx[k] = posp(u) * W - C;
-        s.amx[k] = negp(u) * W + C;
-        if (j >= 0 && j < MX) amax = fmax(amax, au);
-    }
-    // y-edges (i, e - 1/2): e in [0, MX], i in [-1, MX]
-    for (int k = threadIdx.x; k < NX; k += NT) {
-        const int e = k / (MX + 2), i = k % (MX + 2) - 1;
-        const double *col = &s.q[MB * N + i + MB];
-        const double qm2 = col[(e - 2) * N], qm1 = col[(e - 1) * N], q0 = col[e * N], qp1 = col[(e + 1) * N];
-        const double v = s.vy[e] * s.vx[i + 1];
-        const double W = q0 - qm1;
-        const double Wu = v > 0.0 ? qm1 - qm2 : qp1 - q0;
-        const double av = fabs(v);
-        const double C = av * (1.0 - lam * av) * limit(c.lim, W, Wu);
-        s.cy[k] = C;
-        s.bpy[k] = posp(v) * W - C;
-        s.bmy[k] = negp(v) * W + C;
-        if (i >= 0 && i < MX) amax = fmax(amax, av);
+    for (int item = threadIdx.x; item < (MX + 2) * NSEG; item += NT) {
+        const int line = item / NSEG - 1, e0 = (item % NSEG) * SEG;
+        const int e1 = e0 + SEG < MX + 1 ? e0 + SEG : MX + 1;
+        {   // x-edges (e - 1/2, j = line), e in [e0, e1)
+            const int j = line;
+            const double *row = &s.q[(j + MB) * NP + MB];
+            const double uyj = s.uy[j + 1];
+            double qm2 = row[e0 - 2], qm1 = row[e0 - 1], q0 = row[e0];
+            for (int e = e0; e < e1; e++) {
+                const double qp1 = row[e + 1];
+                const double u = s.ux[e] * uyj;
+                const double W = q0 - qm1;
+                const double Wu = u > 0.0 ? qm1 - qm2 : qp1 - q0;
+                const double au = fabs(u);
+                const double C = au * (1.0 - lam * au) * limit(c.lim, W, Wu);
+                const int k = (j + 1) * (MX + 1) + e;
+                s.cx[k] = C;
+                s.apx[k] = posp(u) * W - C;
+                s.amx[k] = negp(u) * W + C;
+                if (j >= 0 && j < MX) amax = fmax(amax, au);
+                qm2 = qm1; qm1 = q0; q0 = qp1;
+            }
+        }
+        {   // y-edges (i = line, e - 1/2), e in [e0, e1)
+            const int i = line;
+            const double *col = &s.q[MB * NP + i + MB];
+            const double vxi = s.vx[i + 1];
+            double qm2 = col[(e0 - 2) * NP], qm1 = col[(e0 - 1) * NP], q0 = col[e0 * NP];
+            for (int e = e0; e < e1; e++) {
+                const double qp1 = col[(e + 1) * NP];
+                const double v = s.vy[e] * vxi;
+                const double W = q0 - qm1;
+                const double Wu = v > 0.0 ? qm1 - qm2 : qp1 - q0;
+                const double av = fabs(v);
+                const double C = av * (1.0 - lam * av) * limit(c.lim, W, Wu);
+                const int k = e * (MX + 2) + i + 1;
+                s.cy[k] = C;
+                s.bpy[k] = posp(v) * W - C;
+                s.bmy[k] = negp(v) * W + C;
+                if (i >= 0 && i < MX) amax = fmax(amax, av);
+                qm2 = qm1; qm1 = q0; q0 = qp1;
+            }
+        }
     }
     __syncthreads();
     // per cell: TX = A+*_{i-1/2} + A-*_{i+1/2} (rows -1..MX), TY likewise
@@ -341,25 +369,36 @@ __device__ void advance_scalar_patch(const Ctx &c, const View &w, ScalarSmem<MX>
         s.bpy[b] = s.bpy[b] + s.bmy[b + MX + 2];
     }
     __syncthreads();
-    // conservative update:
+    // conservative update, a band of R rows per interior column:
     // Q - lam (TX + TY) + lam/2 (dCx + dCy) + lam^2/2 (dTF + dTG), where
     // TF(i-1/2) = u+ TY(i-1) + u- TY(i) and TG(j-1/2) = v+ TX(j-1) + v- TX(j)
-    for (int k = threadIdx.x; k < MX * MX; k += NT) {
-        const int j = k / MX, i = k % MX;
-        const int ax = (j + 1) * (MX + 1) + i;
-        const double TXc = s.apx[ax], TXd = s.apx[ax - (MX + 1)], TXu = s.apx[ax + (MX + 1)];
-        const int by = j * (MX + 2) + i + 1;
-        const double TYc = s.bpy[by], TYl = s.bpy[by - 1], TYr = s.bpy[by + 1];
-        const double uL = s.ux[i] * s.uy[j + 1], uR = s.ux[i + 1] * s.uy[j + 1];
-        const double vD = s.vy[j] * s.vx[i + 1], vU = s.vy[j + 1] * s.vx[i + 1];
-        const double TFl = posp(uL) * TYl + negp(uL) * TYc;
-        const double TFr = posp(uR) * TYc + negp(uR) * TYr;
-        const double TGd = posp(vD) * TXd + negp(vD) * TXc;
-        const double TGu = posp(vU) * TXc + negp(vU) * TXu;
-        const double dC = (s.cx[ax + 1] - s.cx[ax]) + (s.cy[by + MX + 2] - s.cy[by]);
-        const double Q = s.q[(j + MB) * N + i + MB];
-        out[base + (j + MB) * N + i + MB] =
-            Q - lam * (TXc + TYc) + 0.5 * lam * dC + 0.5 * lam * lam * ((TFr - TFl) + (TGu - TGd));
+    constexpr int R = (MX * MX) / NT > 0 ? (MX * MX) / NT : 1;
+    constexpr int NBAND = MX / R;
+    if (threadIdx.x < MX * NBAND) {
+        const int i = threadIdx.x % MX, j0 = (threadIdx.x / MX) * R;
+        const double uxl = s.ux[i], uxr = s.ux[i + 1], vxi = s.vx[i + 1];
+        double TXd = s.apx[j0 * (MX + 1) + i], TXc = s.apx[(j0 + 1) * (MX + 1) + i];
+        double vD = s.vy[j0] * vxi;
+        double cyd = s.cy[j0 * (MX + 2) + i + 1];
+        for (int j = j0; j < j0 + R; j++) {
+            const int ax = (j + 1) * (MX + 1) + i;
+            const double TXu = s.apx[ax + (MX + 1)];
+            const int by = j * (MX + 2) + i + 1;
+            const double TYc = s.bpy[by], TYl = s.bpy[by - 1], TYr = s.bpy[by + 1];
+            const double uyj = s.uy[j + 1];
+            const double uL = uxl * uyj, uR = uxr * uyj;
+            const double vU = s.vy[j + 1] * vxi;
+            const double TFl = posp(uL) * TYl + negp(uL) * TYc;
+            const double TFr = posp(uR) * TYc + negp(uR) * TYr;
+            const double TGd = posp(vD) * TXd + negp(vD) * TXc;
+            const double TGu = posp(vU) * TXc + negp(vU) * TXu;
+            const double cyu = s.cy[by + MX + 2];
+            const double dC = (s.cx[ax + 1] - s.cx[ax]) + (cyu - cyd);
+            const double Q = s.q[(j + MB) * NP + i + MB];
+            out[base + (j + MB) * N + i + MB] =
+                Q - lam * (TXc + TYc) + 0.5 * lam * dC + 0.5 * lam * lam * ((TFr - TFl) + (TGu - TGd));
+            TXd = TXc; TXc = TXu; vD = vU; cyd = cyu;
+        }
     }
     cfl = fmax(cfl, lam * amax);
 }

@@ -317,3 +317,38 @@ def test_swe_single_step_cfl(B, O):
     c_o = o.advance_level(3, 0.0, 0.002)
     assert rel(ps.interior(), o.interior()) <= TOL
     assert abs(cfl.item() - c_o) <= 1e-14 * c_o
+
+
+def _oracle_run_adaptive(o, dt, ncoarse, regrid_every, tau_r, tau_c):
+    t = 0.0
+    for k in range(ncoarse):
+        if k % regrid_every == 0 and k > 0:
+            o.ghost_fill()
+            tags, _ = o.tag(tau_r, tau_c)
+            o.regrid(o.adapt(tags))
+        o.coarse_step(t, dt)
+        t = t + dt
+    return t
+
+
+@pytest.mark.parametrize("mx", [8, 16])
+def test_adaptive_swirl_with_regrid(B, O, mx):
+    """Levels 2-5, swirl, Gaussians; regrid every 2 coarse steps by tagging
+    |grad q|; multirate through the persistent kernel between regrids."""
+    from paper_1703_03116_amd.amr import run_adaptive
+    gp = S.gaussian_params(3)
+    L = S.refine_where(lambda l, ix, iy: S.gaussian_grad_max(gp, (l, ix, iy)) / (mx << l) > 0.02, 2, 4)
+    q0 = S.sample_on_leaves(S.gaussians(gp), L, mx)
+    ps = B.PatchStore(L, mx=mx, velocity="swirl", vel_params=(1.0, 0, 0), min_level=2, max_level=5,
+                      capacity=4 ** 5)
+    ps.set_interior(q0)
+    o = O.Oracle(L, mx=mx, velocity="swirl", vel_params=(1.0, 0, 0), lmin=2, lmax=5)
+    o.set_interior(q0)
+    dt = 0.9 / (mx * 4)
+    tau_r, tau_c = 2.0, 1.0
+    run_adaptive(ps, dt, 6, regrid_every=2, tau_refine=tau_r, tau_coarsen=tau_c)
+    _oracle_run_adaptive(o, dt, 6, 2, tau_r, tau_c)
+    ps.check()
+    assert np.array_equal(np.sort(ps.leaves().view("i4,i4,i4"), axis=0), np.sort(o.leaves().view("i4,i4,i4"), axis=0))
+    assert ps.nleaves == o.n and ps.nleaves != len(L)
+    assert rel(ps.interior(), o.interior()) <= TOL

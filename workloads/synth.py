@@ -307,11 +307,9 @@ def workload(name: str, **over):
         seed = over.get("seed", 3)
         gp = gaussian_params(seed)
         tau = over.get("tau", 0.05)
-        # geometric input rule: refine quadrants whose analytic gradient bound
-        # exceeds tau times 4 (leaves a margin for the evolving field)
-        leaves = refine_where(
-            lambda l, ix, iy: gaussian_grad_max(gp, (l, ix, iy)) * (1.0 / (mx << l)) > tau * over.get("grad_scale", 0.02),
-            lmin, lmax)
+        # geometric input rule: refine a quadrant while an analytic upper
+        # bound of |grad q0| over it exceeds tau, then 2:1 balance
+        leaves = refine_where(lambda l, ix, iy: gaussian_grad_max(gp, (l, ix, iy)) > tau, lmin, lmax)
         q0 = sample_on_leaves(gaussians(gp), leaves, mx)
         dt = 0.9 / (mx * (1 << lmin))
         w = dict(leaves=leaves, mx=mx, equation="advection",
