@@ -1209,13 +1209,27 @@ static const void *persistent_select(LaunchCfg lc, int eq) {
     return nullptr;
 }
 
+// Workgroups of the persistent kernel that are certainly co-resident: the
+// occupancy query, capped by an LDS count that rounds each workgroup's
+// allocation up to 2 KiB (a kernel at the edge of the CU's LDS must not be
+// counted one workgroup too many: its barrier would then wait on a workgroup
+// that cannot start).
 int persistent_max_grid(LaunchCfg lc, int eq) {
     const void *fn = persistent_select(lc, eq);
     if (!fn) return 0;
-    int per_cu = 0, dev = 0, cus = 0;
+    int per_cu = 0, dev = 0, cus = 0, lds_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, lc.nt, 0) != hipSuccess) return 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess)
+        return 0;
+    hipFuncAttributes fa;
+    if (hipFuncGetAttributes(&fa, fn) != hipSuccess) return 0;
+    const size_t lds = ((fa.sharedSizeBytes + 2047) / 2048) * 2048;
+    if (lds > 0 && lds_cu > 0) {
+        const int by_lds = (int)((size_t)lds_cu / lds);
+        if (by_lds < per_cu) per_cu = by_lds;
+    }
     return per_cu * cus;
 }
 

@@ -35,12 +35,13 @@ def rel(a, b):
 
 
 def pair(B, O, leaves, mx, q, equation="advection", velocity="constant", vel_params=(1.0, 0.5, 0.0),
-         bc=("periodic",) * 4, lmin=None, lmax=None, limiter="mc", time_stepping="multirate"):
+         bc=("periodic",) * 4, lmin=None, lmax=None, limiter="mc", time_stepping="multirate", capacity=None):
     lv = np.asarray(leaves)
     lmin = int(lv[:, 0].min()) if lmin is None else lmin
     lmax = int(lv[:, 0].max()) if lmax is None else lmax
     ps = B.PatchStore(leaves, mx=mx, equation=equation, limiter=limiter, bc=bc, velocity=velocity,
-                      vel_params=vel_params, min_level=lmin, max_level=lmax, time_stepping=time_stepping)
+                      vel_params=vel_params, min_level=lmin, max_level=lmax, time_stepping=time_stepping,
+                      capacity=capacity)
     ps.set_interior(q)
     o = O.Oracle(leaves, mx=mx, equation=equation, limiter=limiter, bc=bc, velocity=velocity,
                  vel_params=vel_params, lmin=lmin, lmax=lmax)
@@ -229,7 +230,7 @@ def test_replicated_blocks_identical(B):
 def test_tag_and_adapt_parity(B, O):
     L = S.random_balanced_leaves(9, 2, 4)
     q = S.sample_on_leaves(S.gaussians(S.gaussian_params(9)), L, 8)
-    ps, o = pair(B, O, L, 8, q, velocity="swirl", vel_params=(1.0, 0, 0), lmin=2, lmax=5)
+    ps, o = pair(B, O, L, 8, q, velocity="swirl", vel_params=(1.0, 0, 0), lmin=2, lmax=5, capacity=4 ** 5)
     ps.ghost_fill()
     o.ghost_fill()
     tg, g2 = ps.tag(2.0, 0.5)
