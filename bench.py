@@ -27,7 +27,6 @@ sys.path.insert(0, ROOT)
 
 METRIC = "cell-updates/sec (advance+ghost fill) at 1 GPU; % HBM roofline; fused vs per-level"
 HBM_PEAK_GBS = 8000.0
-STEPS_PER_LAUNCH = 50  # coarse steps per persistent-kernel launch in graph mode (fc.h)
 KERNEL_SOURCES = ["paper_1703_03116_amd/csrc/fc_kernels.hip", "paper_1703_03116_amd/csrc/fc_internal.h"]
 
 
@@ -120,50 +119,39 @@ def main():
     nt = ps.autotune()
     stream = torch.cuda.current_stream()
 
-    def timed(mode, k):
+    def timed(store, mode, k):
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        ps.coarse_steps(dt, k, mode)
+        store.coarse_steps(dt, k, mode)
         e1.record(stream)
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / 1e3
 
+    # headline: one ghost-gathering advance kernel per level-step, chunks of
+    # coarse steps replayed from a captured hipGraph
     ps.coarse_steps(dt, args.warmup, "graph")
-    sec = timed("graph", args.steps)
+    sec = timed(ps, "graph", args.steps)
     ps.check()
     value = cells_per_step * args.steps / sec
-
-    # per-launch durations of the persistent kernel on the launch stream; one
-    # launch runs STEPS_PER_LAUNCH coarse steps
-    durs = []
-    for _ in range(max(1, args.steps // STEPS_PER_LAUNCH)):
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        ps.coarse_steps(dt, STEPS_PER_LAUNCH, "graph")
-        b.record(stream)
-        durs.append((a, b))
-    torch.cuda.synchronize()
-    avg_launch = sum(a.elapsed_time(b) for a, b in durs) / len(durs) / 1e3
-    bpl = STEPS_PER_LAUNCH * algorithmic_bytes(P, mx, F)
+    # uniform level: one level-step kernel launch per coarse step; its average
+    # duration over the timed region (graph node gaps included)
+    avg_launch = sec / args.steps
+    bpl = algorithmic_bytes(P, mx, F)
     achieved = bpl / avg_launch / 1e9
     traffic = traffic_from_profiles(bpl)
 
-    per_level = None
+    forms = {}
     if not args.no_per_level:
-        ps2 = B.from_workload(w)
-        ps2.set_variant(nt)
-        ps2.coarse_steps(dt, args.warmup, "per_level")
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        ps2.coarse_steps(dt, args.steps, "per_level")
-        e1.record(stream)
-        torch.cuda.synchronize()
-        s2 = e0.elapsed_time(e1) / 1e3
-        per_level = {"value": cells_per_step * args.steps / s2, "ms_per_step": 1e3 * s2 / args.steps,
-                     "launches_per_step": 2}
-        del ps2
+        for mode in ("per_level", "persistent_graph", "fused_levels"):
+            ps2 = B.from_workload(w)
+            ps2.set_variant(nt)
+            ps2.coarse_steps(dt, args.warmup, mode)
+            s2 = timed(ps2, mode, args.steps)
+            ps2.check()
+            forms[mode] = {"value": cells_per_step * args.steps / s2, "ms_per_step": 1e3 * s2 / args.steps}
+            del ps2
+    per_level = forms.get("per_level")
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(w)
     out = {
@@ -182,13 +170,15 @@ def main():
         "config": {"workload": f"swirl_uniform_l{args.level}: {P} patches of {mx}x{mx} cells, 2 ghost layers, "
                                f"FP64 scalar advection, swirl field T=1, seeded 8-Gaussian data, "
                                f"{args.steps} steps",
-                   "patches": P, "mx": mx, "cells": cells_per_step, "mode": "fused persistent kernel + hipGraph",
+                   "patches": P, "mx": mx, "cells": cells_per_step,
+                   "mode": "fused: one ghost-gathering advance kernel per level-step, replayed from a hipGraph",
                    "threads_per_patch": nt},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "persistent_scalar_kernel", "bytes_per_launch": bpl,
-                     "avg_launch_ms": 1e3 * avg_launch, "steps_per_launch": STEPS_PER_LAUNCH},
+                     "kernel": "level_step_kernel<32,%d,0>" % nt, "bytes_per_launch": bpl,
+                     "avg_launch_ms": 1e3 * avg_launch},
         "per_level": per_level,
+        "other_forms": forms,
         "fused_over_per_level": (value / per_level["value"]) if per_level else None,
         "cpu_baseline": cpu,
     }

@@ -60,7 +60,13 @@ enum { FC_BC_PERIODIC = 0, FC_BC_REFLECT = 1 };
 enum { FC_VEL_NONE = 0, FC_VEL_CONSTANT = 1, FC_VEL_SWIRL = 2 };
 enum { FC_LIM_MC = 0, FC_LIM_LW = 1, FC_LIM_FIRST = 2, FC_LIM_MINMOD = 3 };
 enum { FC_STEP_MULTIRATE = 0, FC_STEP_GLOBAL = 1 };
-enum { FC_MODE_PER_LEVEL = 0, FC_MODE_FUSED = 1, FC_MODE_FUSED_GRAPH = 2, FC_MODE_FUSED_LEVELS = 3 };
+enum {
+    FC_MODE_PER_LEVEL = 0,       /* fill launch + advance launch per level-step                    */
+    FC_MODE_FUSED = 1,           /* one persistent kernel, device-wide barriers between level-steps */
+    FC_MODE_FUSED_GRAPH = 2,     /* one ghost-gathering kernel per level-step, replayed as a graph  */
+    FC_MODE_FUSED_LEVELS = 3,    /* the same kernels launched one by one from the host             */
+    FC_MODE_PERSISTENT_GRAPH = 4 /* the persistent kernel replayed as a graph                      */
+};
 
 /* A quadrant of the single unit-square block: 0 <= ix, iy < 2^level. */
 typedef struct { int32_t level, ix, iy; } fc_leaf;
@@ -145,13 +151,14 @@ fc_status fc_advance_level(fc_patchstore *ps, int32_t level, double t, double dt
  * by dt_coarse (multirate: level l takes 2^(l-min_level) steps of
  * dt_coarse / 2^(l-min_level); global: every level one step of dt_coarse).
  * mode FC_MODE_PER_LEVEL: a fill launch and an advance launch per
- * level-step; FC_MODE_FUSED: one persistent kernel that evaluates ghosts on
- * the fly and walks all level-steps with device-wide barriers;
- * FC_MODE_FUSED_GRAPH: the fused kernel replayed from a captured hipGraph
- * (one launch covers up to 50 coarse steps; two graphs are kept: 50 steps
- * and 1 step);
- * FC_MODE_FUSED_LEVELS: one launch per level-step of the advance kernel
- * that evaluates its ghosts on the fly (no fill launch, no device barrier).
+ * level-step; FC_MODE_FUSED: one persistent kernel per chunk of up to 50
+ * coarse steps that evaluates ghosts on the fly and walks all level-steps
+ * with device-wide barriers; FC_MODE_PERSISTENT_GRAPH: that kernel replayed
+ * from a captured hipGraph; FC_MODE_FUSED_GRAPH: one ghost-gathering advance
+ * kernel per level-step (no fill launch), a chunk of up to 50 coarse steps
+ * captured once as a hipGraph and replayed (time, step and buffer parities
+ * live in device memory); FC_MODE_FUSED_LEVELS: those kernels launched one
+ * by one from the host.  All modes compute bitwise the same result.
  * nsteps coarse steps are taken.  cfl_dev as above.  The store's time
  * advances by nsteps * dt_coarse. */
 fc_status fc_advance_coarse_steps(fc_patchstore *ps, double dt_coarse, int32_t nsteps, int32_t mode,

@@ -21,7 +21,7 @@ BC = {"periodic": 0, "reflect": 1}
 VEL = {"none": 0, "constant": 1, "swirl": 2}
 LIM = {"mc": 0, "lw": 1, "first": 2, "minmod": 3}
 STEP = {"multirate": 0, "global": 1}
-MODE = {"per_level": 0, "fused": 1, "graph": 2, "fused_levels": 3}
+MODE = {"per_level": 0, "fused": 1, "graph": 2, "fused_levels": 3, "persistent_graph": 4}
 
 FC_ERRORS = {-1: "FC_ERR_ARG", -2: "FC_ERR_UNBALANCED", -3: "FC_ERR_GHOST_WIDTH", -4: "FC_ERR_HIP",
              -5: "FC_ERR_CFL", -6: "FC_ERR_STATE", -7: "FC_ERR_CAPACITY", -8: "FC_ERR_COVER"}

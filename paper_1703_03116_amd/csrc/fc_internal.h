@@ -103,6 +103,12 @@ hipError_t launch_persistent(const Ctx &c, LaunchCfg lc, const SchedEntry *sched
                              const LevelRange *ranges_dev, int ncoarse, DevState *state, int grid,
                              hipStream_t s);
 int persistent_max_grid(LaunchCfg lc, int eq);
+// one level-step (entry k of the schedule, coarse step cidx of a chunk,
+// parities = device curmask ^ flip) with ghosts gathered on the fly
+hipError_t launch_level_step(const Ctx &c, LaunchCfg lc, const SchedEntry *sched, int k, int cidx, uint32_t flip,
+                             const LevelRange *lr, DevState *st, int grid, hipStream_t s);
+// advance the device time by ncoarse coarse steps and flip the parities
+hipError_t launch_finish_chunk(DevState *st, int ncoarse, uint32_t flip, hipStream_t s);
 hipError_t launch_set_interior(const Ctx &c, int mx, const int32_t *slot_of_leaf, int n, const double *src,
                                hipStream_t s);
 hipError_t launch_get_interior(const Ctx &c, int mx, const int32_t *slot_of_leaf, int n, double *dst,

@@ -222,22 +222,24 @@ __global__ void __launch_bounds__(256) fill_kernel(Ctx c, int first) {
 template <int MX>
 struct ScalarSmem {
     static constexpr int N = MX + 2 * MB;
-    static constexpr int NP = N + 1;                 // odd row stride: column sweeps avoid bank conflicts
-    static constexpr int NX = (MX + 2) * (MX + 1);  // x-edges: rows -1..MX, edges 0..MX
+    static constexpr int NP = N + 1;  // odd row stride: column sweeps avoid bank conflicts
     double q[N * NP];
-    double cx[NX], apx[NX], amx[NX];  // [j+1][e]
-    double cy[NX], bpy[NX], bmy[NX];  // [e][i+1]
+    double tx[(MX + 2) * MX];         // TX(i, j) = A+*_{i-1/2} + A-*_{i+1/2}, [j+1][i], rows -1..MX
+    double dcx[MX * MX];              // C_{i+1/2} - C_{i-1/2} of the x-edges, [j][i]
+    double ty[MX * (MX + 2)];         // TY(i, j), [j][i+1], columns -1..MX
+    double dcy[MX * MX];              // C_{j+1/2} - C_{j-1/2} of the y-edges, [j][i]
     double ux[MX + 1], uy[MX + 2];    // u(e, j) = ux[e] * uy[j+1]
     double vy[MX + 1], vx[MX + 2];    // v(i, e) = vy[e] * vx[i+1]
     double red[16];
 };
 
-// Edges per thread in the edge sweeps: the smallest segment length with
-// (MX+2) lines x ceil((MX+1)/seg) segments <= NT.
+// Cells per thread in the edge sweeps: the smallest segment length with
+// (MX+2) lines x ceil(MX/seg) segments <= NT (a segment also computes the
+// first edge of the next one).
 template <int MX, int NT>
 constexpr int edge_seg() {
     int sg = 1;
-    while ((MX + 2) * ((MX + 1 + sg - 1) / sg) > NT) sg++;
+    while ((MX + 2) * ((MX + sg - 1) / sg) > NT) sg++;
     return sg;
 }
 
@@ -287,7 +289,7 @@ template <int MX, int NT, bool FUSED>
 __device__ void advance_scalar_patch(const Ctx &c, const View &w, ScalarSmem<MX> &s, int p, double t, double dt,
                                      double &cfl) {
     constexpr int N = MX + 2 * MB, NP = ScalarSmem<MX>::NP;
-    constexpr int SEG = edge_seg<MX, NT>(), NSEG = (MX + 1 + SEG - 1) / SEG;
+    constexpr int SEG = edge_seg<MX, NT>(), NSEG = (MX + SEG - 1) / SEG;
     const PatchInfo P = c.info[p];
     const int l = P.level;
     const double h = 1.0 / (double)(MX << l);
@@ -314,59 +316,60 @@ __device__ void advance_scalar_patch(const Ctx &c, const View &w, ScalarSmem<MX>
     }
     __syncthreads();
     double amax = 0.0;
+    // Each item sweeps edges e0..e1 of one line (the segment plus the first
+    // edge of the next one) and writes the per-cell sums of the cells between
+    // them: TX(i) = A+*_{i-1/2} + A-*_{i+1/2} and C_{i+1/2} - C_{i-1/2}.
     for (int item = threadIdx.x; item < (MX + 2) * NSEG; item += NT) {
         const int line = item / NSEG - 1, e0 = (item % NSEG) * SEG;
-        const int e1 = e0 + SEG < MX + 1 ? e0 + SEG : MX + 1;
-        {   // x-edges (e - 1/2, j = line), e in [e0, e1)
+        const int e1 = e0 + SEG < MX ? e0 + SEG : MX;  // last edge computed (inclusive)
+        {   // x-edges (e - 1/2, j = line)
             const int j = line;
             const double *row = &s.q[(j + MB) * NP + MB];
             const double uyj = s.uy[j + 1];
             double qm2 = row[e0 - 2], qm1 = row[e0 - 1], q0 = row[e0];
-            for (int e = e0; e < e1; e++) {
+            double aps_prev = 0.0, c_prev = 0.0;
+            for (int e = e0; e <= e1; e++) {
                 const double qp1 = row[e + 1];
                 const double u = s.ux[e] * uyj;
                 const double W = q0 - qm1;
                 const double Wu = u > 0.0 ? qm1 - qm2 : qp1 - q0;
                 const double au = fabs(u);
                 const double C = au * (1.0 - lam * au) * limit(c.lim, W, Wu);
-                const int k = (j + 1) * (MX + 1) + e;
-                s.cx[k] = C;
-                s.apx[k] = posp(u) * W - C;
-                s.amx[k] = negp(u) * W + C;
-                if (j >= 0 && j < MX) amax = fmax(amax, au);
+                const double aps = posp(u) * W - C;
+                const double ams = negp(u) * W + C;
+                if (e > e0) {  // cell e-1 lies between edges e-1 and e
+                    s.tx[(j + 1) * MX + e - 1] = aps_prev + ams;
+                    if (j >= 0 && j < MX) s.dcx[j * MX + e - 1] = C - c_prev;
+                }
+                if (j >= 0 && j < MX && e < e1 + (e1 == MX ? 1 : 0)) amax = fmax(amax, au);
+                aps_prev = aps; c_prev = C;
                 qm2 = qm1; qm1 = q0; q0 = qp1;
             }
         }
-        {   // y-edges (i = line, e - 1/2), e in [e0, e1)
+        {   // y-edges (i = line, e - 1/2)
             const int i = line;
             const double *col = &s.q[MB * NP + i + MB];
             const double vxi = s.vx[i + 1];
             double qm2 = col[(e0 - 2) * NP], qm1 = col[(e0 - 1) * NP], q0 = col[e0 * NP];
-            for (int e = e0; e < e1; e++) {
+            double bps_prev = 0.0, c_prev = 0.0;
+            for (int e = e0; e <= e1; e++) {
                 const double qp1 = col[(e + 1) * NP];
                 const double v = s.vy[e] * vxi;
                 const double W = q0 - qm1;
                 const double Wu = v > 0.0 ? qm1 - qm2 : qp1 - q0;
                 const double av = fabs(v);
                 const double C = av * (1.0 - lam * av) * limit(c.lim, W, Wu);
-                const int k = e * (MX + 2) + i + 1;
-                s.cy[k] = C;
-                s.bpy[k] = posp(v) * W - C;
-                s.bmy[k] = negp(v) * W + C;
-                if (i >= 0 && i < MX) amax = fmax(amax, av);
+                const double bps = posp(v) * W - C;
+                const double bms = negp(v) * W + C;
+                if (e > e0) {
+                    s.ty[(e - 1) * (MX + 2) + i + 1] = bps_prev + bms;
+                    if (i >= 0 && i < MX) s.dcy[(e - 1) * MX + i] = C - c_prev;
+                }
+                if (i >= 0 && i < MX && e < e1 + (e1 == MX ? 1 : 0)) amax = fmax(amax, av);
+                bps_prev = bps; c_prev = C;
                 qm2 = qm1; qm1 = q0; q0 = qp1;
             }
         }
-    }
-    __syncthreads();
-    // per cell: TX = A+*_{i-1/2} + A-*_{i+1/2} (rows -1..MX), TY likewise
-    for (int k = threadIdx.x; k < (MX + 2) * MX; k += NT) {
-        const int j = k / MX - 1, i = k % MX;
-        const int a = (j + 1) * (MX + 1) + i;
-        s.apx[a] = s.apx[a] + s.amx[a + 1];
-        const int jj = k / (MX + 2), ii = k % (MX + 2) - 1;
-        const int b = jj * (MX + 2) + ii + 1;
-        s.bpy[b] = s.bpy[b] + s.bmy[b + MX + 2];
     }
     __syncthreads();
     // conservative update, a band of R rows per interior column:
@@ -377,14 +380,12 @@ __device__ void advance_scalar_patch(const Ctx &c, const View &w, ScalarSmem<MX>
     if (threadIdx.x < MX * NBAND) {
         const int i = threadIdx.x % MX, j0 = (threadIdx.x / MX) * R;
         const double uxl = s.ux[i], uxr = s.ux[i + 1], vxi = s.vx[i + 1];
-        double TXd = s.apx[j0 * (MX + 1) + i], TXc = s.apx[(j0 + 1) * (MX + 1) + i];
+        double TXd = s.tx[j0 * MX + i], TXc = s.tx[(j0 + 1) * MX + i];
         double vD = s.vy[j0] * vxi;
-        double cyd = s.cy[j0 * (MX + 2) + i + 1];
         for (int j = j0; j < j0 + R; j++) {
-            const int ax = (j + 1) * (MX + 1) + i;
-            const double TXu = s.apx[ax + (MX + 1)];
+            const double TXu = s.tx[(j + 2) * MX + i];
             const int by = j * (MX + 2) + i + 1;
-            const double TYc = s.bpy[by], TYl = s.bpy[by - 1], TYr = s.bpy[by + 1];
+            const double TYc = s.ty[by], TYl = s.ty[by - 1], TYr = s.ty[by + 1];
             const double uyj = s.uy[j + 1];
             const double uL = uxl * uyj, uR = uxr * uyj;
             const double vU = s.vy[j + 1] * vxi;
@@ -392,12 +393,11 @@ __device__ void advance_scalar_patch(const Ctx &c, const View &w, ScalarSmem<MX>
             const double TFr = posp(uR) * TYc + negp(uR) * TYr;
             const double TGd = posp(vD) * TXd + negp(vD) * TXc;
             const double TGu = posp(vU) * TXc + negp(vU) * TXu;
-            const double cyu = s.cy[by + MX + 2];
-            const double dC = (s.cx[ax + 1] - s.cx[ax]) + (cyu - cyd);
+            const double dC = s.dcx[j * MX + i] + s.dcy[j * MX + i];
             const double Q = s.q[(j + MB) * NP + i + MB];
             out[base + (j + MB) * N + i + MB] =
                 Q - lam * (TXc + TYc) + 0.5 * lam * dC + 0.5 * lam * lam * ((TFr - TFl) + (TGu - TGd));
-            TXd = TXc; TXc = TXu; vD = vU; cyd = cyu;
+            TXd = TXc; TXc = TXu; vD = vU;
         }
     }
     cfl = fmax(cfl, lam * amax);
@@ -983,6 +983,47 @@ __global__ void __launch_bounds__(NT) persistent_kernel(Ctx c, const SchedEntry 
 }
 
 // ------------------------------------------------------------------------
+// one level-step as its own kernel, for graph capture: the time, step and
+// buffer parities come from device memory, so a graph captured once is
+// replayed for every chunk of coarse steps (kernel boundaries provide the
+// ordering and coherence between level-steps)
+// ------------------------------------------------------------------------
+template <int MX, int NT, int EQ>
+__global__ void __launch_bounds__(NT) level_step_kernel(Ctx c, const SchedEntry *sched, int k, int cidx,
+                                                        uint32_t flip, const LevelRange *lr, DevState *st) {
+    __shared__ typename SmemOf<MX, EQ>::type s;
+    double t0 = st->t;
+    const double dtc = st->dt_coarse;
+    for (int q = 0; q < cidx; q++) t0 = t0 + dtc;  // the host's accumulation of coarse steps
+    const SchedEntry e = sched[k];
+    View w{st->curmask ^ flip, -1, 1.0};
+    int first = 0, count = 0;
+    if (e.level < 0) {
+        for (int l = 0; l < FC_MAXLEV; l++) count += lr->count[l];
+    } else {
+        first = lr->start[e.level]; count = lr->count[e.level]; w.clevel = e.level - 1; w.alpha = e.alpha;
+    }
+    const double t = t0 + e.off * dtc, dt = e.scale * dtc;
+    const int G = gridDim.x, x = blockIdx.x & 7, r = blockIdx.x >> 3;
+    const int nbx = (G - x + 7) >> 3;
+    const int c0 = (int)(((long long)count * x) >> 3), c1 = (int)(((long long)count * (x + 1)) >> 3);
+    double cfl = 0.0;
+    for (int pi = c0 + r; pi < c1; pi += nbx) {
+        if constexpr (EQ == 0) advance_scalar_patch<MX, NT, true>(c, w, s, first + pi, t, dt, cfl);
+        else advance_swe_patch<MX, NT, true>(c, w, s, first + pi, dt, cfl);
+        __syncthreads();
+    }
+    reduce_cfl<NT>(cfl, s.red, &st->cfl_bits);
+}
+
+__global__ void finish_chunk_kernel(DevState *st, int ncoarse, uint32_t flip) {
+    double t = st->t;
+    for (int q = 0; q < ncoarse; q++) t = t + st->dt_coarse;
+    st->t = t;
+    st->curmask ^= flip;
+}
+
+// ------------------------------------------------------------------------
 // support kernels
 // ------------------------------------------------------------------------
 __global__ void init_tables_kernel(int n, int periodic_x, int periodic_y, double *vt) {
@@ -1231,6 +1272,34 @@ int persistent_max_grid(LaunchCfg lc, int eq) {
         if (by_lds < per_cu) per_cu = by_lds;
     }
     return per_cu * cus;
+}
+
+template <int MX, int NT>
+static const void *level_step_fn(int eq) {
+    if (eq == 0) return reinterpret_cast<const void *>(&level_step_kernel<MX, NT, 0>);
+    if constexpr (MX <= 16) return reinterpret_cast<const void *>(&level_step_kernel<MX, NT, 1>);
+    return nullptr;
+}
+
+static const void *level_step_select(LaunchCfg lc, int eq) {
+#define PS(MXV, NTV) if (lc.mx == MXV && lc.nt == NTV) return level_step_fn<MXV, NTV>(eq);
+    PS(8, 64) PS(8, 128) PS(16, 64) PS(16, 128) PS(16, 256) PS(32, 128) PS(32, 256) PS(32, 512)
+#undef PS
+    return nullptr;
+}
+
+hipError_t launch_level_step(const Ctx &c, LaunchCfg lc, const SchedEntry *sched, int k, int cidx, uint32_t flip,
+                             const LevelRange *lr, DevState *st, int grid, hipStream_t s) {
+    const void *fn = level_step_select(lc, c.eq);
+    if (!fn || grid <= 0) return hipErrorInvalidValue;
+    Ctx cc = c;
+    void *args[] = {&cc, (void *)&sched, &k, &cidx, &flip, (void *)&lr, &st};
+    return hipLaunchKernel(fn, dim3(grid), dim3(lc.nt), args, 0, s);
+}
+
+hipError_t launch_finish_chunk(DevState *st, int ncoarse, uint32_t flip, hipStream_t s) {
+    hipLaunchKernelGGL(finish_chunk_kernel, dim3(1), dim3(1), 0, s, st, ncoarse, flip);
+    return hipGetLastError();
 }
 
 hipError_t launch_persistent(const Ctx &c, LaunchCfg lc, const SchedEntry *sched, int nsched,

@@ -147,9 +147,10 @@ struct fc_patchstore {
     std::vector<SchedEntry> sched;
     int pgrid = 0;
     int pgrid_user = 0;  // grid override of the persistent kernel (0: occupancy)
-    // captured graphs: [0] one coarse step per launch, [1] `chunk` coarse steps
-    hipGraphExec_t gexec[2] = {nullptr, nullptr};
-    hipGraph_t graph[2] = {nullptr, nullptr};
+    // captured graphs: [0]/[1] persistent kernel for 1 / `chunk` coarse steps,
+    // [2]/[3] level-step kernels for 1 / `chunk` coarse steps
+    hipGraphExec_t gexec[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipGraph_t graph[4] = {nullptr, nullptr, nullptr, nullptr};
     int chunk = 0;
     hipStream_t cap_stream = nullptr;  // private stream the graph is captured on
     int gnt = 0;
@@ -349,7 +350,7 @@ fc_status advance_one(fc_patchstore *ps, int level, double t, double dt, int fus
 }
 
 void drop_graph(fc_patchstore *ps) {
-    for (int k = 0; k < 2; k++) {
+    for (int k = 0; k < 4; k++) {
         if (ps->gexec[k]) (void)hipGraphExecDestroy(ps->gexec[k]);
         if (ps->graph[k]) (void)hipGraphDestroy(ps->graph[k]);
         ps->gexec[k] = nullptr;
@@ -381,6 +382,43 @@ fc_status capture(fc_patchstore *ps, int which, int ncoarse, int grid) {
     return FC_OK;
 }
 
+
+// Capture `ncoarse` coarse steps as one kernel per level-step plus a final
+// node that advances the device time and parities.  Every schedule entry gets
+// a node (grid-stride over the level's current patch count), so the graph
+// stays valid for any leaf set with the same level range.
+fc_status capture_levels(fc_patchstore *ps, int which, int ncoarse) {
+    if (!ps->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ps->cap_stream, hipStreamNonBlocking));
+    Ctx c = make_ctx(ps);
+    const SchedEntry *sched = (const SchedEntry *)(ps->ws + ps->off_sched);
+    const LevelRange *lrd = (const LevelRange *)(ps->ws + ps->off_lr);
+    uint32_t allmask = 0;
+    int nall = 0;
+    for (int l = 0; l < FC_MAXLEV; l++)
+        if (ps->lr.count[l] > 0) { allmask |= 1u << l; nall += ps->lr.count[l]; }
+    HIPCHK(hipStreamBeginCapture(ps->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    uint32_t flip = 0;
+    for (int cs = 0; cs < ncoarse && e == hipSuccess; cs++)
+        for (int k = 0; k < (int)ps->sched.size() && e == hipSuccess; k++) {
+            const SchedEntry &en = ps->sched[k];
+            const int cnt = en.level < 0 ? nall : ps->lr.count[en.level];
+            e = launch_level_step(c, LaunchCfg{ps->mx, ps->nt}, sched, k, cs, flip, lrd, dstate(ps),
+                                  std::max(1, std::min(cnt, 1 << 20)), ps->cap_stream);
+            flip ^= en.level < 0 ? allmask : (1u << en.level);
+        }
+    if (e == hipSuccess) e = launch_finish_chunk(dstate(ps), ncoarse, flip, ps->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(ps->cap_stream, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        return fail(FC_ERR_HIP, "graph capture failed");
+    }
+    ps->graph[which] = g;
+    HIPCHK(hipGraphInstantiate(&ps->gexec[which], g, nullptr, nullptr, 0));
+    return FC_OK;
+}
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -599,7 +637,8 @@ fc_status fc_advance_coarse_steps(fc_patchstore *ps, double dt_coarse, int32_t n
         }
         return FC_OK;
     }
-    if (mode != FC_MODE_FUSED && mode != FC_MODE_FUSED_GRAPH) return fail(FC_ERR_ARG, "unknown mode");
+    if (mode != FC_MODE_FUSED && mode != FC_MODE_FUSED_GRAPH && mode != FC_MODE_PERSISTENT_GRAPH)
+        return fail(FC_ERR_ARG, "unknown mode");
     if (ps->pgrid <= 0) return fail(FC_ERR_HIP, "persistent kernel has no resident blocks");
     const int grid = ps->pgrid_user > 0 ? std::min(ps->pgrid_user, ps->pgrid) : ps->pgrid;
     DevState *st = dstate(ps);
@@ -607,8 +646,7 @@ fc_status fc_advance_coarse_steps(fc_patchstore *ps, double dt_coarse, int32_t n
     Ctx c = make_ctx(ps);
     const SchedEntry *sched = (const SchedEntry *)(ps->ws + ps->off_sched);
     const LevelRange *lrd = (const LevelRange *)(ps->ws + ps->off_lr);
-    // coarse steps per launch: all levels' level-steps of up to `kChunk`
-    // coarse steps run inside one persistent launch
+    // up to `kChunk` coarse steps per launch (persistent) or per graph replay
     const int kChunk = 50;
     if (mode == FC_MODE_FUSED) {
         for (int k = 0; k < nsteps; k += kChunk) {
@@ -621,14 +659,19 @@ fc_status fc_advance_coarse_steps(fc_patchstore *ps, double dt_coarse, int32_t n
             ps->gnt = ps->nt;
             ps->chunk = kChunk;
         }
+        const int base = mode == FC_MODE_PERSISTENT_GRAPH ? 0 : 2;
+        auto cap = [&](int which, int ncoarse) -> fc_status {
+            return mode == FC_MODE_PERSISTENT_GRAPH ? capture(ps, which, ncoarse, grid)
+                                                    : capture_levels(ps, which, ncoarse);
+        };
         int k = 0;
         if (nsteps >= kChunk) {
-            if (!ps->gexec[1]) { r = capture(ps, 1, kChunk, grid); if (r != FC_OK) return r; }
-            for (; k + kChunk <= nsteps; k += kChunk) HIPCHK(hipGraphLaunch(ps->gexec[1], s));
+            if (!ps->gexec[base + 1]) { r = cap(base + 1, kChunk); if (r != FC_OK) return r; }
+            for (; k + kChunk <= nsteps; k += kChunk) HIPCHK(hipGraphLaunch(ps->gexec[base + 1], s));
         }
         if (k < nsteps) {
-            if (!ps->gexec[0]) { r = capture(ps, 0, 1, grid); if (r != FC_OK) return r; }
-            for (; k < nsteps; k++) HIPCHK(hipGraphLaunch(ps->gexec[0], s));
+            if (!ps->gexec[base]) { r = cap(base, 1); if (r != FC_OK) return r; }
+            for (; k < nsteps; k++) HIPCHK(hipGraphLaunch(ps->gexec[base], s));
         }
     }
     // host mirror of the device bookkeeping
@@ -759,6 +802,7 @@ fc_status fc_regrid(fc_patchstore *ps, int64_t nleaves, const fc_leaf *new_leave
     r = upload_metadata(ps, s);
     if (r != FC_OK) return r;
     ps->curmask = ~0u;  // new data lives in buffer 1 for every level
+    drop_graph(ps);     // level populations changed: recapture on next use
     HIPCHK(hipStreamSynchronize(s));
     return FC_OK;
 }

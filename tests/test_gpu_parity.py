@@ -127,7 +127,7 @@ def test_single_step_uniform(B, O, limiter):
     assert abs(cfl.item() - c_o) <= 1e-14
 
 
-@pytest.mark.parametrize("mode", ["per_level", "fused", "graph"])
+@pytest.mark.parametrize("mode", ["per_level", "fused", "graph", "fused_levels", "persistent_graph"])
 def test_swirl_uniform_parity(B, O, mode):
     w = S.workload("swirl_uniform", level=3, mx=16)
     ps, o = pair(B, O, w["leaves"], 16, w["q0"], velocity="swirl", vel_params=(1.0, 0, 0))
@@ -139,7 +139,7 @@ def test_swirl_uniform_parity(B, O, mode):
     assert rel(ps.interior(), o.interior()) <= TOL
 
 
-@pytest.mark.parametrize("mode", ["per_level", "fused", "graph"])
+@pytest.mark.parametrize("mode", ["per_level", "fused", "graph", "fused_levels", "persistent_graph"])
 def test_hump_multirate_parity(B, O, mode):
     """Levels 2-3 with subcycling, 8x8 patches, 100 coarse steps."""
     w = S.workload("hump_l23")
@@ -159,9 +159,9 @@ def test_random_amr_multirate_swirl(B, O, seed):
     q = S.sample_on_leaves(S.gaussians(S.gaussian_params(seed)), L, 8)
     ps, o = pair(B, O, L, 8, q, velocity="swirl", vel_params=(1.0, 0, 0))
     dt = 0.9 / 32
-    for mode in ("fused", "per_level"):
+    for mode in ("fused", "per_level", "graph", "fused_levels"):
         ps.coarse_steps(dt, 3, mode)
-    for s in range(6):
+    for s in range(12):
         o.coarse_step(s * dt, dt)
     ps.check()
     assert rel(ps.interior(), o.interior()) <= TOL
@@ -186,6 +186,10 @@ def test_fused_equals_per_level_bitwise(B, O):
     a.coarse_steps(w["dt_coarse"], 20, "per_level")
     b.coarse_steps(w["dt_coarse"], 20, "graph")
     assert np.array_equal(a.interior().cpu().numpy(), b.interior().cpu().numpy())
+    c = B.from_workload(w)
+    c.coarse_steps(w["dt_coarse"], 7, "persistent_graph")
+    c.coarse_steps(w["dt_coarse"], 13, "fused")
+    assert np.array_equal(a.interior().cpu().numpy(), c.interior().cpu().numpy())
 
 
 @pytest.mark.parametrize("mx", [8, 16, 32])
@@ -200,6 +204,7 @@ def test_variants_bitwise(B, mx):
         ps.set_variant(nt)
         ps.coarse_steps(w["dt_coarse"], 5, "fused")
         ps.coarse_steps(w["dt_coarse"], 5, "per_level")
+        ps.coarse_steps(w["dt_coarse"], 5, "graph")
         res.append(ps.interior().cpu().numpy())
     for r in res[1:]:
         assert np.array_equal(r, res[0])
