@@ -49,7 +49,8 @@ struct DevState {
     unsigned long long cfl_bits;  // max Courant number (bits of a non-negative double)
     uint32_t curmask;          // bit l: current buffer of level l
     uint32_t bar_count, bar_gen;
-    int32_t err;               // bit 0: barrier spin limit hit; bit 1: stencil out of range
+    int32_t err;               // bit 0: barrier spin limit hit; bit 1: stencil out of range;
+                               // bit 2: a level-step kernel's grid did not cover its level
     int32_t pad;
 };
 

@@ -945,8 +945,11 @@ __global__ void __launch_bounds__(NT) persistent_kernel(Ctx c, const SchedEntry 
     const double dtc = st->dt_coarse;
     View w{st->curmask, -1, 1.0};
     const unsigned G = gridDim.x;
-    const int x = blockIdx.x & 7, r = blockIdx.x >> 3;
-    const int nbx = ((int)G - x + 7) >> 3;  // blocks on this XCD
+    // XCD-aware split: workgroup b runs on XCD b mod 8 and takes a stride of
+    // that XCD's contiguous chunk (NXC chunks when fewer than 8 workgroups)
+    const int NXC = G < 8 ? (int)G : 8;
+    const int x = blockIdx.x % NXC, r = blockIdx.x / NXC;
+    const int nbx = ((int)G - x + NXC - 1) / NXC;  // workgroups on this chunk
     uint32_t allmask = 0;
     int nall = 0;
     for (int l = 0; l < FC_MAXLEV; l++)
@@ -963,7 +966,7 @@ __global__ void __launch_bounds__(NT) persistent_kernel(Ctx c, const SchedEntry 
                 continue;
             }
             const double t = t0 + e.off * dtc, dt = e.scale * dtc;
-            const int c0 = (int)(((long long)count * x) >> 3), c1 = (int)(((long long)count * (x + 1)) >> 3);
+            const int c0 = (int)((long long)count * x / NXC), c1 = (int)((long long)count * (x + 1) / NXC);
             for (int pi = c0 + r; pi < c1; pi += nbx) {
                 if constexpr (EQ == 0) advance_scalar_patch<MX, NT, true>(c, w, s, first + pi, t, dt, cfl);
                 else advance_swe_patch<MX, NT, true>(c, w, s, first + pi, dt, cfl);
@@ -992,26 +995,27 @@ template <int MX, int NT, int EQ>
 __global__ void __launch_bounds__(NT) level_step_kernel(Ctx c, const SchedEntry *sched, int k, int cidx,
                                                         uint32_t flip, const LevelRange *lr, DevState *st) {
     __shared__ typename SmemOf<MX, EQ>::type s;
-    double t0 = st->t;
-    const double dtc = st->dt_coarse;
-    for (int q = 0; q < cidx; q++) t0 = t0 + dtc;  // the host's accumulation of coarse steps
     const SchedEntry e = sched[k];
-    View w{st->curmask ^ flip, -1, 1.0};
     int first = 0, count = 0;
     if (e.level < 0) {
         for (int l = 0; l < FC_MAXLEV; l++) count += lr->count[l];
     } else {
-        first = lr->start[e.level]; count = lr->count[e.level]; w.clevel = e.level - 1; w.alpha = e.alpha;
+        first = lr->start[e.level]; count = lr->count[e.level];
     }
+    double t0 = st->t;
+    const double dtc = st->dt_coarse;
+    for (int q = 0; q < cidx; q++) t0 = t0 + dtc;  // the host's accumulation of coarse steps
+    const View w{st->curmask ^ flip, e.level < 0 ? -1 : e.level - 1, e.level < 0 ? 1.0 : e.alpha};
     const double t = t0 + e.off * dtc, dt = e.scale * dtc;
-    const int G = gridDim.x, x = blockIdx.x & 7, r = blockIdx.x >> 3;
-    const int nbx = (G - x + 7) >> 3;
-    const int c0 = (int)(((long long)count * x) >> 3), c1 = (int)(((long long)count * (x + 1)) >> 3);
     double cfl = 0.0;
-    for (int pi = c0 + r; pi < c1; pi += nbx) {
-        if constexpr (EQ == 0) advance_scalar_patch<MX, NT, true>(c, w, s, first + pi, t, dt, cfl);
-        else advance_swe_patch<MX, NT, true>(c, w, s, first + pi, dt, cfl);
-        __syncthreads();
+    // one patch per workgroup: graphs are captured with the level's patch
+    // count as grid and recaptured whenever a regrid changes the counts; a
+    // grid that does not cover the level is reported, not stepped over
+    if (count > (int)gridDim.x && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&st->err, 4);
+    if ((int)blockIdx.x < count) {
+        const int p = first + xcd_remap(blockIdx.x, count);
+        if constexpr (EQ == 0) advance_scalar_patch<MX, NT, true>(c, w, s, p, t, dt, cfl);
+        else advance_swe_patch<MX, NT, true>(c, w, s, p, dt, cfl);
     }
     reduce_cfl<NT>(cfl, s.red, &st->cfl_bits);
 }

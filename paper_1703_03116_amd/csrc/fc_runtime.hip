@@ -316,6 +316,7 @@ fc_status check_device_error(fc_patchstore *ps, hipStream_t s) {
     HIPCHK(hipStreamSynchronize(s));
     if (err & 1) return fail(FC_ERR_HIP, "device-wide barrier timed out (grid not co-resident)");
     if (err & 2) return fail(FC_ERR_HIP, "interpolation stencil needed a third level (Prop. 2.1 violated)");
+    if (err & 4) return fail(FC_ERR_STATE, "a captured graph did not cover a level's patches");
     return FC_OK;
 }
 
