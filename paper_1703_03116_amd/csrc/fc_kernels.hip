@@ -404,6 +404,8 @@ __device__ void advance_scalar_patch(const Ctx &c, const View &w, ScalarSmem<MX>
 }
 
 // block-wide max of a non-negative double, then one atomicMax on its bits
+// (kernels that run one workgroup per patch record per slot instead: a
+// thousand atomics on one address serialise in L2)
 template <int NT>
 __device__ void reduce_cfl(double v, double *red, unsigned long long *cfl_bits) {
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
@@ -418,14 +420,29 @@ __device__ void reduce_cfl(double v, double *red, unsigned long long *cfl_bits) 
     }
 }
 
+// block-wide max, then slot = max(slot, value) by thread 0 (the workgroup
+// owns the slot of its patch for the whole launch)
+template <int NT>
+__device__ void reduce_cfl_slot(double v, double *red, double *slot) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    if (threadIdx.x == 0 && slot) {
+        double m = red[0];
+        for (int k = 1; k < NT / 64; k++) m = fmax(m, red[k]);
+        *slot = fmax(*slot, m);
+    }
+}
+
 template <int MX, int NT, bool FUSED>
-__global__ void __launch_bounds__(NT) advance_scalar_kernel(Ctx c, int first, int count, double t, double dt,
-                                                            unsigned long long *cfl_bits) {
+__global__ void __launch_bounds__(NT) advance_scalar_kernel(Ctx c, int first, int count, double t, double dt) {
     __shared__ ScalarSmem<MX> s;
     const int p = first + xcd_remap(blockIdx.x, count);
     double cfl = 0.0;
     advance_scalar_patch<MX, NT, FUSED>(c, view_of(c), s, p, t, dt, cfl);
-    reduce_cfl<NT>(cfl, s.red, cfl_bits);
+    reduce_cfl_slot<NT>(cfl, s.red, c.cflp ? c.cflp + p : nullptr);
 }
 
 // ------------------------------------------------------------------------
@@ -673,13 +690,12 @@ __device__ void advance_swe_patch(const Ctx &c, const View &w, SweSmem<MX> &s, i
 }
 
 template <int MX, int NT, bool FUSED>
-__global__ void __launch_bounds__(NT) advance_swe_kernel(Ctx c, int first, int count, double dt,
-                                                         unsigned long long *cfl_bits) {
+__global__ void __launch_bounds__(NT) advance_swe_kernel(Ctx c, int first, int count, double dt) {
     __shared__ SweSmem<MX> s;
     const int p = first + xcd_remap(blockIdx.x, count);
     double cfl = 0.0;
     advance_swe_patch<MX, NT, FUSED>(c, view_of(c), s, p, dt, cfl);
-    reduce_cfl<NT>(cfl, s.red, cfl_bits);
+    reduce_cfl_slot<NT>(cfl, s.red, c.cflp ? c.cflp + p : nullptr);
 }
 
 // ------------------------------------------------------------------------
@@ -991,33 +1007,30 @@ __global__ void __launch_bounds__(NT) persistent_kernel(Ctx c, const SchedEntry 
 // replayed for every chunk of coarse steps (kernel boundaries provide the
 // ordering and coherence between level-steps)
 // ------------------------------------------------------------------------
+// The node's constants (level range, time offset and scale, time fraction)
+// are baked in at capture; the graph is recaptured whenever a regrid changes
+// the level populations.  Only the time, step and parities come from device
+// memory (independent loads).
+struct StepArgs {
+    int32_t level, first, count, cidx;
+    uint32_t flip, pad;
+    double off, scale, alpha;
+};
+
 template <int MX, int NT, int EQ>
-__global__ void __launch_bounds__(NT) level_step_kernel(Ctx c, const SchedEntry *sched, int k, int cidx,
-                                                        uint32_t flip, const LevelRange *lr, DevState *st) {
+__global__ void __launch_bounds__(NT) level_step_kernel(Ctx c, StepArgs a, DevState *st) {
     __shared__ typename SmemOf<MX, EQ>::type s;
-    const SchedEntry e = sched[k];
-    int first = 0, count = 0;
-    if (e.level < 0) {
-        for (int l = 0; l < FC_MAXLEV; l++) count += lr->count[l];
-    } else {
-        first = lr->start[e.level]; count = lr->count[e.level];
-    }
     double t0 = st->t;
     const double dtc = st->dt_coarse;
-    for (int q = 0; q < cidx; q++) t0 = t0 + dtc;  // the host's accumulation of coarse steps
-    const View w{st->curmask ^ flip, e.level < 0 ? -1 : e.level - 1, e.level < 0 ? 1.0 : e.alpha};
-    const double t = t0 + e.off * dtc, dt = e.scale * dtc;
+    const uint32_t cm = st->curmask;
+    for (int q = 0; q < a.cidx; q++) t0 = t0 + dtc;  // the host's accumulation of coarse steps
+    const View w{cm ^ a.flip, a.level < 0 ? -1 : a.level - 1, a.level < 0 ? 1.0 : a.alpha};
+    const double t = t0 + a.off * dtc, dt = a.scale * dtc;
     double cfl = 0.0;
-    // one patch per workgroup: graphs are captured with the level's patch
-    // count as grid and recaptured whenever a regrid changes the counts; a
-    // grid that does not cover the level is reported, not stepped over
-    if (count > (int)gridDim.x && blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&st->err, 4);
-    if ((int)blockIdx.x < count) {
-        const int p = first + xcd_remap(blockIdx.x, count);
-        if constexpr (EQ == 0) advance_scalar_patch<MX, NT, true>(c, w, s, p, t, dt, cfl);
-        else advance_swe_patch<MX, NT, true>(c, w, s, p, dt, cfl);
-    }
-    reduce_cfl<NT>(cfl, s.red, &st->cfl_bits);
+    const int p = a.first + xcd_remap(blockIdx.x, a.count);
+    if constexpr (EQ == 0) advance_scalar_patch<MX, NT, true>(c, w, s, p, t, dt, cfl);
+    else advance_swe_patch<MX, NT, true>(c, w, s, p, dt, cfl);
+    reduce_cfl_slot<NT>(cfl, s.red, c.cflp + p);
 }
 
 __global__ void finish_chunk_kernel(DevState *st, int ncoarse, uint32_t flip) {
@@ -1053,17 +1066,36 @@ __global__ void init_tables_kernel(int n, int periodic_x, int periodic_y, double
     }
 }
 
-__global__ void set_state_kernel(DevState *st, double t, double dt, uint32_t curmask, int reset_cfl) {
-    st->t = t;
-    st->dt_coarse = dt;
-    st->curmask = curmask;
-    st->bar_count = 0;
-    if (reset_cfl) st->cfl_bits = 0ull;
+__global__ void set_state_kernel(DevState *st, double t, double dt, uint32_t curmask, int reset_cfl, double *cflp,
+                                 int n) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k == 0) {
+        st->t = t;
+        st->dt_coarse = dt;
+        st->curmask = curmask;
+        st->bar_count = 0;
+        if (reset_cfl) st->cfl_bits = 0ull;
+    }
+    if (reset_cfl && cflp && k < n) cflp[k] = 0.0;
 }
 
-__global__ void export_cfl_kernel(DevState *st, double *cfl) {
-    const double v = __longlong_as_double((long long)st->cfl_bits);
-    if (cfl && v > *cfl) *cfl = v;
+__global__ void zero_cfl_kernel(double *cflp, int n) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) cflp[k] = 0.0;
+}
+
+__global__ void __launch_bounds__(256) export_cfl_kernel(const DevState *st, const double *cflp, int n, double *cfl) {
+    __shared__ double red[4];
+    double v = 0.0;
+    for (int k = threadIdx.x; k < n; k += 256) v = fmax(v, cflp[k]);
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+        if (st) m = fmax(m, __longlong_as_double((long long)st->cfl_bits));
+        if (m > *cfl) *cfl = m;
+    }
 }
 
 // interior data, input-leaf order [n][F][mx][mx] <-> store slots
@@ -1181,13 +1213,21 @@ hipError_t launch_init_tables(int level, int mx, int periodic_x, int periodic_y,
     return hipGetLastError();
 }
 
-hipError_t launch_set_state(DevState *st, double t, double dt, uint32_t curmask, int reset_cfl, hipStream_t s) {
-    hipLaunchKernelGGL(set_state_kernel, dim3(1), dim3(1), 0, s, st, t, dt, curmask, reset_cfl);
+hipError_t launch_set_state(DevState *st, double t, double dt, uint32_t curmask, int reset_cfl, double *cflp, int n,
+                            hipStream_t s) {
+    const int nb = (n > 0 ? n : 1) + 255;
+    hipLaunchKernelGGL(set_state_kernel, dim3(nb / 256), dim3(256), 0, s, st, t, dt, curmask, reset_cfl, cflp, n);
     return hipGetLastError();
 }
 
-hipError_t launch_export_cfl(DevState *state, double *cfl_dev, hipStream_t s) {
-    hipLaunchKernelGGL(export_cfl_kernel, dim3(1), dim3(1), 0, s, state, cfl_dev);
+hipError_t launch_zero_cfl(double *cflp, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_cfl_kernel, dim3((n + 255) / 256), dim3(256), 0, s, cflp, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_export_cfl(DevState *state, const double *cflp, int n, double *cfl_dev, hipStream_t s) {
+    hipLaunchKernelGGL(export_cfl_kernel, dim3(1), dim3(256), 0, s, state, cflp, n, cfl_dev);
     return hipGetLastError();
 }
 
@@ -1209,31 +1249,29 @@ hipError_t launch_fill(const Ctx &c, int mx, int first, int count, hipStream_t s
 }
 
 template <int MX, int NT>
-static hipError_t adv_scalar(const Ctx &c, int first, int count, double t, double dt, int fused,
-                             unsigned long long *cfl, hipStream_t s) {
-    if (fused) hipLaunchKernelGGL((advance_scalar_kernel<MX, NT, true>), dim3(count), dim3(NT), 0, s, c, first, count, t, dt, cfl);
-    else hipLaunchKernelGGL((advance_scalar_kernel<MX, NT, false>), dim3(count), dim3(NT), 0, s, c, first, count, t, dt, cfl);
+static hipError_t adv_scalar(const Ctx &c, int first, int count, double t, double dt, int fused, hipStream_t s) {
+    if (fused) hipLaunchKernelGGL((advance_scalar_kernel<MX, NT, true>), dim3(count), dim3(NT), 0, s, c, first, count, t, dt);
+    else hipLaunchKernelGGL((advance_scalar_kernel<MX, NT, false>), dim3(count), dim3(NT), 0, s, c, first, count, t, dt);
     return hipGetLastError();
 }
 
 template <int MX, int NT>
-static hipError_t adv_swe(const Ctx &c, int first, int count, double dt, int fused, unsigned long long *cfl,
-                          hipStream_t s) {
-    if (fused) hipLaunchKernelGGL((advance_swe_kernel<MX, NT, true>), dim3(count), dim3(NT), 0, s, c, first, count, dt, cfl);
-    else hipLaunchKernelGGL((advance_swe_kernel<MX, NT, false>), dim3(count), dim3(NT), 0, s, c, first, count, dt, cfl);
+static hipError_t adv_swe(const Ctx &c, int first, int count, double dt, int fused, hipStream_t s) {
+    if (fused) hipLaunchKernelGGL((advance_swe_kernel<MX, NT, true>), dim3(count), dim3(NT), 0, s, c, first, count, dt);
+    else hipLaunchKernelGGL((advance_swe_kernel<MX, NT, false>), dim3(count), dim3(NT), 0, s, c, first, count, dt);
     return hipGetLastError();
 }
 
 hipError_t launch_advance(const Ctx &c, LaunchCfg lc, int level, int first, int count, double t, double dt,
-                          int fused, unsigned long long *cfl_bits, hipStream_t s) {
+                          int fused, hipStream_t s) {
     (void)level;
     if (count <= 0) return hipSuccess;
     if (c.eq == 0) {
-#define ADV(MXV, NTV) if (lc.mx == MXV && lc.nt == NTV) return adv_scalar<MXV, NTV>(c, first, count, t, dt, fused, cfl_bits, s);
+#define ADV(MXV, NTV) if (lc.mx == MXV && lc.nt == NTV) return adv_scalar<MXV, NTV>(c, first, count, t, dt, fused, s);
         ADV(8, 64) ADV(8, 128) ADV(16, 64) ADV(16, 128) ADV(16, 256) ADV(32, 128) ADV(32, 256) ADV(32, 512)
 #undef ADV
     } else {
-#define ADV(MXV, NTV) if (lc.mx == MXV && lc.nt == NTV) return adv_swe<MXV, NTV>(c, first, count, dt, fused, cfl_bits, s);
+#define ADV(MXV, NTV) if (lc.mx == MXV && lc.nt == NTV) return adv_swe<MXV, NTV>(c, first, count, dt, fused, s);
         ADV(8, 64) ADV(8, 128) ADV(16, 64) ADV(16, 128) ADV(16, 256)
 #undef ADV
     }
@@ -1292,13 +1330,14 @@ static const void *level_step_select(LaunchCfg lc, int eq) {
     return nullptr;
 }
 
-hipError_t launch_level_step(const Ctx &c, LaunchCfg lc, const SchedEntry *sched, int k, int cidx, uint32_t flip,
-                             const LevelRange *lr, DevState *st, int grid, hipStream_t s) {
+hipError_t launch_level_step(const Ctx &c, LaunchCfg lc, const SchedEntry &e, int first, int count, int cidx,
+                             uint32_t flip, DevState *st, hipStream_t s) {
     const void *fn = level_step_select(lc, c.eq);
-    if (!fn || grid <= 0) return hipErrorInvalidValue;
+    if (!fn) return hipErrorInvalidValue;
     Ctx cc = c;
-    void *args[] = {&cc, (void *)&sched, &k, &cidx, &flip, (void *)&lr, &st};
-    return hipLaunchKernel(fn, dim3(grid), dim3(lc.nt), args, 0, s);
+    StepArgs a{e.level, first, count, cidx, flip, 0u, e.off, e.scale, e.alpha};
+    void *args[] = {&cc, &a, &st};
+    return hipLaunchKernel(fn, dim3(count > 0 ? count : 1), dim3(lc.nt), args, 0, s);
 }
 
 hipError_t launch_finish_chunk(DevState *st, int ncoarse, uint32_t flip, hipStream_t s) {

@@ -143,7 +143,7 @@ struct fc_patchstore {
     char *ws = nullptr;
     size_t ws_bytes = 0;
     size_t off_info = 0, off_nbr = 0, off_sl = 0, off_ls = 0, off_lr = 0, off_sched = 0, off_state = 0,
-           off_plan = 0, off_tag = 0, off_vt[FC_MAXLEV] = {0}, off_abar = 0;
+           off_plan = 0, off_tag = 0, off_cfl = 0, off_vt[FC_MAXLEV] = {0}, off_abar = 0;
     std::vector<SchedEntry> sched;
     int pgrid = 0;
     int pgrid_user = 0;  // grid override of the persistent kernel (0: occupancy)
@@ -253,6 +253,7 @@ void layout_workspace(fc_patchstore *ps) {
     ps->off_ls = o; o = align256(o + sizeof(int32_t) * cap);
     ps->off_plan = o; o = align256(o + sizeof(TransferRec) * cap);
     ps->off_tag = o; o = align256(o + sizeof(double) * cap);
+    ps->off_cfl = o; o = align256(o + sizeof(double) * cap);
     for (int l = 0; l < FC_MAXLEV; l++) {
         ps->off_vt[l] = o;
         if (l >= ps->cfg.min_level && l <= ps->cfg.max_level && ps->cfg.velocity == FC_VEL_SWIRL)
@@ -260,6 +261,8 @@ void layout_workspace(fc_patchstore *ps) {
     }
     ps->ws_bytes = o;
 }
+
+double *cflp(const fc_patchstore *ps) { return (double *)(ps->ws + ps->off_cfl); }
 
 Ctx make_ctx(const fc_patchstore *ps) {
     Ctx c;
@@ -278,6 +281,7 @@ Ctx make_ctx(const fc_patchstore *ps) {
     c.vel_u = ps->cfg.vel_params[0]; c.vel_v = ps->cfg.vel_params[1]; c.vel_T = ps->cfg.vel_params[0];
     c.g = ps->cfg.gravity;
     c.err = (int32_t *)(ps->ws + ps->off_state + offsetof(DevState, err));
+    c.cflp = cflp(ps);
     return c;
 }
 
@@ -337,14 +341,16 @@ fc_status fill_levels(fc_patchstore *ps, int lo, int hi, double alpha, hipStream
     return FC_OK;
 }
 
+// rec: record the patches' Courant numbers in their slots
 fc_status advance_one(fc_patchstore *ps, int level, double t, double dt, int fused_load, int clevel, double alpha,
-                      unsigned long long *cfl_bits, hipStream_t s) {
+                      bool rec, hipStream_t s) {
     if (ps->lr.count[level] > 0) {
         Ctx c = make_ctx(ps);
         c.clevel = clevel;
         c.alpha = alpha;
+        if (!rec) c.cflp = nullptr;
         HIPCHK(launch_advance(c, LaunchCfg{ps->mx, ps->nt}, level, ps->lr.start[level], ps->lr.count[level], t, dt,
-                              fused_load, cfl_bits, s));
+                              fused_load, s));
     }
     ps->curmask ^= 1u << level;
     return FC_OK;
@@ -391,8 +397,6 @@ fc_status capture(fc_patchstore *ps, int which, int ncoarse, int grid) {
 fc_status capture_levels(fc_patchstore *ps, int which, int ncoarse) {
     if (!ps->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ps->cap_stream, hipStreamNonBlocking));
     Ctx c = make_ctx(ps);
-    const SchedEntry *sched = (const SchedEntry *)(ps->ws + ps->off_sched);
-    const LevelRange *lrd = (const LevelRange *)(ps->ws + ps->off_lr);
     uint32_t allmask = 0;
     int nall = 0;
     for (int l = 0; l < FC_MAXLEV; l++)
@@ -403,9 +407,10 @@ fc_status capture_levels(fc_patchstore *ps, int which, int ncoarse) {
     for (int cs = 0; cs < ncoarse && e == hipSuccess; cs++)
         for (int k = 0; k < (int)ps->sched.size() && e == hipSuccess; k++) {
             const SchedEntry &en = ps->sched[k];
+            const int first = en.level < 0 ? 0 : ps->lr.start[en.level];
             const int cnt = en.level < 0 ? nall : ps->lr.count[en.level];
-            e = launch_level_step(c, LaunchCfg{ps->mx, ps->nt}, sched, k, cs, flip, lrd, dstate(ps),
-                                  std::max(1, std::min(cnt, 1 << 20)), ps->cap_stream);
+            if (cnt > 0) e = launch_level_step(c, LaunchCfg{ps->mx, ps->nt}, en, first, cnt, cs, flip, dstate(ps),
+                                               ps->cap_stream);
             flip ^= en.level < 0 ? allmask : (1u << en.level);
         }
     if (e == hipSuccess) e = launch_finish_chunk(dstate(ps), ncoarse, flip, ps->cap_stream);
@@ -571,8 +576,12 @@ fc_status fc_advance_level(fc_patchstore *ps, int32_t level, double t, double dt
     if (r != FC_OK) return r;
     if (level < ps->cfg.min_level || level > ps->cfg.max_level) return fail(FC_ERR_ARG, "bad level");
     if (!(dt > 0)) return fail(FC_ERR_ARG, "dt must be positive");
-    (void)t;
-    return advance_one(ps, level, t, dt, 0, -1, 1.0, (unsigned long long *)cfl_dev, (hipStream_t)stream);
+    hipStream_t s = (hipStream_t)stream;
+    const int n = (int)ps->mesh.lv.size();
+    if (cfl_dev) HIPCHK(launch_zero_cfl(cflp(ps), n, s));
+    r = advance_one(ps, level, t, dt, 0, -1, 1.0, cfl_dev != nullptr, s);
+    if (r == FC_OK && cfl_dev) HIPCHK(launch_export_cfl(nullptr, cflp(ps), n, cfl_dev, s));
+    return r;
 }
 
 fc_status fc_get_time(const fc_patchstore *ps, double *t) {
@@ -593,7 +602,10 @@ fc_status fc_advance_coarse_steps(fc_patchstore *ps, double dt_coarse, int32_t n
     if (r != FC_OK) return r;
     if (!(dt_coarse > 0) || nsteps < 0) return fail(FC_ERR_ARG, "bad step arguments");
     hipStream_t s = (hipStream_t)stream;
-    unsigned long long *cfl = (unsigned long long *)cfl_dev;
+    const bool cfl = cfl_dev != nullptr;
+    const int nleaf = (int)ps->mesh.lv.size();
+    if (cfl && (mode == FC_MODE_PER_LEVEL || mode == FC_MODE_FUSED_LEVELS))
+        HIPCHK(launch_zero_cfl(cflp(ps), nleaf, s));
     if (mode == FC_MODE_PER_LEVEL) {
         for (int n = 0; n < nsteps; n++) {
             for (const SchedEntry &e : ps->sched) {
@@ -616,6 +628,7 @@ fc_status fc_advance_coarse_steps(fc_patchstore *ps, double dt_coarse, int32_t n
             }
             ps->t += dt_coarse;
         }
+        if (cfl) HIPCHK(launch_export_cfl(nullptr, cflp(ps), nleaf, cfl_dev, s));
         return FC_OK;
     }
     if (mode == FC_MODE_FUSED_LEVELS) {
@@ -625,8 +638,8 @@ fc_status fc_advance_coarse_steps(fc_patchstore *ps, double dt_coarse, int32_t n
                 const double t = ps->t + e.off * dt_coarse, dt = e.scale * dt_coarse;
                 if (e.level < 0) {
                     Ctx c = make_ctx(ps);
-                    int cnt = (int)ps->mesh.lv.size();
-                    HIPCHK(launch_advance(c, LaunchCfg{ps->mx, ps->nt}, -1, 0, cnt, t, dt, 1, cfl, s));
+                    if (!cfl) c.cflp = nullptr;
+                    HIPCHK(launch_advance(c, LaunchCfg{ps->mx, ps->nt}, -1, 0, nleaf, t, dt, 1, s));
                     for (int l = 0; l < FC_MAXLEV; l++)
                         if (ps->lr.count[l] > 0) ps->curmask ^= 1u << l;
                 } else {
@@ -636,6 +649,7 @@ fc_status fc_advance_coarse_steps(fc_patchstore *ps, double dt_coarse, int32_t n
             }
             ps->t += dt_coarse;
         }
+        if (cfl) HIPCHK(launch_export_cfl(nullptr, cflp(ps), nleaf, cfl_dev, s));
         return FC_OK;
     }
     if (mode != FC_MODE_FUSED && mode != FC_MODE_FUSED_GRAPH && mode != FC_MODE_PERSISTENT_GRAPH)
@@ -643,7 +657,7 @@ fc_status fc_advance_coarse_steps(fc_patchstore *ps, double dt_coarse, int32_t n
     if (ps->pgrid <= 0) return fail(FC_ERR_HIP, "persistent kernel has no resident blocks");
     const int grid = ps->pgrid_user > 0 ? std::min(ps->pgrid_user, ps->pgrid) : ps->pgrid;
     DevState *st = dstate(ps);
-    HIPCHK(launch_set_state(st, ps->t, dt_coarse, ps->curmask, 1, s));
+    HIPCHK(launch_set_state(st, ps->t, dt_coarse, ps->curmask, 1, cflp(ps), nleaf, s));
     Ctx c = make_ctx(ps);
     const SchedEntry *sched = (const SchedEntry *)(ps->ws + ps->off_sched);
     const LevelRange *lrd = (const LevelRange *)(ps->ws + ps->off_lr);
@@ -683,7 +697,7 @@ fc_status fc_advance_coarse_steps(fc_patchstore *ps, double dt_coarse, int32_t n
         for (const SchedEntry &e : ps->sched) ps->curmask ^= e.level < 0 ? allmask : (1u << e.level);
         ps->t += dt_coarse;
     }
-    if (cfl_dev) HIPCHK(launch_export_cfl(st, cfl_dev, s));
+    if (cfl_dev) HIPCHK(launch_export_cfl(st, cflp(ps), nleaf, cfl_dev, s));
     return FC_OK;
 }
 
@@ -881,12 +895,13 @@ fc_status fc_autotune(fc_patchstore *ps, int32_t *threads_out, void *stream) {
         const int nt = cl[k];
         if (!valid_nt(ps->mx, nt, ps->cfg.equation)) continue;
         Ctx c = make_ctx(ps);
+        c.cflp = nullptr;
         LaunchCfg lc{ps->mx, nt};
         for (int w = 0; w < 2; w++)
-            HIPCHK(launch_advance(c, lc, lbest, ps->lr.start[lbest], ps->lr.count[lbest], ps->t, dt, 1, nullptr, s));
+            HIPCHK(launch_advance(c, lc, lbest, ps->lr.start[lbest], ps->lr.count[lbest], ps->t, dt, 1, s));
         HIPCHK(hipEventRecord(e0, s));
         for (int w = 0; w < 5; w++)
-            HIPCHK(launch_advance(c, lc, lbest, ps->lr.start[lbest], ps->lr.count[lbest], ps->t, dt, 1, nullptr, s));
+            HIPCHK(launch_advance(c, lc, lbest, ps->lr.start[lbest], ps->lr.count[lbest], ps->t, dt, 1, s));
         HIPCHK(hipEventRecord(e1, s));
         HIPCHK(hipEventSynchronize(e1));
         float ms = 0;
