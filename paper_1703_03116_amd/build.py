@@ -16,7 +16,10 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-munsafe-fp-atomics"]
+         "-munsafe-fp-atomics",
+         # multiply-adds fused per source expression only: every launch
+         # variant (segment length, unrolling) then rounds identically
+         "-ffp-contract=on"]
 
 
 def build(verbose: bool = False) -> str:

@@ -43,15 +43,20 @@ struct SchedEntry {
 
 // Device-resident state used by the persistent kernel (graph replays read
 // and update it, so replays need no host involvement).
+// coarse steps per graph replay / persistent launch (at most)
+constexpr int FC_TCHUNK = 50;
+
 struct DevState {
     double t;                  // time all levels are synchronised at
     double dt_coarse;
     unsigned long long cfl_bits;  // max Courant number (bits of a non-negative double)
     uint32_t curmask;          // bit l: current buffer of level l
     uint32_t bar_count, bar_gen;
-    int32_t err;               // bit 0: barrier spin limit hit; bit 1: stencil out of range;
-                               // bit 2: a level-step kernel's grid did not cover its level
+    int32_t err;               // bit 0: barrier spin limit hit; bit 1: stencil out of range
     int32_t pad;
+    // ts[k]: the time after k further coarse steps, accumulated as the host
+    // accumulates it (t += dt_coarse), k = 0 .. FC_TCHUNK
+    double ts[FC_TCHUNK + 1];
 };
 
 // Everything a kernel needs to read or evaluate patch data.
@@ -68,6 +73,7 @@ struct Ctx {
     const double *vt[FC_MAXLEV];
     int32_t velocity;
     double vel_u, vel_v, vel_T, g;
+    double vel_invT;           // 1 / T of the swirl field
     int32_t *err;              // device error flags
     double *cflp;              // per-slot max Courant number [cap]; NULL: not recorded
 };

@@ -23,8 +23,10 @@ namespace {
 
 constexpr int MB = 2;  // ghost layers used by the kernels
 
-__device__ __forceinline__ size_t qidx(int cap, int N, int f, int p, int i, int j) {
-    return ((size_t)(f * cap + p) * N + (j + MB)) * N + (i + MB);
+// element index of cell (i, j) (ghost-inclusive local indices) of field f of
+// slot p; the store keeps a buffer below 2^32 doubles
+__device__ __forceinline__ uint32_t qidx(int cap, int N, int f, int p, int i, int j) {
+    return ((uint32_t)(f * cap + p) * N + (uint32_t)(j + MB)) * N + (uint32_t)(i + MB);
 }
 
 // The time-dependent part of a kernel's view of the store: which buffer holds
@@ -50,7 +52,7 @@ __device__ __forceinline__ double *other_of(const Ctx &c, const View &v, int l) 
 template <int MX>
 __device__ __forceinline__ double read_state(const Ctx &c, const View &w, int p, int l, int i, int j, int f) {
     constexpr int N = MX + 2 * MB;
-    const size_t k = qidx(c.cap, N, f, p, i, j);
+    const uint32_t k = qidx(c.cap, N, f, p, i, j);
     const bool b = (w.curmask >> l) & 1u;
     double v = (b ? c.q1 : c.q0)[k];
     if (l == w.clevel && w.alpha != 1.0) {
@@ -121,43 +123,36 @@ __device__ void coarse_cell(const Ctx &c, const View &w, int p, int i, int j, do
     apply_signs<F>(v, su, sv);
 }
 
-// Ghost value of patch p at local (i, j): the result of Algorithm 1.
+// Ghost value at local (i, j) of patch p (level l) lying in region r of the
+// frame (no wall folding): copy, eq. ghost_coarse average or eq. ghost_fine
+// interpolation, as the region's neighbour record says.
 template <int MX, int F>
-__device__ void ghost_cell(const Ctx &c, const View &w, int p, int i, int j, double *v) {
-    const PatchInfo P = c.info[p];
-    const int l = P.level;
-    double su, sv;
-    fold<MX>(P.walls, i, j, su, sv);
-    if (i >= 0 && i < MX && j >= 0 && j < MX) {
+__device__ __forceinline__ void ghost_cell_r(const Ctx &c, const View &w, int p, int l, int i, int j, int r,
+                                             double *v) {
+    const NbrRec rec = c.nbr[p * FC_NREC + r];
+    if (rec.type == NB_SAME) {
 #pragma unroll
-        for (int f = 0; f < F; f++) v[f] = read_state<MX>(c, w, p, l, i, j, f);
-        apply_signs<F>(v, su, sv);
-        return;
-    }
-    const NbrRec r = c.nbr[p * FC_NREC + region_rec<MX>(i, j)];
-    if (r.type == NB_SAME) {
-#pragma unroll
-        for (int f = 0; f < F; f++) v[f] = read_state<MX>(c, w, r.id, l, i - r.ox, j - r.oy, f);
-    } else if (r.type == NB_FINE) {
-        const int li = 2 * (i - r.ox), lj = 2 * (j - r.oy);
+        for (int f = 0; f < F; f++) v[f] = read_state<MX>(c, w, rec.id, l, i - rec.ox, j - rec.oy, f);
+    } else if (rec.type == NB_FINE) {
+        const int li = 2 * (i - rec.ox), lj = 2 * (j - rec.oy);
 #pragma unroll
         for (int f = 0; f < F; f++)
-            v[f] = 0.25 * (read_state<MX>(c, w, r.id, l + 1, li, lj, f) + read_state<MX>(c, w, r.id, l + 1, li + 1, lj, f) +
-                           read_state<MX>(c, w, r.id, l + 1, li, lj + 1, f) +
-                           read_state<MX>(c, w, r.id, l + 1, li + 1, lj + 1, f));
-    } else if (r.type == NB_COARSE) {
+            v[f] = 0.25 * (read_state<MX>(c, w, rec.id, l + 1, li, lj, f) + read_state<MX>(c, w, rec.id, l + 1, li + 1, lj, f) +
+                           read_state<MX>(c, w, rec.id, l + 1, li, lj + 1, f) +
+                           read_state<MX>(c, w, rec.id, l + 1, li + 1, lj + 1, f));
+    } else if (rec.type == NB_COARSE) {
         // eq. ghost_fine: q_c + (1/4)(d_x s_x + d_y s_y), s = minmod of the
         // one-sided differences on the coarse grid, d = +1 for the upper half
-        const int I = i - r.ox, J = j - r.oy;
+        const int I = i - rec.ox, J = j - rec.oy;
         const int ic = I >> 1, jc = J >> 1;
         const double dx = (I & 1) ? 1.0 : -1.0, dy = (J & 1) ? 1.0 : -1.0;
         double cc[F], xm[F], xp[F], ym[F], yp[F];
 #pragma unroll
-        for (int f = 0; f < F; f++) cc[f] = read_state<MX>(c, w, r.id, l - 1, ic, jc, f);
-        coarse_cell<MX, F>(c, w, r.id, ic - 1, jc, xm);
-        coarse_cell<MX, F>(c, w, r.id, ic + 1, jc, xp);
-        coarse_cell<MX, F>(c, w, r.id, ic, jc - 1, ym);
-        coarse_cell<MX, F>(c, w, r.id, ic, jc + 1, yp);
+        for (int f = 0; f < F; f++) cc[f] = read_state<MX>(c, w, rec.id, l - 1, ic, jc, f);
+        coarse_cell<MX, F>(c, w, rec.id, ic - 1, jc, xm);
+        coarse_cell<MX, F>(c, w, rec.id, ic + 1, jc, xp);
+        coarse_cell<MX, F>(c, w, rec.id, ic, jc - 1, ym);
+        coarse_cell<MX, F>(c, w, rec.id, ic, jc + 1, yp);
 #pragma unroll
         for (int f = 0; f < F; f++) {
             const double sx = minmod(xp[f] - cc[f], cc[f] - xm[f]);
@@ -169,7 +164,46 @@ __device__ void ghost_cell(const Ctx &c, const View &w, int p, int i, int j, dou
 #pragma unroll
         for (int f = 0; f < F; f++) v[f] = __builtin_nan("");
     }
+}
+
+// Ghost value of patch p at local (i, j): the result of Algorithm 1.
+template <int MX, int F>
+__device__ void ghost_cell(const Ctx &c, const View &w, int p, int i, int j, double *v) {
+    const PatchInfo P = c.info[p];
+    const int l = P.level;
+    double su, sv;
+    fold<MX>(P.walls, i, j, su, sv);
+    if (i >= 0 && i < MX && j >= 0 && j < MX) {
+#pragma unroll
+        for (int f = 0; f < F; f++) v[f] = read_state<MX>(c, w, p, l, i, j, f);
+    } else {
+        ghost_cell_r<MX, F>(c, w, p, l, i, j, region_rec<MX>(i, j), v);
+    }
     apply_signs<F>(v, su, sv);
+}
+
+// g-th cell of the ghost frame in region-major order: the eight face halves
+// (MB x MX/2 cells each, numbered as region_rec numbers them), then the four
+// MB x MB corners.  Consecutive g share a region and so a neighbour record.
+template <int MX>
+__device__ __forceinline__ void ghost_region_index(int g, int &i, int &j, int &r) {
+    constexpr int H = MX / 2, HF = MB * H;
+    if (g < 8 * HF) {
+        r = g / HF;
+        const int k = g % HF, along = (r & 1) * H + k % H, across = k / H;
+        switch (r >> 1) {
+            case 0: i = across - MB; j = along; break;
+            case 1: i = MX + across; j = along; break;
+            case 2: i = along; j = across - MB; break;
+            default: i = along; j = MX + across; break;
+        }
+    } else {
+        const int k = g - 8 * HF;
+        r = 8 + k / (MB * MB);
+        const int a = k % MB, b = (k / MB) % MB;
+        i = (r & 1) ? MX + a : a - MB;
+        j = (r & 2) ? MX + b : b - MB;
+    }
 }
 
 // g-th ghost cell of the (MX+4)^2 frame: two bottom rows, two top rows, then
@@ -222,50 +256,60 @@ __global__ void __launch_bounds__(256) fill_kernel(Ctx c, int first) {
 template <int MX>
 struct ScalarSmem {
     static constexpr int N = MX + 2 * MB;
-    static constexpr int NP = N + 1;  // odd row stride: column sweeps avoid bank conflicts
-    double q[N * NP];
-    double tx[(MX + 2) * MX];         // TX(i, j) = A+*_{i-1/2} + A-*_{i+1/2}, [j+1][i], rows -1..MX
-    double dcx[MX * MX];              // C_{i+1/2} - C_{i-1/2} of the x-edges, [j][i]
-    double ty[MX * (MX + 2)];         // TY(i, j), [j][i+1], columns -1..MX
-    double dcy[MX * MX];              // C_{j+1/2} - C_{j-1/2} of the y-edges, [j][i]
+    static constexpr int NP = N + 1;  // odd row strides: row- and column-wise lanes hit distinct banks
+    static constexpr int S = MX + 1;
+    double q[N * NP];                 // the tile; after the sweeps, the new interior (staged for the store)
+    double tx[(MX + 2) * S];          // TX(i, j) = A+*_{i-1/2} + A-*_{i+1/2} at [(j+1) S + i], rows -1..MX
+    double ty[(MX + 2) * S];          // TY(i, j) at [(i+1) S + j], columns -1..MX
+    double dcy[MX * S];               // C_{j+1/2} - C_{j-1/2} of the y-edges at [i S + j]
     double ux[MX + 1], uy[MX + 2];    // u(e, j) = ux[e] * uy[j+1]
     double vy[MX + 1], vx[MX + 2];    // v(i, e) = vy[e] * vx[i+1]
     double red[16];
 };
 
-// Cells per thread in the edge sweeps: the smallest segment length with
-// (MX+2) lines x ceil(MX/seg) segments <= NT (a segment also computes the
-// first edge of the next one).
+// Cells per edge-sweep item: every interior line is split into MX/SEG
+// segments and the x- and y-items of the interior lines fill at most NT
+// threads; a segment of SEG cells computes its SEG+1 edges.
 template <int MX, int NT>
-constexpr int edge_seg() {
-    int sg = 1;
-    while ((MX + 2) * ((MX + sg - 1) / sg) > NT) sg++;
+constexpr int scalar_seg() {
+    int sg = 2 * MX * MX / NT;
+    if (sg < 4) sg = 4;
+    if (sg > MX) sg = MX;
     return sg;
-}
-
-__device__ __forceinline__ double limit(int lim, double W, double Wu) {
-    if (lim == 1) return W;          // Lax-Wendroff
-    if (lim == 2) return 0.0;        // first order
-    const double aw = fabs(W), au = fabs(Wu);
-    double mn;
-    if (lim == 3) mn = fmin(aw, au);  // minmod
-    else mn = fmin(0.5 * fabs(W + Wu), fmin(2.0 * aw, 2.0 * au));  // MC
-    return (W * Wu > 0.0) ? copysign(mn, W) : 0.0;
 }
 
 __device__ __forceinline__ double posp(double a) { return a > 0.0 ? a : 0.0; }
 __device__ __forceinline__ double negp(double a) { return a < 0.0 ? a : 0.0; }
+
+// Second-order correction C = |s| (1 - lam |s|) W~ of one wave W, with W~
+// the limited wave and Wu its upwind neighbour.  Limiter codes: 0 MC,
+// 1 Lax-Wendroff (no limiting), 2 first order, 3 minmod.  The MC value
+// phi(theta) W, theta = Wu / W, is formed without the division: zero unless
+// W Wu > 0, else sign(W) min((|W| + |Wu|) / 2, 2 |W|, 2 |Wu|).
+template <int LIM>
+__device__ __forceinline__ double correction(double W, double Wu, double as, double lam) {
+    if constexpr (LIM == 2) return 0.0;
+    const double k = as - (lam * as) * as;
+    if constexpr (LIM == 1) return k * W;
+    const double aw = fabs(W), au = fabs(Wu);
+    double m;
+    if constexpr (LIM == 3) m = fmin(aw, au);
+    else m = fmin(0.5 * (aw + au), 2.0 * fmin(aw, au));
+    return (W * Wu > 0.0) ? k * copysign(m, W) : 0.0;  // k < 0 where lam |s| > 1
+}
 
 // velocity factors of a patch into LDS
 template <int MX>
 __device__ void load_velocity(const Ctx &c, ScalarSmem<MX> &s, int l, int gx, int gy, double tm) {
     const int n = MX << l;
     if (c.velocity == 2) {
-        const double ct = cos(M_PI * tm / c.vel_T);
-        const double *vt = c.vt[l];
-        const double *ex = vt + vt_ex(n, MB), *cxv = vt + vt_cx(n, MB);
-        const double *ey = vt + vt_ey(n, MB), *cyv = vt + vt_cy(n, MB);
-        for (int k = threadIdx.x; k < MX + 2; k += blockDim.x) {
+        // blockDim >= 64 > MX + 2: the first wave alone evaluates c(t)
+        const int k = threadIdx.x;
+        if (k < MX + 2) {
+            const double ct = cos(M_PI * (tm * c.vel_invT));
+            const double *vt = c.vt[l];
+            const double *ex = vt + vt_ex(n, MB), *cxv = vt + vt_cx(n, MB);
+            const double *ey = vt + vt_ey(n, MB), *cyv = vt + vt_cy(n, MB);
             if (k <= MX) { s.ux[k] = ex[gx + k]; s.vy[k] = ey[gy + k]; }
             s.uy[k] = cyv[gy + k - 1] * ct;
             s.vx[k] = -(cxv[gx + k - 1] * ct);
@@ -279,128 +323,197 @@ __device__ void load_velocity(const Ctx &c, ScalarSmem<MX> &s, int l, int gx, in
     }
 }
 
+// One segment of one interior line: edges e0 .. e0+SEG (edge e lies between
+// cells e-1 and e of the line), cells e0 .. e0+SEG-1.  DIR 0: x-edges of row
+// `line`; DIR 1: y-edges of column `line`.  Writes TX (TY) of the cells; for
+// a row also R = Q - lam TX + lam/2 (C_{i+1/2} - C_{i-1/2}) (kept in
+// registers for the update), for a column the y differences of C.
+// amax: largest |velocity| over the edges.
+template <int MX, int SEG, int LIM, int DIR>
+__device__ __forceinline__ void sweep_segment(ScalarSmem<MX> &s, int line, int e0, double lam, double (&R)[SEG],
+                                              double &amax) {
+    constexpr int NP = ScalarSmem<MX>::NP, S = ScalarSmem<MX>::S;
+    constexpr int STR = DIR == 0 ? 1 : NP;
+    const double *qp = DIR == 0 ? &s.q[(line + MB) * NP + MB + e0 - 2] : &s.q[(MB + e0 - 2) * NP + line + MB];
+    const double *ve = DIR == 0 ? &s.ux[e0] : &s.vy[e0];
+    const double vl = DIR == 0 ? s.uy[line + 1] : s.vx[line + 1];
+    double q[SEG + 4];
+#pragma unroll
+    for (int k = 0; k < SEG + 4; k++) q[k] = qp[k * STR];
+    double am = 0.0, aprev = 0.0, cprev = 0.0;
+#pragma unroll
+    for (int k = 0; k <= SEG; k++) {  // edge e0 + k, between q[k+1] and q[k+2]
+        const double u = ve[k] * vl;
+        const double W = q[k + 2] - q[k + 1];
+        const double Wu = u > 0.0 ? q[k + 1] - q[k] : q[k + 3] - q[k + 2];
+        const double au = fabs(u);
+        const double C = correction<LIM>(W, Wu, au, lam);
+        const double aps = posp(u) * W - C;
+        const double ams = negp(u) * W + C;
+        am = fmax(am, au);
+        if (k > 0) {  // cell e0 + k - 1
+            const int cc = e0 + k - 1;
+            const double T = aprev + ams;
+            if (DIR == 0) {
+                s.tx[(line + 1) * S + cc] = T;
+                R[k - 1] = q[k + 1] - lam * T + (0.5 * lam) * (C - cprev);
+            } else {
+                s.ty[(line + 1) * S + cc] = T;
+                s.dcy[line * S + cc] = C - cprev;
+            }
+        }
+        aprev = aps;
+        cprev = C;
+    }
+    amax = fmax(amax, am);
+}
+
+// The same for a line outside the interior (row -1 or MX: DIR 0, column -1
+// or MX: DIR 1), TX (TY) only.  Direction-generic (per-lane stride and base)
+// so that a wave holding both kinds takes one path.
+template <int MX, int SEG, int LIM>
+__device__ __forceinline__ void sweep_outer(ScalarSmem<MX> &s, int dir, int line, int e0, double lam) {
+    constexpr int NP = ScalarSmem<MX>::NP, S = ScalarSmem<MX>::S;
+    const int str = dir == 0 ? 1 : NP;
+    const double *qp = dir == 0 ? &s.q[(line + MB) * NP + MB + e0 - 2] : &s.q[(MB + e0 - 2) * NP + line + MB];
+    const double *ve = dir == 0 ? &s.ux[e0] : &s.vy[e0];
+    const double vl = dir == 0 ? s.uy[line + 1] : s.vx[line + 1];
+    double *to = (dir == 0 ? s.tx : s.ty) + (line + 1) * S + e0 - 1;
+    double q[SEG + 4];
+#pragma unroll
+    for (int k = 0; k < SEG + 4; k++) q[k] = qp[k * str];
+    double aprev = 0.0;
+#pragma unroll
+    for (int k = 0; k <= SEG; k++) {
+        const double u = ve[k] * vl;
+        const double W = q[k + 2] - q[k + 1];
+        const double Wu = u > 0.0 ? q[k + 1] - q[k] : q[k + 3] - q[k + 2];
+        const double C = correction<LIM>(W, Wu, fabs(u), lam);
+        const double ams = negp(u) * W + C;
+        if (k > 0) to[k] = aprev + ams;
+        aprev = posp(u) * W - C;
+    }
+}
+
+// The update of the cells e0 .. e0+SEG-1 of interior row j from R and the
+// stored TX, TY, y-differences of C:
+//   Q_new = R - lam TY + lam/2 dCy + lam^2/2 ((TF_{i+1/2} - TF_{i-1/2}) + (TG_{j+1/2} - TG_{j-1/2}))
+// with TF(e) = u+ TY(e-1) + u- TY(e) on x-edges and TG likewise from TX.
+// The result goes to the tile (staging for a coalesced store).
+template <int MX, int SEG>
+__device__ __forceinline__ void update_segment(ScalarSmem<MX> &s, int j, int e0, double lam, const double (&R)[SEG]) {
+    constexpr int NP = ScalarSmem<MX>::NP, S = ScalarSmem<MX>::S;
+    const double uyj = s.uy[j + 1], vyd = s.vy[j], vyu = s.vy[j + 1];
+    double ty[SEG + 2];
+#pragma unroll
+    for (int k = 0; k < SEG + 2; k++) ty[k] = s.ty[(e0 + k) * S + j];  // TY(e0 - 1 + k, j)
+    double tf[SEG + 1];
+#pragma unroll
+    for (int k = 0; k <= SEG; k++) {
+        const double u = s.ux[e0 + k] * uyj;
+        tf[k] = posp(u) * ty[k] + negp(u) * ty[k + 1];
+    }
+    const double hl = 0.5 * lam, hl2 = 0.5 * lam * lam;
+#pragma unroll
+    for (int k = 0; k < SEG; k++) {
+        const int cc = e0 + k;
+        const double txd = s.tx[j * S + cc], txc = s.tx[(j + 1) * S + cc], txu = s.tx[(j + 2) * S + cc];
+        const double vxc = s.vx[cc + 1];
+        const double vd = vyd * vxc, vu = vyu * vxc;
+        const double tgd = posp(vd) * txd + negp(vd) * txc;
+        const double tgu = posp(vu) * txc + negp(vu) * txu;
+        const double dcy = s.dcy[cc * S + j];
+        s.q[(j + MB) * NP + cc + MB] = R[k] - lam * ty[k + 1] + hl * dcy + hl2 * ((tf[k + 1] - tf[k]) + (tgu - tgd));
+    }
+}
+
 // One step on patch p of level l: stage its tile, compute, write the new
 // interior into the level's other buffer.  FUSED: ghosts evaluated on the fly
 // instead of read from the patch's own ghost cells.
-//   x-edges are swept along rows and y-edges along columns, each thread
-//   keeping the four cells of the limiter stencil in registers; the update
-//   sweeps a band of rows per interior column.
-template <int MX, int NT, bool FUSED>
-__device__ void advance_scalar_patch(const Ctx &c, const View &w, ScalarSmem<MX> &s, int p, double t, double dt,
-                                     double &cfl) {
+//   Edge sweeps: one item per (line, segment); the x-items of the interior
+//   rows keep their partial sums in registers and, after the barrier, finish
+//   the update of their cells.
+template <int MX, int NT, int LIM, bool FUSED>
+__device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, ScalarSmem<MX> &s, int p, double t, double dt,
+                                   double &cfl) {
     constexpr int N = MX + 2 * MB, NP = ScalarSmem<MX>::NP;
-    constexpr int SEG = edge_seg<MX, NT>(), NSEG = (MX + SEG - 1) / SEG;
+    constexpr int SEG = scalar_seg<MX, NT>(), NSEG = MX / SEG, NI = MX * NSEG, NTOT = 2 * NI + 4 * NSEG;
+    static_assert(NI <= NT, "the x-items of the interior rows must fit one pass");
     const PatchInfo P = c.info[p];
     const int l = P.level;
-    const double h = 1.0 / (double)(MX << l);
-    const double lam = dt / h;
+    const double lam = dt * (double)(MX << l);  // dt / h, exact: h = 1 / (MX 2^l)
     const double *in = buf_of(c, w, l);
     double *out = other_of(c, w, l);
     const size_t base = (size_t)p * N * N;
     load_velocity<MX>(c, s, l, P.ix * MX, P.iy * MX, t + 0.5 * dt);
+    // rows are 16-byte aligned (N and MB even): two cells per load
     if (!FUSED) {
-        for (int k = threadIdx.x; k < N * N; k += NT) s.q[(k / N) * NP + k % N] = in[base + k];
+        for (int k = threadIdx.x; k < N * N / 2; k += NT) {
+            const int i = 2 * (k % (N / 2)), j = k / (N / 2);
+            const double2 v = *reinterpret_cast<const double2 *>(&in[base + j * N + i]);
+            s.q[j * NP + i] = v.x;
+            s.q[j * NP + i + 1] = v.y;
+        }
     } else {
-        for (int k = threadIdx.x; k < MX * MX; k += NT) {
-            const int i = k % MX, j = k / MX;
-            s.q[(j + MB) * NP + i + MB] = in[base + (j + MB) * N + i + MB];
+        for (int k = threadIdx.x; k < MX * MX / 2; k += NT) {
+            const int i = 2 * (k % (MX / 2)), j = k / (MX / 2);
+            const double2 v = *reinterpret_cast<const double2 *>(&in[base + (j + MB) * N + i + MB]);
+            s.q[(j + MB) * NP + i + MB] = v.x;
+            s.q[(j + MB) * NP + i + MB + 1] = v.y;
         }
         constexpr int NG = N * N - MX * MX;
-        for (int g = threadIdx.x; g < NG; g += NT) {
-            int i, j;
-            ghost_index<MX>(g, i, j);
-            double v[1];
-            ghost_cell<MX, 1>(c, w, p, i, j, v);
-            s.q[(j + MB) * NP + i + MB] = v[0];
+        if (P.walls == 0) {
+            for (int g = threadIdx.x; g < NG; g += NT) {
+                int i, j, r;
+                ghost_region_index<MX>(g, i, j, r);
+                double v[1];
+                ghost_cell_r<MX, 1>(c, w, p, l, i, j, r, v);
+                s.q[(j + MB) * NP + i + MB] = v[0];
+            }
+        } else {
+            for (int g = threadIdx.x; g < NG; g += NT) {
+                int i, j;
+                ghost_index<MX>(g, i, j);
+                double v[1];
+                ghost_cell<MX, 1>(c, w, p, i, j, v);
+                s.q[(j + MB) * NP + i + MB] = v[0];
+            }
         }
     }
     __syncthreads();
+    double R[SEG];
     double amax = 0.0;
-    // Each item sweeps edges e0..e1 of one line (the segment plus the first
-    // edge of the next one) and writes the per-cell sums of the cells between
-    // them: TX(i) = A+*_{i-1/2} + A-*_{i+1/2} and C_{i+1/2} - C_{i-1/2}.
-    for (int item = threadIdx.x; item < (MX + 2) * NSEG; item += NT) {
-        const int line = item / NSEG - 1, e0 = (item % NSEG) * SEG;
-        const int e1 = e0 + SEG < MX ? e0 + SEG : MX;  // last edge computed (inclusive)
-        {   // x-edges (e - 1/2, j = line)
-            const int j = line;
-            const double *row = &s.q[(j + MB) * NP + MB];
-            const double uyj = s.uy[j + 1];
-            double qm2 = row[e0 - 2], qm1 = row[e0 - 1], q0 = row[e0];
-            double aps_prev = 0.0, c_prev = 0.0;
-            for (int e = e0; e <= e1; e++) {
-                const double qp1 = row[e + 1];
-                const double u = s.ux[e] * uyj;
-                const double W = q0 - qm1;
-                const double Wu = u > 0.0 ? qm1 - qm2 : qp1 - q0;
-                const double au = fabs(u);
-                const double C = au * (1.0 - lam * au) * limit(c.lim, W, Wu);
-                const double aps = posp(u) * W - C;
-                const double ams = negp(u) * W + C;
-                if (e > e0) {  // cell e-1 lies between edges e-1 and e
-                    s.tx[(j + 1) * MX + e - 1] = aps_prev + ams;
-                    if (j >= 0 && j < MX) s.dcx[j * MX + e - 1] = C - c_prev;
-                }
-                if (j >= 0 && j < MX && e < e1 + (e1 == MX ? 1 : 0)) amax = fmax(amax, au);
-                aps_prev = aps; c_prev = C;
-                qm2 = qm1; qm1 = q0; q0 = qp1;
-            }
-        }
-        {   // y-edges (i = line, e - 1/2)
-            const int i = line;
-            const double *col = &s.q[MB * NP + i + MB];
-            const double vxi = s.vx[i + 1];
-            double qm2 = col[(e0 - 2) * NP], qm1 = col[(e0 - 1) * NP], q0 = col[e0 * NP];
-            double bps_prev = 0.0, c_prev = 0.0;
-            for (int e = e0; e <= e1; e++) {
-                const double qp1 = col[(e + 1) * NP];
-                const double v = s.vy[e] * vxi;
-                const double W = q0 - qm1;
-                const double Wu = v > 0.0 ? qm1 - qm2 : qp1 - q0;
-                const double av = fabs(v);
-                const double C = av * (1.0 - lam * av) * limit(c.lim, W, Wu);
-                const double bps = posp(v) * W - C;
-                const double bms = negp(v) * W + C;
-                if (e > e0) {
-                    s.ty[(e - 1) * (MX + 2) + i + 1] = bps_prev + bms;
-                    if (i >= 0 && i < MX) s.dcy[(e - 1) * MX + i] = C - c_prev;
-                }
-                if (i >= 0 && i < MX && e < e1 + (e1 == MX ? 1 : 0)) amax = fmax(amax, av);
-                bps_prev = bps; c_prev = C;
-                qm2 = qm1; qm1 = q0; q0 = qp1;
-            }
+    for (int item = threadIdx.x; item < NTOT; item += NT) {
+        if (item < NI) {
+            sweep_segment<MX, SEG, LIM, 0>(s, item % MX, (item / MX) * SEG, lam, R, amax);
+        } else if (item < 2 * NI) {
+            const int k = item - NI;
+            sweep_segment<MX, SEG, LIM, 1>(s, k % MX, (k / MX) * SEG, lam, R, amax);
+        } else {  // rows -1, MX and columns -1, MX: TX, TY only (transverse terms at the patch edge)
+            const int k = item - 2 * NI, g = k / NSEG, e0 = (k % NSEG) * SEG;
+            sweep_outer<MX, SEG, LIM>(s, g >> 1, (g & 1) ? MX : -1, e0, lam);
         }
     }
     __syncthreads();
-    // conservative update, a band of R rows per interior column:
-    // Q - lam (TX + TY) + lam/2 (dCx + dCy) + lam^2/2 (dTF + dTG), where
-    // TF(i-1/2) = u+ TY(i-1) + u- TY(i) and TG(j-1/2) = v+ TX(j-1) + v- TX(j)
-    constexpr int R = (MX * MX) / NT > 0 ? (MX * MX) / NT : 1;
-    constexpr int NBAND = MX / R;
-    if (threadIdx.x < MX * NBAND) {
-        const int i = threadIdx.x % MX, j0 = (threadIdx.x / MX) * R;
-        const double uxl = s.ux[i], uxr = s.ux[i + 1], vxi = s.vx[i + 1];
-        double TXd = s.tx[j0 * MX + i], TXc = s.tx[(j0 + 1) * MX + i];
-        double vD = s.vy[j0] * vxi;
-        for (int j = j0; j < j0 + R; j++) {
-            const double TXu = s.tx[(j + 2) * MX + i];
-            const int by = j * (MX + 2) + i + 1;
-            const double TYc = s.ty[by], TYl = s.ty[by - 1], TYr = s.ty[by + 1];
-            const double uyj = s.uy[j + 1];
-            const double uL = uxl * uyj, uR = uxr * uyj;
-            const double vU = s.vy[j + 1] * vxi;
-            const double TFl = posp(uL) * TYl + negp(uL) * TYc;
-            const double TFr = posp(uR) * TYc + negp(uR) * TYr;
-            const double TGd = posp(vD) * TXd + negp(vD) * TXc;
-            const double TGu = posp(vU) * TXc + negp(vU) * TXu;
-            const double dC = s.dcx[j * MX + i] + s.dcy[j * MX + i];
-            const double Q = s.q[(j + MB) * NP + i + MB];
-            out[base + (j + MB) * N + i + MB] =
-                Q - lam * (TXc + TYc) + 0.5 * lam * dC + 0.5 * lam * lam * ((TFr - TFl) + (TGu - TGd));
-            TXd = TXc; TXc = TXu; vD = vU;
-        }
+    if ((int)threadIdx.x < NI) update_segment<MX, SEG>(s, threadIdx.x % MX, (threadIdx.x / MX) * SEG, lam, R);
+    __syncthreads();
+    for (int k = threadIdx.x; k < MX * MX / 2; k += NT) {
+        const int i = 2 * (k % (MX / 2)), j = k / (MX / 2);
+        *reinterpret_cast<double2 *>(&out[base + (j + MB) * N + i + MB]) =
+            make_double2(s.q[(j + MB) * NP + i + MB], s.q[(j + MB) * NP + i + MB + 1]);
     }
     cfl = fmax(cfl, lam * amax);
+}
+
+template <int MX, int NT, bool FUSED>
+__device__ __forceinline__ void advance_scalar_patch(const Ctx &c, const View &w, ScalarSmem<MX> &s, int p, double t, double dt,
+                                     double &cfl) {
+    switch (c.lim) {
+        case 1: advance_scalar_lim<MX, NT, 1, FUSED>(c, w, s, p, t, dt, cfl); break;
+        case 2: advance_scalar_lim<MX, NT, 2, FUSED>(c, w, s, p, t, dt, cfl); break;
+        case 3: advance_scalar_lim<MX, NT, 3, FUSED>(c, w, s, p, t, dt, cfl); break;
+        default: advance_scalar_lim<MX, NT, 0, FUSED>(c, w, s, p, t, dt, cfl); break;
+    }
 }
 
 // block-wide max of a non-negative double, then one atomicMax on its bits
@@ -436,8 +549,14 @@ __device__ void reduce_cfl_slot(double v, double *red, double *slot) {
     }
 }
 
+// Waves per SIMD the scalar kernels are compiled for: at mx = 32 the LDS
+// tile admits four workgroups per CU, and the register budget is set so that
+// all four are resident.
+template <int MX, int NT, int EQ>
+constexpr int min_waves() { return (EQ == 0 && MX == 32) ? NT / 64 : 1; }
+
 template <int MX, int NT, bool FUSED>
-__global__ void __launch_bounds__(NT) advance_scalar_kernel(Ctx c, int first, int count, double t, double dt) {
+__global__ void __launch_bounds__(NT, (min_waves<MX, NT, 0>())) advance_scalar_kernel(Ctx c, int first, int count, double t, double dt) {
     __shared__ ScalarSmem<MX> s;
     const int p = first + xcd_remap(blockIdx.x, count);
     double cfl = 0.0;
@@ -582,8 +701,8 @@ __device__ void advance_swe_patch(const Ctx &c, const View &w, SweSmem<MX> &s, i
     constexpr int N = MX + 2 * MB, NR = SweSmem<MX>::NR;
     const PatchInfo P = c.info[p];
     const int l = P.level;
-    const double h = 1.0 / (double)(MX << l);
-    const double lam = dt / h, g = c.g;
+    // h = 1 / (MX 2^l) is a power of two: dt / h is exact as a product
+    const double lam = dt * (double)(MX << l), g = c.g;
     const double *in = buf_of(c, w, l);
     double *out = other_of(c, w, l);
     if (!FUSED) {
@@ -749,7 +868,7 @@ __global__ void __launch_bounds__(NT) adjoint_kernel(Ctx c, int first, int count
     const View w = view_of(c);
     const PatchInfo P = c.info[p];
     const int l = P.level;
-    const double h = 1.0 / (double)(MX << l), lam = dt / h;
+    const double lam = dt * (double)(MX << l);  // dt / h, exact: h = 1 / (MX 2^l)
     const double *in = buf_of(c, w, l);
     const size_t base = (size_t)p * N * N;
     // velocities (same factors as the forward step)
@@ -757,7 +876,7 @@ __global__ void __launch_bounds__(NT) adjoint_kernel(Ctx c, int first, int count
         const int n = MX << l, gx0 = P.ix * MX, gy0 = P.iy * MX;
         const double tm = t + 0.5 * dt;
         if (c.velocity == 2) {
-            const double ct = cos(M_PI * tm / c.vel_T);
+            const double ct = cos(M_PI * (tm * c.vel_invT));
             const double *vt = c.vt[l];
             const double *ex = vt + vt_ex(n, MB), *cxv = vt + vt_cx(n, MB);
             const double *ey = vt + vt_ey(n, MB), *cyv = vt + vt_cy(n, MB);
@@ -1018,12 +1137,11 @@ struct StepArgs {
 };
 
 template <int MX, int NT, int EQ>
-__global__ void __launch_bounds__(NT) level_step_kernel(Ctx c, StepArgs a, DevState *st) {
+__global__ void __launch_bounds__(NT, (min_waves<MX, NT, EQ>())) level_step_kernel(Ctx c, StepArgs a, DevState *st) {
     __shared__ typename SmemOf<MX, EQ>::type s;
-    double t0 = st->t;
+    const double t0 = st->ts[a.cidx];
     const double dtc = st->dt_coarse;
     const uint32_t cm = st->curmask;
-    for (int q = 0; q < a.cidx; q++) t0 = t0 + dtc;  // the host's accumulation of coarse steps
     const View w{cm ^ a.flip, a.level < 0 ? -1 : a.level - 1, a.level < 0 ? 1.0 : a.alpha};
     const double t = t0 + a.off * dtc, dt = a.scale * dtc;
     double cfl = 0.0;
@@ -1033,11 +1151,18 @@ __global__ void __launch_bounds__(NT) level_step_kernel(Ctx c, StepArgs a, DevSt
     reduce_cfl_slot<NT>(cfl, s.red, c.cflp + p);
 }
 
-__global__ void finish_chunk_kernel(DevState *st, int ncoarse, uint32_t flip) {
+__device__ void fill_times(DevState *st) {
     double t = st->t;
-    for (int q = 0; q < ncoarse; q++) t = t + st->dt_coarse;
-    st->t = t;
+    for (int q = 0; q <= FC_TCHUNK; q++) {
+        st->ts[q] = t;
+        t = t + st->dt_coarse;
+    }
+}
+
+__global__ void finish_chunk_kernel(DevState *st, int ncoarse, uint32_t flip) {
+    st->t = st->ts[ncoarse];
     st->curmask ^= flip;
+    fill_times(st);
 }
 
 // ------------------------------------------------------------------------
@@ -1075,6 +1200,7 @@ __global__ void set_state_kernel(DevState *st, double t, double dt, uint32_t cur
         st->curmask = curmask;
         st->bar_count = 0;
         if (reset_cfl) st->cfl_bits = 0ull;
+        fill_times(st);
     }
     if (reset_cfl && cflp && k < n) cflp[k] = 0.0;
 }

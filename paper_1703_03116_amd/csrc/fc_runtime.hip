@@ -279,6 +279,7 @@ Ctx make_ctx(const fc_patchstore *ps) {
                       ? (const double *)(ps->ws + ps->off_vt[l] ) : nullptr;
     c.velocity = ps->cfg.velocity;
     c.vel_u = ps->cfg.vel_params[0]; c.vel_v = ps->cfg.vel_params[1]; c.vel_T = ps->cfg.vel_params[0];
+    c.vel_invT = ps->cfg.velocity == FC_VEL_SWIRL ? 1.0 / ps->cfg.vel_params[0] : 0.0;
     c.g = ps->cfg.gravity;
     c.err = (int32_t *)(ps->ws + ps->off_state + offsetof(DevState, err));
     c.cflp = cflp(ps);
@@ -452,6 +453,11 @@ fc_status fc_patchstore_create(const fc_config *cfg, int64_t nleaves, const fc_l
     if (cfg->min_level < 0 || cfg->max_level < cfg->min_level || cfg->max_level >= FC_MAXLEV - 1)
         return fail(FC_ERR_ARG, "bad level range");
     if (cfg->capacity < nleaves) return fail(FC_ERR_CAPACITY, "capacity below the number of leaves");
+    {
+        const int64_t n = cfg->mx + 2 * MBK, nf = cfg->equation == FC_EQ_SWE ? 3 : 1;
+        if (nf * (int64_t)cfg->capacity * n * n > (int64_t)UINT32_MAX)
+            return fail(FC_ERR_CAPACITY, "a patch buffer must stay below 2^32 doubles (32-bit cell indices)");
+    }
     if (cfg->equation == FC_EQ_ADVECTION && cfg->velocity == FC_VEL_NONE) return fail(FC_ERR_ARG, "advection needs a velocity");
     if (cfg->velocity == FC_VEL_SWIRL && !(cfg->vel_params[0] > 0)) return fail(FC_ERR_ARG, "swirl period must be > 0");
     std::vector<fc_leaf> L(leaves, leaves + nleaves);
@@ -662,7 +668,7 @@ fc_status fc_advance_coarse_steps(fc_patchstore *ps, double dt_coarse, int32_t n
     const SchedEntry *sched = (const SchedEntry *)(ps->ws + ps->off_sched);
     const LevelRange *lrd = (const LevelRange *)(ps->ws + ps->off_lr);
     // up to `kChunk` coarse steps per launch (persistent) or per graph replay
-    const int kChunk = 50;
+    const int kChunk = FC_TCHUNK;
     if (mode == FC_MODE_FUSED) {
         for (int k = 0; k < nsteps; k += kChunk) {
             const int m = std::min(kChunk, nsteps - k);
