@@ -75,7 +75,8 @@ struct Ctx {
     double vel_u, vel_v, vel_T, g;
     double vel_invT;           // 1 / T of the swirl field
     int32_t *err;              // device error flags
-    double *cflp;              // per-slot max Courant number [cap]; NULL: not recorded
+    unsigned long long *cflp;  // per-slot max Courant number (bits of a non-negative double) [cap];
+                               // NULL: not recorded
 };
 
 // Velocity factor tables of one level with n = mx 2^l cells per axis and m
@@ -103,9 +104,9 @@ struct LaunchCfg {
 
 hipError_t launch_init_tables(int level, int mx, int periodic_x, int periodic_y, double *vt, hipStream_t s);
 // reset_cfl: also zero the n per-slot Courant maxima
-hipError_t launch_set_state(DevState *st, double t, double dt, uint32_t curmask, int reset_cfl, double *cflp, int n,
+hipError_t launch_set_state(DevState *st, double t, double dt, uint32_t curmask, int reset_cfl, unsigned long long *cflp, int n,
                             hipStream_t s);
-hipError_t launch_zero_cfl(double *cflp, int n, hipStream_t s);
+hipError_t launch_zero_cfl(unsigned long long *cflp, int n, hipStream_t s);
 hipError_t launch_fill(const Ctx &c, int mx, int first, int count, hipStream_t s);
 hipError_t launch_advance(const Ctx &c, LaunchCfg lc, int level, int first, int count, double t, double dt,
                           int fused, hipStream_t s);
@@ -115,10 +116,10 @@ hipError_t launch_persistent(const Ctx &c, LaunchCfg lc, const SchedEntry *sched
                              hipStream_t s);
 int persistent_max_grid(LaunchCfg lc, int eq);
 // one level-step (schedule entry e over slots [first, first+count), coarse
-// step cidx of a chunk, parities = device curmask ^ flip), ghosts gathered
-// on the fly, one workgroup per patch
+// step cidx of a chunk of steps dt_coarse, buffer parities mask), ghosts
+// gathered on the fly, one workgroup per patch
 hipError_t launch_level_step(const Ctx &c, LaunchCfg lc, const SchedEntry &e, int first, int count, int cidx,
-                             uint32_t flip, DevState *st, hipStream_t s);
+                             uint32_t mask, double dt_coarse, DevState *st, hipStream_t s);
 // advance the device time by ncoarse coarse steps and flip the parities
 hipError_t launch_finish_chunk(DevState *st, int ncoarse, uint32_t flip, hipStream_t s);
 hipError_t launch_set_interior(const Ctx &c, int mx, const int32_t *slot_of_leaf, int n, const double *src,
@@ -130,7 +131,7 @@ hipError_t launch_tag(const Ctx &c, int mx, const int32_t *slot_of_leaf, int n, 
 hipError_t launch_consolidate(const Ctx &c, int mx, int n, hipStream_t s);
 hipError_t launch_transfer(const Ctx &c, int mx, const TransferRec *plan, int n, hipStream_t s);
 // *cfl_dev = max(*cfl_dev, device state's maximum, max of the n slots)
-hipError_t launch_export_cfl(DevState *state, const double *cflp, int n, double *cfl_dev, hipStream_t s);
+hipError_t launch_export_cfl(DevState *state, const unsigned long long *cflp, int n, double *cfl_dev, hipStream_t s);
 hipError_t launch_adjoint(const Ctx &c, int mx, int first, int count, double t, double dt,
                           const int32_t *leaf_of_slot, const double *lam_in, double *abar, hipStream_t s);
 hipError_t launch_adjoint_gather(const Ctx &c, int mx, int first, int count, const int32_t *leaf_of_slot,

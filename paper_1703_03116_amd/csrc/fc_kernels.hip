@@ -127,9 +127,8 @@ __device__ void coarse_cell(const Ctx &c, const View &w, int p, int i, int j, do
 // frame (no wall folding): copy, eq. ghost_coarse average or eq. ghost_fine
 // interpolation, as the region's neighbour record says.
 template <int MX, int F>
-__device__ __forceinline__ void ghost_cell_r(const Ctx &c, const View &w, int p, int l, int i, int j, int r,
-                                             double *v) {
-    const NbrRec rec = c.nbr[p * FC_NREC + r];
+__device__ __forceinline__ void ghost_cell_rec(const Ctx &c, const View &w, int l, int i, int j, const NbrRec rec,
+                                               double *v) {
     if (rec.type == NB_SAME) {
 #pragma unroll
         for (int f = 0; f < F; f++) v[f] = read_state<MX>(c, w, rec.id, l, i - rec.ox, j - rec.oy, f);
@@ -164,6 +163,12 @@ __device__ __forceinline__ void ghost_cell_r(const Ctx &c, const View &w, int p,
 #pragma unroll
         for (int f = 0; f < F; f++) v[f] = __builtin_nan("");
     }
+}
+
+template <int MX, int F>
+__device__ __forceinline__ void ghost_cell_r(const Ctx &c, const View &w, int p, int l, int i, int j, int r,
+                                             double *v) {
+    ghost_cell_rec<MX, F>(c, w, l, i, j, c.nbr[p * FC_NREC + r], v);
 }
 
 // Ghost value of patch p at local (i, j): the result of Algorithm 1.
@@ -261,7 +266,7 @@ struct ScalarSmem {
     double q[N * NP];                 // the tile; after the sweeps, the new interior (staged for the store)
     double tx[(MX + 2) * S];          // TX(i, j) = A+*_{i-1/2} + A-*_{i+1/2} at [(j+1) S + i], rows -1..MX
     double ty[(MX + 2) * S];          // TY(i, j) at [(i+1) S + j], columns -1..MX
-    double dcy[MX * S];               // C_{j+1/2} - C_{j-1/2} of the y-edges at [i S + j]
+    double part[MX * S];              // one direction's partial update of a cell, at [j S + i]
     double ux[MX + 1], uy[MX + 2];    // u(e, j) = ux[e] * uy[j+1]
     double vy[MX + 1], vx[MX + 2];    // v(i, e) = vy[e] * vx[i+1]
     double red[16];
@@ -299,13 +304,24 @@ __device__ __forceinline__ double correction(double W, double Wu, double as, dou
 }
 
 // velocity factors of a patch into LDS
+// at the mid-step time t + dt/2, with t = *tdev + t when tdev is given
+// (threads k0 .. k0+MX+1 do the work; blockDim >= k0 + MX + 2)
 template <int MX>
-__device__ void load_velocity(const Ctx &c, ScalarSmem<MX> &s, int l, int gx, int gy, double tm) {
+__device__ void load_velocity(const Ctx &c, ScalarSmem<MX> &s, int l, int gx, int gy, double t, double dt,
+                              const double *tdev, int k0) {
     const int n = MX << l;
+    const int k = (int)threadIdx.x - k0;
     if (c.velocity == 2) {
-        // blockDim >= 64 > MX + 2: the first wave alone evaluates c(t)
-        const int k = threadIdx.x;
-        if (k < MX + 2) {
+        if (k >= 0 && k < MX + 2) {
+            if (tdev) {
+                // a per-lane zero the compiler cannot see through keeps this a
+                // vector load: a scalar one would be waited on together with
+                // the kernel arguments, ahead of the first tile loads
+                int zero;
+                asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
+                t = tdev[zero] + t;
+            }
+            const double tm = t + 0.5 * dt;
             const double ct = cos(M_PI * (tm * c.vel_invT));
             const double *vt = c.vt[l];
             const double *ex = vt + vt_ex(n, MB), *cxv = vt + vt_cx(n, MB);
@@ -314,20 +330,19 @@ __device__ void load_velocity(const Ctx &c, ScalarSmem<MX> &s, int l, int gx, in
             s.uy[k] = cyv[gy + k - 1] * ct;
             s.vx[k] = -(cxv[gx + k - 1] * ct);
         }
-    } else {
-        for (int k = threadIdx.x; k < MX + 2; k += blockDim.x) {
-            if (k <= MX) { s.ux[k] = c.vel_u; s.vy[k] = c.vel_v; }
-            s.uy[k] = 1.0;
-            s.vx[k] = 1.0;
-        }
+    } else if (k >= 0 && k < MX + 2) {
+        if (k <= MX) { s.ux[k] = c.vel_u; s.vy[k] = c.vel_v; }
+        s.uy[k] = 1.0;
+        s.vx[k] = 1.0;
     }
 }
 
 // One segment of one interior line: edges e0 .. e0+SEG (edge e lies between
 // cells e-1 and e of the line), cells e0 .. e0+SEG-1.  DIR 0: x-edges of row
-// `line`; DIR 1: y-edges of column `line`.  Writes TX (TY) of the cells; for
-// a row also R = Q - lam TX + lam/2 (C_{i+1/2} - C_{i-1/2}) (kept in
-// registers for the update), for a column the y differences of C.
+// `line`; DIR 1: y-edges of column `line`.  Writes TX (TY) of the cells and
+// returns the line's partial update of each cell in R:
+//   rows     Rx = Q - lam TX + lam/2 (C_{i+1/2} - C_{i-1/2}),
+//   columns  Ry = lam/2 (C_{j+1/2} - C_{j-1/2}) - lam TY.
 // amax: largest |velocity| over the edges.
 template <int MX, int SEG, int LIM, int DIR>
 __device__ __forceinline__ void sweep_segment(ScalarSmem<MX> &s, int line, int e0, double lam, double (&R)[SEG],
@@ -359,7 +374,7 @@ __device__ __forceinline__ void sweep_segment(ScalarSmem<MX> &s, int line, int e
                 R[k - 1] = q[k + 1] - lam * T + (0.5 * lam) * (C - cprev);
             } else {
                 s.ty[(line + 1) * S + cc] = T;
-                s.dcy[line * S + cc] = C - cprev;
+                R[k - 1] = (0.5 * lam) * (C - cprev) - lam * T;
             }
         }
         aprev = aps;
@@ -395,13 +410,15 @@ __device__ __forceinline__ void sweep_outer(ScalarSmem<MX> &s, int dir, int line
     }
 }
 
-// The update of the cells e0 .. e0+SEG-1 of interior row j from R and the
-// stored TX, TY, y-differences of C:
-//   Q_new = R - lam TY + lam/2 dCy + lam^2/2 ((TF_{i+1/2} - TF_{i-1/2}) + (TG_{j+1/2} - TG_{j-1/2}))
-// with TF(e) = u+ TY(e-1) + u- TY(e) on x-edges and TG likewise from TX.
+// Final update of a cell from the two partials and the transverse terms:
+//   Q_new = Rx + Ry + lam^2/2 ((TF_{i+1/2} - TF_{i-1/2}) + (TG_{j+1/2} - TG_{j-1/2}))
+// with TF(e) = u+ TY(e-1) + u- TY(e) on x-edges and TG(e) = v+ TX(e-1) +
+// v- TX(e) on y-edges.  Cells of the lower half of the patch are finished
+// row-wise by the x-items (Rx in registers, Ry from LDS), those of the upper
+// half column-wise by the y-items; both forms evaluate the same expression.
 // The result goes to the tile (staging for a coalesced store).
 template <int MX, int SEG>
-__device__ __forceinline__ void update_segment(ScalarSmem<MX> &s, int j, int e0, double lam, const double (&R)[SEG]) {
+__device__ __forceinline__ void update_row(ScalarSmem<MX> &s, int j, int e0, double lam, const double (&R)[SEG]) {
     constexpr int NP = ScalarSmem<MX>::NP, S = ScalarSmem<MX>::S;
     const double uyj = s.uy[j + 1], vyd = s.vy[j], vyu = s.vy[j + 1];
     double ty[SEG + 2];
@@ -413,7 +430,7 @@ __device__ __forceinline__ void update_segment(ScalarSmem<MX> &s, int j, int e0,
         const double u = s.ux[e0 + k] * uyj;
         tf[k] = posp(u) * ty[k] + negp(u) * ty[k + 1];
     }
-    const double hl = 0.5 * lam, hl2 = 0.5 * lam * lam;
+    const double hl2 = 0.5 * lam * lam;
 #pragma unroll
     for (int k = 0; k < SEG; k++) {
         const int cc = e0 + k;
@@ -422,8 +439,33 @@ __device__ __forceinline__ void update_segment(ScalarSmem<MX> &s, int j, int e0,
         const double vd = vyd * vxc, vu = vyu * vxc;
         const double tgd = posp(vd) * txd + negp(vd) * txc;
         const double tgu = posp(vu) * txc + negp(vu) * txu;
-        const double dcy = s.dcy[cc * S + j];
-        s.q[(j + MB) * NP + cc + MB] = R[k] - lam * ty[k + 1] + hl * dcy + hl2 * ((tf[k + 1] - tf[k]) + (tgu - tgd));
+        s.q[(j + MB) * NP + cc + MB] = (R[k] + s.part[j * S + cc]) + hl2 * ((tf[k + 1] - tf[k]) + (tgu - tgd));
+    }
+}
+
+template <int MX, int SEG>
+__device__ __forceinline__ void update_col(ScalarSmem<MX> &s, int i, int e0, double lam, const double (&R)[SEG]) {
+    constexpr int NP = ScalarSmem<MX>::NP, S = ScalarSmem<MX>::S;
+    const double vxi = s.vx[i + 1], uxl = s.ux[i], uxr = s.ux[i + 1];
+    double tx[SEG + 2];
+#pragma unroll
+    for (int k = 0; k < SEG + 2; k++) tx[k] = s.tx[(e0 + k) * S + i];  // TX(i, e0 - 1 + k)
+    double tg[SEG + 1];
+#pragma unroll
+    for (int k = 0; k <= SEG; k++) {
+        const double v = s.vy[e0 + k] * vxi;
+        tg[k] = posp(v) * tx[k] + negp(v) * tx[k + 1];
+    }
+    const double hl2 = 0.5 * lam * lam;
+#pragma unroll
+    for (int k = 0; k < SEG; k++) {
+        const int cc = e0 + k;
+        const double tyl = s.ty[i * S + cc], tyc = s.ty[(i + 1) * S + cc], tyr = s.ty[(i + 2) * S + cc];
+        const double uyc = s.uy[cc + 1];
+        const double ul = uxl * uyc, ur = uxr * uyc;
+        const double tfl = posp(ul) * tyl + negp(ul) * tyc;
+        const double tfr = posp(ur) * tyc + negp(ur) * tyr;
+        s.q[(cc + MB) * NP + i + MB] = (s.part[cc * S + i] + R[k]) + hl2 * ((tfr - tfl) + (tg[k + 1] - tg[k]));
     }
 }
 
@@ -434,68 +476,119 @@ __device__ __forceinline__ void update_segment(ScalarSmem<MX> &s, int j, int e0,
 //   rows keep their partial sums in registers and, after the barrier, finish
 //   the update of their cells.
 template <int MX, int NT, int LIM, bool FUSED>
-__device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, ScalarSmem<MX> &s, int p, double t, double dt,
-                                   double &cfl) {
+__device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, ScalarSmem<MX> &s, int p, int lev,
+                                                   double t, double dt, const double *tdev, double &cfl) {
     constexpr int N = MX + 2 * MB, NP = ScalarSmem<MX>::NP;
-    constexpr int SEG = scalar_seg<MX, NT>(), NSEG = MX / SEG, NI = MX * NSEG, NTOT = 2 * NI + 4 * NSEG;
-    static_assert(NI <= NT, "the x-items of the interior rows must fit one pass");
-    const PatchInfo P = c.info[p];
-    const int l = P.level;
+    // Work split (items = line segments): threads [0, NI) sweep the interior
+    // rows, [NI, 2 NI) the interior columns; each half of either set covers
+    // one half of the patch.  The lower-half rows and the upper-half columns
+    // finish the update (the other two store their partials); the outer-line
+    // items, the odd ghost cells and c(t) go to threads with less to do.
+    // With one workgroup's wave k on SIMD k, this keeps the SIMDs balanced.
+    constexpr int SEG = scalar_seg<MX, NT>(), NSEG = MX / SEG, NI = MX * NSEG, HI = NI / 2;
+    constexpr int GT0 = (NT - 2 * NI >= 4 * NSEG) ? 2 * NI : HI;  // first thread of the outer-line items
+    static_assert(2 * NI <= NT && NSEG % 2 == 0, "interior items must fit one pass, in two halves");
+    static_assert(NI + MX + 2 <= NT, "velocity factors are loaded by threads NI .. NI+MX+1");
+    const int tid = threadIdx.x;
+    // The loads that depend only on the slot (interior, neighbour records)
+    // are issued before the patch record arrives, so that the ghost values
+    // wait on one memory round trip after them, not two.
+    const int l = lev >= 0 ? lev : c.info[p].level;
     const double lam = dt * (double)(MX << l);  // dt / h, exact: h = 1 / (MX 2^l)
     const double *in = buf_of(c, w, l);
     double *out = other_of(c, w, l);
     const size_t base = (size_t)p * N * N;
-    load_velocity<MX>(c, s, l, P.ix * MX, P.iy * MX, t + 0.5 * dt);
     // rows are 16-byte aligned (N and MB even): two cells per load
     if (!FUSED) {
-        for (int k = threadIdx.x; k < N * N / 2; k += NT) {
+        const PatchInfo P = c.info[p];
+        load_velocity<MX>(c, s, l, P.ix * MX, P.iy * MX, t, dt, tdev, NI);
+        for (int k = tid; k < N * N / 2; k += NT) {
             const int i = 2 * (k % (N / 2)), j = k / (N / 2);
             const double2 v = *reinterpret_cast<const double2 *>(&in[base + j * N + i]);
             s.q[j * NP + i] = v.x;
             s.q[j * NP + i + 1] = v.y;
         }
     } else {
-        for (int k = threadIdx.x; k < MX * MX / 2; k += NT) {
-            const int i = 2 * (k % (MX / 2)), j = k / (MX / 2);
-            const double2 v = *reinterpret_cast<const double2 *>(&in[base + (j + MB) * N + i + MB]);
-            s.q[(j + MB) * NP + i + MB] = v.x;
-            s.q[(j + MB) * NP + i + MB + 1] = v.y;
-        }
         constexpr int NG = N * N - MX * MX;
+        constexpr int NV = (MX * MX / 2 + NT - 1) / NT, NGH = (NG + NT - 1) / NT;
+        double2 iv[NV];
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            const int k = tid + v * NT, i = 2 * (k % (MX / 2)), j = k / (MX / 2);
+            if (k < MX * MX / 2) iv[v] = *reinterpret_cast<const double2 *>(&in[base + (j + MB) * N + i + MB]);
+        }
+        const int g0 = (tid + NT - NI) % NT;  // the odd ghost cells go to a lightly loaded wave
+        int gi[NGH], gj[NGH];
+        NbrRec gr[NGH];
+#pragma unroll
+        for (int v = 0; v < NGH; v++) {
+            int r = 0;
+            gi[v] = gj[v] = 0;
+            if (g0 + v * NT < NG) {
+                ghost_region_index<MX>(g0 + v * NT, gi[v], gj[v], r);
+                gr[v] = c.nbr[p * FC_NREC + r];
+            }
+        }
+        const PatchInfo P = c.info[p];
+        load_velocity<MX>(c, s, l, P.ix * MX, P.iy * MX, t, dt, tdev, NI);
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            const int k = tid + v * NT, i = 2 * (k % (MX / 2)), j = k / (MX / 2);
+            if (k < MX * MX / 2) {
+                s.q[(j + MB) * NP + i + MB] = iv[v].x;
+                s.q[(j + MB) * NP + i + MB + 1] = iv[v].y;
+            }
+        }
         if (P.walls == 0) {
-            for (int g = threadIdx.x; g < NG; g += NT) {
-                int i, j, r;
-                ghost_region_index<MX>(g, i, j, r);
-                double v[1];
-                ghost_cell_r<MX, 1>(c, w, p, l, i, j, r, v);
-                s.q[(j + MB) * NP + i + MB] = v[0];
+#pragma unroll
+            for (int v = 0; v < NGH; v++) {
+                if (g0 + v * NT < NG) {
+                    double val[1];
+                    ghost_cell_rec<MX, 1>(c, w, l, gi[v], gj[v], gr[v], val);
+                    s.q[(gj[v] + MB) * NP + gi[v] + MB] = val[0];
+                }
             }
         } else {
-            for (int g = threadIdx.x; g < NG; g += NT) {
+            for (int g = g0; g < NG; g += NT) {
                 int i, j;
                 ghost_index<MX>(g, i, j);
-                double v[1];
-                ghost_cell<MX, 1>(c, w, p, i, j, v);
-                s.q[(j + MB) * NP + i + MB] = v[0];
+                double val[1];
+                ghost_cell<MX, 1>(c, w, p, i, j, val);
+                s.q[(j + MB) * NP + i + MB] = val[0];
             }
         }
     }
     __syncthreads();
+    constexpr int S = ScalarSmem<MX>::S;
     double R[SEG];
     double amax = 0.0;
-    for (int item = threadIdx.x; item < NTOT; item += NT) {
-        if (item < NI) {
-            sweep_segment<MX, SEG, LIM, 0>(s, item % MX, (item / MX) * SEG, lam, R, amax);
-        } else if (item < 2 * NI) {
-            const int k = item - NI;
-            sweep_segment<MX, SEG, LIM, 1>(s, k % MX, (k / MX) * SEG, lam, R, amax);
-        } else {  // rows -1, MX and columns -1, MX: TX, TY only (transverse terms at the patch edge)
-            const int k = item - 2 * NI, g = k / NSEG, e0 = (k % NSEG) * SEG;
-            sweep_outer<MX, SEG, LIM>(s, g >> 1, (g & 1) ? MX : -1, e0, lam);
+    int line = 0, e0 = 0;
+    const bool xs = tid < NI, ys = !xs && tid < 2 * NI;
+    const int half = (xs ? tid : tid - NI) / HI, r = (xs ? tid : tid - NI) % HI;
+    if (xs) {
+        line = half * (MX / 2) + r % (MX / 2);
+        e0 = (r / (MX / 2)) * SEG;
+        sweep_segment<MX, SEG, LIM, 0>(s, line, e0, lam, R, amax);
+        if (half == 1) {
+#pragma unroll
+            for (int k = 0; k < SEG; k++) s.part[line * S + e0 + k] = R[k];
+        }
+    } else if (ys) {
+        line = r % MX;
+        e0 = (half * (NSEG / 2) + r / MX) * SEG;
+        sweep_segment<MX, SEG, LIM, 1>(s, line, e0, lam, R, amax);
+        if (half == 0) {
+#pragma unroll
+            for (int k = 0; k < SEG; k++) s.part[(e0 + k) * S + line] = R[k];
         }
     }
+    if (tid >= GT0 && tid < GT0 + 4 * NSEG) {  // rows -1, MX and columns -1, MX: TX, TY only
+        const int k = tid - GT0, g = k / NSEG;
+        sweep_outer<MX, SEG, LIM>(s, g >> 1, (g & 1) ? MX : -1, (k % NSEG) * SEG, lam);
+    }
     __syncthreads();
-    if ((int)threadIdx.x < NI) update_segment<MX, SEG>(s, threadIdx.x % MX, (threadIdx.x / MX) * SEG, lam, R);
+    if (xs && half == 0) update_row<MX, SEG>(s, line, e0, lam, R);
+    else if (ys && half == 1) update_col<MX, SEG>(s, line, e0, lam, R);
     __syncthreads();
     for (int k = threadIdx.x; k < MX * MX / 2; k += NT) {
         const int i = 2 * (k % (MX / 2)), j = k / (MX / 2);
@@ -506,13 +599,15 @@ __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, 
 }
 
 template <int MX, int NT, bool FUSED>
-__device__ __forceinline__ void advance_scalar_patch(const Ctx &c, const View &w, ScalarSmem<MX> &s, int p, double t, double dt,
-                                     double &cfl) {
+// lev: the patch's level when the caller knows it (a level-step), else -1;
+// tdev: if given, the step starts at *tdev + t
+__device__ __forceinline__ void advance_scalar_patch(const Ctx &c, const View &w, ScalarSmem<MX> &s, int p, int lev,
+                                                     double t, double dt, double &cfl, const double *tdev = nullptr) {
     switch (c.lim) {
-        case 1: advance_scalar_lim<MX, NT, 1, FUSED>(c, w, s, p, t, dt, cfl); break;
-        case 2: advance_scalar_lim<MX, NT, 2, FUSED>(c, w, s, p, t, dt, cfl); break;
-        case 3: advance_scalar_lim<MX, NT, 3, FUSED>(c, w, s, p, t, dt, cfl); break;
-        default: advance_scalar_lim<MX, NT, 0, FUSED>(c, w, s, p, t, dt, cfl); break;
+        case 1: advance_scalar_lim<MX, NT, 1, FUSED>(c, w, s, p, lev, t, dt, tdev, cfl); break;
+        case 2: advance_scalar_lim<MX, NT, 2, FUSED>(c, w, s, p, lev, t, dt, tdev, cfl); break;
+        case 3: advance_scalar_lim<MX, NT, 3, FUSED>(c, w, s, p, lev, t, dt, tdev, cfl); break;
+        default: advance_scalar_lim<MX, NT, 0, FUSED>(c, w, s, p, lev, t, dt, tdev, cfl); break;
     }
 }
 
@@ -533,10 +628,16 @@ __device__ void reduce_cfl(double v, double *red, unsigned long long *cfl_bits) 
     }
 }
 
-// block-wide max, then slot = max(slot, value) by thread 0 (the workgroup
-// owns the slot of its patch for the whole launch)
+// The workgroup owns its patch's slot for the whole launch: thread 0 reads
+// the slot when the workgroup starts (the latency hides behind the step) and
+// stores max(old, block max) at the end -- a plain store, where a device-wide
+// atomic would add a round trip to memory before the workgroup can retire.
+__device__ __forceinline__ double cfl_slot_old(const unsigned long long *slot) {
+    return (slot && threadIdx.x == 0) ? __longlong_as_double((long long)*slot) : 0.0;
+}
+
 template <int NT>
-__device__ void reduce_cfl_slot(double v, double *red, double *slot) {
+__device__ void reduce_cfl_slot(double v, double *red, unsigned long long *slot, double old) {
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
     const int w = threadIdx.x >> 6;
     __syncthreads();
@@ -545,7 +646,7 @@ __device__ void reduce_cfl_slot(double v, double *red, double *slot) {
     if (threadIdx.x == 0 && slot) {
         double m = red[0];
         for (int k = 1; k < NT / 64; k++) m = fmax(m, red[k]);
-        *slot = fmax(*slot, m);
+        *slot = (unsigned long long)__double_as_longlong(fmax(old, m));
     }
 }
 
@@ -556,12 +657,15 @@ template <int MX, int NT, int EQ>
 constexpr int min_waves() { return (EQ == 0 && MX == 32) ? NT / 64 : 1; }
 
 template <int MX, int NT, bool FUSED>
-__global__ void __launch_bounds__(NT, (min_waves<MX, NT, 0>())) advance_scalar_kernel(Ctx c, int first, int count, double t, double dt) {
+__global__ void __launch_bounds__(NT, (min_waves<MX, NT, 0>())) advance_scalar_kernel(Ctx c, int first, int count, int level, double t,
+                                                                                     double dt) {
     __shared__ ScalarSmem<MX> s;
     const int p = first + xcd_remap(blockIdx.x, count);
+    unsigned long long *slot = c.cflp ? c.cflp + p : nullptr;
+    const double old = cfl_slot_old(slot);
     double cfl = 0.0;
-    advance_scalar_patch<MX, NT, FUSED>(c, view_of(c), s, p, t, dt, cfl);
-    reduce_cfl_slot<NT>(cfl, s.red, c.cflp ? c.cflp + p : nullptr);
+    advance_scalar_patch<MX, NT, FUSED>(c, view_of(c), s, p, level, t, dt, cfl);
+    reduce_cfl_slot<NT>(cfl, s.red, slot, old);
 }
 
 // ------------------------------------------------------------------------
@@ -812,9 +916,11 @@ template <int MX, int NT, bool FUSED>
 __global__ void __launch_bounds__(NT) advance_swe_kernel(Ctx c, int first, int count, double dt) {
     __shared__ SweSmem<MX> s;
     const int p = first + xcd_remap(blockIdx.x, count);
+    unsigned long long *slot = c.cflp ? c.cflp + p : nullptr;
+    const double old = cfl_slot_old(slot);
     double cfl = 0.0;
     advance_swe_patch<MX, NT, FUSED>(c, view_of(c), s, p, dt, cfl);
-    reduce_cfl_slot<NT>(cfl, s.red, c.cflp ? c.cflp + p : nullptr);
+    reduce_cfl_slot<NT>(cfl, s.red, slot, old);
 }
 
 // ------------------------------------------------------------------------
@@ -1103,7 +1209,7 @@ __global__ void __launch_bounds__(NT) persistent_kernel(Ctx c, const SchedEntry 
             const double t = t0 + e.off * dtc, dt = e.scale * dtc;
             const int c0 = (int)((long long)count * x / NXC), c1 = (int)((long long)count * (x + 1) / NXC);
             for (int pi = c0 + r; pi < c1; pi += nbx) {
-                if constexpr (EQ == 0) advance_scalar_patch<MX, NT, true>(c, w, s, first + pi, t, dt, cfl);
+                if constexpr (EQ == 0) advance_scalar_patch<MX, NT, true>(c, w, s, first + pi, e.level, t, dt, cfl);
                 else advance_swe_patch<MX, NT, true>(c, w, s, first + pi, dt, cfl);
                 __syncthreads();
             }
@@ -1126,29 +1232,28 @@ __global__ void __launch_bounds__(NT) persistent_kernel(Ctx c, const SchedEntry 
 // replayed for every chunk of coarse steps (kernel boundaries provide the
 // ordering and coherence between level-steps)
 // ------------------------------------------------------------------------
-// The node's constants (level range, time offset and scale, time fraction)
-// are baked in at capture; the graph is recaptured whenever a regrid changes
-// the level populations.  Only the time, step and parities come from device
-// memory (independent loads).
+// The node's constants (level range, buffer parities, coarse step, time
+// offset and scale, time fraction) are baked in at capture; the graph is
+// recaptured when a regrid changes the level populations or the coarse step
+// changes.  Only the start time of the coarse step comes from device memory,
+// read where the velocity factors need it.
 struct StepArgs {
     int32_t level, first, count, cidx;
-    uint32_t flip, pad;
-    double off, scale, alpha;
+    uint32_t mask, pad;
+    double off, scale, alpha, dtc;
 };
 
 template <int MX, int NT, int EQ>
 __global__ void __launch_bounds__(NT, (min_waves<MX, NT, EQ>())) level_step_kernel(Ctx c, StepArgs a, DevState *st) {
     __shared__ typename SmemOf<MX, EQ>::type s;
-    const double t0 = st->ts[a.cidx];
-    const double dtc = st->dt_coarse;
-    const uint32_t cm = st->curmask;
-    const View w{cm ^ a.flip, a.level < 0 ? -1 : a.level - 1, a.level < 0 ? 1.0 : a.alpha};
-    const double t = t0 + a.off * dtc, dt = a.scale * dtc;
+    const View w{a.mask, a.level < 0 ? -1 : a.level - 1, a.level < 0 ? 1.0 : a.alpha};
+    const double dt = a.scale * a.dtc;
     double cfl = 0.0;
     const int p = a.first + xcd_remap(blockIdx.x, a.count);
-    if constexpr (EQ == 0) advance_scalar_patch<MX, NT, true>(c, w, s, p, t, dt, cfl);
+    const double old = cfl_slot_old(c.cflp + p);
+    if constexpr (EQ == 0) advance_scalar_patch<MX, NT, true>(c, w, s, p, a.level, a.off * a.dtc, dt, cfl, &st->ts[a.cidx]);
     else advance_swe_patch<MX, NT, true>(c, w, s, p, dt, cfl);
-    reduce_cfl_slot<NT>(cfl, s.red, c.cflp + p);
+    reduce_cfl_slot<NT>(cfl, s.red, c.cflp + p, old);
 }
 
 __device__ void fill_times(DevState *st) {
@@ -1191,8 +1296,8 @@ __global__ void init_tables_kernel(int n, int periodic_x, int periodic_y, double
     }
 }
 
-__global__ void set_state_kernel(DevState *st, double t, double dt, uint32_t curmask, int reset_cfl, double *cflp,
-                                 int n) {
+__global__ void set_state_kernel(DevState *st, double t, double dt, uint32_t curmask, int reset_cfl,
+                                 unsigned long long *cflp, int n) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k == 0) {
         st->t = t;
@@ -1202,18 +1307,19 @@ __global__ void set_state_kernel(DevState *st, double t, double dt, uint32_t cur
         if (reset_cfl) st->cfl_bits = 0ull;
         fill_times(st);
     }
-    if (reset_cfl && cflp && k < n) cflp[k] = 0.0;
+    if (reset_cfl && cflp && k < n) cflp[k] = 0ull;
 }
 
-__global__ void zero_cfl_kernel(double *cflp, int n) {
+__global__ void zero_cfl_kernel(unsigned long long *cflp, int n) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n) cflp[k] = 0.0;
+    if (k < n) cflp[k] = 0ull;
 }
 
-__global__ void __launch_bounds__(256) export_cfl_kernel(const DevState *st, const double *cflp, int n, double *cfl) {
+__global__ void __launch_bounds__(256) export_cfl_kernel(const DevState *st, const unsigned long long *cflp, int n,
+                                                            double *cfl) {
     __shared__ double red[4];
     double v = 0.0;
-    for (int k = threadIdx.x; k < n; k += 256) v = fmax(v, cflp[k]);
+    for (int k = threadIdx.x; k < n; k += 256) v = fmax(v, __longlong_as_double((long long)cflp[k]));
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
@@ -1339,20 +1445,21 @@ hipError_t launch_init_tables(int level, int mx, int periodic_x, int periodic_y,
     return hipGetLastError();
 }
 
-hipError_t launch_set_state(DevState *st, double t, double dt, uint32_t curmask, int reset_cfl, double *cflp, int n,
-                            hipStream_t s) {
+hipError_t launch_set_state(DevState *st, double t, double dt, uint32_t curmask, int reset_cfl, unsigned long long *cflp,
+                            int n, hipStream_t s) {
     const int nb = (n > 0 ? n : 1) + 255;
     hipLaunchKernelGGL(set_state_kernel, dim3(nb / 256), dim3(256), 0, s, st, t, dt, curmask, reset_cfl, cflp, n);
     return hipGetLastError();
 }
 
-hipError_t launch_zero_cfl(double *cflp, int n, hipStream_t s) {
+hipError_t launch_zero_cfl(unsigned long long *cflp, int n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(zero_cfl_kernel, dim3((n + 255) / 256), dim3(256), 0, s, cflp, n);
     return hipGetLastError();
 }
 
-hipError_t launch_export_cfl(DevState *state, const double *cflp, int n, double *cfl_dev, hipStream_t s) {
+hipError_t launch_export_cfl(DevState *state, const unsigned long long *cflp, int n, double *cfl_dev,
+                             hipStream_t s) {
     hipLaunchKernelGGL(export_cfl_kernel, dim3(1), dim3(256), 0, s, state, cflp, n, cfl_dev);
     return hipGetLastError();
 }
@@ -1375,9 +1482,10 @@ hipError_t launch_fill(const Ctx &c, int mx, int first, int count, hipStream_t s
 }
 
 template <int MX, int NT>
-static hipError_t adv_scalar(const Ctx &c, int first, int count, double t, double dt, int fused, hipStream_t s) {
-    if (fused) hipLaunchKernelGGL((advance_scalar_kernel<MX, NT, true>), dim3(count), dim3(NT), 0, s, c, first, count, t, dt);
-    else hipLaunchKernelGGL((advance_scalar_kernel<MX, NT, false>), dim3(count), dim3(NT), 0, s, c, first, count, t, dt);
+static hipError_t adv_scalar(const Ctx &c, int first, int count, int level, double t, double dt, int fused,
+                             hipStream_t s) {
+    if (fused) hipLaunchKernelGGL((advance_scalar_kernel<MX, NT, true>), dim3(count), dim3(NT), 0, s, c, first, count, level, t, dt);
+    else hipLaunchKernelGGL((advance_scalar_kernel<MX, NT, false>), dim3(count), dim3(NT), 0, s, c, first, count, level, t, dt);
     return hipGetLastError();
 }
 
@@ -1390,10 +1498,9 @@ static hipError_t adv_swe(const Ctx &c, int first, int count, double dt, int fus
 
 hipError_t launch_advance(const Ctx &c, LaunchCfg lc, int level, int first, int count, double t, double dt,
                           int fused, hipStream_t s) {
-    (void)level;
     if (count <= 0) return hipSuccess;
     if (c.eq == 0) {
-#define ADV(MXV, NTV) if (lc.mx == MXV && lc.nt == NTV) return adv_scalar<MXV, NTV>(c, first, count, t, dt, fused, s);
+#define ADV(MXV, NTV) if (lc.mx == MXV && lc.nt == NTV) return adv_scalar<MXV, NTV>(c, first, count, level, t, dt, fused, s);
         ADV(8, 64) ADV(8, 128) ADV(16, 64) ADV(16, 128) ADV(16, 256) ADV(32, 128) ADV(32, 256) ADV(32, 512)
 #undef ADV
     } else {
@@ -1457,11 +1564,11 @@ static const void *level_step_select(LaunchCfg lc, int eq) {
 }
 
 hipError_t launch_level_step(const Ctx &c, LaunchCfg lc, const SchedEntry &e, int first, int count, int cidx,
-                             uint32_t flip, DevState *st, hipStream_t s) {
+                             uint32_t mask, double dt_coarse, DevState *st, hipStream_t s) {
     const void *fn = level_step_select(lc, c.eq);
     if (!fn) return hipErrorInvalidValue;
     Ctx cc = c;
-    StepArgs a{e.level, first, count, cidx, flip, 0u, e.off, e.scale, e.alpha};
+    StepArgs a{e.level, first, count, cidx, mask, 0u, e.off, e.scale, e.alpha, dt_coarse};
     void *args[] = {&cc, &a, &st};
     return hipLaunchKernel(fn, dim3(count > 0 ? count : 1), dim3(lc.nt), args, 0, s);
 }

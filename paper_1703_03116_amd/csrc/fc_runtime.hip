@@ -148,9 +148,14 @@ struct fc_patchstore {
     int pgrid = 0;
     int pgrid_user = 0;  // grid override of the persistent kernel (0: occupancy)
     // captured graphs: [0]/[1] persistent kernel for 1 / `chunk` coarse steps,
-    // [2]/[3] level-step kernels for 1 / `chunk` coarse steps
-    hipGraphExec_t gexec[4] = {nullptr, nullptr, nullptr, nullptr};
-    hipGraph_t graph[4] = {nullptr, nullptr, nullptr, nullptr};
+    // [2]/[3] level-step kernels for 1 / `chunk` coarse steps, [4] for 1 coarse
+    // step from the other buffer parity.  Level-step graphs carry the buffer
+    // parities as constants: gmask = the parities they were captured from.
+    static constexpr int NGRAPH = 5;
+    hipGraphExec_t gexec[NGRAPH] = {};
+    hipGraph_t graph[NGRAPH] = {};
+    uint32_t gmask[NGRAPH] = {};
+    double gdt[NGRAPH] = {};  // coarse step a level-step graph was captured for
     int chunk = 0;
     hipStream_t cap_stream = nullptr;  // private stream the graph is captured on
     int gnt = 0;
@@ -262,7 +267,7 @@ void layout_workspace(fc_patchstore *ps) {
     ps->ws_bytes = o;
 }
 
-double *cflp(const fc_patchstore *ps) { return (double *)(ps->ws + ps->off_cfl); }
+unsigned long long *cflp(const fc_patchstore *ps) { return (unsigned long long *)(ps->ws + ps->off_cfl); }
 
 Ctx make_ctx(const fc_patchstore *ps) {
     Ctx c;
@@ -357,13 +362,15 @@ fc_status advance_one(fc_patchstore *ps, int level, double t, double dt, int fus
     return FC_OK;
 }
 
+void drop_slot(fc_patchstore *ps, int k) {
+    if (ps->gexec[k]) (void)hipGraphExecDestroy(ps->gexec[k]);
+    if (ps->graph[k]) (void)hipGraphDestroy(ps->graph[k]);
+    ps->gexec[k] = nullptr;
+    ps->graph[k] = nullptr;
+}
+
 void drop_graph(fc_patchstore *ps) {
-    for (int k = 0; k < 4; k++) {
-        if (ps->gexec[k]) (void)hipGraphExecDestroy(ps->gexec[k]);
-        if (ps->graph[k]) (void)hipGraphDestroy(ps->graph[k]);
-        ps->gexec[k] = nullptr;
-        ps->graph[k] = nullptr;
-    }
+    for (int k = 0; k < fc_patchstore::NGRAPH; k++) drop_slot(ps, k);
 }
 
 // Capture one persistent launch of `ncoarse` coarse steps.  The kernel reads
@@ -391,11 +398,11 @@ fc_status capture(fc_patchstore *ps, int which, int ncoarse, int grid) {
 }
 
 
-// Capture `ncoarse` coarse steps as one kernel per level-step plus a final
-// node that advances the device time and parities.  Every schedule entry gets
-// a node (grid-stride over the level's current patch count), so the graph
-// stays valid for any leaf set with the same level range.
-fc_status capture_levels(fc_patchstore *ps, int which, int ncoarse) {
+// Capture `ncoarse` coarse steps, starting from buffer parities `mask`, as
+// one kernel per level-step (one workgroup per patch of the level, parities
+// and level range baked in) plus a final node that advances the device time
+// and parities.  A regrid drops the graph.
+fc_status capture_levels(fc_patchstore *ps, int which, int ncoarse, uint32_t mask, double dtc) {
     if (!ps->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ps->cap_stream, hipStreamNonBlocking));
     Ctx c = make_ctx(ps);
     uint32_t allmask = 0;
@@ -410,8 +417,8 @@ fc_status capture_levels(fc_patchstore *ps, int which, int ncoarse) {
             const SchedEntry &en = ps->sched[k];
             const int first = en.level < 0 ? 0 : ps->lr.start[en.level];
             const int cnt = en.level < 0 ? nall : ps->lr.count[en.level];
-            if (cnt > 0) e = launch_level_step(c, LaunchCfg{ps->mx, ps->nt}, en, first, cnt, cs, flip, dstate(ps),
-                                               ps->cap_stream);
+            if (cnt > 0) e = launch_level_step(c, LaunchCfg{ps->mx, ps->nt}, en, first, cnt, cs, mask ^ flip, dtc,
+                                               dstate(ps), ps->cap_stream);
             flip ^= en.level < 0 ? allmask : (1u << en.level);
         }
     if (e == hipSuccess) e = launch_finish_chunk(dstate(ps), ncoarse, flip, ps->cap_stream);
@@ -423,6 +430,8 @@ fc_status capture_levels(fc_patchstore *ps, int which, int ncoarse) {
         return fail(FC_ERR_HIP, "graph capture failed");
     }
     ps->graph[which] = g;
+    ps->gmask[which] = mask;
+    ps->gdt[which] = dtc;
     HIPCHK(hipGraphInstantiate(&ps->gexec[which], g, nullptr, nullptr, 0));
     return FC_OK;
 }
@@ -680,19 +689,35 @@ fc_status fc_advance_coarse_steps(fc_patchstore *ps, double dt_coarse, int32_t n
             ps->gnt = ps->nt;
             ps->chunk = kChunk;
         }
-        const int base = mode == FC_MODE_PERSISTENT_GRAPH ? 0 : 2;
-        auto cap = [&](int which, int ncoarse) -> fc_status {
-            return mode == FC_MODE_PERSISTENT_GRAPH ? capture(ps, which, ncoarse, grid)
-                                                    : capture_levels(ps, which, ncoarse);
+        uint32_t allm = 0, step_flip = 0;
+        for (int l = 0; l < FC_MAXLEV; l++)
+            if (ps->lr.count[l] > 0) allm |= 1u << l;
+        for (const SchedEntry &e : ps->sched) step_flip ^= e.level < 0 ? allm : (1u << e.level);
+        uint32_t mask = ps->curmask;  // parities at the start of the next replay
+        // graph slot for n coarse steps from the current parities (captured on demand)
+        auto slot = [&](int n, int &which) -> fc_status {
+            if (mode == FC_MODE_PERSISTENT_GRAPH) {
+                which = n == kChunk ? 1 : 0;
+                return ps->gexec[which] ? FC_OK : capture(ps, which, n, grid);
+            }
+            auto fits = [&](int k) { return ps->gexec[k] && ps->gmask[k] == mask && ps->gdt[k] == dt_coarse; };
+            if (n == kChunk) which = 3;
+            else which = fits(4) ? 4 : 2;
+            if (fits(which)) return FC_OK;
+            if (which == 2 && ps->gexec[2] && ps->gdt[2] == dt_coarse) which = 4;  // keep the other parity's graph
+            drop_slot(ps, which);
+            return capture_levels(ps, which, n, mask, dt_coarse);
         };
-        int k = 0;
-        if (nsteps >= kChunk) {
-            if (!ps->gexec[base + 1]) { r = cap(base + 1, kChunk); if (r != FC_OK) return r; }
-            for (; k + kChunk <= nsteps; k += kChunk) HIPCHK(hipGraphLaunch(ps->gexec[base + 1], s));
+        int k = 0, which = 0;
+        for (; k + kChunk <= nsteps; k += kChunk) {
+            if ((r = slot(kChunk, which)) != FC_OK) return r;
+            HIPCHK(hipGraphLaunch(ps->gexec[which], s));
+            if (kChunk & 1) mask ^= step_flip;
         }
-        if (k < nsteps) {
-            if (!ps->gexec[base]) { r = cap(base, 1); if (r != FC_OK) return r; }
-            for (; k < nsteps; k++) HIPCHK(hipGraphLaunch(ps->gexec[base], s));
+        for (; k < nsteps; k++) {
+            if ((r = slot(1, which)) != FC_OK) return r;
+            HIPCHK(hipGraphLaunch(ps->gexec[which], s));
+            mask ^= step_flip;
         }
     }
     // host mirror of the device bookkeeping
