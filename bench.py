@@ -5,10 +5,12 @@ Workload (default): uniform level 5 of the unit square, 1024 patches of
 deformational field, seeded sum of 8 Gaussians, 500 steps.  A "step" is
 one coarse step of the whole path: ghost fill + advance of every patch.
 
-The headline uses the fused form: one persistent kernel per coarse step
-(ghosts gathered on the fly, device-wide barriers between level-steps)
-replayed from a hipGraph.  The plain per-level launch form (a fill launch
-and an advance launch per level-step) is timed on the same workload and
+The headline uses the fused form: one advance kernel per level-step that
+gathers its ghost values on the fly from neighbour interiors (no fill
+launch), chunks of 50 coarse steps captured once and replayed from a
+hipGraph.  The plain per-level launch form (a fill launch and an advance
+launch per level-step), the same fused kernels launched from the host, and
+the persistent single-kernel form are timed on the same workload and
 reported beside it.
 
 Output: one JSON line on stdout.
@@ -43,16 +45,17 @@ def algorithmic_bytes(npatch, mx, F):
     return npatch * F * 8 * (N * N + mx * mx)
 
 
-def traffic_from_profiles(bytes_per_launch_alg):
-    """HBM bytes per launch from the committed counter summary, if it was
-    taken on the current kernel source."""
-    p = os.path.join(ROOT, "profiles", "traffic_persistent_swirl_l5.json")
+def traffic_from_profiles(nt):
+    """HBM bytes per launch of the level-step kernel from the committed
+    counter summary, if it was taken on the current kernel source and launch
+    variant."""
+    p = os.path.join(ROOT, "profiles", "traffic_level_step_swirl_l5.json")
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
     if d.get("kernel_sha") != kernel_hash():
         return None
-    return d.get("hbm_bytes_per_launch")
+    return d.get("hbm_bytes_per_launch", {}).get(str(nt))
 
 
 def cpu_baseline(w, budget_s=15.0):
@@ -86,6 +89,8 @@ def main():
                     choices=["swirl_uniform", "swirl_amr", "dam_break"],
                     help="swirl_uniform (default; --level sets its size), swirl_amr (levels 3-7, regrid "
                          "every 2 coarse steps), dam_break (shallow water, levels 2-6, 16x16)")
+    ap.add_argument("--threads", type=int, default=0,
+                    help="threads per patch of the advance kernels (0: autotune)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-level", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -116,7 +121,11 @@ def main():
     dt = w["dt_coarse"]
     cells_per_step = P * mx * mx
     ps = B.from_workload(w)
-    nt = ps.autotune()
+    if args.threads:
+        ps.set_variant(args.threads)
+        nt = args.threads
+    else:
+        nt = ps.autotune()
     stream = torch.cuda.current_stream()
 
     def timed(store, mode, k):
@@ -134,12 +143,14 @@ def main():
     sec = timed(ps, "graph", args.steps)
     ps.check()
     value = cells_per_step * args.steps / sec
-    # uniform level: one level-step kernel launch per coarse step; its average
-    # duration over the timed region (graph node gaps included)
+    # uniform level: one level-step kernel launch per coarse step (plus one
+    # small bookkeeping node per 50 steps); the average launch duration over
+    # the timed region, measured with events on the stream the graph runs on
+    # (node gaps included)
     avg_launch = sec / args.steps
     bpl = algorithmic_bytes(P, mx, F)
     achieved = bpl / avg_launch / 1e9
-    traffic = traffic_from_profiles(bpl)
+    traffic = traffic_from_profiles(nt)
 
     forms = {}
     if not args.no_per_level:

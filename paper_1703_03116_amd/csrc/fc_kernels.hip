@@ -477,7 +477,8 @@ __device__ __forceinline__ void update_col(ScalarSmem<MX> &s, int i, int e0, dou
 //   the update of their cells.
 template <int MX, int NT, int LIM, bool FUSED>
 __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, ScalarSmem<MX> &s, int p, int lev,
-                                                   double t, double dt, const double *tdev, double &cfl) {
+                                                   double t, double dt, const double *tdev,
+                                                   const unsigned long long *slot, double &cfl) {
     constexpr int N = MX + 2 * MB, NP = ScalarSmem<MX>::NP;
     // Work split (items = line segments): threads [0, NI) sweep the interior
     // rows, [NI, 2 NI) the interior columns; each half of either set covers
@@ -508,6 +509,7 @@ __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, 
             s.q[j * NP + i] = v.x;
             s.q[j * NP + i + 1] = v.y;
         }
+        if (slot && tid == 0) s.red[15] = __longlong_as_double((long long)*slot);
     } else {
         constexpr int NG = N * N - MX * MX;
         constexpr int NV = (MX * MX / 2 + NT - 1) / NT, NGH = (NG + NT - 1) / NT;
@@ -529,8 +531,12 @@ __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, 
                 gr[v] = c.nbr[p * FC_NREC + r];
             }
         }
+        // the CFL slot's old value (read by the workgroup's last thread, parked
+        // in LDS so that no register holds it across the step)
+        const double sold = (slot && tid == NT - 1) ? __longlong_as_double((long long)*slot) : 0.0;
         const PatchInfo P = c.info[p];
         load_velocity<MX>(c, s, l, P.ix * MX, P.iy * MX, t, dt, tdev, NI);
+        if (slot && tid == NT - 1) s.red[15] = sold;
 #pragma unroll
         for (int v = 0; v < NV; v++) {
             const int k = tid + v * NT, i = 2 * (k % (MX / 2)), j = k / (MX / 2);
@@ -590,24 +596,30 @@ __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, 
     if (xs && half == 0) update_row<MX, SEG>(s, line, e0, lam, R);
     else if (ys && half == 1) update_col<MX, SEG>(s, line, e0, lam, R);
     __syncthreads();
-    for (int k = threadIdx.x; k < MX * MX / 2; k += NT) {
-        const int i = 2 * (k % (MX / 2)), j = k / (MX / 2);
-        *reinterpret_cast<double2 *>(&out[base + (j + MB) * N + i + MB]) =
-            make_double2(s.q[(j + MB) * NP + i + MB], s.q[(j + MB) * NP + i + MB + 1]);
+    // Whole rows go out, ghost columns included (they carry the values the
+    // step gathered; nothing reads a patch's own ghost cells before the next
+    // fill or gather overwrites them): rows MB .. MB+MX-1 are one contiguous
+    // range, so L2 writes back full lines instead of partial ones at every
+    // row end.
+    for (int k = threadIdx.x; k < MX * N / 2; k += NT) {
+        const int i = 2 * (k % (N / 2)), j = k / (N / 2) + MB;
+        *reinterpret_cast<double2 *>(&out[base + j * N + i]) = make_double2(s.q[j * NP + i], s.q[j * NP + i + 1]);
     }
     cfl = fmax(cfl, lam * amax);
 }
 
 template <int MX, int NT, bool FUSED>
 // lev: the patch's level when the caller knows it (a level-step), else -1;
-// tdev: if given, the step starts at *tdev + t
+// tdev: if given, the step starts at *tdev + t;
+// slot: if given, its old value is left in s.red[15] for reduce_cfl_slot
 __device__ __forceinline__ void advance_scalar_patch(const Ctx &c, const View &w, ScalarSmem<MX> &s, int p, int lev,
-                                                     double t, double dt, double &cfl, const double *tdev = nullptr) {
+                                                     double t, double dt, double &cfl, const double *tdev = nullptr,
+                                                     const unsigned long long *slot = nullptr) {
     switch (c.lim) {
-        case 1: advance_scalar_lim<MX, NT, 1, FUSED>(c, w, s, p, lev, t, dt, tdev, cfl); break;
-        case 2: advance_scalar_lim<MX, NT, 2, FUSED>(c, w, s, p, lev, t, dt, tdev, cfl); break;
-        case 3: advance_scalar_lim<MX, NT, 3, FUSED>(c, w, s, p, lev, t, dt, tdev, cfl); break;
-        default: advance_scalar_lim<MX, NT, 0, FUSED>(c, w, s, p, lev, t, dt, tdev, cfl); break;
+        case 1: advance_scalar_lim<MX, NT, 1, FUSED>(c, w, s, p, lev, t, dt, tdev, slot, cfl); break;
+        case 2: advance_scalar_lim<MX, NT, 2, FUSED>(c, w, s, p, lev, t, dt, tdev, slot, cfl); break;
+        case 3: advance_scalar_lim<MX, NT, 3, FUSED>(c, w, s, p, lev, t, dt, tdev, slot, cfl); break;
+        default: advance_scalar_lim<MX, NT, 0, FUSED>(c, w, s, p, lev, t, dt, tdev, slot, cfl); break;
     }
 }
 
@@ -662,10 +674,9 @@ __global__ void __launch_bounds__(NT, (min_waves<MX, NT, 0>())) advance_scalar_k
     __shared__ ScalarSmem<MX> s;
     const int p = first + xcd_remap(blockIdx.x, count);
     unsigned long long *slot = c.cflp ? c.cflp + p : nullptr;
-    const double old = cfl_slot_old(slot);
     double cfl = 0.0;
-    advance_scalar_patch<MX, NT, FUSED>(c, view_of(c), s, p, level, t, dt, cfl);
-    reduce_cfl_slot<NT>(cfl, s.red, slot, old);
+    advance_scalar_patch<MX, NT, FUSED>(c, view_of(c), s, p, level, t, dt, cfl, nullptr, slot);
+    reduce_cfl_slot<NT>(cfl, s.red, slot, s.red[15]);
 }
 
 // ------------------------------------------------------------------------
@@ -1250,10 +1261,14 @@ __global__ void __launch_bounds__(NT, (min_waves<MX, NT, EQ>())) level_step_kern
     const double dt = a.scale * a.dtc;
     double cfl = 0.0;
     const int p = a.first + xcd_remap(blockIdx.x, a.count);
-    const double old = cfl_slot_old(c.cflp + p);
-    if constexpr (EQ == 0) advance_scalar_patch<MX, NT, true>(c, w, s, p, a.level, a.off * a.dtc, dt, cfl, &st->ts[a.cidx]);
-    else advance_swe_patch<MX, NT, true>(c, w, s, p, dt, cfl);
-    reduce_cfl_slot<NT>(cfl, s.red, c.cflp + p, old);
+    if constexpr (EQ == 0) {
+        advance_scalar_patch<MX, NT, true>(c, w, s, p, a.level, a.off * a.dtc, dt, cfl, &st->ts[a.cidx], c.cflp + p);
+        reduce_cfl_slot<NT>(cfl, s.red, c.cflp + p, s.red[15]);
+    } else {
+        const double old = cfl_slot_old(c.cflp + p);
+        advance_swe_patch<MX, NT, true>(c, w, s, p, dt, cfl);
+        reduce_cfl_slot<NT>(cfl, s.red, c.cflp + p, old);
+    }
 }
 
 __device__ void fill_times(DevState *st) {

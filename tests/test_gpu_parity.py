@@ -7,6 +7,7 @@ compared bitwise.  Inputs are seeded and synthetic (workloads.synth).
 """
 import numpy as np
 import pytest
+import torch
 
 from workloads import synth as S
 
@@ -190,6 +191,27 @@ def test_fused_equals_per_level_bitwise(B, O):
     c.coarse_steps(w["dt_coarse"], 7, "persistent_graph")
     c.coarse_steps(w["dt_coarse"], 13, "fused")
     assert np.array_equal(a.interior().cpu().numpy(), c.interior().cpu().numpy())
+
+
+def test_graph_replays_track_parity_and_step(B):
+    """Graph nodes carry the buffer parities and the coarse step as constants:
+    replays from either parity, chunk and single-step graphs, and a change of
+    step (recapture) must reproduce the host-driven sequence bit for bit,
+    CFL numbers included."""
+    w = S.workload("hump_l23")
+    dt = w["dt_coarse"]
+    plan = [(1, dt), (1, dt), (3, dt), (50, dt), (1, dt), (55, 0.5 * dt), (2, dt), (51, dt)]
+    a = B.from_workload(w)
+    b = B.from_workload(w)
+    for n, h in plan:
+        ca = torch.zeros(1, dtype=torch.float64, device="cuda")
+        cb = torch.zeros(1, dtype=torch.float64, device="cuda")
+        a.coarse_steps(h, n, "per_level", cfl=ca)
+        b.coarse_steps(h, n, "graph", cfl=cb)
+        assert np.array_equal(a.interior().cpu().numpy(), b.interior().cpu().numpy())
+        assert float(ca) == float(cb) and float(ca) > 0.0
+        assert a.time == b.time
+    b.check()
 
 
 @pytest.mark.parametrize("mx", [8, 16, 32])
