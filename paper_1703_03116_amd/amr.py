@@ -46,8 +46,8 @@ def run_adaptive(store, dt_coarse, ncoarse, regrid_every=2, tau_refine=0.05, tau
                 timings["regrid"] = timings.get("regrid", 0.0) + time.perf_counter() - t0
         m = min(regrid_every - done % regrid_every, ncoarse - done)
         lv = store.leaves()[:, 0]
-        per_step = sum(int((lv == l).sum()) * store.mx ** 2 * (1 << (l - store.min_level))
-                       for l in np.unique(lv))
+        per_step = sum(int((lv == l).sum()) * store.mx ** 2 * (1 << (int(l) - store.min_level))
+                       for l in np.unique(lv))  # Python ints: a NumPy int32 would overflow over many steps
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         store.coarse_steps(dt_coarse, m, mode)
