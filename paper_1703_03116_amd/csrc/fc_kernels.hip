@@ -270,6 +270,7 @@ struct ScalarSmem {
     double ux[MX + 1], uy[MX + 2];    // u(e, j) = ux[e] * uy[j+1]
     double vy[MX + 1], vx[MX + 2];    // v(i, e) = vy[e] * vx[i+1]
     double red[16];
+    unsigned long long cfl;           // the patch's Courant number (bits of a non-negative double)
 };
 
 // Cells per edge-sweep item: every interior line is split into MX/SEG
@@ -564,6 +565,7 @@ __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, 
             }
         }
     }
+    if (tid == 0) s.cfl = 0ull;
     __syncthreads();
     constexpr int S = ScalarSmem<MX>::S;
     double R[SEG];
@@ -592,6 +594,15 @@ __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, 
         const int k = tid - GT0, g = k / NSEG;
         sweep_outer<MX, SEG, LIM>(s, g >> 1, (g & 1) ? MX : -1, (k % NSEG) * SEG, lam);
     }
+    // CFL number of the patch: a max across the wave (done here, where waves
+    // that finish their sweeps early hide its latency behind the others),
+    // then one LDS atomic max per wave (the bits of non-negative doubles
+    // order as the values do), read after the barrier
+    {
+        double m = lam * amax;
+        for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+        if ((tid & 63) == 0 && m > 0.0) atomicMax(&s.cfl, (unsigned long long)__double_as_longlong(m));
+    }
     __syncthreads();
     if (xs && half == 0) update_row<MX, SEG>(s, line, e0, lam, R);
     else if (ys && half == 1) update_col<MX, SEG>(s, line, e0, lam, R);
@@ -605,7 +616,7 @@ __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, 
         const int i = 2 * (k % (N / 2)), j = k / (N / 2) + MB;
         *reinterpret_cast<double2 *>(&out[base + j * N + i]) = make_double2(s.q[j * NP + i], s.q[j * NP + i + 1]);
     }
-    cfl = fmax(cfl, lam * amax);
+    cfl = fmax(cfl, __longlong_as_double((long long)s.cfl));
 }
 
 template <int MX, int NT, bool FUSED>
@@ -648,6 +659,11 @@ __device__ __forceinline__ double cfl_slot_old(const unsigned long long *slot) {
     return (slot && threadIdx.x == 0) ? __longlong_as_double((long long)*slot) : 0.0;
 }
 
+// scalar kernels: every thread already holds the patch's Courant number
+__device__ __forceinline__ void store_cfl_slot(unsigned long long *slot, double old, double cfl) {
+    if (threadIdx.x == 0 && slot) *slot = (unsigned long long)__double_as_longlong(fmax(old, cfl));
+}
+
 template <int NT>
 __device__ void reduce_cfl_slot(double v, double *red, unsigned long long *slot, double old) {
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
@@ -676,7 +692,7 @@ __global__ void __launch_bounds__(NT, (min_waves<MX, NT, 0>())) advance_scalar_k
     unsigned long long *slot = c.cflp ? c.cflp + p : nullptr;
     double cfl = 0.0;
     advance_scalar_patch<MX, NT, FUSED>(c, view_of(c), s, p, level, t, dt, cfl, nullptr, slot);
-    reduce_cfl_slot<NT>(cfl, s.red, slot, s.red[15]);
+    store_cfl_slot(slot, s.red[15], cfl);
 }
 
 // ------------------------------------------------------------------------
@@ -1263,7 +1279,7 @@ __global__ void __launch_bounds__(NT, (min_waves<MX, NT, EQ>())) level_step_kern
     const int p = a.first + xcd_remap(blockIdx.x, a.count);
     if constexpr (EQ == 0) {
         advance_scalar_patch<MX, NT, true>(c, w, s, p, a.level, a.off * a.dtc, dt, cfl, &st->ts[a.cidx], c.cflp + p);
-        reduce_cfl_slot<NT>(cfl, s.red, c.cflp + p, s.red[15]);
+        store_cfl_slot(c.cflp + p, s.red[15], cfl);
     } else {
         const double old = cfl_slot_old(c.cflp + p);
         advance_swe_patch<MX, NT, true>(c, w, s, p, dt, cfl);
