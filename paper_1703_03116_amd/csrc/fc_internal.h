@@ -75,6 +75,10 @@ struct Ctx {
     double vel_u, vel_v, vel_T, g;
     double vel_invT;           // 1 / T of the swirl field
     int32_t *err;              // device error flags
+    // bit l: level l holds all 4^l quadrants (slots lstart[l] + Morton index)
+    // and wraps periodically, so neighbour slots follow from the index
+    uint32_t complete;
+    int32_t lstart[FC_MAXLEV];
     unsigned long long *cflp;  // per-slot max Courant number (bits of a non-negative double) [cap];
                                // NULL: not recorded
 };

@@ -225,6 +225,22 @@ __device__ __forceinline__ void ghost_index(int g, int &i, int &j) {
     i = k < MB ? k - MB : MX + k - MB;
 }
 
+// Morton index <-> quadrant coordinates (x on the even bits, y on the odd)
+__device__ __forceinline__ uint32_t morton_spread(uint32_t x) {
+    x &= 0xffffu;
+    x = (x | (x << 8)) & 0x00ff00ffu;
+    x = (x | (x << 4)) & 0x0f0f0f0fu;
+    x = (x | (x << 2)) & 0x33333333u;
+    return (x | (x << 1)) & 0x55555555u;
+}
+__device__ __forceinline__ uint32_t morton_compact(uint32_t x) {
+    x &= 0x55555555u;
+    x = (x | (x >> 1)) & 0x33333333u;
+    x = (x | (x >> 2)) & 0x0f0f0f0fu;
+    x = (x | (x >> 4)) & 0x00ff00ffu;
+    return (x | (x >> 8)) & 0x0000ffffu;
+}
+
 // XCD-aware block -> work item map: consecutive Morton patches go to one
 // XCD (blocks are dispatched round-robin over the 8 XCDs), so neighbour
 // reads hit that XCD's L2.
@@ -521,47 +537,83 @@ __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, 
             if (k < MX * MX / 2) iv[v] = *reinterpret_cast<const double2 *>(&in[base + (j + MB) * N + i + MB]);
         }
         const int g0 = (tid + NT - NI) % NT;  // the odd ghost cells go to a lightly loaded wave
-        int gi[NGH], gj[NGH];
-        NbrRec gr[NGH];
-#pragma unroll
-        for (int v = 0; v < NGH; v++) {
-            int r = 0;
-            gi[v] = gj[v] = 0;
-            if (g0 + v * NT < NG) {
-                ghost_region_index<MX>(g0 + v * NT, gi[v], gj[v], r);
-                gr[v] = c.nbr[p * FC_NREC + r];
-            }
-        }
-        // the CFL slot's old value (read by the workgroup's last thread, parked
-        // in LDS so that no register holds it across the step)
-        const double sold = (slot && tid == NT - 1) ? __longlong_as_double((long long)*slot) : 0.0;
-        const PatchInfo P = c.info[p];
-        load_velocity<MX>(c, s, l, P.ix * MX, P.iy * MX, t, dt, tdev, NI);
-        if (slot && tid == NT - 1) s.red[15] = sold;
-#pragma unroll
-        for (int v = 0; v < NV; v++) {
-            const int k = tid + v * NT, i = 2 * (k % (MX / 2)), j = k / (MX / 2);
-            if (k < MX * MX / 2) {
-                s.q[(j + MB) * NP + i + MB] = iv[v].x;
-                s.q[(j + MB) * NP + i + MB + 1] = iv[v].y;
-            }
-        }
-        if (P.walls == 0) {
+        if (lev >= 0 && ((c.complete >> lev) & 1u)) {
+            // A complete periodic level: every neighbour is a same-level
+            // patch whose slot follows from the Morton index, so no record is
+            // read and all loads of the step leave at once.
+            const uint32_t m = (uint32_t)(p - c.lstart[l]);
+            const int ix = (int)morton_compact(m), iy = (int)morton_compact(m >> 1), wrap = (1 << l) - 1;
+            double gv[NGH];
+            int gi[NGH], gj[NGH];
 #pragma unroll
             for (int v = 0; v < NGH; v++) {
+                int r;
+                gi[v] = gj[v] = 0;
                 if (g0 + v * NT < NG) {
-                    double val[1];
-                    ghost_cell_rec<MX, 1>(c, w, l, gi[v], gj[v], gr[v], val);
-                    s.q[(gj[v] + MB) * NP + gi[v] + MB] = val[0];
+                    ghost_region_index<MX>(g0 + v * NT, gi[v], gj[v], r);
+                    const int dx = gi[v] < 0 ? -1 : (gi[v] >= MX ? 1 : 0), dy = gj[v] < 0 ? -1 : (gj[v] >= MX ? 1 : 0);
+                    const uint32_t q = (uint32_t)c.lstart[l] + (morton_spread((uint32_t)((ix + dx) & wrap)) |
+                                                                (morton_spread((uint32_t)((iy + dy) & wrap)) << 1));
+                    gv[v] = in[(size_t)q * N * N + (size_t)((gj[v] - dy * MX + MB) * N + gi[v] - dx * MX + MB)];
                 }
             }
+            const double sold = (slot && tid == NT - 1) ? __longlong_as_double((long long)*slot) : 0.0;
+            load_velocity<MX>(c, s, l, ix * MX, iy * MX, t, dt, tdev, NI);
+            if (slot && tid == NT - 1) s.red[15] = sold;
+#pragma unroll
+            for (int v = 0; v < NV; v++) {
+                const int k = tid + v * NT, i = 2 * (k % (MX / 2)), j = k / (MX / 2);
+                if (k < MX * MX / 2) {
+                    s.q[(j + MB) * NP + i + MB] = iv[v].x;
+                    s.q[(j + MB) * NP + i + MB + 1] = iv[v].y;
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < NGH; v++)
+                if (g0 + v * NT < NG) s.q[(gj[v] + MB) * NP + gi[v] + MB] = gv[v];
         } else {
-            for (int g = g0; g < NG; g += NT) {
-                int i, j;
-                ghost_index<MX>(g, i, j);
-                double val[1];
-                ghost_cell<MX, 1>(c, w, p, i, j, val);
-                s.q[(j + MB) * NP + i + MB] = val[0];
+            int gi[NGH], gj[NGH];
+            NbrRec gr[NGH];
+#pragma unroll
+            for (int v = 0; v < NGH; v++) {
+                int r = 0;
+                gi[v] = gj[v] = 0;
+                if (g0 + v * NT < NG) {
+                    ghost_region_index<MX>(g0 + v * NT, gi[v], gj[v], r);
+                    gr[v] = c.nbr[p * FC_NREC + r];
+                }
+            }
+            // the CFL slot's old value (read by the workgroup's last thread, parked
+            // in LDS so that no register holds it across the step)
+            const double sold = (slot && tid == NT - 1) ? __longlong_as_double((long long)*slot) : 0.0;
+            const PatchInfo P = c.info[p];
+            load_velocity<MX>(c, s, l, P.ix * MX, P.iy * MX, t, dt, tdev, NI);
+            if (slot && tid == NT - 1) s.red[15] = sold;
+#pragma unroll
+            for (int v = 0; v < NV; v++) {
+                const int k = tid + v * NT, i = 2 * (k % (MX / 2)), j = k / (MX / 2);
+                if (k < MX * MX / 2) {
+                    s.q[(j + MB) * NP + i + MB] = iv[v].x;
+                    s.q[(j + MB) * NP + i + MB + 1] = iv[v].y;
+                }
+            }
+            if (P.walls == 0) {
+#pragma unroll
+                for (int v = 0; v < NGH; v++) {
+                    if (g0 + v * NT < NG) {
+                        double val[1];
+                        ghost_cell_rec<MX, 1>(c, w, l, gi[v], gj[v], gr[v], val);
+                        s.q[(gj[v] + MB) * NP + gi[v] + MB] = val[0];
+                    }
+                }
+            } else {
+                for (int g = g0; g < NG; g += NT) {
+                    int i, j;
+                    ghost_index<MX>(g, i, j);
+                    double val[1];
+                    ghost_cell<MX, 1>(c, w, p, i, j, val);
+                    s.q[(j + MB) * NP + i + MB] = val[0];
+                }
             }
         }
     }

@@ -288,6 +288,11 @@ Ctx make_ctx(const fc_patchstore *ps) {
     c.g = ps->cfg.gravity;
     c.err = (int32_t *)(ps->ws + ps->off_state + offsetof(DevState, err));
     c.cflp = cflp(ps);
+    const bool per = ps->cfg.bc[0] == FC_BC_PERIODIC && ps->cfg.bc[2] == FC_BC_PERIODIC;
+    for (int l = 0; l < FC_MAXLEV; l++) {
+        c.lstart[l] = ps->lr.start[l];
+        if (per && l < 16 && ps->lr.count[l] == (1 << (2 * l))) c.complete |= 1u << l;
+    }
     return c;
 }
 

@@ -193,6 +193,20 @@ def test_fused_equals_per_level_bitwise(B, O):
     assert np.array_equal(a.interior().cpu().numpy(), c.interior().cpu().numpy())
 
 
+@pytest.mark.parametrize("mx", [8, 32])
+def test_complete_level_fused_equals_per_level_bitwise(B, mx):
+    """On a complete periodic level the fused kernels derive neighbour slots
+    from the Morton index instead of reading records; the result must be
+    the fill-then-advance result bit for bit."""
+    w = S.workload("swirl_uniform", level=3 if mx == 8 else 2, mx=mx)
+    a = B.from_workload(w)
+    b = B.from_workload(w)
+    a.coarse_steps(w["dt_coarse"], 6, "per_level")
+    b.coarse_steps(w["dt_coarse"], 3, "graph")
+    b.coarse_steps(w["dt_coarse"], 3, "fused_levels")
+    assert np.array_equal(a.interior().cpu().numpy(), b.interior().cpu().numpy())
+
+
 def test_graph_replays_track_parity_and_step(B):
     """Graph nodes carry the buffer parities and the coarse step as constants:
     replays from either parity, chunk and single-step graphs, and a change of
