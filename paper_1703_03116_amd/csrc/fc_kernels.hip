@@ -764,19 +764,23 @@ struct SweSmem {
     double red[16];
 };
 
-// Roe linearisation in the frame (h, h u_n, h u_t)
+// Roe linearisation in the frame (h, h u_n, h u_t).  Each denominator is
+// inverted once (a double division costs a dozen instructions).
 __device__ __forceinline__ void roe_solve(double g, double hL, double nL, double tL, double hR, double nR, double tR,
                                           double *r) {
-    const double uL = nL / hL, uR = nR / hR, vL = tL / hL, vR = tR / hR;
+    const double ihL = 1.0 / hL, ihR = 1.0 / hR;
+    const double uL = nL * ihL, uR = nR * ihR, vL = tL * ihL, vR = tR * ihR;
     const double sL = sqrt(hL), sR = sqrt(hR);
     const double hb = 0.5 * (hL + hR);
-    const double uh = (sL * uL + sR * uR) / (sL + sR);
-    const double vh = (sL * vL + sR * vR) / (sL + sR);
+    const double is = 1.0 / (sL + sR);
+    const double uh = (sL * uL + sR * uR) * is;
+    const double vh = (sL * vL + sR * vR) * is;
     const double ch = sqrt(g * hb);
+    const double i2c = 0.5 / ch;
     const double d0 = hR - hL, d1 = nR - nL, d2 = tR - tL;
-    r[0] = ((uh + ch) * d0 - d1) / (2.0 * ch);
+    r[0] = ((uh + ch) * d0 - d1) * i2c;
     r[1] = d2 - vh * d0;
-    r[2] = (d1 - (uh - ch) * d0) / (2.0 * ch);
+    r[2] = (d1 - (uh - ch) * d0) * i2c;
     r[3] = uh; r[4] = vh; r[5] = ch;
 }
 
@@ -797,9 +801,10 @@ __device__ __forceinline__ double phi_limit(int lim, double th) {
 }
 
 // split A (frame h, n, t) into its +t and -t moving parts with the Roe state r
-__device__ __forceinline__ void roe_transverse(const double *r, const double *A, double *bp, double *bm) {
+// (i2c = 1 / (2 c), shared by the two splits of an edge)
+__device__ __forceinline__ void roe_transverse(const double *r, double i2c, const double *A, double *bp, double *bm) {
     const double un = r[3], ut = r[4], c = r[5];
-    const double be[3] = {((ut + c) * A[0] - A[2]) / (2.0 * c), A[1] - un * A[0], (A[2] - (ut - c) * A[0]) / (2.0 * c)};
+    const double be[3] = {((ut + c) * A[0] - A[2]) * i2c, A[1] - un * A[0], (A[2] - (ut - c) * A[0]) * i2c};
     const double mu[3] = {ut - c, ut, ut + c};
     const double rv[3][3] = {{1.0, un, ut - c}, {0.0, 1.0, 0.0}, {1.0, un, ut + c}};
 #pragma unroll
@@ -823,13 +828,21 @@ __device__ __forceinline__ void swe_edge(double g, int lim, double lam, const do
     double W[3][3], sp[3];
     waves_of(r, W, sp);
     // Harten-Hyman fix on transonic rarefactions of families 1 and 3
+    // (the middle states are needed only where the outer speed has the
+    // sign that allows a transonic rarefaction)
     const double l1L = qL[1] / qL[0] - sqrt(g * qL[0]);
-    const double hm = qL[0] + W[0][0];
-    const double l1R = (qL[1] + W[0][1]) / hm - sqrt(g * hm);
+    double l1R = 0.0;
+    if (l1L < 0.0) {
+        const double hm = qL[0] + W[0][0];
+        l1R = (qL[1] + W[0][1]) / hm - sqrt(g * hm);
+    }
     const bool fix1 = l1L < 0.0 && l1R > 0.0;
-    const double hm3 = qR[0] - W[2][0];
-    const double l3L = (qR[1] - W[2][1]) / hm3 + sqrt(g * hm3);
     const double l3R = qR[1] / qR[0] + sqrt(g * qR[0]);
+    double l3L = 0.0;
+    if (l3R > 0.0) {
+        const double hm3 = qR[0] - W[2][0];
+        l3L = (qR[1] - W[2][1]) / hm3 + sqrt(g * hm3);
+    }
     const bool fix3 = l3L < 0.0 && l3R > 0.0;
     double am[3] = {0, 0, 0}, ap[3] = {0, 0, 0};
 #pragma unroll
@@ -871,8 +884,9 @@ __device__ __forceinline__ void swe_edge(double g, int lim, double lam, const do
     }
 #pragma unroll
     for (int e = 0; e < 3; e++) { Aps[e] = ap[e] - C[e]; Ams[e] = am[e] + C[e]; }
-    roe_transverse(r, Aps, bpp, bmp);
-    roe_transverse(r, Ams, bpm, bmm);
+    const double i2c = 0.5 / r[5];
+    roe_transverse(r, i2c, Aps, bpp, bmp);
+    roe_transverse(r, i2c, Ams, bpm, bmm);
 }
 
 // One step on a shallow-water patch.  Sweep X then Y; each sweep: Riemann
