@@ -86,9 +86,10 @@ def main():
     ap.add_argument("--level", type=int, default=5)
     ap.add_argument("--mx", type=int, default=32)
     ap.add_argument("--workload", default="swirl_uniform",
-                    choices=["swirl_uniform", "swirl_amr", "dam_break"],
+                    choices=["swirl_uniform", "swirl_amr", "dam_break", "adjoint"],
                     help="swirl_uniform (default; --level sets its size), swirl_amr (levels 3-7, regrid "
-                         "every 2 coarse steps), dam_break (shallow water, levels 2-6, 16x16)")
+                         "every 2 coarse steps), dam_break (shallow water, levels 2-6, 16x16), adjoint "
+                         "(gradient of an L2 misfit, uniform level 6, 256 steps, checkpoints every 16)")
     ap.add_argument("--threads", type=int, default=0,
                     help="threads per patch of the advance kernels (0: autotune)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -114,6 +115,8 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.workload == "adjoint":
+        return adjoint_workload(args)
     if args.workload != "swirl_uniform":
         return other_workload(args)
     w = S.workload("swirl_uniform", level=args.level, mx=args.mx, steps=args.steps)
@@ -240,6 +243,49 @@ def other_workload(args):
            "dtype": "f64", "data": "synthetic", "config": {"workload": args.workload, "threads_per_patch": nt},
            "fused_graph": res["graph"], "per_level": res["per_level"],
            "fused_over_per_level": res["graph"]["value"] / res["per_level"]["value"]}
+    print(json.dumps(out), flush=True)
+
+
+def adjoint_workload(args):
+    """Gradient of L = 1/2 ||q(T) - q_target||^2 with respect to q0: forward
+    pass with checkpoints, then per segment recomputation and the hand-written
+    adjoint steps.  Value: forward-equivalent cell updates per second of
+    gradient time (cells x steps / seconds); the forward pass alone and the
+    adjoint step kernel's share are reported beside it."""
+    import torch
+    from paper_1703_03116_amd import binding as B
+    from paper_1703_03116_amd.adjoint import loss_and_grad
+    from workloads import synth as S
+
+    level, mx, n, every = 6, 32, (args.steps if args.steps != 500 else 256), 16
+    L = S.uniform_leaves(level)
+    q0 = torch.tensor(S.sample_on_leaves(S.gaussians(S.gaussian_params(5)), L, mx), device="cuda")
+    qt = torch.tensor(S.sample_on_leaves(S.gaussians(S.gaussian_params(6)), L, mx), device="cuda")
+    dt = 0.9 / (mx << level)
+    ps = B.PatchStore(L, mx=mx, velocity="swirl", vel_params=(1.0, 0, 0), limiter="mc")
+    nt = ps.autotune()
+    loss_and_grad(ps, q0, qt, level, dt, 16, every)  # warm-up (graphs, kernels)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Lv, g = loss_and_grad(ps, q0, qt, level, dt, n, every)
+    torch.cuda.synchronize()
+    grad_s = time.perf_counter() - t0
+    ps.time = 0.0
+    ps.set_interior(q0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ps.coarse_steps(dt, n, "graph")
+    torch.cuda.synchronize()
+    fwd_s = time.perf_counter() - t0
+    ps.check()
+    cells = len(L) * mx * mx
+    out = {"metric": "cell-updates/sec of the gradient (forward + recompute + adjoint) at 1 GPU",
+           "value": cells * n / grad_s, "unit": "cell-updates/s", "n_gpus": 1, "steps": n, "warmup": 1,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"adjoint: uniform level {level}, {len(L)} patches of {mx}x{mx}, swirl, MC limiter, "
+                                  f"{n} steps, checkpoint every {every}", "threads_per_patch": nt},
+           "gradient_s": grad_s, "forward_s": fwd_s, "gradient_over_forward": grad_s / fwd_s,
+           "loss": float(Lv), "grad_norm": float(g.norm())}
     print(json.dumps(out), flush=True)
 
 

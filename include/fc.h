@@ -194,6 +194,7 @@ fc_status fc_regrid(fc_patchstore *ps, int64_t nleaves, const fc_leaf *new_leave
  * advance): lambda_out = (J_adv J_fill)^T lambda_in with the limiter
  * branches frozen at the step's input state q_in.  q_in, lambda_in,
  * lambda_out: device arrays [nleaves][1][mx][mx] in input-leaf order.
+ * Needs a uniform level and periodic boundaries (FC_ERR_ARG otherwise).
  * Uses the store's buffers as scratch (their contents are overwritten). */
 fc_status fc_adjoint_step(fc_patchstore *ps, int32_t level, double t, double dt, const double *q_in,
                           const double *lambda_in, double *lambda_out, void *stream);

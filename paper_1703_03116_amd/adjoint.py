@@ -1,7 +1,7 @@
 """Differentiation of the uniform-level advance + ghost fill.
 
 ``AdvanceFill`` is a torch.autograd.Function whose forward runs ``nsteps``
-coarse steps of the GPU path (persistent kernel replayed from a hipGraph)
+coarse steps of the GPU path (graph mode)
 from q0 and returns q(T); its backward is the hand-written discrete adjoint
 (fc_adjoint_step: transpose of the limited step with branches frozen at the
 forward state, then transpose of the ghost copy), with checkpoints every
@@ -37,8 +37,8 @@ class AdvanceFill(torch.autograd.Function):
             store.coarse_steps(dt, m, "graph")
             k += m
             if k < nsteps:
-                ckpts.append(store.interior().clone())
-        out = store.interior().clone()
+                ckpts.append(store.interior())  # a fresh tensor
+        out = store.interior()
         ctx.store, ctx.level, ctx.dt, ctx.nsteps, ctx.every = store, level, dt, nsteps, every
         ctx.times, ctx.ckpts = times, ckpts
         return out
@@ -56,7 +56,7 @@ class AdvanceFill(torch.autograd.Function):
             states = [ctx.ckpts[seg]]
             for _ in range(a, b - 1):
                 store.coarse_steps(dt, 1, "graph")
-                states.append(store.interior().clone())
+                states.append(store.interior())
             for k in reversed(range(a, b)):
                 lam = store.adjoint_step(level, ctx.times[k], dt, states[k - a], lam)
         return lam, None, None, None, None, None, None

@@ -1057,18 +1057,18 @@ struct AdjSmem {
     double ux[MX + 1], uy[MX + 2], vy[MX + 1], vx[MX + 2];
 };
 
+// (two workgroups of 512 threads fit a CU's LDS at mx = 32: registers are
+// budgeted for all sixteen waves)
 template <int MX, int NT>
-__global__ void __launch_bounds__(NT) adjoint_kernel(Ctx c, int first, int count, double t, double dt,
-                                                     const int32_t *leaf_of_slot, const double *lam_in,
-                                                     double *abar) {
+__global__ void __launch_bounds__(NT, (NT >= 512 ? 4 : 1)) adjoint_kernel(Ctx c, int first, int count, double t, double dt,
+                                                     const int32_t *leaf_of_slot, const double *q_in,
+                                                     const double *lam_in, double *abar) {
     constexpr int N = MX + 2 * MB, NX = AdjSmem<MX>::NX;
     __shared__ AdjSmem<MX> s;
     const int p = first + blockIdx.x;
-    const View w = view_of(c);
     const PatchInfo P = c.info[p];
     const int l = P.level;
     const double lam = dt * (double)(MX << l);  // dt / h, exact: h = 1 / (MX 2^l)
-    const double *in = buf_of(c, w, l);
     const size_t base = (size_t)p * N * N;
     // velocities (same factors as the forward step)
     {
@@ -1092,7 +1092,21 @@ __global__ void __launch_bounds__(NT) adjoint_kernel(Ctx c, int first, int count
             }
         }
     }
-    for (int k = threadIdx.x; k < N * N; k += NT) s.u.a.q[k] = in[base + k];
+    // the step's input tile straight from q_in (input-leaf order): interior
+    // cells and the same-size copies that fill its ghost frame (a uniform
+    // periodic level: every neighbour record is a same-level one)
+    {
+        const double *qi = q_in + (size_t)leaf_of_slot[p] * MX * MX;
+        for (int k = threadIdx.x; k < MX * MX; k += NT) s.u.a.q[(k / MX + MB) * N + k % MX + MB] = qi[k];
+        constexpr int NG = N * N - MX * MX;
+        for (int g = threadIdx.x; g < NG; g += NT) {
+            int i, j, r;
+            ghost_region_index<MX>(g, i, j, r);
+            const NbrRec rec = c.nbr[p * FC_NREC + r];
+            const double *qn = q_in + (size_t)leaf_of_slot[rec.id] * MX * MX;
+            s.u.a.q[(j + MB) * N + i + MB] = qn[(j - rec.oy) * MX + i - rec.ox];
+        }
+    }
     const double *li = lam_in + (size_t)leaf_of_slot[p] * MX * MX;
     for (int k = threadIdx.x; k < MX * MX; k += NT) s.lam[k] = li[k];
     __syncthreads();
@@ -1729,12 +1743,13 @@ hipError_t launch_tag(const Ctx &c, int mx, const int32_t *slot_of_leaf, int n, 
 }
 
 hipError_t launch_adjoint(const Ctx &c, int mx, int first, int count, double t, double dt,
-                          const int32_t *leaf_of_slot, const double *lam_in, double *abar, hipStream_t s) {
+                          const int32_t *leaf_of_slot, const double *q_in, const double *lam_in, double *abar,
+                          hipStream_t s) {
     if (count <= 0) return hipSuccess;
     switch (mx) {
-        case 8: hipLaunchKernelGGL((adjoint_kernel<8, 64>), dim3(count), dim3(64), 0, s, c, first, count, t, dt, leaf_of_slot, lam_in, abar); break;
-        case 16: hipLaunchKernelGGL((adjoint_kernel<16, 256>), dim3(count), dim3(256), 0, s, c, first, count, t, dt, leaf_of_slot, lam_in, abar); break;
-        case 32: hipLaunchKernelGGL((adjoint_kernel<32, 256>), dim3(count), dim3(256), 0, s, c, first, count, t, dt, leaf_of_slot, lam_in, abar); break;
+        case 8: hipLaunchKernelGGL((adjoint_kernel<8, 64>), dim3(count), dim3(64), 0, s, c, first, count, t, dt, leaf_of_slot, q_in, lam_in, abar); break;
+        case 16: hipLaunchKernelGGL((adjoint_kernel<16, 256>), dim3(count), dim3(256), 0, s, c, first, count, t, dt, leaf_of_slot, q_in, lam_in, abar); break;
+        case 32: hipLaunchKernelGGL((adjoint_kernel<32, 512>), dim3(count), dim3(512), 0, s, c, first, count, t, dt, leaf_of_slot, q_in, lam_in, abar); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -868,17 +868,15 @@ fc_status fc_adjoint_step(fc_patchstore *ps, int32_t level, double t, double dt,
     const int n = (int)ps->mesh.lv.size();
     if (ps->lr.count[level] != n) return fail(FC_ERR_ARG, "the adjoint needs a uniform mesh at `level`");
     if (!(dt > 0)) return fail(FC_ERR_ARG, "dt must be positive");
+    for (int k = 0; k < 4; k++)
+        if (ps->cfg.bc[k] != FC_BC_PERIODIC) return fail(FC_ERR_ARG, "the adjoint covers periodic boundaries");
     hipStream_t s = (hipStream_t)stream;
-    const int32_t *sl = (const int32_t *)(ps->ws + ps->off_sl);
     const int32_t *ls = (const int32_t *)(ps->ws + ps->off_ls);
-    // forward state with its ghosts in the level's current buffer
-    HIPCHK(launch_set_interior(make_ctx(ps), ps->mx, sl, n, q_in, s));
-    r = fill_levels(ps, level, level, 1.0, s);
-    if (r != FC_OK) return r;
-    // transpose of the advance into the other buffer, then of the copy
+    // transpose of the advance (its input tile gathered from q_in, ghosts
+    // by same-size copy) into the other buffer, then of the copy
     Ctx c = make_ctx(ps);
     double *abar = ((ps->curmask >> level) & 1u) ? ps->q0 : ps->q1;
-    HIPCHK(launch_adjoint(c, ps->mx, ps->lr.start[level], n, t, dt, ls, lambda_in, abar, s));
+    HIPCHK(launch_adjoint(c, ps->mx, ps->lr.start[level], n, t, dt, ls, q_in, lambda_in, abar, s));
     HIPCHK(launch_adjoint_gather(c, ps->mx, ps->lr.start[level], n, ls, abar, lambda_out, s));
     return FC_OK;
 }
