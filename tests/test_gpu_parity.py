@@ -394,3 +394,36 @@ def test_adaptive_swirl_with_regrid(B, O, mx):
     assert np.array_equal(np.sort(ps.leaves().view("i4,i4,i4"), axis=0), np.sort(o.leaves().view("i4,i4,i4"), axis=0))
     assert ps.nleaves == o.n and ps.nleaves != len(L)
     assert rel(ps.interior(), o.interior()) <= TOL
+
+
+def test_full_size_dam_break_levels_2_6(B, O):
+    """The dam-break workload at its full size (levels 2-6, 685 patches of
+    16x16, reflecting walls, 31 level-steps per coarse step), graph form,
+    5 coarse steps, against the oracle."""
+    w = S.workload("dam_break")
+    ps = B.from_workload(w)
+    o = O.from_workload(w)
+    dt = 0.6 / (w["mx"] << w["lmin"]) / 2.5  # finest-level Courant number <= 0.6 for |u| + c <= 2.5
+    ps.coarse_steps(dt, 5, "graph")
+    for s_ in range(5):
+        o.coarse_step(s_ * dt, dt)
+    ps.check()
+    assert rel(ps.interior(), o.interior()) <= TOL
+
+
+def test_full_size_adaptive_swirl_levels_3_7(B, O):
+    """The adaptive workload at its full size (levels 3-7, 8224 patches of
+    32x32 at the start), regrid every 2 coarse steps with the bench's
+    thresholds, 4 coarse steps: the leaf sets must agree exactly and the
+    solution to the tolerance."""
+    from paper_1703_03116_amd.amr import run_adaptive
+    w = S.workload("swirl_amr")
+    ps = B.from_workload(w, capacity=4 ** w["lmax"])
+    o = O.from_workload(w)
+    dt = w["dt_coarse"]
+    run_adaptive(ps, dt, 4, regrid_every=2, tau_refine=0.05, tau_coarsen=0.025)
+    _oracle_run_adaptive(o, dt, 4, 2, 0.05, 0.025)
+    ps.check()
+    assert np.array_equal(np.sort(ps.leaves().view("i4,i4,i4"), axis=0), np.sort(o.leaves().view("i4,i4,i4"), axis=0))
+    assert rel(ps.interior(), o.interior()) <= TOL
+
