@@ -500,12 +500,16 @@ __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, 
     // Work split (items = line segments): threads [0, NI) sweep the interior
     // rows, [NI, 2 NI) the interior columns; each half of either set covers
     // one half of the patch.  The lower-half rows and the upper-half columns
-    // finish the update (the other two store their partials); the outer-line
-    // items, the odd ghost cells and c(t) go to threads with less to do.
-    // With one workgroup's wave k on SIMD k, this keeps the SIMDs balanced.
+    // finish the update (the other two store their partials).  The four
+    // outer lines are cut into segments of two cells, one per thread of the
+    // lower-half column items (or of idle threads), so that no wave carries a
+    // long extra chain into the barrier; the odd ghost cells and c(t) go to
+    // the same threads.
     constexpr int SEG = scalar_seg<MX, NT>(), NSEG = MX / SEG, NI = MX * NSEG, HI = NI / 2;
-    constexpr int GT0 = (NT - 2 * NI >= 4 * NSEG) ? 2 * NI : HI;  // first thread of the outer-line items
+    constexpr int SO = 2, NO = 4 * (MX / SO);  // outer-line segment length and item count
+    constexpr int GT0 = (NT - 2 * NI >= NO) ? 2 * NI : NI;  // first thread of the outer-line items
     static_assert(2 * NI <= NT && NSEG % 2 == 0, "interior items must fit one pass, in two halves");
+    static_assert(GT0 + NO <= NT, "outer-line items must fit one pass");
     static_assert(NI + MX + 2 <= NT, "velocity factors are loaded by threads NI .. NI+MX+1");
     const int tid = threadIdx.x;
     // The loads that depend only on the slot (interior, neighbour records)
@@ -642,9 +646,9 @@ __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, 
             for (int k = 0; k < SEG; k++) s.part[(e0 + k) * S + line] = R[k];
         }
     }
-    if (tid >= GT0 && tid < GT0 + 4 * NSEG) {  // rows -1, MX and columns -1, MX: TX, TY only
-        const int k = tid - GT0, g = k / NSEG;
-        sweep_outer<MX, SEG, LIM>(s, g >> 1, (g & 1) ? MX : -1, (k % NSEG) * SEG, lam);
+    if (tid >= GT0 && tid < GT0 + NO) {  // rows -1, MX and columns -1, MX: TX, TY only
+        const int k = tid - GT0, g = k / (MX / SO);
+        sweep_outer<MX, SO, LIM>(s, g >> 1, (g & 1) ? MX : -1, (k % (MX / SO)) * SO, lam);
     }
     // CFL number of the patch: a max across the wave (done here, where waves
     // that finish their sweeps early hide its latency behind the others),
