@@ -206,7 +206,8 @@ fc_status fc_check_device(fc_patchstore *ps, void *stream);
 
 /* Choose the launch configuration (waves per patch) of the advance kernels
  * by timing every variant on the bound store (results are bitwise equal); a
- * variant with more threads is taken only if it is at least 3% faster.
+ * variant other than the default (64 threads at mx = 8, else 256) is taken
+ * only if it is at least 5% faster (best of three interleaved timing rounds).
  * Returns the chosen threads per patch. */
 fc_status fc_autotune(fc_patchstore *ps, int32_t *threads_out, void *stream);
 fc_status fc_set_variant(fc_patchstore *ps, int32_t threads_per_patch);

@@ -923,26 +923,34 @@ fc_status fc_autotune(fc_patchstore *ps, int32_t *threads_out, void *stream) {
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
-    float best = 1e30f;
-    int bnt = ps->nt;
-    for (int k = 0; k < 3; k++) {
-        const int nt = cl[k];
-        if (!valid_nt(ps->mx, nt, ps->cfg.equation)) continue;
-        Ctx c = make_ctx(ps);
-        c.cflp = nullptr;
-        LaunchCfg lc{ps->mx, nt};
-        for (int w = 0; w < 2; w++)
-            HIPCHK(launch_advance(c, lc, lbest, ps->lr.start[lbest], ps->lr.count[lbest], ps->t, dt, 1, s));
-        HIPCHK(hipEventRecord(e0, s));
-        for (int w = 0; w < 5; w++)
-            HIPCHK(launch_advance(c, lc, lbest, ps->lr.start[lbest], ps->lr.count[lbest], ps->t, dt, 1, s));
-        HIPCHK(hipEventRecord(e1, s));
-        HIPCHK(hipEventSynchronize(e1));
-        float ms = 0;
-        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-        // a larger variant must win by 3%: timing noise alone does not flip the choice
-        if (ms < 0.97f * best) { best = ms; bnt = nt; }
-    }
+    // three interleaved rounds of 10 launches per variant, the best round
+    // counts; another variant replaces the default one only if it is at
+    // least 5% faster, so that noise does not flip the choice from run to run
+    float t[3] = {1e30f, 1e30f, 1e30f};
+    for (int round = 0; round < 3; round++)
+        for (int k = 0; k < 3; k++) {
+            const int nt = cl[k];
+            if (!valid_nt(ps->mx, nt, ps->cfg.equation)) continue;
+            Ctx c = make_ctx(ps);
+            c.cflp = nullptr;
+            LaunchCfg lc{ps->mx, nt};
+            for (int w = 0; w < 2; w++)
+                HIPCHK(launch_advance(c, lc, lbest, ps->lr.start[lbest], ps->lr.count[lbest], ps->t, dt, 1, s));
+            HIPCHK(hipEventRecord(e0, s));
+            for (int w = 0; w < 10; w++)
+                HIPCHK(launch_advance(c, lc, lbest, ps->lr.start[lbest], ps->lr.count[lbest], ps->t, dt, 1, s));
+            HIPCHK(hipEventRecord(e1, s));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            t[k] = std::min(t[k], ms);
+        }
+    int bnt = default_nt(ps->mx), kd = 0;
+    for (int k = 0; k < 3; k++)
+        if (cl[k] == bnt) kd = k;
+    float best = t[kd];
+    for (int k = 0; k < 3; k++)
+        if (k != kd && t[k] < 0.95f * best) { best = t[k]; bnt = cl[k]; }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     r = fc_set_variant(ps, bnt);
