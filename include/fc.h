@@ -190,12 +190,23 @@ fc_status fc_adapt(const fc_patchstore *ps, const int8_t *tags, fc_leaf *out, in
  * synchronised.  Afterwards "input-leaf order" is the order of new_leaves. */
 fc_status fc_regrid(fc_patchstore *ps, int64_t nleaves, const fc_leaf *new_leaves, void *stream);
 
+/* One step of the unsplit scheme (the same step as fc_advance_level after
+ * a same-size fill, bitwise) on a uniform periodic level of scalar
+ * advection, from q_in to q_out: device arrays [nleaves][1][mx][mx] in
+ * input-leaf order, 16-byte aligned, q_out != q_in (FC_ERR_ARG otherwise,
+ * also for a non-uniform mesh, other equations or non-periodic sides).  The
+ * store's solution and time are left as they were; the step starts at t.
+ * This is the form the adjoint's recomputation walks through. */
+fc_status fc_step_uniform(fc_patchstore *ps, int32_t level, double t, double dt, const double *q_in,
+                          double *q_out, void *stream);
+
 /* Adjoint of one uniform-level scalar step (fill by same-size copy, then
  * advance): lambda_out = (J_adv J_fill)^T lambda_in with the limiter
  * branches frozen at the step's input state q_in.  q_in, lambda_in,
- * lambda_out: device arrays [nleaves][1][mx][mx] in input-leaf order.
- * Needs a uniform level and periodic boundaries (FC_ERR_ARG otherwise).
- * Uses the store's buffers as scratch (their contents are overwritten). */
+ * lambda_out: device arrays [nleaves][1][mx][mx] in input-leaf order,
+ * 16-byte aligned.  Needs a uniform level and periodic boundaries
+ * (FC_ERR_ARG otherwise).  lambda_out must not be lambda_in or q_in
+ * (FC_ERR_ARG).  The store's solution is left as it was. */
 fc_status fc_adjoint_step(fc_patchstore *ps, int32_t level, double t, double dt, const double *q_in,
                           const double *lambda_in, double *lambda_out, void *stream);
 

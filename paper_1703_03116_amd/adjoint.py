@@ -6,7 +6,7 @@ from q0 and returns q(T); its backward is the hand-written discrete adjoint
 (fc_adjoint_step: transpose of the limited step with branches frozen at the
 forward state, then transpose of the ghost copy), with checkpoints every
 ``checkpoint_every`` steps and the states of one segment recomputed at a
-time.  Shapes: [nleaves][1][mx][mx] float64 on the GPU, in the leaf order the
+time by fc_step_uniform (leaf order in, leaf order out).  Shapes: [nleaves][1][mx][mx] float64 on the GPU, in the leaf order the
 store was created with.
 """
 from __future__ import annotations
@@ -50,13 +50,11 @@ class AdvanceFill(torch.autograd.Function):
         nseg = (n + every - 1) // every
         for seg in reversed(range(nseg)):
             a, b = seg * every, min(n, (seg + 1) * every)
-            # recompute the segment's step inputs q^a .. q^(b-1)
-            store.time = ctx.times[a]
-            store.set_interior(ctx.ckpts[seg])
+            # recompute the segment's step inputs q^a .. q^(b-1), leaf order
+            # to leaf order (bitwise the forward's states)
             states = [ctx.ckpts[seg]]
-            for _ in range(a, b - 1):
-                store.coarse_steps(dt, 1, "graph")
-                states.append(store.interior())
+            for k in range(a, b - 1):
+                states.append(store.step_uniform(level, ctx.times[k], dt, states[-1]))
             for k in reversed(range(a, b)):
                 lam = store.adjoint_step(level, ctx.times[k], dt, states[k - a], lam)
         return lam, None, None, None, None, None, None

@@ -30,7 +30,7 @@ EXPORTS = ["fc_last_error", "fc_patchstore_create", "fc_patchstore_destroy", "fc
            "fc_patchstore_bind", "fc_patchstore_info", "fc_patchstore_leaves", "fc_set_interior",
            "fc_get_interior", "fc_get_patches", "fc_ghost_fill", "fc_advance_level",
            "fc_advance_coarse_steps", "fc_get_time", "fc_set_time", "fc_tag_refine", "fc_adapt", "fc_regrid",
-           "fc_adjoint_step", "fc_check_device", "fc_autotune", "fc_set_variant", "fc_set_persistent_grid"]
+           "fc_step_uniform", "fc_adjoint_step", "fc_check_device", "fc_autotune", "fc_set_variant", "fc_set_persistent_grid"]
 
 
 class FcError(RuntimeError):
@@ -79,6 +79,7 @@ def lib():
         L.fc_tag_refine.argtypes = [vp, C.c_double, C.c_double, vp, vp, vp]
         L.fc_adapt.argtypes = [vp, C.POINTER(C.c_int8), C.POINTER(Leaf), C.c_int64, C.POINTER(C.c_int64)]
         L.fc_regrid.argtypes = [vp, C.c_int64, C.POINTER(Leaf), vp]
+        L.fc_step_uniform.argtypes = [vp, C.c_int32, C.c_double, C.c_double, vp, vp, vp]
         L.fc_adjoint_step.argtypes = [vp, C.c_int32, C.c_double, C.c_double, vp, vp, vp, vp]
         L.fc_check_device.argtypes = [vp, vp]
         L.fc_autotune.argtypes = [vp, C.POINTER(C.c_int32), vp]
@@ -227,6 +228,15 @@ class PatchStore:
         arr, n = _leaves_array(new_leaves)
         _check(lib().fc_regrid(self._h, n, arr, _stream()))
         self.nleaves = n
+
+    def step_uniform(self, level, t, dt, q_in):
+        """q(t + dt) from q(t) = q_in on a uniform periodic level, leaf order;
+        the store's own state is not touched."""
+        q = _dev(q_in).reshape(self.nleaves, 1, self.mx, self.mx)
+        out = torch.empty_like(q)
+        _check(lib().fc_step_uniform(self._h, int(level), float(t), float(dt), C.c_void_p(q.data_ptr()),
+                                     C.c_void_p(out.data_ptr()), _stream()))
+        return out
 
     def adjoint_step(self, level, t, dt, q_in, lam_in):
         q = _dev(q_in).reshape(self.nleaves, 1, self.mx, self.mx)

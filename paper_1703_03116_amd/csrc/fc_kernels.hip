@@ -492,10 +492,22 @@ __device__ __forceinline__ void update_col(ScalarSmem<MX> &s, int i, int e0, dou
 //   Edge sweeps: one item per (line, segment); the x-items of the interior
 //   rows keep their partial sums in registers and, after the barrier, finish
 //   the update of their cells.
-template <int MX, int NT, int LIM, bool FUSED>
+// Arrays of a uniform periodic level in input-leaf order (the form the
+// adjoint's recomputation steps through): [nleaves][mx][mx].
+struct LeafIO {
+    const double *qin;
+    double *qout;
+    const int32_t *leaf_of_slot;
+};
+
+// LEAF: read the step's input from io->qin and write its result to io->qout
+// instead of the store's buffers (uniform periodic level: every ghost value
+// is a same-size copy); the arithmetic is the same code either way.
+template <int MX, int NT, int LIM, bool FUSED, bool LEAF = false>
 __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, ScalarSmem<MX> &s, int p, int lev,
                                                    double t, double dt, const double *tdev,
-                                                   const unsigned long long *slot, double &cfl) {
+                                                   const unsigned long long *slot, double &cfl,
+                                                   const LeafIO *io = nullptr) {
     constexpr int N = MX + 2 * MB, NP = ScalarSmem<MX>::NP;
     // Work split (items = line segments): threads [0, NI) sweep the interior
     // rows, [NI, 2 NI) the interior columns; each half of either set covers
@@ -521,7 +533,24 @@ __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, 
     double *out = other_of(c, w, l);
     const size_t base = (size_t)p * N * N;
     // rows are 16-byte aligned (N and MB even): two cells per load
-    if (!FUSED) {
+    if constexpr (LEAF) {
+        const PatchInfo P = c.info[p];
+        const double *qi = io->qin + (size_t)io->leaf_of_slot[p] * MX * MX;
+        for (int k = tid; k < MX * MX / 2; k += NT) {
+            const int i = 2 * (k % (MX / 2)), j = k / (MX / 2);
+            const double2 v = *reinterpret_cast<const double2 *>(qi + 2 * k);
+            s.q[(j + MB) * NP + i + MB] = v.x;
+            s.q[(j + MB) * NP + i + MB + 1] = v.y;
+        }
+        for (int g = tid; g < N * N - MX * MX; g += NT) {
+            int i, j, r;
+            ghost_region_index<MX>(g, i, j, r);
+            const NbrRec rec = c.nbr[(size_t)p * FC_NREC + r];
+            s.q[(j + MB) * NP + i + MB] =
+                io->qin[(size_t)io->leaf_of_slot[rec.id] * MX * MX + (j - rec.oy) * MX + i - rec.ox];
+        }
+        load_velocity<MX>(c, s, l, P.ix * MX, P.iy * MX, t, dt, nullptr, NI);
+    } else if (!FUSED) {
         const PatchInfo P = c.info[p];
         load_velocity<MX>(c, s, l, P.ix * MX, P.iy * MX, t, dt, tdev, NI);
         for (int k = tid; k < N * N / 2; k += NT) {
@@ -668,9 +697,17 @@ __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, 
     // fill or gather overwrites them): rows MB .. MB+MX-1 are one contiguous
     // range, so L2 writes back full lines instead of partial ones at every
     // row end.
-    for (int k = threadIdx.x; k < MX * N / 2; k += NT) {
-        const int i = 2 * (k % (N / 2)), j = k / (N / 2) + MB;
-        *reinterpret_cast<double2 *>(&out[base + j * N + i]) = make_double2(s.q[j * NP + i], s.q[j * NP + i + 1]);
+    if constexpr (LEAF) {
+        double *qo = io->qout + (size_t)io->leaf_of_slot[p] * MX * MX;
+        for (int k = threadIdx.x; k < MX * MX / 2; k += NT) {
+            const int i = 2 * (k % (MX / 2)), j = k / (MX / 2) + MB;
+            *reinterpret_cast<double2 *>(qo + 2 * k) = make_double2(s.q[j * NP + i + MB], s.q[j * NP + i + MB + 1]);
+        }
+    } else {
+        for (int k = threadIdx.x; k < MX * N / 2; k += NT) {
+            const int i = 2 * (k % (N / 2)), j = k / (N / 2) + MB;
+            *reinterpret_cast<double2 *>(&out[base + j * N + i]) = make_double2(s.q[j * NP + i], s.q[j * NP + i + 1]);
+        }
     }
     cfl = fmax(cfl, __longlong_as_double((long long)s.cfl));
 }
@@ -749,6 +786,22 @@ __global__ void __launch_bounds__(NT, (min_waves<MX, NT, 0>())) advance_scalar_k
     double cfl = 0.0;
     advance_scalar_patch<MX, NT, FUSED>(c, view_of(c), s, p, level, t, dt, cfl, nullptr, slot);
     store_cfl_slot(slot, s.red[15], cfl);
+}
+
+// one step of a uniform periodic level from leaf-order q_in to q_out
+template <int MX, int NT>
+__global__ void __launch_bounds__(NT, (min_waves<MX, NT, 0>())) step_leaf_kernel(Ctx c, int first, int count, int level,
+                                                                                double t, double dt, LeafIO io) {
+    __shared__ ScalarSmem<MX> s;
+    const int p = first + xcd_remap(blockIdx.x, count);
+    const View w = view_of(c);
+    double cfl = 0.0;
+    switch (c.lim) {
+        case 1: advance_scalar_lim<MX, NT, 1, false, true>(c, w, s, p, level, t, dt, nullptr, nullptr, cfl, &io); break;
+        case 2: advance_scalar_lim<MX, NT, 2, false, true>(c, w, s, p, level, t, dt, nullptr, nullptr, cfl, &io); break;
+        case 3: advance_scalar_lim<MX, NT, 3, false, true>(c, w, s, p, level, t, dt, nullptr, nullptr, cfl, &io); break;
+        default: advance_scalar_lim<MX, NT, 0, false, true>(c, w, s, p, level, t, dt, nullptr, nullptr, cfl, &io); break;
+    }
 }
 
 // ------------------------------------------------------------------------
@@ -1023,230 +1076,209 @@ __global__ void __launch_bounds__(NT) advance_swe_kernel(Ctx c, int first, int c
 // ------------------------------------------------------------------------
 // adjoint of one uniform-level scalar step (fill by copy, then advance)
 // ------------------------------------------------------------------------
-// The limited step is piecewise linear in Q; its Jacobian is the step with
-// the limiter branches frozen at the forward state.  Branch codes follow the
-// forward limiter's tie order (half-sum, then 2W, then 2Wu).
-__device__ __forceinline__ void limiter_partials(int lim, double W, double Wu, double &dW, double &dWu) {
-    dW = 0.0; dWu = 0.0;
-    if (lim == 1) { dW = 1.0; return; }
-    if (lim == 2) return;
-    if (W * Wu <= 0.0) return;
+// On a uniform periodic level every ghost value is a same-size copy, so the
+// patch step is the global stencil of the unsplit scheme (Sec. 3) and the
+// transpose of copy + advance is the global transposed stencil:
+//   lambda_out(c) = sum over d of dQnew(d)/dQ(c) lambda_in(d),
+// with d within two cells of c.  It is evaluated in gather form, one
+// workgroup per patch: lambda_in with two ghost layers and q with three
+// (along the axes only) come straight from the neighbours' interiors.
+//
+// The step is piecewise linear in Q; its Jacobian is the step with the
+// limiter branches frozen at the forward state.  Per line (a row for the x
+// sweep, a column for the y sweep; L = lambda_in, lam = dt/h):
+//   Tbar(i) = -lam L(i) + lam^2/2 (s+_up (L(i) - L_up(i)) + s-_dn (L_dn(i) - L(i)))
+//             adjoint of the cell's total fluctuation (TX or TY), the
+//             transverse edges' speeds s_up, s_dn on either side of the line;
+//   per edge e (between cells e-1 and e, speed u, W = Q(e) - Q(e-1), Wu its
+//   upwind neighbour):
+//   Cbar = lam/2 (L(e-1) - L(e)) - Tbar(e) + Tbar(e-1),  w = |u| (1 - lam |u|) Cbar,
+//   g(e) = u+ Tbar(e) + u- Tbar(e-1) + dphi/dW w,  h(e) = dphi/dWu w,
+//   D(e) = g(e) + [u(e+1) > 0] h(e+1) + [u(e-1) <= 0] h(e-1)
+//             total adjoint of the difference W(e);
+//   cell i receives D(i) - D(i+1).
+// lambda_out(c) = L(c) + (row part) + (column part).
+
+// Partial derivatives of the limited wave phi(W, Wu) (the correction's
+// factor k excluded) on the forward branch.  Ties follow the forward
+// limiter's order: the half sum, then 2|W|, then 2|Wu|; minmod takes W on a tie.
+template <int LIM>
+__device__ __forceinline__ void limiter_partials(double W, double Wu, double &dW, double &dWu) {
+    if constexpr (LIM == 2) { dW = 0.0; dWu = 0.0; return; }
+    if constexpr (LIM == 1) { dW = 1.0; dWu = 0.0; return; }
+    const bool on = W * Wu > 0.0;
     const double aw = fabs(W), au = fabs(Wu);
-    if (lim == 3) { if (aw <= au) dW = 1.0; else dWu = 1.0; return; }
-    const double a = 0.5 * fabs(W + Wu), b = 2.0 * aw, cc = 2.0 * au;
-    int br = 1;
-    double mn = a;
-    if (b < mn) { mn = b; br = 2; }
-    if (cc < mn) br = 3;
-    if (br == 1) { dW = 0.5; dWu = 0.5; }
-    else if (br == 2) dW = 2.0;
-    else dWu = 2.0;
+    if constexpr (LIM == 3) {
+        const bool tw = aw <= au;
+        dW = (on && tw) ? 1.0 : 0.0;
+        dWu = (on && !tw) ? 1.0 : 0.0;
+        return;
+    }
+    const double a = 0.5 * (aw + au), b = 2.0 * aw, cc = 2.0 * au;
+    const bool t1 = b < a;
+    const bool t2 = cc < (t1 ? b : a);
+    dW = (!on || t2) ? 0.0 : (t1 ? 2.0 : 0.5);
+    dWu = !on ? 0.0 : (t2 ? 2.0 : (t1 ? 0.0 : 0.5));
 }
 
 template <int MX>
 struct AdjSmem {
-    static constexpr int N = MX + 2 * MB;
-    static constexpr int NX = (MX + 2) * (MX + 1);  // edges of one direction
-    union {
-        struct {
-            double q[N * N];
-            double tx[(MX + 2) * MX], ty[MX * (MX + 2)];  // adjoints of TX, TY
-        } a;
-        struct {
-            double dx[(MX + 2) * (MX + 3)], dy[(MX + 3) * (MX + 2)];  // total adjoint of each difference
-        } b;
-    } u;
-    double lam[MX * MX];
-    double gx[NX], hx[NX], gy[NX], hy[NX];  // adjoints w.r.t. W and the upwind W
-    double ux[MX + 1], uy[MX + 2], vy[MX + 1], vx[MX + 2];
+    static constexpr int NQ = MX + 6, QP = NQ + 1;  // q, three ghost layers (corners unused)
+    static constexpr int NL = MX + 4, LP = NL + 1;  // lambda_in, two ghost layers
+    double q[NQ * QP];
+    double l[NL * LP];
+    double part[MX * (MX + 1)];  // L + row part of each interior cell
+    // velocity factors (the forward step's): x-edge e -> ue[e + 1], row j ->
+    // uc[j + 2]; y-edge e -> ve[e + 1], column i -> vc[i + 2]
+    double ue[MX + 3], uc[MX + 4], ve[MX + 3], vc[MX + 4];
 };
 
-// (two workgroups of 512 threads fit a CU's LDS at mx = 32: registers are
-// budgeted for all sixteen waves)
+// One segment of one line: cells e0 .. e0+SEG-1 of row `line` (DIR 0) or
+// column `line` (DIR 1).  Returns D(i) - D(i+1) of each cell.
+template <int MX, int SEG, int LIM, int DIR>
+__device__ __forceinline__ void adjoint_line(const AdjSmem<MX> &s, int line, int e0, double lam, double (&R)[SEG]) {
+    using A = AdjSmem<MX>;
+    constexpr int SQ = DIR == 0 ? 1 : A::QP, SL = DIR == 0 ? 1 : A::LP, XL = DIR == 0 ? A::LP : 1;
+    const double *qp = DIR == 0 ? &s.q[(line + 3) * A::QP + 3] : &s.q[3 * A::QP + line + 3];
+    const double *lp = DIR == 0 ? &s.l[(line + 2) * A::LP + 2] : &s.l[2 * A::LP + line + 2];
+    const double *ea = DIR == 0 ? &s.ue[1] : &s.ve[1];   // speed factor of the line's edges
+    const double *ca = DIR == 0 ? &s.vc[2] : &s.uc[2];   // cell factor of the transverse edges
+    const double lf = DIR == 0 ? s.uc[line + 2] : s.vc[line + 2];
+    const double fup = DIR == 0 ? s.ve[line + 2] : s.ue[line + 2];  // transverse edge line + 1/2
+    const double fdn = DIR == 0 ? s.ve[line + 1] : s.ue[line + 1];  // transverse edge line - 1/2
+    const double hl = 0.5 * lam, hl2 = 0.5 * lam * lam;
+    // w[k] = W(e0 - 2 + k) from q(e0 - 3 .. e0 + SEG + 2)
+    double w[SEG + 5];
+    {
+        double q[SEG + 6];
+#pragma unroll
+        for (int k = 0; k < SEG + 6; k++) q[k] = qp[(e0 - 3 + k) * SQ];
+#pragma unroll
+        for (int k = 0; k < SEG + 5; k++) w[k] = q[k + 1] - q[k];
+    }
+    // L(i) and Tbar(i), i = e0 - 2 + k
+    double lv[SEG + 4], tb[SEG + 4];
+#pragma unroll
+    for (int k = 0; k < SEG + 4; k++) {
+        const double *lc = lp + (e0 - 2 + k) * SL;
+        const double L = lc[0], Lu = lc[XL], Ld = lc[-XL];
+        const double cf = ca[e0 - 2 + k];
+        lv[k] = L;
+        tb[k] = hl2 * (posp(fup * cf) * (L - Lu) + negp(fdn * cf) * (Ld - L)) - lam * L;
+    }
+    // edges e = e0 - 1 + m
+    double g[SEG + 3], h[SEG + 3];
+    bool up[SEG + 3];
+#pragma unroll
+    for (int m = 0; m < SEG + 3; m++) {
+        const double u = ea[e0 - 1 + m] * lf;
+        up[m] = u > 0.0;
+        const double W = w[m + 1];
+        const double Wu = up[m] ? w[m] : w[m + 2];
+        const double tr = tb[m + 1], tl = tb[m];
+        const double au = fabs(u);
+        const double wb = (au * (1.0 - lam * au)) * (hl * (lv[m] - lv[m + 1]) - tr + tl);
+        double dW, dWu;
+        limiter_partials<LIM>(W, Wu, dW, dWu);
+        g[m] = posp(u) * tr + negp(u) * tl + dW * wb;
+        h[m] = dWu * wb;
+    }
+    double D[SEG + 1];
+#pragma unroll
+    for (int k = 0; k <= SEG; k++) {  // edge e0 + k
+        const int m = k + 1;
+        D[k] = g[m] + (up[m + 1] ? h[m + 1] : 0.0) + (up[m - 1] ? 0.0 : h[m - 1]);
+    }
+#pragma unroll
+    for (int k = 0; k < SEG; k++) R[k] = D[k] - D[k + 1];
+}
+
 template <int MX, int NT>
-__global__ void __launch_bounds__(NT, (NT >= 512 ? 4 : 1)) adjoint_kernel(Ctx c, int first, int count, double t, double dt,
-                                                     const int32_t *leaf_of_slot, const double *q_in,
-                                                     const double *lam_in, double *abar) {
-    constexpr int N = MX + 2 * MB, NX = AdjSmem<MX>::NX;
-    __shared__ AdjSmem<MX> s;
-    const int p = first + blockIdx.x;
+constexpr int adj_seg() { return (2 * MX * MX / NT) < 4 ? 4 : 2 * MX * MX / NT; }
+
+template <int MX, int NT, int LIM>
+__global__ void __launch_bounds__(NT, (MX == 32 ? 4 : 1)) adjoint_kernel(Ctx c, int first, int count, double t,
+                                                                         double dt, const int32_t *leaf_of_slot,
+                                                                         const double *q_in, const double *lam_in,
+                                                                         double *lam_out) {
+    using A = AdjSmem<MX>;
+    constexpr int SEG = adj_seg<MX, NT>(), NI = MX * (MX / SEG);  // segments per direction
+    static_assert(2 * NI <= NT && MX % SEG == 0, "one segment per thread");
+    __shared__ A s;
+    const int tid = threadIdx.x;
+    const int p = first + xcd_remap(blockIdx.x, count);
     const PatchInfo P = c.info[p];
     const int l = P.level;
     const double lam = dt * (double)(MX << l);  // dt / h, exact: h = 1 / (MX 2^l)
-    const size_t base = (size_t)p * N * N;
-    // velocities (same factors as the forward step)
+    const NbrRec *nb = c.nbr + (size_t)p * FC_NREC;
+    const size_t PS = (size_t)MX * MX;
+    // interiors of q and lambda_in
+    {
+        const double *qi = q_in + (size_t)leaf_of_slot[p] * PS, *li = lam_in + (size_t)leaf_of_slot[p] * PS;
+        for (int k = tid; k < MX * MX / 2; k += NT) {
+            const int i = 2 * (k % (MX / 2)), j = k / (MX / 2);
+            const double2 a = *reinterpret_cast<const double2 *>(qi + 2 * k);
+            const double2 b = *reinterpret_cast<const double2 *>(li + 2 * k);
+            s.q[(j + 3) * A::QP + i + 3] = a.x;
+            s.q[(j + 3) * A::QP + i + 4] = a.y;
+            s.l[(j + 2) * A::LP + i + 2] = b.x;
+            s.l[(j + 2) * A::LP + i + 3] = b.y;
+        }
+    }
+    // q: three layers beyond each side (side neighbours W, E, S, N)
+    for (int g = tid; g < 12 * MX; g += NT) {
+        const int side = g / (3 * MX), k = g % (3 * MX);
+        int i, j, along;
+        if (side < 2) { along = k / 3; j = along; i = side == 0 ? k % 3 - 3 : MX + k % 3; }
+        else { along = k % MX; i = along; j = side == 2 ? k / MX - 3 : MX + k / MX; }
+        const NbrRec r = nb[2 * side + (along >= MX / 2)];
+        s.q[(j + 3) * A::QP + i + 3] = q_in[(size_t)leaf_of_slot[r.id] * PS + (j - r.oy) * MX + i - r.ox];
+    }
+    // lambda_in: two ghost layers, corners included
+    for (int g = tid; g < (MX + 4) * (MX + 4) - MX * MX; g += NT) {
+        int i, j, rr;
+        ghost_region_index<MX>(g, i, j, rr);
+        const NbrRec r = nb[rr];
+        s.l[(j + 2) * A::LP + i + 2] = lam_in[(size_t)leaf_of_slot[r.id] * PS + (j - r.oy) * MX + i - r.ox];
+    }
+    // velocity factors at the mid-step time, as the forward step takes them
     {
         const int n = MX << l, gx0 = P.ix * MX, gy0 = P.iy * MX;
-        const double tm = t + 0.5 * dt;
         if (c.velocity == 2) {
-            const double ct = cos(M_PI * (tm * c.vel_invT));
+            const double ct = cos(M_PI * ((t + 0.5 * dt) * c.vel_invT));
             const double *vt = c.vt[l];
             const double *ex = vt + vt_ex(n, MB), *cxv = vt + vt_cx(n, MB);
             const double *ey = vt + vt_ey(n, MB), *cyv = vt + vt_cy(n, MB);
-            for (int k = threadIdx.x; k < MX + 2; k += NT) {
-                if (k <= MX) { s.ux[k] = ex[gx0 + k]; s.vy[k] = ey[gy0 + k]; }
-                s.uy[k] = cyv[gy0 + k - 1] * ct;
-                s.vx[k] = -(cxv[gx0 + k - 1] * ct);
+            for (int k = tid; k < MX + 4; k += NT) {
+                if (k < MX + 3) { s.ue[k] = ex[gx0 + k - 1]; s.ve[k] = ey[gy0 + k - 1]; }
+                s.uc[k] = cyv[gy0 + k - 2] * ct;
+                s.vc[k] = -(cxv[gx0 + k - 2] * ct);
             }
         } else {
-            for (int k = threadIdx.x; k < MX + 2; k += NT) {
-                if (k <= MX) { s.ux[k] = c.vel_u; s.vy[k] = c.vel_v; }
-                s.uy[k] = 1.0;
-                s.vx[k] = 1.0;
+            for (int k = tid; k < MX + 4; k += NT) {
+                if (k < MX + 3) { s.ue[k] = c.vel_u; s.ve[k] = c.vel_v; }
+                s.uc[k] = 1.0;
+                s.vc[k] = 1.0;
             }
-        }
-    }
-    // the step's input tile straight from q_in (input-leaf order): interior
-    // cells and the same-size copies that fill its ghost frame (a uniform
-    // periodic level: every neighbour record is a same-level one)
-    {
-        const double *qi = q_in + (size_t)leaf_of_slot[p] * MX * MX;
-        for (int k = threadIdx.x; k < MX * MX; k += NT) s.u.a.q[(k / MX + MB) * N + k % MX + MB] = qi[k];
-        constexpr int NG = N * N - MX * MX;
-        for (int g = threadIdx.x; g < NG; g += NT) {
-            int i, j, r;
-            ghost_region_index<MX>(g, i, j, r);
-            const NbrRec rec = c.nbr[p * FC_NREC + r];
-            const double *qn = q_in + (size_t)leaf_of_slot[rec.id] * MX * MX;
-            s.u.a.q[(j + MB) * N + i + MB] = qn[(j - rec.oy) * MX + i - rec.ox];
-        }
-    }
-    const double *li = lam_in + (size_t)leaf_of_slot[p] * MX * MX;
-    for (int k = threadIdx.x; k < MX * MX; k += NT) s.lam[k] = li[k];
-    __syncthreads();
-    auto LN = [&](int i, int j) -> double {
-        return (i >= 0 && i < MX && j >= 0 && j < MX) ? s.lam[j * MX + i] : 0.0;
-    };
-    // adjoint of TX (cells i in [0,MX), rows -1..MX) and TY (cols -1..MX, rows 0..MX-1):
-    // -lam * lambda_n plus the transverse terms that read them
-    for (int k = threadIdx.x; k < (MX + 2) * MX; k += NT) {
-        {
-            const int j = k / MX - 1, i = k % MX;
-            double v = -lam * LN(i, j);
-            if (j + 1 <= MX) {  // y-edge (i, j+1): v+ TX(i, j)
-                const double ve = s.vy[j + 1] * s.vx[i + 1];
-                v += posp(ve) * (0.5 * lam * lam * (LN(i, j) - LN(i, j + 1)));
-            }
-            if (j >= 0) {       // y-edge (i, j): v- TX(i, j)
-                const double ve = s.vy[j] * s.vx[i + 1];
-                v += negp(ve) * (0.5 * lam * lam * (LN(i, j - 1) - LN(i, j)));
-            }
-            s.u.a.tx[k] = v;
-        }
-        {
-            const int j = k / (MX + 2), i = k % (MX + 2) - 1;
-            double v = -lam * LN(i, j);
-            if (i + 1 <= MX) {  // x-edge (i+1, j): u+ TY(i, j)
-                const double ue = s.ux[i + 1] * s.uy[j + 1];
-                v += posp(ue) * (0.5 * lam * lam * (LN(i, j) - LN(i + 1, j)));
-            }
-            if (i >= 0) {       // x-edge (i, j): u- TY(i, j)
-                const double ue = s.ux[i] * s.uy[j + 1];
-                v += negp(ue) * (0.5 * lam * lam * (LN(i - 1, j) - LN(i, j)));
-            }
-            s.u.a.ty[k] = v;
         }
     }
     __syncthreads();
-    // per edge: adjoints w.r.t. its difference W (g) and its upwind difference (h)
-    for (int k = threadIdx.x; k < NX; k += NT) {
-        {   // x-edge (e, j), e in [0, MX], j in [-1, MX]
-            const int j = k / (MX + 1) - 1, e = k % (MX + 1);
-            const double *row = &s.u.a.q[(j + MB) * N + MB];
-            const double u = s.ux[e] * s.uy[j + 1];
-            const double W = row[e] - row[e - 1];
-            const double Wu = u > 0.0 ? row[e - 1] - row[e - 2] : row[e + 1] - row[e];
-            const double apsb = e < MX ? s.u.a.tx[(j + 1) * MX + e] : 0.0;
-            const double amsb = e >= 1 ? s.u.a.tx[(j + 1) * MX + e - 1] : 0.0;
-            const double cxb = (j >= 0 && j < MX) ? 0.5 * lam * (LN(e - 1, j) - LN(e, j)) : 0.0;
-            const double cb = cxb - apsb + amsb;
-            const double au = fabs(u);
-            const double wlb = au * (1.0 - lam * au) * cb;
-            double dW, dWu;
-            limiter_partials(c.lim, W, Wu, dW, dWu);
-            s.gx[k] = posp(u) * apsb + negp(u) * amsb + dW * wlb;
-            s.hx[k] = dWu * wlb;
-        }
-        {   // y-edge (i, e), e in [0, MX], i in [-1, MX]
-            const int e = k / (MX + 2), i = k % (MX + 2) - 1;
-            const double *col = &s.u.a.q[MB * N + i + MB];
-            const double v = s.vy[e] * s.vx[i + 1];
-            const double W = col[e * N] - col[(e - 1) * N];
-            const double Wu = v > 0.0 ? col[(e - 1) * N] - col[(e - 2) * N] : col[(e + 1) * N] - col[e * N];
-            const double bpsb = e < MX ? s.u.a.ty[e * (MX + 2) + i + 1] : 0.0;
-            const double bmsb = e >= 1 ? s.u.a.ty[(e - 1) * (MX + 2) + i + 1] : 0.0;
-            const double cyb = (i >= 0 && i < MX) ? 0.5 * lam * (LN(i, e - 1) - LN(i, e)) : 0.0;
-            const double cb = cyb - bpsb + bmsb;
-            const double av = fabs(v);
-            const double wlb = av * (1.0 - lam * av) * cb;
-            double dW, dWu;
-            limiter_partials(c.lim, W, Wu, dW, dWu);
-            s.gy[k] = posp(v) * bpsb + negp(v) * bmsb + dW * wlb;
-            s.hy[k] = dWu * wlb;
-        }
+    double R[SEG];
+    if (tid < NI) {  // rows: L + row part into LDS
+        const int j = tid % MX, e0 = (tid / MX) * SEG;
+        adjoint_line<MX, SEG, LIM, 0>(s, j, e0, lam, R);
+#pragma unroll
+        for (int k = 0; k < SEG; k++) s.part[j * (MX + 1) + e0 + k] = s.l[(j + 2) * A::LP + e0 + k + 2] + R[k];
+    } else if (tid < 2 * NI) {
+        const int k0 = tid - NI;
+        adjoint_line<MX, SEG, LIM, 1>(s, k0 % MX, (k0 / MX) * SEG, lam, R);
     }
     __syncthreads();
-    // total adjoint of each difference W_e = Q(e) - Q(e-1), e in [-1, MX+1]:
-    // its own edge plus the neighbouring edges that use it as upwind difference
-    for (int k = threadIdx.x; k < (MX + 2) * (MX + 3); k += NT) {
-        {
-            const int j = k / (MX + 3) - 1, e = k % (MX + 3) - 1;
-            const int r = (j + 1) * (MX + 1);
-            double v = (e >= 0 && e <= MX) ? s.gx[r + e] : 0.0;
-            if (e + 1 <= MX && s.ux[e + 1] * s.uy[j + 1] > 0.0) v += s.hx[r + e + 1];
-            if (e - 1 >= 0 && !(s.ux[e - 1] * s.uy[j + 1] > 0.0)) v += s.hx[r + e - 1];
-            s.u.b.dx[k] = v;
-        }
-        {
-            const int e = k / (MX + 2) - 1, i = k % (MX + 2) - 1;
-            double v = (e >= 0 && e <= MX) ? s.gy[e * (MX + 2) + i + 1] : 0.0;
-            if (e + 1 <= MX && s.vy[e + 1] * s.vx[i + 1] > 0.0) v += s.hy[(e + 1) * (MX + 2) + i + 1];
-            if (e - 1 >= 0 && !(s.vy[e - 1] * s.vx[i + 1] > 0.0)) v += s.hy[(e - 1) * (MX + 2) + i + 1];
-            s.u.b.dy[k] = v;
-        }
-    }
-    __syncthreads();
-    // adjoint of every cell of the patch array (interior and ghosts)
-    for (int k = threadIdx.x; k < N * N; k += NT) {
-        const int i = k % N - MB, j = k / N - MB;
-        double v = LN(i, j);
-        if (j >= -1 && j <= MX) {
-            const int r = (j + 1) * (MX + 3);
-            const double a = (i >= -1 && i <= MX + 1) ? s.u.b.dx[r + i + 1] : 0.0;
-            const double b = (i + 1 >= -1 && i + 1 <= MX + 1) ? s.u.b.dx[r + i + 2] : 0.0;
-            v += a - b;
-        }
-        if (i >= -1 && i <= MX) {
-            const double a = (j >= -1 && j <= MX + 1) ? s.u.b.dy[(j + 1) * (MX + 2) + i + 1] : 0.0;
-            const double b = (j + 1 >= -1 && j + 1 <= MX + 1) ? s.u.b.dy[(j + 2) * (MX + 2) + i + 1] : 0.0;
-            v += a - b;
-        }
-        abar[base + k] = v;
-    }
-}
-
-// Transpose of the same-size ghost copy, in gather form: an interior cell
-// collects its own adjoint and that of every ghost cell that copied it.
-template <int MX>
-__global__ void adjoint_gather_kernel(Ctx c, int first, const int32_t *leaf_of_slot, const double *abar,
-                                      double *lam_out) {
-    constexpr int N = MX + 2 * MB;
-    const int p = first + blockIdx.x;
-    // one record per direction: W, E, S, N, SW, SE, NW, NE
-    const int rec[8] = {0, 2, 4, 6, 8, 9, 10, 11};
-    double *lo = lam_out + (size_t)leaf_of_slot[p] * MX * MX;
-    for (int k = threadIdx.x; k < MX * MX; k += blockDim.x) {
-        const int i = k % MX, j = k / MX;
-        double v = abar[(size_t)p * N * N + (j + MB) * N + i + MB];
-        for (int d = 0; d < 8; d++) {
-            const NbrRec r = c.nbr[p * FC_NREC + rec[d]];
-            if (r.type != NB_SAME) continue;
-            const int iN = i - r.ox, jN = j - r.oy;
-            if (iN < -MB || iN >= MX + MB || jN < -MB || jN >= MX + MB) continue;
-            if (iN >= 0 && iN < MX && jN >= 0 && jN < MX) continue;
-            v += abar[(size_t)r.id * N * N + (jN + MB) * N + iN + MB];
-        }
-        lo[k] = v;
+    if (tid >= NI && tid < 2 * NI) {  // columns finish the cells (a row of lanes per store)
+        const int k0 = tid - NI, i = k0 % MX, e0 = (k0 / MX) * SEG;
+        double *lo = lam_out + (size_t)leaf_of_slot[p] * PS;
+#pragma unroll
+        for (int k = 0; k < SEG; k++) lo[(e0 + k) * MX + i] = s.part[(e0 + k) * (MX + 1) + i] + R[k];
     }
 }
 
@@ -1746,26 +1778,38 @@ hipError_t launch_tag(const Ctx &c, int mx, const int32_t *slot_of_leaf, int n, 
     return hipGetLastError();
 }
 
-hipError_t launch_adjoint(const Ctx &c, int mx, int first, int count, double t, double dt,
-                          const int32_t *leaf_of_slot, const double *q_in, const double *lam_in, double *abar,
-                          hipStream_t s) {
+hipError_t launch_step_leaf(const Ctx &c, int mx, int level, int first, int count, double t, double dt,
+                            const int32_t *leaf_of_slot, const double *q_in, double *q_out, hipStream_t s) {
     if (count <= 0) return hipSuccess;
+    const LeafIO io{q_in, q_out, leaf_of_slot};
     switch (mx) {
-        case 8: hipLaunchKernelGGL((adjoint_kernel<8, 64>), dim3(count), dim3(64), 0, s, c, first, count, t, dt, leaf_of_slot, q_in, lam_in, abar); break;
-        case 16: hipLaunchKernelGGL((adjoint_kernel<16, 256>), dim3(count), dim3(256), 0, s, c, first, count, t, dt, leaf_of_slot, q_in, lam_in, abar); break;
-        case 32: hipLaunchKernelGGL((adjoint_kernel<32, 512>), dim3(count), dim3(512), 0, s, c, first, count, t, dt, leaf_of_slot, q_in, lam_in, abar); break;
+        case 8: hipLaunchKernelGGL((step_leaf_kernel<8, 64>), dim3(count), dim3(64), 0, s, c, first, count, level, t, dt, io); break;
+        case 16: hipLaunchKernelGGL((step_leaf_kernel<16, 256>), dim3(count), dim3(256), 0, s, c, first, count, level, t, dt, io); break;
+        case 32: hipLaunchKernelGGL((step_leaf_kernel<32, 256>), dim3(count), dim3(256), 0, s, c, first, count, level, t, dt, io); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_adjoint_gather(const Ctx &c, int mx, int first, int count, const int32_t *leaf_of_slot,
-                                 const double *abar, double *lam_out, hipStream_t s) {
+template <int MX, int NT>
+static void launch_adjoint_mx(const Ctx &c, int first, int count, double t, double dt, const int32_t *leaf_of_slot,
+                              const double *q_in, const double *lam_in, double *lam_out, hipStream_t s) {
+    switch (c.lim) {
+        case 1: hipLaunchKernelGGL((adjoint_kernel<MX, NT, 1>), dim3(count), dim3(NT), 0, s, c, first, count, t, dt, leaf_of_slot, q_in, lam_in, lam_out); break;
+        case 2: hipLaunchKernelGGL((adjoint_kernel<MX, NT, 2>), dim3(count), dim3(NT), 0, s, c, first, count, t, dt, leaf_of_slot, q_in, lam_in, lam_out); break;
+        case 3: hipLaunchKernelGGL((adjoint_kernel<MX, NT, 3>), dim3(count), dim3(NT), 0, s, c, first, count, t, dt, leaf_of_slot, q_in, lam_in, lam_out); break;
+        default: hipLaunchKernelGGL((adjoint_kernel<MX, NT, 0>), dim3(count), dim3(NT), 0, s, c, first, count, t, dt, leaf_of_slot, q_in, lam_in, lam_out); break;
+    }
+}
+
+hipError_t launch_adjoint(const Ctx &c, int mx, int first, int count, double t, double dt,
+                          const int32_t *leaf_of_slot, const double *q_in, const double *lam_in, double *lam_out,
+                          hipStream_t s) {
     if (count <= 0) return hipSuccess;
     switch (mx) {
-        case 8: hipLaunchKernelGGL(adjoint_gather_kernel<8>, dim3(count), dim3(64), 0, s, c, first, leaf_of_slot, abar, lam_out); break;
-        case 16: hipLaunchKernelGGL(adjoint_gather_kernel<16>, dim3(count), dim3(256), 0, s, c, first, leaf_of_slot, abar, lam_out); break;
-        case 32: hipLaunchKernelGGL(adjoint_gather_kernel<32>, dim3(count), dim3(256), 0, s, c, first, leaf_of_slot, abar, lam_out); break;
+        case 8: launch_adjoint_mx<8, 64>(c, first, count, t, dt, leaf_of_slot, q_in, lam_in, lam_out, s); break;
+        case 16: launch_adjoint_mx<16, 128>(c, first, count, t, dt, leaf_of_slot, q_in, lam_in, lam_out, s); break;
+        case 32: launch_adjoint_mx<32, 256>(c, first, count, t, dt, leaf_of_slot, q_in, lam_in, lam_out, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -858,26 +858,49 @@ fc_status fc_regrid(fc_patchstore *ps, int64_t nleaves, const fc_leaf *new_leave
     return FC_OK;
 }
 
-fc_status fc_adjoint_step(fc_patchstore *ps, int32_t level, double t, double dt, const double *q_in,
-                          const double *lambda_in, double *lambda_out, void *stream) {
+// a uniform periodic level of scalar advection (the leaf-order step and its
+// adjoint need every neighbour record to be a same-size one)
+static fc_status check_uniform_periodic(fc_patchstore *ps, int32_t level, double dt) {
     fc_status r = check_bound(ps);
     if (r != FC_OK) return r;
-    if (!q_in || !lambda_in || !lambda_out) return fail(FC_ERR_ARG, "null array");
-    if (ps->cfg.equation != FC_EQ_ADVECTION) return fail(FC_ERR_ARG, "the adjoint covers scalar advection");
+    if (ps->cfg.equation != FC_EQ_ADVECTION) return fail(FC_ERR_ARG, "scalar advection only");
     if (level < ps->cfg.min_level || level > ps->cfg.max_level) return fail(FC_ERR_ARG, "bad level");
-    const int n = (int)ps->mesh.lv.size();
-    if (ps->lr.count[level] != n) return fail(FC_ERR_ARG, "the adjoint needs a uniform mesh at `level`");
+    if (ps->lr.count[level] != (int)ps->mesh.lv.size()) return fail(FC_ERR_ARG, "needs a uniform mesh at `level`");
     if (!(dt > 0)) return fail(FC_ERR_ARG, "dt must be positive");
     for (int k = 0; k < 4; k++)
-        if (ps->cfg.bc[k] != FC_BC_PERIODIC) return fail(FC_ERR_ARG, "the adjoint covers periodic boundaries");
-    hipStream_t s = (hipStream_t)stream;
+        if (ps->cfg.bc[k] != FC_BC_PERIODIC) return fail(FC_ERR_ARG, "needs periodic boundaries");
+    return FC_OK;
+}
+
+static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+fc_status fc_step_uniform(fc_patchstore *ps, int32_t level, double t, double dt, const double *q_in, double *q_out,
+                          void *stream) {
+    fc_status r = check_uniform_periodic(ps, level, dt);
+    if (r != FC_OK) return r;
+    if (!q_in || !q_out) return fail(FC_ERR_ARG, "null array");
+    if (q_in == q_out) return fail(FC_ERR_ARG, "q_out must be a separate array");
+    if (!aligned16(q_in) || !aligned16(q_out)) return fail(FC_ERR_ARG, "arrays must be 16-byte aligned");
     const int32_t *ls = (const int32_t *)(ps->ws + ps->off_ls);
-    // transpose of the advance (its input tile gathered from q_in, ghosts
-    // by same-size copy) into the other buffer, then of the copy
     Ctx c = make_ctx(ps);
-    double *abar = ((ps->curmask >> level) & 1u) ? ps->q0 : ps->q1;
-    HIPCHK(launch_adjoint(c, ps->mx, ps->lr.start[level], n, t, dt, ls, q_in, lambda_in, abar, s));
-    HIPCHK(launch_adjoint_gather(c, ps->mx, ps->lr.start[level], n, ls, abar, lambda_out, s));
+    HIPCHK(launch_step_leaf(c, ps->mx, level, ps->lr.start[level], ps->lr.count[level], t, dt, ls, q_in, q_out,
+                            (hipStream_t)stream));
+    return FC_OK;
+}
+
+fc_status fc_adjoint_step(fc_patchstore *ps, int32_t level, double t, double dt, const double *q_in,
+                          const double *lambda_in, double *lambda_out, void *stream) {
+    fc_status r = check_uniform_periodic(ps, level, dt);
+    if (r != FC_OK) return r;
+    if (!q_in || !lambda_in || !lambda_out) return fail(FC_ERR_ARG, "null array");
+    if (lambda_out == lambda_in || lambda_out == q_in) return fail(FC_ERR_ARG, "lambda_out must be a separate array");
+    if (!aligned16(q_in) || !aligned16(lambda_in) || !aligned16(lambda_out))
+        return fail(FC_ERR_ARG, "arrays must be 16-byte aligned");
+    const int32_t *ls = (const int32_t *)(ps->ws + ps->off_ls);
+    // transpose of copy + advance in one gather pass
+    Ctx c = make_ctx(ps);
+    HIPCHK(launch_adjoint(c, ps->mx, ps->lr.start[level], ps->lr.count[level], t, dt, ls, q_in, lambda_in, lambda_out,
+                          (hipStream_t)stream));
     return FC_OK;
 }
 

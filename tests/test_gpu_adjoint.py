@@ -45,6 +45,42 @@ def test_adjoint_step_matches_oracle(B, oracle_lib, limiter, level, mx):
     assert rel(g, r) <= 1e-12
 
 
+@pytest.mark.parametrize("limiter", ["mc", "lw", "first", "minmod"])
+@pytest.mark.parametrize("level,mx", [(1, 32), (2, 16), (3, 8)])
+def test_leaf_order_step_equals_graph_step_bitwise(B, limiter, level, mx):
+    """fc_step_uniform (leaf order in and out) reproduces the store's
+    graph-mode steps bit for bit, at the times the store accumulates."""
+    import torch
+    L = S.uniform_leaves(level)
+    q0 = torch.tensor(S.sample_on_leaves(S.gaussians(S.gaussian_params(5)), L, mx), device="cuda")
+    ps = B.PatchStore(L, mx=mx, velocity="swirl", vel_params=(1.0, 0, 0), limiter=limiter)
+    dt = 0.9 / (mx << level)
+    ps.time = 0.05
+    ps.set_interior(q0)
+    q, t = q0, 0.05
+    for _ in range(3):
+        q = ps.step_uniform(level, t, dt, q)
+        t = t + dt
+    ps.coarse_steps(dt, 3, "graph")
+    assert torch.equal(q, ps.interior())
+
+
+def test_leaf_order_step_rejects_adaptive_meshes_and_aliasing(B):
+    import torch
+    L = S.refine_leaves(S.uniform_leaves(1), [0])
+    ps = B.PatchStore(L, mx=8, velocity="swirl", vel_params=(1.0, 0, 0))
+    q = torch.zeros((len(L), 1, 8, 8), dtype=torch.float64, device="cuda")
+    with pytest.raises(RuntimeError):
+        ps.step_uniform(1, 0.0, 0.01, q)
+    L = S.uniform_leaves(1)
+    ps = B.PatchStore(L, mx=8, velocity="swirl", vel_params=(1.0, 0, 0))
+    q = torch.zeros((len(L), 1, 8, 8), dtype=torch.float64, device="cuda")
+    from paper_1703_03116_amd import binding
+    with pytest.raises(RuntimeError):
+        binding._check(binding.lib().fc_step_uniform(ps._h, 1, 0.0, 0.01, binding.C.c_void_p(q.data_ptr()),
+                                                      binding.C.c_void_p(q.data_ptr()), binding._stream()))
+
+
 def test_reverse_sweep_matches_oracle_discrete_adjoint(B, oracle_lib):
     """Whole gradient through 40 MC-limited steps with checkpoints every 8."""
     import torch
