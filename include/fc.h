@@ -163,6 +163,14 @@ fc_status fc_advance_level(fc_patchstore *ps, int32_t level, double t, double dt
  * advances by nsteps * dt_coarse. */
 fc_status fc_advance_coarse_steps(fc_patchstore *ps, double dt_coarse, int32_t nsteps, int32_t mode,
                                   double *cfl_dev, void *stream);
+/* Set-up for the graph modes: capture and instantiate, without running them,
+ * the graphs that a call fc_advance_coarse_steps(ps, dt_coarse, nsteps,
+ * mode) made next (from the store's current parities) replays, so that the
+ * one-time capture cost stays out of that call.  The schedule captured is
+ * the multirate recursion of the time-stepping section.  A no-op for the
+ * other modes.  FC_ERR_ARG for dt_coarse <= 0, nsteps < 0 or an unknown
+ * mode.  Allocates nothing on the device beyond the graphs themselves. */
+fc_status fc_prepare_steps(fc_patchstore *ps, double dt_coarse, int32_t nsteps, int32_t mode, void *stream);
 /* Store time (host value of the time all levels are synchronised at). */
 fc_status fc_get_time(const fc_patchstore *ps, double *t);
 fc_status fc_set_time(fc_patchstore *ps, double t);

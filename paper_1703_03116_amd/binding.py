@@ -30,7 +30,7 @@ EXPORTS = ["fc_last_error", "fc_patchstore_create", "fc_patchstore_destroy", "fc
            "fc_patchstore_bind", "fc_patchstore_info", "fc_patchstore_leaves", "fc_set_interior",
            "fc_get_interior", "fc_get_patches", "fc_ghost_fill", "fc_advance_level",
            "fc_advance_coarse_steps", "fc_get_time", "fc_set_time", "fc_tag_refine", "fc_adapt", "fc_regrid",
-           "fc_step_uniform", "fc_adjoint_step", "fc_check_device", "fc_autotune", "fc_set_variant", "fc_set_persistent_grid"]
+           "fc_prepare_steps", "fc_step_uniform", "fc_adjoint_step", "fc_check_device", "fc_autotune", "fc_set_variant", "fc_set_persistent_grid"]
 
 
 class FcError(RuntimeError):
@@ -79,6 +79,7 @@ def lib():
         L.fc_tag_refine.argtypes = [vp, C.c_double, C.c_double, vp, vp, vp]
         L.fc_adapt.argtypes = [vp, C.POINTER(C.c_int8), C.POINTER(Leaf), C.c_int64, C.POINTER(C.c_int64)]
         L.fc_regrid.argtypes = [vp, C.c_int64, C.POINTER(Leaf), vp]
+        L.fc_prepare_steps.argtypes = [vp, C.c_double, C.c_int32, C.c_int32, vp]
         L.fc_step_uniform.argtypes = [vp, C.c_int32, C.c_double, C.c_double, vp, vp, vp]
         L.fc_adjoint_step.argtypes = [vp, C.c_int32, C.c_double, C.c_double, vp, vp, vp, vp]
         L.fc_check_device.argtypes = [vp, vp]
@@ -204,6 +205,11 @@ class PatchStore:
     def advance_level(self, level, t, dt, cfl=None):
         p = C.c_void_p(cfl.data_ptr()) if cfl is not None else None
         _check(lib().fc_advance_level(self._h, int(level), float(t), float(dt), p, _stream()))
+
+    def prepare_steps(self, dt_coarse, nsteps, mode="graph"):
+        """Capture the graphs the next coarse_steps(dt_coarse, nsteps, mode)
+        replays (one-time set-up kept out of that call)."""
+        _check(lib().fc_prepare_steps(self._h, float(dt_coarse), int(nsteps), MODE[mode], _stream()))
 
     def coarse_steps(self, dt_coarse, nsteps=1, mode="per_level", cfl=None):
         p = C.c_void_p(cfl.data_ptr()) if cfl is not None else None

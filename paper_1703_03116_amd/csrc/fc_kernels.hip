@@ -320,38 +320,67 @@ __device__ __forceinline__ double correction(double W, double Wu, double as, dou
     return (W * Wu > 0.0) ? k * copysign(m, W) : 0.0;  // k < 0 where lam |s| > 1
 }
 
-// velocity factors of a patch into LDS
-// at the mid-step time t + dt/2, with t = *tdev + t when tdev is given
-// (threads k0 .. k0+MX+1 do the work; blockDim >= k0 + MX + 2)
+// Velocity factors of a patch into LDS, at the mid-step time t + dt/2 with
+// t = *tdev + t when tdev is given (threads k0 .. k0+MX+1 do the work;
+// blockDim >= k0 + MX + 2).  Two parts: fetch_velocity issues the loads (the
+// device-resident start time first), put_velocity evaluates c(t) and writes
+// LDS; a caller that issues its tile loads between the two lets the cosine
+// run while they are in flight (a wave's loads retire in order, so a wait
+// for a load issued after the tile would wait for the whole tile).
+struct VelRegs {
+    double tv, ex, ey, cy, cx;
+};
+
 template <int MX>
-__device__ void load_velocity(const Ctx &c, ScalarSmem<MX> &s, int l, int gx, int gy, double t, double dt,
-                              const double *tdev, int k0) {
-    const int n = MX << l;
+__device__ __forceinline__ void fetch_velocity(const Ctx &c, int l, int gx, int gy, const double *tdev, int k0,
+                                               VelRegs &v) {
     const int k = (int)threadIdx.x - k0;
-    if (c.velocity == 2) {
-        if (k >= 0 && k < MX + 2) {
-            if (tdev) {
-                // a per-lane zero the compiler cannot see through keeps this a
-                // vector load: a scalar one would be waited on together with
-                // the kernel arguments, ahead of the first tile loads
-                int zero;
-                asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
-                t = tdev[zero] + t;
-            }
-            const double tm = t + 0.5 * dt;
-            const double ct = cos(M_PI * (tm * c.vel_invT));
-            const double *vt = c.vt[l];
-            const double *ex = vt + vt_ex(n, MB), *cxv = vt + vt_cx(n, MB);
-            const double *ey = vt + vt_ey(n, MB), *cyv = vt + vt_cy(n, MB);
-            if (k <= MX) { s.ux[k] = ex[gx + k]; s.vy[k] = ey[gy + k]; }
-            s.uy[k] = cyv[gy + k - 1] * ct;
-            s.vx[k] = -(cxv[gx + k - 1] * ct);
+    v.tv = v.ex = v.ey = v.cy = v.cx = 0.0;
+    if (c.velocity == 2 && k >= 0 && k < MX + 2) {
+        if (tdev) {
+            // a per-lane zero the compiler cannot see through keeps this a
+            // vector load: a scalar one would be waited on together with
+            // the kernel arguments, ahead of the first tile loads
+            int zero;
+            asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
+            v.tv = tdev[zero];
         }
-    } else if (k >= 0 && k < MX + 2) {
+        const int n = MX << l;
+        const double *vt = c.vt[l];
+        if (k <= MX) {
+            v.ex = vt[vt_ex(n, MB) + gx + k];
+            v.ey = vt[vt_ey(n, MB) + gy + k];
+        }
+        v.cy = vt[vt_cy(n, MB) + gy + k - 1];
+        v.cx = vt[vt_cx(n, MB) + gx + k - 1];
+    }
+}
+
+template <int MX>
+__device__ __forceinline__ void put_velocity(const Ctx &c, ScalarSmem<MX> &s, double t, double dt,
+                                             const double *tdev, int k0, const VelRegs &v) {
+    const int k = (int)threadIdx.x - k0;
+    if (k < 0 || k >= MX + 2) return;
+    if (c.velocity == 2) {
+        if (tdev) t = v.tv + t;
+        const double tm = t + 0.5 * dt;
+        const double ct = cos(M_PI * (tm * c.vel_invT));
+        if (k <= MX) { s.ux[k] = v.ex; s.vy[k] = v.ey; }
+        s.uy[k] = v.cy * ct;
+        s.vx[k] = -(v.cx * ct);
+    } else {
         if (k <= MX) { s.ux[k] = c.vel_u; s.vy[k] = c.vel_v; }
         s.uy[k] = 1.0;
         s.vx[k] = 1.0;
     }
+}
+
+template <int MX>
+__device__ void load_velocity(const Ctx &c, ScalarSmem<MX> &s, int l, int gx, int gy, double t, double dt,
+                              const double *tdev, int k0) {
+    VelRegs v;
+    fetch_velocity<MX>(c, l, gx, gy, tdev, k0, v);
+    put_velocity<MX>(c, s, t, dt, tdev, k0, v);
 }
 
 // One segment of one interior line: edges e0 .. e0+SEG (edge e lies between
@@ -563,6 +592,14 @@ __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, 
     } else {
         constexpr int NG = N * N - MX * MX;
         constexpr int NV = (MX * MX / 2 + NT - 1) / NT, NGH = (NG + NT - 1) / NT;
+        // A complete periodic level: every neighbour is a same-level patch
+        // whose slot follows from the Morton index, so no record is read and
+        // all loads of the step leave at once, the velocity's first.
+        const bool complete = lev >= 0 && ((c.complete >> lev) & 1u);
+        const uint32_t m = (uint32_t)(p - c.lstart[l]);
+        const int ix = (int)morton_compact(m), iy = (int)morton_compact(m >> 1), wrap = (1 << l) - 1;
+        VelRegs vr;
+        if (complete) fetch_velocity<MX>(c, l, ix * MX, iy * MX, tdev, NI, vr);
         double2 iv[NV];
 #pragma unroll
         for (int v = 0; v < NV; v++) {
@@ -570,12 +607,7 @@ __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, 
             if (k < MX * MX / 2) iv[v] = *reinterpret_cast<const double2 *>(&in[base + (j + MB) * N + i + MB]);
         }
         const int g0 = (tid + NT - NI) % NT;  // the odd ghost cells go to a lightly loaded wave
-        if (lev >= 0 && ((c.complete >> lev) & 1u)) {
-            // A complete periodic level: every neighbour is a same-level
-            // patch whose slot follows from the Morton index, so no record is
-            // read and all loads of the step leave at once.
-            const uint32_t m = (uint32_t)(p - c.lstart[l]);
-            const int ix = (int)morton_compact(m), iy = (int)morton_compact(m >> 1), wrap = (1 << l) - 1;
+        if (complete) {
             double gv[NGH];
             int gi[NGH], gj[NGH];
 #pragma unroll
@@ -591,7 +623,7 @@ __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, 
                 }
             }
             const double sold = (slot && tid == NT - 1) ? __longlong_as_double((long long)*slot) : 0.0;
-            load_velocity<MX>(c, s, l, ix * MX, iy * MX, t, dt, tdev, NI);
+            put_velocity<MX>(c, s, t, dt, tdev, NI, vr);
             if (slot && tid == NT - 1) s.red[15] = sold;
 #pragma unroll
             for (int v = 0; v < NV; v++) {

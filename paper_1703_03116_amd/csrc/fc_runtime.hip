@@ -616,6 +616,63 @@ fc_status fc_set_time(fc_patchstore *ps, double t) {
     return FC_OK;
 }
 
+// Graph forms: replay (launch) or only capture (!launch) the graphs that
+// `nsteps` coarse steps from the current parities need: chunks of
+// FC_TCHUNK coarse steps, then single steps.  Graphs are captured on demand
+// and kept per slot (keyed by parities and dt_coarse).
+static fc_status graph_steps(fc_patchstore *ps, double dt_coarse, int nsteps, int mode, int grid, bool launch,
+                             hipStream_t s) {
+    fc_status r = FC_OK;
+    const int kChunk = FC_TCHUNK;
+    if (ps->gnt != ps->nt || ps->chunk != kChunk) {
+        drop_graph(ps);
+        ps->gnt = ps->nt;
+        ps->chunk = kChunk;
+    }
+    uint32_t allm = 0, step_flip = 0;
+    for (int l = 0; l < FC_MAXLEV; l++)
+        if (ps->lr.count[l] > 0) allm |= 1u << l;
+    for (const SchedEntry &e : ps->sched) step_flip ^= e.level < 0 ? allm : (1u << e.level);
+    uint32_t mask = ps->curmask;  // parities at the start of the next replay
+    // graph slot for n coarse steps from the current parities (captured on demand)
+    auto slot = [&](int n, int &which) -> fc_status {
+        if (mode == FC_MODE_PERSISTENT_GRAPH) {
+            which = n == kChunk ? 1 : 0;
+            return ps->gexec[which] ? FC_OK : capture(ps, which, n, grid);
+        }
+        auto fits = [&](int k) { return ps->gexec[k] && ps->gmask[k] == mask && ps->gdt[k] == dt_coarse; };
+        if (n == kChunk) which = 3;
+        else which = fits(4) ? 4 : 2;
+        if (fits(which)) return FC_OK;
+        if (which == 2 && ps->gexec[2] && ps->gdt[2] == dt_coarse) which = 4;  // keep the other parity's graph
+        drop_slot(ps, which);
+        return capture_levels(ps, which, n, mask, dt_coarse);
+    };
+    int k = 0, which = 0;
+    for (; k + kChunk <= nsteps; k += kChunk) {
+        if ((r = slot(kChunk, which)) != FC_OK) return r;
+        if (launch) HIPCHK(hipGraphLaunch(ps->gexec[which], s));
+        if (kChunk & 1) mask ^= step_flip;
+    }
+    for (; k < nsteps; k++) {
+        if ((r = slot(1, which)) != FC_OK) return r;
+        if (launch) HIPCHK(hipGraphLaunch(ps->gexec[which], s));
+        mask ^= step_flip;
+    }
+    return FC_OK;
+}
+
+fc_status fc_prepare_steps(fc_patchstore *ps, double dt_coarse, int32_t nsteps, int32_t mode, void *stream) {
+    fc_status r = check_bound(ps);
+    if (r != FC_OK) return r;
+    if (!(dt_coarse > 0) || nsteps < 0) return fail(FC_ERR_ARG, "bad step arguments");
+    if (mode == FC_MODE_PER_LEVEL || mode == FC_MODE_FUSED_LEVELS || mode == FC_MODE_FUSED) return FC_OK;
+    if (mode != FC_MODE_FUSED_GRAPH && mode != FC_MODE_PERSISTENT_GRAPH) return fail(FC_ERR_ARG, "unknown mode");
+    if (ps->pgrid <= 0) return fail(FC_ERR_HIP, "persistent kernel has no resident blocks");
+    const int grid = ps->pgrid_user > 0 ? std::min(ps->pgrid_user, ps->pgrid) : ps->pgrid;
+    return graph_steps(ps, dt_coarse, nsteps, mode, grid, false, (hipStream_t)stream);
+}
+
 fc_status fc_advance_coarse_steps(fc_patchstore *ps, double dt_coarse, int32_t nsteps, int32_t mode, double *cfl_dev,
                                   void *stream) {
     fc_status r = check_bound(ps);
@@ -689,41 +746,7 @@ fc_status fc_advance_coarse_steps(fc_patchstore *ps, double dt_coarse, int32_t n
             HIPCHK(launch_persistent(c, LaunchCfg{ps->mx, ps->nt}, sched, (int)ps->sched.size(), lrd, m, st, grid, s));
         }
     } else {
-        if (ps->gnt != ps->nt || ps->chunk != kChunk) {
-            drop_graph(ps);
-            ps->gnt = ps->nt;
-            ps->chunk = kChunk;
-        }
-        uint32_t allm = 0, step_flip = 0;
-        for (int l = 0; l < FC_MAXLEV; l++)
-            if (ps->lr.count[l] > 0) allm |= 1u << l;
-        for (const SchedEntry &e : ps->sched) step_flip ^= e.level < 0 ? allm : (1u << e.level);
-        uint32_t mask = ps->curmask;  // parities at the start of the next replay
-        // graph slot for n coarse steps from the current parities (captured on demand)
-        auto slot = [&](int n, int &which) -> fc_status {
-            if (mode == FC_MODE_PERSISTENT_GRAPH) {
-                which = n == kChunk ? 1 : 0;
-                return ps->gexec[which] ? FC_OK : capture(ps, which, n, grid);
-            }
-            auto fits = [&](int k) { return ps->gexec[k] && ps->gmask[k] == mask && ps->gdt[k] == dt_coarse; };
-            if (n == kChunk) which = 3;
-            else which = fits(4) ? 4 : 2;
-            if (fits(which)) return FC_OK;
-            if (which == 2 && ps->gexec[2] && ps->gdt[2] == dt_coarse) which = 4;  // keep the other parity's graph
-            drop_slot(ps, which);
-            return capture_levels(ps, which, n, mask, dt_coarse);
-        };
-        int k = 0, which = 0;
-        for (; k + kChunk <= nsteps; k += kChunk) {
-            if ((r = slot(kChunk, which)) != FC_OK) return r;
-            HIPCHK(hipGraphLaunch(ps->gexec[which], s));
-            if (kChunk & 1) mask ^= step_flip;
-        }
-        for (; k < nsteps; k++) {
-            if ((r = slot(1, which)) != FC_OK) return r;
-            HIPCHK(hipGraphLaunch(ps->gexec[which], s));
-            mask ^= step_flip;
-        }
+        if ((r = graph_steps(ps, dt_coarse, nsteps, mode, grid, true, s)) != FC_OK) return r;
     }
     // host mirror of the device bookkeeping
     uint32_t allmask = 0;

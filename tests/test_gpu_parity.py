@@ -228,6 +228,26 @@ def test_graph_replays_track_parity_and_step(B):
     b.check()
 
 
+@pytest.mark.parametrize("mode", ["graph", "persistent_graph"])
+def test_prepared_graphs_replay_the_same_steps(B, mode):
+    """Graphs captured ahead by prepare_steps (after an odd number of steps,
+    so from the other parity) give the same bits as the on-demand ones, and
+    prepare_steps itself changes neither the solution nor the time."""
+    w = S.workload("hump_l23")
+    dt = w["dt_coarse"]
+    a = B.from_workload(w)
+    b = B.from_workload(w)
+    for ps in (a, b):
+        ps.coarse_steps(dt, 3, "per_level")
+    q3, t3 = b.interior().clone(), b.time
+    b.prepare_steps(dt, 53, mode)
+    assert torch.equal(b.interior(), q3) and b.time == t3
+    a.coarse_steps(dt, 53, "per_level")
+    b.coarse_steps(dt, 53, mode)
+    assert torch.equal(a.interior(), b.interior())
+    b.check()
+
+
 @pytest.mark.parametrize("mx", [8, 16, 32])
 def test_variants_bitwise(B, mx):
     """Every launch variant (threads per patch) computes the same bits."""
