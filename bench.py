@@ -104,7 +104,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=500,
+                    help="untimed steps first (the GPU's clocks settle over the first few milliseconds of load)")
     ap.add_argument("--level", type=int, default=5)
     ap.add_argument("--mx", type=int, default=32)
     ap.add_argument("--workload", default="swirl_uniform",
