@@ -81,6 +81,7 @@ struct Ctx {
     int32_t lstart[FC_MAXLEV];
     unsigned long long *cflp;  // per-slot max Courant number (bits of a non-negative double) [cap];
                                // NULL: not recorded
+    int32_t stream_out;        // advance output by streaming (nontemporal) stores
 };
 
 // Velocity factor tables of one level with n = mx 2^l cells per axis and m

@@ -302,7 +302,7 @@ constexpr int scalar_seg() {
 
 // A streaming store of two doubles (16-byte aligned): the step's output is
 // not read again within the launch, so it need not stay dirty in the XCD's
-// L2 until the end-of-kernel write-back.
+// L2 until the end-of-kernel write-back (the host decides where it pays).
 typedef double dpair __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ void store_stream2(double *p, double a, double b) {
     dpair v;
@@ -744,12 +744,14 @@ __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, 
         double *qo = io->qout + (size_t)io->leaf_of_slot[p] * MX * MX;
         for (int k = threadIdx.x; k < MX * MX / 2; k += NT) {
             const int i = 2 * (k % (MX / 2)), j = k / (MX / 2) + MB;
-            store_stream2(qo + 2 * k, s.q[j * NP + i + MB], s.q[j * NP + i + MB + 1]);
+            // plain stores: the next step reads this state right away
+            *reinterpret_cast<double2 *>(qo + 2 * k) = make_double2(s.q[j * NP + i + MB], s.q[j * NP + i + MB + 1]);
         }
     } else {
         for (int k = threadIdx.x; k < MX * N / 2; k += NT) {
             const int i = 2 * (k % (N / 2)), j = k / (N / 2) + MB;
-            store_stream2(&out[base + j * N + i], s.q[j * NP + i], s.q[j * NP + i + 1]);
+            if (c.stream_out) store_stream2(&out[base + j * N + i], s.q[j * NP + i], s.q[j * NP + i + 1]);
+            else *reinterpret_cast<double2 *>(&out[base + j * N + i]) = make_double2(s.q[j * NP + i], s.q[j * NP + i + 1]);
         }
     }
     cfl = fmax(cfl, __longlong_as_double((long long)s.cfl));
@@ -1321,7 +1323,7 @@ __global__ void __launch_bounds__(NT, (MX == 32 ? 4 : 1)) adjoint_kernel(Ctx c, 
         const int k0 = tid - NI, i = k0 % MX, e0 = (k0 / MX) * SEG;
         double *lo = lam_out + (size_t)leaf_of_slot[p] * PS;
 #pragma unroll
-        for (int k = 0; k < SEG; k++) __builtin_nontemporal_store(s.part[(e0 + k) * (MX + 1) + i] + R[k], &lo[(e0 + k) * MX + i]);
+        for (int k = 0; k < SEG; k++) lo[(e0 + k) * MX + i] = s.part[(e0 + k) * (MX + 1) + i] + R[k];
     }
 }
 
