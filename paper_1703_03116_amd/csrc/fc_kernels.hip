@@ -467,17 +467,17 @@ __device__ __forceinline__ void sweep_outer(ScalarSmem<MX> &s, int dir, int line
     }
 }
 
-// Final update of a cell from the two partials and the transverse terms:
-//   Q_new = Rx + Ry + lam^2/2 ((TF_{i+1/2} - TF_{i-1/2}) + (TG_{j+1/2} - TG_{j-1/2}))
+// Final update of a cell, as two direction parts:
+//   Q_new = [Rx + lam^2/2 (TF_{i+1/2} - TF_{i-1/2})] + [Ry + lam^2/2 (TG_{j+1/2} - TG_{j-1/2})]
 // with TF(e) = u+ TY(e-1) + u- TY(e) on x-edges and TG(e) = v+ TX(e-1) +
-// v- TX(e) on y-edges.  Cells of the lower half of the patch are finished
-// row-wise by the x-items (Rx in registers, Ry from LDS), those of the upper
-// half column-wise by the y-items; both forms evaluate the same expression.
-// The result goes to the tile (staging for a coalesced store).
+// v- TX(e) on y-edges.  Each item adds the transverse term of its own
+// line's edges, evaluated once per edge: the x-items form the first bracket
+// for their row segment, the y-items the second for their column segment;
+// the store sums the two.
 template <int MX, int SEG>
-__device__ __forceinline__ void update_row(ScalarSmem<MX> &s, int j, int e0, double lam, const double (&R)[SEG]) {
-    constexpr int NP = ScalarSmem<MX>::NP, S = ScalarSmem<MX>::S;
-    const double uyj = s.uy[j + 1], vyd = s.vy[j], vyu = s.vy[j + 1];
+__device__ __forceinline__ void part_row(const ScalarSmem<MX> &s, int j, int e0, double lam, double (&R)[SEG]) {
+    constexpr int S = ScalarSmem<MX>::S;
+    const double uyj = s.uy[j + 1];
     double ty[SEG + 2];
 #pragma unroll
     for (int k = 0; k < SEG + 2; k++) ty[k] = s.ty[(e0 + k) * S + j];  // TY(e0 - 1 + k, j)
@@ -489,21 +489,13 @@ __device__ __forceinline__ void update_row(ScalarSmem<MX> &s, int j, int e0, dou
     }
     const double hl2 = 0.5 * lam * lam;
 #pragma unroll
-    for (int k = 0; k < SEG; k++) {
-        const int cc = e0 + k;
-        const double txd = s.tx[j * S + cc], txc = s.tx[(j + 1) * S + cc], txu = s.tx[(j + 2) * S + cc];
-        const double vxc = s.vx[cc + 1];
-        const double vd = vyd * vxc, vu = vyu * vxc;
-        const double tgd = posp(vd) * txd + negp(vd) * txc;
-        const double tgu = posp(vu) * txc + negp(vu) * txu;
-        s.q[(j + MB) * NP + cc + MB] = (R[k] + s.part[j * S + cc]) + hl2 * ((tf[k + 1] - tf[k]) + (tgu - tgd));
-    }
+    for (int k = 0; k < SEG; k++) R[k] = R[k] + hl2 * (tf[k + 1] - tf[k]);
 }
 
 template <int MX, int SEG>
-__device__ __forceinline__ void update_col(ScalarSmem<MX> &s, int i, int e0, double lam, const double (&R)[SEG]) {
-    constexpr int NP = ScalarSmem<MX>::NP, S = ScalarSmem<MX>::S;
-    const double vxi = s.vx[i + 1], uxl = s.ux[i], uxr = s.ux[i + 1];
+__device__ __forceinline__ void part_col(const ScalarSmem<MX> &s, int i, int e0, double lam, double (&R)[SEG]) {
+    constexpr int S = ScalarSmem<MX>::S;
+    const double vxi = s.vx[i + 1];
     double tx[SEG + 2];
 #pragma unroll
     for (int k = 0; k < SEG + 2; k++) tx[k] = s.tx[(e0 + k) * S + i];  // TX(i, e0 - 1 + k)
@@ -515,23 +507,15 @@ __device__ __forceinline__ void update_col(ScalarSmem<MX> &s, int i, int e0, dou
     }
     const double hl2 = 0.5 * lam * lam;
 #pragma unroll
-    for (int k = 0; k < SEG; k++) {
-        const int cc = e0 + k;
-        const double tyl = s.ty[i * S + cc], tyc = s.ty[(i + 1) * S + cc], tyr = s.ty[(i + 2) * S + cc];
-        const double uyc = s.uy[cc + 1];
-        const double ul = uxl * uyc, ur = uxr * uyc;
-        const double tfl = posp(ul) * tyl + negp(ul) * tyc;
-        const double tfr = posp(ur) * tyc + negp(ur) * tyr;
-        s.q[(cc + MB) * NP + i + MB] = (s.part[cc * S + i] + R[k]) + hl2 * ((tfr - tfl) + (tg[k + 1] - tg[k]));
-    }
+    for (int k = 0; k < SEG; k++) R[k] = R[k] + hl2 * (tg[k + 1] - tg[k]);
 }
 
 // One step on patch p of level l: stage its tile, compute, write the new
 // interior into the level's other buffer.  FUSED: ghosts evaluated on the fly
 // instead of read from the patch's own ghost cells.
-//   Edge sweeps: one item per (line, segment); the x-items of the interior
-//   rows keep their partial sums in registers and, after the barrier, finish
-//   the update of their cells.
+//   Edge sweeps: one item per (line, segment); every item keeps its
+//   direction's partial sums in registers and, after the barrier, adds its
+//   transverse term to them.
 // Arrays of a uniform periodic level in input-leaf order (the form the
 // adjoint's recomputation steps through): [nleaves][mx][mx].
 struct LeafIO {
@@ -551,8 +535,9 @@ __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, 
     constexpr int N = MX + 2 * MB, NP = ScalarSmem<MX>::NP;
     // Work split (items = line segments): threads [0, NI) sweep the interior
     // rows, [NI, 2 NI) the interior columns; each half of either set covers
-    // one half of the patch.  The lower-half rows and the upper-half columns
-    // finish the update (the other two store their partials).  The four
+    // one half of the patch.  After the sweeps every item adds its
+    // direction's transverse term and parks its part in LDS; the store sums
+    // the row and column parts of each cell.  The four
     // outer lines are cut into segments of two cells, one per thread of the
     // lower-half column items (or of idle threads), so that no wave carries a
     // long extra chain into the barrier; the odd ghost cells and c(t) go to
@@ -705,18 +690,10 @@ __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, 
         line = half * (MX / 2) + r % (MX / 2);
         e0 = (r / (MX / 2)) * SEG;
         sweep_segment<MX, SEG, LIM, 0>(s, line, e0, lam, R, amax);
-        if (half == 1) {
-#pragma unroll
-            for (int k = 0; k < SEG; k++) s.part[line * S + e0 + k] = R[k];
-        }
     } else if (ys) {
         line = r % MX;
         e0 = (half * (NSEG / 2) + r / MX) * SEG;
         sweep_segment<MX, SEG, LIM, 1>(s, line, e0, lam, R, amax);
-        if (half == 0) {
-#pragma unroll
-            for (int k = 0; k < SEG; k++) s.part[(e0 + k) * S + line] = R[k];
-        }
     }
     if (tid >= GT0 && tid < GT0 + NO) {  // rows -1, MX and columns -1, MX: TX, TY only
         const int k = tid - GT0, g = k / (MX / SO);
@@ -732,8 +709,17 @@ __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, 
         if ((tid & 63) == 0 && m > 0.0) atomicMax(&s.cfl, (unsigned long long)__double_as_longlong(m));
     }
     __syncthreads();
-    if (xs && half == 0) update_row<MX, SEG>(s, line, e0, lam, R);
-    else if (ys && half == 1) update_col<MX, SEG>(s, line, e0, lam, R);
+    // direction parts: rows into s.part, columns into the tile's interior
+    // (nothing reads the staged interior after the sweeps)
+    if (xs) {
+        part_row<MX, SEG>(s, line, e0, lam, R);
+#pragma unroll
+        for (int k = 0; k < SEG; k++) s.part[line * S + e0 + k] = R[k];
+    } else if (ys) {
+        part_col<MX, SEG>(s, line, e0, lam, R);
+#pragma unroll
+        for (int k = 0; k < SEG; k++) s.q[(e0 + k + MB) * NP + line + MB] = R[k];
+    }
     __syncthreads();
     // Whole rows go out, ghost columns included (they carry the values the
     // step gathered; nothing reads a patch's own ghost cells before the next
@@ -743,15 +729,22 @@ __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, 
     if constexpr (LEAF) {
         double *qo = io->qout + (size_t)io->leaf_of_slot[p] * MX * MX;
         for (int k = threadIdx.x; k < MX * MX / 2; k += NT) {
-            const int i = 2 * (k % (MX / 2)), j = k / (MX / 2) + MB;
+            const int i = 2 * (k % (MX / 2)), j = k / (MX / 2);
+            const double a = s.part[j * S + i] + s.q[(j + MB) * NP + i + MB];
+            const double b = s.part[j * S + i + 1] + s.q[(j + MB) * NP + i + MB + 1];
             // plain stores: the next step reads this state right away
-            *reinterpret_cast<double2 *>(qo + 2 * k) = make_double2(s.q[j * NP + i + MB], s.q[j * NP + i + MB + 1]);
+            *reinterpret_cast<double2 *>(qo + 2 * k) = make_double2(a, b);
         }
     } else {
         for (int k = threadIdx.x; k < MX * N / 2; k += NT) {
             const int i = 2 * (k % (N / 2)), j = k / (N / 2) + MB;
-            if (c.stream_out) store_stream2(&out[base + j * N + i], s.q[j * NP + i], s.q[j * NP + i + 1]);
-            else *reinterpret_cast<double2 *>(&out[base + j * N + i]) = make_double2(s.q[j * NP + i], s.q[j * NP + i + 1]);
+            double a = s.q[j * NP + i], b = s.q[j * NP + i + 1];
+            if (i >= MB && i < MX + MB) {  // pairs never straddle (MB, MX even)
+                a = s.part[(j - MB) * S + i - MB] + a;
+                b = s.part[(j - MB) * S + i - MB + 1] + b;
+            }
+            if (c.stream_out) store_stream2(&out[base + j * N + i], a, b);
+            else *reinterpret_cast<double2 *>(&out[base + j * N + i]) = make_double2(a, b);
         }
     }
     cfl = fmax(cfl, __longlong_as_double((long long)s.cfl));
