@@ -229,6 +229,9 @@ fc_status fc_check_device(fc_patchstore *ps, void *stream);
  * only if it is at least 5% faster (best of three interleaved timing rounds).
  * Returns the chosen threads per patch. */
 fc_status fc_autotune(fc_patchstore *ps, int32_t *threads_out, void *stream);
+/* Set the threads per patch directly: 64 or 128 at mx = 8; 64, 128 or 256 at
+ * mx = 16 (also 512 for shallow water); 128, 256 or 512 at mx = 32
+ * (FC_ERR_ARG otherwise).  Drops captured graphs. */
 fc_status fc_set_variant(fc_patchstore *ps, int32_t threads_per_patch);
 /* Workgroups of the persistent kernel: 0 = as many as can be co-resident
  * (occupancy x compute units), else min(grid, that).  max_grid (may be

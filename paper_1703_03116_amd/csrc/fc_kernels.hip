@@ -813,7 +813,11 @@ __device__ void reduce_cfl_slot(double v, double *red, unsigned long long *slot,
 // tile admits four workgroups per CU, and the register budget is set so that
 // all four are resident.
 template <int MX, int NT, int EQ>
-constexpr int min_waves() { return (EQ == 0 && MX == 32) ? NT / 64 : 1; }
+constexpr int min_waves() {
+    // scalar mx = 32: four workgroups per CU; shallow water with 512 threads:
+    // two workgroups per CU (registers capped at 128 per lane)
+    return (EQ == 0 && MX == 32) ? NT / 64 : ((EQ == 1 && NT == 512) ? 4 : 1);
+}
 
 template <int MX, int NT, bool FUSED>
 __global__ void __launch_bounds__(NT, (min_waves<MX, NT, 0>())) advance_scalar_kernel(Ctx c, int first, int count, int level, double t,
@@ -1101,7 +1105,7 @@ __device__ void advance_swe_patch(const Ctx &c, const View &w, SweSmem<MX> &s, i
 }
 
 template <int MX, int NT, bool FUSED>
-__global__ void __launch_bounds__(NT) advance_swe_kernel(Ctx c, int first, int count, double dt) {
+__global__ void __launch_bounds__(NT, (min_waves<MX, NT, 1>())) advance_swe_kernel(Ctx c, int first, int count, double dt) {
     __shared__ SweSmem<MX> s;
     const int p = first + xcd_remap(blockIdx.x, count);
     unsigned long long *slot = c.cflp ? c.cflp + p : nullptr;
@@ -1360,7 +1364,7 @@ template <int MX>
 struct SmemOf<MX, 1> { using type = SweSmem<MX>; };
 
 template <int MX, int NT, int EQ>
-__global__ void __launch_bounds__(NT) persistent_kernel(Ctx c, const SchedEntry *sched, int nsched,
+__global__ void __launch_bounds__(NT, ((EQ == 1 && NT == 512) ? 4 : 1)) persistent_kernel(Ctx c, const SchedEntry *sched, int nsched,
                                                         const LevelRange *lr, int ncoarse, DevState *st) {
     __shared__ typename SmemOf<MX, EQ>::type s;
     double t0 = st->t;
@@ -1690,7 +1694,7 @@ hipError_t launch_advance(const Ctx &c, LaunchCfg lc, int level, int first, int 
 #undef ADV
     } else {
 #define ADV(MXV, NTV) if (lc.mx == MXV && lc.nt == NTV) return adv_swe<MXV, NTV>(c, first, count, dt, fused, s);
-        ADV(8, 64) ADV(8, 128) ADV(16, 64) ADV(16, 128) ADV(16, 256)
+        ADV(8, 64) ADV(8, 128) ADV(16, 64) ADV(16, 128) ADV(16, 256) ADV(16, 512)
 #undef ADV
     }
     return hipErrorInvalidValue;
@@ -1707,6 +1711,7 @@ static const void *persistent_select(LaunchCfg lc, int eq) {
 #define PS(MXV, NTV) if (lc.mx == MXV && lc.nt == NTV) return persistent_fn<MXV, NTV>(eq);
     PS(8, 64) PS(8, 128) PS(16, 64) PS(16, 128) PS(16, 256) PS(32, 128) PS(32, 256) PS(32, 512)
 #undef PS
+    if (lc.mx == 16 && lc.nt == 512 && eq == 1) return reinterpret_cast<const void *>(&persistent_kernel<16, 512, 1>);
     return nullptr;
 }
 
@@ -1745,6 +1750,7 @@ static const void *level_step_select(LaunchCfg lc, int eq) {
 #define PS(MXV, NTV) if (lc.mx == MXV && lc.nt == NTV) return level_step_fn<MXV, NTV>(eq);
     PS(8, 64) PS(8, 128) PS(16, 64) PS(16, 128) PS(16, 256) PS(32, 128) PS(32, 256) PS(32, 512)
 #undef PS
+    if (lc.mx == 16 && lc.nt == 512 && eq == 1) return reinterpret_cast<const void *>(&level_step_kernel<16, 512, 1>);
     return nullptr;
 }
 

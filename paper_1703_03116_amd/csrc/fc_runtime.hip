@@ -320,7 +320,7 @@ bool valid_nt(int mx, int nt, int eq = 0) {
     if (eq == FC_EQ_SWE && mx == 32) return false;
     switch (mx) {
         case 8: return nt == 64 || nt == 128;
-        case 16: return nt == 64 || nt == 128 || nt == 256;
+        case 16: return nt == 64 || nt == 128 || nt == 256 || (nt == 512 && eq == FC_EQ_SWE);
         case 32: return nt == 128 || nt == 256 || nt == 512;
     }
     return false;
@@ -973,7 +973,7 @@ fc_status fc_autotune(fc_patchstore *ps, int32_t *threads_out, void *stream) {
     const double dt = 0.5 * h;
     const int cands[3] = {64, 128, 256};
     const int cands32[3] = {128, 256, 512};
-    const int *cl = ps->mx == 32 ? cands32 : cands;
+    const int *cl = (ps->mx == 32 || (ps->mx == 16 && ps->cfg.equation == FC_EQ_SWE)) ? cands32 : cands;
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));

@@ -358,6 +358,22 @@ def test_swe_dam_break_amr_parity(B, O, mode, mx):
     assert rel(ps.interior(), o.interior()) <= TOL
 
 
+def test_swe_variants_bitwise(B):
+    """Every shallow-water launch variant at mx = 16 (128, 256 and 512
+    threads per patch) computes the same bits, in the graph form."""
+    w = S.workload("dam_break", lmin=2, lmax=4, mx=16)
+    dt = 0.6 / (16 * 4) / 1.6
+    res = []
+    for nt in (128, 256, 512):
+        ps = B.from_workload(w)
+        ps.set_variant(nt)
+        ps.coarse_steps(dt, 4, "graph")
+        ps.check()
+        res.append(ps.interior().cpu().numpy())
+    for r in res[1:]:
+        assert np.array_equal(r, res[0])
+
+
 def test_swe_lake_at_rest_bitwise(B):
     L = S.random_balanced_leaves(3, 2, 4, periodic=(False, False))
     q = np.zeros((len(L), 3, 16, 16))
