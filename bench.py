@@ -303,6 +303,17 @@ def adjoint_workload(args):
     Lv, g = loss_and_grad(ps, q0, qt, level, dt, n, every)
     torch.cuda.synchronize()
     grad_s = time.perf_counter() - t0
+    # the same gradient with every state kept in HBM (n solution copies,
+    # 8.6 GB at level 6 and 256 steps): no recomputation
+    loss_and_grad(ps, q0, qt, level, dt, 16, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, g1 = loss_and_grad(ps, q0, qt, level, dt, n, 1)
+    torch.cuda.synchronize()
+    grad1_s = time.perf_counter() - t0
+    same = bool(torch.equal(g, g1))
+    del g1
+    torch.cuda.empty_cache()
     ps.time = 0.0
     ps.set_interior(q0)
     ps.prepare_steps(dt, n, "graph")
@@ -319,6 +330,8 @@ def adjoint_workload(args):
            "config": {"workload": f"adjoint: uniform level {level}, {len(L)} patches of {mx}x{mx}, swirl, MC limiter, "
                                   f"{n} steps, checkpoint every {every}", "threads_per_patch": nt},
            "gradient_s": grad_s, "forward_s": fwd_s, "gradient_over_forward": grad_s / fwd_s,
+           "all_states_resident": {"gradient_s": grad1_s, "gradient_over_forward": grad1_s / fwd_s,
+                                   "bitwise_equal_gradient": same},
            "loss": float(Lv), "grad_norm": float(g.norm())}
     print(json.dumps(out), flush=True)
 

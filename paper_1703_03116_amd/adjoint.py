@@ -6,7 +6,9 @@ from q0 and returns q(T); its backward is the hand-written discrete adjoint
 (fc_adjoint_step: transpose of the limited step with branches frozen at the
 forward state, then transpose of the ghost copy), with checkpoints every
 ``checkpoint_every`` steps and the states of one segment recomputed at a
-time by fc_step_uniform (leaf order in, leaf order out).  Shapes: [nleaves][1][mx][mx] float64 on the GPU, in the leaf order the
+time by fc_step_uniform (leaf order in, leaf order out).  checkpoint_every=1
+keeps every state in HBM instead (nsteps solution copies) and recomputes
+nothing; the forward then runs fc_step_uniform, bitwise the same steps.  Shapes: [nleaves][1][mx][mx] float64 on the GPU, in the leaf order the
 store was created with.
 """
 from __future__ import annotations
@@ -27,18 +29,30 @@ class AdvanceFill(torch.autograd.Function):
     @staticmethod
     def forward(ctx, q0, store, level, dt, nsteps, checkpoint_every=16, t0=0.0):
         every = max(1, int(checkpoint_every))
-        times = _times(t0, dt, nsteps)
-        store.time = t0
-        store.set_interior(q0.detach())
-        ckpts = [q0.detach().clone()]
-        k = 0
-        while k < nsteps:
-            m = min(every, nsteps - k)
-            store.coarse_steps(dt, m, "graph")
-            k += m
-            if k < nsteps:
-                ckpts.append(store.interior())  # a fresh tensor
-        out = store.interior()
+        times = _times(t0, dt, nsteps + 1)
+        t_end, times = times[nsteps], times[:nsteps]
+        if every == 1:
+            # every state kept (nsteps x the solution size of HBM): the
+            # leaf-order step writes each one as a tensor of its own, so
+            # nothing is copied and the backward sweep recomputes nothing
+            ckpts = [q0.detach().clone()]
+            for k in range(nsteps):
+                ckpts.append(store.step_uniform(level, times[k], dt, ckpts[-1]))
+            out = ckpts.pop()
+            store.set_interior(out)  # the store ends at q(T), as after the graph path
+            store.time = t_end
+        else:
+            store.time = t0
+            store.set_interior(q0.detach())
+            ckpts = [q0.detach().clone()]
+            k = 0
+            while k < nsteps:
+                m = min(every, nsteps - k)
+                store.coarse_steps(dt, m, "graph")
+                k += m
+                if k < nsteps:
+                    ckpts.append(store.interior())  # a fresh tensor
+            out = store.interior()
         ctx.store, ctx.level, ctx.dt, ctx.nsteps, ctx.every = store, level, dt, nsteps, every
         ctx.times, ctx.ckpts = times, ckpts
         return out

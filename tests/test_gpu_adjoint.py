@@ -117,7 +117,10 @@ def test_checkpointing_does_not_change_the_gradient(B):
     dt = 0.9 / (mx << level)
     _, g1 = loss_and_grad(ps, q0, qt, level, dt, n, 4)
     _, g2 = loss_and_grad(ps, q0, qt, level, dt, n, n)
+    L3, g3 = loss_and_grad(ps, q0, qt, level, dt, n, 1)  # every state resident, no recomputation
     assert torch.equal(g1, g2)
+    assert torch.equal(g1, g3)
+    assert ps.time == pytest.approx(n * dt, rel=1e-12)
 
 
 def _fd_check(B, limiter, ndir, tol):
