@@ -143,7 +143,7 @@ struct fc_patchstore {
     char *ws = nullptr;
     size_t ws_bytes = 0;
     size_t off_info = 0, off_nbr = 0, off_sl = 0, off_ls = 0, off_lr = 0, off_sched = 0, off_state = 0,
-           off_plan = 0, off_tag = 0, off_cfl = 0, off_vt[FC_MAXLEV] = {0}, off_abar = 0;
+           off_plan = 0, off_tag = 0, off_cfl = 0, off_vt[FC_MAXLEV] = {0};
     std::vector<SchedEntry> sched;
     int pgrid = 0;
     int pgrid_user = 0;  // grid override of the persistent kernel (0: occupancy)
