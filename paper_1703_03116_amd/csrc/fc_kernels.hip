@@ -400,10 +400,8 @@ __device__ void load_velocity(const Ctx &c, ScalarSmem<MX> &s, int l, int gx, in
 // returns the line's partial update of each cell in R:
 //   rows     Rx = Q - lam TX + lam/2 (C_{i+1/2} - C_{i-1/2}),
 //   columns  Ry = lam/2 (C_{j+1/2} - C_{j-1/2}) - lam TY.
-// amax: largest |velocity| over the edges.
 template <int MX, int SEG, int LIM, int DIR>
-__device__ __forceinline__ void sweep_segment(ScalarSmem<MX> &s, int line, int e0, double lam, double (&R)[SEG],
-                                              double &amax) {
+__device__ __forceinline__ void sweep_segment(ScalarSmem<MX> &s, int line, int e0, double lam, double (&R)[SEG]) {
     constexpr int NP = ScalarSmem<MX>::NP, S = ScalarSmem<MX>::S;
     constexpr int STR = DIR == 0 ? 1 : NP;
     const double *qp = DIR == 0 ? &s.q[(line + MB) * NP + MB + e0 - 2] : &s.q[(MB + e0 - 2) * NP + line + MB];
@@ -412,7 +410,7 @@ __device__ __forceinline__ void sweep_segment(ScalarSmem<MX> &s, int line, int e
     double q[SEG + 4];
 #pragma unroll
     for (int k = 0; k < SEG + 4; k++) q[k] = qp[k * STR];
-    double am = 0.0, aprev = 0.0, cprev = 0.0;
+    double aprev = 0.0, cprev = 0.0;
 #pragma unroll
     for (int k = 0; k <= SEG; k++) {  // edge e0 + k, between q[k+1] and q[k+2]
         const double u = ve[k] * vl;
@@ -422,7 +420,6 @@ __device__ __forceinline__ void sweep_segment(ScalarSmem<MX> &s, int line, int e
         const double C = correction<LIM>(W, Wu, au, lam);
         const double aps = posp(u) * W - C;
         const double ams = negp(u) * W + C;
-        am = fmax(am, au);
         if (k > 0) {  // cell e0 + k - 1
             const int cc = e0 + k - 1;
             const double T = aprev + ams;
@@ -437,7 +434,6 @@ __device__ __forceinline__ void sweep_segment(ScalarSmem<MX> &s, int line, int e
         aprev = aps;
         cprev = C;
     }
-    amax = fmax(amax, am);
 }
 
 // The same for a line outside the interior (row -1 or MX: DIR 0, column -1
@@ -678,37 +674,44 @@ __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, 
             }
         }
     }
-    if (tid == 0) s.cfl = 0ull;
     __syncthreads();
     constexpr int S = ScalarSmem<MX>::S;
     double R[SEG];
-    double amax = 0.0;
     int line = 0, e0 = 0;
     const bool xs = tid < NI, ys = !xs && tid < 2 * NI;
     const int half = (xs ? tid : tid - NI) / HI, r = (xs ? tid : tid - NI) % HI;
     if (xs) {
         line = half * (MX / 2) + r % (MX / 2);
         e0 = (r / (MX / 2)) * SEG;
-        sweep_segment<MX, SEG, LIM, 0>(s, line, e0, lam, R, amax);
+        sweep_segment<MX, SEG, LIM, 0>(s, line, e0, lam, R);
     } else if (ys) {
         line = r % MX;
         e0 = (half * (NSEG / 2) + r / MX) * SEG;
-        sweep_segment<MX, SEG, LIM, 1>(s, line, e0, lam, R, amax);
+        sweep_segment<MX, SEG, LIM, 1>(s, line, e0, lam, R);
     }
     if (tid >= GT0 && tid < GT0 + NO) {  // rows -1, MX and columns -1, MX: TX, TY only
         const int k = tid - GT0, g = k / (MX / SO);
         sweep_outer<MX, SO, LIM>(s, g >> 1, (g & 1) ? MX : -1, (k % (MX / SO)) * SO, lam);
     }
-    // CFL number of the patch: a max across the wave (done here, where waves
-    // that finish their sweeps early hide its latency behind the others),
-    // then one LDS atomic max per wave (the bits of non-negative doubles
-    // order as the values do), read after the barrier
-    {
-        double m = lam * amax;
-        for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
-        if ((tid & 63) == 0 && m > 0.0) atomicMax(&s.cfl, (unsigned long long)__double_as_longlong(m));
-    }
     __syncthreads();
+    // CFL number of the patch.  The velocity is a product of one factor per
+    // axis, u(e, j) = ux(e) uy(j), and rounding a product of non-negative
+    // numbers is monotone in each, so the largest |u| over the x-edges is
+    // max|ux| max|uy| exactly (likewise for v): the last wave reduces the
+    // 1-D factors instead of every item tracking its edges.
+    if (tid >= NT - 64) {
+        const int k = tid - (NT - 64);
+        double ax = 0.0, bx = 0.0, ay = 0.0, by = 0.0;
+        if (k <= MX) { ax = fabs(s.ux[k]); ay = fabs(s.vy[k]); }
+        if (k < MX) { bx = fabs(s.uy[k + 1]); by = fabs(s.vx[k + 1]); }
+        for (int o = 32; o > 0; o >>= 1) {
+            ax = fmax(ax, __shfl_xor(ax, o, 64));
+            bx = fmax(bx, __shfl_xor(bx, o, 64));
+            ay = fmax(ay, __shfl_xor(ay, o, 64));
+            by = fmax(by, __shfl_xor(by, o, 64));
+        }
+        if (k == 0) s.cfl = (unsigned long long)__double_as_longlong(lam * fmax(ax * bx, ay * by));
+    }
     // direction parts: rows into s.part, columns into the tile's interior
     // (nothing reads the staged interior after the sweeps)
     if (xs) {
