@@ -248,6 +248,25 @@ def test_prepared_graphs_replay_the_same_steps(B, mode):
     b.check()
 
 
+def test_forms_bitwise_at_level_6(B):
+    """4096 patches (85 MB of solution: the advance writes with plain
+    stores at this size, with streaming stores below and above it): the
+    graph form, the host-launched fused kernels and the per-level form take
+    the same steps bit for bit, CFL numbers included."""
+    w = S.workload("swirl_uniform", level=6, mx=32)
+    dt = w["dt_coarse"]
+    out, cfls = [], []
+    for mode in ("graph", "fused_levels", "per_level"):
+        ps = B.from_workload(w)
+        cfl = torch.zeros(1, dtype=torch.float64, device="cuda")
+        ps.coarse_steps(dt, 6, mode, cfl=cfl)
+        ps.check()
+        out.append(ps.interior())
+        cfls.append(float(cfl))
+    assert torch.equal(out[0], out[1]) and torch.equal(out[0], out[2])
+    assert cfls[0] == cfls[1] == cfls[2] > 0.0
+
+
 @pytest.mark.parametrize("mx", [8, 16, 32])
 def test_variants_bitwise(B, mx):
     """Every launch variant (threads per patch) computes the same bits."""
