@@ -998,6 +998,7 @@ __device__ __forceinline__ void swe_edge(double g, int lim, double lam, const do
 template <int MX, int NT, bool FUSED>
 __device__ void advance_swe_patch(const Ctx &c, const View &w, SweSmem<MX> &s, int p, double dt, double &cfl) {
     constexpr int N = MX + 2 * MB, NR = SweSmem<MX>::NR;
+    constexpr bool ONEPASS = NT >= (MX + 1) * (MX + 2);  // every edge of a direction in one pass
     const PatchInfo P = c.info[p];
     const int l = P.level;
     // h = 1 / (MX 2^l) is a power of two: dt / h is exact as a product
@@ -1036,13 +1037,22 @@ __device__ void advance_swe_patch(const Ctx &c, const View &w, SweSmem<MX> &s, i
             roe_solve(g, QA(0, iL, jL), QA(fn, iL, jL), QA(ft, iL, jL), QA(0, iR, jR), QA(fn, iR, jR),
                       QA(ft, iR, jR), s.R[k]);
         }
+        if constexpr (ONEPASS) {  // accumulators start at -0: -0 + x is x exactly
+            double *acc = &s.acc[0][0];
+            for (int k = threadIdx.x; k < SweSmem<MX>::NC * 12; k += NT) acc[k] = -0.0;
+        }
         __syncthreads();
-        // edges e in [0, MX] of parity `par`, lines [-1, MX]; cell (e) gets
-        // the right-going part, cell (e-1) the left-going part
-        for (int par = 0; par < 2; par++) {
-            constexpr int NEH = (MX / 2 + 1) * (MX + 2);
+        // edges e in [0, MX], lines [-1, MX]; cell (e) gets the right-going
+        // part, cell (e-1) the left-going part.  Every accumulator receives
+        // exactly two contributions (one per edge of its cell), so the sum does
+        // not depend on their order: with enough threads all edges go in one
+        // pass of LDS atomic adds, otherwise in two passes of alternate edges
+        // (even edges set, odd edges add).
+        for (int par = 0; par < (ONEPASS ? 1 : 2); par++) {
+            constexpr int NEH = ONEPASS ? (MX + 1) * (MX + 2) : (MX / 2 + 1) * (MX + 2);
             for (int k = threadIdx.x; k < NEH; k += NT) {
-                const int ln = k / (MX / 2 + 1) - 1, e = 2 * (k % (MX / 2 + 1)) + par;
+                const int ln = ONEPASS ? k / (MX + 1) - 1 : k / (MX / 2 + 1) - 1;
+                const int e = ONEPASS ? k % (MX + 1) : 2 * (k % (MX / 2 + 1)) + par;
                 if (e > MX) continue;
                 const int rk = (ln + 1) * (MX + 3) + (e + 1);
                 const int iL = dir == 0 ? e - 1 : ln, jL = dir == 0 ? ln : e - 1;
@@ -1060,7 +1070,10 @@ __device__ void advance_swe_patch(const Ctx &c, const View &w, SweSmem<MX> &s, i
 #pragma unroll
                     for (int f = 0; f < 3; f++) {
                         const int o = sw[f];
-                        if (par == 0) {
+                        if (ONEPASS) {
+                            atomicAdd(&a[o], Aps[f]); atomicAdd(&a[3 + o], bpp[f]);
+                            atomicAdd(&a[6 + o], bmp[f]); atomicAdd(&a[9 + o], -C[f]);
+                        } else if (par == 0) {
                             a[o] = Aps[f]; a[3 + o] = bpp[f]; a[6 + o] = bmp[f]; a[9 + o] = -C[f];
                         } else {
                             a[o] += Aps[f]; a[3 + o] += bpp[f]; a[6 + o] += bmp[f]; a[9 + o] -= C[f];
@@ -1072,7 +1085,10 @@ __device__ void advance_swe_patch(const Ctx &c, const View &w, SweSmem<MX> &s, i
 #pragma unroll
                     for (int f = 0; f < 3; f++) {
                         const int o = sw[f];
-                        if (par == 0) {
+                        if (ONEPASS) {
+                            atomicAdd(&a[o], Ams[f]); atomicAdd(&a[3 + o], bpm[f]);
+                            atomicAdd(&a[6 + o], bmm[f]); atomicAdd(&a[9 + o], C[f]);
+                        } else if (par == 0) {
                             a[o] = Ams[f]; a[3 + o] = bpm[f]; a[6 + o] = bmm[f]; a[9 + o] = C[f];
                         } else {
                             a[o] += Ams[f]; a[3 + o] += bpm[f]; a[6 + o] += bmm[f]; a[9 + o] += C[f];

@@ -377,13 +377,15 @@ def test_swe_dam_break_amr_parity(B, O, mode, mx):
     assert rel(ps.interior(), o.interior()) <= TOL
 
 
-def test_swe_variants_bitwise(B):
-    """Every shallow-water launch variant at mx = 16 (128, 256 and 512
-    threads per patch) computes the same bits, in the graph form."""
-    w = S.workload("dam_break", lmin=2, lmax=4, mx=16)
-    dt = 0.6 / (16 * 4) / 1.6
+@pytest.mark.parametrize("mx,nts", [(16, (128, 256, 512)), (8, (64, 128))])
+def test_swe_variants_bitwise(B, mx, nts):
+    """Every shallow-water launch variant computes the same bits, in the
+    graph form: two passes of alternate edges (fewer threads) and one pass of
+    LDS atomic adds (512 threads at mx = 16, 128 at mx = 8) alike."""
+    w = S.workload("dam_break", lmin=2, lmax=4, mx=mx)
+    dt = 0.6 / (mx * 4) / 1.6
     res = []
-    for nt in (128, 256, 512):
+    for nt in nts:
         ps = B.from_workload(w)
         ps.set_variant(nt)
         ps.coarse_steps(dt, 4, "graph")
