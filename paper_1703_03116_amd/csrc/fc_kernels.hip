@@ -863,6 +863,8 @@ struct SweSmem {
     double R[NR][6];     // alpha_1..3, u_hat, v_hat, c_hat (normal frame)
     double acc[NC][12];  // per cell: T (3), transverse + (3), transverse - (3), dC (3)
     double D[3][MX * MX];
+    double vel[2][N * N];  // per cell hu/h and hv/h
+    double cel[N * N];     // per cell sqrt(g h)
     double red[16];
 };
 
@@ -923,7 +925,9 @@ __device__ __forceinline__ void roe_transverse(const double *r, double i2c, cons
 // limited second-order correction C, corrected fluctuations and their
 // transverse splits.  qL/qR in the normal frame; rU/rD: Roe data of the
 // neighbouring edges on the two sides (for the upwind waves).
+// uL, cL, uR, cR: normal velocity and sqrt(g h) of the two cells.
 __device__ __forceinline__ void swe_edge(double g, int lim, double lam, const double *qL, const double *qR,
+                                         double uL, double cL, double uR, double cR,
                                          const double *r, const double *rlo, const double *rhi, double C[3],
                                          double Aps[3], double Ams[3], double bpp[3], double bmp[3], double bpm[3],
                                          double bmm[3], double &smax) {
@@ -932,14 +936,14 @@ __device__ __forceinline__ void swe_edge(double g, int lim, double lam, const do
     // Harten-Hyman fix on transonic rarefactions of families 1 and 3
     // (the middle states are needed only where the outer speed has the
     // sign that allows a transonic rarefaction)
-    const double l1L = qL[1] / qL[0] - sqrt(g * qL[0]);
+    const double l1L = uL - cL;
     double l1R = 0.0;
     if (l1L < 0.0) {
         const double hm = qL[0] + W[0][0];
         l1R = (qL[1] + W[0][1]) / hm - sqrt(g * hm);
     }
     const bool fix1 = l1L < 0.0 && l1R > 0.0;
-    const double l3R = qR[1] / qR[0] + sqrt(g * qR[0]);
+    const double l3R = uR + cR;
     double l3L = 0.0;
     if (l3R > 0.0) {
         const double hm3 = qR[0] - W[2][0];
@@ -992,9 +996,9 @@ __device__ __forceinline__ void swe_edge(double g, int lim, double lam, const do
 }
 
 // One step on a shallow-water patch.  Sweep X then Y; each sweep: Riemann
-// problems into R, then the edges of even and odd index add their
-// contributions to the two adjacent cells (two conflict-free passes), then
-// the cells turn them into their share of the update.
+// problems into R, then every edge adds its contributions to its two cells
+// (one pass of LDS atomic adds, or two passes of alternate edges), then the
+// cells turn them into their share of the update.
 template <int MX, int NT, bool FUSED>
 __device__ void advance_swe_patch(const Ctx &c, const View &w, SweSmem<MX> &s, int p, double dt, double &cfl) {
     constexpr int N = MX + 2 * MB, NR = SweSmem<MX>::NR;
@@ -1005,14 +1009,26 @@ __device__ void advance_swe_patch(const Ctx &c, const View &w, SweSmem<MX> &s, i
     const double lam = dt * (double)(MX << l), g = c.g;
     const double *in = buf_of(c, w, l);
     double *out = other_of(c, w, l);
+    // each staged cell also gets its velocities and gravity-wave speed, the
+    // quantities every edge of the cell starts its entropy check with
+    auto stage = [&](int k, const double (&v)[3]) {
+        for (int f = 0; f < 3; f++) s.q[f][k] = v[f];
+        s.vel[0][k] = v[1] / v[0];
+        s.vel[1][k] = v[2] / v[0];
+        s.cel[k] = sqrt(g * v[0]);
+    };
     if (!FUSED) {
-        for (int f = 0; f < 3; f++)
-            for (int k = threadIdx.x; k < N * N; k += NT) s.q[f][k] = in[(size_t)(f * c.cap + p) * N * N + k];
+        for (int k = threadIdx.x; k < N * N; k += NT) {
+            double v[3];
+            for (int f = 0; f < 3; f++) v[f] = in[(size_t)(f * c.cap + p) * N * N + k];
+            stage(k, v);
+        }
     } else {
         for (int k = threadIdx.x; k < MX * MX; k += NT) {
             const int i = k % MX, j = k / MX;
-            for (int f = 0; f < 3; f++)
-                s.q[f][(j + MB) * N + i + MB] = in[(size_t)(f * c.cap + p) * N * N + (j + MB) * N + i + MB];
+            double v[3];
+            for (int f = 0; f < 3; f++) v[f] = in[(size_t)(f * c.cap + p) * N * N + (j + MB) * N + i + MB];
+            stage((j + MB) * N + i + MB, v);
         }
         constexpr int NG = N * N - MX * MX;
         for (int gidx = threadIdx.x; gidx < NG; gidx += NT) {
@@ -1020,7 +1036,7 @@ __device__ void advance_swe_patch(const Ctx &c, const View &w, SweSmem<MX> &s, i
             ghost_index<MX>(gidx, i, j);
             double v[3];
             ghost_cell<MX, 3>(c, w, p, i, j, v);
-            for (int f = 0; f < 3; f++) s.q[f][(j + MB) * N + i + MB] = v[f];
+            stage((j + MB) * N + i + MB, v);
         }
     }
     __syncthreads();
@@ -1061,7 +1077,9 @@ __device__ void advance_swe_patch(const Ctx &c, const View &w, SweSmem<MX> &s, i
                 const double qR[3] = {QA(0, iR, jR), QA(fn, iR, jR), QA(ft, iR, jR)};
                 double C[3], Aps[3], Ams[3], bpp[3], bmp[3], bpm[3], bmm[3];
                 double sm = 0.0;
-                swe_edge(g, c.lim, lam, qL, qR, s.R[rk], s.R[rk - 1], s.R[rk + 1], C, Aps, Ams, bpp, bmp, bpm, bmm, sm);
+                const int cLk = (jL + MB) * N + iL + MB, cRk = (jR + MB) * N + iR + MB;
+                swe_edge(g, c.lim, lam, qL, qR, s.vel[dir][cLk], s.cel[cLk], s.vel[dir][cRk], s.cel[cRk], s.R[rk],
+                         s.R[rk - 1], s.R[rk + 1], C, Aps, Ams, bpp, bmp, bpm, bmm, sm);
                 if (ln >= 0 && ln < MX) smax = fmax(smax, sm);
                 // back to (h, hu, hv)
                 const int sw[3] = {0, fn, ft};
