@@ -693,12 +693,13 @@ __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, 
         const int k = tid - GT0, g = k / (MX / SO);
         sweep_outer<MX, SO, LIM>(s, g >> 1, (g & 1) ? MX : -1, (k % (MX / SO)) * SO, lam);
     }
-    __syncthreads();
     // CFL number of the patch.  The velocity is a product of one factor per
     // axis, u(e, j) = ux(e) uy(j), and rounding a product of non-negative
     // numbers is monotone in each, so the largest |u| over the x-edges is
     // max|ux| max|uy| exactly (likewise for v): the last wave reduces the
-    // 1-D factors instead of every item tracking its edges.
+    // 1-D factors instead of every item tracking its edges.  It does so
+    // during the sweeps, where (at 256 and 512 threads) the outer-line
+    // segments load another wave.
     if (tid >= NT - 64) {
         const int k = tid - (NT - 64);
         double ax = 0.0, bx = 0.0, ay = 0.0, by = 0.0;
@@ -712,6 +713,7 @@ __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, 
         }
         if (k == 0) s.cfl = (unsigned long long)__double_as_longlong(lam * fmax(ax * bx, ay * by));
     }
+    __syncthreads();
     // direction parts: rows into s.part, columns into the tile's interior
     // (nothing reads the staged interior after the sweeps)
     if (xs) {
