@@ -311,6 +311,27 @@ __device__ __forceinline__ void store_stream2(double *p, double a, double b) {
     __builtin_nontemporal_store(v, reinterpret_cast<dpair *>(p));
 }
 
+// Maximum of a non-negative double over a wave64 with DPP row operations
+// (no trip through LDS): shifts by 1, 2, 4 and 8 within each row of 16 lanes,
+// then row broadcasts of lane 15 and lane 31.  Lanes whose source lies
+// outside the row keep their own value.  Lane 63 ends with the maximum.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_max_step(double v) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    const int lo2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWS, 0xf, false);
+    const int hi2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWS, 0xf, false);
+    return fmax(v, __hiloint2double(hi2, lo2));
+}
+__device__ __forceinline__ double wave_max_last_lane(double v) {
+    v = dpp_max_step<0x111, 0xf>(v);  // row_shr:1
+    v = dpp_max_step<0x112, 0xf>(v);  // row_shr:2
+    v = dpp_max_step<0x114, 0xf>(v);  // row_shr:4
+    v = dpp_max_step<0x118, 0xf>(v);  // row_shr:8
+    v = dpp_max_step<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    v = dpp_max_step<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
 __device__ __forceinline__ double posp(double a) { return a > 0.0 ? a : 0.0; }
 __device__ __forceinline__ double negp(double a) { return a < 0.0 ? a : 0.0; }
 
@@ -705,13 +726,11 @@ __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, 
         double ax = 0.0, bx = 0.0, ay = 0.0, by = 0.0;
         if (k <= MX) { ax = fabs(s.ux[k]); ay = fabs(s.vy[k]); }
         if (k < MX) { bx = fabs(s.uy[k + 1]); by = fabs(s.vx[k + 1]); }
-        for (int o = 32; o > 0; o >>= 1) {
-            ax = fmax(ax, __shfl_xor(ax, o, 64));
-            bx = fmax(bx, __shfl_xor(bx, o, 64));
-            ay = fmax(ay, __shfl_xor(ay, o, 64));
-            by = fmax(by, __shfl_xor(by, o, 64));
-        }
-        if (k == 0) s.cfl = (unsigned long long)__double_as_longlong(lam * fmax(ax * bx, ay * by));
+        ax = wave_max_last_lane(ax);
+        bx = wave_max_last_lane(bx);
+        ay = wave_max_last_lane(ay);
+        by = wave_max_last_lane(by);
+        if (k == 63) s.cfl = (unsigned long long)__double_as_longlong(lam * fmax(ax * bx, ay * by));
     }
     __syncthreads();
     // direction parts: rows into s.part, columns into the tile's interior
