@@ -311,6 +311,26 @@ __device__ __forceinline__ void store_stream2(double *p, double a, double b) {
     __builtin_nontemporal_store(v, reinterpret_cast<dpair *>(p));
 }
 
+__device__ __forceinline__ double posp(double a) { return a > 0.0 ? a : 0.0; }
+__device__ __forceinline__ double negp(double a) { return a < 0.0 ? a : 0.0; }
+
+// Second-order correction C = |s| (1 - lam |s|) W~ of one wave W, with W~
+// the limited wave and Wu its upwind neighbour.  Limiter codes: 0 MC,
+// 1 Lax-Wendroff (no limiting), 2 first order, 3 minmod.  The MC value
+// phi(theta) W, theta = Wu / W, is formed without the division: zero unless
+// W Wu > 0, else sign(W) min((|W| + |Wu|) / 2, 2 |W|, 2 |Wu|).
+template <int LIM>
+__device__ __forceinline__ double correction(double W, double Wu, double as, double lam) {
+    if constexpr (LIM == 2) return 0.0;
+    const double k = as - (lam * as) * as;
+    if constexpr (LIM == 1) return k * W;
+    const double aw = fabs(W), au = fabs(Wu);
+    double m;
+    if constexpr (LIM == 3) m = fmin(aw, au);
+    else m = fmin(0.5 * (aw + au), 2.0 * fmin(aw, au));
+    return (W * Wu > 0.0) ? k * copysign(m, W) : 0.0;  // k < 0 where lam |s| > 1
+}
+
 // Maximum of a non-negative double over a wave64 with DPP row operations
 // (no trip through LDS): shifts by 1, 2, 4 and 8 within each row of 16 lanes,
 // then row broadcasts of lane 15 and lane 31.  Lanes whose source lies
@@ -330,26 +350,6 @@ __device__ __forceinline__ double wave_max_last_lane(double v) {
     v = dpp_max_step<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
     v = dpp_max_step<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
     return v;
-}
-
-__device__ __forceinline__ double posp(double a) { return a > 0.0 ? a : 0.0; }
-__device__ __forceinline__ double negp(double a) { return a < 0.0 ? a : 0.0; }
-
-// Second-order correction C = |s| (1 - lam |s|) W~ of one wave W, with W~
-// the limited wave and Wu its upwind neighbour.  Limiter codes: 0 MC,
-// 1 Lax-Wendroff (no limiting), 2 first order, 3 minmod.  The MC value
-// phi(theta) W, theta = Wu / W, is formed without the division: zero unless
-// W Wu > 0, else sign(W) min((|W| + |Wu|) / 2, 2 |W|, 2 |Wu|).
-template <int LIM>
-__device__ __forceinline__ double correction(double W, double Wu, double as, double lam) {
-    if constexpr (LIM == 2) return 0.0;
-    const double k = as - (lam * as) * as;
-    if constexpr (LIM == 1) return k * W;
-    const double aw = fabs(W), au = fabs(Wu);
-    double m;
-    if constexpr (LIM == 3) m = fmin(aw, au);
-    else m = fmin(0.5 * (aw + au), 2.0 * fmin(aw, au));
-    return (W * Wu > 0.0) ? k * copysign(m, W) : 0.0;  // k < 0 where lam |s| > 1
 }
 
 // Velocity factors of a patch into LDS, at the mid-step time t + dt/2 with
@@ -388,23 +388,41 @@ __device__ __forceinline__ void fetch_velocity(const Ctx &c, int l, int gx, int 
     }
 }
 
+//
+// The same wave also finds the patch's largest edge speed.  The velocity is
+// a product of one factor per axis, u(e, j) = ux(e) uy(j), and rounding a
+// product of non-negative numbers is monotone in each, so the largest |u|
+// over the x-edges of the interior rows is max|ux| max|uy| exactly
+// (likewise for v).  The factors are at hand here, while the tile's loads
+// are still in flight; s.cfl receives the unscaled maximum.  (The lanes
+// k0 .. k0+MX+1 lie in one wave for every launch variant.)
 template <int MX>
 __device__ __forceinline__ void put_velocity(const Ctx &c, ScalarSmem<MX> &s, double t, double dt,
                                              const double *tdev, int k0, const VelRegs &v) {
     const int k = (int)threadIdx.x - k0;
-    if (k < 0 || k >= MX + 2) return;
-    if (c.velocity == 2) {
-        if (tdev) t = v.tv + t;
-        const double tm = t + 0.5 * dt;
-        const double ct = cos(M_PI * (tm * c.vel_invT));
-        if (k <= MX) { s.ux[k] = v.ex; s.vy[k] = v.ey; }
-        s.uy[k] = v.cy * ct;
-        s.vx[k] = -(v.cx * ct);
-    } else {
-        if (k <= MX) { s.ux[k] = c.vel_u; s.vy[k] = c.vel_v; }
-        s.uy[k] = 1.0;
-        s.vx[k] = 1.0;
+    if ((int)threadIdx.x / 64 != k0 / 64) return;
+    double ux = 0.0, uy = 0.0, vy = 0.0, vx = 0.0;
+    if (k >= 0 && k < MX + 2) {
+        if (c.velocity == 2) {
+            if (tdev) t = v.tv + t;
+            const double tm = t + 0.5 * dt;
+            const double ct = cos(M_PI * (tm * c.vel_invT));
+            ux = v.ex; vy = v.ey;
+            uy = v.cy * ct;
+            vx = -(v.cx * ct);
+        } else {
+            ux = c.vel_u; vy = c.vel_v;
+            uy = 1.0;
+            vx = 1.0;
+        }
+        if (k <= MX) { s.ux[k] = ux; s.vy[k] = vy; }
+        s.uy[k] = uy;
+        s.vx[k] = vx;
     }
+    const bool in_e = k >= 0 && k <= MX, in_c = k >= 1 && k <= MX;
+    const double ax = wave_max_last_lane(in_e ? fabs(ux) : 0.0), ay = wave_max_last_lane(in_e ? fabs(vy) : 0.0);
+    const double bx = wave_max_last_lane(in_c ? fabs(uy) : 0.0), by = wave_max_last_lane(in_c ? fabs(vx) : 0.0);
+    if ((threadIdx.x & 63) == 63) s.cfl = (unsigned long long)__double_as_longlong(fmax(ax * bx, ay * by));
 }
 
 template <int MX>
@@ -714,24 +732,6 @@ __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, 
         const int k = tid - GT0, g = k / (MX / SO);
         sweep_outer<MX, SO, LIM>(s, g >> 1, (g & 1) ? MX : -1, (k % (MX / SO)) * SO, lam);
     }
-    // CFL number of the patch.  The velocity is a product of one factor per
-    // axis, u(e, j) = ux(e) uy(j), and rounding a product of non-negative
-    // numbers is monotone in each, so the largest |u| over the x-edges is
-    // max|ux| max|uy| exactly (likewise for v): the last wave reduces the
-    // 1-D factors instead of every item tracking its edges.  It does so
-    // during the sweeps, where (at 256 and 512 threads) the outer-line
-    // segments load another wave.
-    if (tid >= NT - 64) {
-        const int k = tid - (NT - 64);
-        double ax = 0.0, bx = 0.0, ay = 0.0, by = 0.0;
-        if (k <= MX) { ax = fabs(s.ux[k]); ay = fabs(s.vy[k]); }
-        if (k < MX) { bx = fabs(s.uy[k + 1]); by = fabs(s.vx[k + 1]); }
-        ax = wave_max_last_lane(ax);
-        bx = wave_max_last_lane(bx);
-        ay = wave_max_last_lane(ay);
-        by = wave_max_last_lane(by);
-        if (k == 63) s.cfl = (unsigned long long)__double_as_longlong(lam * fmax(ax * bx, ay * by));
-    }
     __syncthreads();
     // direction parts: rows into s.part, columns into the tile's interior
     // (nothing reads the staged interior after the sweeps)
@@ -771,7 +771,7 @@ __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, 
             else *reinterpret_cast<double2 *>(&out[base + j * N + i]) = make_double2(a, b);
         }
     }
-    cfl = fmax(cfl, __longlong_as_double((long long)s.cfl));
+    cfl = fmax(cfl, lam * __longlong_as_double((long long)s.cfl));
 }
 
 template <int MX, int NT, bool FUSED>
