@@ -139,5 +139,5 @@ hipError_t launch_transfer(const Ctx &c, int mx, const TransferRec *plan, int n,
 hipError_t launch_export_cfl(DevState *state, const unsigned long long *cflp, int n, double *cfl_dev, hipStream_t s);
 hipError_t launch_step_leaf(const Ctx &c, int mx, int level, int first, int count, double t, double dt,
                             const int32_t *leaf_of_slot, const double *q_in, double *q_out, hipStream_t s);
-hipError_t launch_adjoint(const Ctx &c, int mx, int first, int count, double t, double dt, const int32_t *leaf_of_slot,
+hipError_t launch_adjoint(const Ctx &c, int mx, int level, int first, int count, double t, double dt, const int32_t *leaf_of_slot,
                           const double *q_in, const double *lam_in, double *lam_out, hipStream_t s);

@@ -1297,53 +1297,71 @@ template <int MX, int NT>
 constexpr int adj_seg() { return (2 * MX * MX / NT) < 4 ? 4 : 2 * MX * MX / NT; }
 
 template <int MX, int NT, int LIM>
-__global__ void __launch_bounds__(NT, (MX == 32 ? 4 : 1)) adjoint_kernel(Ctx c, int first, int count, double t,
-                                                                         double dt, const int32_t *leaf_of_slot,
+__global__ void __launch_bounds__(NT, (MX == 32 ? 4 : 1)) adjoint_kernel(Ctx c, int level, int first, int count,
+                                                                         double t, double dt,
+                                                                         const int32_t *leaf_of_slot,
                                                                          const double *q_in, const double *lam_in,
                                                                          double *lam_out) {
     using A = AdjSmem<MX>;
     constexpr int SEG = adj_seg<MX, NT>(), NI = MX * (MX / SEG);  // segments per direction
     static_assert(2 * NI <= NT && MX % SEG == 0, "one segment per thread");
+    constexpr int NG2 = (MX + 4) * (MX + 4) - MX * MX;             // lambda ghost ring
+    constexpr int NVI = (MX * MX / 2 + NT - 1) / NT, NVA = (12 * MX + NT - 1) / NT, NVR = (NG2 + NT - 1) / NT;
     __shared__ A s;
     const int tid = threadIdx.x;
     const int p = first + xcd_remap(blockIdx.x, count);
-    const PatchInfo P = c.info[p];
-    const int l = P.level;
+    const int l = level;
     const double lam = dt * (double)(MX << l);  // dt / h, exact: h = 1 / (MX 2^l)
-    const NbrRec *nb = c.nbr + (size_t)p * FC_NREC;
     const size_t PS = (size_t)MX * MX;
-    // interiors of q and lambda_in
-    {
-        const double *qi = q_in + (size_t)leaf_of_slot[p] * PS, *li = lam_in + (size_t)leaf_of_slot[p] * PS;
-        for (int k = tid; k < MX * MX / 2; k += NT) {
-            const int i = 2 * (k % (MX / 2)), j = k / (MX / 2);
-            const double2 a = *reinterpret_cast<const double2 *>(qi + 2 * k);
-            const double2 b = *reinterpret_cast<const double2 *>(li + 2 * k);
-            s.q[(j + 3) * A::QP + i + 3] = a.x;
-            s.q[(j + 3) * A::QP + i + 4] = a.y;
-            s.l[(j + 2) * A::LP + i + 2] = b.x;
-            s.l[(j + 2) * A::LP + i + 3] = b.y;
-        }
+    // A complete periodic level: the slot of every neighbour follows from the
+    // Morton index.  All leaf indices are loaded first, then all values, so the
+    // staging costs two memory round trips.
+    const uint32_t m = (uint32_t)(p - c.lstart[l]);
+    const int ix = (int)morton_compact(m), iy = (int)morton_compact(m >> 1), wrap = (1 << l) - 1;
+    auto leaf_at = [&](int dx, int dy) {
+        return leaf_of_slot[c.lstart[l] + (int)(morton_spread((uint32_t)((ix + dx) & wrap)) |
+                                                  (morton_spread((uint32_t)((iy + dy) & wrap)) << 1))];
+    };
+    auto side = [](int i) { return i < 0 ? -1 : (i >= MX ? 1 : 0); };
+    // Indices past the end are clamped to the last valid cell, so every load
+    // is issued without a branch; only the LDS stores below are guarded.
+    const int self = leaf_of_slot[p];
+    int ai[NVA], aj[NVA], al[NVA], ri[NVR], rj[NVR], rl[NVR];
+#pragma unroll
+    for (int v = 0; v < NVA; v++) {  // q: three layers beyond each side
+        const int g = min(tid + v * NT, 12 * MX - 1);
+        const int sd = g / (3 * MX), k = g % (3 * MX);
+        if (sd < 2) { aj[v] = k / 3; ai[v] = sd == 0 ? k % 3 - 3 : MX + k % 3; }
+        else { ai[v] = k % MX; aj[v] = sd == 2 ? k / MX - 3 : MX + k / MX; }
+        al[v] = leaf_at(side(ai[v]), side(aj[v]));
     }
-    // q: three layers beyond each side (side neighbours W, E, S, N)
-    for (int g = tid; g < 12 * MX; g += NT) {
-        const int side = g / (3 * MX), k = g % (3 * MX);
-        int i, j, along;
-        if (side < 2) { along = k / 3; j = along; i = side == 0 ? k % 3 - 3 : MX + k % 3; }
-        else { along = k % MX; i = along; j = side == 2 ? k / MX - 3 : MX + k / MX; }
-        const NbrRec r = nb[2 * side + (along >= MX / 2)];
-        s.q[(j + 3) * A::QP + i + 3] = q_in[(size_t)leaf_of_slot[r.id] * PS + (j - r.oy) * MX + i - r.ox];
+#pragma unroll
+    for (int v = 0; v < NVR; v++) {  // lambda_in: two ghost layers, corners included
+        int rr;
+        ghost_region_index<MX>(min(tid + v * NT, NG2 - 1), ri[v], rj[v], rr);
+        rl[v] = leaf_at(side(ri[v]), side(rj[v]));
     }
-    // lambda_in: two ghost layers, corners included
-    for (int g = tid; g < (MX + 4) * (MX + 4) - MX * MX; g += NT) {
-        int i, j, rr;
-        ghost_region_index<MX>(g, i, j, rr);
-        const NbrRec r = nb[rr];
-        s.l[(j + 2) * A::LP + i + 2] = lam_in[(size_t)leaf_of_slot[r.id] * PS + (j - r.oy) * MX + i - r.ox];
+    double2 qa[NVI], la[NVI];
+#pragma unroll
+    for (int v = 0; v < NVI; v++) {
+        const int k = min(tid + v * NT, MX * MX / 2 - 1);
+        qa[v] = *reinterpret_cast<const double2 *>(q_in + (size_t)self * PS + 2 * k);
+        la[v] = *reinterpret_cast<const double2 *>(lam_in + (size_t)self * PS + 2 * k);
+    }
+    double av[NVA], rv[NVR];
+#pragma unroll
+    for (int v = 0; v < NVA; v++) {
+        const int dx = side(ai[v]), dy = side(aj[v]);
+        av[v] = q_in[(size_t)al[v] * PS + (aj[v] - dy * MX) * MX + ai[v] - dx * MX];
+    }
+#pragma unroll
+    for (int v = 0; v < NVR; v++) {
+        const int dx = side(ri[v]), dy = side(rj[v]);
+        rv[v] = lam_in[(size_t)rl[v] * PS + (rj[v] - dy * MX) * MX + ri[v] - dx * MX];
     }
     // velocity factors at the mid-step time, as the forward step takes them
     {
-        const int n = MX << l, gx0 = P.ix * MX, gy0 = P.iy * MX;
+        const int n = MX << l, gx0 = ix * MX, gy0 = iy * MX;
         if (c.velocity == 2) {
             const double ct = cos(M_PI * ((t + 0.5 * dt) * c.vel_invT));
             const double *vt = c.vt[l];
@@ -1362,6 +1380,23 @@ __global__ void __launch_bounds__(NT, (MX == 32 ? 4 : 1)) adjoint_kernel(Ctx c, 
             }
         }
     }
+#pragma unroll
+    for (int v = 0; v < NVI; v++) {
+        const int k = tid + v * NT;
+        if (k < MX * MX / 2) {
+            const int i = 2 * (k % (MX / 2)), j = k / (MX / 2);
+            s.q[(j + 3) * A::QP + i + 3] = qa[v].x;
+            s.q[(j + 3) * A::QP + i + 4] = qa[v].y;
+            s.l[(j + 2) * A::LP + i + 2] = la[v].x;
+            s.l[(j + 2) * A::LP + i + 3] = la[v].y;
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < NVA; v++)
+        if (tid + v * NT < 12 * MX) s.q[(aj[v] + 3) * A::QP + ai[v] + 3] = av[v];
+#pragma unroll
+    for (int v = 0; v < NVR; v++)
+        if (tid + v * NT < NG2) s.l[(rj[v] + 2) * A::LP + ri[v] + 2] = rv[v];
     __syncthreads();
     double R[SEG];
     if (tid < NI) {  // rows: L + row part into LDS
@@ -1894,24 +1929,26 @@ hipError_t launch_step_leaf(const Ctx &c, int mx, int level, int first, int coun
 }
 
 template <int MX, int NT>
-static void launch_adjoint_mx(const Ctx &c, int first, int count, double t, double dt, const int32_t *leaf_of_slot,
-                              const double *q_in, const double *lam_in, double *lam_out, hipStream_t s) {
+static void launch_adjoint_mx(const Ctx &c, int level, int first, int count, double t, double dt,
+                              const int32_t *leaf_of_slot, const double *q_in, const double *lam_in, double *lam_out,
+                              hipStream_t s) {
     switch (c.lim) {
-        case 1: hipLaunchKernelGGL((adjoint_kernel<MX, NT, 1>), dim3(count), dim3(NT), 0, s, c, first, count, t, dt, leaf_of_slot, q_in, lam_in, lam_out); break;
-        case 2: hipLaunchKernelGGL((adjoint_kernel<MX, NT, 2>), dim3(count), dim3(NT), 0, s, c, first, count, t, dt, leaf_of_slot, q_in, lam_in, lam_out); break;
-        case 3: hipLaunchKernelGGL((adjoint_kernel<MX, NT, 3>), dim3(count), dim3(NT), 0, s, c, first, count, t, dt, leaf_of_slot, q_in, lam_in, lam_out); break;
-        default: hipLaunchKernelGGL((adjoint_kernel<MX, NT, 0>), dim3(count), dim3(NT), 0, s, c, first, count, t, dt, leaf_of_slot, q_in, lam_in, lam_out); break;
+        case 1: hipLaunchKernelGGL((adjoint_kernel<MX, NT, 1>), dim3(count), dim3(NT), 0, s, c, level, first, count, t, dt, leaf_of_slot, q_in, lam_in, lam_out); break;
+        case 2: hipLaunchKernelGGL((adjoint_kernel<MX, NT, 2>), dim3(count), dim3(NT), 0, s, c, level, first, count, t, dt, leaf_of_slot, q_in, lam_in, lam_out); break;
+        case 3: hipLaunchKernelGGL((adjoint_kernel<MX, NT, 3>), dim3(count), dim3(NT), 0, s, c, level, first, count, t, dt, leaf_of_slot, q_in, lam_in, lam_out); break;
+        default: hipLaunchKernelGGL((adjoint_kernel<MX, NT, 0>), dim3(count), dim3(NT), 0, s, c, level, first, count, t, dt, leaf_of_slot, q_in, lam_in, lam_out); break;
     }
 }
 
-hipError_t launch_adjoint(const Ctx &c, int mx, int first, int count, double t, double dt,
+hipError_t launch_adjoint(const Ctx &c, int mx, int level, int first, int count, double t, double dt,
                           const int32_t *leaf_of_slot, const double *q_in, const double *lam_in, double *lam_out,
                           hipStream_t s) {
     if (count <= 0) return hipSuccess;
+    if (!((c.complete >> level) & 1u)) return hipErrorInvalidValue;  // neighbour slots from the Morton index
     switch (mx) {
-        case 8: launch_adjoint_mx<8, 64>(c, first, count, t, dt, leaf_of_slot, q_in, lam_in, lam_out, s); break;
-        case 16: launch_adjoint_mx<16, 128>(c, first, count, t, dt, leaf_of_slot, q_in, lam_in, lam_out, s); break;
-        case 32: launch_adjoint_mx<32, 256>(c, first, count, t, dt, leaf_of_slot, q_in, lam_in, lam_out, s); break;
+        case 8: launch_adjoint_mx<8, 64>(c, level, first, count, t, dt, leaf_of_slot, q_in, lam_in, lam_out, s); break;
+        case 16: launch_adjoint_mx<16, 128>(c, level, first, count, t, dt, leaf_of_slot, q_in, lam_in, lam_out, s); break;
+        case 32: launch_adjoint_mx<32, 256>(c, level, first, count, t, dt, leaf_of_slot, q_in, lam_in, lam_out, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

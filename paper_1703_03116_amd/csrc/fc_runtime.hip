@@ -930,7 +930,7 @@ fc_status fc_adjoint_step(fc_patchstore *ps, int32_t level, double t, double dt,
     const int32_t *ls = (const int32_t *)(ps->ws + ps->off_ls);
     // transpose of copy + advance in one gather pass
     Ctx c = make_ctx(ps);
-    HIPCHK(launch_adjoint(c, ps->mx, ps->lr.start[level], ps->lr.count[level], t, dt, ls, q_in, lambda_in, lambda_out,
+    HIPCHK(launch_adjoint(c, ps->mx, level, ps->lr.start[level], ps->lr.count[level], t, dt, ls, q_in, lambda_in, lambda_out,
                           (hipStream_t)stream));
     return FC_OK;
 }
