@@ -594,22 +594,48 @@ __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, 
     const size_t base = (size_t)p * N * N;
     // rows are 16-byte aligned (N and MB even): two cells per load
     if constexpr (LEAF) {
-        const PatchInfo P = c.info[p];
-        const double *qi = io->qin + (size_t)io->leaf_of_slot[p] * MX * MX;
-        for (int k = tid; k < MX * MX / 2; k += NT) {
-            const int i = 2 * (k % (MX / 2)), j = k / (MX / 2);
-            const double2 v = *reinterpret_cast<const double2 *>(qi + 2 * k);
-            s.q[(j + MB) * NP + i + MB] = v.x;
-            s.q[(j + MB) * NP + i + MB + 1] = v.y;
+        // A complete periodic level: every neighbour's slot follows from the
+        // Morton index.  Each thread loads all its leaf indices, then all its
+        // values (indices past the end clamped, so no load waits behind a
+        // branch), then writes LDS: two dependent memory round trips.
+        constexpr int NG = N * N - MX * MX;
+        constexpr int NV = (MX * MX / 2 + NT - 1) / NT, NGH = (NG + NT - 1) / NT;
+        const uint32_t m = (uint32_t)(p - c.lstart[l]);
+        const int ix = (int)morton_compact(m), iy = (int)morton_compact(m >> 1), wrap = (1 << l) - 1;
+        auto side = [](int i) { return i < 0 ? -1 : (i >= MX ? 1 : 0); };
+        const int self = io->leaf_of_slot[p];
+        int gi[NGH], gj[NGH], gl[NGH];
+#pragma unroll
+        for (int v = 0; v < NGH; v++) {
+            int r;
+            ghost_region_index<MX>(min(tid + v * NT, NG - 1), gi[v], gj[v], r);
+            const int dx = side(gi[v]), dy = side(gj[v]);
+            gl[v] = io->leaf_of_slot[c.lstart[l] + (int)(morton_spread((uint32_t)((ix + dx) & wrap)) |
+                                                         (morton_spread((uint32_t)((iy + dy) & wrap)) << 1))];
         }
-        for (int g = tid; g < N * N - MX * MX; g += NT) {
-            int i, j, r;
-            ghost_region_index<MX>(g, i, j, r);
-            const NbrRec rec = c.nbr[(size_t)p * FC_NREC + r];
-            s.q[(j + MB) * NP + i + MB] =
-                io->qin[(size_t)io->leaf_of_slot[rec.id] * MX * MX + (j - rec.oy) * MX + i - rec.ox];
+        const double *qi = io->qin + (size_t)self * MX * MX;
+        double2 iv[NV];
+#pragma unroll
+        for (int v = 0; v < NV; v++)
+            iv[v] = *reinterpret_cast<const double2 *>(qi + 2 * min(tid + v * NT, MX * MX / 2 - 1));
+        double gv[NGH];
+#pragma unroll
+        for (int v = 0; v < NGH; v++) {
+            const int dx = side(gi[v]), dy = side(gj[v]);
+            gv[v] = io->qin[(size_t)gl[v] * MX * MX + (gj[v] - dy * MX) * MX + gi[v] - dx * MX];
         }
-        load_velocity<MX>(c, s, l, P.ix * MX, P.iy * MX, t, dt, nullptr, NI);
+        load_velocity<MX>(c, s, l, ix * MX, iy * MX, t, dt, nullptr, NI);
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            const int k = tid + v * NT, i = 2 * (k % (MX / 2)), j = k / (MX / 2);
+            if (k < MX * MX / 2) {
+                s.q[(j + MB) * NP + i + MB] = iv[v].x;
+                s.q[(j + MB) * NP + i + MB + 1] = iv[v].y;
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < NGH; v++)
+            if (tid + v * NT < NG) s.q[(gj[v] + MB) * NP + gi[v] + MB] = gv[v];
     } else if (!FUSED) {
         const PatchInfo P = c.info[p];
         load_velocity<MX>(c, s, l, P.ix * MX, P.iy * MX, t, dt, tdev, NI);
@@ -1919,6 +1945,7 @@ hipError_t launch_step_leaf(const Ctx &c, int mx, int level, int first, int coun
                             const int32_t *leaf_of_slot, const double *q_in, double *q_out, hipStream_t s) {
     if (count <= 0) return hipSuccess;
     const LeafIO io{q_in, q_out, leaf_of_slot};
+    if (!((c.complete >> level) & 1u)) return hipErrorInvalidValue;  // neighbour slots from the Morton index
     switch (mx) {
         case 8: hipLaunchKernelGGL((step_leaf_kernel<8, 64>), dim3(count), dim3(64), 0, s, c, first, count, level, t, dt, io); break;
         case 16: hipLaunchKernelGGL((step_leaf_kernel<16, 256>), dim3(count), dim3(256), 0, s, c, first, count, level, t, dt, io); break;
