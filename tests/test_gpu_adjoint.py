@@ -31,7 +31,7 @@ def rel(a, b):
 
 
 @pytest.mark.parametrize("limiter", ["mc", "lw", "minmod"])
-@pytest.mark.parametrize("level,mx", [(1, 32), (2, 16), (3, 8)])
+@pytest.mark.parametrize("level,mx", [(0, 16), (1, 32), (2, 16), (3, 8)])
 def test_adjoint_step_matches_oracle(B, oracle_lib, limiter, level, mx):
     L = S.uniform_leaves(level)
     q = S.sample_on_leaves(lambda x, y: np.exp(-((x - 0.4) ** 2 + (y - 0.6) ** 2) / 0.02)
@@ -46,7 +46,7 @@ def test_adjoint_step_matches_oracle(B, oracle_lib, limiter, level, mx):
 
 
 @pytest.mark.parametrize("limiter", ["mc", "lw", "first", "minmod"])
-@pytest.mark.parametrize("level,mx", [(1, 32), (2, 16), (3, 8)])
+@pytest.mark.parametrize("level,mx", [(0, 16), (1, 32), (2, 16), (3, 8)])
 def test_leaf_order_step_equals_graph_step_bitwise(B, limiter, level, mx):
     """fc_step_uniform (leaf order in and out) reproduces the store's
     graph-mode steps bit for bit, at the times the store accumulates."""
