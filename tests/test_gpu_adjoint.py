@@ -152,3 +152,25 @@ def test_full_size_gradient_matches_finite_differences_linear_scheme(B):
 
 def test_full_size_gradient_finite_differences_mc(B):
     _fd_check(B, "mc", 6, 5e-2)
+
+
+@pytest.mark.parametrize("limiter", ["mc", "minmod"])
+def test_full_size_steps_match_oracle(B, oracle_lib, limiter):
+    """The gradient workload's size (uniform level 6, 4096 patches of 32x32):
+    one leaf-order forward step and one adjoint step, every element, against
+    the oracle's step and hand-written discrete adjoint."""
+    import torch
+    level, mx = 6, 32
+    L = S.uniform_leaves(level)
+    q = S.sample_on_leaves(S.gaussians(S.gaussian_params(5)), L, mx)
+    lam = np.random.default_rng(6).standard_normal(q.shape)
+    dt, t = 0.9 / (mx << level), 0.17
+    ps = B.PatchStore(L, mx=mx, velocity="swirl", vel_params=(1.0, 0, 0), limiter=limiter)
+    o = oracle_lib.Oracle(L, mx=mx, velocity="swirl", vel_params=(1.0, 0, 0), limiter=limiter)
+    qd = torch.tensor(q, device="cuda")
+    g = ps.adjoint_step(level, t, dt, qd, torch.tensor(lam, device="cuda"))
+    assert rel(g, o.adjoint_step(level, t, dt, q, lam)) <= 1e-12
+    f = ps.step_uniform(level, t, dt, qd)
+    o.set_interior(q)
+    o.coarse_step(t, dt)
+    assert rel(f, o.interior()) <= 1e-12
