@@ -499,6 +499,13 @@ static double vel_v(const Orc *o, int l, int Ic, int Je, double tm) {
     return -(sy * sy * sin(2.0 * M_PI * x) * sig * c);
 }
 
+/* Read-only accessor for the tests: the edge velocity the scalar step uses.
+ * dir 0: u on x-edge I (between cells I-1 and I) of row J; dir 1: v on
+ * y-edge J of column I; level-l indices, at time tm. */
+double orc_edge_velocity(const Orc *o, int l, int dir, int I, int J, double tm) {
+    return dir == 0 ? vel_u(o, l, I, J, tm) : vel_v(o, l, I, J, tm);
+}
+
 /* ------------------------------------------------------------------ */
 /* scalar wave-propagation step on one patch                            */
 /* ------------------------------------------------------------------ */

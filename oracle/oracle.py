@@ -67,6 +67,8 @@ def lib():
         L.orc_regrid.restype = C.c_int
         L.orc_tangent_step.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_double, dp, dp, dp]
         L.orc_adjoint_step.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_double, dp, dp, dp]
+        L.orc_edge_velocity.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double]
+        L.orc_edge_velocity.restype = C.c_double
         L.orc_set_threads.argtypes = [C.c_int]
         L.orc_max_threads.restype = C.c_int
         _lib = L
@@ -201,6 +203,12 @@ class Oracle:
         out = np.empty_like(q)
         lib().orc_tangent_step(self._h, int(level), float(t), float(dt), _dp(q), _dp(d), _dp(out))
         return out
+
+    def edge_velocity(self, level, direction, I, J, tm):
+        """Edge velocity of the scalar step: direction 0 gives u on x-edge I
+        of row J, direction 1 gives v on y-edge J of column I (level-`level`
+        indices), at time tm."""
+        return lib().orc_edge_velocity(self._h, int(level), int(direction), int(I), int(J), float(tm))
 
     def adjoint_step(self, level, t, dt, q, lam):
         q = np.ascontiguousarray(q, dtype=np.float64)
