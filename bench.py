@@ -1,19 +1,25 @@
 """Benchmark: cell-updates/s of the AMR advance + ghost fill on one MI355X.
 
-Workload (default): uniform level 5 of the unit square, 1024 patches of
-32x32 cells with 2 ghost layers, FP64 scalar advection in the swirling
-deformational field, seeded sum of 8 Gaussians, 500 steps.  A "step" is
-one coarse step of the whole path: ghost fill + advance of every patch.
+Default workload: adaptive levels 3-7 of the unit square with 32x32 patches
+and 2 ghost layers, FP64 scalar advection in the swirling deformational
+field, seeded sum of 8 Gaussians, multirate subcycling (31 level-steps per
+coarse step), regrid every 2 coarse steps by tagging |grad q| > 0.05.  A
+"step" is one coarse step: ghost fill + advance of every patch on every
+level.  The metric counts cell updates (sum over level-steps of patches x
+mx^2) over the advance + fill time, measured with HIP events on the stream
+the work runs on; regridding (tag, host adaptation, transfer, and the graph
+capture a new mesh needs) is timed apart, as the paper reports it.
 
 The headline uses the fused form: one advance kernel per level-step that
 gathers its ghost values on the fly from neighbour interiors (no fill
-launch), chunks of 50 coarse steps captured once and replayed from a
-hipGraph.  The plain per-level launch form (a fill launch and an advance
-launch per level-step), the same fused kernels launched from the host, and
-the persistent single-kernel form are timed on the same workload and
-reported beside it.
+launch), the coarse steps between two regrids captured as one hipGraph and
+replayed.  The plain per-level form (a fill launch and an advance launch per
+level-step) is timed on the same meshes.  The line also carries the HBM
+roofline of the same kernel on uniform level 8 (65536 patches, 1.36 GB per
+buffer, far beyond the 256 MB Infinity Cache) and the CPU oracle's rate.
 
-Output: one JSON line on stdout.
+Other workloads: --workload swirl_uniform (--level sets the size),
+dam_break, adjoint.  Output: one JSON line on stdout.
 """
 from __future__ import annotations
 
@@ -21,6 +27,7 @@ import argparse
 import hashlib
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -45,17 +52,17 @@ def algorithmic_bytes(npatch, mx, F):
     return npatch * F * 8 * (N * N + mx * mx)
 
 
-def traffic_from_profiles(nt):
-    """HBM bytes per launch of the level-step kernel from the committed
-    counter summary, if it was taken on the current kernel source and launch
-    variant."""
-    p = os.path.join(ROOT, "profiles", "traffic_level_step_swirl_l5.json")
+def traffic_from_profiles(name, nt):
+    """Measured HBM bytes per algorithmic byte of the level-step kernel from a
+    committed counter summary, if it was taken on the current kernel source
+    and launch variant (else None)."""
+    p = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
     if d.get("kernel_sha") != kernel_hash():
         return None
-    return d.get("hbm_bytes_per_launch", {}).get(str(nt))
+    return d.get("hbm_over_algorithmic", {}).get(str(nt))
 
 
 def stream_copy_gbs(nbytes=1 << 30, reps=5):
@@ -80,14 +87,39 @@ def stream_copy_gbs(nbytes=1 << 30, reps=5):
     return 2.0 * n * 8 * reps / sec / 1e9
 
 
-def cpu_baseline(w, budget_s=15.0):
-    """The oracle, as is, on a bounded sample of the same workload."""
+def host_cpu():
+    """nproc, the CPU model and the cores this process may use (at most 16:
+    the host share of one GPU)."""
+    model = ""
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    try:
+        nproc = int(subprocess.run(["nproc"], capture_output=True, text=True, timeout=10).stdout.strip())
+    except Exception:
+        nproc = os.cpu_count() or 1
+    usable = min(len(os.sched_getaffinity(0)), 16)
+    return nproc, model, usable
+
+
+def cpu_baseline(w, budget_s=12.0):
+    """The oracle, as is, on a bounded sample of the same workload: every
+    usable core (OpenMP over patches) on whole coarse steps of the initial
+    mesh, and one core on one level-step (fill + advance) of the most
+    populated level."""
+    import numpy as np
     from oracle import oracle as O
-    nth = min(os.cpu_count() or 1, 16)
-    O.set_threads(nth)
+    nproc, model, usable = host_cpu()
+    O.set_threads(usable)
     o = O.from_workload(w)
     dt = w["dt_coarse"]
-    cells = len(w["leaves"]) * w["mx"] ** 2
+    lv = np.asarray(w["leaves"])[:, 0]
+    lmin = w["lmin"]
+    per_step = sum(int((lv == l).sum()) * w["mx"] ** 2 * (1 << (int(l) - lmin)) for l in np.unique(lv))
     t0 = time.perf_counter()
     o.coarse_step(0.0, dt)
     one = time.perf_counter() - t0
@@ -96,29 +128,49 @@ def cpu_baseline(w, budget_s=15.0):
     for s in range(n):
         o.coarse_step((s + 1) * dt, dt)
     el = time.perf_counter() - t0
-    return {"value": cells * n / el, "unit": "cell-updates/s", "cores": O.max_threads(), "kind": "oracle",
-            "sample": f"{n} steps of the same {len(w['leaves'])}-patch workload (after 1 untimed step)"}
+    allc = per_step * n / el
+    threads = O.max_threads()
+    # one core: fill + advance of the most populated level once
+    O.set_threads(1)
+    lbig = int(np.bincount(lv).argmax())
+    o2 = O.from_workload(w)
+    dtl = dt / (1 << (lbig - lmin))
+    t0 = time.perf_counter()
+    o2.ghost_fill(lbig, lbig, 1.0)
+    o2.advance_level(lbig, 0.0, dtl)
+    el1 = time.perf_counter() - t0
+    one_core = int((lv == lbig).sum()) * w["mx"] ** 2 / el1
+    return {"value": allc, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} coarse steps of the initial {len(lv)}-patch mesh (after 1 untimed step), "
+                      f"{threads} threads",
+            "nproc": nproc, "cpu_model": model,
+            "one_core": {"value": one_core, "unit": "cell-updates/s",
+                         "sample": f"one level-step (fill + advance) of level {lbig}, "
+                                   f"{int((lv == lbig).sum())} patches, 1 thread"}}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500)
-    ap.add_argument("--warmup", type=int, default=500,
-                    help="untimed steps first (the GPU's clocks settle over the first few milliseconds of load)")
-    ap.add_argument("--level", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed coarse steps (default: 40 for swirl_amr, 500 for swirl_uniform, 100 for dam_break)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed coarse steps first (default: 4 for swirl_amr, 500 for swirl_uniform)")
+    ap.add_argument("--level", type=int, default=5, help="level of --workload swirl_uniform")
     ap.add_argument("--mx", type=int, default=32)
-    ap.add_argument("--workload", default="swirl_uniform",
-                    choices=["swirl_uniform", "swirl_amr", "dam_break", "adjoint"],
-                    help="swirl_uniform (default; --level sets its size), swirl_amr (levels 3-7, regrid "
-                         "every 2 coarse steps), dam_break (shallow water, levels 2-6, 16x16), adjoint "
-                         "(gradient of an L2 misfit, uniform level 6, 256 steps, checkpoints every 16)")
+    ap.add_argument("--workload", default="swirl_amr",
+                    choices=["swirl_amr", "swirl_uniform", "dam_break", "adjoint"],
+                    help="swirl_amr (default: levels 3-7, regrid every 2 coarse steps), swirl_uniform (--level "
+                         "sets its size), dam_break (shallow water, levels 2-6, 16x16), adjoint (gradient of an "
+                         "L2 misfit, uniform level 6, 256 steps, checkpoints every 16)")
     ap.add_argument("--threads", type=int, default=0,
                     help="threads per patch of the advance kernels (0: autotune)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-level", action="store_true")
+    ap.add_argument("--no-l8", action="store_true", help="skip the uniform level-8 HBM-roofline field")
+    ap.add_argument("--l8-steps", type=int, default=40)
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
+                    help="first run three plain 256 MiB device copies (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -126,9 +178,6 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_1703_03116_amd import binding as B
-    from workloads import synth as S
-
     torch.cuda.set_device(0)
     if args.copy_calibration:
         # a plain copy kernel of known size: reads 256 MiB, writes 256 MiB
@@ -140,16 +189,37 @@ def main():
         del src, dst
     if args.workload == "adjoint":
         return adjoint_workload(args)
-    if args.workload != "swirl_uniform":
-        return other_workload(args)
-    w = S.workload("swirl_uniform", level=args.level, mx=args.mx, steps=args.steps)
-    P, mx, F = len(w["leaves"]), w["mx"], 1
+    if args.workload == "dam_break":
+        return dam_break_workload(args)
+    if args.workload == "swirl_uniform":
+        steps = args.steps if args.steps is not None else 500
+        warm = args.warmup if args.warmup is not None else 500
+        out = uniform_workload(args.level, args.mx, steps, warm, args.threads, not args.no_per_level)
+        if not args.no_cpu_baseline:
+            from workloads import synth as S
+            w = S.workload("swirl_uniform", level=args.level, mx=args.mx, steps=steps)
+            out["cpu_baseline"] = cpu_baseline(w)
+        print(json.dumps(out), flush=True)
+        return
+    return amr_workload(args)
+
+
+def uniform_workload(level, mx, steps, warmup, threads=0, forms=True):
+    """Uniform level of the swirl workload, graph form (one level-step kernel
+    per coarse step, 50-step chunks plus one graph for the rest replayed);
+    returns the fields of a bench line (no cpu_baseline)."""
+    import torch
+    from paper_1703_03116_amd import binding as B
+    from workloads import synth as S
+
+    w = S.workload("swirl_uniform", level=level, mx=mx, steps=steps)
+    P, F = len(w["leaves"]), 1
     dt = w["dt_coarse"]
     cells_per_step = P * mx * mx
     ps = B.from_workload(w)
-    if args.threads:
-        ps.set_variant(args.threads)
-        nt = args.threads
+    if threads:
+        ps.set_variant(threads)
+        nt = threads
     else:
         nt = ps.autotune()
     stream = torch.cuda.current_stream()
@@ -163,117 +233,170 @@ def main():
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / 1e3
 
-    # headline: one ghost-gathering advance kernel per level-step, chunks of
-    # coarse steps replayed from a captured hipGraph; the graphs the timed
-    # steps replay are captured (one-time set-up, timed apart) after the
-    # warm-up steps and before the timed region
-    ps.coarse_steps(dt, args.warmup, "graph")
+    # the graphs the timed steps replay are captured (one-time set-up, timed
+    # apart) after the warm-up steps and before the timed region
+    ps.coarse_steps(dt, warmup, "graph")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ps.prepare_steps(dt, args.steps, "graph")
+    ps.prepare_steps(dt, steps, "graph")
     torch.cuda.synchronize()
     capture_ms = 1e3 * (time.perf_counter() - t0)
-    sec = timed(ps, "graph", args.steps)
+    sec = timed(ps, "graph", steps)
     ps.check()
-    value = cells_per_step * args.steps / sec
-    # uniform level: one level-step kernel launch per coarse step (plus one
-    # small bookkeeping node per 50 steps); the average launch duration over
-    # the timed region, measured with events on the stream the graph runs on
-    # (node gaps included)
-    avg_launch = sec / args.steps
+    value = cells_per_step * steps / sec
+    # one level-step kernel launch per coarse step (plus one bookkeeping node
+    # per replayed graph): the average launch duration over the timed region,
+    # measured with events on the stream the graph runs on (node gaps included)
+    avg_launch = sec / steps
     bpl = algorithmic_bytes(P, mx, F)
     achieved = bpl / avg_launch / 1e9
-    traffic = traffic_from_profiles(nt)
-
-    forms = {}
-    if not args.no_per_level:
-        for mode in ("per_level", "persistent_graph", "fused_levels"):
+    ratio = traffic_from_profiles(f"traffic_level_step_swirl_l{level}.json", nt)
+    del ps
+    forms_out = {}
+    if forms:
+        for mode in ("per_level", "fused_levels"):
             ps2 = B.from_workload(w)
             ps2.set_variant(nt)
-            ps2.coarse_steps(dt, args.warmup, mode)
-            ps2.prepare_steps(dt, args.steps, mode)
-            s2 = timed(ps2, mode, args.steps)
+            ps2.coarse_steps(dt, min(warmup, 50), mode)
+            ps2.prepare_steps(dt, steps, mode)
+            s2 = timed(ps2, mode, steps)
             ps2.check()
-            forms[mode] = {"value": cells_per_step * args.steps / s2, "ms_per_step": 1e3 * s2 / args.steps}
+            forms_out[mode] = {"value": cells_per_step * steps / s2, "ms_per_step": 1e3 * s2 / steps}
             del ps2
-    per_level = forms.get("per_level")
-
+    torch.cuda.empty_cache()
     copy_gbs = stream_copy_gbs()
-    cpu = None if args.no_cpu_baseline else cpu_baseline(w)
-    out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "cell-updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * sec / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": f"swirl_uniform_l{args.level}: {P} patches of {mx}x{mx} cells, 2 ghost layers, "
-                               f"FP64 scalar advection, swirl field T=1, seeded 8-Gaussian data, "
-                               f"{args.steps} steps",
+    per_level = forms_out.get("per_level")
+    return {
+        "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": 1e3 * sec / steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"swirl_uniform_l{level}: {P} patches of {mx}x{mx} cells, 2 ghost layers, "
+                               f"FP64 scalar advection, swirl field T=1, seeded 8-Gaussian data, {steps} steps",
                    "patches": P, "mx": mx, "cells": cells_per_step,
                    "mode": "fused: one ghost-gathering advance kernel per level-step, replayed from a hipGraph",
                    "threads_per_patch": nt, "graph_capture_ms": capture_ms},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "level_step_kernel<32,%d,0>" % nt, "bytes_per_launch": bpl,
-                     "avg_launch_ms": 1e3 * avg_launch,
-                     "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": (ratio * bpl) if ratio else None,
+                     "kernel": "level_step_kernel<%d,%d,0>" % (mx, nt), "bytes_per_launch": bpl,
+                     "avg_launch_ms": 1e3 * avg_launch, "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
         "per_level": per_level,
-        "other_forms": forms,
+        "other_forms": forms_out,
         "fused_over_per_level": (value / per_level["value"]) if per_level else None,
-        "cpu_baseline": cpu,
     }
-    print(json.dumps(out), flush=True)
 
 
-def other_workload(args):
-    """Adaptive workloads: cell updates over advance + fill time (regrid timed
-    apart), fused graph form and per-level form, one JSON line."""
-    import numpy as np
+def amr_workload(args):
+    """The default line: adaptive swirl, levels 3-7 (see the module
+    docstring), graph form against the per-level form on the same meshes."""
     import torch
     from paper_1703_03116_amd import binding as B
     from paper_1703_03116_amd.amr import run_adaptive
     from workloads import synth as S
 
+    steps = args.steps if args.steps is not None else 40
+    warm = args.warmup if args.warmup is not None else 4
+    w = S.workload("swirl_amr", steps=steps)
+    dt = w["dt_coarse"]
+    cap = 4 ** w["lmax"]
+    ps = B.from_workload(w, capacity=cap)
+    if args.threads:
+        nt = args.threads
+    else:
+        nt = ps.autotune()
+    del ps
+    res = {}
+    for mode in ("graph",) + (() if args.no_per_level else ("per_level",)):
+        ps = B.from_workload(w, capacity=cap)
+        ps.set_variant(nt)
+        run_adaptive(ps, dt, warm, regrid_every=2, mode=mode)
+        tm = {}
+        cells = run_adaptive(ps, dt, steps, regrid_every=2, mode=mode, timings=tm)
+        ps.check()
+        res[mode] = {"value": cells / tm["advance"], "ms_per_step": 1e3 * tm["advance"] / steps,
+                     "advance_s": tm["advance"], "regrid_s": tm["regrid"], "regrids": tm["regrids"],
+                     "launches": tm["launches"], "bytes": tm["bytes"], "cells": cells,
+                     "patches_end": ps.nleaves}
+        del ps
+        torch.cuda.empty_cache()
+    g = res["graph"]
+    achieved = g["bytes"] / g["advance_s"] / 1e9
+    bpl = g["bytes"] / g["launches"]
+    ratio = traffic_from_profiles("traffic_level_step_swirl_amr.json", nt)
+    copy_gbs = stream_copy_gbs()
+    l8 = None
+    if not args.no_l8:
+        u = uniform_workload(8, 32, args.l8_steps, args.l8_steps, nt, not args.no_per_level)
+        l8 = {"workload": u["config"]["workload"], "value": u["value"], "unit": "cell-updates/s",
+              "ms_per_step": u["ms_per_step"], "roofline": u["roofline"],
+              "per_level": u["per_level"], "fused_over_per_level": u["fused_over_per_level"]}
+        torch.cuda.empty_cache()
+    lv = w["leaves"][:, 0]
+    per_level = res.get("per_level")
+    out = {
+        "metric": METRIC, "value": g["value"], "unit": "cell-updates/s", "n_gpus": 1, "steps": steps,
+        "warmup": warm, "ms_per_step": g["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"swirl_amr: adaptive levels 3-7, 32x32 patches, 2 ghost layers, FP64 scalar "
+                               f"advection, swirl field T=1, seeded 8-Gaussian data (seed 3), multirate "
+                               f"(31 level-steps per coarse step), regrid every 2 coarse steps by |grad q| > 0.05, "
+                               f"{steps} coarse steps after {warm}",
+                   "patches_start": len(lv), "patches_end": g["patches_end"], "mx": 32,
+                   "mode": "fused: one ghost-gathering advance kernel per level-step, the coarse steps between "
+                           "two regrids replayed from one hipGraph",
+                   "threads_per_patch": nt, "cell_updates": g["cells"],
+                   "regrid_ms_each": 1e3 * g["regrid_s"] / max(1, g["regrids"]),
+                   "value_with_regrid": g["cells"] / (g["advance_s"] + g["regrid_s"])},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": (ratio * bpl) if ratio else None,
+                     "kernel": "level_step_kernel<32,%d,0>" % nt, "launches": g["launches"],
+                     "bytes_per_launch": bpl, "avg_launch_ms": 1e3 * g["advance_s"] / g["launches"],
+                     "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
+        "per_level": per_level,
+        "fused_over_per_level": (g["value"] / per_level["value"]) if per_level else None,
+        "hbm_roofline_uniform_l8": l8,
+        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline(w),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def dam_break_workload(args):
+    """Shallow-water dam break (levels 2-6, 16x16, reflecting walls), fixed
+    coarse step, graph form against the per-level form, one JSON line."""
+    import numpy as np
+    import torch
+    from paper_1703_03116_amd import binding as B
+    from workloads import synth as S
+
+    steps = args.steps if args.steps is not None else 100
     res = {}
     for mode in ("graph", "per_level"):
-        if args.workload == "swirl_amr":
-            w = S.workload("swirl_amr")
-            ps = B.from_workload(w, capacity=4 ** w["lmax"])
-            nt = ps.autotune()
-            tm = {}
-            run_adaptive(ps, w["dt_coarse"], 2, regrid_every=2, mode=mode)  # warm-up
-            cells = run_adaptive(ps, w["dt_coarse"], args.steps, regrid_every=2, mode=mode, timings=tm)
-            res[mode] = {"value": cells / tm["advance"], "advance_s": tm["advance"],
-                         "regrid_s": tm.get("regrid", 0.0), "patches_end": ps.nleaves}
+        w = S.workload("dam_break")
+        ps = B.from_workload(w)
+        if args.threads:
+            ps.set_variant(args.threads)
+            nt = args.threads
         else:
-            w = S.workload("dam_break")
-            ps = B.from_workload(w)
             nt = ps.autotune()
-            lv = np.asarray(w["leaves"])[:, 0]
-            dt = 0.6 / (w["mx"] << w["lmin"]) / 2.5   # finest-level Courant number <= 0.6 for speeds <= 2.5
-            per_step = sum(int((lv == l).sum()) * w["mx"] ** 2 * (1 << (l - w["lmin"])) for l in np.unique(lv))
-            ps.coarse_steps(dt, 2, mode)
-            torch.cuda.synchronize()
-            stream = torch.cuda.current_stream()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            ps.coarse_steps(dt, args.steps, mode)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            sec = e0.elapsed_time(e1) / 1e3
-            ps.check()
-            res[mode] = {"value": per_step * args.steps / sec, "ms_per_coarse_step": 1e3 * sec / args.steps,
-                         "patches": len(lv)}
+        lv = np.asarray(w["leaves"])[:, 0]
+        dt = 0.6 / (w["mx"] << w["lmin"]) / 2.5   # finest-level Courant number <= 0.6 for speeds <= 2.5
+        per_step = sum(int((lv == l).sum()) * w["mx"] ** 2 * (1 << (l - w["lmin"])) for l in np.unique(lv))
+        ps.coarse_steps(dt, 2, mode)
+        ps.prepare_steps(dt, steps, mode)
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ps.coarse_steps(dt, steps, mode)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) / 1e3
+        ps.check()
+        res[mode] = {"value": per_step * steps / sec, "ms_per_coarse_step": 1e3 * sec / steps,
+                     "patches": len(lv)}
     out = {"metric": METRIC, "value": res["graph"]["value"], "unit": "cell-updates/s", "n_gpus": 1,
-           "steps": args.steps, "warmup": 2, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f64", "data": "synthetic", "config": {"workload": args.workload, "threads_per_patch": nt},
+           "steps": steps, "warmup": 2, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "ms_per_step": res["graph"]["ms_per_coarse_step"],
+           "dtype": "f64", "data": "synthetic", "config": {"workload": "dam_break", "threads_per_patch": nt},
            "fused_graph": res["graph"], "per_level": res["per_level"],
            "fused_over_per_level": res["graph"]["value"] / res["per_level"]["value"]}
     print(json.dumps(out), flush=True)
@@ -290,7 +413,7 @@ def adjoint_workload(args):
     from paper_1703_03116_amd.adjoint import loss_and_grad
     from workloads import synth as S
 
-    level, mx, n, every = 6, 32, (args.steps if args.steps != 500 else 256), 16
+    level, mx, n, every = 6, 32, (args.steps if args.steps is not None else 256), 16
     L = S.uniform_leaves(level)
     q0 = torch.tensor(S.sample_on_leaves(S.gaussians(S.gaussian_params(5)), L, mx), device="cuda")
     qt = torch.tensor(S.sample_on_leaves(S.gaussians(S.gaussian_params(6)), L, mx), device="cuda")

@@ -49,10 +49,11 @@ enum {
     FC_ERR_UNBALANCED = -2,   /* leaves not 2:1 balanced over faces and corners      */
     FC_ERR_GHOST_WIDTH = -3,  /* m > mx/4 or mx odd: Prop. 2.1 condition violated     */
     FC_ERR_HIP = -4,          /* a HIP runtime call failed                            */
-    FC_ERR_CFL = -5,          /* reserved: the binding reports CFL > cfl_max          */
+    FC_ERR_CFL = -5,          /* a step's Courant number exceeded cfl_max             */
     FC_ERR_STATE = -6,        /* call out of order (e.g. not bound)                   */
     FC_ERR_CAPACITY = -7,     /* more leaves than the store's capacity                */
-    FC_ERR_COVER = -8         /* leaves overlap or do not tile the unit square        */
+    FC_ERR_COVER = -8,        /* leaves overlap or do not tile the unit square        */
+    FC_ERR_NONFINITE = -9     /* a patch holds a NaN (found by the tagging reduction) */
 };
 
 enum { FC_EQ_ADVECTION = 0, FC_EQ_SWE = 1 };
@@ -85,6 +86,9 @@ typedef struct {
     int32_t time_stepping; /* FC_STEP_MULTIRATE | FC_STEP_GLOBAL                     */
     int32_t reserved;
     int64_t capacity;      /* patch slots; >= number of leaves; regrid up to this    */
+    double cfl_max;        /* > 0: largest Courant number a step may reach (a
+                              larger one is an error, or a rejected step in
+                              fc_advance_adaptive); 0: not checked              */
 } fc_config;
 
 typedef struct fc_patchstore fc_patchstore;
@@ -103,7 +107,9 @@ fc_status fc_patchstore_destroy(fc_patchstore *ps);
 
 /* Sizes of the caller-owned device memory: q_doubles = doubles per patch
  * buffer (nfields * capacity * N * N; two such buffers are needed) and
- * ws_bytes = workspace bytes (metadata, velocity tables, schedule, state). */
+ * ws_bytes = workspace bytes (metadata, velocity tables, schedule, state;
+ * with cfl_max > 0 also room to keep one copy of the interiors, for
+ * rejected steps). */
 fc_status fc_patchstore_sizes(const fc_patchstore *ps, int64_t *q_doubles, int64_t *ws_bytes);
 
 /* Bind caller-owned device memory (q0, q1: q_doubles each; workspace:
@@ -147,7 +153,11 @@ fc_status fc_ghost_fill(fc_patchstore *ps, int32_t level_lo, int32_t level_hi, d
 fc_status fc_advance_level(fc_patchstore *ps, int32_t level, double t, double dt, double *cfl_dev,
                            void *stream);
 
-/* One coarse step of the configured time stepping, from the store's time t
+/* As above; with cfl_max > 0 in the configuration and cfl_dev given, a
+ * Courant number above cfl_max is recorded on the device and reported as
+ * FC_ERR_CFL by fc_check_device.
+ *
+ * One coarse step of the configured time stepping, from the store's time t
  * by dt_coarse (multirate: level l takes 2^(l-min_level) steps of
  * dt_coarse / 2^(l-min_level); global: every level one step of dt_coarse).
  * mode FC_MODE_PER_LEVEL: a fill launch and an advance launch per
@@ -163,6 +173,27 @@ fc_status fc_advance_level(fc_patchstore *ps, int32_t level, double t, double dt
  * advances by nsteps * dt_coarse. */
 fc_status fc_advance_coarse_steps(fc_patchstore *ps, double dt_coarse, int32_t nsteps, int32_t mode,
                                   double *cfl_dev, void *stream);
+/* Advance the store to time t_end with a coarse step chosen from the
+ * measured Courant number, as Clawpack does (the time step the paper's
+ * solver library takes; Sec. 5 runs Clawpack): each coarse step is tried
+ * with dt = *dt_inout (the last one shortened to land on t_end); if its
+ * Courant number (the maximum over every level-step of the coarse step, the
+ * same value cfl_dev receives above) exceeds cfl_max the step is rejected:
+ * the interiors are restored from a copy taken before it, and it is tried
+ * again with dt * cfl_target / CFL (dt / 2 if the Courant number is not a
+ * finite number: the try blew up).  After an accepted step the next try is
+ * dt * cfl_target / CFL.  The store's time ends at exactly t_end.
+ * *dt_inout receives the next proposed coarse step; steps_out / rejected_out
+ * (may be NULL) the accepted and rejected coarse steps.  Synchronises
+ * `stream` once per coarse step (the Courant number decides on the host).
+ * Needs cfl_max > 0 at create (FC_ERR_STATE otherwise); FC_ERR_ARG for
+ * dt <= 0, cfl_target outside (0, cfl_max] or max_steps < 1; FC_ERR_CFL when
+ * one step is rejected eight times in a row; stops after max_steps accepted
+ * steps (check the time). */
+fc_status fc_advance_adaptive(fc_patchstore *ps, double t_end, double cfl_target, int32_t mode,
+                              double *dt_inout, int32_t max_steps, int32_t *steps_out,
+                              int32_t *rejected_out, void *stream);
+
 /* Set-up for the graph modes: capture and instantiate, without running them,
  * the graphs that a call fc_advance_coarse_steps(ps, dt_coarse, nsteps,
  * mode) made next (from the store's current parities) replays, so that the
@@ -179,7 +210,9 @@ fc_status fc_set_time(fc_patchstore *ps, double t);
  * cells of |grad q| (central differences of field 0 divided by 2h; ghosts
  * must be valid).  tags_dev[k] = +1 if g > tau_refine and level < max_level,
  * -1 if g <= tau_coarsen and level > min_level, else 0.  gmax2_dev (may be
- * NULL) receives g^2.  Device arrays of nleaves entries. */
+ * NULL) receives g^2.  Device arrays of nleaves entries.  The reduction
+ * carries NaN through: a patch whose gradient is NaN gets g^2 = NaN and tag
+ * 0, and fc_check_device then reports FC_ERR_NONFINITE. */
 fc_status fc_tag_refine(fc_patchstore *ps, double tau_refine, double tau_coarsen, int8_t *tags_dev,
                         double *gmax2_dev, void *stream);
 
@@ -195,7 +228,10 @@ fc_status fc_adapt(const fc_patchstore *ps, const int8_t *tags, fc_leaf *out, in
  * the solution: unchanged leaves are copied, children are interpolated from
  * their parent with the ghost-fill interpolation (fill ghosts first),
  * parents are the mean of their four children.  All levels must be
- * synchronised.  Afterwards "input-leaf order" is the order of new_leaves. */
+ * synchronised.  Afterwards "input-leaf order" is the order of new_leaves.
+ * A leaf set that is not a valid 2:1 tiling, or has a leaf that is neither
+ * an old leaf, a child of one nor the parent of four, is rejected before
+ * anything changes (the store stays as it was). */
 fc_status fc_regrid(fc_patchstore *ps, int64_t nleaves, const fc_leaf *new_leaves, void *stream);
 
 /* One step of the unsplit scheme (the same step as fc_advance_level after
@@ -219,8 +255,10 @@ fc_status fc_adjoint_step(fc_patchstore *ps, int32_t level, double t, double dt,
                           const double *lambda_in, double *lambda_out, void *stream);
 
 /* Synchronise `stream` and report device-side errors raised since bind:
- * a device-wide barrier that timed out (FC_ERR_HIP) or an interpolation
- * stencil that needed a third level (FC_ERR_HIP; excluded by Prop. 2.1). */
+ * a device-wide barrier that timed out (FC_ERR_HIP), an interpolation
+ * stencil that needed a third level (FC_ERR_HIP; excluded by Prop. 2.1), a
+ * Courant number above cfl_max (FC_ERR_CFL), a NaN met by the tagging
+ * reduction (FC_ERR_NONFINITE).  The flags stay raised until the next bind. */
 fc_status fc_check_device(fc_patchstore *ps, void *stream);
 
 /* Choose the launch configuration (waves per patch) of the advance kernels

@@ -24,12 +24,13 @@ STEP = {"multirate": 0, "global": 1}
 MODE = {"per_level": 0, "fused": 1, "graph": 2, "fused_levels": 3, "persistent_graph": 4}
 
 FC_ERRORS = {-1: "FC_ERR_ARG", -2: "FC_ERR_UNBALANCED", -3: "FC_ERR_GHOST_WIDTH", -4: "FC_ERR_HIP",
-             -5: "FC_ERR_CFL", -6: "FC_ERR_STATE", -7: "FC_ERR_CAPACITY", -8: "FC_ERR_COVER"}
+             -5: "FC_ERR_CFL", -6: "FC_ERR_STATE", -7: "FC_ERR_CAPACITY", -8: "FC_ERR_COVER",
+             -9: "FC_ERR_NONFINITE"}
 
 EXPORTS = ["fc_last_error", "fc_patchstore_create", "fc_patchstore_destroy", "fc_patchstore_sizes",
            "fc_patchstore_bind", "fc_patchstore_info", "fc_patchstore_leaves", "fc_set_interior",
            "fc_get_interior", "fc_get_patches", "fc_ghost_fill", "fc_advance_level",
-           "fc_advance_coarse_steps", "fc_get_time", "fc_set_time", "fc_tag_refine", "fc_adapt", "fc_regrid",
+           "fc_advance_coarse_steps", "fc_advance_adaptive", "fc_get_time", "fc_set_time", "fc_tag_refine", "fc_adapt", "fc_regrid",
            "fc_prepare_steps", "fc_step_uniform", "fc_adjoint_step", "fc_check_device", "fc_autotune", "fc_set_variant", "fc_set_persistent_grid"]
 
 
@@ -47,7 +48,8 @@ class Config(C.Structure):
     _fields_ = [("mx", C.c_int32), ("mbc", C.c_int32), ("equation", C.c_int32), ("limiter", C.c_int32),
                 ("bc", C.c_int32 * 4), ("velocity", C.c_int32), ("vel_params", C.c_double * 3),
                 ("gravity", C.c_double), ("min_level", C.c_int32), ("max_level", C.c_int32),
-                ("time_stepping", C.c_int32), ("reserved", C.c_int32), ("capacity", C.c_int64)]
+                ("time_stepping", C.c_int32), ("reserved", C.c_int32), ("capacity", C.c_int64),
+                ("cfl_max", C.c_double)]
 
 
 _lib = None
@@ -74,6 +76,8 @@ def lib():
         L.fc_ghost_fill.argtypes = [vp, C.c_int32, C.c_int32, C.c_double, vp]
         L.fc_advance_level.argtypes = [vp, C.c_int32, C.c_double, C.c_double, vp, vp]
         L.fc_advance_coarse_steps.argtypes = [vp, C.c_double, C.c_int32, C.c_int32, vp, vp]
+        L.fc_advance_adaptive.argtypes = [vp, C.c_double, C.c_double, C.c_int32, C.POINTER(C.c_double), C.c_int32,
+                                          C.POINTER(C.c_int32), C.POINTER(C.c_int32), vp]
         L.fc_get_time.argtypes = [vp, C.POINTER(C.c_double)]
         L.fc_set_time.argtypes = [vp, C.c_double]
         L.fc_tag_refine.argtypes = [vp, C.c_double, C.c_double, vp, vp, vp]
@@ -120,7 +124,7 @@ class PatchStore:
 
     def __init__(self, leaves, mx=32, equation="advection", limiter="mc", bc=("periodic",) * 4,
                  velocity="swirl", vel_params=(1.0, 0.0, 0.0), gravity=1.0, min_level=None, max_level=None,
-                 time_stepping="multirate", capacity=None):
+                 time_stepping="multirate", capacity=None, cfl_max=0.0):
         L = lib()
         arr, n = _leaves_array(leaves)
         lv = np.asarray(leaves, dtype=np.int32).reshape(-1, 3)
@@ -138,6 +142,7 @@ class PatchStore:
         cfg.max_level = int(lv[:, 0].max()) if max_level is None else int(max_level)
         cfg.time_stepping = STEP[time_stepping]
         cfg.capacity = int(capacity if capacity is not None else n)
+        cfg.cfl_max = float(cfl_max)
         self.cfg = cfg
         self.mx, self.N, self.F = mx, mx + 4, 3 if equation == "swe" else 1
         self.min_level, self.max_level = cfg.min_level, cfg.max_level
@@ -157,6 +162,7 @@ class PatchStore:
         _check(L.fc_patchstore_bind(h, C.c_void_p(self.q0.data_ptr()), C.c_void_p(self.q1.data_ptr()),
                                     C.c_void_p(self._ws_ptr), _stream()))
         self.nleaves = n
+        self.input_leaves = lv.copy()   # the order interior arrays use
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -215,6 +221,15 @@ class PatchStore:
         p = C.c_void_p(cfl.data_ptr()) if cfl is not None else None
         _check(lib().fc_advance_coarse_steps(self._h, float(dt_coarse), int(nsteps), MODE[mode], p, _stream()))
 
+    def advance_adaptive(self, t_end, dt, cfl_target=0.9, mode="graph", max_steps=100000):
+        """Clawpack-style adaptive coarse steps to t_end (needs cfl_max at
+        creation); returns (next proposed dt, accepted steps, rejected steps)."""
+        d = C.c_double(float(dt))
+        ns, nr = C.c_int32(), C.c_int32()
+        _check(lib().fc_advance_adaptive(self._h, float(t_end), float(cfl_target), MODE[mode], C.byref(d),
+                                         int(max_steps), C.byref(ns), C.byref(nr), _stream()))
+        return d.value, ns.value, nr.value
+
     def tag(self, tau_refine, tau_coarsen):
         tags = torch.zeros(self.nleaves, dtype=torch.int8, device="cuda")
         g2 = torch.zeros(self.nleaves, dtype=torch.float64, device="cuda")
@@ -234,6 +249,7 @@ class PatchStore:
         arr, n = _leaves_array(new_leaves)
         _check(lib().fc_regrid(self._h, n, arr, _stream()))
         self.nleaves = n
+        self.input_leaves = np.asarray(new_leaves, dtype=np.int32).reshape(-1, 3).copy()
 
     def step_uniform(self, level, t, dt, q_in):
         """q(t + dt) from q(t) = q_in on a uniform periodic level, leaf order;
@@ -270,11 +286,12 @@ class PatchStore:
         return mg.value
 
 
-def from_workload(w, limiter="mc", capacity=None, time_stepping=None):
+def from_workload(w, limiter="mc", capacity=None, time_stepping=None, cfl_max=0.0):
     """PatchStore for a workloads.synth workload dict, q0 loaded."""
     ps = PatchStore(w["leaves"], mx=w["mx"], equation=w["equation"], limiter=limiter, bc=w["bc"],
                     velocity=w["velocity"], vel_params=w["vel_params"], gravity=w.get("gravity", 1.0),
                     min_level=w["lmin"], max_level=w["lmax"],
-                    time_stepping=time_stepping or w.get("time_stepping", "multirate"), capacity=capacity)
+                    time_stepping=time_stepping or w.get("time_stepping", "multirate"), capacity=capacity,
+                    cfl_max=cfl_max)
     ps.set_interior(w["q0"])
     return ps

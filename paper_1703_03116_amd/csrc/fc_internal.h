@@ -52,7 +52,9 @@ struct DevState {
     unsigned long long cfl_bits;  // max Courant number (bits of a non-negative double)
     uint32_t curmask;          // bit l: current buffer of level l
     uint32_t bar_count, bar_gen;
-    int32_t err;               // bit 0: barrier spin limit hit; bit 1: stencil out of range
+    int32_t err;               // bit 0: barrier spin limit hit; bit 1: stencil out of range;
+                               // bit 2: graph did not cover a level; bit 3: NaN met by tagging;
+                               // bit 4: Courant number above cfl_max
     int32_t pad;
     // ts[k]: the time after k further coarse steps, accumulated as the host
     // accumulates it (t += dt_coarse), k = 0 .. FC_TCHUNK
@@ -135,8 +137,13 @@ hipError_t launch_tag(const Ctx &c, int mx, const int32_t *slot_of_leaf, int n, 
                       double tau_r, double tau_c, int8_t *tags, double *g2, hipStream_t s);
 hipError_t launch_consolidate(const Ctx &c, int mx, int n, hipStream_t s);
 hipError_t launch_transfer(const Ctx &c, int mx, const TransferRec *plan, int n, hipStream_t s);
-// *cfl_dev = max(*cfl_dev, device state's maximum, max of the n slots)
-hipError_t launch_export_cfl(DevState *state, const unsigned long long *cflp, int n, double *cfl_dev, hipStream_t s);
+// *cfl_dev = max(*cfl_dev, device state's maximum, max of the n slots); with
+// cfl_max > 0 a maximum above it raises bit 16 of *err
+hipError_t launch_export_cfl(DevState *state, const unsigned long long *cflp, int n, double *cfl_dev, double cfl_max,
+                             int32_t *err, hipStream_t s);
+// restore == 0: save[leaf k in store order][F][mx][mx] <- the current
+// interiors of slot k; restore == 1: the reverse
+hipError_t launch_copy_interiors(const Ctx &c, int mx, int n, double *save, int restore, hipStream_t s);
 hipError_t launch_step_leaf(const Ctx &c, int mx, int level, int first, int count, double t, double dt,
                             const int32_t *leaf_of_slot, const double *q_in, double *q_out, hipStream_t s);
 hipError_t launch_adjoint(const Ctx &c, int mx, int level, int first, int count, double t, double dt, const int32_t *leaf_of_slot,

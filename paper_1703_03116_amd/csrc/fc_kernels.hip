@@ -1624,7 +1624,7 @@ __global__ void zero_cfl_kernel(unsigned long long *cflp, int n) {
 }
 
 __global__ void __launch_bounds__(256) export_cfl_kernel(const DevState *st, const unsigned long long *cflp, int n,
-                                                            double *cfl) {
+                                                            double *cfl, double cfl_max, int32_t *err) {
     __shared__ double red[4];
     double v = 0.0;
     for (int k = threadIdx.x; k < n; k += 256) v = fmax(v, __longlong_as_double((long long)cflp[k]));
@@ -1635,6 +1635,21 @@ __global__ void __launch_bounds__(256) export_cfl_kernel(const DevState *st, con
         double m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
         if (st) m = fmax(m, __longlong_as_double((long long)st->cfl_bits));
         if (m > *cfl) *cfl = m;
+        if (cfl_max > 0.0 && m > cfl_max) atomicOr(err, 16);
+    }
+}
+
+// interiors of the n slots' current buffers <-> save[slot][F][mx][mx]
+template <int MX>
+__global__ void copy_interiors_kernel(Ctx c, int n, double *save, int restore) {
+    constexpr int N = MX + 2 * MB;
+    const long long tot = (long long)n * c.F * MX * MX;
+    for (long long k = blockIdx.x * (long long)blockDim.x + threadIdx.x; k < tot; k += (long long)gridDim.x * blockDim.x) {
+        const int i = k % MX, j = (k / MX) % MX, f = (k / (MX * MX)) % c.F;
+        const int p = (int)(k / ((long long)MX * MX * c.F));
+        double *q = buf_of(c, view_of(c), c.info[p].level) + qidx(c.cap, N, f, p, i, j);
+        if (restore) *q = save[k];
+        else save[k] = *q;
     }
 }
 
@@ -1664,7 +1679,12 @@ __global__ void get_interior_kernel(Ctx c, const int32_t *slot_of_leaf, int n, d
     }
 }
 
-// tagging: max over interior of |grad q|^2 with central differences / 2h
+// maximum that keeps a NaN: once either argument is NaN the result is NaN
+__device__ __forceinline__ double nan_max(double a, double b) { return (a > b || a != a) ? a : b; }
+
+// tagging: max over interior of |grad q|^2 with central differences / 2h; a
+// NaN anywhere in the patch survives the reduction and raises bit 8 of the
+// error flags
 template <int MX>
 __global__ void __launch_bounds__(256) tag_kernel(Ctx c, const int32_t *slot_of_leaf, int lmin, int lmax,
                                                   double tau_r, double tau_c, int8_t *tags, double *g2out) {
@@ -1680,16 +1700,17 @@ __global__ void __launch_bounds__(256) tag_kernel(Ctx c, const int32_t *slot_of_
         const int i = k % MX, j = k / MX;
         const double gx = (q[qidx(c.cap, N, 0, p, i + 1, j)] - q[qidx(c.cap, N, 0, p, i - 1, j)]) / (2.0 * h);
         const double gy = (q[qidx(c.cap, N, 0, p, i, j + 1)] - q[qidx(c.cap, N, 0, p, i, j - 1)]) / (2.0 * h);
-        g2 = fmax(g2, gx * gx + gy * gy);
+        g2 = nan_max(g2, gx * gx + gy * gy);
     }
-    for (int o = 32; o > 0; o >>= 1) g2 = fmax(g2, __shfl_xor(g2, o, 64));
+    for (int o = 32; o > 0; o >>= 1) g2 = nan_max(g2, __shfl_xor(g2, o, 64));
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = g2;
     __syncthreads();
     if (threadIdx.x == 0) {
         double m = red[0];
-        for (int w = 1; w < (int)(blockDim.x >> 6); w++) m = fmax(m, red[w]);
+        for (int w = 1; w < (int)(blockDim.x >> 6); w++) m = nan_max(m, red[w]);
         int8_t tg = 0;
-        if (m > tau_r * tau_r && P.level < lmax) tg = 1;
+        if (m != m) atomicOr(c.err, 8);
+        else if (m > tau_r * tau_r && P.level < lmax) tg = 1;
         else if (m <= tau_c * tau_c && P.level > lmin) tg = -1;
         tags[leaf] = tg;
         if (g2out) g2out[leaf] = m;
@@ -1767,8 +1788,21 @@ hipError_t launch_zero_cfl(unsigned long long *cflp, int n, hipStream_t s) {
 }
 
 hipError_t launch_export_cfl(DevState *state, const unsigned long long *cflp, int n, double *cfl_dev,
-                             hipStream_t s) {
-    hipLaunchKernelGGL(export_cfl_kernel, dim3(1), dim3(256), 0, s, state, cflp, n, cfl_dev);
+                             double cfl_max, int32_t *err, hipStream_t s) {
+    hipLaunchKernelGGL(export_cfl_kernel, dim3(1), dim3(256), 0, s, state, cflp, n, cfl_dev, cfl_max, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_interiors(const Ctx &c, int mx, int n, double *save, int restore, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const long long tot = (long long)n * c.F * mx * mx;
+    const int blocks = (int)((tot + 255) / 256 < 65536 ? (tot + 255) / 256 : 65536);
+    switch (mx) {
+        case 8: hipLaunchKernelGGL(copy_interiors_kernel<8>, dim3(blocks), dim3(256), 0, s, c, n, save, restore); break;
+        case 16: hipLaunchKernelGGL(copy_interiors_kernel<16>, dim3(blocks), dim3(256), 0, s, c, n, save, restore); break;
+        case 32: hipLaunchKernelGGL(copy_interiors_kernel<32>, dim3(blocks), dim3(256), 0, s, c, n, save, restore); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -143,37 +143,49 @@ struct fc_patchstore {
     char *ws = nullptr;
     size_t ws_bytes = 0;
     size_t off_info = 0, off_nbr = 0, off_sl = 0, off_ls = 0, off_lr = 0, off_sched = 0, off_state = 0,
-           off_plan = 0, off_tag = 0, off_cfl = 0, off_vt[FC_MAXLEV] = {0};
+           off_plan = 0, off_tag = 0, off_cfl = 0, off_cflv = 0, off_save = 0, off_vt[FC_MAXLEV] = {0};
     std::vector<SchedEntry> sched;
     int pgrid = 0;
     int pgrid_user = 0;  // grid override of the persistent kernel (0: occupancy)
-    // captured graphs: [0]/[1] persistent kernel for 1 / `chunk` coarse steps,
-    // [2]/[3] level-step kernels for 1 / `chunk` coarse steps, [4] for 1 coarse
-    // step from the other buffer parity.  Level-step graphs carry the buffer
-    // parities as constants: gmask = the parities they were captured from.
-    static constexpr int NGRAPH = 5;
-    hipGraphExec_t gexec[NGRAPH] = {};
-    hipGraph_t graph[NGRAPH] = {};
-    uint32_t gmask[NGRAPH] = {};
-    double gdt[NGRAPH] = {};  // coarse step a level-step graph was captured for
-    int chunk = 0;
+    // Captured graphs, each for `n` coarse steps of one execution form.
+    // Level-step graphs carry the buffer parities and the coarse step as node
+    // constants, so they are keyed by (n, mask, dt); the persistent kernel
+    // reads both from device memory and is keyed by (n, grid).  Every graph
+    // is for the current launch variant; a regrid or a variant change drops
+    // them all.  At most kMaxGraphs are kept (least recently used goes).
+    struct Graph {
+        hipGraphExec_t exec = nullptr;
+        hipGraph_t graph = nullptr;
+        int mode = 0, n = 0, grid = 0;
+        uint32_t mask = 0;
+        double dt = 0.0;
+        uint64_t used = 0;
+    };
+    static constexpr int kMaxGraphs = 8;
+    std::vector<Graph> graphs;
+    uint64_t graph_clock = 0;
     hipStream_t cap_stream = nullptr;  // private stream the graph is captured on
-    int gnt = 0;
 };
 
 namespace {
 
 int nfields(const fc_config &c) { return c.equation == FC_EQ_SWE ? 3 : 1; }
 
-// store order, level ranges, patch info and neighbour records
-void build_metadata(fc_patchstore *ps, const std::vector<fc_leaf> &input) {
-    const int n = (int)input.size();
-    std::vector<int> order(n);
-    for (int k = 0; k < n; k++) order[k] = k;
+// store order of a leaf list: by level, then by Morton index inside a level
+std::vector<int> store_order(const std::vector<fc_leaf> &input) {
+    std::vector<int> order(input.size());
+    for (size_t k = 0; k < input.size(); k++) order[k] = (int)k;
     std::sort(order.begin(), order.end(), [&](int a, int b) {
         if (input[a].level != input[b].level) return input[a].level < input[b].level;
         return morton(input[a].ix, input[a].iy) < morton(input[b].ix, input[b].iy);
     });
+    return order;
+}
+
+// store order, level ranges, patch info and neighbour records
+void build_metadata(fc_patchstore *ps, const std::vector<fc_leaf> &input) {
+    const int n = (int)input.size();
+    const std::vector<int> order = store_order(input);
     ps->mesh.lv.resize(n);
     ps->slot_of_leaf.assign(n, 0);
     ps->leaf_of_slot.assign(n, 0);
@@ -259,6 +271,9 @@ void layout_workspace(fc_patchstore *ps) {
     ps->off_plan = o; o = align256(o + sizeof(TransferRec) * cap);
     ps->off_tag = o; o = align256(o + sizeof(double) * cap);
     ps->off_cfl = o; o = align256(o + sizeof(double) * cap);
+    ps->off_cflv = o; o = align256(o + sizeof(double));
+    ps->off_save = o;  // interiors kept across a coarse step that may be rejected
+    if (ps->cfg.cfl_max > 0) o = align256(o + sizeof(double) * cap * ps->F * ps->mx * ps->mx);
     for (int l = 0; l < FC_MAXLEV; l++) {
         ps->off_vt[l] = o;
         if (l >= ps->cfg.min_level && l <= ps->cfg.max_level && ps->cfg.velocity == FC_VEL_SWIRL)
@@ -305,6 +320,7 @@ Ctx make_ctx(const fc_patchstore *ps) {
 }
 
 DevState *dstate(fc_patchstore *ps) { return (DevState *)(ps->ws + ps->off_state); }
+int32_t *derr(fc_patchstore *ps) { return (int32_t *)(ps->ws + ps->off_state + offsetof(DevState, err)); }
 
 fc_status upload_metadata(fc_patchstore *ps, hipStream_t s) {
     const int n = (int)ps->mesh.lv.size();
@@ -340,6 +356,8 @@ fc_status check_device_error(fc_patchstore *ps, hipStream_t s) {
     if (err & 1) return fail(FC_ERR_HIP, "device-wide barrier timed out (grid not co-resident)");
     if (err & 2) return fail(FC_ERR_HIP, "interpolation stencil needed a third level (Prop. 2.1 violated)");
     if (err & 4) return fail(FC_ERR_STATE, "a captured graph did not cover a level's patches");
+    if (err & 8) return fail(FC_ERR_NONFINITE, "the tagging reduction met a NaN");
+    if (err & 16) return fail(FC_ERR_CFL, "a Courant number exceeded cfl_max");
     return FC_OK;
 }
 
@@ -375,29 +393,20 @@ fc_status advance_one(fc_patchstore *ps, int level, double t, double dt, int fus
     return FC_OK;
 }
 
-void drop_slot(fc_patchstore *ps, int k) {
-    if (ps->gexec[k]) (void)hipGraphExecDestroy(ps->gexec[k]);
-    if (ps->graph[k]) (void)hipGraphDestroy(ps->graph[k]);
-    ps->gexec[k] = nullptr;
-    ps->graph[k] = nullptr;
+void destroy_graph(fc_patchstore::Graph &g) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    g.exec = nullptr;
+    g.graph = nullptr;
 }
 
 void drop_graph(fc_patchstore *ps) {
-    for (int k = 0; k < fc_patchstore::NGRAPH; k++) drop_slot(ps, k);
+    for (auto &g : ps->graphs) destroy_graph(g);
+    ps->graphs.clear();
 }
 
-// Capture one persistent launch of `ncoarse` coarse steps.  The kernel reads
-// the time, step, buffer parities and level ranges from device memory, so one
-// capture serves every replay.  Capture runs on a private stream (the null
-// stream cannot be captured); replays go to the caller's stream.
-fc_status capture(fc_patchstore *ps, int which, int ncoarse, int grid) {
-    if (!ps->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ps->cap_stream, hipStreamNonBlocking));
-    Ctx c = make_ctx(ps);
-    const SchedEntry *sched = (const SchedEntry *)(ps->ws + ps->off_sched);
-    const LevelRange *lrd = (const LevelRange *)(ps->ws + ps->off_lr);
-    HIPCHK(hipStreamBeginCapture(ps->cap_stream, hipStreamCaptureModeThreadLocal));
-    hipError_t e = launch_persistent(c, LaunchCfg{ps->mx, ps->nt}, sched, (int)ps->sched.size(), lrd, ncoarse,
-                                     dstate(ps), grid, ps->cap_stream);
+// end a capture on ps->cap_stream and instantiate it into `out`
+fc_status finish_capture(fc_patchstore *ps, hipError_t e, fc_patchstore::Graph &out) {
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(ps->cap_stream, &g);
     if (e != hipSuccess || e2 != hipSuccess) {
@@ -405,9 +414,31 @@ fc_status capture(fc_patchstore *ps, int which, int ncoarse, int grid) {
         (void)hipGetLastError();
         return fail(FC_ERR_HIP, "graph capture failed");
     }
-    ps->graph[which] = g;
-    HIPCHK(hipGraphInstantiate(&ps->gexec[which], g, nullptr, nullptr, 0));
+    out.graph = g;
+    hipError_t e3 = hipGraphInstantiate(&out.exec, g, nullptr, nullptr, 0);
+    if (e3 != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        out.graph = nullptr;
+        out.exec = nullptr;
+        (void)hipGetLastError();
+        return fail(FC_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e3));
+    }
     return FC_OK;
+}
+
+// Capture one persistent launch of `ncoarse` coarse steps.  The kernel reads
+// the time, step, buffer parities and level ranges from device memory, so one
+// capture serves every replay.  Capture runs on a private stream (the null
+// stream cannot be captured); replays go to the caller's stream.
+fc_status capture(fc_patchstore *ps, fc_patchstore::Graph &out, int ncoarse, int grid) {
+    if (!ps->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ps->cap_stream, hipStreamNonBlocking));
+    Ctx c = make_ctx(ps);
+    const SchedEntry *sched = (const SchedEntry *)(ps->ws + ps->off_sched);
+    const LevelRange *lrd = (const LevelRange *)(ps->ws + ps->off_lr);
+    HIPCHK(hipStreamBeginCapture(ps->cap_stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = launch_persistent(c, LaunchCfg{ps->mx, ps->nt}, sched, (int)ps->sched.size(), lrd, ncoarse,
+                                     dstate(ps), grid, ps->cap_stream);
+    return finish_capture(ps, e, out);
 }
 
 
@@ -415,7 +446,7 @@ fc_status capture(fc_patchstore *ps, int which, int ncoarse, int grid) {
 // one kernel per level-step (one workgroup per patch of the level, parities
 // and level range baked in) plus a final node that advances the device time
 // and parities.  A regrid drops the graph.
-fc_status capture_levels(fc_patchstore *ps, int which, int ncoarse, uint32_t mask, double dtc) {
+fc_status capture_levels(fc_patchstore *ps, fc_patchstore::Graph &out, int ncoarse, uint32_t mask, double dtc) {
     if (!ps->cap_stream) HIPCHK(hipStreamCreateWithFlags(&ps->cap_stream, hipStreamNonBlocking));
     Ctx c = make_ctx(ps);
     uint32_t allmask = 0;
@@ -435,18 +466,7 @@ fc_status capture_levels(fc_patchstore *ps, int which, int ncoarse, uint32_t mas
             flip ^= en.level < 0 ? allmask : (1u << en.level);
         }
     if (e == hipSuccess) e = launch_finish_chunk(dstate(ps), ncoarse, flip, ps->cap_stream);
-    hipGraph_t g = nullptr;
-    hipError_t e2 = hipStreamEndCapture(ps->cap_stream, &g);
-    if (e != hipSuccess || e2 != hipSuccess) {
-        if (g) (void)hipGraphDestroy(g);
-        (void)hipGetLastError();
-        return fail(FC_ERR_HIP, "graph capture failed");
-    }
-    ps->graph[which] = g;
-    ps->gmask[which] = mask;
-    ps->gdt[which] = dtc;
-    HIPCHK(hipGraphInstantiate(&ps->gexec[which], g, nullptr, nullptr, 0));
-    return FC_OK;
+    return finish_capture(ps, e, out);
 }
 }  // namespace
 
@@ -482,6 +502,7 @@ fc_status fc_patchstore_create(const fc_config *cfg, int64_t nleaves, const fc_l
     }
     if (cfg->equation == FC_EQ_ADVECTION && cfg->velocity == FC_VEL_NONE) return fail(FC_ERR_ARG, "advection needs a velocity");
     if (cfg->velocity == FC_VEL_SWIRL && !(cfg->vel_params[0] > 0)) return fail(FC_ERR_ARG, "swirl period must be > 0");
+    if (!(cfg->cfl_max >= 0.0)) return fail(FC_ERR_ARG, "cfl_max must be >= 0 (0: not checked)");
     std::vector<fc_leaf> L(leaves, leaves + nleaves);
     for (const auto &q : L)
         if (q.level < cfg->min_level || q.level > cfg->max_level) return fail(FC_ERR_ARG, "leaf level outside [min_level, max_level]");
@@ -608,7 +629,7 @@ fc_status fc_advance_level(fc_patchstore *ps, int32_t level, double t, double dt
     const int n = (int)ps->mesh.lv.size();
     if (cfl_dev) HIPCHK(launch_zero_cfl(cflp(ps), n, s));
     r = advance_one(ps, level, t, dt, 0, -1, 1.0, cfl_dev != nullptr, s);
-    if (r == FC_OK && cfl_dev) HIPCHK(launch_export_cfl(nullptr, cflp(ps), n, cfl_dev, s));
+    if (r == FC_OK && cfl_dev) HIPCHK(launch_export_cfl(nullptr, cflp(ps), n, cfl_dev, ps->cfg.cfl_max, derr(ps), s));
     return r;
 }
 
@@ -625,47 +646,53 @@ fc_status fc_set_time(fc_patchstore *ps, double t) {
 }
 
 // Graph forms: replay (launch) or only capture (!launch) the graphs that
-// `nsteps` coarse steps from the current parities need: chunks of
-// FC_TCHUNK coarse steps, then single steps.  Graphs are captured on demand
-// and kept per slot (keyed by parities and dt_coarse).
+// `nsteps` coarse steps from the current parities need: as many chunks of
+// FC_TCHUNK coarse steps as fit, then ONE graph for the remaining steps, so
+// that any step count is a few replays.  Graphs are captured on demand and
+// cached (see fc_patchstore::Graph).
 static fc_status graph_steps(fc_patchstore *ps, double dt_coarse, int nsteps, int mode, int grid, bool launch,
                              hipStream_t s) {
     fc_status r = FC_OK;
     const int kChunk = FC_TCHUNK;
-    if (ps->gnt != ps->nt || ps->chunk != kChunk) {
-        drop_graph(ps);
-        ps->gnt = ps->nt;
-        ps->chunk = kChunk;
-    }
     uint32_t allm = 0, step_flip = 0;
     for (int l = 0; l < FC_MAXLEV; l++)
         if (ps->lr.count[l] > 0) allm |= 1u << l;
     for (const SchedEntry &e : ps->sched) step_flip ^= e.level < 0 ? allm : (1u << e.level);
     uint32_t mask = ps->curmask;  // parities at the start of the next replay
-    // graph slot for n coarse steps from the current parities (captured on demand)
-    auto slot = [&](int n, int &which) -> fc_status {
-        if (mode == FC_MODE_PERSISTENT_GRAPH) {
-            which = n == kChunk ? 1 : 0;
-            return ps->gexec[which] ? FC_OK : capture(ps, which, n, grid);
+    const bool persistent = mode == FC_MODE_PERSISTENT_GRAPH;
+    // the cached graph for n coarse steps from the current parities
+    auto get = [&](int n, hipGraphExec_t &exec) -> fc_status {
+        fc_patchstore::Graph *hit = nullptr;
+        for (auto &g : ps->graphs) {
+            if (g.mode != mode || g.n != n) continue;
+            if (persistent ? g.grid == grid : (g.mask == mask && g.dt == dt_coarse)) { hit = &g; break; }
         }
-        auto fits = [&](int k) { return ps->gexec[k] && ps->gmask[k] == mask && ps->gdt[k] == dt_coarse; };
-        if (n == kChunk) which = 3;
-        else which = fits(4) ? 4 : 2;
-        if (fits(which)) return FC_OK;
-        if (which == 2 && ps->gexec[2] && ps->gdt[2] == dt_coarse) which = 4;  // keep the other parity's graph
-        drop_slot(ps, which);
-        return capture_levels(ps, which, n, mask, dt_coarse);
+        if (!hit) {
+            if ((int)ps->graphs.size() >= fc_patchstore::kMaxGraphs) {
+                size_t lru = 0;
+                for (size_t k = 1; k < ps->graphs.size(); k++)
+                    if (ps->graphs[k].used < ps->graphs[lru].used) lru = k;
+                destroy_graph(ps->graphs[lru]);
+                ps->graphs.erase(ps->graphs.begin() + lru);
+            }
+            fc_patchstore::Graph g;
+            g.mode = mode; g.n = n; g.grid = grid; g.mask = mask; g.dt = dt_coarse;
+            fc_status st = persistent ? capture(ps, g, n, grid) : capture_levels(ps, g, n, mask, dt_coarse);
+            if (st != FC_OK) return st;
+            ps->graphs.push_back(g);
+            hit = &ps->graphs.back();
+        }
+        hit->used = ++ps->graph_clock;
+        exec = hit->exec;
+        return FC_OK;
     };
-    int k = 0, which = 0;
-    for (; k + kChunk <= nsteps; k += kChunk) {
-        if ((r = slot(kChunk, which)) != FC_OK) return r;
-        if (launch) HIPCHK(hipGraphLaunch(ps->gexec[which], s));
-        if (kChunk & 1) mask ^= step_flip;
-    }
-    for (; k < nsteps; k++) {
-        if ((r = slot(1, which)) != FC_OK) return r;
-        if (launch) HIPCHK(hipGraphLaunch(ps->gexec[which], s));
-        mask ^= step_flip;
+    for (int k = 0; k < nsteps;) {
+        const int n = std::min(kChunk, nsteps - k);
+        hipGraphExec_t exec = nullptr;
+        if ((r = get(n, exec)) != FC_OK) return r;
+        if (launch) HIPCHK(hipGraphLaunch(exec, s));
+        if (n & 1) mask ^= step_flip;
+        k += n;
     }
     return FC_OK;
 }
@@ -681,13 +708,23 @@ fc_status fc_prepare_steps(fc_patchstore *ps, double dt_coarse, int32_t nsteps, 
     return graph_steps(ps, dt_coarse, nsteps, mode, grid, false, (hipStream_t)stream);
 }
 
+// flag_cfl: a Courant number above cfl_max raises the device flag that
+// fc_check_device reports (the adaptive driver decides on the host instead)
+static fc_status advance_steps(fc_patchstore *ps, double dt_coarse, int32_t nsteps, int32_t mode, double *cfl_dev,
+                               bool flag_cfl, hipStream_t s);
+
 fc_status fc_advance_coarse_steps(fc_patchstore *ps, double dt_coarse, int32_t nsteps, int32_t mode, double *cfl_dev,
                                   void *stream) {
+    return advance_steps(ps, dt_coarse, nsteps, mode, cfl_dev, true, (hipStream_t)stream);
+}
+
+static fc_status advance_steps(fc_patchstore *ps, double dt_coarse, int32_t nsteps, int32_t mode, double *cfl_dev,
+                               bool flag_cfl, hipStream_t s) {
     fc_status r = check_bound(ps);
     if (r != FC_OK) return r;
     if (!(dt_coarse > 0) || nsteps < 0) return fail(FC_ERR_ARG, "bad step arguments");
-    hipStream_t s = (hipStream_t)stream;
     const bool cfl = cfl_dev != nullptr;
+    const double cmax = flag_cfl ? ps->cfg.cfl_max : 0.0;
     const int nleaf = (int)ps->mesh.lv.size();
     if (cfl && (mode == FC_MODE_PER_LEVEL || mode == FC_MODE_FUSED_LEVELS))
         HIPCHK(launch_zero_cfl(cflp(ps), nleaf, s));
@@ -713,7 +750,7 @@ fc_status fc_advance_coarse_steps(fc_patchstore *ps, double dt_coarse, int32_t n
             }
             ps->t += dt_coarse;
         }
-        if (cfl) HIPCHK(launch_export_cfl(nullptr, cflp(ps), nleaf, cfl_dev, s));
+        if (cfl) HIPCHK(launch_export_cfl(nullptr, cflp(ps), nleaf, cfl_dev, cmax, derr(ps), s));
         return FC_OK;
     }
     if (mode == FC_MODE_FUSED_LEVELS) {
@@ -734,7 +771,7 @@ fc_status fc_advance_coarse_steps(fc_patchstore *ps, double dt_coarse, int32_t n
             }
             ps->t += dt_coarse;
         }
-        if (cfl) HIPCHK(launch_export_cfl(nullptr, cflp(ps), nleaf, cfl_dev, s));
+        if (cfl) HIPCHK(launch_export_cfl(nullptr, cflp(ps), nleaf, cfl_dev, cmax, derr(ps), s));
         return FC_OK;
     }
     if (mode != FC_MODE_FUSED && mode != FC_MODE_FUSED_GRAPH && mode != FC_MODE_PERSISTENT_GRAPH)
@@ -764,7 +801,62 @@ fc_status fc_advance_coarse_steps(fc_patchstore *ps, double dt_coarse, int32_t n
         for (const SchedEntry &e : ps->sched) ps->curmask ^= e.level < 0 ? allmask : (1u << e.level);
         ps->t += dt_coarse;
     }
-    if (cfl_dev) HIPCHK(launch_export_cfl(st, cflp(ps), nleaf, cfl_dev, s));
+    if (cfl_dev) HIPCHK(launch_export_cfl(st, cflp(ps), nleaf, cfl_dev, cmax, derr(ps), s));
+    return FC_OK;
+}
+
+fc_status fc_advance_adaptive(fc_patchstore *ps, double t_end, double cfl_target, int32_t mode, double *dt_inout,
+                              int32_t max_steps, int32_t *steps_out, int32_t *rejected_out, void *stream) {
+    fc_status r = check_bound(ps);
+    if (r != FC_OK) return r;
+    if (!(ps->cfg.cfl_max > 0)) return fail(FC_ERR_STATE, "the store was created without cfl_max");
+    if (!dt_inout || !(*dt_inout > 0) || !(cfl_target > 0) || cfl_target > ps->cfg.cfl_max || max_steps < 1)
+        return fail(FC_ERR_ARG, "bad arguments");
+    hipStream_t s = (hipStream_t)stream;
+    const int n = (int)ps->mesh.lv.size();
+    double *save = (double *)(ps->ws + ps->off_save);
+    double *cflv = (double *)(ps->ws + ps->off_cflv);
+    double dt = *dt_inout;
+    int steps = 0, rejected = 0, in_row = 0;
+    if (steps_out) *steps_out = 0;
+    if (rejected_out) *rejected_out = 0;
+    while (steps < max_steps) {
+        const double rem = t_end - ps->t;
+        if (!(rem > 1e-14 * std::fabs(t_end))) break;
+        const bool last = dt >= rem;
+        const double dtu = last ? rem : dt;
+        const uint32_t mask0 = ps->curmask;
+        const double t0 = ps->t;
+        HIPCHK(launch_copy_interiors(make_ctx(ps), ps->mx, n, save, 0, s));
+        HIPCHK(launch_zero_cfl((unsigned long long *)cflv, 1, s));
+        r = advance_steps(ps, dtu, 1, mode, cflv, false, s);
+        if (r != FC_OK) return r;
+        double c = 0.0;
+        HIPCHK(hipMemcpyAsync(&c, cflv, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (!(c <= ps->cfg.cfl_max)) {  // also NaN
+            ps->curmask = mask0;
+            ps->t = t0;
+            HIPCHK(launch_copy_interiors(make_ctx(ps), ps->mx, n, save, 1, s));
+            rejected++;
+            if (rejected_out) *rejected_out = rejected;
+            if (++in_row >= 8) {
+                HIPCHK(hipStreamSynchronize(s));
+                return fail(FC_ERR_CFL, "coarse step rejected eight times in a row (last Courant number " +
+                                            std::to_string(c) + ")");
+            }
+            // a step that blew up (the later substeps of a long multirate
+            // coarse step can) has no usable Courant number: halve it
+            dt = std::isfinite(c) ? dtu * cfl_target / c : 0.5 * dtu;
+            continue;
+        }
+        in_row = 0;
+        steps++;
+        if (steps_out) *steps_out = steps;
+        if (last) ps->t = t_end;
+        if (c > 0) dt = dtu * cfl_target / c;
+    }
+    *dt_inout = dt;
     return FC_OK;
 }
 
@@ -844,46 +936,51 @@ fc_status fc_adapt(const fc_patchstore *ps, const int8_t *tags, fc_leaf *out, in
 }
 
 fc_status fc_regrid(fc_patchstore *ps, int64_t nleaves, const fc_leaf *new_leaves, void *stream) {
-    fc_status r = check_bound(ps);
-    if (r != FC_OK) return r;
+    if (!ps) return fail(FC_ERR_ARG, "null store");
     if (!new_leaves || nleaves <= 0) return fail(FC_ERR_ARG, "bad arguments");
     if (nleaves > ps->cfg.capacity) return fail(FC_ERR_CAPACITY, "new leaf set exceeds capacity");
     std::vector<fc_leaf> L(new_leaves, new_leaves + nleaves);
     for (const auto &q : L)
         if (q.level < ps->cfg.min_level || q.level > ps->cfg.max_level) return fail(FC_ERR_ARG, "leaf level outside range");
-    r = validate(ps->mesh, L);
+    fc_status r = validate(ps->mesh, L);
     if (r != FC_OK) return r;
-    hipStream_t s = (hipStream_t)stream;
-    // every old patch (with the ghosts filled by the caller) into buffer 0
-    Ctx old = make_ctx(ps);
-    HIPCHK(launch_consolidate(old, ps->mx, (int)ps->mesh.lv.size(), s));
-    Mesh oldmesh = ps->mesh;
-    build_metadata(ps, L);
+    // The transfer plan, built against the new leaves in store order before
+    // anything in the store changes: every new leaf must be an old leaf, a
+    // child of one or the parent of four.  A leaf set that fails this leaves
+    // the store as it was.
+    const std::vector<int> order = store_order(L);
     const int n = (int)L.size();
     std::vector<TransferRec> plan(n);
     for (int p = 0; p < n; p++) {
-        const fc_leaf q = ps->mesh.lv[p];
+        const fc_leaf q = L[order[p]];
         TransferRec tr{};
         int o;
-        if ((o = oldmesh.find(q.level, q.ix, q.iy)) >= 0) {
+        if ((o = ps->mesh.find(q.level, q.ix, q.iy)) >= 0) {
             tr.kind = TR_COPY; tr.src[0] = o;
-        } else if ((o = oldmesh.find(q.level - 1, q.ix >> 1, q.iy >> 1)) >= 0) {
+        } else if ((o = ps->mesh.find(q.level - 1, q.ix >> 1, q.iy >> 1)) >= 0) {
             tr.kind = TR_REFINE; tr.src[0] = o; tr.cx = q.ix & 1; tr.cy = q.iy & 1;
         } else {
             tr.kind = TR_COARSEN;
             for (int c = 0; c < 4; c++) {
-                tr.src[c] = oldmesh.find(q.level + 1, 2 * q.ix + (c & 1), 2 * q.iy + (c >> 1));
+                tr.src[c] = ps->mesh.find(q.level + 1, 2 * q.ix + (c & 1), 2 * q.iy + (c >> 1));
                 if (tr.src[c] < 0) return fail(FC_ERR_ARG, "new leaf is neither old, child nor parent of old leaves");
             }
         }
         plan[p] = tr;
     }
+    r = check_bound(ps);
+    if (r != FC_OK) return r;
+    hipStream_t s = (hipStream_t)stream;
+    // every old patch (with the ghosts filled by the caller) into buffer 0
+    Ctx old = make_ctx(ps);
+    HIPCHK(launch_consolidate(old, ps->mx, (int)ps->mesh.lv.size(), s));
+    build_metadata(ps, L);
     HIPCHK(hipMemcpyAsync(ps->ws + ps->off_plan, plan.data(), sizeof(TransferRec) * n, hipMemcpyHostToDevice, s));
+    ps->curmask = ~0u;  // new data lives in buffer 1 for every level
     Ctx nc = make_ctx(ps);
     HIPCHK(launch_transfer(nc, ps->mx, (const TransferRec *)(ps->ws + ps->off_plan), n, s));
     r = upload_metadata(ps, s);
     if (r != FC_OK) return r;
-    ps->curmask = ~0u;  // new data lives in buffer 1 for every level
     drop_graph(ps);     // level populations changed: recapture on next use
     HIPCHK(hipStreamSynchronize(s));
     return FC_OK;

@@ -1,0 +1,239 @@
+"""GPU path (through the C ABI) on the cases that exercise its contracts:
+
+* shallow-water transonic rarefactions, where the Harten-Hyman entropy fix
+  changes the solution (the oracle pins show it), so the kernel's fix
+  branches run and must match the oracle;
+* Clawpack-style adaptive coarse steps with step rejection to T = 0.25 on
+  the full dam-break workload (levels 2-6), against the same rule driven
+  with the oracle;
+* the device error flags: a Courant number above cfl_max (FC_ERR_CFL) and a
+  NaN met by the tagging reduction (FC_ERR_NONFINITE);
+* graph replays of any step count, a rejected regrid that leaves the store
+  usable, and the adaptive swirl workload (levels 3-7) run to 40 coarse
+  steps against the oracle's stored reference.
+
+Tolerance: relative max-norm 1e-12 (FP64); leaf sets exact.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from workloads import synth as S
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def B():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1703_03116_amd import binding
+    binding.lib()
+    return binding
+
+
+@pytest.fixture(scope="module")
+def O(oracle_lib):
+    return oracle_lib
+
+
+def rel(a, b):
+    a = a.cpu().numpy() if hasattr(a, "cpu") else np.asarray(a)
+    b = np.asarray(b)
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+# ---------------------------------------------------------------------------
+# transonic rarefactions (entropy fix)
+# ---------------------------------------------------------------------------
+
+def transonic_data(L, mx, mirrored, hr=0.05):
+    def init(x, y):
+        h = np.where(x < 0.5, 1.0, hr) if not mirrored else np.where(x < 0.5, hr, 1.0)
+        return [h, 0 * x, 0 * x]
+    return S.sample_on_leaves(init, L, mx, nfields=3)
+
+
+@pytest.mark.parametrize("mode", ["per_level", "graph"])
+@pytest.mark.parametrize("limiter", ["first", "mc"])
+@pytest.mark.parametrize("mirrored", [False, True])
+@pytest.mark.parametrize("mx,lev", [(8, 4), (16, 3)])
+def test_swe_transonic_rarefaction_parity(B, O, mode, limiter, mirrored, mx, lev):
+    """h = 1 | 0.05 at rest (and its mirror): the 1- (3-) rarefaction spans
+    zero speed, so the entropy fix of family 1 (3) acts at the edges around
+    the sonic point.  GPU and oracle agree to 1e-12 after 0.12 time units."""
+    L = S.uniform_leaves(lev)
+    q0 = transonic_data(L, mx, mirrored)
+    kw = dict(mx=mx, equation="swe", limiter=limiter, bc=("reflect",) * 4, velocity="none")
+    ps = B.PatchStore(L, **kw)
+    ps.set_interior(q0)
+    o = O.Oracle(L, **kw)
+    o.set_interior(q0)
+    n = mx << lev
+    dt = 0.5 / n / 1.6
+    nst = int(round(0.12 / dt))
+    ps.coarse_steps(dt, nst, mode)
+    for s in range(nst):
+        o.coarse_step(s * dt, dt)
+    ps.check()
+    assert rel(ps.interior(), o.interior()) <= TOL
+
+
+# ---------------------------------------------------------------------------
+# adaptive coarse steps (Clawpack style) with rejection
+# ---------------------------------------------------------------------------
+
+def oracle_adaptive(o, t_end, dt, cfl_target, cfl_max):
+    """The rule of fc_advance_adaptive driven with the oracle: try dt (the
+    last step shortened to land on t_end), reject and retry with
+    dt * target / CFL when CFL > cfl_max, else accept and propose
+    dt * target / CFL (dt / 2 for a non-finite CFL).  Returns (t, next dt,
+    accepted, rejected)."""
+    t, acc, rej = 0.0, 0, 0
+    while t_end - t > 1e-14 * abs(t_end):
+        rem = t_end - t
+        last = dt >= rem
+        dtu = rem if last else dt
+        save = o.interior()
+        c = o.coarse_step(t, dtu)
+        if not c <= cfl_max:
+            o.set_interior(save)
+            rej += 1
+            dt = dtu * cfl_target / c if np.isfinite(c) else 0.5 * dtu
+            assert rej < 8
+            continue
+        acc += 1
+        t = t_end if last else t + dtu
+        if c > 0:
+            dt = dtu * cfl_target / c
+    return t, dt, acc, rej
+
+
+@pytest.mark.parametrize("mode", ["graph", "per_level"])
+def test_full_size_dam_break_adaptive_dt_to_t_025(B, O, mode):
+    """The dam-break workload at full size (levels 2-6, 685 patches of 16x16,
+    reflecting walls) to T = 0.25 with coarse steps from the measured
+    Courant number (target 0.9, cfl_max 1).  The first try (Courant number
+    0.95 for the initial speeds) comes out at 1.16 as the dam breaks and is
+    rejected, restored and retried."""
+    w = S.workload("dam_break")
+    O.set_threads(max(1, min(16, O.max_threads())))
+    ps = B.from_workload(w, cfl_max=1.0)
+    o = O.from_workload(w)
+    dt0 = 0.95 / ((w["mx"] << w["lmin"]) * np.sqrt(2.0))
+    dt_g, acc_g, rej_g = ps.advance_adaptive(0.25, dt0, 0.9, mode)
+    t_o, dt_o, acc_o, rej_o = oracle_adaptive(o, 0.25, dt0, 0.9, 1.0)
+    ps.check()
+    assert ps.time == 0.25 and t_o == 0.25
+    assert rej_g == rej_o >= 1 and acc_g == acc_o > 10
+    assert abs(dt_g - dt_o) <= 1e-12 * dt_o
+    assert rel(ps.interior(), o.interior()) <= TOL
+
+
+def test_cfl_above_cfl_max_is_reported(B):
+    """With cfl_max set, a coarse step whose Courant number exceeds it is
+    reported by fc_check_device as FC_ERR_CFL (when the Courant number is
+    requested)."""
+    w = S.workload("hump_l23")
+    ps = B.from_workload(w, cfl_max=0.5)
+    cfl = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ps.coarse_steps(w["dt_coarse"] * 0.5, 2, "graph", cfl)
+    ps.check()                                   # 0.45 <= 0.5: fine
+    assert 0.4 < cfl.item() <= 0.5
+    ps.coarse_steps(w["dt_coarse"], 1, "graph", cfl)  # Courant number 0.9
+    with pytest.raises(B.FcError) as e:
+        ps.check()
+    assert e.value.status == -5
+
+
+def test_nan_is_found_by_the_tagging_reduction(B):
+    """A NaN in one patch survives the tagging reduction: that patch gets
+    g^2 = NaN and tag 0, and fc_check_device reports FC_ERR_NONFINITE."""
+    L = S.uniform_leaves(2)
+    q = S.sample_on_leaves(S.hump, L, 8)
+    q[5, 0, 3, 4] = np.nan
+    ps = B.PatchStore(L, mx=8, velocity="constant", vel_params=(1.0, 0.5, 0.0), min_level=1, max_level=3)
+    ps.set_interior(q)
+    ps.ghost_fill()
+    tags, g2 = ps.tag(0.05, 0.01)
+    g2 = g2.cpu().numpy()
+    assert np.isnan(g2[5]) and tags[5].item() == 0
+    assert np.isfinite(g2).sum() >= 8           # patches away from the NaN are unaffected
+    with pytest.raises(B.FcError) as e:
+        ps.check()
+    assert e.value.status == -9
+
+
+# ---------------------------------------------------------------------------
+# graph replays, regrid rejection
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("nsteps", [1, 7, 20, 53])
+def test_graph_any_step_count_bitwise(B, nsteps):
+    """Any number of coarse steps replays whole-chunk graphs plus one graph
+    for the rest; the result is bitwise that of the host-launched kernels,
+    and replaying again from the other buffer parity still is."""
+    w = S.workload("hump_l23")
+    a, b = B.from_workload(w), B.from_workload(w)
+    for _ in range(2):
+        a.coarse_steps(w["dt_coarse"], nsteps, "graph")
+        b.coarse_steps(w["dt_coarse"], nsteps, "fused_levels")
+    a.check()
+    assert torch.equal(a.interior(), b.interior())
+    assert a.time == b.time
+
+
+def test_rejected_regrid_leaves_a_working_store(B, O):
+    """A regrid to a leaf set two levels finer (a valid tiling, but no
+    transfer exists for it) is refused; the store keeps its mesh and data and
+    steps on exactly like the oracle that never regridded."""
+    w = S.workload("hump_l23")
+    kw = dict(mx=8, velocity="constant", vel_params=(1.0, 0.5, 0.0))
+    ps = B.PatchStore(w["leaves"], min_level=2, max_level=5, capacity=4 ** 5, **kw)
+    ps.set_interior(w["q0"])
+    with pytest.raises(B.FcError) as e:
+        ps.regrid(S.uniform_leaves(4))
+    assert e.value.status == -1 and "neither old" in str(e.value)
+    o = O.Oracle(w["leaves"], lmin=2, lmax=5, **kw)
+    o.set_interior(w["q0"])
+    dt = w["dt_coarse"]
+    ps.coarse_steps(dt, 3, "graph")
+    for s in range(3):
+        o.coarse_step(s * dt, dt)
+    ps.check()
+    assert rel(ps.interior(), o.interior()) <= TOL
+
+
+# ---------------------------------------------------------------------------
+# adaptive swirl, levels 3-7, 40 coarse steps
+# ---------------------------------------------------------------------------
+
+def test_full_size_adaptive_swirl_40_coarse_steps(B):
+    """The adaptive workload at full size (levels 3-7, 32x32 patches, 8224 at
+    the start), regrid every 2 coarse steps (tau 0.05 / 0.025), 40 coarse
+    steps in the graph form, against the oracle's reference written by
+    tests/golden/make_swirl_amr_reference.py: the final leaf set exactly,
+    40000 sampled cells to 1e-12 of the largest |q|, and the total mass."""
+    from paper_1703_03116_amd.amr import run_adaptive
+    ref = np.load(os.path.join(HERE, "golden", "swirl_amr_40.npz"))
+    w = S.workload("swirl_amr")
+    ps = B.from_workload(w, capacity=4 ** w["lmax"])
+    run_adaptive(ps, w["dt_coarse"], 40, regrid_every=2, tau_refine=0.05, tau_coarsen=0.025)
+    ps.check()
+    leaves = ps.leaves()
+    assert np.array_equal(np.sort(leaves.view("i4,i4,i4"), axis=0),
+                          np.sort(np.ascontiguousarray(ref["leaves"]).view("i4,i4,i4"), axis=0))
+    assert abs(ps.time - float(ref["t"])) <= 1e-15
+    q = ps.interior().cpu().numpy()[:, 0]
+    lv = ps.input_leaves   # the order interior arrays come in (the last regrid's list)
+    pos = {tuple(x): k for k, x in enumerate(np.asarray(lv).tolist())}
+    k = np.array([pos[tuple(x)] for x in ref["sample_leaf"].tolist()])
+    got = q[k, ref["sample_j"], ref["sample_i"]]
+    assert np.abs(got - ref["sample_value"]).max() <= TOL * float(ref["qmax"])
+    mx = w["mx"]
+    area = 4.0 ** -np.asarray(lv)[:, 0].astype(np.float64) / (mx * mx)
+    mass = (q.sum(axis=(1, 2)) * area).sum()
+    assert abs(mass - float(ref["mass"])) <= 1e-12 * abs(float(ref["mass"]))

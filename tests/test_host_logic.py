@@ -162,3 +162,53 @@ def test_largest_product_of_factors_is_product_of_largest_factors():
         e = np.sin(np.pi * (np.arange(n + 1) * h)) ** 2
         c = np.sin(2.0 * np.pi * ((np.arange(n) + 0.5) * h)) * (np.sin(np.pi * h) / (np.pi * h)) * np.cos(np.pi * 0.37)
         assert np.max(np.abs(np.outer(e, c))) == np.abs(e).max() * np.abs(c).max()
+
+
+def _store_leaves(B, h, n):
+    out = (B.Leaf * n)()
+    assert B.lib().fc_patchstore_leaves(h, out) == 0
+    return [(x.level, x.ix, x.iy) for x in out]
+
+
+def test_regrid_rejects_a_leaf_set_two_levels_finer_before_changing_anything(B):
+    """A valid 2:1 tiling whose leaves are neither old leaves, children nor
+    parents of old ones (here: every level-2 leaf replaced by its level-4
+    descendants) is refused before the store changes; the plan check runs on
+    the host, ahead of the bound-memory check, so this needs no GPU."""
+    L = B.lib()
+    st, h, _ = create(B, S.uniform_leaves(2))
+    assert st == 0
+    before = _store_leaves(B, h, 16)
+    arr, n = B._leaves_array(S.uniform_leaves(4))
+    assert L.fc_regrid(h, n, arr, None) == -1                      # FC_ERR_ARG
+    assert b"neither old, child nor parent" in L.fc_last_error()
+    assert _store_leaves(B, h, 16) == before
+    # one level finer is a valid plan; the unbound store then reports FC_ERR_STATE
+    arr, n = B._leaves_array(S.uniform_leaves(3))
+    assert L.fc_regrid(h, n, arr, None) == -6
+    assert _store_leaves(B, h, 16) == before
+    L.fc_patchstore_destroy(h)
+
+
+def test_cfl_max_validation(B):
+    L = B.lib()
+    cfg = make_cfg(B)
+    cfg.cfl_max = -1.0
+    arr, n = B._leaves_array(S.uniform_leaves(1))
+    h = C.c_void_p()
+    assert L.fc_patchstore_create(C.byref(cfg), n, arr, C.byref(h), None) == -1
+    cfg.cfl_max = 1.0
+    assert L.fc_patchstore_create(C.byref(cfg), n, arr, C.byref(h), None) == 0
+    # workspace grows by one copy of the interiors when steps may be rejected
+    q0, w0, q1, w1 = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
+    assert L.fc_patchstore_sizes(h, C.byref(q1), C.byref(w1)) == 0
+    cfg.cfl_max = 0.0
+    h0 = C.c_void_p()
+    assert L.fc_patchstore_create(C.byref(cfg), n, arr, C.byref(h0), None) == 0
+    assert L.fc_patchstore_sizes(h0, C.byref(q0), C.byref(w0)) == 0
+    assert w1.value - w0.value >= 4 * 8 * 8 * 8 and q0.value == q1.value
+    d = C.c_double(0.01)
+    # not bound: FC_ERR_STATE before any device work
+    assert L.fc_advance_adaptive(h, 1.0, 0.9, 2, C.byref(d), 10, None, None, None) == -6
+    L.fc_patchstore_destroy(h)
+    L.fc_patchstore_destroy(h0)
