@@ -153,6 +153,20 @@ fc_status fc_ghost_fill(fc_patchstore *ps, int32_t level_lo, int32_t level_hi, d
 fc_status fc_advance_level(fc_patchstore *ps, int32_t level, double t, double dt, double *cfl_dev,
                            void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * step as fc_advance_level, bitwise, whose per-patch Courant maxima (the
+ * partial results reduced into *cfl_dev) live in a fixed device array of the
+ * library instead of the store's workspace.  The call allocates nothing and
+ * issues kernel launches only.  Limit: stores of at most 65536 slots
+ * (capacity; FC_ERR_CAPACITY otherwise, before anything is queued); the
+ * array holds 512 KiB on every GPU the library runs on, until the process
+ * ends.  All calls on one GPU share that GPU's array: calls that overlap on
+ * one GPU (other streams, other threads) race; each call clears the slots it
+ * reduces over.  Other errors as fc_advance_level. */
+fc_status fc_advance_level_noalloc(fc_patchstore *ps, int32_t level, double t, double dt, double *cfl_dev,
+                                   void *stream);
+
 /* As above; with cfl_max > 0 in the configuration and cfl_dev given, a
  * Courant number above cfl_max is recorded on the device and reported as
  * FC_ERR_CFL by fc_check_device.

@@ -30,7 +30,7 @@ FC_ERRORS = {-1: "FC_ERR_ARG", -2: "FC_ERR_UNBALANCED", -3: "FC_ERR_GHOST_WIDTH"
 EXPORTS = ["fc_last_error", "fc_patchstore_create", "fc_patchstore_destroy", "fc_patchstore_sizes",
            "fc_patchstore_bind", "fc_patchstore_info", "fc_patchstore_leaves", "fc_set_interior",
            "fc_get_interior", "fc_get_patches", "fc_ghost_fill", "fc_advance_level",
-           "fc_advance_coarse_steps", "fc_advance_adaptive", "fc_get_time", "fc_set_time", "fc_tag_refine", "fc_adapt", "fc_regrid",
+           "fc_advance_coarse_steps", "fc_advance_adaptive", "fc_advance_level_noalloc", "fc_get_time", "fc_set_time", "fc_tag_refine", "fc_adapt", "fc_regrid",
            "fc_prepare_steps", "fc_step_uniform", "fc_adjoint_step", "fc_check_device", "fc_autotune", "fc_set_variant", "fc_set_persistent_grid"]
 
 
@@ -75,6 +75,7 @@ def lib():
             getattr(L, f).argtypes = [vp, vp, vp]
         L.fc_ghost_fill.argtypes = [vp, C.c_int32, C.c_int32, C.c_double, vp]
         L.fc_advance_level.argtypes = [vp, C.c_int32, C.c_double, C.c_double, vp, vp]
+        L.fc_advance_level_noalloc.argtypes = [vp, C.c_int32, C.c_double, C.c_double, vp, vp]
         L.fc_advance_coarse_steps.argtypes = [vp, C.c_double, C.c_int32, C.c_int32, vp, vp]
         L.fc_advance_adaptive.argtypes = [vp, C.c_double, C.c_double, C.c_int32, C.POINTER(C.c_double), C.c_int32,
                                           C.POINTER(C.c_int32), C.POINTER(C.c_int32), vp]

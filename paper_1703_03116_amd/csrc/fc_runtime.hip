@@ -14,12 +14,21 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
 
 #include "../../include/fc.h"
 #include "fc_internal.h"
+
+// Per-slot Courant maxima of fc_advance_level_noalloc: a fixed array in
+// device memory instead of the caller's workspace.  Host code must never pass
+// `scratch` itself to a kernel (in host code the name is only a stand-in);
+// it uses the device address that scratch_ptr() obtained for the current
+// device.
+constexpr int kNoallocSlots = 65536;  // 512 KiB on every device the library runs on
+static __device__ __align__(256) unsigned long long scratch[kNoallocSlots];
 
 namespace {
 
@@ -40,6 +49,27 @@ fc_status fail(fc_status st, const std::string &msg) {
             return fail(FC_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));           \
         }                                                                                         \
     } while (0)
+
+// Device address of `scratch` on the current device, looked up once per
+// device with that device current.
+std::mutex g_scratch_mu;
+constexpr int kMaxDevices = 64;
+unsigned long long *g_scratch_ptr[kMaxDevices] = {};
+
+fc_status scratch_ptr(unsigned long long **out) {
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(FC_ERR_HIP, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(FC_ERR_HIP, "hipGetSymbolAddress returned no address for the scratch array");
+        g_scratch_ptr[dev] = (unsigned long long *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return FC_OK;
+}
 
 inline uint64_t key3(int l, int ix, int iy) {
     return ((uint64_t)(uint32_t)l << 56) | ((uint64_t)(uint32_t)iy << 28) | (uint64_t)(uint32_t)ix;
@@ -631,6 +661,36 @@ fc_status fc_advance_level(fc_patchstore *ps, int32_t level, double t, double dt
     r = advance_one(ps, level, t, dt, 0, -1, 1.0, cfl_dev != nullptr, s);
     if (r == FC_OK && cfl_dev) HIPCHK(launch_export_cfl(nullptr, cflp(ps), n, cfl_dev, ps->cfg.cfl_max, derr(ps), s));
     return r;
+}
+
+fc_status fc_advance_level_noalloc(fc_patchstore *ps, int32_t level, double t, double dt, double *cfl_dev,
+                                   void *stream) {
+    if (!ps) return fail(FC_ERR_ARG, "null store");
+    if (ps->cfg.capacity > kNoallocSlots)
+        return fail(FC_ERR_CAPACITY, "store capacity above the 65536 slots of the fixed scratch array");
+    fc_status r = check_bound(ps);
+    if (r != FC_OK) return r;
+    if (level < ps->cfg.min_level || level > ps->cfg.max_level) return fail(FC_ERR_ARG, "bad level");
+    if (!(dt > 0)) return fail(FC_ERR_ARG, "dt must be positive");
+    hipStream_t s = (hipStream_t)stream;
+    const int n = (int)ps->mesh.lv.size();
+    unsigned long long *slots = nullptr;
+    if (cfl_dev) {
+        r = scratch_ptr(&slots);
+        if (r != FC_OK) return r;
+        // the array keeps the previous call's maxima: clear the slots this
+        // call reduces over (a kernel, so the call can be graph-captured)
+        HIPCHK(launch_zero_cfl(slots, n, s));
+    }
+    if (ps->lr.count[level] > 0) {
+        Ctx c = make_ctx(ps);
+        c.cflp = slots;
+        HIPCHK(launch_advance(c, LaunchCfg{ps->mx, ps->nt}, level, ps->lr.start[level], ps->lr.count[level], t, dt,
+                              0, s));
+    }
+    ps->curmask ^= 1u << level;
+    if (cfl_dev) HIPCHK(launch_export_cfl(nullptr, slots, n, cfl_dev, ps->cfg.cfl_max, derr(ps), s));
+    return FC_OK;
 }
 
 fc_status fc_get_time(const fc_patchstore *ps, double *t) {
