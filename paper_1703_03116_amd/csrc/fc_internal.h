@@ -10,7 +10,9 @@
 // Neighbour record types: what covers one ghost region of a patch.
 enum { NB_NONE = 0, NB_SAME = 1, NB_COARSE = 2, NB_FINE = 3 };
 
-// One ghost region (a face half or a corner) of a patch P at level l.  The
+// One ghost region (a face half or a corner) of a patch P at level l.
+// type: bits 0-3 the NB_* kind, bits 4-7 the reflecting walls of the covering
+// leaf (PatchInfo::walls of slot `id`; a coarse stencil folds at them).  The
 // covering leaf `id` (a store slot) has its origin at P-local coordinates
 // (ox, oy), measured in level-l cells, periodic images already unwrapped:
 //   SAME:   neighbour-local cell = (i - ox, j - oy)

@@ -91,73 +91,134 @@ __device__ __forceinline__ void apply_signs(double *v, double su, double sv) {
     if (F == 3) { v[1] *= su; v[2] *= sv; }
 }
 
-// Cell (i, j) of patch p as a coarse interpolation stencil sees it: its
-// interior, or a ghost by copy / eq. ghost_coarse averaging.
-template <int MX, int F>
-__device__ void coarse_cell(const Ctx &c, const View &w, int p, int i, int j, double *v) {
-    const PatchInfo P = c.info[p];
-    double su, sv;
-    fold<MX>(P.walls, i, j, su, sv);
-    if (i >= 0 && i < MX && j >= 0 && j < MX) {
+__device__ __forceinline__ int rec_kind(const NbrRec &r) { return r.type & 15; }
+__device__ __forceinline__ int rec_walls(const NbrRec &r) { return (r.type >> 4) & 15; }
+
+// eq. ghost_fine at local (i, j) of a level-l patch whose ghost region is
+// covered by the coarse patch of `rec`: q_c + (1/4)(d_x s_x + d_y s_y), s the
+// minmod of the one-sided differences on the coarse grid, d = +1 for the
+// upper half.  The four stencil neighbours of the coarse cell are the coarse
+// patch's interior or its ghost values (copy from its same-size neighbour,
+// eq. ghost_coarse average of its fine neighbour, or its interior mirrored at
+// a wall; Prop. 2.1 excludes a third level).  The coarse patch's walls come
+// with the record, so the records of the regions the neighbours fall in are
+// loaded at once, and then every value: two dependent rounds of loads, with
+// no load behind a branch.
+// PIPE: overlap the fields' loads (two fields' values live at once); off
+// where the kernel's register budget is too small for that.
+template <int MX, int F, bool PIPE = true>
+__device__ __forceinline__ void coarse_interp(const Ctx &c, const View &w, int l, int i, int j, const NbrRec rec,
+                                              double *v) {
+    constexpr int N = MX + 2 * MB;
+    const int I = i - rec.ox, J = j - rec.oy;
+    const int ic = I >> 1, jc = J >> 1;
+    const double dx = (I & 1) ? 1.0 : -1.0, dy = (J & 1) ? 1.0 : -1.0;
+    const int C = rec.id, lc = l - 1, cw = rec_walls(rec);
+    int ni[4] = {ic - 1, ic + 1, ic, ic}, nj[4] = {jc, jc, jc - 1, jc + 1};
+    double su[4], sv[4];
+    bool in[4];
+    NbrRec nr[4];
 #pragma unroll
-        for (int f = 0; f < F; f++) v[f] = read_state<MX>(c, w, p, P.level, i, j, f);
-    } else {
-        const NbrRec r = c.nbr[p * FC_NREC + region_rec<MX>(i, j)];
-        if (r.type == NB_SAME) {
-#pragma unroll
-            for (int f = 0; f < F; f++) v[f] = read_state<MX>(c, w, r.id, P.level, i - r.ox, j - r.oy, f);
-        } else if (r.type == NB_FINE) {
-            const int li = 2 * (i - r.ox), lj = 2 * (j - r.oy), lf = P.level + 1;
-#pragma unroll
-            for (int f = 0; f < F; f++)
-                v[f] = 0.25 * (read_state<MX>(c, w, r.id, lf, li, lj, f) + read_state<MX>(c, w, r.id, lf, li + 1, lj, f) +
-                               read_state<MX>(c, w, r.id, lf, li, lj + 1, f) +
-                               read_state<MX>(c, w, r.id, lf, li + 1, lj + 1, f));
-        } else {
-            // a stencil crossing two level curves: excluded by Prop. 2.1
-            atomicOr(c.err, 2);
-#pragma unroll
-            for (int f = 0; f < F; f++) v[f] = __builtin_nan("");
-        }
+    for (int n = 0; n < 4; n++) {
+        fold<MX>(cw, ni[n], nj[n], su[n], sv[n]);
+        in[n] = ni[n] >= 0 && ni[n] < MX && nj[n] >= 0 && nj[n] < MX;
+        nr[n] = c.nbr[C * FC_NREC + (in[n] ? 0 : region_rec<MX>(ni[n], nj[n]))];
     }
-    apply_signs<F>(v, su, sv);
+    // the coarse level is read time-interpolated in a multirate fill
+    const bool tint = lc == w.clevel && w.alpha != 1.0;
+    const double *cur_c = buf_of(c, w, lc), *old_c = other_of(c, w, lc), *cur_f = buf_of(c, w, l);
+    // per neighbour: one coarse cell (current, old) or four fine cells (at
+    // +0, +1, +N, +N+1 from the first)
+    uint32_t k[4];
+    bool fine[4], bad[4];
+#pragma unroll
+    for (int n = 0; n < 4; n++) {
+        const int kind = rec_kind(nr[n]);
+        fine[n] = !in[n] && kind == NB_FINE;
+        bad[n] = !in[n] && kind != NB_SAME && kind != NB_FINE;
+        const int slot = (in[n] || bad[n]) ? C : nr[n].id;
+        const int ci = in[n] ? ni[n] : (bad[n] ? 0 : ni[n] - nr[n].ox);
+        const int cj = in[n] ? nj[n] : (bad[n] ? 0 : nj[n] - nr[n].oy);
+        k[n] = fine[n] ? qidx(c.cap, N, 0, slot, 2 * ci, 2 * cj) : qidx(c.cap, N, 0, slot, ci, cj);
+        if (bad[n]) atomicOr(c.err, 2);
+    }
+    const uint32_t kc = qidx(c.cap, N, 0, C, ic, jc);
+    const uint32_t plane = (uint32_t)c.cap * N * N;
+    // the five stencil values of field f (centre, then xm, xp, ym, yp:
+    // current and old value, or four fine cells)
+    auto load = [&](int f, double (&x)[5][4]) {
+        const uint32_t fo = f * plane;
+        x[0][0] = cur_c[kc + fo];
+        x[0][2] = old_c[kc + fo];
+#pragma unroll
+        for (int n = 0; n < 4; n++) {
+            const double *b0 = (fine[n] ? cur_f : cur_c) + k[n] + fo, *b1 = (fine[n] ? cur_f : old_c) + k[n] + fo;
+            const int d1 = fine[n] ? 1 : 0, dn = fine[n] ? N : 0;
+            x[n + 1][0] = b0[0];
+            x[n + 1][1] = b0[d1];
+            x[n + 1][2] = b1[dn];
+            x[n + 1][3] = b1[dn + d1];
+        }
+    };
+    auto combine = [&](int f, const double (&x)[5][4]) {
+        const double cc = tint ? x[0][2] + w.alpha * (x[0][0] - x[0][2]) : x[0][0];
+        double nv[4];
+#pragma unroll
+        for (int n = 0; n < 4; n++) {
+            const double *y = x[n + 1];
+            double t = fine[n] ? 0.25 * (y[0] + y[1] + y[2] + y[3]) : (tint ? y[2] + w.alpha * (y[0] - y[2]) : y[0]);
+            if (bad[n]) t = __builtin_nan("");
+            if (F == 3 && f == 1) t *= su[n];
+            if (F == 3 && f == 2) t *= sv[n];
+            nv[n] = t;
+        }
+        const double sx = minmod(nv[1] - cc, cc - nv[0]);
+        const double sy = minmod(nv[3] - cc, cc - nv[2]);
+        return cc + 0.25 * (dx * sx + dy * sy);
+    };
+    double xa[5][4];
+    if constexpr (F == 1) {
+        load(0, xa);
+        v[0] = combine(0, xa);
+    } else if constexpr (!PIPE) {
+#pragma unroll 1
+        for (int f = 0; f < F; f++) {
+            load(f, xa);
+            v[f] = combine(f, xa);
+        }
+    } else {
+        // software-pipelined over the fields: at most two fields' values are
+        // live, so the three-field kernels keep their register budget, and
+        // the next field's loads are in flight while one is combined
+        double xb[5][4];
+        load(0, xa);
+        load(1, xb);
+        v[0] = combine(0, xa);
+        load(2, xa);
+        v[1] = combine(1, xb);
+        v[2] = combine(2, xa);
+    }
 }
 
 // Ghost value at local (i, j) of patch p (level l) lying in region r of the
 // frame (no wall folding): copy, eq. ghost_coarse average or eq. ghost_fine
 // interpolation, as the region's neighbour record says.
-template <int MX, int F>
+template <int MX, int F, bool PIPE = true>
 __device__ __forceinline__ void ghost_cell_rec(const Ctx &c, const View &w, int l, int i, int j, const NbrRec rec,
                                                double *v) {
-    if (rec.type == NB_SAME) {
+    const int kind = rec_kind(rec);
+    if (kind == NB_SAME) {
 #pragma unroll
         for (int f = 0; f < F; f++) v[f] = read_state<MX>(c, w, rec.id, l, i - rec.ox, j - rec.oy, f);
-    } else if (rec.type == NB_FINE) {
+    } else if (kind == NB_FINE) {
         const int li = 2 * (i - rec.ox), lj = 2 * (j - rec.oy);
 #pragma unroll
         for (int f = 0; f < F; f++)
             v[f] = 0.25 * (read_state<MX>(c, w, rec.id, l + 1, li, lj, f) + read_state<MX>(c, w, rec.id, l + 1, li + 1, lj, f) +
                            read_state<MX>(c, w, rec.id, l + 1, li, lj + 1, f) +
                            read_state<MX>(c, w, rec.id, l + 1, li + 1, lj + 1, f));
-    } else if (rec.type == NB_COARSE) {
-        // eq. ghost_fine: q_c + (1/4)(d_x s_x + d_y s_y), s = minmod of the
-        // one-sided differences on the coarse grid, d = +1 for the upper half
-        const int I = i - rec.ox, J = j - rec.oy;
-        const int ic = I >> 1, jc = J >> 1;
-        const double dx = (I & 1) ? 1.0 : -1.0, dy = (J & 1) ? 1.0 : -1.0;
-        double cc[F], xm[F], xp[F], ym[F], yp[F];
-#pragma unroll
-        for (int f = 0; f < F; f++) cc[f] = read_state<MX>(c, w, rec.id, l - 1, ic, jc, f);
-        coarse_cell<MX, F>(c, w, rec.id, ic - 1, jc, xm);
-        coarse_cell<MX, F>(c, w, rec.id, ic + 1, jc, xp);
-        coarse_cell<MX, F>(c, w, rec.id, ic, jc - 1, ym);
-        coarse_cell<MX, F>(c, w, rec.id, ic, jc + 1, yp);
-#pragma unroll
-        for (int f = 0; f < F; f++) {
-            const double sx = minmod(xp[f] - cc[f], cc[f] - xm[f]);
-            const double sy = minmod(yp[f] - cc[f], cc[f] - ym[f]);
-            v[f] = cc[f] + 0.25 * (dx * sx + dy * sy);
-        }
+    } else if (kind == NB_COARSE) {
+        coarse_interp<MX, F, PIPE>(c, w, l, i, j, rec, v);
     } else {
         atomicOr(c.err, 2);
 #pragma unroll
@@ -165,16 +226,17 @@ __device__ __forceinline__ void ghost_cell_rec(const Ctx &c, const View &w, int 
     }
 }
 
-template <int MX, int F>
+template <int MX, int F, bool PIPE = true>
 __device__ __forceinline__ void ghost_cell_r(const Ctx &c, const View &w, int p, int l, int i, int j, int r,
                                              double *v) {
-    ghost_cell_rec<MX, F>(c, w, l, i, j, c.nbr[p * FC_NREC + r], v);
+    ghost_cell_rec<MX, F, PIPE>(c, w, l, i, j, c.nbr[p * FC_NREC + r], v);
 }
 
-// Ghost value of patch p at local (i, j): the result of Algorithm 1.
-template <int MX, int F>
-__device__ void ghost_cell(const Ctx &c, const View &w, int p, int i, int j, double *v) {
-    const PatchInfo P = c.info[p];
+// Ghost value of patch p (geometry P) at local (i, j): the result of
+// Algorithm 1.
+template <int MX, int F, bool PIPE = true>
+__device__ __forceinline__ void ghost_cell_of(const Ctx &c, const View &w, int p, const PatchInfo &P, int i, int j,
+                                              double *v) {
     const int l = P.level;
     double su, sv;
     fold<MX>(P.walls, i, j, su, sv);
@@ -182,9 +244,15 @@ __device__ void ghost_cell(const Ctx &c, const View &w, int p, int i, int j, dou
 #pragma unroll
         for (int f = 0; f < F; f++) v[f] = read_state<MX>(c, w, p, l, i, j, f);
     } else {
-        ghost_cell_r<MX, F>(c, w, p, l, i, j, region_rec<MX>(i, j), v);
+        ghost_cell_r<MX, F, PIPE>(c, w, p, l, i, j, region_rec<MX>(i, j), v);
     }
     apply_signs<F>(v, su, sv);
+}
+
+template <int MX, int F>
+__device__ void ghost_cell(const Ctx &c, const View &w, int p, int i, int j, double *v) {
+    const PatchInfo P = c.info[p];
+    ghost_cell_of<MX, F>(c, w, p, P, i, j, v);
 }
 
 // g-th cell of the ghost frame in region-major order: the eight face halves
@@ -864,9 +932,9 @@ __device__ void reduce_cfl_slot(double v, double *red, unsigned long long *slot,
 // all four are resident.
 template <int MX, int NT, int EQ>
 constexpr int min_waves() {
-    // scalar mx = 32: four workgroups per CU; shallow water with 512 threads:
-    // two workgroups per CU (registers capped at 128 per lane)
-    return (EQ == 0 && MX == 32) ? NT / 64 : ((EQ == 1 && NT == 512) ? 4 : 1);
+    // scalar mx = 32: four workgroups per CU; shallow water at mx = 16: two
+    // workgroups per CU (the LDS tile and accumulators take 68 KB)
+    return (EQ == 0 && MX == 32) ? NT / 64 : ((EQ == 1 && MX == 16 && NT >= 256) ? NT / 128 : 1);
 }
 
 template <int MX, int NT, bool FUSED>
@@ -901,31 +969,39 @@ __global__ void __launch_bounds__(NT, (min_waves<MX, NT, 0>())) step_leaf_kernel
 // waves, transverse splitting in the Roe eigenbasis (system form of the
 // same unsplit scheme; the paper runs Clawpack's wave-propagation solvers)
 // ------------------------------------------------------------------------
+// Tile of one shallow-water patch and its per-cell accumulators.  The tile
+// rows have an odd stride so that lanes walking a column hit distinct banks.
 template <int MX>
 struct SweSmem {
     static constexpr int N = MX + 2 * MB;
-    static constexpr int NR = (MX + 3) * (MX + 2);  // Riemann problems per direction
-    static constexpr int NC = MX * (MX + 2);        // accumulator cells per direction
-    double q[3][N * N];
-    double R[NR][6];     // alpha_1..3, u_hat, v_hat, c_hat (normal frame)
-    double acc[NC][12];  // per cell: T (3), transverse + (3), transverse - (3), dC (3)
-    double D[3][MX * MX];
-    double vel[2][N * N];  // per cell hu/h and hv/h
-    double cel[N * N];     // per cell sqrt(g h)
+    static constexpr int NP = N + 1;                // tile row stride
+    static constexpr int AP = MX + 1;               // accumulator line stride
+    static constexpr int NA = (MX + 2) * AP;        // accumulator cells per direction: lines -1..MX
+    double q[3][N * NP];   // h, hu, hv
+    double u[N * NP];      // hu / h
+    double v[N * NP];      // hv / h
+    double sh[N * NP];     // sqrt(h)
+    double cs[N * NP];     // sqrt(g h)
+    // [direction][component][cell]: components 0..2 the normal part of the
+    // cell's update (h, hu, hv), 3..5 the transverse waves it sends across
+    // its upper (right) side, 6..8 across its lower (left) side, already
+    // scaled by lam^2 / 2.  Each receives exactly two contributions, one per
+    // edge of the cell, added to -0 (order-independent bits).
+    double acc[2][9][NA];
+    unsigned long long cfl;  // largest wave speed over interior edges (bits of a non-negative double)
     double red[16];
 };
 
-// Roe linearisation in the frame (h, h u_n, h u_t).  Each denominator is
-// inverted once (a double division costs a dozen instructions).
-__device__ __forceinline__ void roe_solve(double g, double hL, double nL, double tL, double hR, double nR, double tR,
-                                          double *r) {
-    const double ihL = 1.0 / hL, ihR = 1.0 / hR;
-    const double uL = nL * ihL, uR = nR * ihR, vL = tL * ihL, vR = tR * ihR;
-    const double sL = sqrt(hL), sR = sqrt(hR);
+// Roe linearisation of one edge in the frame (h, h u_n, h u_t) from the two
+// cells' staged values (un, ut: velocities; sh = sqrt(h)).  r: alpha_1..3,
+// u_hat, v_hat, c_hat.
+__device__ __forceinline__ void roe_edge(double g, double hL, double nL, double tL, double unL, double utL, double shL,
+                                         double hR, double nR, double tR, double unR, double utR, double shR,
+                                         double *r) {
     const double hb = 0.5 * (hL + hR);
-    const double is = 1.0 / (sL + sR);
-    const double uh = (sL * uL + sR * uR) * is;
-    const double vh = (sL * vL + sR * vR) * is;
+    const double is = 1.0 / (shL + shR);
+    const double uh = (shL * unL + shR * unR) * is;
+    const double vh = (shL * utL + shR * utR) * is;
     const double ch = sqrt(g * hb);
     const double i2c = 0.5 / ch;
     const double d0 = hR - hL, d1 = nR - nL, d2 = tR - tL;
@@ -968,33 +1044,50 @@ __device__ __forceinline__ void roe_transverse(const double *r, double i2c, cons
     }
 }
 
-// One edge of a sweep (normal frame): fluctuations with the entropy fix,
-// limited second-order correction C, corrected fluctuations and their
-// transverse splits.  qL/qR in the normal frame; rU/rD: Roe data of the
-// neighbouring edges on the two sides (for the upwind waves).
-// uL, cL, uR, cR: normal velocity and sqrt(g h) of the two cells.
-__device__ __forceinline__ void swe_edge(double g, int lim, double lam, const double *qL, const double *qR,
-                                         double uL, double cL, double uR, double cR,
-                                         const double *r, const double *rlo, const double *rhi, double C[3],
-                                         double Aps[3], double Ams[3], double bpp[3], double bmp[3], double bpm[3],
-                                         double bmm[3], double &smax) {
+// One edge, the whole of its update: the Roe solves of the edge and of its
+// two neighbours along the line (their waves are the limiter's upwind waves),
+// fluctuations with the Harten-Hyman fix on transonic rarefactions of
+// families 1 and 3, MC-limited correction C, corrected fluctuations and
+// their transverse splits.  Line `line` of direction `dir` (0: x-edges of a
+// row, 1: y-edges of a column); edge e lies between cells e-1 and e.  Adds
+// its parts to the accumulators of cells e-1 and e; returns the largest
+// wave speed at the edge.
+template <int MX>
+__device__ __forceinline__ double swe_edge(SweSmem<MX> &s, double g, int lim, double lam, int dir, int line, int e) {
+    constexpr int NP = SweSmem<MX>::NP, AP = SweSmem<MX>::AP;
+    const int fn = dir == 0 ? 1 : 2, ft = 3 - fn;  // normal / tangential momentum fields
+    const double *un = dir == 0 ? s.u : s.v, *ut = dir == 0 ? s.v : s.u;
+    // cells e-2 .. e+1 of the line
+    const int k0 = dir == 0 ? (line + MB) * NP + (e - 2 + MB) : (e - 2 + MB) * NP + (line + MB);
+    const int st = dir == 0 ? 1 : NP;
+    double h[4], n[4], t[4], a[4], b[4], r2[4];
+#pragma unroll
+    for (int m = 0; m < 4; m++) {
+        const int k = k0 + m * st;
+        h[m] = s.q[0][k]; n[m] = s.q[fn][k]; t[m] = s.q[ft][k];
+        a[m] = un[k]; b[m] = ut[k]; r2[m] = s.sh[k];
+    }
+    double rl[6], r[6], rh[6];
+    roe_edge(g, h[0], n[0], t[0], a[0], b[0], r2[0], h[1], n[1], t[1], a[1], b[1], r2[1], rl);
+    roe_edge(g, h[1], n[1], t[1], a[1], b[1], r2[1], h[2], n[2], t[2], a[2], b[2], r2[2], r);
+    roe_edge(g, h[2], n[2], t[2], a[2], b[2], r2[2], h[3], n[3], t[3], a[3], b[3], r2[3], rh);
     double W[3][3], sp[3];
     waves_of(r, W, sp);
-    // Harten-Hyman fix on transonic rarefactions of families 1 and 3
-    // (the middle states are needed only where the outer speed has the
-    // sign that allows a transonic rarefaction)
-    const double l1L = uL - cL;
+    // Harten-Hyman fix (the middle states are needed only where the outer
+    // speed has the sign that allows a transonic rarefaction)
+    const double cL = s.cs[k0 + st], cR = s.cs[k0 + 2 * st];
+    const double l1L = a[1] - cL;
     double l1R = 0.0;
     if (l1L < 0.0) {
-        const double hm = qL[0] + W[0][0];
-        l1R = (qL[1] + W[0][1]) / hm - sqrt(g * hm);
+        const double hm = h[1] + W[0][0];
+        l1R = (n[1] + W[0][1]) / hm - sqrt(g * hm);
     }
     const bool fix1 = l1L < 0.0 && l1R > 0.0;
-    const double l3R = uR + cR;
+    const double l3R = a[2] + cR;
     double l3L = 0.0;
     if (l3R > 0.0) {
-        const double hm3 = qR[0] - W[2][0];
-        l3L = (qR[1] - W[2][1]) / hm3 + sqrt(g * hm3);
+        const double hm3 = h[2] - W[2][0];
+        l3L = (n[2] - W[2][1]) / hm3 + sqrt(g * hm3);
     }
     const bool fix3 = l3L < 0.0 && l3R > 0.0;
     double am[3] = {0, 0, 0}, ap[3] = {0, 0, 0};
@@ -1012,180 +1105,134 @@ __device__ __forceinline__ void swe_edge(double g, int lim, double lam, const do
             spp = sp[p] > 0 ? sp[p] : 0.0;
         }
 #pragma unroll
-        for (int e = 0; e < 3; e++) { am[e] += sm * W[p][e]; ap[e] += spp * W[p][e]; }
+        for (int f = 0; f < 3; f++) { am[f] += sm * W[p][f]; ap[f] += spp * W[p][f]; }
     }
     // MC limiter on each wave against the upwind wave of its family
     double Wl[3][3], spl[3], Wh[3][3], sph[3];
-    waves_of(rlo, Wl, spl);
-    waves_of(rhi, Wh, sph);
-#pragma unroll
-    for (int e = 0; e < 3; e++) C[e] = 0.0;
+    waves_of(rl, Wl, spl);
+    waves_of(rh, Wh, sph);
+    double C[3] = {0, 0, 0}, smax = 0.0;
 #pragma unroll
     for (int p = 0; p < 3; p++) {
         double ww = 0, wu = 0;
 #pragma unroll
-        for (int e = 0; e < 3; e++) {
-            const double wup = sp[p] > 0 ? Wl[p][e] : Wh[p][e];
-            ww += W[p][e] * W[p][e];
-            wu += wup * W[p][e];
+        for (int f = 0; f < 3; f++) {
+            const double wup = sp[p] > 0 ? Wl[p][f] : Wh[p][f];
+            ww += W[p][f] * W[p][f];
+            wu += wup * W[p][f];
         }
         const double ph = ww == 0.0 ? 0.0 : phi_limit(lim, wu / ww);
         const double as = fabs(sp[p]);
 #pragma unroll
-        for (int e = 0; e < 3; e++) C[e] += as * (1.0 - lam * as) * ph * W[p][e];
+        for (int f = 0; f < 3; f++) C[f] += as * (1.0 - lam * as) * ph * W[p][f];
         smax = fmax(smax, as);
     }
+    double Aps[3], Ams[3], bpp[3], bmp[3], bpm[3], bmm[3];
 #pragma unroll
-    for (int e = 0; e < 3; e++) { Aps[e] = ap[e] - C[e]; Ams[e] = am[e] + C[e]; }
+    for (int f = 0; f < 3; f++) { Aps[f] = ap[f] - C[f]; Ams[f] = am[f] + C[f]; }
     const double i2c = 0.5 / r[5];
     roe_transverse(r, i2c, Aps, bpp, bmp);
     roe_transverse(r, i2c, Ams, bpm, bmm);
+    // back to (h, hu, hv): frame component c goes to field 0, fn, ft
+    const double hl = 0.5 * lam, hl2 = 0.5 * lam * lam;
+    // cell e (right of the edge) and cell e-1 (left): accumulator index along
+    // the line, line -1 .. MX
+    const int ar = (line + 1) * AP + e, al = ar - 1;
+    double *A = &s.acc[dir][0][0];
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        const int f = c == 0 ? 0 : (c == 1 ? fn : ft);
+        if (e < MX) {
+            atomicAdd(&A[(0 + f) * SweSmem<MX>::NA + ar], -lam * Aps[c] - hl * C[c]);
+            atomicAdd(&A[(3 + f) * SweSmem<MX>::NA + ar], hl2 * bpp[c]);
+            atomicAdd(&A[(6 + f) * SweSmem<MX>::NA + ar], hl2 * bmp[c]);
+        }
+        if (e > 0) {
+            atomicAdd(&A[(0 + f) * SweSmem<MX>::NA + al], -lam * Ams[c] + hl * C[c]);
+            atomicAdd(&A[(3 + f) * SweSmem<MX>::NA + al], hl2 * bpm[c]);
+            atomicAdd(&A[(6 + f) * SweSmem<MX>::NA + al], hl2 * bmm[c]);
+        }
+    }
+    return (line >= 0 && line < MX) ? smax : 0.0;
 }
 
-// One step on a shallow-water patch.  Sweep X then Y; each sweep: Riemann
-// problems into R, then every edge adds its contributions to its two cells
-// (one pass of LDS atomic adds, or two passes of alternate edges), then the
-// cells turn them into their share of the update.
+// One step on a shallow-water patch: stage the tile (with per-cell
+// velocities, sqrt(h) and sqrt(g h)), one pass over every x- and y-edge
+// (each a whole edge update, accumulated into the two cells it touches),
+// one pass over the cells.  Two barriers after the staging.  cfl is
+// max-accumulated with the patch's Courant number (in every thread).
 template <int MX, int NT, bool FUSED>
 __device__ void advance_swe_patch(const Ctx &c, const View &w, SweSmem<MX> &s, int p, double dt, double &cfl) {
-    constexpr int N = MX + 2 * MB, NR = SweSmem<MX>::NR;
-    constexpr bool ONEPASS = NT >= (MX + 1) * (MX + 2);  // every edge of a direction in one pass
+    constexpr int N = MX + 2 * MB, NP = SweSmem<MX>::NP, NA = SweSmem<MX>::NA, AP = SweSmem<MX>::AP;
+    constexpr int NE = (MX + 1) * (MX + 2);  // edges per direction: MX+1 along each of lines -1..MX
     const PatchInfo P = c.info[p];
     const int l = P.level;
     // h = 1 / (MX 2^l) is a power of two: dt / h is exact as a product
     const double lam = dt * (double)(MX << l), g = c.g;
     const double *in = buf_of(c, w, l);
     double *out = other_of(c, w, l);
-    // each staged cell also gets its velocities and gravity-wave speed, the
-    // quantities every edge of the cell starts its entropy check with
-    auto stage = [&](int k, const double (&v)[3]) {
+    auto stage = [&](int i, int j, const double (&v)[3]) {
+        const int k = (j + MB) * NP + i + MB;
+#pragma unroll
         for (int f = 0; f < 3; f++) s.q[f][k] = v[f];
-        s.vel[0][k] = v[1] / v[0];
-        s.vel[1][k] = v[2] / v[0];
-        s.cel[k] = sqrt(g * v[0]);
+        s.u[k] = v[1] / v[0];
+        s.v[k] = v[2] / v[0];
+        s.sh[k] = sqrt(v[0]);
+        s.cs[k] = sqrt(g * v[0]);
     };
     if (!FUSED) {
         for (int k = threadIdx.x; k < N * N; k += NT) {
             double v[3];
+#pragma unroll
             for (int f = 0; f < 3; f++) v[f] = in[(size_t)(f * c.cap + p) * N * N + k];
-            stage(k, v);
+            stage(k % N - MB, k / N - MB, v);
         }
     } else {
-        for (int k = threadIdx.x; k < MX * MX; k += NT) {
-            const int i = k % MX, j = k / MX;
-            double v[3];
-            for (int f = 0; f < 3; f++) v[f] = in[(size_t)(f * c.cap + p) * N * N + (j + MB) * N + i + MB];
-            stage((j + MB) * N + i + MB, v);
-        }
+        // ghost cells (items below NG) and interior cells in one item space,
+        // so that their loads go out together
         constexpr int NG = N * N - MX * MX;
-        for (int gidx = threadIdx.x; gidx < NG; gidx += NT) {
+        for (int k = threadIdx.x; k < N * N; k += NT) {
             int i, j;
-            ghost_index<MX>(gidx, i, j);
             double v[3];
-            ghost_cell<MX, 3>(c, w, p, i, j, v);
-            stage((j + MB) * N + i + MB, v);
+            if (k < NG) {
+                ghost_index<MX>(k, i, j);
+                // the 512- and 640-thread variants are held to 128 and 96
+                // registers (two workgroups per CU)
+                ghost_cell_of<MX, 3, (NT <= 384)>(c, w, p, P, i, j, v);
+            } else {
+                i = (k - NG) % MX;
+                j = (k - NG) / MX;
+#pragma unroll
+                for (int f = 0; f < 3; f++) v[f] = in[(size_t)(f * c.cap + p) * N * N + (j + MB) * N + i + MB];
+            }
+            stage(i, j, v);
         }
+    }
+    {
+        double *A = &s.acc[0][0][0];
+        for (int k = threadIdx.x; k < 2 * 9 * NA; k += NT) A[k] = -0.0;
+        if (threadIdx.x == 0) s.cfl = 0ull;
     }
     __syncthreads();
     double smax = 0.0;
-#define QA(f, i, j) s.q[f][((j) + MB) * N + (i) + MB]
-    for (int dir = 0; dir < 2; dir++) {
-        // normal frame: x sweep (h, hu, hv); y sweep (h, hv, hu)
-        const int fn = dir == 0 ? 1 : 2, ft = dir == 0 ? 2 : 1;
-        // Riemann problems: edge index e in [-1, MX+1] along the sweep, line in [-1, MX]
-        for (int k = threadIdx.x; k < NR; k += NT) {
-            const int ln = k / (MX + 3) - 1, e = k % (MX + 3) - 1;
-            const int iL = dir == 0 ? e - 1 : ln, jL = dir == 0 ? ln : e - 1;
-            const int iR = dir == 0 ? e : ln, jR = dir == 0 ? ln : e;
-            roe_solve(g, QA(0, iL, jL), QA(fn, iL, jL), QA(ft, iL, jL), QA(0, iR, jR), QA(fn, iR, jR),
-                      QA(ft, iR, jR), s.R[k]);
-        }
-        if constexpr (ONEPASS) {  // accumulators start at -0: -0 + x is x exactly
-            double *acc = &s.acc[0][0];
-            for (int k = threadIdx.x; k < SweSmem<MX>::NC * 12; k += NT) acc[k] = -0.0;
-        }
-        __syncthreads();
-        // edges e in [0, MX], lines [-1, MX]; cell (e) gets the right-going
-        // part, cell (e-1) the left-going part.  Every accumulator receives
-        // exactly two contributions (one per edge of its cell), so the sum does
-        // not depend on their order: with enough threads all edges go in one
-        // pass of LDS atomic adds, otherwise in two passes of alternate edges
-        // (even edges set, odd edges add).
-        for (int par = 0; par < (ONEPASS ? 1 : 2); par++) {
-            constexpr int NEH = ONEPASS ? (MX + 1) * (MX + 2) : (MX / 2 + 1) * (MX + 2);
-            for (int k = threadIdx.x; k < NEH; k += NT) {
-                const int ln = ONEPASS ? k / (MX + 1) - 1 : k / (MX / 2 + 1) - 1;
-                const int e = ONEPASS ? k % (MX + 1) : 2 * (k % (MX / 2 + 1)) + par;
-                if (e > MX) continue;
-                const int rk = (ln + 1) * (MX + 3) + (e + 1);
-                const int iL = dir == 0 ? e - 1 : ln, jL = dir == 0 ? ln : e - 1;
-                const int iR = dir == 0 ? e : ln, jR = dir == 0 ? ln : e;
-                const double qL[3] = {QA(0, iL, jL), QA(fn, iL, jL), QA(ft, iL, jL)};
-                const double qR[3] = {QA(0, iR, jR), QA(fn, iR, jR), QA(ft, iR, jR)};
-                double C[3], Aps[3], Ams[3], bpp[3], bmp[3], bpm[3], bmm[3];
-                double sm = 0.0;
-                const int cLk = (jL + MB) * N + iL + MB, cRk = (jR + MB) * N + iR + MB;
-                swe_edge(g, c.lim, lam, qL, qR, s.vel[dir][cLk], s.cel[cLk], s.vel[dir][cRk], s.cel[cRk], s.R[rk],
-                         s.R[rk - 1], s.R[rk + 1], C, Aps, Ams, bpp, bmp, bpm, bmm, sm);
-                if (ln >= 0 && ln < MX) smax = fmax(smax, sm);
-                // back to (h, hu, hv)
-                const int sw[3] = {0, fn, ft};
-                if (e < MX) {  // cell e along the sweep: right-going part
-                    double *a = dir == 0 ? s.acc[(ln + 1) * MX + e] : s.acc[e * (MX + 2) + (ln + 1)];
-#pragma unroll
-                    for (int f = 0; f < 3; f++) {
-                        const int o = sw[f];
-                        if (ONEPASS) {
-                            atomicAdd(&a[o], Aps[f]); atomicAdd(&a[3 + o], bpp[f]);
-                            atomicAdd(&a[6 + o], bmp[f]); atomicAdd(&a[9 + o], -C[f]);
-                        } else if (par == 0) {
-                            a[o] = Aps[f]; a[3 + o] = bpp[f]; a[6 + o] = bmp[f]; a[9 + o] = -C[f];
-                        } else {
-                            a[o] += Aps[f]; a[3 + o] += bpp[f]; a[6 + o] += bmp[f]; a[9 + o] -= C[f];
-                        }
-                    }
-                }
-                if (e > 0) {  // cell e-1: left-going part
-                    double *a = dir == 0 ? s.acc[(ln + 1) * MX + e - 1] : s.acc[(e - 1) * (MX + 2) + (ln + 1)];
-#pragma unroll
-                    for (int f = 0; f < 3; f++) {
-                        const int o = sw[f];
-                        if (ONEPASS) {
-                            atomicAdd(&a[o], Ams[f]); atomicAdd(&a[3 + o], bpm[f]);
-                            atomicAdd(&a[6 + o], bmm[f]); atomicAdd(&a[9 + o], C[f]);
-                        } else if (par == 0) {
-                            a[o] = Ams[f]; a[3 + o] = bpm[f]; a[6 + o] = bmm[f]; a[9 + o] = C[f];
-                        } else {
-                            a[o] += Ams[f]; a[3 + o] += bpm[f]; a[6 + o] += bmm[f]; a[9 + o] += C[f];
-                        }
-                    }
-                }
-            }
-            __syncthreads();
-        }
-        // the sweep's share of the update of interior cell (i, j):
-        // -lam T + lam/2 dC + lam^2/2 (P(i) + M(i+1) - P(i-1) - M(i)) along
-        // the transverse direction
-        for (int k = threadIdx.x; k < MX * MX; k += NT) {
-            const int i = k % MX, j = k / MX;
-            const double *a0, *am_, *ap_;
-            if (dir == 0) {
-                a0 = s.acc[(j + 1) * MX + i]; am_ = s.acc[j * MX + i]; ap_ = s.acc[(j + 2) * MX + i];
-            } else {
-                a0 = s.acc[j * (MX + 2) + i + 1]; am_ = s.acc[j * (MX + 2) + i]; ap_ = s.acc[j * (MX + 2) + i + 2];
-            }
-#pragma unroll
-            for (int f = 0; f < 3; f++) {
-                const double dT = a0[3 + f] + ap_[6 + f] - am_[3 + f] - a0[6 + f];
-                const double part = -lam * a0[f] + 0.5 * lam * a0[9 + f] + 0.5 * lam * lam * dT;
-                if (dir == 0) s.D[f][k] = part;
-                else out[(size_t)(f * c.cap + p) * N * N + (j + MB) * N + i + MB] = QA(f, i, j) + s.D[f][k] + part;
-            }
-        }
-        __syncthreads();
+    for (int k = threadIdx.x; k < 2 * NE; k += NT) {
+        const int dir = k >= NE ? 1 : 0, kk = k - dir * NE;
+        smax = fmax(smax, swe_edge<MX>(s, g, c.lim, lam, dir, kk / (MX + 1) - 1, kk % (MX + 1)));
     }
-#undef QA
-    cfl = fmax(cfl, lam * smax);
+    smax = wave_max_last_lane(smax);
+    if ((threadIdx.x & 63) == 63 && smax > 0.0) atomicMax(&s.cfl, (unsigned long long)__double_as_longlong(smax));
+    __syncthreads();
+    // the update of cell (i, j): Q + [x normal + x transverse] + [y normal + y transverse]
+    for (int k = threadIdx.x; k < 3 * MX * MX; k += NT) {
+        const int f = k / (MX * MX), i = k % MX, j = (k / MX) % MX;
+        const double *X = &s.acc[0][0][0], *Y = &s.acc[1][0][0];
+        const int xc = (j + 1) * AP + i, yc = (i + 1) * AP + j;
+        const double tx = X[(3 + f) * NA + xc] + X[(6 + f) * NA + xc + AP] - X[(3 + f) * NA + xc - AP] - X[(6 + f) * NA + xc];
+        const double ty = Y[(3 + f) * NA + yc] + Y[(6 + f) * NA + yc + AP] - Y[(3 + f) * NA + yc - AP] - Y[(6 + f) * NA + yc];
+        const double q = s.q[f][(j + MB) * NP + i + MB];
+        out[(size_t)(f * c.cap + p) * N * N + (j + MB) * N + i + MB] = q + (X[f * NA + xc] + ty) + (Y[f * NA + yc] + tx);
+    }
+    cfl = fmax(cfl, lam * __longlong_as_double((long long)s.cfl));
 }
 
 template <int MX, int NT, bool FUSED>
@@ -1196,7 +1243,7 @@ __global__ void __launch_bounds__(NT, (min_waves<MX, NT, 1>())) advance_swe_kern
     const double old = cfl_slot_old(slot);
     double cfl = 0.0;
     advance_swe_patch<MX, NT, FUSED>(c, view_of(c), s, p, dt, cfl);
-    reduce_cfl_slot<NT>(cfl, s.red, slot, old);
+    store_cfl_slot(slot, old, cfl);
 }
 
 // ------------------------------------------------------------------------
@@ -1483,7 +1530,7 @@ template <int MX>
 struct SmemOf<MX, 1> { using type = SweSmem<MX>; };
 
 template <int MX, int NT, int EQ>
-__global__ void __launch_bounds__(NT, ((EQ == 1 && NT == 512) ? 4 : 1)) persistent_kernel(Ctx c, const SchedEntry *sched, int nsched,
+__global__ void __launch_bounds__(NT, (min_waves<MX, NT, EQ>())) persistent_kernel(Ctx c, const SchedEntry *sched, int nsched,
                                                         const LevelRange *lr, int ncoarse, DevState *st) {
     __shared__ typename SmemOf<MX, EQ>::type s;
     double t0 = st->t;
@@ -1560,7 +1607,7 @@ __global__ void __launch_bounds__(NT, (min_waves<MX, NT, EQ>())) level_step_kern
     } else {
         const double old = cfl_slot_old(c.cflp + p);
         advance_swe_patch<MX, NT, true>(c, w, s, p, dt, cfl);
-        reduce_cfl_slot<NT>(cfl, s.red, c.cflp + p, old);
+        store_cfl_slot(c.cflp + p, old, cfl);
     }
 }
 
@@ -1847,24 +1894,21 @@ hipError_t launch_advance(const Ctx &c, LaunchCfg lc, int level, int first, int 
 #undef ADV
     } else {
 #define ADV(MXV, NTV) if (lc.mx == MXV && lc.nt == NTV) return adv_swe<MXV, NTV>(c, first, count, dt, fused, s);
-        ADV(8, 64) ADV(8, 128) ADV(16, 64) ADV(16, 128) ADV(16, 256) ADV(16, 512)
+        ADV(8, 64) ADV(8, 128) ADV(8, 192) ADV(16, 256) ADV(16, 384) ADV(16, 512) ADV(16, 640)
 #undef ADV
     }
     return hipErrorInvalidValue;
 }
 
-template <int MX, int NT>
-static const void *persistent_fn(int eq) {
-    if (eq == 0) return reinterpret_cast<const void *>(&persistent_kernel<MX, NT, 0>);
-    if constexpr (MX <= 16) return reinterpret_cast<const void *>(&persistent_kernel<MX, NT, 1>);
-    return nullptr;
-}
-
+// launch variants: scalar advection (64/128 threads at mx = 8; 64-256 at
+// mx = 16; 128-512 at mx = 32), shallow water (64/128/192 at mx = 8,
+// 256/384/512/640 at mx = 16)
 static const void *persistent_select(LaunchCfg lc, int eq) {
-#define PS(MXV, NTV) if (lc.mx == MXV && lc.nt == NTV) return persistent_fn<MXV, NTV>(eq);
-    PS(8, 64) PS(8, 128) PS(16, 64) PS(16, 128) PS(16, 256) PS(32, 128) PS(32, 256) PS(32, 512)
+#define PS(MXV, NTV, EQV) \
+    if (lc.mx == MXV && lc.nt == NTV && eq == EQV) return reinterpret_cast<const void *>(&persistent_kernel<MXV, NTV, EQV>);
+    PS(8, 64, 0) PS(8, 128, 0) PS(16, 64, 0) PS(16, 128, 0) PS(16, 256, 0) PS(32, 128, 0) PS(32, 256, 0) PS(32, 512, 0)
+    PS(8, 64, 1) PS(8, 128, 1) PS(8, 192, 1) PS(16, 256, 1) PS(16, 384, 1) PS(16, 512, 1) PS(16, 640, 1)
 #undef PS
-    if (lc.mx == 16 && lc.nt == 512 && eq == 1) return reinterpret_cast<const void *>(&persistent_kernel<16, 512, 1>);
     return nullptr;
 }
 
@@ -1892,18 +1936,12 @@ int persistent_max_grid(LaunchCfg lc, int eq) {
     return per_cu * cus;
 }
 
-template <int MX, int NT>
-static const void *level_step_fn(int eq) {
-    if (eq == 0) return reinterpret_cast<const void *>(&level_step_kernel<MX, NT, 0>);
-    if constexpr (MX <= 16) return reinterpret_cast<const void *>(&level_step_kernel<MX, NT, 1>);
-    return nullptr;
-}
-
 static const void *level_step_select(LaunchCfg lc, int eq) {
-#define PS(MXV, NTV) if (lc.mx == MXV && lc.nt == NTV) return level_step_fn<MXV, NTV>(eq);
-    PS(8, 64) PS(8, 128) PS(16, 64) PS(16, 128) PS(16, 256) PS(32, 128) PS(32, 256) PS(32, 512)
+#define PS(MXV, NTV, EQV) \
+    if (lc.mx == MXV && lc.nt == NTV && eq == EQV) return reinterpret_cast<const void *>(&level_step_kernel<MXV, NTV, EQV>);
+    PS(8, 64, 0) PS(8, 128, 0) PS(16, 64, 0) PS(16, 128, 0) PS(16, 256, 0) PS(32, 128, 0) PS(32, 256, 0) PS(32, 512, 0)
+    PS(8, 64, 1) PS(8, 128, 1) PS(8, 192, 1) PS(16, 256, 1) PS(16, 384, 1) PS(16, 512, 1) PS(16, 640, 1)
 #undef PS
-    if (lc.mx == 16 && lc.nt == 512 && eq == 1) return reinterpret_cast<const void *>(&level_step_kernel<16, 512, 1>);
     return nullptr;
 }
 

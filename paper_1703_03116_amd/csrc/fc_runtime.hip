@@ -238,13 +238,17 @@ void build_metadata(fc_patchstore *ps, const std::vector<fc_leaf> &input) {
                                  {0, mx}, {mx / 2, mx}, {-1, -1}, {mx, -1}, {-1, mx}, {mx, mx}};
     for (int s = 0; s < n; s++) {
         const fc_leaf P = ps->mesh.lv[s];
-        const int l = P.level, nl = mx << l, nq = 1 << l;
+        const int nq = 1 << P.level;
         int walls = 0;
         if (P.ix == 0 && bc[0] == FC_BC_REFLECT) walls |= 1;
         if (P.ix == nq - 1 && bc[1] == FC_BC_REFLECT) walls |= 2;
         if (P.iy == 0 && bc[2] == FC_BC_REFLECT) walls |= 4;
         if (P.iy == nq - 1 && bc[3] == FC_BC_REFLECT) walls |= 8;
-        ps->info[s] = PatchInfo{l, P.ix, P.iy, walls};
+        ps->info[s] = PatchInfo{P.level, P.ix, P.iy, walls};
+    }
+    for (int s = 0; s < n; s++) {
+        const fc_leaf P = ps->mesh.lv[s];
+        const int l = P.level, nl = mx << l;
         for (int r = 0; r < FC_NREC; r++) {
             const int ri = rep[r][0], rj = rep[r][1];
             int I = P.ix * mx + ri, J = P.iy * mx + rj;
@@ -272,7 +276,7 @@ void build_metadata(fc_patchstore *ps, const std::vector<fc_leaf> &input) {
             while (ri - ox >= ext) ox += nl;
             while (rj - oy < 0) oy -= nl;
             while (rj - oy >= ext) oy += nl;
-            ps->nbr[(size_t)s * FC_NREC + r] = NbrRec{type, id, ox, oy};
+            ps->nbr[(size_t)s * FC_NREC + r] = NbrRec{type | (ps->info[id].walls << 4), id, ox, oy};
         }
     }
 }
@@ -362,16 +366,43 @@ fc_status upload_metadata(fc_patchstore *ps, hipStream_t s) {
     return FC_OK;
 }
 
-bool valid_nt(int mx, int nt, int eq = 0) {
-    if (eq == FC_EQ_SWE && mx == 32) return false;
-    switch (mx) {
-        case 8: return nt == 64 || nt == 128;
-        case 16: return nt == 64 || nt == 128 || nt == 256 || (nt == 512 && eq == FC_EQ_SWE);
-        case 32: return nt == 128 || nt == 256 || nt == 512;
+// launch variants (threads per patch) of the advance kernels
+const int kVariantsScalar8[] = {64, 128}, kVariantsScalar16[] = {64, 128, 256}, kVariantsScalar32[] = {128, 256, 512};
+const int kVariantsSwe8[] = {64, 128, 192}, kVariantsSwe16[] = {256, 384, 512, 640};
+
+std::vector<int> variants(int mx, int eq) {
+    if (eq == FC_EQ_SWE) {
+        if (mx == 8) return {std::begin(kVariantsSwe8), std::end(kVariantsSwe8)};
+        if (mx == 16) return {std::begin(kVariantsSwe16), std::end(kVariantsSwe16)};
+        return {};
     }
+    if (mx == 8) return {std::begin(kVariantsScalar8), std::end(kVariantsScalar8)};
+    if (mx == 16) return {std::begin(kVariantsScalar16), std::end(kVariantsScalar16)};
+    if (mx == 32) return {std::begin(kVariantsScalar32), std::end(kVariantsScalar32)};
+    return {};
+}
+bool valid_nt(int mx, int nt, int eq = 0) {
+    for (int v : variants(mx, eq))
+        if (v == nt) return true;
     return false;
 }
-int default_nt(int mx) { return mx == 8 ? 64 : 256; }
+// shallow water: at mx = 8 every edge of the patch in one pass (192 = 3
+// waves >= 180 edges); at mx = 16 eight waves (two workgroups per CU; the
+// measured fastest on the dam break)
+int default_nt(int mx, int eq) {
+    if (eq == FC_EQ_SWE) return mx == 8 ? 192 : 512;
+    return mx == 8 ? 64 : 256;
+}
+// The persistent kernel's device-wide barrier needs its whole grid resident;
+// with three-wave workgroups (shallow water, 192 threads)
+// the occupancy-derived grid was not (the bounded barrier timed out), so the
+// persistent form runs the largest power-of-two variant not above the
+// chosen one (all variants compute the same bits).
+LaunchCfg persistent_cfg(const fc_patchstore *ps) {
+    int nt = ps->nt;
+    while (nt & (nt - 1)) nt &= nt - 1;
+    return LaunchCfg{ps->mx, nt};
+}
 
 fc_status check_bound(const fc_patchstore *ps) {
     if (!ps) return fail(FC_ERR_ARG, "null store");
@@ -466,7 +497,7 @@ fc_status capture(fc_patchstore *ps, fc_patchstore::Graph &out, int ncoarse, int
     const SchedEntry *sched = (const SchedEntry *)(ps->ws + ps->off_sched);
     const LevelRange *lrd = (const LevelRange *)(ps->ws + ps->off_lr);
     HIPCHK(hipStreamBeginCapture(ps->cap_stream, hipStreamCaptureModeThreadLocal));
-    hipError_t e = launch_persistent(c, LaunchCfg{ps->mx, ps->nt}, sched, (int)ps->sched.size(), lrd, ncoarse,
+    hipError_t e = launch_persistent(c, persistent_cfg(ps), sched, (int)ps->sched.size(), lrd, ncoarse,
                                      dstate(ps), grid, ps->cap_stream);
     return finish_capture(ps, e, out);
 }
@@ -551,7 +582,7 @@ fc_status fc_patchstore_create(const fc_config *cfg, int64_t nleaves, const fc_l
     build_metadata(ps, L);
     if (cfg->time_stepping == FC_STEP_GLOBAL) ps->sched.push_back(SchedEntry{-1, 0, 0.0, 1.0, 1.0});
     else gen_sched(ps->sched, cfg->min_level, cfg->max_level, 0.0, 1.0, 1.0);
-    ps->nt = default_nt(ps->mx);
+    ps->nt = default_nt(ps->mx, cfg->equation);
     layout_workspace(ps);
     if (perm_out)
         for (int64_t k = 0; k < nleaves; k++) perm_out[k] = ps->slot_of_leaf[k];
@@ -595,7 +626,7 @@ fc_status fc_patchstore_bind(fc_patchstore *ps, double *q0, double *q1, void *wo
         for (int l = ps->cfg.min_level; l <= ps->cfg.max_level; l++)
             HIPCHK(launch_init_tables(l, ps->mx, ps->cfg.bc[0] == FC_BC_PERIODIC, ps->cfg.bc[2] == FC_BC_PERIODIC,
                                       (double *)(ps->ws + ps->off_vt[l]), s));
-    ps->pgrid = persistent_max_grid(LaunchCfg{ps->mx, ps->nt}, ps->cfg.equation);
+    ps->pgrid = persistent_max_grid(persistent_cfg(ps), ps->cfg.equation);
     HIPCHK(hipStreamSynchronize(s));
     return FC_OK;
 }
@@ -848,7 +879,7 @@ static fc_status advance_steps(fc_patchstore *ps, double dt_coarse, int32_t nste
     if (mode == FC_MODE_FUSED) {
         for (int k = 0; k < nsteps; k += kChunk) {
             const int m = std::min(kChunk, nsteps - k);
-            HIPCHK(launch_persistent(c, LaunchCfg{ps->mx, ps->nt}, sched, (int)ps->sched.size(), lrd, m, st, grid, s));
+            HIPCHK(launch_persistent(c, persistent_cfg(ps), sched, (int)ps->sched.size(), lrd, m, st, grid, s));
         }
     } else {
         if ((r = graph_steps(ps, dt_coarse, nsteps, mode, grid, true, s)) != FC_OK) return r;
@@ -1112,7 +1143,7 @@ fc_status fc_set_variant(fc_patchstore *ps, int32_t threads_per_patch) {
     if (!valid_nt(ps->mx, threads_per_patch, ps->cfg.equation))
         return fail(FC_ERR_ARG, "unsupported threads per patch for this mx");
     ps->nt = threads_per_patch;
-    if (ps->ws) ps->pgrid = persistent_max_grid(LaunchCfg{ps->mx, ps->nt}, ps->cfg.equation);
+    if (ps->ws) ps->pgrid = persistent_max_grid(persistent_cfg(ps), ps->cfg.equation);
     drop_graph(ps);
     return FC_OK;
 }
@@ -1128,20 +1159,18 @@ fc_status fc_autotune(fc_patchstore *ps, int32_t *threads_out, void *stream) {
         if (ps->lr.count[l] > ps->lr.count[lbest]) lbest = l;
     const double h = 1.0 / (double)(ps->mx << lbest);
     const double dt = 0.5 * h;
-    const int cands[3] = {64, 128, 256};
-    const int cands32[3] = {128, 256, 512};
-    const int *cl = (ps->mx == 32 || (ps->mx == 16 && ps->cfg.equation == FC_EQ_SWE)) ? cands32 : cands;
+    const std::vector<int> cl = variants(ps->mx, ps->cfg.equation);
+    const int nc = (int)cl.size();
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     // three interleaved rounds of 10 launches per variant, the best round
     // counts; another variant replaces the default one only if it is at
     // least 5% faster, so that noise does not flip the choice from run to run
-    float t[3] = {1e30f, 1e30f, 1e30f};
+    std::vector<float> t(nc, 1e30f);
     for (int round = 0; round < 3; round++)
-        for (int k = 0; k < 3; k++) {
+        for (int k = 0; k < nc; k++) {
             const int nt = cl[k];
-            if (!valid_nt(ps->mx, nt, ps->cfg.equation)) continue;
             Ctx c = make_ctx(ps);
             c.cflp = nullptr;
             LaunchCfg lc{ps->mx, nt};
@@ -1156,11 +1185,11 @@ fc_status fc_autotune(fc_patchstore *ps, int32_t *threads_out, void *stream) {
             HIPCHK(hipEventElapsedTime(&ms, e0, e1));
             t[k] = std::min(t[k], ms);
         }
-    int bnt = default_nt(ps->mx), kd = 0;
-    for (int k = 0; k < 3; k++)
+    int bnt = default_nt(ps->mx, ps->cfg.equation), kd = 0;
+    for (int k = 0; k < nc; k++)
         if (cl[k] == bnt) kd = k;
     float best = t[kd];
-    for (int k = 0; k < 3; k++)
+    for (int k = 0; k < nc; k++)
         if (k != kd && t[k] < 0.95f * best) { best = t[k]; bnt = cl[k]; }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
