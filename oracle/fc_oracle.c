@@ -941,11 +941,6 @@ void orc_tag(const Orc *o, double tau_r, double tau_c, signed char *tags, double
     }
 }
 
-/* New leaf set from tags: refine +1 leaves (below lmax); replace a family of
- * four sibling leaves by its parent when all four are tagged -1; then refine
- * until 2:1 balanced over faces and corners (coarsening is not guaranteed,
- * Sec. 4.1).  Output sorted by (level, iy, ix).  Returns the count; out must
- * hold 4*n leaves. */
 static int cmp_leaf(const void *a, const void *b) {
     const int *x = (const int *)a, *y = (const int *)b;
     if (x[0] != y[0]) return x[0] - y[0];
@@ -953,17 +948,70 @@ static int cmp_leaf(const void *a, const void *b) {
     return x[1] - y[1];
 }
 
-int orc_adapt(const Orc *o, const signed char *tags, int *out, int cap) {
+/* Leaf containing the level-lq quadrant (X, Y) (inside the square), found by
+ * searching levels lq, lq-1, ..., 0; -1 if none. */
+static int leaf_containing(const Orc *o, int lq, int X, int Y) {
+    for (int l2 = lq; l2 >= 0; l2--) {
+        int k = find_leaf(o, l2, X >> (lq - l2), Y >> (lq - l2));
+        if (k >= 0) return k;
+    }
+    return -1;
+}
+
+/* Smooth refinement (Sec. 4.2): every leaf's target level is its level plus
+ * its tag (kept within [lmin, lmax]); the level passed on to adaptation is the
+ * maximum of the targets of the leaf and of every leaf touching it across a
+ * face or a corner.  The neighbours are found by point location on the ring
+ * of level-(l+1) quadrants around the leaf (each is covered by one leaf of
+ * level l-1, l or l+1 on a 2:1 balanced mesh); periodic sides wrap, walls
+ * have no neighbour. */
+static void smooth_targets(const Orc *o, const int *target, int *T) {
+    for (int k = 0; k < o->n; k++) {
+        const OLeaf *L = &o->lv[k];
+        int lq = L->level + 1, nq = 1 << lq, m = target[k];
+        for (int dy = -1; dy <= 2; dy++)
+            for (int dx = -1; dx <= 2; dx++) {
+                if (dx >= 0 && dx <= 1 && dy >= 0 && dy <= 1) continue; /* the leaf itself */
+                int X = 2 * L->ix + dx, Y = 2 * L->iy + dy;
+                if (X < 0 || X >= nq) { if (o->bc[X < 0 ? 0 : 1] != BC_PERIODIC) continue; X = (X + nq) % nq; }
+                if (Y < 0 || Y >= nq) { if (o->bc[Y < 0 ? 2 : 3] != BC_PERIODIC) continue; Y = (Y + nq) % nq; }
+                int kk = leaf_containing(o, lq, X, Y);
+                if (kk >= 0 && target[kk] > m) m = target[kk];
+            }
+        T[k] = m;
+    }
+}
+
+/* New leaf set from tags (+1 refine, -1 coarsen, 0 keep), Sec. 4.1: each
+ * leaf's level target is its level plus its tag within [lmin, lmax]; with
+ * `smooth` the target is first raised to the largest of its face and corner
+ * neighbours' targets (Sec. 4.2).  A leaf whose target is above its level is
+ * refined once; a family of four sibling leaves whose targets are all below
+ * their level is replaced by its parent; then leaves are refined until the
+ * set is 2:1 balanced over faces and corners (coarsening is not guaranteed).
+ * Output sorted by (level, iy, ix).  Returns the count; out must hold 4*n
+ * leaves (-1 on overflow). */
+static int adapt_impl(const Orc *o, const signed char *tags, int smooth, int *out, int cap) {
     int cnt = 0;
+    int *target = (int *)malloc(sizeof(int) * (o->n > 0 ? o->n : 1));
+    int *T = (int *)malloc(sizeof(int) * (o->n > 0 ? o->n : 1));
+    for (int k = 0; k < o->n; k++) {
+        int t = o->lv[k].level + tags[k];
+        if (t > o->lmax) t = o->lmax;
+        if (t < o->lmin) t = o->lmin;
+        target[k] = t;
+        T[k] = t;
+    }
+    if (smooth) smooth_targets(o, target, T);
     char *done = (char *)calloc(o->n, 1);
     for (int k = 0; k < o->n; k++) {
         if (done[k]) continue;
         const OLeaf *L = &o->lv[k];
-        if (tags[k] == -1 && L->level > o->lmin) {
+        if (T[k] < L->level && L->level > o->lmin) {
             int px = L->ix >> 1, py = L->iy >> 1, sib[4], ok = 1;
             for (int c = 0; c < 4; c++) {
                 sib[c] = find_leaf(o, L->level, 2 * px + (c & 1), 2 * py + (c >> 1));
-                if (sib[c] < 0 || tags[sib[c]] != -1) ok = 0;
+                if (sib[c] < 0 || !(T[sib[c]] < L->level)) ok = 0;
             }
             if (ok) {
                 for (int c = 0; c < 4; c++) done[sib[c]] = 1;
@@ -972,7 +1020,7 @@ int orc_adapt(const Orc *o, const signed char *tags, int *out, int cap) {
             }
         }
         done[k] = 1;
-        if (tags[k] == 1 && L->level < o->lmax) {
+        if (T[k] > L->level && L->level < o->lmax) {
             for (int c = 0; c < 4; c++) {
                 out[3 * cnt] = L->level + 1; out[3 * cnt + 1] = 2 * L->ix + (c & 1);
                 out[3 * cnt + 2] = 2 * L->iy + (c >> 1); cnt++;
@@ -981,6 +1029,8 @@ int orc_adapt(const Orc *o, const signed char *tags, int *out, int cap) {
             out[3 * cnt] = L->level; out[3 * cnt + 1] = L->ix; out[3 * cnt + 2] = L->iy; cnt++;
         }
     }
+    free(target);
+    free(T);
     free(done);
     /* balance by refinement, using a temporary oracle for point queries */
     for (;;) {
@@ -1016,6 +1066,11 @@ int orc_adapt(const Orc *o, const signed char *tags, int *out, int cap) {
     }
     qsort(out, cnt, sizeof(int) * 3, cmp_leaf);
     return cnt;
+}
+
+int orc_adapt(const Orc *o, const signed char *tags, int *out, int cap) { return adapt_impl(o, tags, 0, out, cap); }
+int orc_adapt_smooth(const Orc *o, const signed char *tags, int *out, int cap) {
+    return adapt_impl(o, tags, 1, out, cap);
 }
 
 /* Replace the leaf set by new_leaves and transfer the solution: unchanged

@@ -63,6 +63,8 @@ def lib():
         L.orc_tag.argtypes = [C.c_void_p, C.c_double, C.c_double, C.POINTER(C.c_byte), dp]
         L.orc_adapt.argtypes = [C.c_void_p, C.POINTER(C.c_byte), ip, C.c_int]
         L.orc_adapt.restype = C.c_int
+        L.orc_adapt_smooth.argtypes = [C.c_void_p, C.POINTER(C.c_byte), ip, C.c_int]
+        L.orc_adapt_smooth.restype = C.c_int
         L.orc_regrid.argtypes = [C.c_void_p, C.c_int, ip]
         L.orc_regrid.restype = C.c_int
         L.orc_tangent_step.argtypes = [C.c_void_p, C.c_int, C.c_double, C.c_double, dp, dp, dp]
@@ -182,11 +184,14 @@ class Oracle:
         lib().orc_tag(self._h, float(tau_r), float(tau_c), tags.ctypes.data_as(C.POINTER(C.c_byte)), _dp(g2))
         return tags, g2
 
-    def adapt(self, tags):
+    def adapt(self, tags, smooth=False):
+        """New leaves from tags (Sec. 4.1); smooth: raise each leaf's target
+        level to its neighbours' largest first (smooth refinement, Sec. 4.2)."""
         tags = np.ascontiguousarray(np.asarray(tags, dtype=np.int8))
         cap = 4 * self.n + 64
         out = np.zeros((cap, 3), dtype=np.int32)
-        cnt = lib().orc_adapt(self._h, tags.ctypes.data_as(C.POINTER(C.c_byte)), _ip(out), cap)
+        fn = lib().orc_adapt_smooth if smooth else lib().orc_adapt
+        cnt = fn(self._h, tags.ctypes.data_as(C.POINTER(C.c_byte)), _ip(out), cap)
         if cnt < 0:
             raise OracleError("adapt overflow")
         return out[:cnt].copy()
