@@ -231,12 +231,27 @@ fc_status fc_tag_refine(fc_patchstore *ps, double tau_refine, double tau_coarsen
                         double *gmax2_dev, void *stream);
 
 /* Adaptation on the host (Sec. 4.1): from tags in input-leaf order (host
- * array), refine +1 leaves below max_level, replace a family of four
- * sibling leaves by its parent when all four are tagged -1, then refine
- * until 2:1 balanced.  Writes the new leaves sorted by (level, iy, ix) into
- * out (host, room for cap leaves) and their count into n_out. */
-fc_status fc_adapt(const fc_patchstore *ps, const int8_t *tags, fc_leaf *out, int64_t cap,
+ * array; +1 refine, -1 coarsen, 0 keep) every leaf gets a target level, its
+ * level plus its tag within [min_level, max_level].  With smooth != 0 that
+ * target is raised to the largest target of the leaves touching it across a
+ * face or a corner (smooth refinement, Sec. 4.2: a buffer of refined patches
+ * around the finest ones).  A leaf whose target is above its level is
+ * refined once; a family of four sibling leaves whose targets are all below
+ * their level is replaced by its parent; then leaves are refined until 2:1
+ * balanced.  Writes the new leaves sorted by (level, iy, ix) into out (host,
+ * room for cap leaves; FC_ERR_CAPACITY otherwise) and their count into n_out. */
+fc_status fc_adapt(const fc_patchstore *ps, const int8_t *tags, int32_t smooth, fc_leaf *out, int64_t cap,
                    int64_t *n_out);
+/* The same adaptation on the device, from tags_dev (device array in
+ * input-leaf order, as fc_tag_refine writes it): the leaves are painted on a
+ * map of the finest level (4^max_level cells, in the workspace), targets,
+ * their neighbourhood maxima, refinement, coarsening and 2:1 balance passes
+ * run there, and only the new leaf list comes back to the host (out, sorted
+ * as fc_adapt sorts it; the same leaves bit for bit).  Synchronises `stream`
+ * once per balance pass.  Needs max_level <= 10 (FC_ERR_ARG otherwise);
+ * FC_ERR_CAPACITY if the new set exceeds the store's capacity or cap. */
+fc_status fc_adapt_device(fc_patchstore *ps, const int8_t *tags_dev, int32_t smooth, fc_leaf *out,
+                          int64_t cap, int64_t *n_out, void *stream);
 
 /* Regrid (Sec. 4.1): replace the leaf set by new_leaves (host) and transfer
  * the solution: unchanged leaves are copied, children are interpolated from

@@ -16,12 +16,14 @@ import numpy as np
 import torch
 
 
-def regrid_once(store, tau_refine, tau_coarsen):
+def regrid_once(store, tau_refine, tau_coarsen, smooth=False, device=True):
     """One tag/adapt/transfer cycle; returns the new leaf list (store order of
-    the new mesh is its own; input order = the returned list)."""
+    the new mesh is its own; input order = the returned list).  device: the
+    adaptation runs on the GPU (fc_adapt_device; only the new leaf list comes
+    to the host), else on the host (fc_adapt); smooth: smooth refinement."""
     store.ghost_fill()
     tags, _ = store.tag(tau_refine, tau_coarsen)
-    new = store.adapt(tags.cpu().numpy())
+    new = store.adapt_device(tags, smooth) if device else store.adapt(tags.cpu().numpy(), smooth)
     store.regrid(new)
     return new
 
@@ -42,10 +44,11 @@ def step_counts(store):
 
 
 def run_adaptive(store, dt_coarse, ncoarse, regrid_every=2, tau_refine=0.05, tau_coarsen=None,
-                 mode="graph", timings=None):
+                 mode="graph", timings=None, smooth=False, device_adapt=True):
     """Advance ``ncoarse`` coarse steps with regridding every ``regrid_every``.
 
-    Returns the number of cell updates performed.  ``timings`` (dict,
+    Returns the number of cell updates performed.  smooth / device_adapt as
+    in regrid_once.  ``timings`` (dict,
     optional) accumulates 'advance' (seconds of advance + fill, HIP events on
     the stream the work runs on), 'regrid' (seconds of tag + adapt + transfer
     + the graph capture for the new mesh), 'launches' and 'bytes' (level-step
@@ -64,7 +67,7 @@ def run_adaptive(store, dt_coarse, ncoarse, regrid_every=2, tau_refine=0.05, tau
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         if done % regrid_every == 0 and done > 0:
-            regrid_once(store, tau_refine, tau_coarsen)
+            regrid_once(store, tau_refine, tau_coarsen, smooth, device_adapt)
             tm["regrids"] += 1
         store.prepare_steps(dt_coarse, m, mode)
         torch.cuda.synchronize()

@@ -30,7 +30,7 @@ FC_ERRORS = {-1: "FC_ERR_ARG", -2: "FC_ERR_UNBALANCED", -3: "FC_ERR_GHOST_WIDTH"
 EXPORTS = ["fc_last_error", "fc_patchstore_create", "fc_patchstore_destroy", "fc_patchstore_sizes",
            "fc_patchstore_bind", "fc_patchstore_info", "fc_patchstore_leaves", "fc_set_interior",
            "fc_get_interior", "fc_get_patches", "fc_ghost_fill", "fc_advance_level",
-           "fc_advance_coarse_steps", "fc_advance_adaptive", "fc_advance_level_noalloc", "fc_get_time", "fc_set_time", "fc_tag_refine", "fc_adapt", "fc_regrid",
+           "fc_advance_coarse_steps", "fc_advance_adaptive", "fc_advance_level_noalloc", "fc_get_time", "fc_set_time", "fc_tag_refine", "fc_adapt", "fc_adapt_device", "fc_regrid",
            "fc_prepare_steps", "fc_step_uniform", "fc_adjoint_step", "fc_check_device", "fc_autotune", "fc_set_variant", "fc_set_persistent_grid"]
 
 
@@ -82,7 +82,8 @@ def lib():
         L.fc_get_time.argtypes = [vp, C.POINTER(C.c_double)]
         L.fc_set_time.argtypes = [vp, C.c_double]
         L.fc_tag_refine.argtypes = [vp, C.c_double, C.c_double, vp, vp, vp]
-        L.fc_adapt.argtypes = [vp, C.POINTER(C.c_int8), C.POINTER(Leaf), C.c_int64, C.POINTER(C.c_int64)]
+        L.fc_adapt.argtypes = [vp, C.POINTER(C.c_int8), C.c_int32, C.POINTER(Leaf), C.c_int64, C.POINTER(C.c_int64)]
+        L.fc_adapt_device.argtypes = [vp, vp, C.c_int32, C.POINTER(Leaf), C.c_int64, C.POINTER(C.c_int64), vp]
         L.fc_regrid.argtypes = [vp, C.c_int64, C.POINTER(Leaf), vp]
         L.fc_prepare_steps.argtypes = [vp, C.c_double, C.c_int32, C.c_int32, vp]
         L.fc_step_uniform.argtypes = [vp, C.c_int32, C.c_double, C.c_double, vp, vp, vp]
@@ -238,13 +239,25 @@ class PatchStore:
                                    C.c_void_p(g2.data_ptr()), _stream()))
         return tags, g2
 
-    def adapt(self, tags):
+    def adapt(self, tags, smooth=False):
+        """New leaves from tags, adapted on the host (smooth: Sec. 4.2)."""
         t = np.ascontiguousarray(np.asarray(tags.cpu() if isinstance(tags, torch.Tensor) else tags, dtype=np.int8))
         cap = 4 * self.nleaves + 64
         out = (Leaf * cap)()
         n = C.c_int64()
-        _check(lib().fc_adapt(self._h, t.ctypes.data_as(C.POINTER(C.c_int8)), out, cap, C.byref(n)))
-        return np.array([(out[k].level, out[k].ix, out[k].iy) for k in range(n.value)], dtype=np.int32)
+        _check(lib().fc_adapt(self._h, t.ctypes.data_as(C.POINTER(C.c_int8)), int(bool(smooth)), out, cap, C.byref(n)))
+        return np.frombuffer(out, dtype=np.int32, count=3 * n.value).reshape(-1, 3).copy()
+
+    def adapt_device(self, tags, smooth=False):
+        """The same adaptation on the device from device tags (as tag()
+        returns them); only the new leaf list comes back."""
+        t = _dev(tags, torch.int8)
+        cap = max(4 * self.nleaves + 64, int(self.cfg.capacity))
+        out = (Leaf * cap)()
+        n = C.c_int64()
+        _check(lib().fc_adapt_device(self._h, C.c_void_p(t.data_ptr()), int(bool(smooth)), out, cap, C.byref(n),
+                                     _stream()))
+        return np.frombuffer(out, dtype=np.int32, count=3 * n.value).reshape(-1, 3).copy()
 
     def regrid(self, new_leaves):
         arr, n = _leaves_array(new_leaves)

@@ -148,5 +148,18 @@ hipError_t launch_export_cfl(DevState *state, const unsigned long long *cflp, in
 hipError_t launch_copy_interiors(const Ctx &c, int mx, int n, double *save, int restore, hipStream_t s);
 hipError_t launch_step_leaf(const Ctx &c, int mx, int level, int first, int count, double t, double dt,
                             const int32_t *leaf_of_slot, const double *q_in, double *q_out, hipStream_t s);
+// Adaptation on the device over a map of the finest level L (2^L x 2^L
+// cells): owner map, per-slot target and neighbour maximum, the new levels
+// painted into lev_a (launch_adapt_device); 2:1 balance passes from one map
+// into the other (b starts as a copy of a; *changed raised when a leaf was
+// refined); the leaves of a map as (level, ix, iy) triples (*count may
+// exceed cap: only cap are written).
+hipError_t launch_adapt_device(const Ctx &c, const int32_t *slot_of_leaf, const int8_t *tags, int nleaf, int L,
+                               int periodic_x, int periodic_y, int lmin, int lmax, int smooth, int32_t *owner,
+                               int32_t *target, int32_t *T, int8_t *lev_a, int8_t *lev_b, int32_t *flags,
+                               hipStream_t s);
+hipError_t launch_balance_pass(const int8_t *a, int8_t *b, int L, int periodic_x, int periodic_y, int lmin, int lmax,
+                               int32_t *changed, hipStream_t s);
+hipError_t launch_extract_leaves(const int8_t *a, int L, int cap, int32_t *count, int32_t *out, hipStream_t s);
 hipError_t launch_adjoint(const Ctx &c, int mx, int level, int first, int count, double t, double dt, const int32_t *leaf_of_slot,
                           const double *q_in, const double *lam_in, double *lam_out, hipStream_t s);

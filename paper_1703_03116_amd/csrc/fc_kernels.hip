@@ -1809,11 +1809,167 @@ __global__ void transfer_kernel(Ctx c, const TransferRec *plan) {
         }
 }
 
+// ------------------------------------------------------------------------
+// adaptation on the device (Sec. 4.1, smooth refinement Sec. 4.2), on a map
+// of the finest level L = max_level: n = 2^L cells per axis, cell (x, y) at
+// index y n + x.  A leaf of level l covers the aligned block of 2^(L-l)
+// cells per axis from (ix, iy) << (L-l).
+// ------------------------------------------------------------------------
+struct AdaptGrid {
+    int L, n;            // finest level, cells per axis
+    int px, py;          // periodic along x / y
+    int lmin, lmax;
+};
+
+// owner[c] = the slot of the leaf covering finest cell c
+__global__ void paint_owner_kernel(const PatchInfo *info, AdaptGrid g, int32_t *owner) {
+    const int s = blockIdx.x;
+    const PatchInfo P = info[s];
+    const int b = 1 << (g.L - P.level), x0 = P.ix * b, y0 = P.iy * b;
+    for (int k = threadIdx.x; k < b * b; k += blockDim.x) owner[(size_t)(y0 + k / b) * g.n + x0 + k % b] = s;
+}
+
+// target level of every leaf: its level plus its tag, within [lmin, lmax]
+__global__ void target_kernel(const PatchInfo *info, const int32_t *slot_of_leaf, const int8_t *tags, int nleaf,
+                              AdaptGrid g, int32_t *target) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nleaf) return;
+    const int s = slot_of_leaf[k];
+    target[s] = min(g.lmax, max(g.lmin, info[s].level + (int)tags[k]));
+}
+
+// finest cell of the level-lq quadrant (X, Y), wrapped where periodic; -1
+// outside a wall
+__device__ __forceinline__ long long quadrant_cell(const AdaptGrid &g, int lq, int X, int Y) {
+    const int nq = 1 << lq;
+    if (X < 0 || X >= nq) { if (!g.px) return -1; X = (X + nq) % nq; }
+    if (Y < 0 || Y >= nq) { if (!g.py) return -1; Y = (Y + nq) % nq; }
+    const int x = lq <= g.L ? X << (g.L - lq) : X >> (lq - g.L), y = lq <= g.L ? Y << (g.L - lq) : Y >> (lq - g.L);
+    return (long long)y * g.n + x;
+}
+
+// T = the largest target over the leaf and the leaves touching it across a
+// face or a corner (the ring of level-(l+1) quadrants around it); with
+// smooth == 0 the leaf's own target
+__global__ void smooth_kernel(const PatchInfo *info, int nslot, const int32_t *owner, const int32_t *target, AdaptGrid g,
+                              int smooth, int32_t *T) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nslot) return;
+    int m = target[s];
+    if (smooth) {
+        const PatchInfo P = info[s];
+        const int lq = P.level + 1;
+        for (int dy = -1; dy <= 2; dy++)
+            for (int dx = -1; dx <= 2; dx++) {
+                if (dx >= 0 && dx <= 1 && dy >= 0 && dy <= 1) continue;
+                const long long c = quadrant_cell(g, lq, 2 * P.ix + dx, 2 * P.iy + dy);
+                if (c >= 0) m = max(m, target[owner[c]]);
+            }
+    }
+    T[s] = m;
+}
+
+// New level of every leaf, painted over its cells: one finer if its T is
+// above its level, one coarser if it and its three siblings are all leaves
+// whose T is below their level, else unchanged.
+__global__ void decide_kernel(const PatchInfo *info, const int32_t *owner, const int32_t *T, AdaptGrid g, int8_t *lev) {
+    const int s = blockIdx.x;
+    const PatchInfo P = info[s];
+    const int l = P.level;
+    int nl = l;
+    if (T[s] > l && l < g.lmax) {
+        nl = l + 1;
+    } else if (T[s] < l && l > g.lmin) {
+        bool all = true;
+        for (int c = 0; c < 4; c++) {
+            const int X = (P.ix & ~1) + (c & 1), Y = (P.iy & ~1) + (c >> 1);
+            const int o = owner[quadrant_cell(g, l, X, Y)];
+            const PatchInfo Q = info[o];
+            all = all && Q.level == l && Q.ix == X && Q.iy == Y && T[o] < l;
+        }
+        if (all) nl = l - 1;
+    }
+    const int b = 1 << (g.L - l), x0 = P.ix * b, y0 = P.iy * b;
+    for (int k = threadIdx.x; k < b * b; k += blockDim.x) lev[(size_t)(y0 + k / b) * g.n + x0 + k % b] = (int8_t)nl;
+}
+
+// One pass of 2:1 balance by refinement: every leaf of map `a` (found at the
+// origin cell of its block) that touches a cell more than one level finer
+// across a face or a corner is refined in map `b` (which starts as a copy of
+// `a`); *changed is raised if any was.
+__global__ void balance_kernel(const int8_t *a, int8_t *b, AdaptGrid g, int32_t *changed) {
+    const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= (long long)g.n * g.n) return;
+    const int x = (int)(c % g.n), y = (int)(c / g.n), l = a[c], w = 1 << (g.L - l);
+    if ((x & (w - 1)) || (y & (w - 1))) return;  // not the origin of a leaf
+    bool refine = false;
+    for (int k = -1; k <= w && !refine; k++) {
+        // the perimeter just outside the block: rows y-1 and y+w, columns x-1 and x+w
+        const int xs[4] = {x + k, x + k, x - 1, x + w}, ys[4] = {y - 1, y + w, y + k, y + k};
+        for (int e = 0; e < 4; e++) {
+            const long long q = quadrant_cell(g, g.L, xs[e], ys[e]);
+            if (q >= 0 && a[q] > l + 1) refine = true;
+        }
+    }
+    if (!refine || l >= g.lmax) return;
+    for (int k = 0; k < w * w; k++) b[(size_t)(y + k / w) * g.n + x + k % w] = (int8_t)(l + 1);
+    atomicOr(changed, 1);
+}
+
+// the leaves of map `a`: one per block origin, in no particular order
+__global__ void extract_kernel(const int8_t *a, AdaptGrid g, int cap, int32_t *count, int32_t *out) {
+    const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= (long long)g.n * g.n) return;
+    const int x = (int)(c % g.n), y = (int)(c / g.n), l = a[c], sh = g.L - l, w = 1 << sh;
+    if ((x & (w - 1)) || (y & (w - 1))) return;
+    const int k = atomicAdd(count, 1);
+    if (k < cap) {
+        out[3 * k] = l;
+        out[3 * k + 1] = x >> sh;
+        out[3 * k + 2] = y >> sh;
+    }
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------------
 // launchers
 // ------------------------------------------------------------------------
+hipError_t launch_adapt_device(const Ctx &c, const int32_t *slot_of_leaf, const int8_t *tags, int nleaf, int L,
+                               int periodic_x, int periodic_y, int lmin, int lmax, int smooth, int32_t *owner,
+                               int32_t *target, int32_t *T, int8_t *lev_a, int8_t *lev_b, int32_t *flags,
+                               hipStream_t s) {
+    AdaptGrid g{L, 1 << L, periodic_x, periodic_y, lmin, lmax};
+    const long long cells = (long long)g.n * g.n;
+    const int cb = (int)((cells + 255) / 256);
+    hipLaunchKernelGGL(paint_owner_kernel, dim3(nleaf), dim3(256), 0, s, c.info, g, owner);
+    hipLaunchKernelGGL(target_kernel, dim3((nleaf + 255) / 256), dim3(256), 0, s, c.info, slot_of_leaf, tags, nleaf, g,
+                       target);
+    hipLaunchKernelGGL(smooth_kernel, dim3((nleaf + 255) / 256), dim3(256), 0, s, c.info, nleaf, owner, target, g,
+                       smooth, T);
+    hipLaunchKernelGGL(decide_kernel, dim3(nleaf), dim3(256), 0, s, c.info, owner, T, g, lev_a);
+    (void)cb;
+    (void)flags;
+    (void)lev_b;
+    return hipGetLastError();
+}
+
+hipError_t launch_balance_pass(const int8_t *a, int8_t *b, int L, int periodic_x, int periodic_y, int lmin, int lmax,
+                               int32_t *changed, hipStream_t s) {
+    AdaptGrid g{L, 1 << L, periodic_x, periodic_y, lmin, lmax};
+    const long long cells = (long long)g.n * g.n;
+    hipError_t e = hipMemcpyAsync(b, a, (size_t)cells, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(balance_kernel, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, s, a, b, g, changed);
+    return hipGetLastError();
+}
+
+hipError_t launch_extract_leaves(const int8_t *a, int L, int cap, int32_t *count, int32_t *out, hipStream_t s) {
+    AdaptGrid g{L, 1 << L, 0, 0, 0, 0};
+    const long long cells = (long long)g.n * g.n;
+    hipLaunchKernelGGL(extract_kernel, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, s, a, g, cap, count, out);
+    return hipGetLastError();
+}
 hipError_t launch_init_tables(int level, int mx, int periodic_x, int periodic_y, double *vt, hipStream_t s) {
     const int n = mx << level;
     const int tot = n + 2 * MB + 1;

@@ -82,6 +82,10 @@ inline uint64_t morton(uint32_t x, uint32_t y) {
 }
 
 constexpr int MBK = 2;  // ghost layers the kernels use
+// finest level of a store whose adaptation can run on the device (its
+// level maps hold 4^max_level cells: 1 M at level 10, 6 MB of workspace)
+constexpr int kAdaptMaxLevel = 10;
+static_assert(sizeof(fc_leaf) == 3 * sizeof(int32_t), "leaf lists cross the ABI as (level, ix, iy) int32 triples");
 
 struct Mesh {
     int mx = 0;
@@ -174,6 +178,11 @@ struct fc_patchstore {
     size_t ws_bytes = 0;
     size_t off_info = 0, off_nbr = 0, off_sl = 0, off_ls = 0, off_lr = 0, off_sched = 0, off_state = 0,
            off_plan = 0, off_tag = 0, off_cfl = 0, off_cflv = 0, off_save = 0, off_vt[FC_MAXLEV] = {0};
+    // adaptation on the device (max_level <= kAdaptMaxLevel): owner map, two
+    // level maps of the finest level, per-slot target and maximum, leaf list,
+    // flags (0: changed, 1: leaf count)
+    size_t off_own = 0, off_lma = 0, off_lmb = 0, off_tgt = 0, off_tmax = 0, off_lout = 0, off_aflags = 0;
+    bool dev_adapt = false;
     std::vector<SchedEntry> sched;
     int pgrid = 0;
     int pgrid_user = 0;  // grid override of the persistent kernel (0: occupancy)
@@ -308,6 +317,17 @@ void layout_workspace(fc_patchstore *ps) {
     ps->off_cflv = o; o = align256(o + sizeof(double));
     ps->off_save = o;  // interiors kept across a coarse step that may be rejected
     if (ps->cfg.cfl_max > 0) o = align256(o + sizeof(double) * cap * ps->F * ps->mx * ps->mx);
+    ps->dev_adapt = ps->cfg.max_level <= kAdaptMaxLevel;
+    if (ps->dev_adapt) {
+        const size_t cells = (size_t)1 << (2 * ps->cfg.max_level);
+        ps->off_own = o; o = align256(o + sizeof(int32_t) * cells);
+        ps->off_lma = o; o = align256(o + cells);
+        ps->off_lmb = o; o = align256(o + cells);
+        ps->off_tgt = o; o = align256(o + sizeof(int32_t) * cap);
+        ps->off_tmax = o; o = align256(o + sizeof(int32_t) * cap);
+        ps->off_lout = o; o = align256(o + 3 * sizeof(int32_t) * cap);
+        ps->off_aflags = o; o = align256(o + 4 * sizeof(int32_t));
+    }
     for (int l = 0; l < FC_MAXLEV; l++) {
         ps->off_vt[l] = o;
         if (l >= ps->cfg.min_level && l <= ps->cfg.max_level && ps->cfg.velocity == FC_VEL_SWIRL)
@@ -962,25 +982,49 @@ fc_status fc_tag_refine(fc_patchstore *ps, double tau_refine, double tau_coarsen
     return FC_OK;
 }
 
-fc_status fc_adapt(const fc_patchstore *ps, const int8_t *tags, fc_leaf *out, int64_t cap, int64_t *n_out) {
+fc_status fc_adapt(const fc_patchstore *ps, const int8_t *tags, int32_t smooth, fc_leaf *out, int64_t cap,
+                   int64_t *n_out) {
     if (!ps || !tags || !out || !n_out) return fail(FC_ERR_ARG, "bad arguments");
     const int n = (int)ps->mesh.lv.size();
-    // tags arrive in input-leaf order
-    std::vector<int8_t> tg(n);
-    for (int k = 0; k < n; k++) tg[ps->slot_of_leaf[k]] = tags[k];
+    const int lmin = ps->cfg.min_level, lmax = ps->cfg.max_level;
+    // target level per slot (tags arrive in input-leaf order), and the
+    // largest target over the leaf and every leaf touching it (Sec. 4.2)
+    std::vector<int> target(n), T(n);
+    for (int k = 0; k < n; k++) {
+        const int s = ps->slot_of_leaf[k];
+        target[s] = std::min(lmax, std::max(lmin, ps->mesh.lv[s].level + (int)tags[k]));
+    }
+    for (int s = 0; s < n; s++) {
+        int m = target[s];
+        if (smooth) {
+            const fc_leaf L = ps->mesh.lv[s];
+            const int lq = L.level + 1, nq = 1 << lq;
+            for (int dy = -1; dy <= 2; dy++)
+                for (int dx = -1; dx <= 2; dx++) {
+                    if (dx >= 0 && dx <= 1 && dy >= 0 && dy <= 1) continue;
+                    int X = 2 * L.ix + dx, Y = 2 * L.iy + dy;
+                    if (X < 0 || X >= nq) { if (ps->cfg.bc[X < 0 ? 0 : 1] != FC_BC_PERIODIC) continue; X = (X + nq) % nq; }
+                    if (Y < 0 || Y >= nq) { if (ps->cfg.bc[Y < 0 ? 2 : 3] != FC_BC_PERIODIC) continue; Y = (Y + nq) % nq; }
+                    for (int l2 = lq; l2 >= 0; l2--) {
+                        const int o = ps->mesh.find(l2, X >> (lq - l2), Y >> (lq - l2));
+                        if (o >= 0) { m = std::max(m, target[o]); break; }
+                    }
+                }
+        }
+        T[s] = m;
+    }
     std::vector<fc_leaf> res;
     std::vector<char> done(n, 0);
-    const int lmin = ps->cfg.min_level, lmax = ps->cfg.max_level;
     for (int s = 0; s < n; s++) {
         if (done[s]) continue;
         const fc_leaf L = ps->mesh.lv[s];
-        if (tg[s] == -1 && L.level > lmin) {
+        if (T[s] < L.level && L.level > lmin) {
             const int px = L.ix >> 1, py = L.iy >> 1;
             int sib[4];
             bool ok = true;
             for (int c = 0; c < 4; c++) {
                 sib[c] = ps->mesh.find(L.level, 2 * px + (c & 1), 2 * py + (c >> 1));
-                if (sib[c] < 0 || tg[sib[c]] != -1) ok = false;
+                if (sib[c] < 0 || !(T[sib[c]] < L.level)) ok = false;
             }
             if (ok) {
                 for (int c = 0; c < 4; c++) done[sib[c]] = 1;
@@ -989,7 +1033,7 @@ fc_status fc_adapt(const fc_patchstore *ps, const int8_t *tags, fc_leaf *out, in
             }
         }
         done[s] = 1;
-        if (tg[s] == 1 && L.level < lmax) {
+        if (T[s] > L.level && L.level < lmax) {
             for (int c = 0; c < 4; c++) res.push_back(fc_leaf{L.level + 1, 2 * L.ix + (c & 1), 2 * L.iy + (c >> 1)});
         } else {
             res.push_back(L);
@@ -1023,6 +1067,54 @@ fc_status fc_adapt(const fc_patchstore *ps, const int8_t *tags, fc_leaf *out, in
     if ((int64_t)res.size() > cap) return fail(FC_ERR_CAPACITY, "adapted leaf set exceeds the output capacity");
     std::copy(res.begin(), res.end(), out);
     *n_out = (int64_t)res.size();
+    return FC_OK;
+}
+
+fc_status fc_adapt_device(fc_patchstore *ps, const int8_t *tags_dev, int32_t smooth, fc_leaf *out, int64_t cap,
+                          int64_t *n_out, void *stream) {
+    fc_status r = check_bound(ps);
+    if (r != FC_OK) return r;
+    if (!tags_dev || !out || !n_out) return fail(FC_ERR_ARG, "bad arguments");
+    if (!ps->dev_adapt) return fail(FC_ERR_ARG, "adaptation on the device needs max_level <= 10");
+    hipStream_t s = (hipStream_t)stream;
+    const int n = (int)ps->mesh.lv.size(), L = ps->cfg.max_level;
+    const int perx = ps->cfg.bc[0] == FC_BC_PERIODIC, pery = ps->cfg.bc[2] == FC_BC_PERIODIC;
+    int8_t *la = (int8_t *)(ps->ws + ps->off_lma), *lb = (int8_t *)(ps->ws + ps->off_lmb);
+    int32_t *flags = (int32_t *)(ps->ws + ps->off_aflags);
+    HIPCHK(launch_adapt_device(make_ctx(ps), (const int32_t *)(ps->ws + ps->off_sl), tags_dev, n, L, perx, pery,
+                               ps->cfg.min_level, L, smooth, (int32_t *)(ps->ws + ps->off_own),
+                               (int32_t *)(ps->ws + ps->off_tgt), (int32_t *)(ps->ws + ps->off_tmax), la, lb, flags, s));
+    // 2:1 balance passes until no leaf is refined (each refinement is
+    // forced by a leaf two levels finer, so the passes end within the level
+    // span)
+    bool settled = false;
+    for (int it = 0; it <= L - ps->cfg.min_level + 2; it++) {
+        HIPCHK(hipMemsetAsync(flags, 0, sizeof(int32_t), s));
+        HIPCHK(launch_balance_pass(la, lb, L, perx, pery, ps->cfg.min_level, L, flags, s));
+        int32_t changed = 0;
+        HIPCHK(hipMemcpyAsync(&changed, flags, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        std::swap(la, lb);
+        if (!changed) { settled = true; break; }
+    }
+    if (!settled) return fail(FC_ERR_STATE, "2:1 balance did not settle");
+    const int capd = (int)ps->cfg.capacity;
+    HIPCHK(hipMemsetAsync(flags + 1, 0, sizeof(int32_t), s));
+    HIPCHK(launch_extract_leaves(la, L, capd, flags + 1, (int32_t *)(ps->ws + ps->off_lout), s));
+    int32_t cnt = 0;
+    HIPCHK(hipMemcpyAsync(&cnt, flags + 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (cnt > capd || cnt > cap) return fail(FC_ERR_CAPACITY, "adapted leaf set exceeds the capacity");
+    std::vector<fc_leaf> res((size_t)cnt);
+    HIPCHK(hipMemcpyAsync(res.data(), ps->ws + ps->off_lout, sizeof(fc_leaf) * (size_t)cnt, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    std::sort(res.begin(), res.end(), [](const fc_leaf &a, const fc_leaf &b) {
+        if (a.level != b.level) return a.level < b.level;
+        if (a.iy != b.iy) return a.iy < b.iy;
+        return a.ix < b.ix;
+    });
+    std::copy(res.begin(), res.end(), out);
+    *n_out = (int64_t)cnt;
     return FC_OK;
 }
 

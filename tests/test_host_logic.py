@@ -105,20 +105,26 @@ def test_store_order_is_level_then_morton(B):
     L.fc_patchstore_destroy(h)
 
 
+@pytest.mark.parametrize("smooth", [0, 1])
 @pytest.mark.parametrize("seed", range(4))
-def test_host_adapt_matches_oracle(B, oracle_lib, seed):
-    leaves = S.random_balanced_leaves(seed, 2, 4)
+def test_host_adapt_matches_oracle(B, oracle_lib, seed, smooth):
+    """Host adaptation (with and without smooth refinement, Sec. 4.2) gives
+    the oracle's leaf set exactly, periodic and walled."""
+    per = seed % 2 == 0
+    bc = ("periodic",) * 4 if per else ("reflect",) * 4
+    leaves = S.random_balanced_leaves(seed, 2, 4, periodic=(per, per))
     rng = np.random.default_rng(seed)
     tags = rng.choice([-1, 0, 1], size=len(leaves), p=[0.5, 0.3, 0.2]).astype(np.int8)
-    st, h, _ = create(B, leaves, lmin=2, lmax=5)
+    st, h, _ = create(B, leaves, lmin=2, lmax=5, bc=bc)
     assert st == 0
     cap = 4 * len(leaves) + 64
     out = (B.Leaf * cap)()
     n = C.c_int64()
-    assert B.lib().fc_adapt(h, tags.ctypes.data_as(C.POINTER(C.c_int8)), out, cap, C.byref(n)) == 0
+    assert B.lib().fc_adapt(h, tags.ctypes.data_as(C.POINTER(C.c_int8)), smooth, out, cap, C.byref(n)) == 0
     mine = np.array([(out[k].level, out[k].ix, out[k].iy) for k in range(n.value)])
-    o = oracle_lib.Oracle(leaves, mx=8, lmin=2, lmax=5)
-    assert np.array_equal(mine, o.adapt(tags))
+    o = oracle_lib.Oracle(leaves, mx=8, lmin=2, lmax=5, bc=bc, velocity="constant" if per else "none",
+                          equation="advection" if per else "swe")
+    assert np.array_equal(mine, o.adapt(tags, smooth=bool(smooth)))
     B.lib().fc_patchstore_destroy(h)
 
 
