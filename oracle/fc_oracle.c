@@ -10,15 +10,19 @@
  * -O2 -ffp-contract=off (no fused multiply-add, no fast-math).
  *
  * What it computes, and where each rule comes from:
- *   - leaves on one unit-square block, 2:1 balance over faces and corners
- *     (Sec. 2, quadtree layout), fixed mx x mx patches with m ghost layers
- *     stored as one contiguous array per patch (Sec. 2);
+ *   - leaves on one unit-square block, or on a brick of unit blocks each
+ *     with its own index orientation (Sec. 2.3, multiblock), 2:1 balance
+ *     over faces and corners across block boundaries too (Sec. 2, quadtree
+ *     layout), fixed mx x mx patches with m ghost layers stored as one
+ *     contiguous array per patch in the block's own indices (Sec. 2);
  *   - ghost filling in the four phases of Algorithm 1 (Sec. 2.2): copy from
  *     same-size neighbours and averaging of fine interiors (eq. ghost_coarse,
  *     Sec. 2.3), physical boundary conditions, coarse->fine interpolation
  *     with a limited one-sided gradient (eq. ghost_fine, Sec. 2.3), boundary
  *     conditions again.  Neighbours are found by GEOMETRIC POINT LOCATION of
- *     each ghost-cell centre in a hash map of leaves -- no neighbour tables.
+ *     each ghost-cell centre in a hash map of leaves -- no neighbour tables;
+ *     on a brick every index goes through the brick's indices into the
+ *     neighbour's own (the index transforms of Sec. 2.3).
  *   - the single-grid update: the unsplit wave-propagation scheme the paper
  *     runs through Clawpack (Sec. 5, cited, not written out in the paper):
  *     Riemann fluctuations, MC-limited second-order correction, transverse
@@ -59,7 +63,13 @@ typedef struct Orc {
     double vp[3], g;
     int lmin, lmax;
     int n;
-    OLeaf *lv;
+    OLeaf *lv;      /* leaves as given: block from the high bits, own indices of the block below */
+    /* multiblock brick (Sec. 2.3): nbx x nby unit blocks, ori[bx + nbx by]
+     * the index orientation of each block; ph[k] is leaf k in brick
+     * coordinates (the point-location key) */
+    int nbx, nby;
+    int *ori;
+    OLeaf *ph;
     double *q, *qold, *qhat;
     int hcap;
     int *hidx;
@@ -76,6 +86,69 @@ static uint64_t hkey(int l, int ix, int iy) {
     return k;
 }
 
+/* ------------------------------------------------------------------ */
+/* multiblock brick: index orientations (Sec. 2.3)                      */
+/* ------------------------------------------------------------------ */
+/* A block's own indices (a, b), n cells (or quadrants) per block side,
+ * against the brick's indices inside that block: code bit 0 exchanges the
+ * two directions, then bit 1 reverses the brick's first direction and bit 2
+ * its second.  Each map has the form of eq. transform, A diagonal or
+ * anti-diagonal with entries +-1, and is used unchanged for indices outside
+ * [0, n) (ghost cells). */
+static void own_to_brick(int code, int n, int a, int b, int *x, int *y) {
+    int p = (code & 1) ? b : a, q = (code & 1) ? a : b;
+    *x = (code & 2) ? n - 1 - p : p;
+    *y = (code & 4) ? n - 1 - q : q;
+}
+static void brick_to_own(int code, int n, int x, int y, int *a, int *b) {
+    int p = (code & 2) ? n - 1 - x : x, q = (code & 4) ? n - 1 - y : y;
+    *a = (code & 1) ? q : p;
+    *b = (code & 1) ? p : q;
+}
+static int block_code(const Orc *o, int bx, int by) {
+    if (!o->ori || bx < 0 || by < 0 || bx >= o->nbx || by >= o->nby) return 0;
+    return o->ori[bx + o->nbx * by];
+}
+static int leaf_code(const Orc *o, int k) {
+    const OLeaf *L = &o->lv[k];
+    return block_code(o, L->ix >> L->level, L->iy >> L->level);
+}
+static int is_brick(const Orc *o) {
+    if (o->nbx != 1 || o->nby != 1) return 1;
+    return o->ori && o->ori[0] != 0;
+}
+
+/* brick coordinates of the level-l quadrant with block-own coordinates (ix, iy) */
+static OLeaf quad_to_brick(const Orc *o, int l, int ix, int iy) {
+    int bx = ix >> l, by = iy >> l, n = 1 << l, x, y;
+    own_to_brick(block_code(o, bx, by), n, ix - bx * n, iy - by * n, &x, &y);
+    OLeaf r = {l, bx * n + x, by * n + y};
+    return r;
+}
+
+/* Brick index (X, Y) of the level-r cell (i, j) of leaf k, counted from the
+ * leaf's first cell in the leaf's own indices (r >= the leaf's level; (i, j)
+ * may lie outside the leaf).  No periodic wrap. */
+static void cell_to_brick(const Orc *o, int k, int r, int i, int j, int *X, int *Y) {
+    const OLeaf *L = &o->lv[k];
+    int l = L->level, sc = o->mx << (r - l), n = o->mx << r;
+    int bx = L->ix >> l, by = L->iy >> l, x, y;
+    own_to_brick(block_code(o, bx, by), n, (L->ix - (bx << l)) * sc + i, (L->iy - (by << l)) * sc + j, &x, &y);
+    *X = bx * n + x;
+    *Y = by * n + y;
+}
+/* The inverse: leaf k's own index of the level-r cell at brick index (X, Y)
+ * (a cell of k's block). */
+static void brick_to_cell(const Orc *o, int k, int r, int X, int Y, int *i, int *j) {
+    const OLeaf *L = &o->lv[k];
+    int l = L->level, sc = o->mx << (r - l), n = o->mx << r;
+    int bx = L->ix >> l, by = L->iy >> l, a, b;
+    brick_to_own(block_code(o, bx, by), n, X - bx * n, Y - by * n, &a, &b);
+    *i = a - (L->ix - (bx << l)) * sc;
+    *j = b - (L->iy - (by << l)) * sc;
+}
+
+/* the hash map is keyed by brick coordinates */
 static void hash_build(Orc *o) {
     int cap = 16;
     while (cap < 4 * o->n) cap <<= 1;
@@ -84,23 +157,39 @@ static void hash_build(Orc *o) {
     o->hidx = (int *)malloc(sizeof(int) * cap);
     for (int i = 0; i < cap; i++) o->hidx[i] = -1;
     for (int k = 0; k < o->n; k++) {
-        uint64_t h = hkey(o->lv[k].level, o->lv[k].ix, o->lv[k].iy) & (uint64_t)(cap - 1);
+        uint64_t h = hkey(o->ph[k].level, o->ph[k].ix, o->ph[k].iy) & (uint64_t)(cap - 1);
         while (o->hidx[h] >= 0) h = (h + 1) & (uint64_t)(cap - 1);
         o->hidx[h] = k;
     }
 }
 
+/* brick coordinates of every leaf, then the hash map */
+static void index_leaves(Orc *o) {
+    free(o->ph);
+    o->ph = (OLeaf *)malloc(sizeof(OLeaf) * (o->n > 0 ? o->n : 1));
+    for (int k = 0; k < o->n; k++) o->ph[k] = quad_to_brick(o, o->lv[k].level, o->lv[k].ix, o->lv[k].iy);
+    hash_build(o);
+}
+
+/* leaf at brick coordinates (l, ix, iy), -1 if none */
 static int find_leaf(const Orc *o, int l, int ix, int iy) {
     if (l < 0) return -1;
-    int nq = 1 << l;
-    if (ix < 0 || iy < 0 || ix >= nq || iy >= nq) return -1;
+    if (ix < 0 || iy < 0 || ix >= (o->nbx << l) || iy >= (o->nby << l)) return -1;
     uint64_t h = hkey(l, ix, iy) & (uint64_t)(o->hcap - 1);
     while (o->hidx[h] >= 0) {
-        const OLeaf *L = &o->lv[o->hidx[h]];
+        const OLeaf *L = &o->ph[o->hidx[h]];
         if (L->level == l && L->ix == ix && L->iy == iy) return o->hidx[h];
         h = (h + 1) & (uint64_t)(o->hcap - 1);
     }
     return -1;
+}
+
+/* leaf at block-own coordinates (l, ix, iy) (parents, children and siblings
+ * share their block and so their indices), -1 if none */
+static int find_local(const Orc *o, int l, int ix, int iy) {
+    if (l < 0 || ix < 0 || iy < 0 || ix >= (o->nbx << l) || iy >= (o->nby << l)) return -1;
+    OLeaf b = quad_to_brick(o, l, ix, iy);
+    return find_leaf(o, b.level, b.ix, b.iy);
 }
 
 /* Leaf containing the centre of level-l cell (I, J), I, J inside [0, mx 2^l).
@@ -142,7 +231,7 @@ static int covered_by_le(const Orc *o, int lf, int X, int Y, int lcap) {
 
 /* 2:1 condition for one leaf against all face and corner neighbours */
 static int balanced_at(const Orc *o, const OLeaf *L) {
-    int l = L->level, lf = l + 2, nf = 1 << lf;
+    int l = L->level, lf = l + 2, nfx = o->nbx << lf, nfy = o->nby << lf;
     int x0 = L->ix * 4, y0 = L->iy * 4;
     for (int dy = -1; dy <= 1; dy++)
         for (int dx = -1; dx <= 1; dx++) {
@@ -154,13 +243,13 @@ static int balanced_at(const Orc *o, const OLeaf *L) {
             for (int yy = ys0; yy <= ys1; yy++)
                 for (int xx = xs0; xx <= xs1; xx++) {
                     int X = xx, Y = yy;
-                    if (X < 0 || X >= nf) {
+                    if (X < 0 || X >= nfx) {
                         if (o->bc[X < 0 ? 0 : 1] != BC_PERIODIC) continue;
-                        X = (X + nf) % nf;
+                        X = (X + nfx) % nfx;
                     }
-                    if (Y < 0 || Y >= nf) {
+                    if (Y < 0 || Y >= nfy) {
                         if (o->bc[Y < 0 ? 2 : 3] != BC_PERIODIC) continue;
-                        Y = (Y + nf) % nf;
+                        Y = (Y + nfy) % nfy;
                     }
                     if (!covered_by_le(o, lf, X, Y, l + 1)) return 0;
                 }
@@ -169,33 +258,51 @@ static int balanced_at(const Orc *o, const OLeaf *L) {
 }
 
 static int check_mesh(Orc *o) {
-    /* leaves must tile the square: areas sum to 1 and no two overlap */
+    /* leaves must tile the brick (the unit square for one block): areas sum
+     * to the number of blocks and no two overlap */
     int err = 0;
     double area = 0.0;
+    index_leaves(o);
     for (int k = 0; k < o->n; k++) {
         const OLeaf *L = &o->lv[k];
-        int nq = 1 << L->level;
-        if (L->level < 0 || L->level > 20 || L->ix < 0 || L->iy < 0 || L->ix >= nq || L->iy >= nq)
+        if (L->level < 0 || L->level > 20 || L->ix < 0 || L->iy < 0 || L->ix >= (o->nbx << L->level) ||
+            L->iy >= (o->nby << L->level))
             return ERR_ARG;
+    }
+    for (int k = 0; k < o->n; k++) {
+        const OLeaf *L = &o->lv[k];
         area += ldexp(1.0, -2 * L->level);
         /* an ancestor that is also a leaf means overlap */
         for (int a = 1; a <= L->level; a++)
-            if (find_leaf(o, L->level - a, L->ix >> a, L->iy >> a) >= 0) err |= ERR_COVER;
-        if (find_leaf(o, L->level, L->ix, L->iy) != k) err |= ERR_COVER;
+            if (find_local(o, L->level - a, L->ix >> a, L->iy >> a) >= 0) err |= ERR_COVER;
+        if (find_local(o, L->level, L->ix, L->iy) != k) err |= ERR_COVER;
     }
-    if (fabs(area - 1.0) > 1e-12) err |= ERR_COVER;
+    if (fabs(area - (double)o->nbx * o->nby) > 1e-12) err |= ERR_COVER;
     if (err) return err;
     /* 2:1 balance over faces and corners (Sec. 2): every quadrant two levels
      * finer that touches a leaf across a face or corner must lie inside a
-     * leaf at most one level finer than that leaf. */
+     * leaf at most one level finer than that leaf; across block boundaries
+     * too (brick coordinates). */
     for (int k = 0; k < o->n; k++)
-        if (!balanced_at(o, &o->lv[k])) err |= ERR_UNBALANCED;
+        if (!balanced_at(o, &o->ph[k])) err |= ERR_UNBALANCED;
     return err;
 }
 
-Orc *orc_create(int mx, int mbc, int eq, int lim, const int *bc, int vel, const double *vp,
-                double g, int lmin, int lmax, int n, const int *leaves, int *status) {
+/* A brick of nbx x nby unit blocks (Sec. 2.3); ori: nbx*nby orientation
+ * codes (block (bx, by) at bx + nbx by), NULL for all zero.  Leaves (level,
+ * ix, iy): block (ix >> level, iy >> level), the low bits the quadrant's
+ * coordinates in the block's own indices.  A brick other than one block
+ * of code 0 takes periodic sides and scalar advection at a constant
+ * velocity (given in the brick's directions). */
+Orc *orc_create_brick(int mx, int mbc, int eq, int lim, const int *bc, int vel, const double *vp, double g,
+                      int lmin, int lmax, int nbx, int nby, const int *ori, int n, const int *leaves, int *status) {
     Orc *o = (Orc *)calloc(1, sizeof(Orc));
+    o->nbx = nbx > 0 ? nbx : 1;
+    o->nby = nby > 0 ? nby : 1;
+    if (ori) {
+        o->ori = (int *)malloc(sizeof(int) * o->nbx * o->nby);
+        for (int b = 0; b < o->nbx * o->nby; b++) o->ori[b] = ori[b] & 7;
+    }
     o->mx = mx; o->m = mbc; o->N = mx + 2 * mbc;
     o->eq = eq; o->F = eq == EQ_SWE ? 3 : 1; o->lim = lim;
     for (int s = 0; s < 4; s++) o->bc[s] = bc[s];
@@ -212,7 +319,13 @@ Orc *orc_create(int mx, int mbc, int eq, int lim, const int *bc, int vel, const 
     *status = 0;
     /* Prop. 2.1: m <= M/4 (the interpolation stencil here is 3 wide) */
     if (mbc < 2 || 4 * mbc > mx || (mx & 1)) { *status = ERR_WIDTH; }
-    hash_build(o);
+    if (nbx < 1 || nby < 1) *status |= ERR_ARG;
+    if (ori)
+        for (int b = 0; b < o->nbx * o->nby; b++)
+            if (ori[b] < 0 || ori[b] > 7) *status |= ERR_ARG;
+    if (is_brick(o) && (eq != EQ_ADV || vel == VEL_SWIRL || bc[0] != BC_PERIODIC || bc[1] != BC_PERIODIC ||
+                        bc[2] != BC_PERIODIC || bc[3] != BC_PERIODIC))
+        *status |= ERR_ARG;
     int e = check_mesh(o);
     if (e) *status |= e;
     size_t sz = (size_t)(n > 0 ? n : 1) * o->F * o->N * o->N;
@@ -222,9 +335,14 @@ Orc *orc_create(int mx, int mbc, int eq, int lim, const int *bc, int vel, const 
     return o;
 }
 
+Orc *orc_create(int mx, int mbc, int eq, int lim, const int *bc, int vel, const double *vp,
+                double g, int lmin, int lmax, int n, const int *leaves, int *status) {
+    return orc_create_brick(mx, mbc, eq, lim, bc, vel, vp, g, lmin, lmax, 1, 1, NULL, n, leaves, status);
+}
+
 void orc_destroy(Orc *o) {
     if (!o) return;
-    free(o->lv); free(o->q); free(o->qold); free(o->qhat); free(o->hidx);
+    free(o->lv); free(o->q); free(o->qold); free(o->qhat); free(o->hidx); free(o->ph); free(o->ori);
     free(o);
 }
 
@@ -315,32 +433,53 @@ static void poison_ghosts(const Orc *o, double *p) {
                 if (is_ghost(o, i, j)) *cell(o, p, f, i, j) = NAN;
 }
 
-/* Phase "copy and average": coarse ghost regions of leaf k (Alg. 1, first loop) */
+/* Brick index of the level-r cell (i, j) of leaf k (own indices from its
+ * first cell), wrapped on periodic sides of the brick; returns 0 if the cell
+ * lies outside a physical wall. */
+static int ghost_to_brick(const Orc *o, int k, int r, int i, int j, int *X, int *Y) {
+    int nl = o->mx << r;
+    cell_to_brick(o, k, r, i, j, X, Y);
+    *X = wrap_axis(o, *X, o->nbx * nl, 0, 1);
+    *Y = wrap_axis(o, *Y, o->nby * nl, 2, 3);
+    return *X >= 0 && *Y >= 0;
+}
+
+/* Phase "copy and average": coarse ghost regions of leaf k (Alg. 1, first
+ * loop).  Sec. 2.3: every index of this patch is carried into the
+ * neighbour's own indices (through the brick's, which amounts to eq.
+ * transform and, for a fine neighbour, the fine points I_f^k of the
+ * direction vectors d_k taken in this patch's indices). */
 static void fill_coarse_ghosts(Orc *o, int k, int clevel) {
     const OLeaf *P = &o->lv[k];
-    int l = P->level, mx = o->mx, nl = mx << l;
+    int l = P->level, mx = o->mx;
     double *dst = src_of(o, k, clevel);
     for (int j = -o->m; j < mx + o->m; j++)
         for (int i = -o->m; i < mx + o->m; i++) {
             if (!is_ghost(o, i, j)) continue;
-            int I = wrap_axis(o, P->ix * mx + i, nl, 0, 1);
-            int J = wrap_axis(o, P->iy * mx + j, nl, 2, 3);
-            if (I < 0 || J < 0) continue; /* exterior: boundary conditions */
+            int I, J;
+            if (!ghost_to_brick(o, k, l, i, j, &I, &J)) continue; /* exterior: boundary conditions */
             int kk = locate(o, l, I, J);
             if (kk < 0) { o->err |= ERR_STENCIL; continue; }
             const OLeaf *L = &o->lv[kk];
             double *s = src_of(o, kk, clevel);
             if (L->level == l) {
-                /* same size: q_c(I_c) = q_n(I_n), A = identity on one block */
-                for (int f = 0; f < o->F; f++)
-                    *cell(o, dst, f, i, j) = *cell(o, s, f, I - L->ix * mx, J - L->iy * mx);
+                /* same size: q_c(I_c) = q_n(I_n) */
+                int a, b;
+                brick_to_cell(o, kk, l, I, J, &a, &b);
+                for (int f = 0; f < o->F; f++) *cell(o, dst, f, i, j) = *cell(o, s, f, a, b);
             } else if (L->level == l + 1) {
                 /* eq. ghost_coarse: mean of the four fine cells I_f^k,
-                 * k = 0..3 in the order of the direction vectors d_k */
-                int fi = 2 * I - L->ix * mx, fj = 2 * J - L->iy * mx;
+                 * k = 0..3 in the order of the direction vectors d_k of
+                 * this (coarse) patch: fine cell (2i, 2j) + (1 + d_k) / 2 */
+                int fa[4], fb[4];
+                for (int d = 0; d < 4; d++) {
+                    int X, Y;
+                    ghost_to_brick(o, k, l + 1, 2 * i + (d & 1), 2 * j + (d >> 1), &X, &Y);
+                    brick_to_cell(o, kk, l + 1, X, Y, &fa[d], &fb[d]);
+                }
                 for (int f = 0; f < o->F; f++)
-                    *cell(o, dst, f, i, j) = 0.25 * (*cell(o, s, f, fi, fj) + *cell(o, s, f, fi + 1, fj) +
-                                                     *cell(o, s, f, fi, fj + 1) + *cell(o, s, f, fi + 1, fj + 1));
+                    *cell(o, dst, f, i, j) = 0.25 * (*cell(o, s, f, fa[0], fb[0]) + *cell(o, s, f, fa[1], fb[1]) +
+                                                     *cell(o, s, f, fa[2], fb[2]) + *cell(o, s, f, fa[3], fb[3]));
             }
             /* L coarser: a fine ghost region, filled by interpolation */
         }
@@ -385,21 +524,24 @@ static void apply_bc(Orc *o, int k, int clevel) {
  * grid's own ghost cells (filled in the earlier phases). */
 static void fill_fine_ghosts(Orc *o, int k, int clevel) {
     const OLeaf *P = &o->lv[k];
-    int l = P->level, mx = o->mx, nl = mx << l;
+    int l = P->level, mx = o->mx;
     double *dst = pat(o, o->q, k);
     for (int j = -o->m; j < mx + o->m; j++)
         for (int i = -o->m; i < mx + o->m; i++) {
             if (!is_ghost(o, i, j)) continue;
-            int I = wrap_axis(o, P->ix * mx + i, nl, 0, 1);
-            int J = wrap_axis(o, P->iy * mx + j, nl, 2, 3);
-            if (I < 0 || J < 0) continue;
+            int I, J;
+            if (!ghost_to_brick(o, k, l, i, j, &I, &J)) continue;
             int kk = locate(o, l, I, J);
             if (kk < 0 || o->lv[kk].level != l - 1) continue;
-            const OLeaf *L = &o->lv[kk];
             double *s = src_of(o, kk, clevel);
-            int ic = I / 2 - L->ix * mx, jc = J / 2 - L->iy * mx;
+            /* the fine cell in the coarse leaf's own indices, at the fine
+             * resolution (Sec. 2.3: the stencil and d_k live in the coarse
+             * grid's index space) */
+            int a, b;
+            brick_to_cell(o, kk, l, I, J, &a, &b);
+            int ic = a >> 1, jc = b >> 1;
             /* d_k: +1 when the fine cell is the upper half of the coarse cell */
-            double dx = (I & 1) ? 1.0 : -1.0, dy = (J & 1) ? 1.0 : -1.0;
+            double dx = (a & 1) ? 1.0 : -1.0, dy = (b & 1) ? 1.0 : -1.0;
             for (int f = 0; f < o->F; f++) {
                 double c = *cell(o, s, f, ic, jc);
                 double xm = *cell(o, s, f, ic - 1, jc), xp = *cell(o, s, f, ic + 1, jc);
@@ -472,8 +614,22 @@ void orc_ghost_fill(Orc *o, int lo, int hi, double alpha) {
  * mid time. */
 static int wrap_idx(int I, int nl) { I %= nl; return I < 0 ? I + nl : I; }
 
-static double vel_u(const Orc *o, int l, int Ie, int Jc, double tm) {
-    if (o->vel == VEL_CONST) return o->vp[0];
+/* A constant velocity (u, v), given in the brick's directions, seen in the
+ * own indices of a block with orientation code `code`: its component along
+ * the block's first (dir 0) or second (dir 1) index direction.  A reversed
+ * brick direction reverses the component; with the directions exchanged the
+ * block's first index runs along the brick's second direction. */
+static double const_own(const Orc *o, int code, int dir) {
+    double u = (code & 2) ? -o->vp[0] : o->vp[0];
+    double v = (code & 4) ? -o->vp[1] : o->vp[1];
+    if (code & 1) return dir == 0 ? v : u;
+    return dir == 0 ? u : v;
+}
+
+/* edge velocities of a leaf whose block has orientation code `code` (the
+ * swirl field lives on one block of code 0) */
+static double vel_u(const Orc *o, int code, int l, int Ie, int Jc, double tm) {
+    if (o->vel == VEL_CONST) return const_own(o, code, 0);
     if (o->vel == VEL_NONE) return 0.0;
     int nl = o->mx << l;
     double h = 1.0 / nl;
@@ -485,8 +641,8 @@ static double vel_u(const Orc *o, int l, int Ie, int Jc, double tm) {
     double c = cos(M_PI * tm / o->vp[0]);
     return sx * sx * sin(2.0 * M_PI * y) * sig * c;
 }
-static double vel_v(const Orc *o, int l, int Ic, int Je, double tm) {
-    if (o->vel == VEL_CONST) return o->vp[1];
+static double vel_v(const Orc *o, int code, int l, int Ic, int Je, double tm) {
+    if (o->vel == VEL_CONST) return const_own(o, code, 1);
     if (o->vel == VEL_NONE) return 0.0;
     int nl = o->mx << l;
     double h = 1.0 / nl;
@@ -503,7 +659,7 @@ static double vel_v(const Orc *o, int l, int Ic, int Je, double tm) {
  * dir 0: u on x-edge I (between cells I-1 and I) of row J; dir 1: v on
  * y-edge J of column I; level-l indices, at time tm. */
 double orc_edge_velocity(const Orc *o, int l, int dir, int I, int J, double tm) {
-    return dir == 0 ? vel_u(o, l, I, J, tm) : vel_v(o, l, I, J, tm);
+    return dir == 0 ? vel_u(o, 0, l, I, J, tm) : vel_v(o, 0, l, I, J, tm);
 }
 
 /* ------------------------------------------------------------------ */
@@ -577,7 +733,7 @@ static double adv_step(const Orc *o, int k, const double *Q, double *Qn, double 
     const OLeaf *P = &o->lv[k];
     int mx = o->mx, l = P->level;
     double h = 1.0 / (mx << l), lam = dt / h, tm = t + 0.5 * dt;
-    int gx = P->ix * mx, gy = P->iy * mx;
+    int gx = P->ix * mx, gy = P->iy * mx, oc = leaf_code(o, k);
     size_t s = (size_t)(w->N + 1) * (w->N + 1);
     memset(w->Ft, 0, s * sizeof(double)); memset(w->Gt, 0, s * sizeof(double));
     const double *D = dQ ? dQ : Q; /* data the (linear in D) update acts on */
@@ -587,7 +743,7 @@ static double adv_step(const Orc *o, int k, const double *Q, double *Qn, double 
     /* x-edges (i-1/2, j), i in [0, mx], j in [-1, mx] */
     for (int j = -1; j <= mx; j++)
         for (int i = 0; i <= mx; i++) {
-            double s_ = vel_u(o, l, gx + i, gy + j, tm);
+            double s_ = vel_u(o, oc, l, gx + i, gy + j, tm);
             double W = DD(i, j) - DD(i - 1, j);
             double Ap = (s_ > 0 ? s_ : 0.0) * W, Am = (s_ < 0 ? s_ : 0.0) * W;
             WE(w, w->Apx, j, i) = Ap; WE(w, w->Amx, j, i) = Am;
@@ -604,8 +760,8 @@ static double adv_step(const Orc *o, int k, const double *Q, double *Qn, double 
             double C = fabs(s_) * (1.0 - lam * fabs(s_)) * Wl;
             WE(w, w->Ft, j, i) += 0.5 * C;
             double Aps = Ap - C, Ams = Am + C;
-            double vpu = vel_v(o, l, gx + i, gy + j + 1, tm), vpd = vel_v(o, l, gx + i, gy + j, tm);
-            double vmu = vel_v(o, l, gx + i - 1, gy + j + 1, tm), vmd = vel_v(o, l, gx + i - 1, gy + j, tm);
+            double vpu = vel_v(o, oc, l, gx + i, gy + j + 1, tm), vpd = vel_v(o, oc, l, gx + i, gy + j, tm);
+            double vmu = vel_v(o, oc, l, gx + i - 1, gy + j + 1, tm), vmd = vel_v(o, oc, l, gx + i - 1, gy + j, tm);
             WE(w, w->Gt, j + 1, i) -= 0.5 * lam * (vpu > 0 ? vpu : 0.0) * Aps;
             WE(w, w->Gt, j, i) -= 0.5 * lam * (vpd < 0 ? vpd : 0.0) * Aps;
             WE(w, w->Gt, j + 1, i - 1) -= 0.5 * lam * (vmu > 0 ? vmu : 0.0) * Ams;
@@ -615,7 +771,7 @@ static double adv_step(const Orc *o, int k, const double *Q, double *Qn, double 
     /* y-edges (i, j-1/2), j in [0, mx], i in [-1, mx] */
     for (int i = -1; i <= mx; i++)
         for (int j = 0; j <= mx; j++) {
-            double s_ = vel_v(o, l, gx + i, gy + j, tm);
+            double s_ = vel_v(o, oc, l, gx + i, gy + j, tm);
             double V = DD(i, j) - DD(i, j - 1);
             double Bp = (s_ > 0 ? s_ : 0.0) * V, Bm = (s_ < 0 ? s_ : 0.0) * V;
             WE(w, w->Bpy, j, i) = Bp; WE(w, w->Bmy, j, i) = Bm;
@@ -632,8 +788,8 @@ static double adv_step(const Orc *o, int k, const double *Q, double *Qn, double 
             double C = fabs(s_) * (1.0 - lam * fabs(s_)) * Vl;
             WE(w, w->Gt, j, i) += 0.5 * C;
             double Bps = Bp - C, Bms = Bm + C;
-            double upr = vel_u(o, l, gx + i + 1, gy + j, tm), upl = vel_u(o, l, gx + i, gy + j, tm);
-            double umr = vel_u(o, l, gx + i + 1, gy + j - 1, tm), uml = vel_u(o, l, gx + i, gy + j - 1, tm);
+            double upr = vel_u(o, oc, l, gx + i + 1, gy + j, tm), upl = vel_u(o, oc, l, gx + i, gy + j, tm);
+            double umr = vel_u(o, oc, l, gx + i + 1, gy + j - 1, tm), uml = vel_u(o, oc, l, gx + i, gy + j - 1, tm);
             WE(w, w->Ft, j, i + 1) -= 0.5 * lam * (upr > 0 ? upr : 0.0) * Bps;
             WE(w, w->Ft, j, i) -= 0.5 * lam * (upl < 0 ? upl : 0.0) * Bps;
             WE(w, w->Ft, j - 1, i + 1) -= 0.5 * lam * (umr > 0 ? umr : 0.0) * Bms;
@@ -948,8 +1104,8 @@ static int cmp_leaf(const void *a, const void *b) {
     return x[1] - y[1];
 }
 
-/* Leaf containing the level-lq quadrant (X, Y) (inside the square), found by
- * searching levels lq, lq-1, ..., 0; -1 if none. */
+/* Leaf containing the level-lq quadrant (X, Y) (brick coordinates, inside the
+ * brick), found by searching levels lq, lq-1, ..., 0; -1 if none. */
 static int leaf_containing(const Orc *o, int lq, int X, int Y) {
     for (int l2 = lq; l2 >= 0; l2--) {
         int k = find_leaf(o, l2, X >> (lq - l2), Y >> (lq - l2));
@@ -967,14 +1123,14 @@ static int leaf_containing(const Orc *o, int lq, int X, int Y) {
  * have no neighbour. */
 static void smooth_targets(const Orc *o, const int *target, int *T) {
     for (int k = 0; k < o->n; k++) {
-        const OLeaf *L = &o->lv[k];
-        int lq = L->level + 1, nq = 1 << lq, m = target[k];
+        const OLeaf *L = &o->ph[k]; /* brick coordinates: the ring crosses blocks */
+        int lq = L->level + 1, nqx = o->nbx << lq, nqy = o->nby << lq, m = target[k];
         for (int dy = -1; dy <= 2; dy++)
             for (int dx = -1; dx <= 2; dx++) {
                 if (dx >= 0 && dx <= 1 && dy >= 0 && dy <= 1) continue; /* the leaf itself */
                 int X = 2 * L->ix + dx, Y = 2 * L->iy + dy;
-                if (X < 0 || X >= nq) { if (o->bc[X < 0 ? 0 : 1] != BC_PERIODIC) continue; X = (X + nq) % nq; }
-                if (Y < 0 || Y >= nq) { if (o->bc[Y < 0 ? 2 : 3] != BC_PERIODIC) continue; Y = (Y + nq) % nq; }
+                if (X < 0 || X >= nqx) { if (o->bc[X < 0 ? 0 : 1] != BC_PERIODIC) continue; X = (X + nqx) % nqx; }
+                if (Y < 0 || Y >= nqy) { if (o->bc[Y < 0 ? 2 : 3] != BC_PERIODIC) continue; Y = (Y + nqy) % nqy; }
                 int kk = leaf_containing(o, lq, X, Y);
                 if (kk >= 0 && target[kk] > m) m = target[kk];
             }
@@ -1010,7 +1166,7 @@ static int adapt_impl(const Orc *o, const signed char *tags, int smooth, int *ou
         if (T[k] < L->level && L->level > o->lmin) {
             int px = L->ix >> 1, py = L->iy >> 1, sib[4], ok = 1;
             for (int c = 0; c < 4; c++) {
-                sib[c] = find_leaf(o, L->level, 2 * px + (c & 1), 2 * py + (c >> 1));
+                sib[c] = find_local(o, L->level, 2 * px + (c & 1), 2 * py + (c >> 1));
                 if (sib[c] < 0 || !(T[sib[c]] < L->level)) ok = 0;
             }
             if (ok) {
@@ -1037,15 +1193,17 @@ static int adapt_impl(const Orc *o, const signed char *tags, int smooth, int *ou
         Orc tmp;
         memset(&tmp, 0, sizeof(tmp));
         tmp.mx = o->mx; tmp.n = cnt; tmp.lv = (OLeaf *)out;
+        tmp.nbx = o->nbx; tmp.nby = o->nby; tmp.ori = o->ori;
         for (int s = 0; s < 4; s++) tmp.bc[s] = o->bc[s];
-        hash_build(&tmp);
+        index_leaves(&tmp);
         int nref = 0;
         int *ref = (int *)calloc(cnt, sizeof(int));
         for (int k = 0; k < cnt; k++) {
-            ref[k] = !balanced_at(&tmp, &tmp.lv[k]);
+            ref[k] = !balanced_at(&tmp, &tmp.ph[k]);
             if (ref[k]) nref++;
         }
         free(tmp.hidx);
+        free(tmp.ph);
         if (!nref) { free(ref); break; }
         int *nw = (int *)malloc(sizeof(int) * 3 * (cnt + 3 * nref));
         int c2 = 0;
@@ -1079,19 +1237,20 @@ int orc_adapt_smooth(const Orc *o, const signed char *tags, int *out, int cap) {
  * the mean of their four children (Sec. 4.1).  Returns 0 or an error code. */
 int orc_regrid(Orc *o, int n_new, const int *leaves_new) {
     int st = 0;
-    Orc *nw = orc_create(o->mx, o->m, o->eq, o->lim, o->bc, o->vel, o->vp, o->g, o->lmin, o->lmax, n_new,
+    Orc *nw = orc_create_brick(o->mx, o->m, o->eq, o->lim, o->bc, o->vel, o->vp, o->g, o->lmin, o->lmax, o->nbx,
+                               o->nby, o->ori, n_new,
                          leaves_new, &st);
     if (st) { orc_destroy(nw); return st; }
     int mx = o->mx;
     for (int k = 0; k < n_new; k++) {
         const OLeaf *L = &nw->lv[k];
         double *d = pat(nw, nw->q, k);
-        int ko = find_leaf(o, L->level, L->ix, L->iy);
+        int ko = find_local(o, L->level, L->ix, L->iy);
         if (ko >= 0) {
             memcpy(d, pat(o, o->q, ko), sizeof(double) * o->F * o->N * o->N);
             continue;
         }
-        int kp = find_leaf(o, L->level - 1, L->ix >> 1, L->iy >> 1);
+        int kp = find_local(o, L->level - 1, L->ix >> 1, L->iy >> 1);
         if (kp >= 0) {
             double *s = pat(o, o->q, kp);
             int ox = (L->ix & 1) * (mx / 2), oy = (L->iy & 1) * (mx / 2);
@@ -1110,7 +1269,7 @@ int orc_regrid(Orc *o, int n_new, const int *leaves_new) {
         /* coarsened: all four children must be leaves of the old set */
         int kc[4];
         for (int c = 0; c < 4; c++) {
-            kc[c] = find_leaf(o, L->level + 1, 2 * L->ix + (c & 1), 2 * L->iy + (c >> 1));
+            kc[c] = find_local(o, L->level + 1, 2 * L->ix + (c & 1), 2 * L->iy + (c >> 1));
             if (kc[c] < 0) { orc_destroy(nw); return ERR_ARG; }
         }
         for (int f = 0; f < o->F; f++)
@@ -1124,9 +1283,10 @@ int orc_regrid(Orc *o, int n_new, const int *leaves_new) {
                 }
     }
     /* swap the new mesh in */
-    free(o->lv); free(o->q); free(o->qold); free(o->qhat); free(o->hidx);
+    free(o->lv); free(o->q); free(o->qold); free(o->qhat); free(o->hidx); free(o->ph);
     o->lv = nw->lv; o->q = nw->q; o->qold = nw->qold; o->qhat = nw->qhat; o->hidx = nw->hidx;
-    o->hcap = nw->hcap; o->n = nw->n;
+    o->ph = nw->ph; o->hcap = nw->hcap; o->n = nw->n;
+    free(nw->ori);
     free(nw);
     return 0;
 }
@@ -1177,6 +1337,7 @@ void orc_adjoint_step(Orc *o, int level, double t, double dt, const double *qin,
                       double *lout) {
     int n = o->n, mx = o->mx, m = o->m;
     size_t psz = (size_t)o->N * o->N;
+    if (is_brick(o)) { o->err |= ERR_ARG; return; } /* one block of code 0 */
     orc_set_interior(o, qin);
     orc_ghost_fill(o, level, level, 1.0);
     double *abar = (double *)calloc(n * psz, sizeof(double)); /* adjoint of patch arrays */
@@ -1192,7 +1353,7 @@ void orc_adjoint_step(Orc *o, int level, double t, double dt, const double *qin,
             const OLeaf *P = &o->lv[k];
             int l = P->level;
             double h = 1.0 / (mx << l), lam = dt / h, tm = t + 0.5 * dt;
-            int gx = P->ix * mx, gy = P->iy * mx;
+            int gx = P->ix * mx, gy = P->iy * mx, oc = leaf_code(o, k);
             double *Q = pat(o, o->q, k);
             double *Ab = abar + k * psz;
             memset(Ftb, 0, sizeof(double) * E * E);
@@ -1216,9 +1377,9 @@ void orc_adjoint_step(Orc *o, int level, double t, double dt, const double *qin,
             /* adjoint of the y sweep (it ran second, so it is undone first) */
             for (int i = mx; i >= -1; i--)
                 for (int j = mx; j >= 0; j--) {
-                    double s_ = vel_v(o, l, gx + i, gy + j, tm);
-                    double upr = vel_u(o, l, gx + i + 1, gy + j, tm), upl = vel_u(o, l, gx + i, gy + j, tm);
-                    double umr = vel_u(o, l, gx + i + 1, gy + j - 1, tm), uml = vel_u(o, l, gx + i, gy + j - 1, tm);
+                    double s_ = vel_v(o, oc, l, gx + i, gy + j, tm);
+                    double upr = vel_u(o, oc, l, gx + i + 1, gy + j, tm), upl = vel_u(o, oc, l, gx + i, gy + j, tm);
+                    double umr = vel_u(o, oc, l, gx + i + 1, gy + j - 1, tm), uml = vel_u(o, oc, l, gx + i, gy + j - 1, tm);
                     double Bpsb = -0.5 * lam * (upr > 0 ? upr : 0.0) * EB(Ftb, j, i + 1)
                                   - 0.5 * lam * (upl < 0 ? upl : 0.0) * EB(Ftb, j, i);
                     double Bmsb = -0.5 * lam * (umr > 0 ? umr : 0.0) * EB(Ftb, j - 1, i + 1)
@@ -1246,9 +1407,9 @@ void orc_adjoint_step(Orc *o, int level, double t, double dt, const double *qin,
             /* adjoint of the x sweep */
             for (int j = mx; j >= -1; j--)
                 for (int i = mx; i >= 0; i--) {
-                    double s_ = vel_u(o, l, gx + i, gy + j, tm);
-                    double vpu = vel_v(o, l, gx + i, gy + j + 1, tm), vpd = vel_v(o, l, gx + i, gy + j, tm);
-                    double vmu = vel_v(o, l, gx + i - 1, gy + j + 1, tm), vmd = vel_v(o, l, gx + i - 1, gy + j, tm);
+                    double s_ = vel_u(o, oc, l, gx + i, gy + j, tm);
+                    double vpu = vel_v(o, oc, l, gx + i, gy + j + 1, tm), vpd = vel_v(o, oc, l, gx + i, gy + j, tm);
+                    double vmu = vel_v(o, oc, l, gx + i - 1, gy + j + 1, tm), vmd = vel_v(o, oc, l, gx + i - 1, gy + j, tm);
                     double Apsb = -0.5 * lam * (vpu > 0 ? vpu : 0.0) * EB(Gtb, j + 1, i)
                                   - 0.5 * lam * (vpd < 0 ? vpd : 0.0) * EB(Gtb, j, i);
                     double Amsb = -0.5 * lam * (vmu > 0 ? vmu : 0.0) * EB(Gtb, j + 1, i - 1)

@@ -47,6 +47,9 @@ def lib():
         L.orc_create.restype = C.c_void_p
         L.orc_create.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, ip, C.c_int, dp, C.c_double,
                                  C.c_int, C.c_int, C.c_int, ip, ip]
+        L.orc_create_brick.restype = C.c_void_p
+        L.orc_create_brick.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, ip, C.c_int, dp, C.c_double,
+                                       C.c_int, C.c_int, C.c_int, C.c_int, ip, C.c_int, ip, ip]
         L.orc_destroy.argtypes = [C.c_void_p]
         for name in ("orc_set_interior", "orc_get_interior", "orc_get_full", "orc_set_full",
                      "orc_get_old_interior"):
@@ -102,7 +105,11 @@ class Oracle:
 
     def __init__(self, leaves, mx=8, mbc=2, equation="advection", limiter="mc",
                  bc=("periodic",) * 4, velocity="constant", vel_params=(1.0, 0.5, 0.0),
-                 gravity=1.0, lmin=None, lmax=None):
+                 gravity=1.0, lmin=None, lmax=None, brick=(1, 1), orient=None):
+        """brick: (nbx, nby) unit blocks (Sec. 2.3); orient: one orientation
+        code 0..7 per block, block (bx, by) at bx + nbx * by (None: all 0).
+        Leaves are (level, ix, iy) with block (ix >> level, iy >> level) and
+        the low bits in the block's own indices."""
         L = lib()
         leaves = np.ascontiguousarray(np.asarray(leaves, dtype=np.int32).reshape(-1, 3))
         self.mx, self.mbc, self.N = mx, mbc, mx + 2 * mbc
@@ -112,9 +119,14 @@ class Oracle:
         bca = np.asarray([BC[b] for b in bc], dtype=np.int32)
         vp = np.asarray(list(vel_params) + [0.0] * (3 - len(vel_params)), dtype=np.float64)
         st = C.c_int(0)
-        self._h = L.orc_create(mx, mbc, EQ[equation], LIM[limiter], _ip(bca), VEL[velocity], _dp(vp),
-                               float(gravity), self.lmin, self.lmax, len(leaves), _ip(leaves),
-                               C.byref(st))
+        self.brick = (int(brick[0]), int(brick[1]))
+        self.orient = None if orient is None else np.ascontiguousarray(np.asarray(orient, dtype=np.int32).ravel())
+        if self.orient is not None and self.orient.size != self.brick[0] * self.brick[1]:
+            raise OracleError("one orientation code per block")
+        self._h = L.orc_create_brick(mx, mbc, EQ[equation], LIM[limiter], _ip(bca), VEL[velocity], _dp(vp),
+                                     float(gravity), self.lmin, self.lmax, self.brick[0], self.brick[1],
+                                     None if self.orient is None else _ip(self.orient), len(leaves), _ip(leaves),
+                                     C.byref(st))
         self._cfg = (mx, mbc, equation, limiter, tuple(bc), velocity, tuple(vel_params), gravity)
         if st.value:
             L.orc_destroy(self._h)

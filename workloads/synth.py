@@ -16,6 +16,13 @@ Conventions
   with ``h = 1 / (mx * 2**l)``.  Arrays are indexed ``[j][i]`` (x fastest).
 * Interchange arrays of patch data are ``[nleaves][nfields][mx][mx]`` in the
   order of the leaf list they belong to.
+* A brick is an ``nbx x nby`` arrangement of unit blocks.  In brick
+  coordinates a leaf ``(l, ix, iy)`` has ``0 <= ix < nbx 2**l``,
+  ``0 <= iy < nby 2**l`` and lies in block ``(ix >> l, iy >> l)``.  A block
+  may carry an index orientation code 0..7 (bit 0 exchanges the two index
+  directions, then bit 1 reverses the brick's first and bit 2 its second);
+  leaves and patch data handed to a brick store are in the blocks' own
+  indices (``brick_own_leaves``, ``brick_own_data``).
 """
 from __future__ import annotations
 
@@ -26,11 +33,11 @@ import numpy as np
 # --------------------------------------------------------------------------
 
 
-def uniform_leaves(level: int) -> np.ndarray:
-    """All ``4**level`` quadrants of one level, row-major in (iy, ix)."""
+def uniform_leaves(level: int, brick=(1, 1)) -> np.ndarray:
+    """All quadrants of one level (``4**level`` per block), row-major in (iy, ix)."""
     n = 1 << level
-    iy, ix = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
-    lv = np.full(n * n, level)
+    iy, ix = np.meshgrid(np.arange(n * brick[1]), np.arange(n * brick[0]), indexing="ij")
+    lv = np.full(ix.size, level)
     return np.stack([lv, ix.ravel(), iy.ravel()], axis=1).astype(np.int32)
 
 
@@ -65,11 +72,12 @@ def _neighbour_offsets():
     return [(-1, 0), (1, 0), (0, -1), (0, 1), (-1, -1), (1, -1), (-1, 1), (1, 1)]
 
 
-def balance_leaves(leaves, periodic=(True, True)) -> np.ndarray:
+def balance_leaves(leaves, periodic=(True, True), brick=(1, 1)) -> np.ndarray:
     """Refine leaves until face- and corner-adjacent leaves differ by <= 1 level.
 
     A pure mesh-generation helper used to build input meshes.  Refinement
-    only; the result is a 2:1 balanced leaf set covering the same square.
+    only; the result is a 2:1 balanced leaf set covering the same square
+    (brick, in brick coordinates).
     """
     cur = {tuple(x) for x in np.asarray(leaves).tolist()}
     while True:
@@ -77,7 +85,8 @@ def balance_leaves(leaves, periodic=(True, True)) -> np.ndarray:
         lmax = max(l for l, _, _ in cur)
         # finest-level coverage map: quadrant at lmax -> level of covering leaf
         nf = 1 << lmax
-        cover = np.full((nf, nf), -1, dtype=np.int32)
+        nfx, nfy = nf * brick[0], nf * brick[1]
+        cover = np.full((nfy, nfx), -1, dtype=np.int32)
         for l, ix, iy in by_key:
             s = 1 << (lmax - l)
             cover[iy * s:(iy + 1) * s, ix * s:(ix + 1) * s] = l
@@ -91,14 +100,14 @@ def balance_leaves(leaves, periodic=(True, True)) -> np.ndarray:
                 ys = [y0 - 1] if dy < 0 else ([y0 + s] if dy > 0 else range(y0, y0 + s))
                 for yy in ys:
                     for xx in xs:
-                        if not (0 <= xx < nf):
+                        if not (0 <= xx < nfx):
                             if not periodic[0]:
                                 continue
-                            xx %= nf
-                        if not (0 <= yy < nf):
+                            xx %= nfx
+                        if not (0 <= yy < nfy):
                             if not periodic[1]:
                                 continue
-                            yy %= nf
+                            yy %= nfy
                         if cover[yy, xx] > l + 1:
                             to_refine.add((l, ix, iy))
         if not to_refine:
@@ -138,10 +147,11 @@ def refine_where(predicate, lmin: int, lmax: int, periodic=(True, True)) -> np.n
 
 
 def random_balanced_leaves(seed: int, lmin: int, lmax: int, p_refine=0.35,
-                           periodic=(True, True)) -> np.ndarray:
-    """Random 2:1 balanced leaf set spanning levels lmin..lmax (test meshes)."""
+                           periodic=(True, True), brick=(1, 1)) -> np.ndarray:
+    """Random 2:1 balanced leaf set spanning levels lmin..lmax (test meshes;
+    brick coordinates for a brick)."""
     rng = np.random.default_rng(seed)
-    cur = [tuple(x) for x in uniform_leaves(lmin).tolist()]
+    cur = [tuple(x) for x in uniform_leaves(lmin, brick).tolist()]
     for _ in range(lmax - lmin):
         nxt = []
         for l, ix, iy in cur:
@@ -152,7 +162,79 @@ def random_balanced_leaves(seed: int, lmin: int, lmax: int, p_refine=0.35,
             else:
                 nxt.append((l, ix, iy))
         cur = nxt
-    return balance_leaves(np.asarray(cur, dtype=np.int32), periodic)
+    return balance_leaves(np.asarray(cur, dtype=np.int32), periodic, brick)
+
+
+def replicate_leaves(leaves, brick) -> np.ndarray:
+    """One block's leaf set copied into every block of a brick (brick
+    coordinates, block-major): the replicated weak-scaling layout."""
+    out = []
+    for by in range(brick[1]):
+        for bx in range(brick[0]):
+            for l, ix, iy in np.asarray(leaves).tolist():
+                out.append((l, ix + (bx << l), iy + (by << l)))
+    return np.asarray(out, dtype=np.int32)
+
+
+# --------------------------------------------------------------------------
+# block orientations of a brick (input format conversion only)
+# --------------------------------------------------------------------------
+
+
+def own_to_brick_index(code: int, n: int, a, b):
+    """Block-own index (a, b) -> brick index inside the block, n per side."""
+    p, q = (b, a) if code & 1 else (a, b)
+    x = n - 1 - p if code & 2 else p
+    y = n - 1 - q if code & 4 else q
+    return x, y
+
+
+def brick_to_own_index(code: int, n: int, x, y):
+    """Inverse of own_to_brick_index."""
+    p = n - 1 - x if code & 2 else x
+    q = n - 1 - y if code & 4 else y
+    return (q, p) if code & 1 else (p, q)
+
+
+def brick_own_leaves(leaves, brick, orient) -> np.ndarray:
+    """Leaves in brick coordinates -> the blocks' own coordinates."""
+    out = []
+    for l, ix, iy in np.asarray(leaves).tolist():
+        bx, by, n = ix >> l, iy >> l, 1 << l
+        a, b = brick_to_own_index(int(orient[bx + brick[0] * by]), n, ix - bx * n, iy - by * n)
+        out.append((l, bx * n + a, by * n + b))
+    return np.asarray(out, dtype=np.int32)
+
+
+def _leaf_code(leaf, brick, orient):
+    l, ix, iy = (int(v) for v in leaf)
+    return int(orient[(ix >> l) + brick[0] * (iy >> l)])
+
+
+def brick_own_data(q, leaves, brick, orient, ghosts: int = 0) -> np.ndarray:
+    """Patch arrays ``[n][F][M][M]`` laid out in brick directions -> the
+    blocks' own index directions (M = mx + 2 ghosts; ghost cells map to
+    ghost cells).  Leaves in brick coordinates, same order."""
+    q = np.asarray(q)
+    out = np.empty_like(q)
+    M = q.shape[-1]
+    a, b = np.meshgrid(np.arange(M) - ghosts, np.arange(M) - ghosts, indexing="xy")
+    for k, leaf in enumerate(np.asarray(leaves)):
+        x, y = own_to_brick_index(_leaf_code(leaf, brick, orient), M - 2 * ghosts, a, b)
+        out[k] = q[k][..., y + ghosts, x + ghosts]
+    return out
+
+
+def brick_aligned_data(q, leaves, brick, orient, ghosts: int = 0) -> np.ndarray:
+    """Inverse of brick_own_data."""
+    q = np.asarray(q)
+    out = np.empty_like(q)
+    M = q.shape[-1]
+    x, y = np.meshgrid(np.arange(M) - ghosts, np.arange(M) - ghosts, indexing="xy")
+    for k, leaf in enumerate(np.asarray(leaves)):
+        a, b = brick_to_own_index(_leaf_code(leaf, brick, orient), M - 2 * ghosts, x, y)
+        out[k] = q[k][..., b + ghosts, a + ghosts]
+    return out
 
 
 # --------------------------------------------------------------------------
