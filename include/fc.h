@@ -69,7 +69,10 @@ enum {
     FC_MODE_PERSISTENT_GRAPH = 4 /* the persistent kernel replayed as a graph                      */
 };
 
-/* A quadrant of the single unit-square block: 0 <= ix, iy < 2^level. */
+/* A quadrant: on one unit-square block 0 <= ix, iy < 2^level.  On a brick of
+ * nbx x nby blocks (fc_patchstore_create_brick) 0 <= ix < nbx 2^level,
+ * 0 <= iy < nby 2^level: block (ix >> level, iy >> level), the low bits the
+ * quadrant's coordinates in that block's own indices. */
 typedef struct { int32_t level, ix, iy; } fc_leaf;
 
 typedef struct {
@@ -103,6 +106,27 @@ const char *fc_last_error(void);
  * each input leaf k, its store index.  Host memory only is allocated. */
 fc_status fc_patchstore_create(const fc_config *cfg, int64_t nleaves, const fc_leaf *leaves,
                                fc_patchstore **out, int64_t *perm_out);
+
+/* The same on a multiblock brick (Sec. 2.3): an nbx x nby arrangement of
+ * unit blocks, each a quadtree with its own index orientation.  orient
+ * (host, nbx * nby codes, block (bx, by) at bx + nbx by; NULL: all 0) gives
+ * each block's index directions against the brick's: bit 0 exchanges the
+ * two, then bit 1 reverses the brick's first direction and bit 2 its second
+ * (the eight index transforms of eq. transform, A diagonal or anti-diagonal
+ * with entries +-1).  Leaves are in the blocks' own coordinates (fc_leaf);
+ * patch data is stored and exchanged in each block's own index directions,
+ * and every ghost copy, eq. ghost_coarse average and eq. ghost_fine
+ * interpolation across a block boundary goes through the index transform
+ * between the two patches.  Tiling and 2:1 balance are checked in the
+ * brick's geometry, across block boundaries.  A brick other than one block
+ * of code 0 needs periodic sides and scalar advection at a constant
+ * velocity (vel_params in the brick's directions); fc_adapt_device,
+ * fc_step_uniform and fc_adjoint_step take one block of code 0 only
+ * (FC_ERR_ARG).  Errors: FC_ERR_ARG for nbx or nby < 1, nbx nby > 65536, a
+ * code outside 0..7 or the above; the rest as fc_patchstore_create. */
+fc_status fc_patchstore_create_brick(const fc_config *cfg, int32_t nbx, int32_t nby, const int32_t *orient,
+                                     int64_t nleaves, const fc_leaf *leaves, fc_patchstore **out,
+                                     int64_t *perm_out);
 fc_status fc_patchstore_destroy(fc_patchstore *ps);
 
 /* Sizes of the caller-owned device memory: q_doubles = doubles per patch
@@ -122,6 +146,20 @@ fc_status fc_patchstore_bind(fc_patchstore *ps, double *q0, double *q1, void *wo
 fc_status fc_patchstore_info(const fc_patchstore *ps, int64_t *nleaves, int32_t *min_level,
                              int32_t *max_level);
 fc_status fc_patchstore_leaves(const fc_patchstore *ps, fc_leaf *out);
+
+/* The neighbour records the ghost-gathering kernels read (host copy, for
+ * checks on the host): out[nleaves][12][4] int32 in store order, per patch
+ * the face halves W, W, E, E, S, S, N, N (lower half first) and the corners
+ * SW, SE, NW, NE, each (type, slot, fx, fy).  type bits 0-3: 0 none (a
+ * wall), 1 same size, 2 coarse, 3 fine; bits 4-7 the reflecting walls of
+ * the neighbour; bits 8-10 the orientation code of the index transform A
+ * (bit 0 exchanges i and j, bit 1 negates the first result, bit 2 the
+ * second).  A ghost cell (i, j) of the patch maps into neighbour `slot`'s
+ * own indices as A (i, j) + F (same size: its cell; coarse: the level-l
+ * index inside it, halved for the coarse cell, the parity giving d_k), or
+ * 2 A (i, j) + F (fine: the first of four cells at +{0,1}^2), F = (fx, fy)
+ * (Sec. 2.3, eq. transform). */
+fc_status fc_patchstore_records(const fc_patchstore *ps, int32_t *out);
 
 /* Interior data in input-leaf order, device arrays [nleaves][nfields][mx][mx]
  * (the order of the leaves passed to create or to the last regrid). */

@@ -27,8 +27,8 @@ FC_ERRORS = {-1: "FC_ERR_ARG", -2: "FC_ERR_UNBALANCED", -3: "FC_ERR_GHOST_WIDTH"
              -5: "FC_ERR_CFL", -6: "FC_ERR_STATE", -7: "FC_ERR_CAPACITY", -8: "FC_ERR_COVER",
              -9: "FC_ERR_NONFINITE"}
 
-EXPORTS = ["fc_last_error", "fc_patchstore_create", "fc_patchstore_destroy", "fc_patchstore_sizes",
-           "fc_patchstore_bind", "fc_patchstore_info", "fc_patchstore_leaves", "fc_set_interior",
+EXPORTS = ["fc_last_error", "fc_patchstore_create", "fc_patchstore_create_brick", "fc_patchstore_destroy", "fc_patchstore_sizes",
+           "fc_patchstore_bind", "fc_patchstore_info", "fc_patchstore_leaves", "fc_patchstore_records", "fc_set_interior",
            "fc_get_interior", "fc_get_patches", "fc_ghost_fill", "fc_advance_level",
            "fc_advance_coarse_steps", "fc_advance_adaptive", "fc_advance_level_noalloc", "fc_get_time", "fc_set_time", "fc_tag_refine", "fc_adapt", "fc_adapt_device", "fc_regrid",
            "fc_prepare_steps", "fc_step_uniform", "fc_adjoint_step", "fc_check_device", "fc_autotune", "fc_set_variant", "fc_set_persistent_grid"]
@@ -66,11 +66,14 @@ def lib():
         L.fc_last_error.restype = C.c_char_p
         L.fc_patchstore_create.argtypes = [C.POINTER(Config), C.c_int64, C.POINTER(Leaf), C.POINTER(vp),
                                            C.POINTER(C.c_int64)]
+        L.fc_patchstore_create_brick.argtypes = [C.POINTER(Config), C.c_int32, C.c_int32, C.POINTER(C.c_int32),
+                                                 C.c_int64, C.POINTER(Leaf), C.POINTER(vp), C.POINTER(C.c_int64)]
         L.fc_patchstore_destroy.argtypes = [vp]
         L.fc_patchstore_sizes.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.fc_patchstore_bind.argtypes = [vp, vp, vp, vp, vp]
         L.fc_patchstore_info.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.fc_patchstore_leaves.argtypes = [vp, C.POINTER(Leaf)]
+        L.fc_patchstore_records.argtypes = [vp, C.POINTER(C.c_int32)]
         for f in ("fc_set_interior", "fc_get_interior", "fc_get_patches"):
             getattr(L, f).argtypes = [vp, vp, vp]
         L.fc_ghost_fill.argtypes = [vp, C.c_int32, C.c_int32, C.c_double, vp]
@@ -126,7 +129,10 @@ class PatchStore:
 
     def __init__(self, leaves, mx=32, equation="advection", limiter="mc", bc=("periodic",) * 4,
                  velocity="swirl", vel_params=(1.0, 0.0, 0.0), gravity=1.0, min_level=None, max_level=None,
-                 time_stepping="multirate", capacity=None, cfl_max=0.0):
+                 time_stepping="multirate", capacity=None, cfl_max=0.0, brick=(1, 1), orient=None):
+        """brick, orient: a multiblock brick of brick[0] x brick[1] unit
+        blocks with one orientation code per block (fc_patchstore_create_brick);
+        leaves then lie in the blocks' own coordinates."""
         L = lib()
         arr, n = _leaves_array(leaves)
         lv = np.asarray(leaves, dtype=np.int32).reshape(-1, 3)
@@ -150,7 +156,13 @@ class PatchStore:
         self.min_level, self.max_level = cfg.min_level, cfg.max_level
         h = C.c_void_p()
         perm = (C.c_int64 * n)()
-        _check(L.fc_patchstore_create(C.byref(cfg), n, arr, C.byref(h), perm))
+        ori = None
+        if orient is not None:
+            o = np.ascontiguousarray(np.asarray(orient, dtype=np.int32).ravel())
+            ori = (C.c_int32 * len(o))(*o.tolist())
+        self.brick = (int(brick[0]), int(brick[1]))
+        _check(L.fc_patchstore_create_brick(C.byref(cfg), self.brick[0], self.brick[1], ori, n, arr, C.byref(h),
+                                            perm))
         self._h = h
         self.perm = np.frombuffer(perm, dtype=np.int64).copy()
         qd, wb = C.c_int64(), C.c_int64()

@@ -12,19 +12,27 @@ enum { NB_NONE = 0, NB_SAME = 1, NB_COARSE = 2, NB_FINE = 3 };
 
 // One ghost region (a face half or a corner) of a patch P at level l.
 // type: bits 0-3 the NB_* kind, bits 4-7 the reflecting walls of the covering
-// leaf (PatchInfo::walls of slot `id`; a coarse stencil folds at them).  The
-// covering leaf `id` (a store slot) has its origin at P-local coordinates
-// (ox, oy), measured in level-l cells, periodic images already unwrapped:
-//   SAME:   neighbour-local cell = (i - ox, j - oy)
-//   COARSE: level-l index inside the coarse leaf = (i - ox, j - oy); the
-//           coarse cell is that >> 1, its parity selects d_k
-//   FINE:   fine cells 2 (i - ox) + {0,1}, 2 (j - oy) + {0,1}
+// leaf (PatchInfo::walls of slot `id`; a coarse stencil folds at them), bits
+// 8-10 the orientation code of the index transform A below (Sec. 2.3, eq.
+// transform: bit 0 exchanges the two indices, bit 1 negates the first
+// result, bit 2 the second; 0 between patches of one block).  A P-local
+// index (i, j) (level-l cells, periodic images already unwrapped) maps into
+// the covering leaf `id` (a store slot), in that leaf's own indices, as
+//   SAME:   neighbour cell = A (i, j) + F
+//   COARSE: level-l index inside the coarse leaf = A (i, j) + F; the coarse
+//           cell is that >> 1, its parity selects d_k (in the coarse leaf's
+//           indices)
+//   FINE:   first of the four fine cells = 2 A (i, j) + F, the four at
+//           + {0, 1} in each index (eq. ghost_coarse averages all four)
+// with F = (fx, fy).
 struct NbrRec {
-    int32_t type, id, ox, oy;
+    int32_t type, id, fx, fy;
 };
 
-// Per-patch geometry.  walls: bit 0 x-lo, 1 x-hi, 2 y-lo, 3 y-hi are
-// reflecting walls touching this patch.
+// Per-patch geometry.  level, (ix, iy) in brick coordinates.  walls: bit 0
+// x-lo, 1 x-hi, 2 y-lo, 3 y-hi are reflecting walls touching this patch (in
+// its own indices); bits 8-10 the orientation code of the patch's block (its
+// own index directions against the brick's, as in NbrRec).
 struct PatchInfo {
     int32_t level, ix, iy, walls;
 };

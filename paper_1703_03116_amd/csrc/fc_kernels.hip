@@ -94,6 +94,20 @@ __device__ __forceinline__ void apply_signs(double *v, double su, double sv) {
 __device__ __forceinline__ int rec_kind(const NbrRec &r) { return r.type & 15; }
 __device__ __forceinline__ int rec_walls(const NbrRec &r) { return (r.type >> 4) & 15; }
 
+// The record's index transform (eq. transform): (I, J) = s A (i, j) + F,
+// A from the orientation code in type bits 8-10 (bit 0 exchanges the two
+// indices, bit 1 negates the first result, bit 2 the second), s = 1 for a
+// same-size or coarse neighbour and 2 for the first of a fine neighbour's
+// four cells.  Identity on one block: (i, j) + F.
+__device__ __forceinline__ void rec_map(const NbrRec &r, int i, int j, int s, int &I, int &J) {
+    const int o = r.type >> 8;
+    int a = (o & 1) ? j : i, b = (o & 1) ? i : j;
+    a = (o & 2) ? -a : a;
+    b = (o & 4) ? -b : b;
+    I = s * a + r.fx;
+    J = s * b + r.fy;
+}
+
 // eq. ghost_fine at local (i, j) of a level-l patch whose ghost region is
 // covered by the coarse patch of `rec`: q_c + (1/4)(d_x s_x + d_y s_y), s the
 // minmod of the one-sided differences on the coarse grid, d = +1 for the
@@ -110,7 +124,8 @@ template <int MX, int F, bool PIPE = true>
 __device__ __forceinline__ void coarse_interp(const Ctx &c, const View &w, int l, int i, int j, const NbrRec rec,
                                               double *v) {
     constexpr int N = MX + 2 * MB;
-    const int I = i - rec.ox, J = j - rec.oy;
+    int I, J;
+    rec_map(rec, i, j, 1, I, J);  // fine-level index inside the coarse leaf, in its own indices
     const int ic = I >> 1, jc = J >> 1;
     const double dx = (I & 1) ? 1.0 : -1.0, dy = (J & 1) ? 1.0 : -1.0;
     const int C = rec.id, lc = l - 1, cw = rec_walls(rec);
@@ -137,9 +152,11 @@ __device__ __forceinline__ void coarse_interp(const Ctx &c, const View &w, int l
         fine[n] = !in[n] && kind == NB_FINE;
         bad[n] = !in[n] && kind != NB_SAME && kind != NB_FINE;
         const int slot = (in[n] || bad[n]) ? C : nr[n].id;
-        const int ci = in[n] ? ni[n] : (bad[n] ? 0 : ni[n] - nr[n].ox);
-        const int cj = in[n] ? nj[n] : (bad[n] ? 0 : nj[n] - nr[n].oy);
-        k[n] = fine[n] ? qidx(c.cap, N, 0, slot, 2 * ci, 2 * cj) : qidx(c.cap, N, 0, slot, ci, cj);
+        int ci, cj;
+        rec_map(nr[n], ni[n], nj[n], fine[n] ? 2 : 1, ci, cj);
+        ci = in[n] ? ni[n] : (bad[n] ? 0 : ci);
+        cj = in[n] ? nj[n] : (bad[n] ? 0 : cj);
+        k[n] = qidx(c.cap, N, 0, slot, ci, cj);
         if (bad[n]) atomicOr(c.err, 2);
     }
     const uint32_t kc = qidx(c.cap, N, 0, C, ic, jc);
@@ -208,10 +225,13 @@ __device__ __forceinline__ void ghost_cell_rec(const Ctx &c, const View &w, int 
                                                double *v) {
     const int kind = rec_kind(rec);
     if (kind == NB_SAME) {
+        int a, b;
+        rec_map(rec, i, j, 1, a, b);
 #pragma unroll
-        for (int f = 0; f < F; f++) v[f] = read_state<MX>(c, w, rec.id, l, i - rec.ox, j - rec.oy, f);
+        for (int f = 0; f < F; f++) v[f] = read_state<MX>(c, w, rec.id, l, a, b, f);
     } else if (kind == NB_FINE) {
-        const int li = 2 * (i - rec.ox), lj = 2 * (j - rec.oy);
+        int li, lj;
+        rec_map(rec, i, j, 2, li, lj);
 #pragma unroll
         for (int f = 0; f < F; f++)
             v[f] = 0.25 * (read_state<MX>(c, w, rec.id, l + 1, li, lj, f) + read_state<MX>(c, w, rec.id, l + 1, li + 1, lj, f) +
@@ -463,10 +483,13 @@ __device__ __forceinline__ void fetch_velocity(const Ctx &c, int l, int gx, int 
 // over the x-edges of the interior rows is max|ux| max|uy| exactly
 // (likewise for v).  The factors are at hand here, while the tile's loads
 // are still in flight; s.cfl receives the unscaled maximum.  (The lanes
-// k0 .. k0+MX+1 lie in one wave for every launch variant.)
+// k0 .. k0+MX+1 lie in one wave for every launch variant.)  A constant
+// velocity is given in the brick's directions; `orient` (the block's
+// orientation code) turns it into the patch's own: a reversed brick
+// direction negates its component, exchanged directions exchange them.
 template <int MX>
 __device__ __forceinline__ void put_velocity(const Ctx &c, ScalarSmem<MX> &s, double t, double dt,
-                                             const double *tdev, int k0, const VelRegs &v) {
+                                             const double *tdev, int k0, const VelRegs &v, int orient = 0) {
     const int k = (int)threadIdx.x - k0;
     if ((int)threadIdx.x / 64 != k0 / 64) return;
     double ux = 0.0, uy = 0.0, vy = 0.0, vx = 0.0;
@@ -479,7 +502,9 @@ __device__ __forceinline__ void put_velocity(const Ctx &c, ScalarSmem<MX> &s, do
             uy = v.cy * ct;
             vx = -(v.cx * ct);
         } else {
-            ux = c.vel_u; vy = c.vel_v;
+            const double bu = (orient & 2) ? -c.vel_u : c.vel_u, bv = (orient & 4) ? -c.vel_v : c.vel_v;
+            ux = (orient & 1) ? bv : bu;
+            vy = (orient & 1) ? bu : bv;
             uy = 1.0;
             vx = 1.0;
         }
@@ -495,10 +520,10 @@ __device__ __forceinline__ void put_velocity(const Ctx &c, ScalarSmem<MX> &s, do
 
 template <int MX>
 __device__ void load_velocity(const Ctx &c, ScalarSmem<MX> &s, int l, int gx, int gy, double t, double dt,
-                              const double *tdev, int k0) {
+                              const double *tdev, int k0, int orient = 0) {
     VelRegs v;
     fetch_velocity<MX>(c, l, gx, gy, tdev, k0, v);
-    put_velocity<MX>(c, s, t, dt, tdev, k0, v);
+    put_velocity<MX>(c, s, t, dt, tdev, k0, v, orient);
 }
 
 // One segment of one interior line: edges e0 .. e0+SEG (edge e lies between
@@ -706,7 +731,7 @@ __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, 
             if (tid + v * NT < NG) s.q[(gj[v] + MB) * NP + gi[v] + MB] = gv[v];
     } else if (!FUSED) {
         const PatchInfo P = c.info[p];
-        load_velocity<MX>(c, s, l, P.ix * MX, P.iy * MX, t, dt, tdev, NI);
+        load_velocity<MX>(c, s, l, P.ix * MX, P.iy * MX, t, dt, tdev, NI, P.walls >> 8);
         for (int k = tid; k < N * N / 2; k += NT) {
             const int i = 2 * (k % (N / 2)), j = k / (N / 2);
             const double2 v = *reinterpret_cast<const double2 *>(&in[base + j * N + i]);
@@ -777,7 +802,7 @@ __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, 
             // in LDS so that no register holds it across the step)
             const double sold = (slot && tid == NT - 1) ? __longlong_as_double((long long)*slot) : 0.0;
             const PatchInfo P = c.info[p];
-            load_velocity<MX>(c, s, l, P.ix * MX, P.iy * MX, t, dt, tdev, NI);
+            load_velocity<MX>(c, s, l, P.ix * MX, P.iy * MX, t, dt, tdev, NI, P.walls >> 8);
             if (slot && tid == NT - 1) s.red[15] = sold;
 #pragma unroll
             for (int v = 0; v < NV; v++) {
@@ -787,7 +812,7 @@ __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, 
                     s.q[(j + MB) * NP + i + MB + 1] = iv[v].y;
                 }
             }
-            if (P.walls == 0) {
+            if ((P.walls & 15) == 0) {
 #pragma unroll
                 for (int v = 0; v < NGH; v++) {
                     if (g0 + v * NT < NG) {

@@ -87,16 +87,21 @@ constexpr int MBK = 2;  // ghost layers the kernels use
 constexpr int kAdaptMaxLevel = 10;
 static_assert(sizeof(fc_leaf) == 3 * sizeof(int32_t), "leaf lists cross the ABI as (level, ix, iy) int32 triples");
 
+// Leaves inside the library are in brick coordinates: a brick of nbx x nby
+// unit blocks (one block: the unit square), level-l quadrant (ix, iy) with
+// 0 <= ix < nbx 2^l, 0 <= iy < nby 2^l.  Blocks may have their own index
+// orientation (Sec. 2.3); leaves cross the ABI in the blocks' own
+// coordinates and are converted at the boundary (to_brick / to_own).
 struct Mesh {
     int mx = 0;
+    int nbx = 1, nby = 1;
     int bc[4] = {0, 0, 0, 0};
     std::vector<fc_leaf> lv;                 // store order
     std::unordered_map<uint64_t, int> at;    // (level, ix, iy) -> slot
 
     int find(int l, int ix, int iy) const {
         if (l < 0 || l > 30) return -1;
-        const int nq = 1 << l;
-        if (ix < 0 || iy < 0 || ix >= nq || iy >= nq) return -1;
+        if (ix < 0 || iy < 0 || ix >= (nbx << l) || iy >= (nby << l)) return -1;
         auto it = at.find(key3(l, ix, iy));
         return it == at.end() ? -1 : it->second;
     }
@@ -107,7 +112,7 @@ struct Mesh {
     }
     // 2:1 balance over faces and corners, with periodic wrap where periodic
     bool balanced_at(const fc_leaf &L) const {
-        const int lf = L.level + 2, nf = 1 << lf, x0 = L.ix * 4, y0 = L.iy * 4;
+        const int lf = L.level + 2, nfx = nbx << lf, nfy = nby << lf, x0 = L.ix * 4, y0 = L.iy * 4;
         for (int dy = -1; dy <= 1; dy++)
             for (int dx = -1; dx <= 1; dx++) {
                 if (!dx && !dy) continue;
@@ -116,13 +121,13 @@ struct Mesh {
                 for (int yy = ya; yy <= yb; yy++)
                     for (int xx = xa; xx <= xb; xx++) {
                         int X = xx, Y = yy;
-                        if (X < 0 || X >= nf) {
+                        if (X < 0 || X >= nfx) {
                             if (bc[X < 0 ? 0 : 1] != FC_BC_PERIODIC) continue;
-                            X = (X + nf) % nf;
+                            X = (X + nfx) % nfx;
                         }
-                        if (Y < 0 || Y >= nf) {
+                        if (Y < 0 || Y >= nfy) {
                             if (bc[Y < 0 ? 2 : 3] != FC_BC_PERIODIC) continue;
-                            Y = (Y + nf) % nf;
+                            Y = (Y + nfy) % nfy;
                         }
                         if (!covered_le(lf, X, Y, L.level + 1)) return false;
                     }
@@ -140,6 +145,8 @@ struct Mesh {
 fc_status validate(const Mesh &m, const std::vector<fc_leaf> &L) {
     Mesh t;
     t.mx = m.mx;
+    t.nbx = m.nbx;
+    t.nby = m.nby;
     std::copy(m.bc, m.bc + 4, t.bc);
     t.lv = L;
     t.index();
@@ -147,13 +154,14 @@ fc_status validate(const Mesh &m, const std::vector<fc_leaf> &L) {
     long double area = 0;
     for (const auto &q : L) {
         if (q.level < 0 || q.level > 20) return fail(FC_ERR_ARG, "leaf level out of range");
-        const int nq = 1 << q.level;
-        if (q.ix < 0 || q.iy < 0 || q.ix >= nq || q.iy >= nq) return fail(FC_ERR_ARG, "leaf coordinates out of range");
+        if (q.ix < 0 || q.iy < 0 || q.ix >= (m.nbx << q.level) || q.iy >= (m.nby << q.level))
+            return fail(FC_ERR_ARG, "leaf coordinates out of range");
         for (int a = 1; a <= q.level; a++)
             if (t.find(q.level - a, q.ix >> a, q.iy >> a) >= 0) return fail(FC_ERR_COVER, "overlapping leaves");
         area += ldexpl(1.0L, -2 * q.level);
     }
-    if (fabsl(area - 1.0L) > 1e-15L) return fail(FC_ERR_COVER, "leaves do not tile the unit square");
+    if (fabsl(area - (long double)m.nbx * m.nby) > 1e-15L)
+        return fail(FC_ERR_COVER, "leaves do not tile the unit square (the brick)");
     for (const auto &q : L)
         if (!t.balanced_at(q)) return fail(FC_ERR_UNBALANCED, "leaves are not 2:1 balanced");
     return FC_OK;
@@ -165,6 +173,11 @@ struct fc_patchstore {
     fc_config cfg;
     int mx = 0, N = 0, F = 1;
     Mesh mesh;
+    // brick of mesh.nbx x mesh.nby blocks: orientation code per block
+    // (bx + nbx by); `multiblock` unless the brick is one block of code 0
+    // (then the one-block fast paths are off)
+    std::vector<int> ori;
+    bool multiblock = false;
     std::vector<int32_t> slot_of_leaf, leaf_of_slot;  // input order <-> store order
     std::vector<PatchInfo> info;
     std::vector<NbrRec> nbr;
@@ -221,6 +234,62 @@ std::vector<int> store_order(const std::vector<fc_leaf> &input) {
     return order;
 }
 
+// ---- block orientations (Sec. 2.3) ----------------------------------------
+// Code bits: 0 exchanges a block's two index directions, then 1 reverses the
+// brick's first direction and 2 its second.  Own index (a, b) of a block with
+// n cells (or quadrants) per side <-> brick index inside the block; both maps
+// extend linearly beyond [0, n) (ghost cells).
+inline void own_to_brick(int code, int n, int a, int b, int &x, int &y) {
+    const int p = (code & 1) ? b : a, q = (code & 1) ? a : b;
+    x = (code & 2) ? n - 1 - p : p;
+    y = (code & 4) ? n - 1 - q : q;
+}
+inline void brick_to_own(int code, int n, int x, int y, int &a, int &b) {
+    const int p = (code & 2) ? n - 1 - x : x, q = (code & 4) ? n - 1 - y : y;
+    a = (code & 1) ? q : p;
+    b = (code & 1) ? p : q;
+}
+int block_code(const fc_patchstore *ps, int l, int ix, int iy) {
+    const int bx = ix >> l, by = iy >> l;
+    if (ps->ori.empty() || bx < 0 || by < 0 || bx >= ps->mesh.nbx || by >= ps->mesh.nby) return 0;
+    return ps->ori[bx + ps->mesh.nbx * by];
+}
+// a leaf in own coordinates -> brick coordinates, and back (same block)
+fc_leaf to_brick(const fc_patchstore *ps, const fc_leaf &q) {
+    const int n = 1 << q.level, bx = q.ix >> q.level, by = q.iy >> q.level;
+    int x, y;
+    own_to_brick(block_code(ps, q.level, q.ix, q.iy), n, q.ix - bx * n, q.iy - by * n, x, y);
+    return fc_leaf{q.level, bx * n + x, by * n + y};
+}
+fc_leaf to_own(const fc_patchstore *ps, const fc_leaf &q) {
+    const int n = 1 << q.level, bx = q.ix >> q.level, by = q.iy >> q.level;
+    int a, b;
+    brick_to_own(block_code(ps, q.level, q.ix, q.iy), n, q.ix - bx * n, q.iy - by * n, a, b);
+    return fc_leaf{q.level, bx * n + a, by * n + b};
+}
+// Brick index of cell (i, j) of leaf P (brick coordinates), counted in P's
+// own indices from its first cell, at the resolution of level r >= P.level.
+void cell_to_brick(const fc_patchstore *ps, const fc_leaf &P, int r, int i, int j, int64_t &X, int64_t &Y) {
+    const fc_leaf own = to_own(ps, P);
+    const int l = P.level, sc = ps->mx << (r - l), n = ps->mx << r;
+    const int bx = P.ix >> l, by = P.iy >> l;
+    int x, y;
+    own_to_brick(block_code(ps, l, P.ix, P.iy), n, (own.ix - (bx << l)) * sc + i, (own.iy - (by << l)) * sc + j, x, y);
+    X = (int64_t)bx * n + x;
+    Y = (int64_t)by * n + y;
+}
+// the inverse for leaf N: its own index of the level-r cell at brick index
+// (X, Y) (in N's block or a linear extension of it)
+void brick_to_cell(const fc_patchstore *ps, const fc_leaf &N, int r, int64_t X, int64_t Y, int &i, int &j) {
+    const fc_leaf own = to_own(ps, N);
+    const int l = N.level, sc = ps->mx << (r - l), n = ps->mx << r;
+    const int bx = N.ix >> l, by = N.iy >> l;
+    int a, b;
+    brick_to_own(block_code(ps, l, N.ix, N.iy), n, (int)(X - (int64_t)bx * n), (int)(Y - (int64_t)by * n), a, b);
+    i = a - (own.ix - (bx << l)) * sc;
+    j = b - (own.iy - (by << l)) * sc;
+}
+
 // store order, level ranges, patch info and neighbour records
 void build_metadata(fc_patchstore *ps, const std::vector<fc_leaf> &input) {
     const int n = (int)input.size();
@@ -252,40 +321,60 @@ void build_metadata(fc_patchstore *ps, const std::vector<fc_leaf> &input) {
         if (P.ix == 0 && bc[0] == FC_BC_REFLECT) walls |= 1;
         if (P.ix == nq - 1 && bc[1] == FC_BC_REFLECT) walls |= 2;
         if (P.iy == 0 && bc[2] == FC_BC_REFLECT) walls |= 4;
-        if (P.iy == nq - 1 && bc[3] == FC_BC_REFLECT) walls |= 8;
-        ps->info[s] = PatchInfo{P.level, P.ix, P.iy, walls};
+        if (P.iy == nq - 1 && bc[3] == FC_BC_REFLECT) walls |= 8;  // (walls only on one block)
+        ps->info[s] = PatchInfo{P.level, P.ix, P.iy, walls | (block_code(ps, P.level, P.ix, P.iy) << 8)};
     }
     for (int s = 0; s < n; s++) {
         const fc_leaf P = ps->mesh.lv[s];
-        const int l = P.level, nl = mx << l;
+        const int l = P.level;
+        const int64_t W = (int64_t)ps->mesh.nbx * (mx << l), H = (int64_t)ps->mesh.nby * (mx << l);
         for (int r = 0; r < FC_NREC; r++) {
             const int ri = rep[r][0], rj = rep[r][1];
-            int I = P.ix * mx + ri, J = P.iy * mx + rj;
+            int64_t X0, Y0;
+            cell_to_brick(ps, P, l, ri, rj, X0, Y0);
+            int64_t I = X0, J = Y0;
             bool wall = false;
-            if (I < 0 || I >= nl) { if (bc[I < 0 ? 0 : 1] == FC_BC_PERIODIC) I = (I + nl) % nl; else wall = true; }
-            if (J < 0 || J >= nl) { if (bc[J < 0 ? 2 : 3] == FC_BC_PERIODIC) J = (J + nl) % nl; else wall = true; }
+            if (I < 0 || I >= W) { if (bc[I < 0 ? 0 : 1] == FC_BC_PERIODIC) I = (I + W) % W; else wall = true; }
+            if (J < 0 || J >= H) { if (bc[J < 0 ? 2 : 3] == FC_BC_PERIODIC) J = (J + H) % H; else wall = true; }
             if (wall) continue;
             // point location: the level-l quadrant, its parent, or a child
-            int type = NB_NONE, id = -1, ext = 0, ox = 0, oy = 0;
-            if ((id = ps->mesh.find(l, I / mx, J / mx)) >= 0) {
-                type = NB_SAME; ext = mx;
-                ox = ps->mesh.lv[id].ix * mx; oy = ps->mesh.lv[id].iy * mx;
-            } else if ((id = ps->mesh.find(l - 1, (I / mx) >> 1, (J / mx) >> 1)) >= 0) {
-                type = NB_COARSE; ext = 2 * mx;
-                ox = ps->mesh.lv[id].ix * 2 * mx; oy = ps->mesh.lv[id].iy * 2 * mx;
-            } else if ((id = ps->mesh.find(l + 1, (2 * I) / mx, (2 * J) / mx)) >= 0) {
-                type = NB_FINE; ext = mx / 2;
-                ox = ps->mesh.lv[id].ix * (mx / 2); oy = ps->mesh.lv[id].iy * (mx / 2);
-            } else {
-                continue;  // cannot happen on a validated mesh
+            int kind = NB_NONE, id = -1;
+            if ((id = ps->mesh.find(l, (int)(I / mx), (int)(J / mx))) >= 0) kind = NB_SAME;
+            else if ((id = ps->mesh.find(l - 1, (int)(I / mx) >> 1, (int)(J / mx) >> 1)) >= 0) kind = NB_COARSE;
+            else if ((id = ps->mesh.find(l + 1, (int)(2 * I / mx), (int)(2 * J / mx))) >= 0) kind = NB_FINE;
+            else continue;  // cannot happen on a validated mesh
+            // The index transform of eq. transform, P's own indices -> the
+            // neighbour's own, taken through the brick's indices (with the
+            // periodic image of the representative cell) at three points: a
+            // fine neighbour's at the fine resolution, the others' at P's.
+            const int sc = kind == NB_FINE ? 2 : 1, rr = l + sc - 1;
+            const int64_t dX = (I - X0) * sc, dY = (J - Y0) * sc;
+            const fc_leaf Nb = ps->mesh.lv[id];
+            const int pi[3] = {sc * ri, sc * ri + 1, sc * ri}, pj[3] = {sc * rj, sc * rj, sc * rj + 1};
+            int g[3][2];
+            for (int t = 0; t < 3; t++) {
+                int64_t X, Y;
+                cell_to_brick(ps, P, rr, pi[t], pj[t], X, Y);
+                brick_to_cell(ps, Nb, rr, X + dX, Y + dY, g[t][0], g[t][1]);
             }
-            ox -= P.ix * mx;
-            oy -= P.iy * mx;
-            while (ri - ox < 0) ox -= nl;
-            while (ri - ox >= ext) ox += nl;
-            while (rj - oy < 0) oy -= nl;
-            while (rj - oy >= ext) oy += nl;
-            ps->nbr[(size_t)s * FC_NREC + r] = NbrRec{type | (ps->info[id].walls << 4), id, ox, oy};
+            const int a00 = g[1][0] - g[0][0], a10 = g[1][1] - g[0][1];
+            const int a01 = g[2][0] - g[0][0], a11 = g[2][1] - g[0][1];
+            int code;
+            if (a01 == 0 && a10 == 0 && std::abs(a00) == 1 && std::abs(a11) == 1)
+                code = (a00 < 0 ? 2 : 0) | (a11 < 0 ? 4 : 0);
+            else if (a00 == 0 && a11 == 0 && std::abs(a01) == 1 && std::abs(a10) == 1)
+                code = 1 | (a01 < 0 ? 2 : 0) | (a10 < 0 ? 4 : 0);
+            else
+                continue;  // cannot happen: orientations compose to a signed permutation
+            const int ta = (code & 1) ? pj[0] : pi[0], tb = (code & 1) ? pi[0] : pj[0];
+            int fx = g[0][0] - ((code & 2) ? -ta : ta), fy = g[0][1] - ((code & 4) ? -tb : tb);
+            if (kind == NB_FINE) {
+                // the first of the four fine cells has the smallest index in
+                // each direction: one less where A negates
+                if (code & 2) fx -= 1;
+                if (code & 4) fy -= 1;
+            }
+            ps->nbr[(size_t)s * FC_NREC + r] = NbrRec{kind | ((ps->info[id].walls & 15) << 4) | (code << 8), id, fx, fy};
         }
     }
 }
@@ -317,7 +406,7 @@ void layout_workspace(fc_patchstore *ps) {
     ps->off_cflv = o; o = align256(o + sizeof(double));
     ps->off_save = o;  // interiors kept across a coarse step that may be rejected
     if (ps->cfg.cfl_max > 0) o = align256(o + sizeof(double) * cap * ps->F * ps->mx * ps->mx);
-    ps->dev_adapt = ps->cfg.max_level <= kAdaptMaxLevel;
+    ps->dev_adapt = ps->cfg.max_level <= kAdaptMaxLevel && !ps->multiblock;
     if (ps->dev_adapt) {
         const size_t cells = (size_t)1 << (2 * ps->cfg.max_level);
         ps->off_own = o; o = align256(o + sizeof(int32_t) * cells);
@@ -368,7 +457,7 @@ Ctx make_ctx(const fc_patchstore *ps) {
     const bool per = ps->cfg.bc[0] == FC_BC_PERIODIC && ps->cfg.bc[2] == FC_BC_PERIODIC;
     for (int l = 0; l < FC_MAXLEV; l++) {
         c.lstart[l] = ps->lr.start[l];
-        if (per && l < 16 && ps->lr.count[l] == (1 << (2 * l))) c.complete |= 1u << l;
+        if (per && !ps->multiblock && l < 16 && ps->lr.count[l] == (1 << (2 * l))) c.complete |= 1u << l;
     }
     return c;
 }
@@ -560,8 +649,26 @@ const char *fc_last_error(void) { return g_err.c_str(); }
 
 fc_status fc_patchstore_create(const fc_config *cfg, int64_t nleaves, const fc_leaf *leaves, fc_patchstore **out,
                                int64_t *perm_out) {
+    return fc_patchstore_create_brick(cfg, 1, 1, nullptr, nleaves, leaves, out, perm_out);
+}
+
+fc_status fc_patchstore_create_brick(const fc_config *cfg, int32_t nbx, int32_t nby, const int32_t *orient,
+                                     int64_t nleaves, const fc_leaf *leaves, fc_patchstore **out, int64_t *perm_out) {
     if (!cfg || !out || (nleaves > 0 && !leaves) || nleaves <= 0) return fail(FC_ERR_ARG, "bad arguments");
     *out = nullptr;
+    if (nbx < 1 || nby < 1 || (int64_t)nbx * nby > (1 << 16)) return fail(FC_ERR_ARG, "brick needs 1 <= nbx, nby and nbx * nby <= 65536");
+    bool multi = nbx * nby > 1;
+    if (orient)
+        for (int b = 0; b < nbx * nby; b++) {
+            if (orient[b] < 0 || orient[b] > 7) return fail(FC_ERR_ARG, "orientation codes are 0 .. 7");
+            if (orient[b] != 0) multi = true;
+        }
+    if (multi) {
+        for (int s = 0; s < 4; s++)
+            if (cfg->bc[s] != FC_BC_PERIODIC) return fail(FC_ERR_ARG, "a brick takes periodic sides");
+        if (cfg->equation != FC_EQ_ADVECTION || cfg->velocity != FC_VEL_CONSTANT)
+            return fail(FC_ERR_ARG, "a brick takes scalar advection at a constant velocity");
+    }
     if (cfg->mx != 8 && cfg->mx != 16 && cfg->mx != 32) return fail(FC_ERR_ARG, "mx must be 8, 16 or 32");
     if (4 * cfg->mbc > cfg->mx || cfg->mbc < 2) return fail(FC_ERR_GHOST_WIDTH, "need 2 <= mbc <= mx/4 (Prop. 2.1)");
     if (cfg->mbc != 2) return fail(FC_ERR_ARG, "the kernels use exactly 2 ghost layers");
@@ -585,20 +692,28 @@ fc_status fc_patchstore_create(const fc_config *cfg, int64_t nleaves, const fc_l
     if (cfg->velocity == FC_VEL_SWIRL && !(cfg->vel_params[0] > 0)) return fail(FC_ERR_ARG, "swirl period must be > 0");
     if (!(cfg->cfl_max >= 0.0)) return fail(FC_ERR_ARG, "cfl_max must be >= 0 (0: not checked)");
     std::vector<fc_leaf> L(leaves, leaves + nleaves);
-    for (const auto &q : L)
+    for (const auto &q : L) {
         if (q.level < cfg->min_level || q.level > cfg->max_level) return fail(FC_ERR_ARG, "leaf level outside [min_level, max_level]");
-    Mesh m;
-    m.mx = cfg->mx;
-    std::copy(cfg->bc, cfg->bc + 4, m.bc);
-    fc_status st = validate(m, L);
-    if (st != FC_OK) return st;
+        if (q.ix < 0 || q.iy < 0 || q.ix >= (nbx << q.level) || q.iy >= (nby << q.level))
+            return fail(FC_ERR_ARG, "leaf coordinates out of range");
+    }
     fc_patchstore *ps = new fc_patchstore();
     ps->cfg = *cfg;
     ps->mx = cfg->mx;
     ps->N = cfg->mx + 2 * MBK;
     ps->F = nfields(*cfg);
     ps->mesh.mx = cfg->mx;
+    ps->mesh.nbx = nbx;
+    ps->mesh.nby = nby;
     std::copy(cfg->bc, cfg->bc + 4, ps->mesh.bc);
+    if (orient) ps->ori.assign(orient, orient + nbx * nby);
+    ps->multiblock = multi;
+    for (auto &q : L) q = to_brick(ps, q);  // leaves arrive in the blocks' own coordinates
+    fc_status st = validate(ps->mesh, L);
+    if (st != FC_OK) {
+        delete ps;
+        return st;
+    }
     build_metadata(ps, L);
     if (cfg->time_stepping == FC_STEP_GLOBAL) ps->sched.push_back(SchedEntry{-1, 0, 0.0, 1.0, 1.0});
     else gen_sched(ps->sched, cfg->min_level, cfg->max_level, 0.0, 1.0, 1.0);
@@ -661,7 +776,16 @@ fc_status fc_patchstore_info(const fc_patchstore *ps, int64_t *nleaves, int32_t 
 
 fc_status fc_patchstore_leaves(const fc_patchstore *ps, fc_leaf *out) {
     if (!ps || !out) return fail(FC_ERR_ARG, "bad arguments");
-    std::copy(ps->mesh.lv.begin(), ps->mesh.lv.end(), out);
+    for (size_t k = 0; k < ps->mesh.lv.size(); k++) out[k] = to_own(ps, ps->mesh.lv[k]);
+    return FC_OK;
+}
+
+fc_status fc_patchstore_records(const fc_patchstore *ps, int32_t *out) {
+    if (!ps || !out) return fail(FC_ERR_ARG, "bad arguments");
+    for (size_t k = 0; k < ps->nbr.size(); k++) {
+        const NbrRec &r = ps->nbr[k];
+        out[4 * k] = r.type; out[4 * k + 1] = r.id; out[4 * k + 2] = r.fx; out[4 * k + 3] = r.fy;
+    }
     return FC_OK;
 }
 
@@ -998,13 +1122,13 @@ fc_status fc_adapt(const fc_patchstore *ps, const int8_t *tags, int32_t smooth, 
         int m = target[s];
         if (smooth) {
             const fc_leaf L = ps->mesh.lv[s];
-            const int lq = L.level + 1, nq = 1 << lq;
+            const int lq = L.level + 1, nqx = ps->mesh.nbx << lq, nqy = ps->mesh.nby << lq;
             for (int dy = -1; dy <= 2; dy++)
                 for (int dx = -1; dx <= 2; dx++) {
                     if (dx >= 0 && dx <= 1 && dy >= 0 && dy <= 1) continue;
                     int X = 2 * L.ix + dx, Y = 2 * L.iy + dy;
-                    if (X < 0 || X >= nq) { if (ps->cfg.bc[X < 0 ? 0 : 1] != FC_BC_PERIODIC) continue; X = (X + nq) % nq; }
-                    if (Y < 0 || Y >= nq) { if (ps->cfg.bc[Y < 0 ? 2 : 3] != FC_BC_PERIODIC) continue; Y = (Y + nq) % nq; }
+                    if (X < 0 || X >= nqx) { if (ps->cfg.bc[X < 0 ? 0 : 1] != FC_BC_PERIODIC) continue; X = (X + nqx) % nqx; }
+                    if (Y < 0 || Y >= nqy) { if (ps->cfg.bc[Y < 0 ? 2 : 3] != FC_BC_PERIODIC) continue; Y = (Y + nqy) % nqy; }
                     for (int l2 = lq; l2 >= 0; l2--) {
                         const int o = ps->mesh.find(l2, X >> (lq - l2), Y >> (lq - l2));
                         if (o >= 0) { m = std::max(m, target[o]); break; }
@@ -1039,10 +1163,13 @@ fc_status fc_adapt(const fc_patchstore *ps, const int8_t *tags, int32_t smooth, 
             res.push_back(L);
         }
     }
-    // 2:1 balance by refinement
+    // 2:1 balance by refinement (brick coordinates; quadtree families are
+    // the same sets in a block's own coordinates)
     for (;;) {
         Mesh m;
         m.mx = ps->mx;
+        m.nbx = ps->mesh.nbx;
+        m.nby = ps->mesh.nby;
         std::copy(ps->cfg.bc, ps->cfg.bc + 4, m.bc);
         m.lv = res;
         m.index();
@@ -1059,6 +1186,7 @@ fc_status fc_adapt(const fc_patchstore *ps, const int8_t *tags, int32_t smooth, 
         res.swap(nx);
         if (!changed) break;
     }
+    for (auto &q : res) q = to_own(ps, q);
     std::sort(res.begin(), res.end(), [](const fc_leaf &a, const fc_leaf &b) {
         if (a.level != b.level) return a.level < b.level;
         if (a.iy != b.iy) return a.iy < b.iy;
@@ -1075,7 +1203,7 @@ fc_status fc_adapt_device(fc_patchstore *ps, const int8_t *tags_dev, int32_t smo
     fc_status r = check_bound(ps);
     if (r != FC_OK) return r;
     if (!tags_dev || !out || !n_out) return fail(FC_ERR_ARG, "bad arguments");
-    if (!ps->dev_adapt) return fail(FC_ERR_ARG, "adaptation on the device needs max_level <= 10");
+    if (!ps->dev_adapt) return fail(FC_ERR_ARG, "adaptation on the device needs one block and max_level <= 10");
     hipStream_t s = (hipStream_t)stream;
     const int n = (int)ps->mesh.lv.size(), L = ps->cfg.max_level;
     const int perx = ps->cfg.bc[0] == FC_BC_PERIODIC, pery = ps->cfg.bc[2] == FC_BC_PERIODIC;
@@ -1123,8 +1251,12 @@ fc_status fc_regrid(fc_patchstore *ps, int64_t nleaves, const fc_leaf *new_leave
     if (!new_leaves || nleaves <= 0) return fail(FC_ERR_ARG, "bad arguments");
     if (nleaves > ps->cfg.capacity) return fail(FC_ERR_CAPACITY, "new leaf set exceeds capacity");
     std::vector<fc_leaf> L(new_leaves, new_leaves + nleaves);
-    for (const auto &q : L)
+    for (auto &q : L) {
         if (q.level < ps->cfg.min_level || q.level > ps->cfg.max_level) return fail(FC_ERR_ARG, "leaf level outside range");
+        if (q.ix < 0 || q.iy < 0 || q.ix >= (ps->mesh.nbx << q.level) || q.iy >= (ps->mesh.nby << q.level))
+            return fail(FC_ERR_ARG, "leaf coordinates out of range");
+        q = to_brick(ps, q);  // own -> brick coordinates
+    }
     fc_status r = validate(ps->mesh, L);
     if (r != FC_OK) return r;
     // The transfer plan, built against the new leaves in store order before
@@ -1141,11 +1273,16 @@ fc_status fc_regrid(fc_patchstore *ps, int64_t nleaves, const fc_leaf *new_leave
         if ((o = ps->mesh.find(q.level, q.ix, q.iy)) >= 0) {
             tr.kind = TR_COPY; tr.src[0] = o;
         } else if ((o = ps->mesh.find(q.level - 1, q.ix >> 1, q.iy >> 1)) >= 0) {
-            tr.kind = TR_REFINE; tr.src[0] = o; tr.cx = q.ix & 1; tr.cy = q.iy & 1;
+            // the child's position in its parent's own indices
+            const fc_leaf w = to_own(ps, q);
+            tr.kind = TR_REFINE; tr.src[0] = o; tr.cx = w.ix & 1; tr.cy = w.iy & 1;
         } else {
             tr.kind = TR_COARSEN;
+            const fc_leaf w = to_own(ps, q);
             for (int c = 0; c < 4; c++) {
-                tr.src[c] = ps->mesh.find(q.level + 1, 2 * q.ix + (c & 1), 2 * q.iy + (c >> 1));
+                // child c at own position (c & 1, c >> 1) of the new parent
+                const fc_leaf ch = to_brick(ps, fc_leaf{w.level + 1, 2 * w.ix + (c & 1), 2 * w.iy + (c >> 1)});
+                tr.src[c] = ps->mesh.find(ch.level, ch.ix, ch.iy);
                 if (tr.src[c] < 0) return fail(FC_ERR_ARG, "new leaf is neither old, child nor parent of old leaves");
             }
         }
@@ -1175,6 +1312,7 @@ static fc_status check_uniform_periodic(fc_patchstore *ps, int32_t level, double
     fc_status r = check_bound(ps);
     if (r != FC_OK) return r;
     if (ps->cfg.equation != FC_EQ_ADVECTION) return fail(FC_ERR_ARG, "scalar advection only");
+    if (ps->multiblock) return fail(FC_ERR_ARG, "one block of orientation code 0 only");
     if (level < ps->cfg.min_level || level > ps->cfg.max_level) return fail(FC_ERR_ARG, "bad level");
     if (ps->lr.count[level] != (int)ps->mesh.lv.size()) return fail(FC_ERR_ARG, "needs a uniform mesh at `level`");
     if (!(dt > 0)) return fail(FC_ERR_ARG, "dt must be positive");

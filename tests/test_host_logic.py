@@ -218,3 +218,167 @@ def test_cfl_max_validation(B):
     assert L.fc_advance_adaptive(h, 1.0, 0.9, 2, C.byref(d), 10, None, None, None) == -6
     L.fc_patchstore_destroy(h)
     L.fc_patchstore_destroy(h0)
+
+
+def create_brick(B, leaves, brick, orient, equation=0, velocity=1, **kw):
+    cfg = make_cfg(B, **kw)
+    cfg.equation, cfg.velocity = equation, velocity
+    arr, n = B._leaves_array(leaves)
+    h = C.c_void_p()
+    perm = (C.c_int64 * n)()
+    ori = None if orient is None else (C.c_int32 * len(orient))(*[int(v) for v in orient])
+    st = B.lib().fc_patchstore_create_brick(C.byref(cfg), brick[0], brick[1], ori, n, arr, C.byref(h), perm)
+    return st, h
+
+
+def test_brick_create_validation(B):
+    """A multiblock brick (Sec. 2.3) is checked in the brick's geometry: a
+    level-3 leaf against a level-1 leaf across a block face is unbalanced in
+    every orientation of the finer block; a missing block does not tile;
+    codes outside 0..7, walls, shallow water and the swirl field are
+    refused on a brick."""
+    L = B.lib()
+    base = S.uniform_leaves(1, (2, 1))
+    k = [tuple(v) for v in base.tolist()].index((1, 2, 0))
+    R = S.refine_leaves(base, [k])
+    bad = S.refine_leaves(R, [[tuple(v) for v in R.tolist()].index((2, 4, 0))])
+    good = S.balance_leaves(bad, brick=(2, 1))
+    for code in range(8):
+        st, _ = create_brick(B, S.brick_own_leaves(bad, (2, 1), [0, code]), (2, 1), [0, code], lmin=1, lmax=3)
+        assert st == -2
+        st, h = create_brick(B, S.brick_own_leaves(good, (2, 1), [0, code]), (2, 1), [0, code], lmin=1, lmax=3)
+        assert st == 0
+        L.fc_patchstore_destroy(h)
+    assert create_brick(B, base[base[:, 1] < 2], (2, 1), None, lmin=1, lmax=3)[0] == -8
+    assert create_brick(B, base, (2, 1), [0, 8], lmin=1, lmax=3)[0] == -1
+    assert create_brick(B, base, (0, 1), None, lmin=1, lmax=3)[0] == -1
+    assert create_brick(B, base, (2, 1), None, lmin=1, lmax=3, bc=("reflect",) * 4)[0] == -1
+    assert create_brick(B, base, (2, 1), None, equation=1, velocity=0, lmin=1, lmax=3)[0] == -1
+    assert create_brick(B, base, (2, 1), None, velocity=2, lmin=1, lmax=3)[0] == -1
+    # one block of code 0 is the one-block store
+    st, h = create_brick(B, S.uniform_leaves(1), (1, 1), [0], lmin=1, lmax=3)
+    assert st == 0
+    L.fc_patchstore_destroy(h)
+
+
+@pytest.mark.parametrize("smooth", [0, 1])
+@pytest.mark.parametrize("seed", range(3))
+def test_brick_host_adapt_matches_oracle(B, oracle_lib, seed, smooth):
+    """Host adaptation on a brick of mixed orientations gives the oracle's
+    leaf set (own coordinates, sorted alike); the store reports its leaves in
+    own coordinates too."""
+    brick = (3, 2)
+    lb = S.random_balanced_leaves(seed, 1, 3, brick=brick)
+    orient = list(np.random.default_rng(seed).integers(0, 8, 6))
+    own = S.brick_own_leaves(lb, brick, orient)
+    rng = np.random.default_rng(seed)
+    tags = rng.choice([-1, 0, 1], size=len(own), p=[0.5, 0.3, 0.2]).astype(np.int8)
+    st, h = create_brick(B, own, brick, orient, lmin=1, lmax=4)
+    assert st == 0
+    out = (B.Leaf * len(own))()
+    assert B.lib().fc_patchstore_leaves(h, out) == 0
+    stored = sorted((out[k].level, out[k].ix, out[k].iy) for k in range(len(own)))
+    assert stored == sorted(map(tuple, own.tolist()))
+    cap = 4 * len(own) + 64
+    res = (B.Leaf * cap)()
+    n = C.c_int64()
+    assert B.lib().fc_adapt(h, tags.ctypes.data_as(C.POINTER(C.c_int8)), smooth, res, cap, C.byref(n)) == 0
+    mine = np.array([(res[k].level, res[k].ix, res[k].iy) for k in range(n.value)])
+    o = oracle_lib.Oracle(own, mx=8, lmin=1, lmax=4, brick=brick, orient=orient, velocity="constant")
+    assert np.array_equal(mine, o.adapt(tags, smooth=bool(smooth)))
+    B.lib().fc_patchstore_destroy(h)
+
+
+def _region(i, j, mx):
+    """Neighbour record of ghost cell (i, j): face halves W, E, S, N (lower
+    half first), then corners SW, SE, NW, NE."""
+    rx = 0 if i < 0 else (2 if i >= mx else 1)
+    ry = 0 if j < 0 else (2 if j >= mx else 1)
+    if ry == 1:
+        return (0 if rx == 0 else 2) + (1 if j >= mx // 2 else 0)
+    if rx == 1:
+        return (4 if ry == 0 else 6) + (1 if i >= mx // 2 else 0)
+    return 8 + (1 if rx == 2 else 0) + (2 if ry == 2 else 0)
+
+
+def _minmod(a, b):
+    return 0.0 if a * b <= 0.0 else (a if abs(a) < abs(b) else b)
+
+
+@pytest.mark.parametrize("case", ["one_block", "brick_a", "brick_b", "all8"])
+def test_records_reproduce_the_oracle_fill(B, oracle_lib, case):
+    """The neighbour records the kernels gather through (Sec. 2.3: every
+    ghost index mapped by A (i, j) + F into the neighbour's own indices) are
+    checked on the host against the oracle's fill, which finds neighbours by
+    point location through the brick's coordinates: every mapped index lies
+    inside the neighbour, copies give the oracle's value bit for bit, the
+    four fine cells its eq. ghost_coarse average, and the coarse cell with
+    its d_k its eq. ghost_fine interpolation (read from the oracle's own
+    filled coarse patch) bit for bit."""
+    mx = 8
+    if case == "one_block":
+        brick, orient, lb = (1, 1), [0], S.random_balanced_leaves(2, 2, 4)
+    elif case == "all8":
+        brick, orient = (4, 2), list(range(8))
+        lb = S.random_balanced_leaves(3, 1, 3, brick=brick)
+    else:
+        brick = (3, 2)
+        seed = 0 if case == "brick_a" else 1
+        orient = [int(v) for v in np.random.default_rng(seed).integers(0, 8, 6)]
+        lb = S.random_balanced_leaves(seed, 1, 3, brick=brick)
+    own = S.brick_own_leaves(lb, brick, orient)
+    lmin, lmax = int(own[:, 0].min()), int(own[:, 0].max())
+    cfg = make_cfg(B, lmin=lmin, lmax=lmax)
+    arr, n = B._leaves_array(own)
+    h = C.c_void_p()
+    perm = (C.c_int64 * n)()
+    ori = (C.c_int32 * len(orient))(*orient)
+    assert B.lib().fc_patchstore_create_brick(C.byref(cfg), brick[0], brick[1], ori, n, arr, C.byref(h), perm) == 0
+    rec = np.zeros((n, 12, 4), dtype=np.int32)
+    assert B.lib().fc_patchstore_records(h, rec.ctypes.data_as(C.POINTER(C.c_int32))) == 0
+    B.lib().fc_patchstore_destroy(h)
+    slot_of = np.frombuffer(perm, dtype=np.int64)
+    leaf_of = np.empty(n, dtype=np.int64)
+    leaf_of[slot_of] = np.arange(n)
+    q = np.random.default_rng(5).random((n, 1, mx, mx))
+    o = oracle_lib.Oracle(own, mx=mx, lmin=lmin, lmax=lmax, velocity="constant", brick=brick, orient=orient)
+    o.set_interior(q)
+    o.ghost_fill()
+    full = o.full()
+    kinds = set()
+    for s in range(n):
+        k = leaf_of[s]
+        for j in range(-2, mx + 2):
+            for i in range(-2, mx + 2):
+                if 0 <= i < mx and 0 <= j < mx:
+                    continue
+                typ, nb, fx, fy = (int(v) for v in rec[s, _region(i, j, mx)])
+                kind, code = typ & 15, (typ >> 8) & 7
+                a, b = (j, i) if code & 1 else (i, j)
+                a, b = (-a if code & 2 else a), (-b if code & 4 else b)
+                want = full[k, 0, j + 2, i + 2]
+                kn = leaf_of[nb]
+                kinds.add((kind, code))
+                if kind == 1:
+                    I, J = a + fx, b + fy
+                    assert 0 <= I < mx and 0 <= J < mx
+                    assert q[kn, 0, J, I] == want
+                elif kind == 3:
+                    I, J = 2 * a + fx, 2 * b + fy
+                    assert 0 <= I < mx - 1 and 0 <= J < mx - 1
+                    got = 0.25 * (q[kn, 0, J, I] + q[kn, 0, J, I + 1] + q[kn, 0, J + 1, I] + q[kn, 0, J + 1, I + 1])
+                    assert abs(got - want) <= 2 * np.spacing(1.0)
+                else:
+                    assert kind == 2
+                    I, J = a + fx, b + fy
+                    assert 0 <= I < 2 * mx and 0 <= J < 2 * mx
+                    ic, jc = I >> 1, J >> 1
+                    dx, dy = (1.0 if I & 1 else -1.0), (1.0 if J & 1 else -1.0)
+                    Cp = full[kn, 0]
+                    c = Cp[jc + 2, ic + 2]
+                    sx = _minmod(Cp[jc + 2, ic + 3] - c, c - Cp[jc + 2, ic + 1])
+                    sy = _minmod(Cp[jc + 3, ic + 2] - c, c - Cp[jc + 1, ic + 2])
+                    assert c + 0.25 * (dx * sx + dy * sy) == want
+    assert {kd for kd, _ in kinds} == {1, 2, 3}
+    if case != "one_block":
+        assert len({cd for _, cd in kinds}) > 4
