@@ -2,11 +2,13 @@
 hand-written discrete adjoint, and against central finite differences.
 
 MC-limited steps are piecewise linear, so a finite difference crosses
-limiter kinks whenever a branch decision sits within eps of a switch; exact
-agreement is therefore pinned against the oracle's discrete adjoint
-(<= 1e-12 relative), while the 1e-6 finite-difference bar is checked where
-the map is linear (Lax-Wendroff), and the MC finite-difference error is
-bounded loosely.
+limiter kinks whenever a branch decision sits within eps of a switch.  The
+adjoint is pinned exactly against the oracle's discrete adjoint (<= 1e-12
+relative); the 1e-6 finite-difference bar is checked for Lax-Wendroff (a
+linear map) and for MC on data without flat regions, with the limiter
+branch decisions of the two perturbed trajectories compared edge by edge
+at every step: where no decision differs, the segment [q - eps d, q + eps d]
+lies in one linear piece and central differences are exact up to rounding.
 """
 import numpy as np
 import pytest
@@ -150,8 +152,84 @@ def test_full_size_gradient_matches_finite_differences_linear_scheme(B):
     _fd_check(B, "lw", 20, 1e-6)
 
 
-def test_full_size_gradient_finite_differences_mc(B):
-    _fd_check(B, "mc", 6, 5e-2)
+def _mc_branches(W, Wu):
+    """MC limiter branch per edge: 0 (W Wu <= 0), 1 half-sum, 2 twice W, 3
+    twice the upwind wave (ties to the first)."""
+    import torch
+    pos = W * Wu > 0
+    a, b, c = 0.5 * (W + Wu).abs(), 2 * W.abs(), 2 * Wu.abs()
+    br = torch.ones_like(W, dtype=torch.int8)
+    mn = a.clone()
+    m2 = b < mn
+    br[m2] = 2
+    mn = torch.where(m2, b, mn)
+    br[c < mn] = 3
+    return torch.where(pos, br, torch.zeros_like(br))
+
+
+def _branch_masks(q, level, mx, tm):
+    """Limiter branches of every x- and y-edge of a uniform periodic level
+    for the swirl field at mid-step time tm (upwind side from the sign of
+    the edge velocity; edges where it vanishes are left out)."""
+    import math
+    import torch
+    n, NG = 1 << level, mx << level
+    G = q.view(n, n, mx, mx).permute(0, 2, 1, 3).reshape(NG, NG)       # [J][I]
+    c = torch.sign(torch.sin(2 * math.pi * (torch.arange(NG, device=q.device, dtype=torch.float64) + 0.5) / NG))
+    ct = math.cos(math.pi * tm)
+    W = G - torch.roll(G, 1, 1)                   # x-edge I of row J; u ~ sin(2 pi y_J) c(t)
+    Wu = torch.where((c[:, None] * ct) > 0, torch.roll(W, 1, 1), torch.roll(W, -1, 1))
+    bx = _mc_branches(W, Wu)
+    bx[:, 0] = 0                                  # u = 0 on the x = 0 edges
+    Wy = G - torch.roll(G, 1, 0)                  # y-edge J of column I; v ~ -sin(2 pi x_I) c(t)
+    Wyu = torch.where((-c[None, :] * ct) > 0, torch.roll(Wy, 1, 0), torch.roll(Wy, -1, 0))
+    by = _mc_branches(Wy, Wyu)
+    by[0, :] = 0
+    return bx, by
+
+
+@pytest.mark.parametrize("eps,tol", [(1e-6, 1e-6), (1e-8, 1e-6), (1e-10, 1e-5)])
+def test_full_size_gradient_finite_differences_mc(B, eps, tol):
+    """MC at the gradient workload's size (uniform level 6, 4096 patches of
+    32x32, swirl, 256 steps, checkpoints every 16) on a Gaussian sum over
+    two plane waves (no flat regions): 20 smooth directions, central
+    differences from the two perturbed trajectories, which are stepped in
+    lockstep while their limiter branches are compared.  The flips per
+    direction are printed; at eps = 1e-10 none may occur (every segment in
+    one linear piece; the bar there is set by rounding, 1e-10 of the
+    state), at the larger eps the few that occur must not move the result
+    past 1e-6."""
+    import torch
+    from paper_1703_03116_amd.adjoint import _times, loss_and_grad
+    level, mx, n = 6, 32, 256
+    L = S.uniform_leaves(level)
+    q0 = torch.tensor(S.sample_on_leaves(S.gaussians_on_waves(S.gaussian_params(5)), L, mx), device="cuda")
+    qt = torch.tensor(S.sample_on_leaves(S.gaussians(S.gaussian_params(6)), L, mx), device="cuda")
+    dt = 0.9 / (mx << level)
+    ps = B.PatchStore(L, mx=mx, velocity="swirl", vel_params=(1.0, 0, 0), limiter="mc")
+    _, g = loss_and_grad(ps, q0, qt, level, dt, n, 16)
+    times = _times(0.0, dt, n)
+    errs, flips = [], []
+    for d in S.smooth_directions(7, 20, L, mx):
+        d = torch.tensor(d, device="cuda")
+        qp, qm = (q0 + eps * d).contiguous(), (q0 - eps * d).contiguous()
+        nf = 0
+        for s in range(n):
+            tm = times[s] + 0.5 * dt
+            bpx, bpy = _branch_masks(qp, level, mx, tm)
+            bmx, bmy = _branch_masks(qm, level, mx, tm)
+            nf += int((bpx != bmx).sum().item() + (bpy != bmy).sum().item())
+            qp = ps.step_uniform(level, times[s], dt, qp)
+            qm = ps.step_uniform(level, times[s], dt, qm)
+        fd = (0.5 * ((qp - qm) * (qp + qm - 2 * qt)).sum()).item() / (2 * eps)
+        ad = (g * d).sum().item()
+        errs.append(abs(fd - ad) / abs(ad))
+        flips.append(nf)
+        print(f"mc eps {eps:.0e} direction {len(errs)}: branch flips {nf} fd {fd:.12e} adjoint {ad:.12e} "
+              f"rel {errs[-1]:.2e}", flush=True)
+    assert max(errs) <= tol, errs
+    if eps <= 1e-10:
+        assert max(flips) == 0, flips
 
 
 @pytest.mark.parametrize("limiter", ["mc", "minmod"])

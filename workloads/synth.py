@@ -295,6 +295,19 @@ def gaussians(params):
     return fn
 
 
+def gaussians_on_waves(params):
+    """The Gaussian sum plus two periodic plane waves, so that cell
+    differences vanish only near isolated curves (no flat regions where the
+    Gaussians underflow): q = gaussians(params) + 0.25 sin(2 pi (x + 2y) +
+    0.4) + 0.15 cos(2 pi (3x - y))."""
+    g = gaussians(params)
+
+    def f(x, y):
+        return (g(x, y) + 0.25 * np.sin(2 * np.pi * (x + 2 * y) + 0.4)
+                + 0.15 * np.cos(2 * np.pi * (3 * x - y)))
+    return f
+
+
 def gaussian_grad_max(params, leaf) -> float:
     """Upper bound of |grad q| over a leaf's quadrant (input-mesh rule)."""
     l, ix, iy = (int(v) for v in leaf)
