@@ -74,6 +74,9 @@ typedef struct Orc {
     int hcap;
     int *hidx;
     int err;
+    /* mapped grid (0: Cartesian): the computational square mapped by
+     * X(xi, eta) = (xi, eta) + alpha sin(2 pi xi) sin(2 pi eta) (1, 1) */
+    double map_alpha;
     /* tangent/adjoint support (scalar only): frozen forward state */
 } Orc;
 
@@ -340,6 +343,18 @@ Orc *orc_create(int mx, int mbc, int eq, int lim, const int *bc, int vel, const 
     return orc_create_brick(mx, mbc, eq, lim, bc, vel, vp, g, lmin, lmax, 1, 1, NULL, n, leaves, status);
 }
 
+/* Map the grid (Sec. 1 mapped grids): X(xi, eta) = (xi, eta) + alpha sin(2 pi
+ * xi) sin(2 pi eta) (1, 1), invertible for |alpha| < 1/(2 pi).  One block,
+ * periodic sides, scalar advection (velocities stay edge fluxes per unit
+ * computational length).  Returns 0 or ERR_ARG. */
+int orc_set_mapping(Orc *o, double alpha) {
+    if (!(fabs(alpha) < 0.5 / M_PI)) return ERR_ARG;
+    if (alpha != 0.0 && (is_brick(o) || o->eq != EQ_ADV || o->bc[0] != BC_PERIODIC || o->bc[2] != BC_PERIODIC))
+        return ERR_ARG;
+    o->map_alpha = alpha;
+    return 0;
+}
+
 void orc_destroy(Orc *o) {
     if (!o) return;
     free(o->lv); free(o->q); free(o->qold); free(o->qhat); free(o->hidx); free(o->ph); free(o->ori);
@@ -444,6 +459,49 @@ static int ghost_to_brick(const Orc *o, int k, int r, int i, int j, int *X, int 
     return *X >= 0 && *Y >= 0;
 }
 
+/* ------------------------------------------------------------------ */
+/* mapped grids: cell areas (the metric terms of a second-order finite   */
+/* volume scheme on a mapped grid, Sec. 1; Sec. 5.2 runs one)            */
+/* ------------------------------------------------------------------ */
+/* Jacobian determinant of the mapping at (xi, eta): with w = alpha s(xi)
+ * t(eta), s = sin(2 pi xi), t = sin(2 pi eta), X = (xi + w, eta + w), so
+ * det = (1 + w_xi)(1 + w_eta) - w_eta w_xi = 1 + w_xi + w_eta. */
+static double map_jacobian(const Orc *o, double xi, double eta) {
+    double tp = 2.0 * M_PI;
+    double w_xi = o->map_alpha * tp * cos(tp * xi) * sin(tp * eta);
+    double w_eta = o->map_alpha * tp * sin(tp * xi) * cos(tp * eta);
+    return 1.0 + w_xi + w_eta;
+}
+
+/* Area of the mapped image of level-l cell (I, J), the integral of the
+ * Jacobian over the cell (4 x 4 Gauss-Legendre points: for this smooth
+ * mapping on cells of at most 1/32 it is exact to rounding), over the
+ * computational area h^2: the capacity.  Exact areas nest: a cell's area is
+ * the sum of its four children's, so area-weighted averages conserve mass.
+ * 1 on a Cartesian grid.  Indices wrap periodically. */
+static double capacity(const Orc *o, int l, int I, int J) {
+    if (o->map_alpha == 0.0) return 1.0;
+    static const double gx[4] = {-0.8611363115940526, -0.3399810435848563, 0.3399810435848563, 0.8611363115940526};
+    static const double gw[4] = {0.3478548451374538, 0.6521451548625461, 0.6521451548625461, 0.3478548451374538};
+    int n = o->mx << l;
+    double h = 1.0 / n;
+    I = ((I % n) + n) % n;
+    J = ((J % n) + n) % n;
+    double xc = (I + 0.5) * h, yc = (J + 0.5) * h, sum = 0.0;
+    for (int b = 0; b < 4; b++)
+        for (int a = 0; a < 4; a++)
+            sum += gw[a] * gw[b] * map_jacobian(o, xc + 0.5 * h * gx[a], yc + 0.5 * h * gx[b]);
+    return 0.25 * sum; /* (h/2)^2 sum / h^2 */
+}
+
+/* capacity of local cell (i, j) of leaf k */
+static double cell_capacity(const Orc *o, int k, int i, int j) {
+    const OLeaf *L = &o->lv[k];
+    return capacity(o, L->level, L->ix * o->mx + i, L->iy * o->mx + j);
+}
+
+double orc_capacity(const Orc *o, int l, int I, int J) { return capacity(o, l, I, J); }
+
 /* Phase "copy and average": coarse ghost regions of leaf k (Alg. 1, first
  * loop).  Sec. 2.3: every index of this patch is carried into the
  * neighbour's own indices (through the brick's, which amounts to eq.
@@ -477,9 +535,24 @@ static void fill_coarse_ghosts(Orc *o, int k, int clevel) {
                     ghost_to_brick(o, k, l + 1, 2 * i + (d & 1), 2 * j + (d >> 1), &X, &Y);
                     brick_to_cell(o, kk, l + 1, X, Y, &fa[d], &fb[d]);
                 }
-                for (int f = 0; f < o->F; f++)
-                    *cell(o, dst, f, i, j) = 0.25 * (*cell(o, s, f, fa[0], fb[0]) + *cell(o, s, f, fa[1], fb[1]) +
-                                                     *cell(o, s, f, fa[2], fb[2]) + *cell(o, s, f, fa[3], fb[3]));
+                if (o->map_alpha == 0.0) {
+                    for (int f = 0; f < o->F; f++)
+                        *cell(o, dst, f, i, j) = 0.25 * (*cell(o, s, f, fa[0], fb[0]) + *cell(o, s, f, fa[1], fb[1]) +
+                                                         *cell(o, s, f, fa[2], fb[2]) + *cell(o, s, f, fa[3], fb[3]));
+                } else {
+                    /* mapped grid: the area-weighted mean of the four fine
+                     * cells (their areas, not the mean, carry the mass) */
+                    double a[4], asum = 0.0;
+                    for (int d = 0; d < 4; d++) {
+                        a[d] = cell_capacity(o, kk, fa[d], fb[d]);
+                        asum += a[d];
+                    }
+                    for (int f = 0; f < o->F; f++) {
+                        double m = 0.0;
+                        for (int d = 0; d < 4; d++) m += a[d] * *cell(o, s, f, fa[d], fb[d]);
+                        *cell(o, dst, f, i, j) = m / asum;
+                    }
+                }
             }
             /* L coarser: a fine ghost region, filled by interpolation */
         }
@@ -739,7 +812,15 @@ static double adv_step(const Orc *o, int k, const double *Q, double *Qn, double 
     const double *D = dQ ? dQ : Q; /* data the (linear in D) update acts on */
 #define QQ(i, j) (*cell(o, (double *)Q, 0, (i), (j)))
 #define DD(i, j) (*cell(o, (double *)D, 0, (i), (j)))
-    double smax = 0.0;
+    /* Capacity form on a mapped grid (Clawpack's, as the mapped-grid schemes
+     * the paper cites use it): a cell's fluctuations and flux differences are
+     * scaled by lam / kappa of that cell, a transverse wave by lam / kappa of
+     * the cell its fluctuation entered, the correction's (1 - lam |s|) by the
+     * mean of lam / kappa of the edge's two cells; the Courant number is
+     * lam / kappa of the cell a wave enters times its speed.  kappa = 1 on a
+     * Cartesian grid gives back the plain scheme, bit for bit. */
+#define LK(i, j) (lam / cell_capacity(o, k, (i), (j)))
+    double cmax = 0.0;
     /* x-edges (i-1/2, j), i in [0, mx], j in [-1, mx] */
     for (int j = -1; j <= mx; j++)
         for (int i = 0; i <= mx; i++) {
@@ -757,16 +838,20 @@ static double adv_step(const Orc *o, int k, const double *Q, double *Qn, double 
                 double Wu = s_ > 0 ? DD(i - 1, j) - DD(i - 2, j) : DD(i + 1, j) - DD(i, j);
                 Wl = limited(o->lim, W, Wu);
             }
-            double C = fabs(s_) * (1.0 - lam * fabs(s_)) * Wl;
+            double lr = LK(i, j), ll = LK(i - 1, j);
+            double C = fabs(s_) * (1.0 - 0.5 * (ll + lr) * fabs(s_)) * Wl;
             WE(w, w->Ft, j, i) += 0.5 * C;
             double Aps = Ap - C, Ams = Am + C;
             double vpu = vel_v(o, oc, l, gx + i, gy + j + 1, tm), vpd = vel_v(o, oc, l, gx + i, gy + j, tm);
             double vmu = vel_v(o, oc, l, gx + i - 1, gy + j + 1, tm), vmd = vel_v(o, oc, l, gx + i - 1, gy + j, tm);
-            WE(w, w->Gt, j + 1, i) -= 0.5 * lam * (vpu > 0 ? vpu : 0.0) * Aps;
-            WE(w, w->Gt, j, i) -= 0.5 * lam * (vpd < 0 ? vpd : 0.0) * Aps;
-            WE(w, w->Gt, j + 1, i - 1) -= 0.5 * lam * (vmu > 0 ? vmu : 0.0) * Ams;
-            WE(w, w->Gt, j, i - 1) -= 0.5 * lam * (vmd < 0 ? vmd : 0.0) * Ams;
-            if (j >= 0 && j < mx && fabs(s_) > smax) smax = fabs(s_);
+            WE(w, w->Gt, j + 1, i) -= 0.5 * lr * (vpu > 0 ? vpu : 0.0) * Aps;
+            WE(w, w->Gt, j, i) -= 0.5 * lr * (vpd < 0 ? vpd : 0.0) * Aps;
+            WE(w, w->Gt, j + 1, i - 1) -= 0.5 * ll * (vmu > 0 ? vmu : 0.0) * Ams;
+            WE(w, w->Gt, j, i - 1) -= 0.5 * ll * (vmd < 0 ? vmd : 0.0) * Ams;
+            if (j >= 0 && j < mx) {
+                double c_ = s_ > 0 ? lr * s_ : (s_ < 0 ? ll * -s_ : 0.0);
+                if (c_ > cmax) cmax = c_;
+            }
         }
     /* y-edges (i, j-1/2), j in [0, mx], i in [-1, mx] */
     for (int i = -1; i <= mx; i++)
@@ -785,27 +870,33 @@ static double adv_step(const Orc *o, int k, const double *Q, double *Qn, double 
                 double Vu = s_ > 0 ? DD(i, j - 1) - DD(i, j - 2) : DD(i, j + 1) - DD(i, j);
                 Vl = limited(o->lim, V, Vu);
             }
-            double C = fabs(s_) * (1.0 - lam * fabs(s_)) * Vl;
+            double lu = LK(i, j), ld = LK(i, j - 1);
+            double C = fabs(s_) * (1.0 - 0.5 * (ld + lu) * fabs(s_)) * Vl;
             WE(w, w->Gt, j, i) += 0.5 * C;
             double Bps = Bp - C, Bms = Bm + C;
             double upr = vel_u(o, oc, l, gx + i + 1, gy + j, tm), upl = vel_u(o, oc, l, gx + i, gy + j, tm);
             double umr = vel_u(o, oc, l, gx + i + 1, gy + j - 1, tm), uml = vel_u(o, oc, l, gx + i, gy + j - 1, tm);
-            WE(w, w->Ft, j, i + 1) -= 0.5 * lam * (upr > 0 ? upr : 0.0) * Bps;
-            WE(w, w->Ft, j, i) -= 0.5 * lam * (upl < 0 ? upl : 0.0) * Bps;
-            WE(w, w->Ft, j - 1, i + 1) -= 0.5 * lam * (umr > 0 ? umr : 0.0) * Bms;
-            WE(w, w->Ft, j - 1, i) -= 0.5 * lam * (uml < 0 ? uml : 0.0) * Bms;
-            if (i >= 0 && i < mx && fabs(s_) > smax) smax = fabs(s_);
+            WE(w, w->Ft, j, i + 1) -= 0.5 * lu * (upr > 0 ? upr : 0.0) * Bps;
+            WE(w, w->Ft, j, i) -= 0.5 * lu * (upl < 0 ? upl : 0.0) * Bps;
+            WE(w, w->Ft, j - 1, i + 1) -= 0.5 * ld * (umr > 0 ? umr : 0.0) * Bms;
+            WE(w, w->Ft, j - 1, i) -= 0.5 * ld * (uml < 0 ? uml : 0.0) * Bms;
+            if (i >= 0 && i < mx) {
+                double c_ = s_ > 0 ? lu * s_ : (s_ < 0 ? ld * -s_ : 0.0);
+                if (c_ > cmax) cmax = c_;
+            }
         }
     /* conservative update of the interior */
     for (int j = 0; j < mx; j++)
         for (int i = 0; i < mx; i++) {
             double fl = WE(w, w->Apx, j, i) + WE(w, w->Amx, j, i + 1) + WE(w, w->Bpy, j, i) + WE(w, w->Bmy, j + 1, i);
             double df = WE(w, w->Ft, j, i + 1) - WE(w, w->Ft, j, i) + WE(w, w->Gt, j + 1, i) - WE(w, w->Gt, j, i);
-            *cell(o, Qn, 0, i, j) = DD(i, j) - lam * fl - lam * df;
+            double lc = LK(i, j);
+            *cell(o, Qn, 0, i, j) = DD(i, j) - lc * fl - lc * df;
         }
 #undef QQ
 #undef DD
-    return lam * smax;
+#undef LK
+    return cmax;
 }
 
 /* ------------------------------------------------------------------ */
@@ -1241,6 +1332,7 @@ int orc_regrid(Orc *o, int n_new, const int *leaves_new) {
                                o->nby, o->ori, n_new,
                          leaves_new, &st);
     if (st) { orc_destroy(nw); return st; }
+    nw->map_alpha = o->map_alpha;
     int mx = o->mx;
     for (int k = 0; k < n_new; k++) {
         const OLeaf *L = &nw->lv[k];
@@ -1276,10 +1368,20 @@ int orc_regrid(Orc *o, int n_new, const int *leaves_new) {
             for (int j = 0; j < mx; j++)
                 for (int i = 0; i < mx; i++) {
                     int cx = i >= mx / 2, cy = j >= mx / 2;
-                    double *s = pat(o, o->q, kc[cx + 2 * cy]);
+                    int kf = kc[cx + 2 * cy];
+                    double *s = pat(o, o->q, kf);
                     int fi = 2 * i - cx * mx, fj = 2 * j - cy * mx;
-                    *cell(o, d, f, i, j) = 0.25 * (*cell(o, s, f, fi, fj) + *cell(o, s, f, fi + 1, fj) +
-                                                   *cell(o, s, f, fi, fj + 1) + *cell(o, s, f, fi + 1, fj + 1));
+                    if (o->map_alpha == 0.0) {
+                        *cell(o, d, f, i, j) = 0.25 * (*cell(o, s, f, fi, fj) + *cell(o, s, f, fi + 1, fj) +
+                                                       *cell(o, s, f, fi, fj + 1) + *cell(o, s, f, fi + 1, fj + 1));
+                    } else {
+                        /* mapped grid: area-weighted mean of the four children's cells */
+                        double a0 = cell_capacity(o, kf, fi, fj), a1 = cell_capacity(o, kf, fi + 1, fj);
+                        double a2 = cell_capacity(o, kf, fi, fj + 1), a3 = cell_capacity(o, kf, fi + 1, fj + 1);
+                        double m = a0 * *cell(o, s, f, fi, fj) + a1 * *cell(o, s, f, fi + 1, fj) +
+                                   a2 * *cell(o, s, f, fi, fj + 1) + a3 * *cell(o, s, f, fi + 1, fj + 1);
+                        *cell(o, d, f, i, j) = m / (a0 + a1 + a2 + a3);
+                    }
                 }
     }
     /* swap the new mesh in */

@@ -51,6 +51,10 @@ def lib():
         L.orc_create_brick.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, ip, C.c_int, dp, C.c_double,
                                        C.c_int, C.c_int, C.c_int, C.c_int, ip, C.c_int, ip, ip]
         L.orc_destroy.argtypes = [C.c_void_p]
+        L.orc_set_mapping.argtypes = [C.c_void_p, C.c_double]
+        L.orc_set_mapping.restype = C.c_int
+        L.orc_capacity.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int]
+        L.orc_capacity.restype = C.c_double
         for name in ("orc_set_interior", "orc_get_interior", "orc_get_full", "orc_set_full",
                      "orc_get_old_interior"):
             getattr(L, name).argtypes = [C.c_void_p, dp]
@@ -105,11 +109,13 @@ class Oracle:
 
     def __init__(self, leaves, mx=8, mbc=2, equation="advection", limiter="mc",
                  bc=("periodic",) * 4, velocity="constant", vel_params=(1.0, 0.5, 0.0),
-                 gravity=1.0, lmin=None, lmax=None, brick=(1, 1), orient=None):
+                 gravity=1.0, lmin=None, lmax=None, brick=(1, 1), orient=None, map_alpha=0.0):
         """brick: (nbx, nby) unit blocks (Sec. 2.3); orient: one orientation
         code 0..7 per block, block (bx, by) at bx + nbx * by (None: all 0).
         Leaves are (level, ix, iy) with block (ix >> level, iy >> level) and
-        the low bits in the block's own indices."""
+        the low bits in the block's own indices.  map_alpha: the mapped grid
+        X = (xi, eta) + map_alpha sin(2 pi xi) sin(2 pi eta) (1, 1) (0:
+        Cartesian)."""
         L = lib()
         leaves = np.ascontiguousarray(np.asarray(leaves, dtype=np.int32).reshape(-1, 3))
         self.mx, self.mbc, self.N = mx, mbc, mx + 2 * mbc
@@ -132,6 +138,11 @@ class Oracle:
             L.orc_destroy(self._h)
             self._h = None
             raise OracleError(f"oracle rejected the mesh: status {st.value}")
+        if map_alpha != 0.0 and L.orc_set_mapping(self._h, float(map_alpha)):
+            L.orc_destroy(self._h)
+            self._h = None
+            raise OracleError("oracle rejected the mapping")
+        self.map_alpha = float(map_alpha)
 
     def __del__(self):
         if getattr(self, "_h", None):
@@ -195,6 +206,10 @@ class Oracle:
         g2 = np.zeros(self.n)
         lib().orc_tag(self._h, float(tau_r), float(tau_c), tags.ctypes.data_as(C.POINTER(C.c_byte)), _dp(g2))
         return tags, g2
+
+    def capacity(self, level, I, J):
+        """Area of the mapped level-`level` cell (I, J) over h^2."""
+        return lib().orc_capacity(self._h, int(level), int(I), int(J))
 
     def adapt(self, tags, smooth=False):
         """New leaves from tags (Sec. 4.1); smooth: raise each leaf's target
