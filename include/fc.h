@@ -92,6 +92,15 @@ typedef struct {
     double cfl_max;        /* > 0: largest Courant number a step may reach (a
                               larger one is an error, or a rejected step in
                               fc_advance_adaptive); 0: not checked              */
+    double map_alpha;      /* mapped grid (Sec. 1 metric terms, Sec. 5.2 runs
+                              one): the physical cell of computational point
+                              (xi, eta) is the image of
+                              X = (xi, eta) + alpha sin(2 pi xi) sin(2 pi eta) (1, 1),
+                              |alpha| < 1/(2 pi); 0: Cartesian.  Non-zero needs
+                              one periodic block and scalar advection; steps
+                              then take the capacity form (cell areas kappa h^2)
+                              in FC_MODE_PER_LEVEL only, and averages from fine
+                              to coarse cells are area-weighted              */
 } fc_config;
 
 typedef struct fc_patchstore fc_patchstore;

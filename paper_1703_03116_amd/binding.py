@@ -49,7 +49,7 @@ class Config(C.Structure):
                 ("bc", C.c_int32 * 4), ("velocity", C.c_int32), ("vel_params", C.c_double * 3),
                 ("gravity", C.c_double), ("min_level", C.c_int32), ("max_level", C.c_int32),
                 ("time_stepping", C.c_int32), ("reserved", C.c_int32), ("capacity", C.c_int64),
-                ("cfl_max", C.c_double)]
+                ("cfl_max", C.c_double), ("map_alpha", C.c_double)]
 
 
 _lib = None
@@ -129,10 +129,12 @@ class PatchStore:
 
     def __init__(self, leaves, mx=32, equation="advection", limiter="mc", bc=("periodic",) * 4,
                  velocity="swirl", vel_params=(1.0, 0.0, 0.0), gravity=1.0, min_level=None, max_level=None,
-                 time_stepping="multirate", capacity=None, cfl_max=0.0, brick=(1, 1), orient=None):
+                 time_stepping="multirate", capacity=None, cfl_max=0.0, brick=(1, 1), orient=None,
+                 map_alpha=0.0):
         """brick, orient: a multiblock brick of brick[0] x brick[1] unit
         blocks with one orientation code per block (fc_patchstore_create_brick);
-        leaves then lie in the blocks' own coordinates."""
+        leaves then lie in the blocks' own coordinates.  map_alpha: the
+        amplitude of the mapped grid (0: Cartesian)."""
         L = lib()
         arr, n = _leaves_array(leaves)
         lv = np.asarray(leaves, dtype=np.int32).reshape(-1, 3)
@@ -151,6 +153,7 @@ class PatchStore:
         cfg.time_stepping = STEP[time_stepping]
         cfg.capacity = int(capacity if capacity is not None else n)
         cfg.cfl_max = float(cfl_max)
+        cfg.map_alpha = float(map_alpha)
         self.cfg = cfg
         self.mx, self.N, self.F = mx, mx + 4, 3 if equation == "swe" else 1
         self.min_level, self.max_level = cfg.min_level, cfg.max_level

@@ -94,6 +94,11 @@ struct Ctx {
     unsigned long long *cflp;  // per-slot max Courant number (bits of a non-negative double) [cap];
                                // NULL: not recorded
     int32_t stream_out;        // advance output by streaming (nontemporal) stores
+    // mapped grid (Sec. 1 metric terms): per level the capacity table K[k],
+    // k = (I + J + 1) mod n, of cell (I, J) (n entries); all NULL on a
+    // Cartesian grid
+    const double *mk[FC_MAXLEV];
+    int32_t mapped;
 };
 
 // Velocity factor tables of one level with n = mx 2^l cells per axis and m
@@ -120,6 +125,8 @@ struct LaunchCfg {
 };
 
 hipError_t launch_init_tables(int level, int mx, int periodic_x, int periodic_y, double *vt, hipStream_t s);
+// capacity table of a mapped level with n cells per axis (alpha: the mapping's amplitude)
+hipError_t launch_init_capacity(int n, double alpha, double *K, hipStream_t s);
 // reset_cfl: also zero the n per-slot Courant maxima
 hipError_t launch_set_state(DevState *st, double t, double dt, uint32_t curmask, int reset_cfl, unsigned long long *cflp, int n,
                             hipStream_t s);

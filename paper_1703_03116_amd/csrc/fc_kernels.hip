@@ -108,6 +108,28 @@ __device__ __forceinline__ void rec_map(const NbrRec &r, int i, int j, int s, in
     J = s * b + r.fy;
 }
 
+// Capacity (cell area over h^2) of the level-l cell at global index (I, J)
+// of a mapped grid, from the level's table (it depends on I + J only);
+// indices wrap periodically.
+__device__ __forceinline__ double capacity_at(const Ctx &c, int l, int n, int I, int J) {
+    int k = (I + J + 1) % n;
+    k = k < 0 ? k + n : k;
+    return c.mk[l][k];
+}
+
+// eq. ghost_coarse on a mapped grid: the area-weighted mean of the four
+// cells (i, j), (i+1, j), (i, j+1), (i+1, j+1) (values y0 .. y3) of the
+// level-lf leaf in `slot` -- the areas, not the count, carry the mass.
+template <int MX>
+__device__ __forceinline__ double area_mean4(const Ctx &c, int slot, int lf, int i, int j, double y0, double y1,
+                                             double y2, double y3) {
+    const PatchInfo P = c.info[slot];
+    const int n = MX << lf, I = P.ix * MX + i, J = P.iy * MX + j;
+    const double a0 = capacity_at(c, lf, n, I, J), a1 = capacity_at(c, lf, n, I + 1, J);
+    const double a2 = capacity_at(c, lf, n, I, J + 1), a3 = capacity_at(c, lf, n, I + 1, J + 1);
+    return (a0 * y0 + a1 * y1 + a2 * y2 + a3 * y3) / (a0 + a1 + a2 + a3);
+}
+
 // eq. ghost_fine at local (i, j) of a level-l patch whose ghost region is
 // covered by the coarse patch of `rec`: q_c + (1/4)(d_x s_x + d_y s_y), s the
 // minmod of the one-sided differences on the coarse grid, d = +1 for the
@@ -119,8 +141,9 @@ __device__ __forceinline__ void rec_map(const NbrRec &r, int i, int j, int s, in
 // loaded at once, and then every value: two dependent rounds of loads, with
 // no load behind a branch.
 // PIPE: overlap the fields' loads (two fields' values live at once); off
-// where the kernel's register budget is too small for that.
-template <int MX, int F, bool PIPE = true>
+// where the kernel's register budget is too small for that.  MAP: a mapped
+// grid (fine neighbours averaged by area).
+template <int MX, int F, bool PIPE = true, bool MAP = false>
 __device__ __forceinline__ void coarse_interp(const Ctx &c, const View &w, int l, int i, int j, const NbrRec rec,
                                               double *v) {
     constexpr int N = MX + 2 * MB;
@@ -146,6 +169,7 @@ __device__ __forceinline__ void coarse_interp(const Ctx &c, const View &w, int l
     // +0, +1, +N, +N+1 from the first)
     uint32_t k[4];
     bool fine[4], bad[4];
+    int fs[4], fi[4], fj[4];  // MAP: slot and first cell of a fine neighbour
 #pragma unroll
     for (int n = 0; n < 4; n++) {
         const int kind = rec_kind(nr[n]);
@@ -156,6 +180,9 @@ __device__ __forceinline__ void coarse_interp(const Ctx &c, const View &w, int l
         rec_map(nr[n], ni[n], nj[n], fine[n] ? 2 : 1, ci, cj);
         ci = in[n] ? ni[n] : (bad[n] ? 0 : ci);
         cj = in[n] ? nj[n] : (bad[n] ? 0 : cj);
+        fs[n] = slot;
+        fi[n] = ci;
+        fj[n] = cj;
         k[n] = qidx(c.cap, N, 0, slot, ci, cj);
         if (bad[n]) atomicOr(c.err, 2);
     }
@@ -183,7 +210,12 @@ __device__ __forceinline__ void coarse_interp(const Ctx &c, const View &w, int l
 #pragma unroll
         for (int n = 0; n < 4; n++) {
             const double *y = x[n + 1];
-            double t = fine[n] ? 0.25 * (y[0] + y[1] + y[2] + y[3]) : (tint ? y[2] + w.alpha * (y[0] - y[2]) : y[0]);
+            double t;
+            if constexpr (MAP)
+                t = fine[n] ? area_mean4<MX>(c, fs[n], l, fi[n], fj[n], y[0], y[1], y[2], y[3])
+                            : (tint ? y[2] + w.alpha * (y[0] - y[2]) : y[0]);
+            else
+                t = fine[n] ? 0.25 * (y[0] + y[1] + y[2] + y[3]) : (tint ? y[2] + w.alpha * (y[0] - y[2]) : y[0]);
             if (bad[n]) t = __builtin_nan("");
             if (F == 3 && f == 1) t *= su[n];
             if (F == 3 && f == 2) t *= sv[n];
@@ -220,7 +252,7 @@ __device__ __forceinline__ void coarse_interp(const Ctx &c, const View &w, int l
 // Ghost value at local (i, j) of patch p (level l) lying in region r of the
 // frame (no wall folding): copy, eq. ghost_coarse average or eq. ghost_fine
 // interpolation, as the region's neighbour record says.
-template <int MX, int F, bool PIPE = true>
+template <int MX, int F, bool PIPE = true, bool MAP = false>
 __device__ __forceinline__ void ghost_cell_rec(const Ctx &c, const View &w, int l, int i, int j, const NbrRec rec,
                                                double *v) {
     const int kind = rec_kind(rec);
@@ -232,13 +264,22 @@ __device__ __forceinline__ void ghost_cell_rec(const Ctx &c, const View &w, int 
     } else if (kind == NB_FINE) {
         int li, lj;
         rec_map(rec, i, j, 2, li, lj);
+        if constexpr (MAP) {
 #pragma unroll
-        for (int f = 0; f < F; f++)
-            v[f] = 0.25 * (read_state<MX>(c, w, rec.id, l + 1, li, lj, f) + read_state<MX>(c, w, rec.id, l + 1, li + 1, lj, f) +
-                           read_state<MX>(c, w, rec.id, l + 1, li, lj + 1, f) +
-                           read_state<MX>(c, w, rec.id, l + 1, li + 1, lj + 1, f));
+            for (int f = 0; f < F; f++)
+                v[f] = area_mean4<MX>(c, rec.id, l + 1, li, lj, read_state<MX>(c, w, rec.id, l + 1, li, lj, f),
+                                      read_state<MX>(c, w, rec.id, l + 1, li + 1, lj, f),
+                                      read_state<MX>(c, w, rec.id, l + 1, li, lj + 1, f),
+                                      read_state<MX>(c, w, rec.id, l + 1, li + 1, lj + 1, f));
+        } else {
+#pragma unroll
+            for (int f = 0; f < F; f++)
+                v[f] = 0.25 * (read_state<MX>(c, w, rec.id, l + 1, li, lj, f) + read_state<MX>(c, w, rec.id, l + 1, li + 1, lj, f) +
+                               read_state<MX>(c, w, rec.id, l + 1, li, lj + 1, f) +
+                               read_state<MX>(c, w, rec.id, l + 1, li + 1, lj + 1, f));
+        }
     } else if (kind == NB_COARSE) {
-        coarse_interp<MX, F, PIPE>(c, w, l, i, j, rec, v);
+        coarse_interp<MX, F, PIPE, MAP>(c, w, l, i, j, rec, v);
     } else {
         atomicOr(c.err, 2);
 #pragma unroll
@@ -246,15 +287,15 @@ __device__ __forceinline__ void ghost_cell_rec(const Ctx &c, const View &w, int 
     }
 }
 
-template <int MX, int F, bool PIPE = true>
+template <int MX, int F, bool PIPE = true, bool MAP = false>
 __device__ __forceinline__ void ghost_cell_r(const Ctx &c, const View &w, int p, int l, int i, int j, int r,
                                              double *v) {
-    ghost_cell_rec<MX, F, PIPE>(c, w, l, i, j, c.nbr[p * FC_NREC + r], v);
+    ghost_cell_rec<MX, F, PIPE, MAP>(c, w, l, i, j, c.nbr[p * FC_NREC + r], v);
 }
 
 // Ghost value of patch p (geometry P) at local (i, j): the result of
 // Algorithm 1.
-template <int MX, int F, bool PIPE = true>
+template <int MX, int F, bool PIPE = true, bool MAP = false>
 __device__ __forceinline__ void ghost_cell_of(const Ctx &c, const View &w, int p, const PatchInfo &P, int i, int j,
                                               double *v) {
     const int l = P.level;
@@ -264,15 +305,15 @@ __device__ __forceinline__ void ghost_cell_of(const Ctx &c, const View &w, int p
 #pragma unroll
         for (int f = 0; f < F; f++) v[f] = read_state<MX>(c, w, p, l, i, j, f);
     } else {
-        ghost_cell_r<MX, F, PIPE>(c, w, p, l, i, j, region_rec<MX>(i, j), v);
+        ghost_cell_r<MX, F, PIPE, MAP>(c, w, p, l, i, j, region_rec<MX>(i, j), v);
     }
     apply_signs<F>(v, su, sv);
 }
 
-template <int MX, int F>
+template <int MX, int F, bool MAP = false>
 __device__ void ghost_cell(const Ctx &c, const View &w, int p, int i, int j, double *v) {
     const PatchInfo P = c.info[p];
-    ghost_cell_of<MX, F>(c, w, p, P, i, j, v);
+    ghost_cell_of<MX, F, true, MAP>(c, w, p, P, i, j, v);
 }
 
 // g-th cell of the ghost frame in region-major order: the eight face halves
@@ -342,7 +383,7 @@ __device__ __forceinline__ int xcd_remap(int b, int count) {
 // ------------------------------------------------------------------------
 // fill: materialise ghost values (per-level form)
 // ------------------------------------------------------------------------
-template <int MX, int F>
+template <int MX, int F, bool MAP = false>
 __global__ void __launch_bounds__(256) fill_kernel(Ctx c, int first) {
     constexpr int N = MX + 2 * MB, NG = N * N - MX * MX;
     const int p = first + blockIdx.x;
@@ -353,7 +394,7 @@ __global__ void __launch_bounds__(256) fill_kernel(Ctx c, int first) {
         int i, j;
         ghost_index<MX>(g, i, j);
         double v[F];
-        ghost_cell<MX, F>(c, w, p, i, j, v);
+        ghost_cell<MX, F, MAP>(c, w, p, i, j, v);
 #pragma unroll
         for (int f = 0; f < F; f++) out[qidx(c.cap, N, f, p, i, j)] = v[f];
     }
@@ -971,6 +1012,171 @@ __global__ void __launch_bounds__(NT, (min_waves<MX, NT, 0>())) advance_scalar_k
     double cfl = 0.0;
     advance_scalar_patch<MX, NT, FUSED>(c, view_of(c), s, p, level, t, dt, cfl, nullptr, slot);
     store_cfl_slot(slot, s.red[15], cfl);
+}
+
+// ------------------------------------------------------------------------
+// mapped grids: capacity-form step (scalar advection)
+// ------------------------------------------------------------------------
+// The computational square is mapped by X = (xi, eta) + alpha sin(2 pi xi)
+// sin(2 pi eta) (1, 1); a cell's capacity is the exact area of its image
+// over h^2.  The Jacobian is 1 + 2 pi alpha sin(2 pi (xi + eta)), whose
+// integral over a cell of side h gives
+//   kappa = 1 + 2 pi alpha sigma^2 sin(2 pi (xi_c + eta_c)), sigma = sin(pi h)/(pi h),
+// a function of I + J alone: per level a table K[k], k = (I + J + 1) mod n.
+__global__ void init_capacity_kernel(int n, double alpha, double *K) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double h = 1.0 / (double)n;
+    const double sig = sin(M_PI * h) / (M_PI * h);
+    K[k] = 1.0 + 2.0 * M_PI * alpha * (sig * sig) * sin(2.0 * M_PI * ((double)k * h));
+}
+
+template <int MX>
+struct MappedSmem {
+    static constexpr int N = MX + 2 * MB, NP = N + 1;
+    static constexpr int EX = (MX + 1) * (MX + 2);  // edges of one direction, lines -1 .. MX
+    double q[N * NP];
+    double lk[N * NP];                     // dt / (kappa h) of every tile cell
+    double ap[EX], am[EX], cx[EX];         // x-edge (i, j), i in [0, MX], j in [-1, MX]: s+ W, s- W, C
+    double bp[EX], bm[EX], cy[EX];         // y-edge (i, j), i in [-1, MX], j in [0, MX]
+    double ux[MX + 1], uy[MX + 2], vy[MX + 1], vx[MX + 2];  // velocity factors, as the scalar step
+    double red[16];
+    unsigned long long cfl;
+};
+
+template <int MX>
+__device__ __forceinline__ int xe_idx(int i, int j) { return (j + 1) * (MX + 1) + i; }
+template <int MX>
+__device__ __forceinline__ int ye_idx(int i, int j) { return (i + 1) * (MX + 1) + j; }
+
+// One capacity-form step (Clawpack's, the form mapped-grid wave propagation
+// takes) of patch p on its filled tile: every x- and y-edge's fluctuations
+// s+- W and limited correction C = |s| (1 - nubar |s|) W~, nubar the mean of
+// dt / (kappa h) over the edge's two cells; then each edge's flux F~ (G~) is
+// gathered: 1/2 C plus the transverse waves of the four adjacent edges of
+// the other direction, each scaled by dt / (kappa h) of the cell its
+// corrected fluctuation entered; then Q -= dt / (kappa h) (fluctuations +
+// flux differences).  The Courant number is dt / (kappa h) of the cell a wave
+// enters times its speed.
+template <int MX, int NT, int LIM>
+__device__ void advance_mapped_patch(const Ctx &c, const View &w, MappedSmem<MX> &s, int p, int lev, double t,
+                                     double dt, double &cfl) {
+    constexpr int N = MX + 2 * MB, NP = N + 1, EX = MappedSmem<MX>::EX;
+    const int tid = threadIdx.x;
+    const PatchInfo P = c.info[p];
+    const int l = lev >= 0 ? lev : P.level, n = MX << l;
+    const double lam = dt * (double)n;  // dt / h, exact
+    const int gx = P.ix * MX, gy = P.iy * MX;
+    const double *in = buf_of(c, w, l);
+    double *out = other_of(c, w, l);
+    const size_t base = (size_t)p * N * N;
+    for (int k = tid; k < N * N; k += NT) {
+        const int i = k % N, j = k / N;
+        s.q[j * NP + i] = in[base + k];
+        s.lk[j * NP + i] = lam / capacity_at(c, l, n, gx + i - MB, gy + j - MB);
+    }
+    // velocity factors at the mid-step time (the scalar step's tables)
+    const double tm = t + 0.5 * dt;
+    const double ct = c.velocity == 2 ? cos(M_PI * (tm * c.vel_invT)) : 1.0;
+    for (int k = tid; k < MX + 2; k += NT) {
+        if (c.velocity == 2) {
+            const double *vt = c.vt[l];
+            if (k <= MX) {
+                s.ux[k] = vt[vt_ex(n, MB) + gx + k];
+                s.vy[k] = vt[vt_ey(n, MB) + gy + k];
+            }
+            s.uy[k] = vt[vt_cy(n, MB) + gy + k - 1] * ct;
+            s.vx[k] = -(vt[vt_cx(n, MB) + gx + k - 1] * ct);
+        } else {
+            if (k <= MX) { s.ux[k] = c.vel_u; s.vy[k] = c.vel_v; }
+            s.uy[k] = 1.0;
+            s.vx[k] = 1.0;
+        }
+    }
+    if (tid == 0) s.cfl = 0ull;
+    __syncthreads();
+    auto Q = [&](int i, int j) { return s.q[(j + MB) * NP + i + MB]; };
+    auto LK = [&](int i, int j) { return s.lk[(j + MB) * NP + i + MB]; };
+    double cm = 0.0;
+    // every edge of both directions: fluctuations and correction
+    for (int e = tid; e < 2 * EX; e += NT) {
+        const bool xd = e < EX;
+        const int k = xd ? e : e - EX;
+        int i, j;
+        if (xd) { i = k % (MX + 1); j = k / (MX + 1) - 1; }
+        else { j = k % (MX + 1); i = k / (MX + 1) - 1; }
+        const int di = xd ? 1 : 0, dj = xd ? 0 : 1;   // edge between cell (i-di, j-dj) and (i, j)
+        const double sp = xd ? s.ux[i] * s.uy[j + 1] : s.vy[j] * s.vx[i + 1];
+        const double W = Q(i, j) - Q(i - di, j - dj);
+        const double Wu = sp > 0.0 ? Q(i - di, j - dj) - Q(i - 2 * di, j - 2 * dj) : Q(i + di, j + dj) - Q(i, j);
+        const double lr = LK(i, j), ll = LK(i - di, j - dj);
+        const double C = correction<LIM>(W, Wu, fabs(sp), 0.5 * (ll + lr));
+        if (xd) { s.ap[k] = posp(sp) * W; s.am[k] = negp(sp) * W; s.cx[k] = C; }
+        else { s.bp[k] = posp(sp) * W; s.bm[k] = negp(sp) * W; s.cy[k] = C; }
+        const bool inner = xd ? (j >= 0 && j < MX) : (i >= 0 && i < MX);
+        const double cw = sp > 0.0 ? lr * sp : (sp < 0.0 ? ll * -sp : 0.0);
+        if (inner) cm = fmax(cm, cw);
+    }
+    __syncthreads();
+    // fluxes gathered per edge, then the update of each interior cell
+    for (int k = tid; k < MX * MX; k += NT) {
+        const int i = k % MX, j = k / MX;
+        auto Fx = [&](int I, int J) {  // F~ at x-edge (I, J), J an interior row
+            const double u = s.ux[I] * s.uy[J + 1];
+            const double up = posp(u), un = negp(u);
+            double f = 0.5 * s.cx[xe_idx<MX>(I, J)];
+            const double bps0 = s.bp[ye_idx<MX>(I - 1, J)] - s.cy[ye_idx<MX>(I - 1, J)];
+            const double bps1 = s.bp[ye_idx<MX>(I, J)] - s.cy[ye_idx<MX>(I, J)];
+            const double bms0 = s.bm[ye_idx<MX>(I - 1, J + 1)] + s.cy[ye_idx<MX>(I - 1, J + 1)];
+            const double bms1 = s.bm[ye_idx<MX>(I, J + 1)] + s.cy[ye_idx<MX>(I, J + 1)];
+            f -= 0.5 * LK(I - 1, J) * up * bps0;
+            f -= 0.5 * LK(I, J) * un * bps1;
+            f -= 0.5 * LK(I - 1, J) * up * bms0;
+            f -= 0.5 * LK(I, J) * un * bms1;
+            return f;
+        };
+        auto Gy = [&](int I, int J) {  // G~ at y-edge (I, J), I an interior column
+            const double v = s.vy[J] * s.vx[I + 1];
+            const double vp = posp(v), vn = negp(v);
+            double g = 0.5 * s.cy[ye_idx<MX>(I, J)];
+            const double aps0 = s.ap[xe_idx<MX>(I, J - 1)] - s.cx[xe_idx<MX>(I, J - 1)];
+            const double aps1 = s.ap[xe_idx<MX>(I, J)] - s.cx[xe_idx<MX>(I, J)];
+            const double ams0 = s.am[xe_idx<MX>(I + 1, J - 1)] + s.cx[xe_idx<MX>(I + 1, J - 1)];
+            const double ams1 = s.am[xe_idx<MX>(I + 1, J)] + s.cx[xe_idx<MX>(I + 1, J)];
+            g -= 0.5 * LK(I, J - 1) * vp * aps0;
+            g -= 0.5 * LK(I, J) * vn * aps1;
+            g -= 0.5 * LK(I, J - 1) * vp * ams0;
+            g -= 0.5 * LK(I, J) * vn * ams1;
+            return g;
+        };
+        const double fl = s.ap[xe_idx<MX>(i, j)] + s.am[xe_idx<MX>(i + 1, j)] + s.bp[ye_idx<MX>(i, j)] +
+                          s.bm[ye_idx<MX>(i, j + 1)];
+        const double df = Fx(i + 1, j) - Fx(i, j) + Gy(i, j + 1) - Gy(i, j);
+        const double lc = LK(i, j);
+        out[base + (size_t)(j + MB) * N + i + MB] = Q(i, j) - lc * fl - lc * df;
+    }
+    cm = wave_max_last_lane(cm);
+    if ((tid & 63) == 63) atomicMax(&s.cfl, (unsigned long long)__double_as_longlong(cm));
+    __syncthreads();
+    cfl = fmax(cfl, __longlong_as_double((long long)s.cfl));
+}
+
+template <int MX, int NT>
+__global__ void __launch_bounds__(NT) advance_mapped_kernel(Ctx c, int first, int count, int level, double t,
+                                                            double dt) {
+    __shared__ MappedSmem<MX> s;
+    const int p = first + xcd_remap(blockIdx.x, count);
+    unsigned long long *slot = c.cflp ? c.cflp + p : nullptr;
+    const double old = cfl_slot_old(slot);
+    double cfl = 0.0;
+    const View w = view_of(c);
+    switch (c.lim) {
+        case 1: advance_mapped_patch<MX, NT, 1>(c, w, s, p, level, t, dt, cfl); break;
+        case 2: advance_mapped_patch<MX, NT, 2>(c, w, s, p, level, t, dt, cfl); break;
+        case 3: advance_mapped_patch<MX, NT, 3>(c, w, s, p, level, t, dt, cfl); break;
+        default: advance_mapped_patch<MX, NT, 0>(c, w, s, p, level, t, dt, cfl); break;
+    }
+    store_cfl_slot(slot, old, cfl);
 }
 
 // one step of a uniform periodic level from leaf-order q_in to q_out
@@ -1827,8 +2033,20 @@ __global__ void transfer_kernel(Ctx c, const TransferRec *plan) {
                 const int cx = i >= MX / 2, cy = j >= MX / 2;
                 const int s = tr.src[cx + 2 * cy];
                 const int fi = 2 * i - cx * MX, fj = 2 * j - cy * MX;
-                v = 0.25 * (c.q0[qidx(c.cap, N, f, s, fi, fj)] + c.q0[qidx(c.cap, N, f, s, fi + 1, fj)] +
-                            c.q0[qidx(c.cap, N, f, s, fi, fj + 1)] + c.q0[qidx(c.cap, N, f, s, fi + 1, fj + 1)]);
+                const double y0 = c.q0[qidx(c.cap, N, f, s, fi, fj)], y1 = c.q0[qidx(c.cap, N, f, s, fi + 1, fj)];
+                const double y2 = c.q0[qidx(c.cap, N, f, s, fi, fj + 1)], y3 = c.q0[qidx(c.cap, N, f, s, fi + 1, fj + 1)];
+                if (c.mapped) {
+                    // area-weighted on a mapped grid; the new patch's cell
+                    // (i, j) covers fine cells 2 (I, J) + {0, 1}
+                    const PatchInfo P = c.info[p];
+                    const int lf = P.level + 1, n = MX << lf;
+                    const int I = 2 * (P.ix * MX + i), J = 2 * (P.iy * MX + j);
+                    const double a0 = capacity_at(c, lf, n, I, J), a1 = capacity_at(c, lf, n, I + 1, J);
+                    const double a2 = capacity_at(c, lf, n, I, J + 1), a3 = capacity_at(c, lf, n, I + 1, J + 1);
+                    v = (a0 * y0 + a1 * y1 + a2 * y2 + a3 * y3) / (a0 + a1 + a2 + a3);
+                } else {
+                    v = 0.25 * (y0 + y1 + y2 + y3);
+                }
             }
             c.q1[qidx(c.cap, N, f, p, i, j)] = v;
         }
@@ -1995,6 +2213,11 @@ hipError_t launch_extract_leaves(const int8_t *a, int L, int cap, int32_t *count
     hipLaunchKernelGGL(extract_kernel, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, s, a, g, cap, count, out);
     return hipGetLastError();
 }
+hipError_t launch_init_capacity(int n, double alpha, double *K, hipStream_t s) {
+    hipLaunchKernelGGL(init_capacity_kernel, dim3((n + 255) / 256), dim3(256), 0, s, n, alpha, K);
+    return hipGetLastError();
+}
+
 hipError_t launch_init_tables(int level, int mx, int periodic_x, int periodic_y, double *vt, hipStream_t s) {
     const int n = mx << level;
     const int tot = n + 2 * MB + 1;
@@ -2037,6 +2260,7 @@ hipError_t launch_copy_interiors(const Ctx &c, int mx, int n, double *save, int 
 template <int MX>
 static hipError_t fill_mx(const Ctx &c, int first, int count, hipStream_t s) {
     if (c.F == 3) hipLaunchKernelGGL((fill_kernel<MX, 3>), dim3(count), dim3(256), 0, s, c, first);
+    else if (c.mapped) hipLaunchKernelGGL((fill_kernel<MX, 1, true>), dim3(count), dim3(256), 0, s, c, first);
     else hipLaunchKernelGGL((fill_kernel<MX, 1>), dim3(count), dim3(256), 0, s, c, first);
     return hipGetLastError();
 }
@@ -2069,6 +2293,15 @@ static hipError_t adv_swe(const Ctx &c, int first, int count, double dt, int fus
 hipError_t launch_advance(const Ctx &c, LaunchCfg lc, int level, int first, int count, double t, double dt,
                           int fused, hipStream_t s) {
     if (count <= 0) return hipSuccess;
+    if (c.mapped) {
+        // capacity form on filled patches only (fused == 0)
+        if (fused) return hipErrorInvalidValue;
+        if (lc.mx == 8) hipLaunchKernelGGL((advance_mapped_kernel<8, 64>), dim3(count), dim3(64), 0, s, c, first, count, level, t, dt);
+        else if (lc.mx == 16) hipLaunchKernelGGL((advance_mapped_kernel<16, 256>), dim3(count), dim3(256), 0, s, c, first, count, level, t, dt);
+        else if (lc.mx == 32) hipLaunchKernelGGL((advance_mapped_kernel<32, 256>), dim3(count), dim3(256), 0, s, c, first, count, level, t, dt);
+        else return hipErrorInvalidValue;
+        return hipGetLastError();
+    }
     if (c.eq == 0) {
 #define ADV(MXV, NTV) if (lc.mx == MXV && lc.nt == NTV) return adv_scalar<MXV, NTV>(c, first, count, level, t, dt, fused, s);
         ADV(8, 64) ADV(8, 128) ADV(16, 64) ADV(16, 128) ADV(16, 256) ADV(32, 128) ADV(32, 256) ADV(32, 512)

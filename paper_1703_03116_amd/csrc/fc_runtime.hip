@@ -190,7 +190,8 @@ struct fc_patchstore {
     char *ws = nullptr;
     size_t ws_bytes = 0;
     size_t off_info = 0, off_nbr = 0, off_sl = 0, off_ls = 0, off_lr = 0, off_sched = 0, off_state = 0,
-           off_plan = 0, off_tag = 0, off_cfl = 0, off_cflv = 0, off_save = 0, off_vt[FC_MAXLEV] = {0};
+           off_plan = 0, off_tag = 0, off_cfl = 0, off_cflv = 0, off_save = 0, off_vt[FC_MAXLEV] = {0},
+           off_mk[FC_MAXLEV] = {0};
     // adaptation on the device (max_level <= kAdaptMaxLevel): owner map, two
     // level maps of the finest level, per-slot target and maximum, leaf list,
     // flags (0: changed, 1: leaf count)
@@ -422,6 +423,11 @@ void layout_workspace(fc_patchstore *ps) {
         if (l >= ps->cfg.min_level && l <= ps->cfg.max_level && ps->cfg.velocity == FC_VEL_SWIRL)
             o = align256(o + sizeof(double) * (size_t)vt_size(ps->mx << l, MBK));
     }
+    for (int l = 0; l < FC_MAXLEV; l++) {
+        ps->off_mk[l] = o;
+        if (l >= ps->cfg.min_level && l <= ps->cfg.max_level && ps->cfg.map_alpha != 0.0)
+            o = align256(o + sizeof(double) * (size_t)(ps->mx << l));
+    }
     ps->ws_bytes = o;
 }
 
@@ -454,6 +460,10 @@ Ctx make_ctx(const fc_patchstore *ps) {
     // keep the next step's input in the Infinity Cache.
     const double foot = 2.0 * 8.0 * (double)ps->F * (double)ps->N * ps->N * (double)ps->mesh.lv.size();
     c.stream_out = (foot <= 48.0 * 1048576.0 || foot >= 256.0 * 1048576.0) ? 1 : 0;
+    c.mapped = ps->cfg.map_alpha != 0.0;
+    for (int l = 0; l < FC_MAXLEV; l++)
+        c.mk[l] = (c.mapped && l >= ps->cfg.min_level && l <= ps->cfg.max_level)
+                      ? (const double *)(ps->ws + ps->off_mk[l]) : nullptr;
     const bool per = ps->cfg.bc[0] == FC_BC_PERIODIC && ps->cfg.bc[2] == FC_BC_PERIODIC;
     for (int l = 0; l < FC_MAXLEV; l++) {
         c.lstart[l] = ps->lr.start[l];
@@ -691,6 +701,13 @@ fc_status fc_patchstore_create_brick(const fc_config *cfg, int32_t nbx, int32_t 
     if (cfg->equation == FC_EQ_ADVECTION && cfg->velocity == FC_VEL_NONE) return fail(FC_ERR_ARG, "advection needs a velocity");
     if (cfg->velocity == FC_VEL_SWIRL && !(cfg->vel_params[0] > 0)) return fail(FC_ERR_ARG, "swirl period must be > 0");
     if (!(cfg->cfl_max >= 0.0)) return fail(FC_ERR_ARG, "cfl_max must be >= 0 (0: not checked)");
+    if (!(fabs(cfg->map_alpha) < 0.5 / M_PI)) return fail(FC_ERR_ARG, "map_alpha must satisfy |alpha| < 1/(2 pi)");
+    if (cfg->map_alpha != 0.0) {
+        if (multi || nbx * nby > 1) return fail(FC_ERR_ARG, "a mapped grid takes one block");
+        if (cfg->equation != FC_EQ_ADVECTION) return fail(FC_ERR_ARG, "a mapped grid takes scalar advection");
+        for (int s = 0; s < 4; s++)
+            if (cfg->bc[s] != FC_BC_PERIODIC) return fail(FC_ERR_ARG, "a mapped grid takes periodic sides");
+    }
     std::vector<fc_leaf> L(leaves, leaves + nleaves);
     for (const auto &q : L) {
         if (q.level < cfg->min_level || q.level > cfg->max_level) return fail(FC_ERR_ARG, "leaf level outside [min_level, max_level]");
@@ -761,6 +778,9 @@ fc_status fc_patchstore_bind(fc_patchstore *ps, double *q0, double *q1, void *wo
         for (int l = ps->cfg.min_level; l <= ps->cfg.max_level; l++)
             HIPCHK(launch_init_tables(l, ps->mx, ps->cfg.bc[0] == FC_BC_PERIODIC, ps->cfg.bc[2] == FC_BC_PERIODIC,
                                       (double *)(ps->ws + ps->off_vt[l]), s));
+    if (ps->cfg.map_alpha != 0.0)
+        for (int l = ps->cfg.min_level; l <= ps->cfg.max_level; l++)
+            HIPCHK(launch_init_capacity(ps->mx << l, ps->cfg.map_alpha, (double *)(ps->ws + ps->off_mk[l]), s));
     ps->pgrid = persistent_max_grid(persistent_cfg(ps), ps->cfg.equation);
     HIPCHK(hipStreamSynchronize(s));
     return FC_OK;
@@ -936,6 +956,8 @@ fc_status fc_prepare_steps(fc_patchstore *ps, double dt_coarse, int32_t nsteps, 
     fc_status r = check_bound(ps);
     if (r != FC_OK) return r;
     if (!(dt_coarse > 0) || nsteps < 0) return fail(FC_ERR_ARG, "bad step arguments");
+    if (ps->cfg.map_alpha != 0.0 && mode != FC_MODE_PER_LEVEL)
+        return fail(FC_ERR_ARG, "a mapped grid steps in FC_MODE_PER_LEVEL only");
     if (mode == FC_MODE_PER_LEVEL || mode == FC_MODE_FUSED_LEVELS || mode == FC_MODE_FUSED) return FC_OK;
     if (mode != FC_MODE_FUSED_GRAPH && mode != FC_MODE_PERSISTENT_GRAPH) return fail(FC_ERR_ARG, "unknown mode");
     if (ps->pgrid <= 0) return fail(FC_ERR_HIP, "persistent kernel has no resident blocks");
@@ -958,6 +980,8 @@ static fc_status advance_steps(fc_patchstore *ps, double dt_coarse, int32_t nste
     fc_status r = check_bound(ps);
     if (r != FC_OK) return r;
     if (!(dt_coarse > 0) || nsteps < 0) return fail(FC_ERR_ARG, "bad step arguments");
+    if (ps->cfg.map_alpha != 0.0 && mode != FC_MODE_PER_LEVEL)
+        return fail(FC_ERR_ARG, "a mapped grid steps in FC_MODE_PER_LEVEL only");
     const bool cfl = cfl_dev != nullptr;
     const double cmax = flag_cfl ? ps->cfg.cfl_max : 0.0;
     const int nleaf = (int)ps->mesh.lv.size();
@@ -1313,6 +1337,7 @@ static fc_status check_uniform_periodic(fc_patchstore *ps, int32_t level, double
     if (r != FC_OK) return r;
     if (ps->cfg.equation != FC_EQ_ADVECTION) return fail(FC_ERR_ARG, "scalar advection only");
     if (ps->multiblock) return fail(FC_ERR_ARG, "one block of orientation code 0 only");
+    if (ps->cfg.map_alpha != 0.0) return fail(FC_ERR_ARG, "a Cartesian grid only (map_alpha = 0)");
     if (level < ps->cfg.min_level || level > ps->cfg.max_level) return fail(FC_ERR_ARG, "bad level");
     if (ps->lr.count[level] != (int)ps->mesh.lv.size()) return fail(FC_ERR_ARG, "needs a uniform mesh at `level`");
     if (!(dt > 0)) return fail(FC_ERR_ARG, "dt must be positive");
@@ -1381,6 +1406,7 @@ fc_status fc_set_variant(fc_patchstore *ps, int32_t threads_per_patch) {
 fc_status fc_autotune(fc_patchstore *ps, int32_t *threads_out, void *stream) {
     fc_status r = check_bound(ps);
     if (r != FC_OK) return r;
+    if (ps->cfg.map_alpha != 0.0) return fail(FC_ERR_ARG, "a mapped grid has one advance kernel: nothing to tune");
     hipStream_t s = (hipStream_t)stream;
     // time the fused-load advance of the most populated level, writing only
     // the levels' other buffers (the state is left unchanged)

@@ -220,6 +220,49 @@ def test_cfl_max_validation(B):
     L.fc_patchstore_destroy(h0)
 
 
+def test_map_alpha_validation(B):
+    """A mapped grid (Sec. 1 metric terms) needs an invertible mapping,
+    |alpha| < 1/(2 pi), one periodic block and scalar advection; its
+    capacity tables take workspace; unbound calls fail before device work."""
+    L = B.lib()
+    arr, n = B._leaves_array(S.uniform_leaves(1))
+
+    def make(alpha, **kw):
+        cfg = make_cfg(B, **{k: v for k, v in kw.items() if k in ("bc", "lmax")})
+        cfg.map_alpha = alpha
+        if kw.get("swe"):
+            cfg.equation = 1
+        h = C.c_void_p()
+        if "brick" in kw:
+            barr, nb = B._leaves_array(kw["leaves"])
+            st = L.fc_patchstore_create_brick(C.byref(cfg), kw["brick"][0], kw["brick"][1], None, nb, barr,
+                                              C.byref(h), None)
+        else:
+            st = L.fc_patchstore_create(C.byref(cfg), n, arr, C.byref(h), None)
+        return st, h
+
+    lim = 0.5 / np.pi
+    for a in (lim, -lim, 0.2, float("nan"), float("inf")):
+        assert make(a)[0] == -1, a
+    assert make(0.1, bc=("reflect",) * 4)[0] == -1
+    assert make(0.1, swe=True)[0] == -1
+    assert make(0.1, brick=(2, 1), leaves=S.uniform_leaves(1, (2, 1)))[0] == -1
+    st, h = make(np.nextafter(lim, 0.0), lmax=3)
+    assert st == 0
+    st0, h0 = make(0.0, lmax=3)
+    assert st0 == 0
+    w, w0, q = C.c_int64(), C.c_int64(), C.c_int64()
+    assert L.fc_patchstore_sizes(h, C.byref(q), C.byref(w)) == 0
+    assert L.fc_patchstore_sizes(h0, C.byref(q), C.byref(w0)) == 0
+    assert w.value - w0.value >= 8 * 8 * (2 + 4 + 8)   # one table per level, n doubles
+    nt = C.c_int32()
+    # not bound: FC_ERR_STATE before any device work
+    assert L.fc_autotune(h, C.byref(nt), None) == -6
+    assert L.fc_advance_coarse_steps(h, 0.01, 1, 2, None, None) == -6
+    L.fc_patchstore_destroy(h)
+    L.fc_patchstore_destroy(h0)
+
+
 def create_brick(B, leaves, brick, orient, equation=0, velocity=1, **kw):
     cfg = make_cfg(B, **kw)
     cfg.equation, cfg.velocity = equation, velocity
