@@ -1321,10 +1321,13 @@ fc_status fc_regrid(fc_patchstore *ps, int64_t nleaves, const fc_leaf *new_leave
     build_metadata(ps, L);
     HIPCHK(hipMemcpyAsync(ps->ws + ps->off_plan, plan.data(), sizeof(TransferRec) * n, hipMemcpyHostToDevice, s));
     ps->curmask = ~0u;  // new data lives in buffer 1 for every level
-    Ctx nc = make_ctx(ps);
-    HIPCHK(launch_transfer(nc, ps->mx, (const TransferRec *)(ps->ws + ps->off_plan), n, s));
+    // the new slots' geometry first: the transfer reads it (area weights
+    // of a mapped grid); consolidation, which read the old, is ahead in
+    // the stream
     r = upload_metadata(ps, s);
     if (r != FC_OK) return r;
+    Ctx nc = make_ctx(ps);
+    HIPCHK(launch_transfer(nc, ps->mx, (const TransferRec *)(ps->ws + ps->off_plan), n, s));
     drop_graph(ps);     // level populations changed: recapture on next use
     HIPCHK(hipStreamSynchronize(s));
     return FC_OK;
