@@ -339,15 +339,17 @@ fc_status fc_check_device(fc_patchstore *ps, void *stream);
 
 /* Choose the launch configuration (waves per patch) of the advance kernels
  * by timing every variant on the bound store (results are bitwise equal); a
- * variant other than the default (scalar advection: 64 threads at mx = 8,
- * else 256; shallow water: 192 at mx = 8, 512 at mx = 16) is taken only if
- * it is at least 5% faster (best of three interleaved timing rounds).
+ * variant other than the default (scalar advection, also on a mapped grid:
+ * 64 threads at mx = 8, else 256; shallow water: 192 at mx = 8, 512 at
+ * mx = 16) is taken only if it is at least 5% faster (best of three
+ * interleaved timing rounds).
  * Returns the chosen threads per patch. */
 fc_status fc_autotune(fc_patchstore *ps, int32_t *threads_out, void *stream);
 /* Set the threads per patch directly.  Scalar advection: 64 or 128 at
  * mx = 8; 64, 128 or 256 at mx = 16; 128, 256 or 512 at mx = 32.  Shallow
- * water: 64, 128 or 192 at mx = 8; 256, 384, 512 or 640 at mx = 16.  FC_ERR_ARG
- * otherwise.  Drops captured graphs. */
+ * water: 64, 128 or 192 at mx = 8; 256, 384, 512 or 640 at mx = 16 (a
+ * mapped grid: those of scalar advection).  FC_ERR_ARG otherwise.  Drops
+ * captured graphs. */
 fc_status fc_set_variant(fc_patchstore *ps, int32_t threads_per_patch);
 /* Workgroups of the persistent kernel: 0 = as many as can be co-resident
  * (occupancy x compute units), else min(grid, that).  max_grid (may be

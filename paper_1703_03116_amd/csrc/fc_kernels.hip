@@ -1031,134 +1031,209 @@ __global__ void init_capacity_kernel(int n, double alpha, double *K) {
     K[k] = 1.0 + 2.0 * M_PI * alpha * (sig * sig) * sin(2.0 * M_PI * ((double)k * h));
 }
 
+// The mapped step has the Cartesian step's structure (line sweeps that keep
+// partial sums in registers, transverse terms TX / TY staged in LDS) with
+// dt / h replaced per cell by dt / (kappa h), which depends on I + J only:
+// one value per diagonal of the tile.  Capacity form (Clawpack's, the form
+// mapped-grid wave propagation takes): the fluctuations entering a cell and
+// its flux differences are scaled by that cell's dt / (kappa h); a
+// transverse wave by that of the cell its corrected fluctuation entered (so
+// TX(i, j) = dt / (kappa h)_{ij} (A+* W_{i-1/2} + A-* W_{i+1/2})); the
+// correction C = |s| (1 - nubar |s|) W~ takes nubar, the mean over the edge's
+// two cells; the Courant number is dt / (kappa h) of the cell a wave enters
+// times its speed.
 template <int MX>
-struct MappedSmem {
-    static constexpr int N = MX + 2 * MB, NP = N + 1;
-    static constexpr int EX = (MX + 1) * (MX + 2);  // edges of one direction, lines -1 .. MX
-    double q[N * NP];
-    double lk[N * NP];                     // dt / (kappa h) of every tile cell
-    double ap[EX], am[EX], cx[EX];         // x-edge (i, j), i in [0, MX], j in [-1, MX]: s+ W, s- W, C
-    double bp[EX], bm[EX], cy[EX];         // y-edge (i, j), i in [-1, MX], j in [0, MX]
-    double ux[MX + 1], uy[MX + 2], vy[MX + 1], vx[MX + 2];  // velocity factors, as the scalar step
-    double red[16];
-    unsigned long long cfl;
+struct MappedSmem : ScalarSmem<MX> {
+    double dk[2 * (MX + 2 * MB)];  // dt / (kappa h) of the cells (i, j) with i + j = d - 2 MB
+    unsigned long long mcfl;       // the patch's Courant number (bits of a non-negative double)
 };
 
-template <int MX>
-__device__ __forceinline__ int xe_idx(int i, int j) { return (j + 1) * (MX + 1) + i; }
-template <int MX>
-__device__ __forceinline__ int ye_idx(int i, int j) { return (i + 1) * (MX + 1) + j; }
+// One segment of one interior line (as sweep_segment): edges e0 .. e0+SEG,
+// cells e0 .. e0+SEG-1; TX (TY) of the cells into LDS and the line's partial
+// update of each cell in R:
+//   rows     Rx = Q - TX + L/2 (C_{i+1/2} - C_{i-1/2}),
+//   columns  Ry = L/2 (C_{j+1/2} - C_{j-1/2}) - TY,
+// L the cell's dt / (kappa h); cm: the largest Courant number of the edges.
+template <int MX, int SEG, int LIM, int DIR>
+__device__ __forceinline__ void msweep_segment(MappedSmem<MX> &s, int line, int e0, double (&R)[SEG], double &cm) {
+    constexpr int NP = ScalarSmem<MX>::NP, S = ScalarSmem<MX>::S;
+    constexpr int STR = DIR == 0 ? 1 : NP;
+    const double *qp = DIR == 0 ? &s.q[(line + MB) * NP + MB + e0 - 2] : &s.q[(MB + e0 - 2) * NP + line + MB];
+    const double *ve = DIR == 0 ? &s.ux[e0] : &s.vy[e0];
+    const double vl = DIR == 0 ? s.uy[line + 1] : s.vx[line + 1];
+    const double *lk = &s.dk[line + e0 - 1 + 2 * MB];  // lk[k]: cell e0 - 1 + k of the line
+    double q[SEG + 4], L[SEG + 2];
+#pragma unroll
+    for (int k = 0; k < SEG + 4; k++) q[k] = qp[k * STR];
+#pragma unroll
+    for (int k = 0; k < SEG + 2; k++) L[k] = lk[k];
+    double aprev = 0.0, cprev = 0.0;
+#pragma unroll
+    for (int k = 0; k <= SEG; k++) {  // edge e0 + k, between cells e0+k-1 (q[k+1], L[k]) and e0+k (q[k+2], L[k+1])
+        const double u = ve[k] * vl;
+        const double W = q[k + 2] - q[k + 1];
+        const double Wu = u > 0.0 ? q[k + 1] - q[k] : q[k + 3] - q[k + 2];
+        const double au = fabs(u);
+        const double C = correction<LIM>(W, Wu, au, 0.5 * (L[k] + L[k + 1]));
+        const double aps = posp(u) * W - C;
+        const double ams = negp(u) * W + C;
+        cm = fmax(cm, u > 0.0 ? L[k + 1] * u : (u < 0.0 ? L[k] * -u : 0.0));
+        if (k > 0) {  // cell e0 + k - 1
+            const int cc = e0 + k - 1;
+            const double T = L[k] * (aprev + ams);
+            if (DIR == 0) {
+                s.tx[(line + 1) * S + cc] = T;
+                R[k - 1] = q[k + 1] - T + (0.5 * L[k]) * (C - cprev);
+            } else {
+                s.ty[(line + 1) * S + cc] = T;
+                R[k - 1] = (0.5 * L[k]) * (C - cprev) - T;
+            }
+        }
+        aprev = aps;
+        cprev = C;
+    }
+}
 
-// One capacity-form step (Clawpack's, the form mapped-grid wave propagation
-// takes) of patch p on its filled tile: every x- and y-edge's fluctuations
-// s+- W and limited correction C = |s| (1 - nubar |s|) W~, nubar the mean of
-// dt / (kappa h) over the edge's two cells; then each edge's flux F~ (G~) is
-// gathered: 1/2 C plus the transverse waves of the four adjacent edges of
-// the other direction, each scaled by dt / (kappa h) of the cell its
-// corrected fluctuation entered; then Q -= dt / (kappa h) (fluctuations +
-// flux differences).  The Courant number is dt / (kappa h) of the cell a wave
-// enters times its speed.
+// The same for a line outside the interior (as sweep_outer): TX (TY) only.
+template <int MX, int SEG, int LIM>
+__device__ __forceinline__ void msweep_outer(MappedSmem<MX> &s, int dir, int line, int e0) {
+    constexpr int NP = ScalarSmem<MX>::NP, S = ScalarSmem<MX>::S;
+    const int str = dir == 0 ? 1 : NP;
+    const double *qp = dir == 0 ? &s.q[(line + MB) * NP + MB + e0 - 2] : &s.q[(MB + e0 - 2) * NP + line + MB];
+    const double *ve = dir == 0 ? &s.ux[e0] : &s.vy[e0];
+    const double vl = dir == 0 ? s.uy[line + 1] : s.vx[line + 1];
+    const double *lk = &s.dk[line + e0 - 1 + 2 * MB];
+    double *to = (dir == 0 ? s.tx : s.ty) + (line + 1) * S + e0 - 1;
+    double q[SEG + 4], L[SEG + 2];
+#pragma unroll
+    for (int k = 0; k < SEG + 4; k++) q[k] = qp[k * str];
+#pragma unroll
+    for (int k = 0; k < SEG + 2; k++) L[k] = lk[k];
+    double aprev = 0.0;
+#pragma unroll
+    for (int k = 0; k <= SEG; k++) {
+        const double u = ve[k] * vl;
+        const double W = q[k + 2] - q[k + 1];
+        const double Wu = u > 0.0 ? q[k + 1] - q[k] : q[k + 3] - q[k + 2];
+        const double C = correction<LIM>(W, Wu, fabs(u), 0.5 * (L[k] + L[k + 1]));
+        const double ams = negp(u) * W + C;
+        if (k > 0) to[k] = L[k] * (aprev + ams);
+        aprev = posp(u) * W - C;
+    }
+}
+
+// Transverse terms of a row segment: R += L/2 (TF_{i+1/2} - TF_{i-1/2}),
+// TF(e) = u+ TY(e-1) + u- TY(e) (the TY already scaled by their cells' L);
+// columns likewise with TG and TX.
+template <int MX, int SEG>
+__device__ __forceinline__ void mpart_row(const MappedSmem<MX> &s, int j, int e0, double (&R)[SEG]) {
+    constexpr int S = ScalarSmem<MX>::S;
+    const double uyj = s.uy[j + 1];
+    double ty[SEG + 2];
+#pragma unroll
+    for (int k = 0; k < SEG + 2; k++) ty[k] = s.ty[(e0 + k) * S + j];  // TY(e0 - 1 + k, j)
+    double tf[SEG + 1];
+#pragma unroll
+    for (int k = 0; k <= SEG; k++) {
+        const double u = s.ux[e0 + k] * uyj;
+        tf[k] = posp(u) * ty[k] + negp(u) * ty[k + 1];
+    }
+#pragma unroll
+    for (int k = 0; k < SEG; k++) R[k] = R[k] + (0.5 * s.dk[e0 + k + j + 2 * MB]) * (tf[k + 1] - tf[k]);
+}
+
+template <int MX, int SEG>
+__device__ __forceinline__ void mpart_col(const MappedSmem<MX> &s, int i, int e0, double (&R)[SEG]) {
+    constexpr int S = ScalarSmem<MX>::S;
+    const double vxi = s.vx[i + 1];
+    double tx[SEG + 2];
+#pragma unroll
+    for (int k = 0; k < SEG + 2; k++) tx[k] = s.tx[(e0 + k) * S + i];  // TX(i, e0 - 1 + k)
+    double tg[SEG + 1];
+#pragma unroll
+    for (int k = 0; k <= SEG; k++) {
+        const double v = s.vy[e0 + k] * vxi;
+        tg[k] = posp(v) * tx[k] + negp(v) * tx[k + 1];
+    }
+#pragma unroll
+    for (int k = 0; k < SEG; k++) R[k] = R[k] + (0.5 * s.dk[i + e0 + k + 2 * MB]) * (tg[k + 1] - tg[k]);
+}
+
+// One capacity-form step of patch p (level lev, or its own if lev < 0) on
+// its filled tile; the work split is the Cartesian step's.
 template <int MX, int NT, int LIM>
 __device__ void advance_mapped_patch(const Ctx &c, const View &w, MappedSmem<MX> &s, int p, int lev, double t,
                                      double dt, double &cfl) {
-    constexpr int N = MX + 2 * MB, NP = N + 1, EX = MappedSmem<MX>::EX;
+    constexpr int N = MX + 2 * MB, NP = ScalarSmem<MX>::NP, S = ScalarSmem<MX>::S;
+    constexpr int SEG = scalar_seg<MX, NT>(), NSEG = MX / SEG, NI = MX * NSEG, HI = NI / 2;
+    constexpr int SO = 2, NO = 4 * (MX / SO);
+    constexpr int GT0 = (NT - 2 * NI >= NO) ? 2 * NI : NI;
+    static_assert(2 * NI <= NT && NSEG % 2 == 0, "interior items must fit one pass, in two halves");
+    static_assert(GT0 + NO <= NT, "outer-line items must fit one pass");
+    static_assert(NI + MX + 2 <= NT, "velocity factors are loaded by threads NI .. NI+MX+1");
     const int tid = threadIdx.x;
     const PatchInfo P = c.info[p];
     const int l = lev >= 0 ? lev : P.level, n = MX << l;
     const double lam = dt * (double)n;  // dt / h, exact
-    const int gx = P.ix * MX, gy = P.iy * MX;
     const double *in = buf_of(c, w, l);
     double *out = other_of(c, w, l);
     const size_t base = (size_t)p * N * N;
-    for (int k = tid; k < N * N; k += NT) {
-        const int i = k % N, j = k / N;
-        s.q[j * NP + i] = in[base + k];
-        s.lk[j * NP + i] = lam / capacity_at(c, l, n, gx + i - MB, gy + j - MB);
+    load_velocity<MX>(c, s, l, P.ix * MX, P.iy * MX, t, dt, nullptr, NI);
+    for (int k = tid; k < N * N / 2; k += NT) {
+        const int i = 2 * (k % (N / 2)), j = k / (N / 2);
+        const double2 v = *reinterpret_cast<const double2 *>(&in[base + j * N + i]);
+        s.q[j * NP + i] = v.x;
+        s.q[j * NP + i + 1] = v.y;
     }
-    // velocity factors at the mid-step time (the scalar step's tables)
-    const double tm = t + 0.5 * dt;
-    const double ct = c.velocity == 2 ? cos(M_PI * (tm * c.vel_invT)) : 1.0;
-    for (int k = tid; k < MX + 2; k += NT) {
-        if (c.velocity == 2) {
-            const double *vt = c.vt[l];
-            if (k <= MX) {
-                s.ux[k] = vt[vt_ex(n, MB) + gx + k];
-                s.vy[k] = vt[vt_ey(n, MB) + gy + k];
-            }
-            s.uy[k] = vt[vt_cy(n, MB) + gy + k - 1] * ct;
-            s.vx[k] = -(vt[vt_cx(n, MB) + gx + k - 1] * ct);
-        } else {
-            if (k <= MX) { s.ux[k] = c.vel_u; s.vy[k] = c.vel_v; }
-            s.uy[k] = 1.0;
-            s.vx[k] = 1.0;
-        }
+    for (int d = tid; d < 2 * N - 1; d += NT) {
+        int k = (P.ix * MX + P.iy * MX + d - 2 * MB + 1) % n;
+        k = k < 0 ? k + n : k;
+        s.dk[d] = lam / c.mk[l][k];
     }
-    if (tid == 0) s.cfl = 0ull;
+    if (tid == 0) s.mcfl = 0ull;
     __syncthreads();
-    auto Q = [&](int i, int j) { return s.q[(j + MB) * NP + i + MB]; };
-    auto LK = [&](int i, int j) { return s.lk[(j + MB) * NP + i + MB]; };
+    double R[SEG];
     double cm = 0.0;
-    // every edge of both directions: fluctuations and correction
-    for (int e = tid; e < 2 * EX; e += NT) {
-        const bool xd = e < EX;
-        const int k = xd ? e : e - EX;
-        int i, j;
-        if (xd) { i = k % (MX + 1); j = k / (MX + 1) - 1; }
-        else { j = k % (MX + 1); i = k / (MX + 1) - 1; }
-        const int di = xd ? 1 : 0, dj = xd ? 0 : 1;   // edge between cell (i-di, j-dj) and (i, j)
-        const double sp = xd ? s.ux[i] * s.uy[j + 1] : s.vy[j] * s.vx[i + 1];
-        const double W = Q(i, j) - Q(i - di, j - dj);
-        const double Wu = sp > 0.0 ? Q(i - di, j - dj) - Q(i - 2 * di, j - 2 * dj) : Q(i + di, j + dj) - Q(i, j);
-        const double lr = LK(i, j), ll = LK(i - di, j - dj);
-        const double C = correction<LIM>(W, Wu, fabs(sp), 0.5 * (ll + lr));
-        if (xd) { s.ap[k] = posp(sp) * W; s.am[k] = negp(sp) * W; s.cx[k] = C; }
-        else { s.bp[k] = posp(sp) * W; s.bm[k] = negp(sp) * W; s.cy[k] = C; }
-        const bool inner = xd ? (j >= 0 && j < MX) : (i >= 0 && i < MX);
-        const double cw = sp > 0.0 ? lr * sp : (sp < 0.0 ? ll * -sp : 0.0);
-        if (inner) cm = fmax(cm, cw);
+    int line = 0, e0 = 0;
+    const bool xs = tid < NI, ys = !xs && tid < 2 * NI;
+    const int half = (xs ? tid : tid - NI) / HI, r = (xs ? tid : tid - NI) % HI;
+    if (xs) {
+        line = half * (MX / 2) + r % (MX / 2);
+        e0 = (r / (MX / 2)) * SEG;
+        msweep_segment<MX, SEG, LIM, 0>(s, line, e0, R, cm);
+    } else if (ys) {
+        line = r % MX;
+        e0 = (half * (NSEG / 2) + r / MX) * SEG;
+        msweep_segment<MX, SEG, LIM, 1>(s, line, e0, R, cm);
     }
-    __syncthreads();
-    // fluxes gathered per edge, then the update of each interior cell
-    for (int k = tid; k < MX * MX; k += NT) {
-        const int i = k % MX, j = k / MX;
-        auto Fx = [&](int I, int J) {  // F~ at x-edge (I, J), J an interior row
-            const double u = s.ux[I] * s.uy[J + 1];
-            const double up = posp(u), un = negp(u);
-            double f = 0.5 * s.cx[xe_idx<MX>(I, J)];
-            const double bps0 = s.bp[ye_idx<MX>(I - 1, J)] - s.cy[ye_idx<MX>(I - 1, J)];
-            const double bps1 = s.bp[ye_idx<MX>(I, J)] - s.cy[ye_idx<MX>(I, J)];
-            const double bms0 = s.bm[ye_idx<MX>(I - 1, J + 1)] + s.cy[ye_idx<MX>(I - 1, J + 1)];
-            const double bms1 = s.bm[ye_idx<MX>(I, J + 1)] + s.cy[ye_idx<MX>(I, J + 1)];
-            f -= 0.5 * LK(I - 1, J) * up * bps0;
-            f -= 0.5 * LK(I, J) * un * bps1;
-            f -= 0.5 * LK(I - 1, J) * up * bms0;
-            f -= 0.5 * LK(I, J) * un * bms1;
-            return f;
-        };
-        auto Gy = [&](int I, int J) {  // G~ at y-edge (I, J), I an interior column
-            const double v = s.vy[J] * s.vx[I + 1];
-            const double vp = posp(v), vn = negp(v);
-            double g = 0.5 * s.cy[ye_idx<MX>(I, J)];
-            const double aps0 = s.ap[xe_idx<MX>(I, J - 1)] - s.cx[xe_idx<MX>(I, J - 1)];
-            const double aps1 = s.ap[xe_idx<MX>(I, J)] - s.cx[xe_idx<MX>(I, J)];
-            const double ams0 = s.am[xe_idx<MX>(I + 1, J - 1)] + s.cx[xe_idx<MX>(I + 1, J - 1)];
-            const double ams1 = s.am[xe_idx<MX>(I + 1, J)] + s.cx[xe_idx<MX>(I + 1, J)];
-            g -= 0.5 * LK(I, J - 1) * vp * aps0;
-            g -= 0.5 * LK(I, J) * vn * aps1;
-            g -= 0.5 * LK(I, J - 1) * vp * ams0;
-            g -= 0.5 * LK(I, J) * vn * ams1;
-            return g;
-        };
-        const double fl = s.ap[xe_idx<MX>(i, j)] + s.am[xe_idx<MX>(i + 1, j)] + s.bp[ye_idx<MX>(i, j)] +
-                          s.bm[ye_idx<MX>(i, j + 1)];
-        const double df = Fx(i + 1, j) - Fx(i, j) + Gy(i, j + 1) - Gy(i, j);
-        const double lc = LK(i, j);
-        out[base + (size_t)(j + MB) * N + i + MB] = Q(i, j) - lc * fl - lc * df;
+    if (tid >= GT0 && tid < GT0 + NO) {  // rows -1, MX and columns -1, MX: TX, TY only
+        const int k = tid - GT0, g = k / (MX / SO);
+        msweep_outer<MX, SO, LIM>(s, g >> 1, (g & 1) ? MX : -1, (k % (MX / SO)) * SO);
     }
     cm = wave_max_last_lane(cm);
-    if ((tid & 63) == 63) atomicMax(&s.cfl, (unsigned long long)__double_as_longlong(cm));
+    if ((tid & 63) == 63) atomicMax(&s.mcfl, (unsigned long long)__double_as_longlong(cm));
     __syncthreads();
-    cfl = fmax(cfl, __longlong_as_double((long long)s.cfl));
+    if (xs) {
+        mpart_row<MX, SEG>(s, line, e0, R);
+#pragma unroll
+        for (int k = 0; k < SEG; k++) s.part[line * S + e0 + k] = R[k];
+    } else if (ys) {
+        mpart_col<MX, SEG>(s, line, e0, R);
+#pragma unroll
+        for (int k = 0; k < SEG; k++) s.q[(e0 + k + MB) * NP + line + MB] = R[k];
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < MX * N / 2; k += NT) {
+        const int i = 2 * (k % (N / 2)), j = k / (N / 2) + MB;
+        double a = s.q[j * NP + i], b = s.q[j * NP + i + 1];
+        if (i >= MB && i < MX + MB) {
+            a = s.part[(j - MB) * S + i - MB] + a;
+            b = s.part[(j - MB) * S + i - MB + 1] + b;
+        }
+        if (c.stream_out) store_stream2(&out[base + j * N + i], a, b);
+        else *reinterpret_cast<double2 *>(&out[base + j * N + i]) = make_double2(a, b);
+    }
+    cfl = fmax(cfl, __longlong_as_double((long long)s.mcfl));
 }
 
 template <int MX, int NT>
@@ -2296,11 +2371,14 @@ hipError_t launch_advance(const Ctx &c, LaunchCfg lc, int level, int first, int 
     if (c.mapped) {
         // capacity form on filled patches only (fused == 0)
         if (fused) return hipErrorInvalidValue;
-        if (lc.mx == 8) hipLaunchKernelGGL((advance_mapped_kernel<8, 64>), dim3(count), dim3(64), 0, s, c, first, count, level, t, dt);
-        else if (lc.mx == 16) hipLaunchKernelGGL((advance_mapped_kernel<16, 256>), dim3(count), dim3(256), 0, s, c, first, count, level, t, dt);
-        else if (lc.mx == 32) hipLaunchKernelGGL((advance_mapped_kernel<32, 256>), dim3(count), dim3(256), 0, s, c, first, count, level, t, dt);
-        else return hipErrorInvalidValue;
-        return hipGetLastError();
+#define ADM(MXV, NTV)                                                                                              \
+    if (lc.mx == MXV && lc.nt == NTV) {                                                                            \
+        hipLaunchKernelGGL((advance_mapped_kernel<MXV, NTV>), dim3(count), dim3(NTV), 0, s, c, first, count, level, t, dt); \
+        return hipGetLastError();                                                                                  \
+    }
+        ADM(8, 64) ADM(8, 128) ADM(16, 64) ADM(16, 128) ADM(16, 256) ADM(32, 128) ADM(32, 256) ADM(32, 512)
+#undef ADM
+        return hipErrorInvalidValue;
     }
     if (c.eq == 0) {
 #define ADV(MXV, NTV) if (lc.mx == MXV && lc.nt == NTV) return adv_scalar<MXV, NTV>(c, first, count, level, t, dt, fused, s);

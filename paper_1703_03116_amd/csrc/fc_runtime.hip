@@ -485,7 +485,9 @@ fc_status upload_metadata(fc_patchstore *ps, hipStream_t s) {
     return FC_OK;
 }
 
-// launch variants (threads per patch) of the advance kernels
+// launch variants (threads per patch) of the advance kernels (the mapped
+// grid's capacity-form kernel shares the scalar kernel's work split and
+// variants)
 const int kVariantsScalar8[] = {64, 128}, kVariantsScalar16[] = {64, 128, 256}, kVariantsScalar32[] = {128, 256, 512};
 const int kVariantsSwe8[] = {64, 128, 192}, kVariantsSwe16[] = {256, 384, 512, 640};
 
@@ -1409,10 +1411,11 @@ fc_status fc_set_variant(fc_patchstore *ps, int32_t threads_per_patch) {
 fc_status fc_autotune(fc_patchstore *ps, int32_t *threads_out, void *stream) {
     fc_status r = check_bound(ps);
     if (r != FC_OK) return r;
-    if (ps->cfg.map_alpha != 0.0) return fail(FC_ERR_ARG, "a mapped grid has one advance kernel: nothing to tune");
     hipStream_t s = (hipStream_t)stream;
-    // time the fused-load advance of the most populated level, writing only
-    // the levels' other buffers (the state is left unchanged)
+    // time the advance of the most populated level (the fused-load kernel;
+    // on a mapped grid the capacity-form kernel), writing only the levels'
+    // other buffers (the state is left unchanged)
+    const int fused = ps->cfg.map_alpha != 0.0 ? 0 : 1;
     int lbest = ps->cfg.min_level;
     for (int l = ps->cfg.min_level; l <= ps->cfg.max_level; l++)
         if (ps->lr.count[l] > ps->lr.count[lbest]) lbest = l;
@@ -1434,10 +1437,10 @@ fc_status fc_autotune(fc_patchstore *ps, int32_t *threads_out, void *stream) {
             c.cflp = nullptr;
             LaunchCfg lc{ps->mx, nt};
             for (int w = 0; w < 2; w++)
-                HIPCHK(launch_advance(c, lc, lbest, ps->lr.start[lbest], ps->lr.count[lbest], ps->t, dt, 1, s));
+                HIPCHK(launch_advance(c, lc, lbest, ps->lr.start[lbest], ps->lr.count[lbest], ps->t, dt, fused, s));
             HIPCHK(hipEventRecord(e0, s));
             for (int w = 0; w < 10; w++)
-                HIPCHK(launch_advance(c, lc, lbest, ps->lr.start[lbest], ps->lr.count[lbest], ps->t, dt, 1, s));
+                HIPCHK(launch_advance(c, lc, lbest, ps->lr.start[lbest], ps->lr.count[lbest], ps->t, dt, fused, s));
             HIPCHK(hipEventRecord(e1, s));
             HIPCHK(hipEventSynchronize(e1));
             float ms = 0;

@@ -226,8 +226,9 @@ def test_mapped_coarsening_is_area_weighted(B, O):
 
 def test_mapped_store_rejects_other_forms(B, O):
     """The capacity form runs in the per-level form only: the ghost-gathering
-    forms, the uniform-level step, the adjoint and the tuner refuse a mapped
-    store with FC_ERR_ARG, leaving the data untouched."""
+    forms, the uniform-level step and the adjoint refuse a mapped store with
+    FC_ERR_ARG, leaving the data untouched; the tuner picks one of the
+    capacity-form kernel's own variants."""
     mx = 16
     L = S.uniform_leaves(1)
     q = np.random.default_rng(2).random((len(L), 1, mx, mx))
@@ -243,7 +244,62 @@ def test_mapped_store_rejects_other_forms(B, O):
         ps.step_uniform(1, 0.0, 0.01, qt)
     with pytest.raises(B.FcError):
         ps.adjoint_step(1, 0.0, 0.01, qt, qt)
+    assert ps.autotune() in (64, 128, 256)
     with pytest.raises(B.FcError):
-        ps.autotune()
+        ps.set_variant(512)
     ps.check()
     assert np.array_equal(ps.interior().cpu().numpy(), q)
+
+
+def test_full_size_mapped_mass_and_courant_l8(B):
+    """At the benchmark's size (uniform level 8, 65536 patches of 32x32, the
+    launch the mapped bench times): five steps keep the mass sum(kappa q) to
+    rounding, with kappa the closed-form area factor
+    1 + 2 pi alpha sigma^2 sin(2 pi (xi_c + eta_c)) (pinned against the
+    oracle's quadrature), and the reported Courant number stays within the
+    bound of the smallest cell, dt max|u| / (h (1 - 2 pi alpha sigma^2))."""
+    mx, l = 32, 8
+    w = S.workload("swirl_uniform", level=l, mx=mx, steps=5)
+    dt = w["dt_coarse"] * (1.0 - 2.0 * np.pi * ALPHA)
+    ps = B.PatchStore(w["leaves"], mx=mx, velocity="swirl", vel_params=w["vel_params"], min_level=l, max_level=l,
+                      map_alpha=ALPHA)
+    ps.set_interior(w["q0"])
+    n = mx << l
+    h = 1.0 / n
+    sig = np.sin(np.pi * h) / (np.pi * h)
+    lv = torch.as_tensor(np.asarray(w["leaves"]), device="cuda")
+    ii = torch.arange(mx, device="cuda", dtype=torch.float64)
+    I = lv[:, 1, None, None].double() * mx + ii[None, None, :]
+    J = lv[:, 2, None, None].double() * mx + ii[None, :, None]
+    kap = 1.0 + 2.0 * np.pi * ALPHA * sig * sig * torch.sin(2.0 * np.pi * (I + J + 1.0) * h)
+    m0 = float((kap * ps.interior()[:, 0]).sum())
+    cfl = torch.zeros(1, dtype=torch.float64, device="cuda")
+    t = 0.0
+    for _ in range(5):
+        ps.ghost_fill()
+        ps.advance_level(l, t, dt, cfl)
+        t += dt
+    ps.check()
+    q = ps.interior()[:, 0]
+    m1 = float((kap * q).sum())
+    assert abs(m1 - m0) <= 1e-12 * abs(m0)
+    assert torch.isfinite(q).all()
+    # swirl speeds are at most 1 (sin^2 sin products)
+    assert 0.0 < cfl.item() <= dt / (h * (1.0 - 2.0 * np.pi * ALPHA * sig * sig)) * (1 + 1e-12)
+
+
+@pytest.mark.parametrize("mx,nts", [(8, (64, 128)), (16, (64, 128, 256)), (32, (128, 256, 512))])
+def test_mapped_launch_variants_bitwise_equal(B, O, mx, nts):
+    """Every launch variant of the capacity-form kernel computes the same
+    bits (each edge and cell is evaluated by the same expression)."""
+    L = S.uniform_leaves(6 - {8: 0, 16: 1, 32: 2}[mx] - 2)
+    q = np.random.default_rng(mx).random((len(L), 1, mx, mx))
+    outs = []
+    for nt in nts:
+        ps, _ = mapped_pair(B, O, L, mx, q)
+        ps.set_variant(nt)
+        ps.coarse_steps(0.3 / (mx << int(np.asarray(L)[0, 0])), 3, "per_level")
+        ps.check()
+        outs.append(ps.interior().cpu().numpy())
+    for o in outs[1:]:
+        assert np.array_equal(outs[0], o)
