@@ -411,7 +411,6 @@ struct ScalarSmem {
     double q[N * NP];                 // the tile; after the sweeps, the new interior (staged for the store)
     double tx[(MX + 2) * S];          // TX(i, j) = A+*_{i-1/2} + A-*_{i+1/2} at [(j+1) S + i], rows -1..MX
     double ty[(MX + 2) * S];          // TY(i, j) at [(i+1) S + j], columns -1..MX
-    double part[MX * S];              // one direction's partial update of a cell, at [j S + i]
     double ux[MX + 1], uy[MX + 2];    // u(e, j) = ux[e] * uy[j+1]
     double vy[MX + 1], vx[MX + 2];    // v(i, e) = vy[e] * vx[i+1]
     double red[16];
@@ -696,7 +695,25 @@ struct LeafIO {
 // LEAF: read the step's input from io->qin and write its result to io->qout
 // instead of the store's buffers (uniform periodic level: every ghost value
 // is a same-size copy); the arithmetic is the same code either way.
-template <int MX, int NT, int LIM, bool FUSED, bool LEAF = false>
+// The sweeps of one limiter (work items as in advance_scalar_lim).
+template <int MX, int NT, int LIM>
+__device__ __forceinline__ void scalar_sweeps(ScalarSmem<MX> &s, int tid, bool xs, bool ys, int line, int e0,
+                                              double lam, double (&R)[scalar_seg<MX, NT>()]) {
+    constexpr int SEG = scalar_seg<MX, NT>(), NI = MX * (MX / SEG);
+    constexpr int SO = 2, NO = 4 * (MX / SO);
+    constexpr int GT0 = (NT - 2 * NI >= NO) ? 2 * NI : NI;
+    if (xs) sweep_segment<MX, SEG, LIM, 0>(s, line, e0, lam, R);
+    else if (ys) sweep_segment<MX, SEG, LIM, 1>(s, line, e0, lam, R);
+    if (tid >= GT0 && tid < GT0 + NO) {  // rows -1, MX and columns -1, MX: TX, TY only
+        const int k = tid - GT0, g = k / (MX / SO);
+        sweep_outer<MX, SO, LIM>(s, g >> 1, (g & 1) ? MX : -1, (k % (MX / SO)) * SO, lam);
+    }
+}
+
+// The limiter (c.lim) selects the sweeps only: the load and gather before
+// them and the transverse terms and the store after them are one code path,
+// so that no value loaded ahead is held across four copies of the kernel.
+template <int MX, int NT, bool FUSED, bool LEAF = false>
 __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, ScalarSmem<MX> &s, int p, int lev,
                                                    double t, double dt, const double *tdev,
                                                    const unsigned long long *slot, double &cfl,
@@ -790,7 +807,6 @@ __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, 
         const uint32_t m = (uint32_t)(p - c.lstart[l]);
         const int ix = (int)morton_compact(m), iy = (int)morton_compact(m >> 1), wrap = (1 << l) - 1;
         VelRegs vr;
-        if (complete) fetch_velocity<MX>(c, l, ix * MX, iy * MX, tdev, NI, vr);
         double2 iv[NV];
 #pragma unroll
         for (int v = 0; v < NV; v++) {
@@ -814,6 +830,10 @@ __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, 
                 }
             }
             const double sold = (slot && tid == NT - 1) ? __longlong_as_double((long long)*slot) : 0.0;
+            // the velocity factors last: held from the start, they would
+            // outlast the ghost loads' registers and push the kernel past
+            // the register budget of five workgroups per CU
+            fetch_velocity<MX>(c, l, ix * MX, iy * MX, tdev, NI, vr);
             put_velocity<MX>(c, s, t, dt, tdev, NI, vr);
             if (slot && tid == NT - 1) s.red[15] = sold;
 #pragma unroll
@@ -874,7 +894,6 @@ __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, 
         }
     }
     __syncthreads();
-    constexpr int S = ScalarSmem<MX>::S;
     double R[SEG];
     int line = 0, e0 = 0;
     const bool xs = tid < NI, ys = !xs && tid < 2 * NI;
@@ -882,27 +901,32 @@ __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, 
     if (xs) {
         line = half * (MX / 2) + r % (MX / 2);
         e0 = (r / (MX / 2)) * SEG;
-        sweep_segment<MX, SEG, LIM, 0>(s, line, e0, lam, R);
     } else if (ys) {
         line = r % MX;
         e0 = (half * (NSEG / 2) + r / MX) * SEG;
-        sweep_segment<MX, SEG, LIM, 1>(s, line, e0, lam, R);
     }
-    if (tid >= GT0 && tid < GT0 + NO) {  // rows -1, MX and columns -1, MX: TX, TY only
-        const int k = tid - GT0, g = k / (MX / SO);
-        sweep_outer<MX, SO, LIM>(s, g >> 1, (g & 1) ? MX : -1, (k % (MX / SO)) * SO, lam);
+    switch (c.lim) {
+        case 1: scalar_sweeps<MX, NT, 1>(s, tid, xs, ys, line, e0, lam, R); break;
+        case 2: scalar_sweeps<MX, NT, 2>(s, tid, xs, ys, line, e0, lam, R); break;
+        case 3: scalar_sweeps<MX, NT, 3>(s, tid, xs, ys, line, e0, lam, R); break;
+        default: scalar_sweeps<MX, NT, 0>(s, tid, xs, ys, line, e0, lam, R); break;
     }
     __syncthreads();
-    // direction parts: rows into s.part, columns into the tile's interior
-    // (nothing reads the staged interior after the sweeps)
+    // direction parts: columns into the tile's interior (nothing reads the
+    // staged interior after the sweeps); rows stay in registers and are
+    // added to them after the barrier (one row item per cell, so no race)
     if (xs) {
         part_row<MX, SEG>(s, line, e0, lam, R);
-#pragma unroll
-        for (int k = 0; k < SEG; k++) s.part[line * S + e0 + k] = R[k];
     } else if (ys) {
         part_col<MX, SEG>(s, line, e0, lam, R);
 #pragma unroll
         for (int k = 0; k < SEG; k++) s.q[(e0 + k + MB) * NP + line + MB] = R[k];
+    }
+    __syncthreads();
+    if (xs) {
+        double *qr = &s.q[(line + MB) * NP + e0 + MB];
+#pragma unroll
+        for (int k = 0; k < SEG; k++) qr[k] = qr[k] + R[k];
     }
     __syncthreads();
     // Whole rows go out, ghost columns included (they carry the values the
@@ -914,19 +938,14 @@ __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, 
         double *qo = io->qout + (size_t)io->leaf_of_slot[p] * MX * MX;
         for (int k = threadIdx.x; k < MX * MX / 2; k += NT) {
             const int i = 2 * (k % (MX / 2)), j = k / (MX / 2);
-            const double a = s.part[j * S + i] + s.q[(j + MB) * NP + i + MB];
-            const double b = s.part[j * S + i + 1] + s.q[(j + MB) * NP + i + MB + 1];
             // plain stores: the next step reads this state right away
-            *reinterpret_cast<double2 *>(qo + 2 * k) = make_double2(a, b);
+            *reinterpret_cast<double2 *>(qo + 2 * k) =
+                make_double2(s.q[(j + MB) * NP + i + MB], s.q[(j + MB) * NP + i + MB + 1]);
         }
     } else {
         for (int k = threadIdx.x; k < MX * N / 2; k += NT) {
             const int i = 2 * (k % (N / 2)), j = k / (N / 2) + MB;
-            double a = s.q[j * NP + i], b = s.q[j * NP + i + 1];
-            if (i >= MB && i < MX + MB) {  // pairs never straddle (MB, MX even)
-                a = s.part[(j - MB) * S + i - MB] + a;
-                b = s.part[(j - MB) * S + i - MB + 1] + b;
-            }
+            const double a = s.q[j * NP + i], b = s.q[j * NP + i + 1];
             if (c.stream_out) store_stream2(&out[base + j * N + i], a, b);
             else *reinterpret_cast<double2 *>(&out[base + j * N + i]) = make_double2(a, b);
         }
@@ -941,12 +960,7 @@ template <int MX, int NT, bool FUSED>
 __device__ __forceinline__ void advance_scalar_patch(const Ctx &c, const View &w, ScalarSmem<MX> &s, int p, int lev,
                                                      double t, double dt, double &cfl, const double *tdev = nullptr,
                                                      const unsigned long long *slot = nullptr) {
-    switch (c.lim) {
-        case 1: advance_scalar_lim<MX, NT, 1, FUSED>(c, w, s, p, lev, t, dt, tdev, slot, cfl); break;
-        case 2: advance_scalar_lim<MX, NT, 2, FUSED>(c, w, s, p, lev, t, dt, tdev, slot, cfl); break;
-        case 3: advance_scalar_lim<MX, NT, 3, FUSED>(c, w, s, p, lev, t, dt, tdev, slot, cfl); break;
-        default: advance_scalar_lim<MX, NT, 0, FUSED>(c, w, s, p, lev, t, dt, tdev, slot, cfl); break;
-    }
+    advance_scalar_lim<MX, NT, FUSED>(c, w, s, p, lev, t, dt, tdev, slot, cfl);
 }
 
 // block-wide max of a non-negative double, then one atomicMax on its bits
@@ -993,14 +1007,18 @@ __device__ void reduce_cfl_slot(double v, double *red, unsigned long long *slot,
     }
 }
 
-// Waves per SIMD the scalar kernels are compiled for: at mx = 32 the LDS
-// tile admits four workgroups per CU, and the register budget is set so that
-// all four are resident.
+// Waves per SIMD the kernels are compiled for (the register budget).  Scalar
+// mx = 32: the LDS tile (29.8 KB) admits five workgroups per CU, and the
+// register budget is set so that all five are resident (at most eight waves
+// per SIMD).  Shallow water at mx = 16: two workgroups per CU (the LDS tile
+// and accumulators take 68 KB).
 template <int MX, int NT, int EQ>
 constexpr int min_waves() {
-    // scalar mx = 32: four workgroups per CU; shallow water at mx = 16: two
-    // workgroups per CU (the LDS tile and accumulators take 68 KB)
-    return (EQ == 0 && MX == 32) ? NT / 64 : ((EQ == 1 && MX == 16 && NT >= 256) ? NT / 128 : 1);
+    if (EQ == 0 && MX == 32) {
+        const int w = (5 * NT / 64 + 3) / 4;
+        return w < 8 ? w : 8;
+    }
+    return (EQ == 1 && MX == 16 && NT >= 256) ? NT / 128 : 1;
 }
 
 template <int MX, int NT, bool FUSED>
@@ -1164,7 +1182,7 @@ __device__ __forceinline__ void mpart_col(const MappedSmem<MX> &s, int i, int e0
 template <int MX, int NT, int LIM>
 __device__ void advance_mapped_patch(const Ctx &c, const View &w, MappedSmem<MX> &s, int p, int lev, double t,
                                      double dt, double &cfl) {
-    constexpr int N = MX + 2 * MB, NP = ScalarSmem<MX>::NP, S = ScalarSmem<MX>::S;
+    constexpr int N = MX + 2 * MB, NP = ScalarSmem<MX>::NP;
     constexpr int SEG = scalar_seg<MX, NT>(), NSEG = MX / SEG, NI = MX * NSEG, HI = NI / 2;
     constexpr int SO = 2, NO = 4 * (MX / SO);
     constexpr int GT0 = (NT - 2 * NI >= NO) ? 2 * NI : NI;
@@ -1215,21 +1233,21 @@ __device__ void advance_mapped_patch(const Ctx &c, const View &w, MappedSmem<MX>
     __syncthreads();
     if (xs) {
         mpart_row<MX, SEG>(s, line, e0, R);
-#pragma unroll
-        for (int k = 0; k < SEG; k++) s.part[line * S + e0 + k] = R[k];
     } else if (ys) {
         mpart_col<MX, SEG>(s, line, e0, R);
 #pragma unroll
         for (int k = 0; k < SEG; k++) s.q[(e0 + k + MB) * NP + line + MB] = R[k];
     }
     __syncthreads();
+    if (xs) {
+        double *qr = &s.q[(line + MB) * NP + e0 + MB];
+#pragma unroll
+        for (int k = 0; k < SEG; k++) qr[k] = qr[k] + R[k];
+    }
+    __syncthreads();
     for (int k = threadIdx.x; k < MX * N / 2; k += NT) {
         const int i = 2 * (k % (N / 2)), j = k / (N / 2) + MB;
-        double a = s.q[j * NP + i], b = s.q[j * NP + i + 1];
-        if (i >= MB && i < MX + MB) {
-            a = s.part[(j - MB) * S + i - MB] + a;
-            b = s.part[(j - MB) * S + i - MB + 1] + b;
-        }
+        const double a = s.q[j * NP + i], b = s.q[j * NP + i + 1];
         if (c.stream_out) store_stream2(&out[base + j * N + i], a, b);
         else *reinterpret_cast<double2 *>(&out[base + j * N + i]) = make_double2(a, b);
     }
@@ -1262,12 +1280,7 @@ __global__ void __launch_bounds__(NT, (min_waves<MX, NT, 0>())) step_leaf_kernel
     const int p = first + xcd_remap(blockIdx.x, count);
     const View w = view_of(c);
     double cfl = 0.0;
-    switch (c.lim) {
-        case 1: advance_scalar_lim<MX, NT, 1, false, true>(c, w, s, p, level, t, dt, nullptr, nullptr, cfl, &io); break;
-        case 2: advance_scalar_lim<MX, NT, 2, false, true>(c, w, s, p, level, t, dt, nullptr, nullptr, cfl, &io); break;
-        case 3: advance_scalar_lim<MX, NT, 3, false, true>(c, w, s, p, level, t, dt, nullptr, nullptr, cfl, &io); break;
-        default: advance_scalar_lim<MX, NT, 0, false, true>(c, w, s, p, level, t, dt, nullptr, nullptr, cfl, &io); break;
-    }
+    advance_scalar_lim<MX, NT, false, true>(c, w, s, p, level, t, dt, nullptr, nullptr, cfl, &io);
 }
 
 // ------------------------------------------------------------------------
