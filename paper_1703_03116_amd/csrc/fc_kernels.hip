@@ -566,14 +566,29 @@ __device__ void load_velocity(const Ctx &c, ScalarSmem<MX> &s, int l, int gx, in
     put_velocity<MX>(c, s, t, dt, tdev, k0, v, orient);
 }
 
+// Upwind side of a line.  Every velocity this library advects with is a
+// product of a factor along the line (ux for rows, vy for columns) and one
+// across it, and the factor along the line has one sign over the line: the
+// swirl's ex, ey = sin^2 >= 0, a constant velocity is constant.  So the sign
+// of the across factor (swirl) or of the product at the first edge (constant
+// velocity) gives every edge's: all s >= 0 (POS) or all s <= 0.  The sweeps
+// below take that side as a template argument instead of selecting per edge;
+// at s = 0 either side gives a zero correction and zero fluctuations, so the
+// results agree with a per-edge choice up to the sign of zeros.
+__device__ __forceinline__ bool line_pos(int velocity, double ve0, double vl) {
+    return (velocity == 2 ? vl : ve0 * vl) >= 0.0;
+}
+
 // One segment of one interior line: edges e0 .. e0+SEG (edge e lies between
 // cells e-1 and e of the line), cells e0 .. e0+SEG-1.  DIR 0: x-edges of row
 // `line`; DIR 1: y-edges of column `line`.  Writes TX (TY) of the cells and
 // returns the line's partial update of each cell in R:
 //   rows     Rx = Q - lam TX + lam/2 (C_{i+1/2} - C_{i-1/2}),
 //   columns  Ry = lam/2 (C_{j+1/2} - C_{j-1/2}) - lam TY.
-template <int MX, int SEG, int LIM, int DIR>
-__device__ __forceinline__ void sweep_segment(ScalarSmem<MX> &s, int line, int e0, double lam, double (&R)[SEG]) {
+// POS: every edge speed of the line is >= 0 (else <= 0): the upwind wave is
+// the previous (next) edge's, A+ W = s W and A- W = 0 (A+ W = 0, A- W = s W).
+template <int MX, int SEG, int LIM, int DIR, bool POS>
+__device__ __forceinline__ void sweep_side(ScalarSmem<MX> &s, int line, int e0, double lam, double (&R)[SEG]) {
     constexpr int NP = ScalarSmem<MX>::NP, S = ScalarSmem<MX>::S;
     constexpr int STR = DIR == 0 ? 1 : NP;
     const double *qp = DIR == 0 ? &s.q[(line + MB) * NP + MB + e0 - 2] : &s.q[(MB + e0 - 2) * NP + line + MB];
@@ -587,11 +602,10 @@ __device__ __forceinline__ void sweep_segment(ScalarSmem<MX> &s, int line, int e
     for (int k = 0; k <= SEG; k++) {  // edge e0 + k, between q[k+1] and q[k+2]
         const double u = ve[k] * vl;
         const double W = q[k + 2] - q[k + 1];
-        const double Wu = u > 0.0 ? q[k + 1] - q[k] : q[k + 3] - q[k + 2];
-        const double au = fabs(u);
-        const double C = correction<LIM>(W, Wu, au, lam);
-        const double aps = posp(u) * W - C;
-        const double ams = negp(u) * W + C;
+        const double Wu = POS ? q[k + 1] - q[k] : q[k + 3] - q[k + 2];
+        const double C = correction<LIM>(W, Wu, POS ? u : -u, lam);
+        const double aps = POS ? u * W - C : -C;
+        const double ams = POS ? C : u * W + C;
         if (k > 0) {  // cell e0 + k - 1
             const int cc = e0 + k - 1;
             const double T = aprev + ams;
@@ -608,11 +622,18 @@ __device__ __forceinline__ void sweep_segment(ScalarSmem<MX> &s, int line, int e
     }
 }
 
+template <int MX, int SEG, int LIM, int DIR>
+__device__ __forceinline__ void sweep_segment(ScalarSmem<MX> &s, int line, int e0, double lam, bool pos,
+                                              double (&R)[SEG]) {
+    if (pos) sweep_side<MX, SEG, LIM, DIR, true>(s, line, e0, lam, R);
+    else sweep_side<MX, SEG, LIM, DIR, false>(s, line, e0, lam, R);
+}
+
 // The same for a line outside the interior (row -1 or MX: DIR 0, column -1
 // or MX: DIR 1), TX (TY) only.  Direction-generic (per-lane stride and base)
 // so that a wave holding both kinds takes one path.
-template <int MX, int SEG, int LIM>
-__device__ __forceinline__ void sweep_outer(ScalarSmem<MX> &s, int dir, int line, int e0, double lam) {
+template <int MX, int SEG, int LIM, bool POS>
+__device__ __forceinline__ void outer_side(ScalarSmem<MX> &s, int dir, int line, int e0, double lam) {
     constexpr int NP = ScalarSmem<MX>::NP, S = ScalarSmem<MX>::S;
     const int str = dir == 0 ? 1 : NP;
     const double *qp = dir == 0 ? &s.q[(line + MB) * NP + MB + e0 - 2] : &s.q[(MB + e0 - 2) * NP + line + MB];
@@ -627,23 +648,32 @@ __device__ __forceinline__ void sweep_outer(ScalarSmem<MX> &s, int dir, int line
     for (int k = 0; k <= SEG; k++) {
         const double u = ve[k] * vl;
         const double W = q[k + 2] - q[k + 1];
-        const double Wu = u > 0.0 ? q[k + 1] - q[k] : q[k + 3] - q[k + 2];
-        const double C = correction<LIM>(W, Wu, fabs(u), lam);
-        const double ams = negp(u) * W + C;
+        const double Wu = POS ? q[k + 1] - q[k] : q[k + 3] - q[k + 2];
+        const double C = correction<LIM>(W, Wu, POS ? u : -u, lam);
+        const double ams = POS ? C : u * W + C;
         if (k > 0) to[k] = aprev + ams;
-        aprev = posp(u) * W - C;
+        aprev = POS ? u * W - C : -C;
     }
+}
+
+template <int MX, int SEG, int LIM>
+__device__ __forceinline__ void sweep_outer(ScalarSmem<MX> &s, int velocity, int dir, int line, int e0, double lam) {
+    const double ve0 = dir == 0 ? s.ux[e0] : s.vy[e0];
+    const double vl = dir == 0 ? s.uy[line + 1] : s.vx[line + 1];
+    if (line_pos(velocity, ve0, vl)) outer_side<MX, SEG, LIM, true>(s, dir, line, e0, lam);
+    else outer_side<MX, SEG, LIM, false>(s, dir, line, e0, lam);
 }
 
 // Final update of a cell, as two direction parts:
 //   Q_new = [Rx + lam^2/2 (TF_{i+1/2} - TF_{i-1/2})] + [Ry + lam^2/2 (TG_{j+1/2} - TG_{j-1/2})]
 // with TF(e) = u+ TY(e-1) + u- TY(e) on x-edges and TG(e) = v+ TX(e-1) +
-// v- TX(e) on y-edges.  Each item adds the transverse term of its own
-// line's edges, evaluated once per edge: the x-items form the first bracket
-// for their row segment, the y-items the second for their column segment;
-// the store sums the two.
+// v- TX(e) on y-edges (one term, on the line's upwind side).  Each item adds
+// the transverse term of its own line's edges, evaluated once per edge: the
+// x-items form the first bracket for their row segment, the y-items the
+// second for their column segment.
 template <int MX, int SEG>
-__device__ __forceinline__ void part_row(const ScalarSmem<MX> &s, int j, int e0, double lam, double (&R)[SEG]) {
+__device__ __forceinline__ void part_row(const ScalarSmem<MX> &s, int j, int e0, double lam, bool pos,
+                                         double (&R)[SEG]) {
     constexpr int S = ScalarSmem<MX>::S;
     const double uyj = s.uy[j + 1];
     double ty[SEG + 2];
@@ -651,17 +681,15 @@ __device__ __forceinline__ void part_row(const ScalarSmem<MX> &s, int j, int e0,
     for (int k = 0; k < SEG + 2; k++) ty[k] = s.ty[(e0 + k) * S + j];  // TY(e0 - 1 + k, j)
     double tf[SEG + 1];
 #pragma unroll
-    for (int k = 0; k <= SEG; k++) {
-        const double u = s.ux[e0 + k] * uyj;
-        tf[k] = posp(u) * ty[k] + negp(u) * ty[k + 1];
-    }
+    for (int k = 0; k <= SEG; k++) tf[k] = (s.ux[e0 + k] * uyj) * (pos ? ty[k] : ty[k + 1]);
     const double hl2 = 0.5 * lam * lam;
 #pragma unroll
     for (int k = 0; k < SEG; k++) R[k] = R[k] + hl2 * (tf[k + 1] - tf[k]);
 }
 
 template <int MX, int SEG>
-__device__ __forceinline__ void part_col(const ScalarSmem<MX> &s, int i, int e0, double lam, double (&R)[SEG]) {
+__device__ __forceinline__ void part_col(const ScalarSmem<MX> &s, int i, int e0, double lam, bool pos,
+                                         double (&R)[SEG]) {
     constexpr int S = ScalarSmem<MX>::S;
     const double vxi = s.vx[i + 1];
     double tx[SEG + 2];
@@ -669,10 +697,7 @@ __device__ __forceinline__ void part_col(const ScalarSmem<MX> &s, int i, int e0,
     for (int k = 0; k < SEG + 2; k++) tx[k] = s.tx[(e0 + k) * S + i];  // TX(i, e0 - 1 + k)
     double tg[SEG + 1];
 #pragma unroll
-    for (int k = 0; k <= SEG; k++) {
-        const double v = s.vy[e0 + k] * vxi;
-        tg[k] = posp(v) * tx[k] + negp(v) * tx[k + 1];
-    }
+    for (int k = 0; k <= SEG; k++) tg[k] = (s.vy[e0 + k] * vxi) * (pos ? tx[k] : tx[k + 1]);
     const double hl2 = 0.5 * lam * lam;
 #pragma unroll
     for (int k = 0; k < SEG; k++) R[k] = R[k] + hl2 * (tg[k + 1] - tg[k]);
@@ -698,15 +723,16 @@ struct LeafIO {
 // The sweeps of one limiter (work items as in advance_scalar_lim).
 template <int MX, int NT, int LIM>
 __device__ __forceinline__ void scalar_sweeps(ScalarSmem<MX> &s, int tid, bool xs, bool ys, int line, int e0,
-                                              double lam, double (&R)[scalar_seg<MX, NT>()]) {
+                                              double lam, bool pos, int velocity,
+                                              double (&R)[scalar_seg<MX, NT>()]) {
     constexpr int SEG = scalar_seg<MX, NT>(), NI = MX * (MX / SEG);
     constexpr int SO = 2, NO = 4 * (MX / SO);
     constexpr int GT0 = (NT - 2 * NI >= NO) ? 2 * NI : NI;
-    if (xs) sweep_segment<MX, SEG, LIM, 0>(s, line, e0, lam, R);
-    else if (ys) sweep_segment<MX, SEG, LIM, 1>(s, line, e0, lam, R);
+    if (xs) sweep_segment<MX, SEG, LIM, 0>(s, line, e0, lam, pos, R);
+    else if (ys) sweep_segment<MX, SEG, LIM, 1>(s, line, e0, lam, pos, R);
     if (tid >= GT0 && tid < GT0 + NO) {  // rows -1, MX and columns -1, MX: TX, TY only
         const int k = tid - GT0, g = k / (MX / SO);
-        sweep_outer<MX, SO, LIM>(s, g >> 1, (g & 1) ? MX : -1, (k % (MX / SO)) * SO, lam);
+        sweep_outer<MX, SO, LIM>(s, velocity, g >> 1, (g & 1) ? MX : -1, (k % (MX / SO)) * SO, lam);
     }
 }
 
@@ -898,27 +924,30 @@ __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, 
     int line = 0, e0 = 0;
     const bool xs = tid < NI, ys = !xs && tid < 2 * NI;
     const int half = (xs ? tid : tid - NI) / HI, r = (xs ? tid : tid - NI) % HI;
+    bool pos = true;
     if (xs) {
         line = half * (MX / 2) + r % (MX / 2);
         e0 = (r / (MX / 2)) * SEG;
+        pos = line_pos(c.velocity, s.ux[e0], s.uy[line + 1]);
     } else if (ys) {
         line = r % MX;
         e0 = (half * (NSEG / 2) + r / MX) * SEG;
+        pos = line_pos(c.velocity, s.vy[e0], s.vx[line + 1]);
     }
     switch (c.lim) {
-        case 1: scalar_sweeps<MX, NT, 1>(s, tid, xs, ys, line, e0, lam, R); break;
-        case 2: scalar_sweeps<MX, NT, 2>(s, tid, xs, ys, line, e0, lam, R); break;
-        case 3: scalar_sweeps<MX, NT, 3>(s, tid, xs, ys, line, e0, lam, R); break;
-        default: scalar_sweeps<MX, NT, 0>(s, tid, xs, ys, line, e0, lam, R); break;
+        case 1: scalar_sweeps<MX, NT, 1>(s, tid, xs, ys, line, e0, lam, pos, c.velocity, R); break;
+        case 2: scalar_sweeps<MX, NT, 2>(s, tid, xs, ys, line, e0, lam, pos, c.velocity, R); break;
+        case 3: scalar_sweeps<MX, NT, 3>(s, tid, xs, ys, line, e0, lam, pos, c.velocity, R); break;
+        default: scalar_sweeps<MX, NT, 0>(s, tid, xs, ys, line, e0, lam, pos, c.velocity, R); break;
     }
     __syncthreads();
     // direction parts: columns into the tile's interior (nothing reads the
     // staged interior after the sweeps); rows stay in registers and are
     // added to them after the barrier (one row item per cell, so no race)
     if (xs) {
-        part_row<MX, SEG>(s, line, e0, lam, R);
+        part_row<MX, SEG>(s, line, e0, lam, pos, R);
     } else if (ys) {
-        part_col<MX, SEG>(s, line, e0, lam, R);
+        part_col<MX, SEG>(s, line, e0, lam, pos, R);
 #pragma unroll
         for (int k = 0; k < SEG; k++) s.q[(e0 + k + MB) * NP + line + MB] = R[k];
     }
