@@ -362,6 +362,21 @@ __device__ __forceinline__ uint32_t morton_spread(uint32_t x) {
     x = (x | (x << 2)) & 0x33333333u;
     return (x | (x << 1)) & 0x55555555u;
 }
+// Morton index of the neighbour (dx, dy) in {-1, 0, 1}^2 of quadrant m on a
+// periodic level l < 16, by dilated-integer arithmetic on m's x bits (even)
+// and y bits (odd) within the level's 2l bits: no interleaving per call.
+// The six candidates are uniform over the workgroup; the caller selects.
+__device__ __forceinline__ void morton_nbr(uint32_t m, int l, uint32_t &x0, uint32_t &xp, uint32_t &xm, uint32_t &y0,
+                                           uint32_t &yp, uint32_t &ym) {
+    const uint32_t win = (1u << (2 * l)) - 1u, ex = 0x55555555u & win, ey = 0xAAAAAAAAu & win;
+    x0 = m & ex;
+    y0 = m & ey;
+    xp = ((x0 | ~ex) + 1u) & ex;  // carries pass the y bits; the top x bit wraps to 0
+    xm = (x0 - 1u) & ex;          // borrows likewise; 0 wraps to the top
+    yp = ((y0 | ~ey) + 2u) & ey;
+    ym = (y0 - 2u) & ey;
+}
+
 __device__ __forceinline__ uint32_t morton_compact(uint32_t x) {
     x &= 0x55555555u;
     x = (x | (x >> 1)) & 0x33333333u;
@@ -831,7 +846,7 @@ __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, 
         // all loads of the step leave at once, the velocity's first.
         const bool complete = lev >= 0 && ((c.complete >> lev) & 1u);
         const uint32_t m = (uint32_t)(p - c.lstart[l]);
-        const int ix = (int)morton_compact(m), iy = (int)morton_compact(m >> 1), wrap = (1 << l) - 1;
+        const int ix = (int)morton_compact(m), iy = (int)morton_compact(m >> 1);
         VelRegs vr;
         double2 iv[NV];
 #pragma unroll
@@ -841,6 +856,8 @@ __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, 
         }
         const int g0 = (tid + NT - NI) % NT;  // the odd ghost cells go to a lightly loaded wave
         if (complete) {
+            uint32_t mx0, mxp, mxm, my0, myp, mym;
+            morton_nbr(m, l, mx0, mxp, mxm, my0, myp, mym);
             double gv[NGH];
             int gi[NGH], gj[NGH];
 #pragma unroll
@@ -850,8 +867,9 @@ __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, 
                 if (g0 + v * NT < NG) {
                     ghost_region_index<MX>(g0 + v * NT, gi[v], gj[v], r);
                     const int dx = gi[v] < 0 ? -1 : (gi[v] >= MX ? 1 : 0), dy = gj[v] < 0 ? -1 : (gj[v] >= MX ? 1 : 0);
-                    const uint32_t q = (uint32_t)c.lstart[l] + (morton_spread((uint32_t)((ix + dx) & wrap)) |
-                                                                (morton_spread((uint32_t)((iy + dy) & wrap)) << 1));
+                    const uint32_t nx = dx > 0 ? mxp : (dx < 0 ? mxm : mx0);
+                    const uint32_t ny = dy > 0 ? myp : (dy < 0 ? mym : my0);
+                    const uint32_t q = (uint32_t)c.lstart[l] + (nx | ny);
                     gv[v] = in[(size_t)q * N * N + (size_t)((gj[v] - dy * MX + MB) * N + gi[v] - dx * MX + MB)];
                 }
             }
