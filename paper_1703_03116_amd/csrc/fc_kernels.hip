@@ -1119,8 +1119,9 @@ struct MappedSmem : ScalarSmem<MX> {
 //   rows     Rx = Q - TX + L/2 (C_{i+1/2} - C_{i-1/2}),
 //   columns  Ry = L/2 (C_{j+1/2} - C_{j-1/2}) - TY,
 // L the cell's dt / (kappa h); cm: the largest Courant number of the edges.
-template <int MX, int SEG, int LIM, int DIR>
-__device__ __forceinline__ void msweep_segment(MappedSmem<MX> &s, int line, int e0, double (&R)[SEG], double &cm) {
+// POS: the line's upwind side, as in sweep_side.
+template <int MX, int SEG, int LIM, int DIR, bool POS>
+__device__ __forceinline__ void msweep_side(MappedSmem<MX> &s, int line, int e0, double (&R)[SEG], double &cm) {
     constexpr int NP = ScalarSmem<MX>::NP, S = ScalarSmem<MX>::S;
     constexpr int STR = DIR == 0 ? 1 : NP;
     const double *qp = DIR == 0 ? &s.q[(line + MB) * NP + MB + e0 - 2] : &s.q[(MB + e0 - 2) * NP + line + MB];
@@ -1137,12 +1138,11 @@ __device__ __forceinline__ void msweep_segment(MappedSmem<MX> &s, int line, int 
     for (int k = 0; k <= SEG; k++) {  // edge e0 + k, between cells e0+k-1 (q[k+1], L[k]) and e0+k (q[k+2], L[k+1])
         const double u = ve[k] * vl;
         const double W = q[k + 2] - q[k + 1];
-        const double Wu = u > 0.0 ? q[k + 1] - q[k] : q[k + 3] - q[k + 2];
-        const double au = fabs(u);
-        const double C = correction<LIM>(W, Wu, au, 0.5 * (L[k] + L[k + 1]));
-        const double aps = posp(u) * W - C;
-        const double ams = negp(u) * W + C;
-        cm = fmax(cm, u > 0.0 ? L[k + 1] * u : (u < 0.0 ? L[k] * -u : 0.0));
+        const double Wu = POS ? q[k + 1] - q[k] : q[k + 3] - q[k + 2];
+        const double C = correction<LIM>(W, Wu, POS ? u : -u, 0.5 * (L[k] + L[k + 1]));
+        const double aps = POS ? u * W - C : -C;
+        const double ams = POS ? C : u * W + C;
+        cm = fmax(cm, POS ? L[k + 1] * u : L[k] * -u);
         if (k > 0) {  // cell e0 + k - 1
             const int cc = e0 + k - 1;
             const double T = L[k] * (aprev + ams);
@@ -1159,9 +1159,16 @@ __device__ __forceinline__ void msweep_segment(MappedSmem<MX> &s, int line, int 
     }
 }
 
+template <int MX, int SEG, int LIM, int DIR>
+__device__ __forceinline__ void msweep_segment(MappedSmem<MX> &s, int line, int e0, bool pos, double (&R)[SEG],
+                                               double &cm) {
+    if (pos) msweep_side<MX, SEG, LIM, DIR, true>(s, line, e0, R, cm);
+    else msweep_side<MX, SEG, LIM, DIR, false>(s, line, e0, R, cm);
+}
+
 // The same for a line outside the interior (as sweep_outer): TX (TY) only.
-template <int MX, int SEG, int LIM>
-__device__ __forceinline__ void msweep_outer(MappedSmem<MX> &s, int dir, int line, int e0) {
+template <int MX, int SEG, int LIM, bool POS>
+__device__ __forceinline__ void mouter_side(MappedSmem<MX> &s, int dir, int line, int e0) {
     constexpr int NP = ScalarSmem<MX>::NP, S = ScalarSmem<MX>::S;
     const int str = dir == 0 ? 1 : NP;
     const double *qp = dir == 0 ? &s.q[(line + MB) * NP + MB + e0 - 2] : &s.q[(MB + e0 - 2) * NP + line + MB];
@@ -1179,19 +1186,27 @@ __device__ __forceinline__ void msweep_outer(MappedSmem<MX> &s, int dir, int lin
     for (int k = 0; k <= SEG; k++) {
         const double u = ve[k] * vl;
         const double W = q[k + 2] - q[k + 1];
-        const double Wu = u > 0.0 ? q[k + 1] - q[k] : q[k + 3] - q[k + 2];
-        const double C = correction<LIM>(W, Wu, fabs(u), 0.5 * (L[k] + L[k + 1]));
-        const double ams = negp(u) * W + C;
+        const double Wu = POS ? q[k + 1] - q[k] : q[k + 3] - q[k + 2];
+        const double C = correction<LIM>(W, Wu, POS ? u : -u, 0.5 * (L[k] + L[k + 1]));
+        const double ams = POS ? C : u * W + C;
         if (k > 0) to[k] = L[k] * (aprev + ams);
-        aprev = posp(u) * W - C;
+        aprev = POS ? u * W - C : -C;
     }
 }
 
+template <int MX, int SEG, int LIM>
+__device__ __forceinline__ void msweep_outer(MappedSmem<MX> &s, int velocity, int dir, int line, int e0) {
+    const double ve0 = dir == 0 ? s.ux[e0] : s.vy[e0];
+    const double vl = dir == 0 ? s.uy[line + 1] : s.vx[line + 1];
+    if (line_pos(velocity, ve0, vl)) mouter_side<MX, SEG, LIM, true>(s, dir, line, e0);
+    else mouter_side<MX, SEG, LIM, false>(s, dir, line, e0);
+}
+
 // Transverse terms of a row segment: R += L/2 (TF_{i+1/2} - TF_{i-1/2}),
-// TF(e) = u+ TY(e-1) + u- TY(e) (the TY already scaled by their cells' L);
-// columns likewise with TG and TX.
+// TF(e) = u+ TY(e-1) + u- TY(e) (the TY already scaled by their cells' L; one
+// term, on the line's upwind side); columns likewise with TG and TX.
 template <int MX, int SEG>
-__device__ __forceinline__ void mpart_row(const MappedSmem<MX> &s, int j, int e0, double (&R)[SEG]) {
+__device__ __forceinline__ void mpart_row(const MappedSmem<MX> &s, int j, int e0, bool pos, double (&R)[SEG]) {
     constexpr int S = ScalarSmem<MX>::S;
     const double uyj = s.uy[j + 1];
     double ty[SEG + 2];
@@ -1199,16 +1214,13 @@ __device__ __forceinline__ void mpart_row(const MappedSmem<MX> &s, int j, int e0
     for (int k = 0; k < SEG + 2; k++) ty[k] = s.ty[(e0 + k) * S + j];  // TY(e0 - 1 + k, j)
     double tf[SEG + 1];
 #pragma unroll
-    for (int k = 0; k <= SEG; k++) {
-        const double u = s.ux[e0 + k] * uyj;
-        tf[k] = posp(u) * ty[k] + negp(u) * ty[k + 1];
-    }
+    for (int k = 0; k <= SEG; k++) tf[k] = (s.ux[e0 + k] * uyj) * (pos ? ty[k] : ty[k + 1]);
 #pragma unroll
     for (int k = 0; k < SEG; k++) R[k] = R[k] + (0.5 * s.dk[e0 + k + j + 2 * MB]) * (tf[k + 1] - tf[k]);
 }
 
 template <int MX, int SEG>
-__device__ __forceinline__ void mpart_col(const MappedSmem<MX> &s, int i, int e0, double (&R)[SEG]) {
+__device__ __forceinline__ void mpart_col(const MappedSmem<MX> &s, int i, int e0, bool pos, double (&R)[SEG]) {
     constexpr int S = ScalarSmem<MX>::S;
     const double vxi = s.vx[i + 1];
     double tx[SEG + 2];
@@ -1216,17 +1228,30 @@ __device__ __forceinline__ void mpart_col(const MappedSmem<MX> &s, int i, int e0
     for (int k = 0; k < SEG + 2; k++) tx[k] = s.tx[(e0 + k) * S + i];  // TX(i, e0 - 1 + k)
     double tg[SEG + 1];
 #pragma unroll
-    for (int k = 0; k <= SEG; k++) {
-        const double v = s.vy[e0 + k] * vxi;
-        tg[k] = posp(v) * tx[k] + negp(v) * tx[k + 1];
-    }
+    for (int k = 0; k <= SEG; k++) tg[k] = (s.vy[e0 + k] * vxi) * (pos ? tx[k] : tx[k + 1]);
 #pragma unroll
     for (int k = 0; k < SEG; k++) R[k] = R[k] + (0.5 * s.dk[i + e0 + k + 2 * MB]) * (tg[k + 1] - tg[k]);
 }
 
+// The sweeps of one limiter (work items as in advance_mapped_patch).
+template <int MX, int NT, int LIM>
+__device__ __forceinline__ void mapped_sweeps(MappedSmem<MX> &s, int tid, bool xs, bool ys, int line, int e0,
+                                              bool pos, int velocity, double (&R)[scalar_seg<MX, NT>()],
+                                              double &cm) {
+    constexpr int SEG = scalar_seg<MX, NT>(), NI = MX * (MX / SEG);
+    constexpr int SO = 2, NO = 4 * (MX / SO);
+    constexpr int GT0 = (NT - 2 * NI >= NO) ? 2 * NI : NI;
+    if (xs) msweep_segment<MX, SEG, LIM, 0>(s, line, e0, pos, R, cm);
+    else if (ys) msweep_segment<MX, SEG, LIM, 1>(s, line, e0, pos, R, cm);
+    if (tid >= GT0 && tid < GT0 + NO) {  // rows -1, MX and columns -1, MX: TX, TY only
+        const int k = tid - GT0, g = k / (MX / SO);
+        msweep_outer<MX, SO, LIM>(s, velocity, g >> 1, (g & 1) ? MX : -1, (k % (MX / SO)) * SO);
+    }
+}
+
 // One capacity-form step of patch p (level lev, or its own if lev < 0) on
 // its filled tile; the work split is the Cartesian step's.
-template <int MX, int NT, int LIM>
+template <int MX, int NT>
 __device__ void advance_mapped_patch(const Ctx &c, const View &w, MappedSmem<MX> &s, int p, int lev, double t,
                                      double dt, double &cfl) {
     constexpr int N = MX + 2 * MB, NP = ScalarSmem<MX>::NP;
@@ -1262,26 +1287,29 @@ __device__ void advance_mapped_patch(const Ctx &c, const View &w, MappedSmem<MX>
     int line = 0, e0 = 0;
     const bool xs = tid < NI, ys = !xs && tid < 2 * NI;
     const int half = (xs ? tid : tid - NI) / HI, r = (xs ? tid : tid - NI) % HI;
+    bool pos = true;
     if (xs) {
         line = half * (MX / 2) + r % (MX / 2);
         e0 = (r / (MX / 2)) * SEG;
-        msweep_segment<MX, SEG, LIM, 0>(s, line, e0, R, cm);
+        pos = line_pos(c.velocity, s.ux[e0], s.uy[line + 1]);
     } else if (ys) {
         line = r % MX;
         e0 = (half * (NSEG / 2) + r / MX) * SEG;
-        msweep_segment<MX, SEG, LIM, 1>(s, line, e0, R, cm);
+        pos = line_pos(c.velocity, s.vy[e0], s.vx[line + 1]);
     }
-    if (tid >= GT0 && tid < GT0 + NO) {  // rows -1, MX and columns -1, MX: TX, TY only
-        const int k = tid - GT0, g = k / (MX / SO);
-        msweep_outer<MX, SO, LIM>(s, g >> 1, (g & 1) ? MX : -1, (k % (MX / SO)) * SO);
+    switch (c.lim) {
+        case 1: mapped_sweeps<MX, NT, 1>(s, tid, xs, ys, line, e0, pos, c.velocity, R, cm); break;
+        case 2: mapped_sweeps<MX, NT, 2>(s, tid, xs, ys, line, e0, pos, c.velocity, R, cm); break;
+        case 3: mapped_sweeps<MX, NT, 3>(s, tid, xs, ys, line, e0, pos, c.velocity, R, cm); break;
+        default: mapped_sweeps<MX, NT, 0>(s, tid, xs, ys, line, e0, pos, c.velocity, R, cm); break;
     }
     cm = wave_max_last_lane(cm);
     if ((tid & 63) == 63) atomicMax(&s.mcfl, (unsigned long long)__double_as_longlong(cm));
     __syncthreads();
     if (xs) {
-        mpart_row<MX, SEG>(s, line, e0, R);
+        mpart_row<MX, SEG>(s, line, e0, pos, R);
     } else if (ys) {
-        mpart_col<MX, SEG>(s, line, e0, R);
+        mpart_col<MX, SEG>(s, line, e0, pos, R);
 #pragma unroll
         for (int k = 0; k < SEG; k++) s.q[(e0 + k + MB) * NP + line + MB] = R[k];
     }
@@ -1310,12 +1338,7 @@ __global__ void __launch_bounds__(NT) advance_mapped_kernel(Ctx c, int first, in
     const double old = cfl_slot_old(slot);
     double cfl = 0.0;
     const View w = view_of(c);
-    switch (c.lim) {
-        case 1: advance_mapped_patch<MX, NT, 1>(c, w, s, p, level, t, dt, cfl); break;
-        case 2: advance_mapped_patch<MX, NT, 2>(c, w, s, p, level, t, dt, cfl); break;
-        case 3: advance_mapped_patch<MX, NT, 3>(c, w, s, p, level, t, dt, cfl); break;
-        default: advance_mapped_patch<MX, NT, 0>(c, w, s, p, level, t, dt, cfl); break;
-    }
+    advance_mapped_patch<MX, NT>(c, w, s, p, level, t, dt, cfl);
     store_cfl_slot(slot, old, cfl);
 }
 
