@@ -46,6 +46,13 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
+def level_step_name(mx, nt, seg):
+    """The scalar level-step kernel as instantiated (last argument: cells per
+    sweep segment, 0 for the default length)."""
+    default = max(4, min(mx, 2 * mx * mx // nt))
+    return "level_step_kernel<%d,%d,0,%d>" % (mx, nt, 0 if seg == default else seg)
+
+
 def algorithmic_bytes(npatch, mx, F):
     """Read every patch tile with its halo once, write its interior once."""
     N = mx + 4
@@ -165,6 +172,8 @@ def main():
                          "L2 misfit, uniform level 6, 256 steps, checkpoints every 16), mapped_uniform (the swirl "
                          "on a mapped grid, --level, --map-alpha; fill and capacity-form advance timed apart)")
     ap.add_argument("--map-alpha", type=float, default=0.1, help="mapping amplitude of --workload mapped_uniform")
+    ap.add_argument("--tile", type=int, default=0,
+                    help="cells per sweep segment of the scalar advance with --threads (0: the default)")
     ap.add_argument("--threads", type=int, default=0,
                     help="threads per patch of the advance kernels (0: autotune)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -199,7 +208,7 @@ def main():
     if args.workload == "swirl_uniform":
         steps = args.steps if args.steps is not None else 500
         warm = args.warmup if args.warmup is not None else 500
-        out = uniform_workload(args.level, args.mx, steps, warm, args.threads, not args.no_per_level)
+        out = uniform_workload(args.level, args.mx, steps, warm, args.threads, not args.no_per_level, args.tile)
         if not args.no_cpu_baseline:
             from workloads import synth as S
             w = S.workload("swirl_uniform", level=args.level, mx=args.mx, steps=steps)
@@ -209,7 +218,7 @@ def main():
     return amr_workload(args)
 
 
-def uniform_workload(level, mx, steps, warmup, threads=0, forms=True):
+def uniform_workload(level, mx, steps, warmup, threads=0, forms=True, tile=0):
     """Uniform level of the swirl workload, graph form (one level-step kernel
     per coarse step, 50-step chunks plus one graph for the rest replayed);
     returns the fields of a bench line (no cpu_baseline)."""
@@ -224,9 +233,10 @@ def uniform_workload(level, mx, steps, warmup, threads=0, forms=True):
     ps = B.from_workload(w)
     if threads:
         ps.set_variant(threads)
-        nt = threads
+        ps.set_tile(tile)
     else:
-        nt = ps.autotune()
+        ps.autotune()
+    nt, seg = ps.launch()
     stream = torch.cuda.current_stream()
 
     def timed(store, mode, k):
@@ -262,6 +272,7 @@ def uniform_workload(level, mx, steps, warmup, threads=0, forms=True):
         for mode in ("per_level", "fused_levels"):
             ps2 = B.from_workload(w)
             ps2.set_variant(nt)
+            ps2.set_tile(seg)
             ps2.coarse_steps(dt, min(warmup, 50), mode)
             ps2.prepare_steps(dt, steps, mode)
             s2 = timed(ps2, mode, steps)
@@ -279,10 +290,10 @@ def uniform_workload(level, mx, steps, warmup, threads=0, forms=True):
                                f"FP64 scalar advection, swirl field T=1, seeded 8-Gaussian data, {steps} steps",
                    "patches": P, "mx": mx, "cells": cells_per_step,
                    "mode": "fused: one ghost-gathering advance kernel per level-step, replayed from a hipGraph",
-                   "threads_per_patch": nt, "graph_capture_ms": capture_ms},
+                   "threads_per_patch": nt, "sweep_segment_cells": seg, "graph_capture_ms": capture_ms},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": (ratio * bpl) if ratio else None,
-                     "kernel": "level_step_kernel<%d,%d,0>" % (mx, nt), "bytes_per_launch": bpl,
+                     "kernel": level_step_name(mx, nt, seg), "bytes_per_launch": bpl,
                      "avg_launch_ms": 1e3 * avg_launch, "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
         "per_level": per_level,
         "other_forms": forms_out,
@@ -381,14 +392,16 @@ def amr_workload(args):
     cap = 4 ** w["lmax"]
     ps = B.from_workload(w, capacity=cap)
     if args.threads:
-        nt = args.threads
+        nt, seg = args.threads, args.tile
     else:
-        nt = ps.autotune()
+        ps.autotune()
+        nt, seg = ps.launch()
     del ps
     res = {}
     for mode in ("graph",) + (() if args.no_per_level else ("per_level",)):
         ps = B.from_workload(w, capacity=cap)
         ps.set_variant(nt)
+        ps.set_tile(seg)
         run_adaptive(ps, dt, warm, regrid_every=2, mode=mode)
         tm = {}
         cells = run_adaptive(ps, dt, steps, regrid_every=2, mode=mode, timings=tm)
@@ -406,7 +419,7 @@ def amr_workload(args):
     copy_gbs = stream_copy_gbs()
     l8 = None
     if not args.no_l8:
-        u = uniform_workload(8, 32, args.l8_steps, args.l8_steps, nt, not args.no_per_level)
+        u = uniform_workload(8, 32, args.l8_steps, args.l8_steps, nt, not args.no_per_level, seg)
         l8 = {"workload": u["config"]["workload"], "value": u["value"], "unit": "cell-updates/s",
               "ms_per_step": u["ms_per_step"], "roofline": u["roofline"],
               "per_level": u["per_level"], "fused_over_per_level": u["fused_over_per_level"]}
@@ -424,12 +437,12 @@ def amr_workload(args):
                    "patches_start": len(lv), "patches_end": g["patches_end"], "mx": 32,
                    "mode": "fused: one ghost-gathering advance kernel per level-step, the coarse steps between "
                            "two regrids replayed from one hipGraph",
-                   "threads_per_patch": nt, "cell_updates": g["cells"],
+                   "threads_per_patch": nt, "sweep_segment_cells": seg, "cell_updates": g["cells"],
                    "regrid_ms_each": 1e3 * g["regrid_s"] / max(1, g["regrids"]),
                    "value_with_regrid": g["cells"] / (g["advance_s"] + g["regrid_s"])},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": (ratio * bpl) if ratio else None,
-                     "kernel": "level_step_kernel<32,%d,0>" % nt, "launches": g["launches"],
+                     "kernel": level_step_name(32, nt, seg), "launches": g["launches"],
                      "bytes_per_launch": bpl, "avg_launch_ms": 1e3 * g["advance_s"] / g["launches"],
                      "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
         "per_level": per_level,

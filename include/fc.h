@@ -337,20 +337,33 @@ fc_status fc_adjoint_step(fc_patchstore *ps, int32_t level, double t, double dt,
  * reduction (FC_ERR_NONFINITE).  The flags stay raised until the next bind. */
 fc_status fc_check_device(fc_patchstore *ps, void *stream);
 
-/* Choose the launch configuration (waves per patch) of the advance kernels
- * by timing every variant on the bound store (results are bitwise equal); a
- * variant other than the default (scalar advection, also on a mapped grid:
- * 64 threads at mx = 8, else 256; shallow water: 192 at mx = 8, 512 at
- * mx = 16) is taken only if it is at least 5% faster (best of three
- * interleaved timing rounds).
- * Returns the chosen threads per patch. */
+/* Choose the launch configuration of the advance kernels by timing every
+ * variant on the bound store (results are bitwise equal): threads (waves) per
+ * patch and, for scalar advection on a Cartesian grid, the tile shape of the
+ * edge sweeps (fc_set_tile).  A variant other than the default (scalar
+ * advection, also on a mapped grid: 64 threads at mx = 8, else 256, shortest
+ * segments; shallow water: 192 at mx = 8, 512 at mx = 16) is taken only if it
+ * is at least 5% faster (best of three interleaved timing rounds).  Returns
+ * the chosen threads per patch (fc_get_launch gives both). */
 fc_status fc_autotune(fc_patchstore *ps, int32_t *threads_out, void *stream);
 /* Set the threads per patch directly.  Scalar advection: 64 or 128 at
  * mx = 8; 64, 128 or 256 at mx = 16; 128, 256 or 512 at mx = 32.  Shallow
  * water: 64, 128 or 192 at mx = 8; 256, 384, 512 or 640 at mx = 16 (a
- * mapped grid: those of scalar advection).  FC_ERR_ARG otherwise.  Drops
- * captured graphs. */
+ * mapped grid: those of scalar advection).  FC_ERR_ARG otherwise.  Resets the
+ * tile shape to the default.  Drops captured graphs. */
 fc_status fc_set_variant(fc_patchstore *ps, int32_t threads_per_patch);
+/* Tile shape of the scalar edge sweeps (Cartesian grid): every interior
+ * line is cut into segments of seg_cells cells, one per work item.  0 (or
+ * the default) = the shortest that gives every segment its own thread,
+ * max(4, min(mx, 2 mx^2 / threads)); the other choice is twice that, where a
+ * line still splits into an even number of segments (mx = 16 at 128 or 256
+ * threads: 8; mx = 32 at 256: 16, at 512: 8).  FC_ERR_ARG otherwise (and for
+ * shallow water and mapped grids, which have one tile shape).  Drops
+ * captured graphs. */
+fc_status fc_set_tile(fc_patchstore *ps, int32_t seg_cells);
+/* The current launch configuration: threads per patch and cells per sweep
+ * segment (either may be NULL). */
+fc_status fc_get_launch(const fc_patchstore *ps, int32_t *threads_per_patch, int32_t *seg_cells);
 /* Workgroups of the persistent kernel: 0 = as many as can be co-resident
  * (occupancy x compute units), else min(grid, that).  max_grid (may be
  * NULL) receives the co-resident maximum. */

@@ -31,7 +31,8 @@ EXPORTS = ["fc_last_error", "fc_patchstore_create", "fc_patchstore_create_brick"
            "fc_patchstore_bind", "fc_patchstore_info", "fc_patchstore_leaves", "fc_patchstore_records", "fc_set_interior",
            "fc_get_interior", "fc_get_patches", "fc_ghost_fill", "fc_advance_level",
            "fc_advance_coarse_steps", "fc_advance_adaptive", "fc_advance_level_noalloc", "fc_get_time", "fc_set_time", "fc_tag_refine", "fc_adapt", "fc_adapt_device", "fc_regrid",
-           "fc_prepare_steps", "fc_step_uniform", "fc_adjoint_step", "fc_check_device", "fc_autotune", "fc_set_variant", "fc_set_persistent_grid"]
+           "fc_prepare_steps", "fc_step_uniform", "fc_adjoint_step", "fc_check_device", "fc_autotune", "fc_set_variant", "fc_set_persistent_grid",
+           "fc_set_tile", "fc_get_launch"]
 
 
 class FcError(RuntimeError):
@@ -93,6 +94,8 @@ def lib():
         L.fc_adjoint_step.argtypes = [vp, C.c_int32, C.c_double, C.c_double, vp, vp, vp, vp]
         L.fc_check_device.argtypes = [vp, vp]
         L.fc_autotune.argtypes = [vp, C.POINTER(C.c_int32), vp]
+        L.fc_set_tile.argtypes = [vp, C.c_int32]
+        L.fc_get_launch.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.fc_set_variant.argtypes = [vp, C.c_int32]
         L.fc_set_persistent_grid.argtypes = [vp, C.c_int32, C.POINTER(C.c_int32)]
         for f in EXPORTS:
@@ -307,6 +310,16 @@ class PatchStore:
 
     def set_variant(self, threads_per_patch):
         _check(lib().fc_set_variant(self._h, int(threads_per_patch)))
+
+    def set_tile(self, seg_cells=0):
+        """Cells per sweep segment of the scalar advance (0: the default)."""
+        _check(lib().fc_set_tile(self._h, int(seg_cells)))
+
+    def launch(self):
+        """(threads per patch, cells per sweep segment) in use."""
+        nt, sg = C.c_int32(), C.c_int32()
+        _check(lib().fc_get_launch(self._h, C.byref(nt), C.byref(sg)))
+        return nt.value, sg.value
 
     def set_persistent_grid(self, grid=0):
         """Persistent-kernel workgroups (0: all that fit); returns the maximum."""

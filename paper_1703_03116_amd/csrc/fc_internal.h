@@ -122,7 +122,24 @@ struct LevelRange {
 // ---- kernel launchers (fc_kernels.hip) --------------------------------
 struct LaunchCfg {
     int mx, nt;                // patch edge, threads per patch
+    int seg;                   // scalar sweeps: cells per segment (0: the shortest that fits)
 };
+
+// Tile shapes of the scalar advance: the shortest segment that lets every
+// interior line segment have its own thread, max(4, min(mx, 2 mx^2 / nt)),
+// and, where the segments of a line still split into two halves, twice that
+// (fewer, longer items: fewer edges computed twice, more threads left for
+// the outer lines).  0 where there is no long variant.
+inline int tile_default(int mx, int nt) {
+    int sg = 2 * mx * mx / nt;
+    if (sg < 4) sg = 4;
+    if (sg > mx) sg = mx;
+    return sg;
+}
+inline int tile_long(int mx, int nt) {
+    const int sg = 2 * tile_default(mx, nt);
+    return (mx / sg >= 2 && (mx / sg) % 2 == 0) ? sg : 0;
+}
 
 hipError_t launch_init_tables(int level, int mx, int periodic_x, int periodic_y, double *vt, hipStream_t s);
 // capacity table of a mapped level with n cells per axis (alpha: the mapping's amplitude)

@@ -732,15 +732,11 @@ struct LeafIO {
     const int32_t *leaf_of_slot;
 };
 
-// LEAF: read the step's input from io->qin and write its result to io->qout
-// instead of the store's buffers (uniform periodic level: every ghost value
-// is a same-size copy); the arithmetic is the same code either way.
 // The sweeps of one limiter (work items as in advance_scalar_lim).
-template <int MX, int NT, int LIM>
+template <int MX, int NT, int LIM, int SEG>
 __device__ __forceinline__ void scalar_sweeps(ScalarSmem<MX> &s, int tid, bool xs, bool ys, int line, int e0,
-                                              double lam, bool pos, int velocity,
-                                              double (&R)[scalar_seg<MX, NT>()]) {
-    constexpr int SEG = scalar_seg<MX, NT>(), NI = MX * (MX / SEG);
+                                              double lam, bool pos, int velocity, double (&R)[SEG]) {
+    constexpr int NI = MX * (MX / SEG);
     constexpr int SO = 2, NO = 4 * (MX / SO);
     constexpr int GT0 = (NT - 2 * NI >= NO) ? 2 * NI : NI;
     if (xs) sweep_segment<MX, SEG, LIM, 0>(s, line, e0, lam, pos, R);
@@ -751,10 +747,14 @@ __device__ __forceinline__ void scalar_sweeps(ScalarSmem<MX> &s, int tid, bool x
     }
 }
 
+// LEAF: read the step's input from io->qin and write its result to io->qout
+// instead of the store's buffers (uniform periodic level: every ghost value
+// is a same-size copy); the arithmetic is the same code either way.
 // The limiter (c.lim) selects the sweeps only: the load and gather before
 // them and the transverse terms and the store after them are one code path,
 // so that no value loaded ahead is held across four copies of the kernel.
-template <int MX, int NT, bool FUSED, bool LEAF = false>
+// SEGC: cells per sweep segment (0: the shortest that fits, scalar_seg).
+template <int MX, int NT, bool FUSED, bool LEAF = false, int SEGC = 0>
 __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, ScalarSmem<MX> &s, int p, int lev,
                                                    double t, double dt, const double *tdev,
                                                    const unsigned long long *slot, double &cfl,
@@ -769,7 +769,7 @@ __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, 
     // lower-half column items (or of idle threads), so that no wave carries a
     // long extra chain into the barrier; the odd ghost cells and c(t) go to
     // the same threads.
-    constexpr int SEG = scalar_seg<MX, NT>(), NSEG = MX / SEG, NI = MX * NSEG, HI = NI / 2;
+    constexpr int SEG = SEGC ? SEGC : scalar_seg<MX, NT>(), NSEG = MX / SEG, NI = MX * NSEG, HI = NI / 2;
     constexpr int SO = 2, NO = 4 * (MX / SO);  // outer-line segment length and item count
     constexpr int GT0 = (NT - 2 * NI >= NO) ? 2 * NI : NI;  // first thread of the outer-line items
     static_assert(2 * NI <= NT && NSEG % 2 == 0, "interior items must fit one pass, in two halves");
@@ -953,10 +953,10 @@ __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, 
         pos = line_pos(c.velocity, s.vy[e0], s.vx[line + 1]);
     }
     switch (c.lim) {
-        case 1: scalar_sweeps<MX, NT, 1>(s, tid, xs, ys, line, e0, lam, pos, c.velocity, R); break;
-        case 2: scalar_sweeps<MX, NT, 2>(s, tid, xs, ys, line, e0, lam, pos, c.velocity, R); break;
-        case 3: scalar_sweeps<MX, NT, 3>(s, tid, xs, ys, line, e0, lam, pos, c.velocity, R); break;
-        default: scalar_sweeps<MX, NT, 0>(s, tid, xs, ys, line, e0, lam, pos, c.velocity, R); break;
+        case 1: scalar_sweeps<MX, NT, 1, SEG>(s, tid, xs, ys, line, e0, lam, pos, c.velocity, R); break;
+        case 2: scalar_sweeps<MX, NT, 2, SEG>(s, tid, xs, ys, line, e0, lam, pos, c.velocity, R); break;
+        case 3: scalar_sweeps<MX, NT, 3, SEG>(s, tid, xs, ys, line, e0, lam, pos, c.velocity, R); break;
+        default: scalar_sweeps<MX, NT, 0, SEG>(s, tid, xs, ys, line, e0, lam, pos, c.velocity, R); break;
     }
     __syncthreads();
     // direction parts: columns into the tile's interior (nothing reads the
@@ -1000,14 +1000,14 @@ __device__ __forceinline__ void advance_scalar_lim(const Ctx &c, const View &w, 
     cfl = fmax(cfl, lam * __longlong_as_double((long long)s.cfl));
 }
 
-template <int MX, int NT, bool FUSED>
 // lev: the patch's level when the caller knows it (a level-step), else -1;
 // tdev: if given, the step starts at *tdev + t;
 // slot: if given, its old value is left in s.red[15] for reduce_cfl_slot
+template <int MX, int NT, bool FUSED, int SEGC = 0>
 __device__ __forceinline__ void advance_scalar_patch(const Ctx &c, const View &w, ScalarSmem<MX> &s, int p, int lev,
                                                      double t, double dt, double &cfl, const double *tdev = nullptr,
                                                      const unsigned long long *slot = nullptr) {
-    advance_scalar_lim<MX, NT, FUSED>(c, w, s, p, lev, t, dt, tdev, slot, cfl);
+    advance_scalar_lim<MX, NT, FUSED, false, SEGC>(c, w, s, p, lev, t, dt, tdev, slot, cfl);
 }
 
 // block-wide max of a non-negative double, then one atomicMax on its bits
@@ -1068,14 +1068,14 @@ constexpr int min_waves() {
     return (EQ == 1 && MX == 16 && NT >= 256) ? NT / 128 : 1;
 }
 
-template <int MX, int NT, bool FUSED>
+template <int MX, int NT, bool FUSED, int SEGC = 0>
 __global__ void __launch_bounds__(NT, (min_waves<MX, NT, 0>())) advance_scalar_kernel(Ctx c, int first, int count, int level, double t,
                                                                                      double dt) {
     __shared__ ScalarSmem<MX> s;
     const int p = first + xcd_remap(blockIdx.x, count);
     unsigned long long *slot = c.cflp ? c.cflp + p : nullptr;
     double cfl = 0.0;
-    advance_scalar_patch<MX, NT, FUSED>(c, view_of(c), s, p, level, t, dt, cfl, nullptr, slot);
+    advance_scalar_patch<MX, NT, FUSED, SEGC>(c, view_of(c), s, p, level, t, dt, cfl, nullptr, slot);
     store_cfl_slot(slot, s.red[15], cfl);
 }
 
@@ -1983,7 +1983,7 @@ struct StepArgs {
     double off, scale, alpha, dtc;
 };
 
-template <int MX, int NT, int EQ>
+template <int MX, int NT, int EQ, int SEGC = 0>
 __global__ void __launch_bounds__(NT, (min_waves<MX, NT, EQ>())) level_step_kernel(Ctx c, StepArgs a, DevState *st) {
     __shared__ typename SmemOf<MX, EQ>::type s;
     const View w{a.mask, a.level < 0 ? -1 : a.level - 1, a.level < 0 ? 1.0 : a.alpha};
@@ -1991,7 +1991,8 @@ __global__ void __launch_bounds__(NT, (min_waves<MX, NT, EQ>())) level_step_kern
     double cfl = 0.0;
     const int p = a.first + xcd_remap(blockIdx.x, a.count);
     if constexpr (EQ == 0) {
-        advance_scalar_patch<MX, NT, true>(c, w, s, p, a.level, a.off * a.dtc, dt, cfl, &st->ts[a.cidx], c.cflp + p);
+        advance_scalar_patch<MX, NT, true, SEGC>(c, w, s, p, a.level, a.off * a.dtc, dt, cfl, &st->ts[a.cidx],
+                                                 c.cflp + p);
         store_cfl_slot(c.cflp + p, s.red[15], cfl);
     } else {
         const double old = cfl_slot_old(c.cflp + p);
@@ -2433,11 +2434,11 @@ hipError_t launch_fill(const Ctx &c, int mx, int first, int count, hipStream_t s
     return hipErrorInvalidValue;
 }
 
-template <int MX, int NT>
+template <int MX, int NT, int SEGC>
 static hipError_t adv_scalar(const Ctx &c, int first, int count, int level, double t, double dt, int fused,
                              hipStream_t s) {
-    if (fused) hipLaunchKernelGGL((advance_scalar_kernel<MX, NT, true>), dim3(count), dim3(NT), 0, s, c, first, count, level, t, dt);
-    else hipLaunchKernelGGL((advance_scalar_kernel<MX, NT, false>), dim3(count), dim3(NT), 0, s, c, first, count, level, t, dt);
+    if (fused) hipLaunchKernelGGL((advance_scalar_kernel<MX, NT, true, SEGC>), dim3(count), dim3(NT), 0, s, c, first, count, level, t, dt);
+    else hipLaunchKernelGGL((advance_scalar_kernel<MX, NT, false, SEGC>), dim3(count), dim3(NT), 0, s, c, first, count, level, t, dt);
     return hipGetLastError();
 }
 
@@ -2464,8 +2465,12 @@ hipError_t launch_advance(const Ctx &c, LaunchCfg lc, int level, int first, int 
         return hipErrorInvalidValue;
     }
     if (c.eq == 0) {
-#define ADV(MXV, NTV) if (lc.mx == MXV && lc.nt == NTV) return adv_scalar<MXV, NTV>(c, first, count, level, t, dt, fused, s);
-        ADV(8, 64) ADV(8, 128) ADV(16, 64) ADV(16, 128) ADV(16, 256) ADV(32, 128) ADV(32, 256) ADV(32, 512)
+#define ADV(MXV, NTV, SG) \
+    if (lc.mx == MXV && lc.nt == NTV && lc.seg == SG) return adv_scalar<MXV, NTV, SG>(c, first, count, level, t, dt, fused, s);
+        ADV(8, 64, 0) ADV(8, 128, 0) ADV(16, 64, 0) ADV(16, 128, 0) ADV(16, 256, 0) ADV(32, 128, 0) ADV(32, 256, 0)
+        ADV(32, 512, 0)
+        // long segments: twice the shortest that fits (see tile_long)
+        ADV(16, 128, 8) ADV(16, 256, 8) ADV(32, 256, 16) ADV(32, 512, 8)
 #undef ADV
     } else {
 #define ADV(MXV, NTV) if (lc.mx == MXV && lc.nt == NTV) return adv_swe<MXV, NTV>(c, first, count, dt, fused, s);
@@ -2513,9 +2518,15 @@ int persistent_max_grid(LaunchCfg lc, int eq) {
 
 static const void *level_step_select(LaunchCfg lc, int eq) {
 #define PS(MXV, NTV, EQV) \
-    if (lc.mx == MXV && lc.nt == NTV && eq == EQV) return reinterpret_cast<const void *>(&level_step_kernel<MXV, NTV, EQV>);
+    if (lc.mx == MXV && lc.nt == NTV && eq == EQV && lc.seg == 0) \
+        return reinterpret_cast<const void *>(&level_step_kernel<MXV, NTV, EQV>);
+#define PL(MXV, NTV, SG) \
+    if (lc.mx == MXV && lc.nt == NTV && eq == 0 && lc.seg == SG) \
+        return reinterpret_cast<const void *>(&level_step_kernel<MXV, NTV, 0, SG>);
     PS(8, 64, 0) PS(8, 128, 0) PS(16, 64, 0) PS(16, 128, 0) PS(16, 256, 0) PS(32, 128, 0) PS(32, 256, 0) PS(32, 512, 0)
     PS(8, 64, 1) PS(8, 128, 1) PS(8, 192, 1) PS(16, 256, 1) PS(16, 384, 1) PS(16, 512, 1) PS(16, 640, 1)
+    PL(16, 128, 8) PL(16, 256, 8) PL(32, 256, 16) PL(32, 512, 8)
+#undef PL
 #undef PS
     return nullptr;
 }

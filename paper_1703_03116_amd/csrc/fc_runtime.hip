@@ -185,6 +185,7 @@ struct fc_patchstore {
     uint32_t curmask = 0;
     double t = 0.0;
     int nt = 0;  // threads per patch of the advance kernels
+    int seg = 0;  // scalar sweeps: cells per segment (0: the shortest that fits nt)
     // device
     double *q0 = nullptr, *q1 = nullptr;
     char *ws = nullptr;
@@ -568,7 +569,7 @@ fc_status advance_one(fc_patchstore *ps, int level, double t, double dt, int fus
         c.clevel = clevel;
         c.alpha = alpha;
         if (!rec) c.cflp = nullptr;
-        HIPCHK(launch_advance(c, LaunchCfg{ps->mx, ps->nt}, level, ps->lr.start[level], ps->lr.count[level], t, dt,
+        HIPCHK(launch_advance(c, LaunchCfg{ps->mx, ps->nt, ps->seg}, level, ps->lr.start[level], ps->lr.count[level], t, dt,
                               fused_load, s));
     }
     ps->curmask ^= 1u << level;
@@ -643,7 +644,7 @@ fc_status capture_levels(fc_patchstore *ps, fc_patchstore::Graph &out, int ncoar
             const SchedEntry &en = ps->sched[k];
             const int first = en.level < 0 ? 0 : ps->lr.start[en.level];
             const int cnt = en.level < 0 ? nall : ps->lr.count[en.level];
-            if (cnt > 0) e = launch_level_step(c, LaunchCfg{ps->mx, ps->nt}, en, first, cnt, cs, mask ^ flip, dtc,
+            if (cnt > 0) e = launch_level_step(c, LaunchCfg{ps->mx, ps->nt, ps->seg}, en, first, cnt, cs, mask ^ flip, dtc,
                                                dstate(ps), ps->cap_stream);
             flip ^= en.level < 0 ? allmask : (1u << en.level);
         }
@@ -882,7 +883,7 @@ fc_status fc_advance_level_noalloc(fc_patchstore *ps, int32_t level, double t, d
     if (ps->lr.count[level] > 0) {
         Ctx c = make_ctx(ps);
         c.cflp = slots;
-        HIPCHK(launch_advance(c, LaunchCfg{ps->mx, ps->nt}, level, ps->lr.start[level], ps->lr.count[level], t, dt,
+        HIPCHK(launch_advance(c, LaunchCfg{ps->mx, ps->nt, ps->seg}, level, ps->lr.start[level], ps->lr.count[level], t, dt,
                               0, s));
     }
     ps->curmask ^= 1u << level;
@@ -1022,7 +1023,7 @@ static fc_status advance_steps(fc_patchstore *ps, double dt_coarse, int32_t nste
                 if (e.level < 0) {
                     Ctx c = make_ctx(ps);
                     if (!cfl) c.cflp = nullptr;
-                    HIPCHK(launch_advance(c, LaunchCfg{ps->mx, ps->nt}, -1, 0, nleaf, t, dt, 1, s));
+                    HIPCHK(launch_advance(c, LaunchCfg{ps->mx, ps->nt, ps->seg}, -1, 0, nleaf, t, dt, 1, s));
                     for (int l = 0; l < FC_MAXLEV; l++)
                         if (ps->lr.count[l] > 0) ps->curmask ^= 1u << l;
                 } else {
@@ -1403,8 +1404,31 @@ fc_status fc_set_variant(fc_patchstore *ps, int32_t threads_per_patch) {
     if (!valid_nt(ps->mx, threads_per_patch, ps->cfg.equation))
         return fail(FC_ERR_ARG, "unsupported threads per patch for this mx");
     ps->nt = threads_per_patch;
+    ps->seg = 0;
     if (ps->ws) ps->pgrid = persistent_max_grid(persistent_cfg(ps), ps->cfg.equation);
     drop_graph(ps);
+    return FC_OK;
+}
+
+// the long tile of the current variant, if the store's advance has tiles
+static int store_tile_long(const fc_patchstore *ps, int nt) {
+    return (ps->cfg.equation == FC_EQ_ADVECTION && ps->cfg.map_alpha == 0.0) ? tile_long(ps->mx, nt) : 0;
+}
+
+fc_status fc_set_tile(fc_patchstore *ps, int32_t seg_cells) {
+    if (!ps) return fail(FC_ERR_ARG, "null store");
+    const int def = tile_default(ps->mx, ps->nt), lg = store_tile_long(ps, ps->nt);
+    if (seg_cells == 0 || seg_cells == def) ps->seg = 0;
+    else if (lg != 0 && seg_cells == lg) ps->seg = lg;
+    else return fail(FC_ERR_ARG, "unsupported segment length for this mx, thread count and equation");
+    drop_graph(ps);
+    return FC_OK;
+}
+
+fc_status fc_get_launch(const fc_patchstore *ps, int32_t *threads_per_patch, int32_t *seg_cells) {
+    if (!ps) return fail(FC_ERR_ARG, "null store");
+    if (threads_per_patch) *threads_per_patch = ps->nt;
+    if (seg_cells) *seg_cells = ps->seg ? ps->seg : tile_default(ps->mx, ps->nt);
     return FC_OK;
 }
 
@@ -1414,14 +1438,20 @@ fc_status fc_autotune(fc_patchstore *ps, int32_t *threads_out, void *stream) {
     hipStream_t s = (hipStream_t)stream;
     // time the advance of the most populated level (the fused-load kernel;
     // on a mapped grid the capacity-form kernel), writing only the levels'
-    // other buffers (the state is left unchanged)
+    // other buffers (the state is left unchanged), for every pair of threads
+    // per patch and tile shape (segment length)
     const int fused = ps->cfg.map_alpha != 0.0 ? 0 : 1;
     int lbest = ps->cfg.min_level;
     for (int l = ps->cfg.min_level; l <= ps->cfg.max_level; l++)
         if (ps->lr.count[l] > ps->lr.count[lbest]) lbest = l;
     const double h = 1.0 / (double)(ps->mx << lbest);
     const double dt = 0.5 * h;
-    const std::vector<int> cl = variants(ps->mx, ps->cfg.equation);
+    std::vector<LaunchCfg> cl;
+    for (int nt : variants(ps->mx, ps->cfg.equation)) {
+        cl.push_back(LaunchCfg{ps->mx, nt, 0});
+        const int lg = store_tile_long(ps, nt);
+        if (lg) cl.push_back(LaunchCfg{ps->mx, nt, lg});
+    }
     const int nc = (int)cl.size();
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
@@ -1432,32 +1462,33 @@ fc_status fc_autotune(fc_patchstore *ps, int32_t *threads_out, void *stream) {
     std::vector<float> t(nc, 1e30f);
     for (int round = 0; round < 3; round++)
         for (int k = 0; k < nc; k++) {
-            const int nt = cl[k];
             Ctx c = make_ctx(ps);
             c.cflp = nullptr;
-            LaunchCfg lc{ps->mx, nt};
             for (int w = 0; w < 2; w++)
-                HIPCHK(launch_advance(c, lc, lbest, ps->lr.start[lbest], ps->lr.count[lbest], ps->t, dt, fused, s));
+                HIPCHK(launch_advance(c, cl[k], lbest, ps->lr.start[lbest], ps->lr.count[lbest], ps->t, dt, fused, s));
             HIPCHK(hipEventRecord(e0, s));
             for (int w = 0; w < 10; w++)
-                HIPCHK(launch_advance(c, lc, lbest, ps->lr.start[lbest], ps->lr.count[lbest], ps->t, dt, fused, s));
+                HIPCHK(launch_advance(c, cl[k], lbest, ps->lr.start[lbest], ps->lr.count[lbest], ps->t, dt, fused, s));
             HIPCHK(hipEventRecord(e1, s));
             HIPCHK(hipEventSynchronize(e1));
             float ms = 0;
             HIPCHK(hipEventElapsedTime(&ms, e0, e1));
             t[k] = std::min(t[k], ms);
         }
-    int bnt = default_nt(ps->mx, ps->cfg.equation), kd = 0;
+    const int dnt = default_nt(ps->mx, ps->cfg.equation);
+    int kd = 0;
     for (int k = 0; k < nc; k++)
-        if (cl[k] == bnt) kd = k;
-    float best = t[kd];
+        if (cl[k].nt == dnt && cl[k].seg == 0) kd = k;
+    int kb = kd;
     for (int k = 0; k < nc; k++)
-        if (k != kd && t[k] < 0.95f * best) { best = t[k]; bnt = cl[k]; }
+        if (k != kd && t[k] < 0.95f * t[kd] && t[k] < t[kb]) kb = k;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    r = fc_set_variant(ps, bnt);
+    r = fc_set_variant(ps, cl[kb].nt);
     if (r != FC_OK) return r;
-    if (threads_out) *threads_out = bnt;
+    r = fc_set_tile(ps, cl[kb].seg);
+    if (r != FC_OK) return r;
+    if (threads_out) *threads_out = cl[kb].nt;
     return FC_OK;
 }
 

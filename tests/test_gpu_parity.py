@@ -269,18 +269,26 @@ def test_forms_bitwise_at_level_6(B):
 
 @pytest.mark.parametrize("mx", [8, 16, 32])
 def test_variants_bitwise(B, mx):
-    """Every launch variant (threads per patch) computes the same bits."""
+    """Every launch variant (threads per patch x tile shape, i.e. cells per
+    sweep segment) computes the same bits."""
     level = {8: 3, 16: 2, 32: 2}[mx]
     w = S.workload("swirl_uniform", level=level, mx=mx)
     nts = {8: [64, 128], 16: [64, 128, 256], 32: [128, 256, 512]}[mx]
-    res = []
+    longs = {(16, 128): 8, (16, 256): 8, (32, 256): 16, (32, 512): 8}
+    res, seen = [], []
     for nt in nts:
-        ps = B.from_workload(w)
-        ps.set_variant(nt)
-        ps.coarse_steps(w["dt_coarse"], 5, "fused")
-        ps.coarse_steps(w["dt_coarse"], 5, "per_level")
-        ps.coarse_steps(w["dt_coarse"], 5, "graph")
-        res.append(ps.interior().cpu().numpy())
+        for seg in (0, longs.get((mx, nt))):
+            if seg is None:
+                continue
+            ps = B.from_workload(w)
+            ps.set_variant(nt)
+            ps.set_tile(seg)
+            seen.append(ps.launch())
+            ps.coarse_steps(w["dt_coarse"], 5, "fused")
+            ps.coarse_steps(w["dt_coarse"], 5, "per_level")
+            ps.coarse_steps(w["dt_coarse"], 5, "graph")
+            res.append(ps.interior().cpu().numpy())
+    assert len(set(seen)) == len(seen)
     for r in res[1:]:
         assert np.array_equal(r, res[0])
 

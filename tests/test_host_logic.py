@@ -263,6 +263,41 @@ def test_map_alpha_validation(B):
     L.fc_patchstore_destroy(h0)
 
 
+def test_tile_shape_validation(B):
+    """Tile shapes of the scalar sweeps: the default and, where a line still
+    splits into an even number of segments, twice its length; refused
+    otherwise, and reset by a change of threads per patch."""
+    L = B.lib()
+    expect = {(8, 64): None, (8, 128): None, (16, 64): None, (16, 128): 8, (16, 256): 8, (32, 128): None,
+              (32, 256): 16, (32, 512): 8}
+    for (mx, nt), lg in expect.items():
+        st, h, _ = create(B, S.uniform_leaves(1), mx=mx)
+        assert st == 0
+        assert L.fc_set_variant(h, nt) == 0
+        d = max(4, min(mx, 2 * mx * mx // nt))
+        a, b = C.c_int32(), C.c_int32()
+        assert L.fc_get_launch(h, C.byref(a), C.byref(b)) == 0 and (a.value, b.value) == (nt, d)
+        assert L.fc_set_tile(h, d) == 0 and L.fc_set_tile(h, 0) == 0
+        for bad in (3, 2 * mx, d + 1):
+            assert L.fc_set_tile(h, bad) == -1
+        if lg is None:
+            assert L.fc_set_tile(h, 2 * d) == -1
+        else:
+            assert L.fc_set_tile(h, lg) == 0
+            assert L.fc_get_launch(h, C.byref(a), C.byref(b)) == 0 and b.value == lg
+            assert L.fc_set_variant(h, nt) == 0
+            assert L.fc_get_launch(h, C.byref(a), C.byref(b)) == 0 and b.value == d
+        L.fc_patchstore_destroy(h)
+    # one tile shape for a mapped grid
+    cfg = make_cfg(B, mx=32)
+    cfg.map_alpha = 0.1
+    arr, n = B._leaves_array(S.uniform_leaves(1))
+    h = C.c_void_p()
+    assert L.fc_patchstore_create(C.byref(cfg), n, arr, C.byref(h), None) == 0
+    assert L.fc_set_tile(h, 16) == -1 and L.fc_set_tile(h, 0) == 0
+    L.fc_patchstore_destroy(h)
+
+
 def create_brick(B, leaves, brick, orient, equation=0, velocity=1, **kw):
     cfg = make_cfg(B, **kw)
     cfg.equation, cfg.velocity = equation, velocity
