@@ -319,25 +319,21 @@ __device__ void ghost_cell(const Ctx &c, const View &w, int p, int i, int j, dou
 // g-th cell of the ghost frame in region-major order: the eight face halves
 // (MB x MX/2 cells each, numbered as region_rec numbers them), then the four
 // MB x MB corners.  Consecutive g share a region and so a neighbour record.
+// Branch-free: lanes of a wave fall in different regions, and a branch per
+// region kind would run every kind on every wave.
 template <int MX>
 __device__ __forceinline__ void ghost_region_index(int g, int &i, int &j, int &r) {
     constexpr int H = MX / 2, HF = MB * H;
-    if (g < 8 * HF) {
-        r = g / HF;
-        const int k = g % HF, along = (r & 1) * H + k % H, across = k / H;
-        switch (r >> 1) {
-            case 0: i = across - MB; j = along; break;
-            case 1: i = MX + across; j = along; break;
-            case 2: i = along; j = across - MB; break;
-            default: i = along; j = MX + across; break;
-        }
-    } else {
-        const int k = g - 8 * HF;
-        r = 8 + k / (MB * MB);
-        const int a = k % MB, b = (k / MB) % MB;
-        i = (r & 1) ? MX + a : a - MB;
-        j = (r & 2) ? MX + b : b - MB;
-    }
+    // face halves: region rf, `across` cells from the patch edge, `along` it
+    const int rf = g / HF, k = g % HF, along = (rf & 1) * H + k % H, across = k / H;
+    const int ac = (rf & 2) ? MX + across : across - MB;  // upper (right) side for odd rf >> 1
+    const bool xface = rf < 4;                            // left and right faces first
+    // corners: MB x MB cells each, regions 8 .. 11
+    const int kc = g - 8 * HF, rc = 8 + kc / (MB * MB), a = kc % MB, b = (kc / MB) % MB;
+    const bool face = g < 8 * HF;
+    i = face ? (xface ? ac : along) : ((rc & 1) ? MX + a : a - MB);
+    j = face ? (xface ? along : ac) : ((rc & 2) ? MX + b : b - MB);
+    r = face ? rf : rc;
 }
 
 // g-th ghost cell of the (MX+4)^2 frame: two bottom rows, two top rows, then

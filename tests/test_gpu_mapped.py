@@ -303,3 +303,29 @@ def test_mapped_launch_variants_bitwise_equal(B, O, mx, nts):
         outs.append(ps.interior().cpu().numpy())
     for o in outs[1:]:
         assert np.array_equal(outs[0], o)
+
+
+def test_mapped_adaptive_steps_with_rejection(B, O):
+    """Clawpack-style adaptive coarse steps on the mapped grid (per-level
+    form, cfl_max 1, target 0.9): the Courant number includes the cell areas,
+    so the first try, sized for the Cartesian grid, is rejected; step sizes,
+    accepted and rejected counts and the state against the same rule driven
+    with the oracle."""
+    from tests.test_gpu_contracts import oracle_adaptive
+    mx = 16
+    L = S.random_balanced_leaves(8, 1, 3)
+    q = S.sample_on_leaves(hump, L, mx)
+    ps = B.PatchStore(L, mx=mx, velocity="swirl", vel_params=(1.0, 0.0, 0.0), min_level=1, max_level=3,
+                      map_alpha=ALPHA, cfl_max=1.0)
+    ps.set_interior(q)
+    o = O.Oracle(L, mx=mx, velocity="swirl", vel_params=(1.0, 0.0, 0.0), lmin=1, lmax=3, map_alpha=ALPHA)
+    o.set_interior(q)
+    dt0 = 0.9 / (mx << 1)  # Courant number 0.9 on the Cartesian grid
+    t_end = 0.05
+    dt_g, acc_g, rej_g = ps.advance_adaptive(t_end, dt0, 0.9, "per_level")
+    t_o, dt_o, acc_o, rej_o = oracle_adaptive(o, t_end, dt0, 0.9, 1.0)
+    ps.check()
+    assert ps.time == t_end and t_o == t_end
+    assert rej_g == rej_o >= 1 and acc_g == acc_o >= 3
+    assert abs(dt_g - dt_o) <= 1e-12 * dt_o
+    assert rel(ps.interior(), o.interior()) <= TOL
