@@ -370,7 +370,7 @@ def mapped_workload(args):
                    "threads_per_patch": nt, "max_courant": float(cfl.item())},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": (ratio * bpl) if ratio else None,
-                     "kernel": "advance_mapped_kernel<%d,%d>" % (mx, nt), "bytes_per_launch": bpl,
+                     "kernel": "advance_mapped_kernel<%d,%d,false>" % (mx, nt), "bytes_per_launch": bpl,
                      "avg_launch_ms": 1e3 * adv_s / steps, "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
         "fill": {"avg_launch_ms": 1e3 * fill_s / steps},
     }

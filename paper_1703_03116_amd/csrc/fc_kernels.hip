@@ -1246,10 +1246,12 @@ __device__ __forceinline__ void mapped_sweeps(MappedSmem<MX> &s, int tid, bool x
 }
 
 // One capacity-form step of patch p (level lev, or its own if lev < 0) on
-// its filled tile; the work split is the Cartesian step's.
-template <int MX, int NT>
+// its filled tile, or (FUSED) with its ghost values gathered from the
+// neighbours' interiors (area-weighted averages); the work split is the
+// Cartesian step's.  tdev: if given, the step starts at *tdev + t.
+template <int MX, int NT, bool FUSED = false>
 __device__ void advance_mapped_patch(const Ctx &c, const View &w, MappedSmem<MX> &s, int p, int lev, double t,
-                                     double dt, double &cfl) {
+                                     double dt, double &cfl, const double *tdev = nullptr) {
     constexpr int N = MX + 2 * MB, NP = ScalarSmem<MX>::NP;
     constexpr int SEG = scalar_seg<MX, NT>(), NSEG = MX / SEG, NI = MX * NSEG, HI = NI / 2;
     constexpr int SO = 2, NO = 4 * (MX / SO);
@@ -1264,12 +1266,29 @@ __device__ void advance_mapped_patch(const Ctx &c, const View &w, MappedSmem<MX>
     const double *in = buf_of(c, w, l);
     double *out = other_of(c, w, l);
     const size_t base = (size_t)p * N * N;
-    load_velocity<MX>(c, s, l, P.ix * MX, P.iy * MX, t, dt, nullptr, NI);
-    for (int k = tid; k < N * N / 2; k += NT) {
-        const int i = 2 * (k % (N / 2)), j = k / (N / 2);
-        const double2 v = *reinterpret_cast<const double2 *>(&in[base + j * N + i]);
-        s.q[j * NP + i] = v.x;
-        s.q[j * NP + i + 1] = v.y;
+    load_velocity<MX>(c, s, l, P.ix * MX, P.iy * MX, t, dt, tdev, NI);
+    if constexpr (FUSED) {
+        constexpr int NG = N * N - MX * MX;
+        for (int k = tid; k < MX * MX / 2; k += NT) {
+            const int i = 2 * (k % (MX / 2)), j = k / (MX / 2);
+            const double2 v = *reinterpret_cast<const double2 *>(&in[base + (j + MB) * N + i + MB]);
+            s.q[(j + MB) * NP + i + MB] = v.x;
+            s.q[(j + MB) * NP + i + MB + 1] = v.y;
+        }
+        for (int g = tid; g < NG; g += NT) {
+            int i, j;
+            ghost_index<MX>(g, i, j);
+            double val[1];
+            ghost_cell<MX, 1, true>(c, w, p, i, j, val);
+            s.q[(j + MB) * NP + i + MB] = val[0];
+        }
+    } else {
+        for (int k = tid; k < N * N / 2; k += NT) {
+            const int i = 2 * (k % (N / 2)), j = k / (N / 2);
+            const double2 v = *reinterpret_cast<const double2 *>(&in[base + j * N + i]);
+            s.q[j * NP + i] = v.x;
+            s.q[j * NP + i + 1] = v.y;
+        }
     }
     for (int d = tid; d < 2 * N - 1; d += NT) {
         int k = (P.ix * MX + P.iy * MX + d - 2 * MB + 1) % n;
@@ -1325,7 +1344,7 @@ __device__ void advance_mapped_patch(const Ctx &c, const View &w, MappedSmem<MX>
     cfl = fmax(cfl, __longlong_as_double((long long)s.mcfl));
 }
 
-template <int MX, int NT>
+template <int MX, int NT, bool FUSED>
 __global__ void __launch_bounds__(NT) advance_mapped_kernel(Ctx c, int first, int count, int level, double t,
                                                             double dt) {
     __shared__ MappedSmem<MX> s;
@@ -1334,7 +1353,7 @@ __global__ void __launch_bounds__(NT) advance_mapped_kernel(Ctx c, int first, in
     const double old = cfl_slot_old(slot);
     double cfl = 0.0;
     const View w = view_of(c);
-    advance_mapped_patch<MX, NT>(c, w, s, p, level, t, dt, cfl);
+    advance_mapped_patch<MX, NT, FUSED>(c, w, s, p, level, t, dt, cfl);
     store_cfl_slot(slot, old, cfl);
 }
 
@@ -1913,6 +1932,8 @@ template <int MX, int EQ>
 struct SmemOf { using type = ScalarSmem<MX>; };
 template <int MX>
 struct SmemOf<MX, 1> { using type = SweSmem<MX>; };
+template <int MX>
+struct SmemOf<MX, 2> { using type = MappedSmem<MX>; };  // scalar advection on a mapped grid
 
 template <int MX, int NT, int EQ>
 __global__ void __launch_bounds__(NT, (min_waves<MX, NT, EQ>())) persistent_kernel(Ctx c, const SchedEntry *sched, int nsched,
@@ -1990,6 +2011,10 @@ __global__ void __launch_bounds__(NT, (min_waves<MX, NT, EQ>())) level_step_kern
         advance_scalar_patch<MX, NT, true, SEGC>(c, w, s, p, a.level, a.off * a.dtc, dt, cfl, &st->ts[a.cidx],
                                                  c.cflp + p);
         store_cfl_slot(c.cflp + p, s.red[15], cfl);
+    } else if constexpr (EQ == 2) {
+        const double old = cfl_slot_old(c.cflp + p);
+        advance_mapped_patch<MX, NT, true>(c, w, s, p, a.level, a.off * a.dtc, dt, cfl, &st->ts[a.cidx]);
+        store_cfl_slot(c.cflp + p, old, cfl);
     } else {
         const double old = cfl_slot_old(c.cflp + p);
         advance_swe_patch<MX, NT, true>(c, w, s, p, dt, cfl);
@@ -2449,11 +2474,13 @@ hipError_t launch_advance(const Ctx &c, LaunchCfg lc, int level, int first, int 
                           int fused, hipStream_t s) {
     if (count <= 0) return hipSuccess;
     if (c.mapped) {
-        // capacity form on filled patches only (fused == 0)
-        if (fused) return hipErrorInvalidValue;
+        // capacity form (fused: ghosts gathered, area-weighted)
 #define ADM(MXV, NTV)                                                                                              \
     if (lc.mx == MXV && lc.nt == NTV) {                                                                            \
-        hipLaunchKernelGGL((advance_mapped_kernel<MXV, NTV>), dim3(count), dim3(NTV), 0, s, c, first, count, level, t, dt); \
+        if (fused)                                                                                                 \
+            hipLaunchKernelGGL((advance_mapped_kernel<MXV, NTV, true>), dim3(count), dim3(NTV), 0, s, c, first, count, level, t, dt); \
+        else                                                                                                       \
+            hipLaunchKernelGGL((advance_mapped_kernel<MXV, NTV, false>), dim3(count), dim3(NTV), 0, s, c, first, count, level, t, dt); \
         return hipGetLastError();                                                                                  \
     }
         ADM(8, 64) ADM(8, 128) ADM(16, 64) ADM(16, 128) ADM(16, 256) ADM(32, 128) ADM(32, 256) ADM(32, 512)
@@ -2522,6 +2549,8 @@ static const void *level_step_select(LaunchCfg lc, int eq) {
     PS(8, 64, 0) PS(8, 128, 0) PS(16, 64, 0) PS(16, 128, 0) PS(16, 256, 0) PS(32, 128, 0) PS(32, 256, 0) PS(32, 512, 0)
     PS(8, 64, 1) PS(8, 128, 1) PS(8, 192, 1) PS(16, 256, 1) PS(16, 384, 1) PS(16, 512, 1) PS(16, 640, 1)
     PL(16, 128, 8) PL(16, 256, 8) PL(32, 256, 16) PL(32, 512, 8)
+    // eq 2: scalar advection on a mapped grid (capacity form)
+    PS(8, 64, 2) PS(8, 128, 2) PS(16, 64, 2) PS(16, 128, 2) PS(16, 256, 2) PS(32, 128, 2) PS(32, 256, 2) PS(32, 512, 2)
 #undef PL
 #undef PS
     return nullptr;
@@ -2529,7 +2558,7 @@ static const void *level_step_select(LaunchCfg lc, int eq) {
 
 hipError_t launch_level_step(const Ctx &c, LaunchCfg lc, const SchedEntry &e, int first, int count, int cidx,
                              uint32_t mask, double dt_coarse, DevState *st, hipStream_t s) {
-    const void *fn = level_step_select(lc, c.eq);
+    const void *fn = level_step_select(lc, c.mapped ? 2 : c.eq);
     if (!fn) return hipErrorInvalidValue;
     Ctx cc = c;
     StepArgs a{e.level, first, count, cidx, mask, 0u, e.off, e.scale, e.alpha, dt_coarse};

@@ -959,8 +959,9 @@ fc_status fc_prepare_steps(fc_patchstore *ps, double dt_coarse, int32_t nsteps, 
     fc_status r = check_bound(ps);
     if (r != FC_OK) return r;
     if (!(dt_coarse > 0) || nsteps < 0) return fail(FC_ERR_ARG, "bad step arguments");
-    if (ps->cfg.map_alpha != 0.0 && mode != FC_MODE_PER_LEVEL)
-        return fail(FC_ERR_ARG, "a mapped grid steps in FC_MODE_PER_LEVEL only");
+    if (ps->cfg.map_alpha != 0.0 && (mode == FC_MODE_FUSED || mode == FC_MODE_PERSISTENT_GRAPH))
+        return fail(FC_ERR_ARG, "a mapped grid has no persistent kernel: use FC_MODE_PER_LEVEL, FC_MODE_FUSED_LEVELS "
+                                "or FC_MODE_FUSED_GRAPH");
     if (mode == FC_MODE_PER_LEVEL || mode == FC_MODE_FUSED_LEVELS || mode == FC_MODE_FUSED) return FC_OK;
     if (mode != FC_MODE_FUSED_GRAPH && mode != FC_MODE_PERSISTENT_GRAPH) return fail(FC_ERR_ARG, "unknown mode");
     if (ps->pgrid <= 0) return fail(FC_ERR_HIP, "persistent kernel has no resident blocks");
@@ -983,8 +984,9 @@ static fc_status advance_steps(fc_patchstore *ps, double dt_coarse, int32_t nste
     fc_status r = check_bound(ps);
     if (r != FC_OK) return r;
     if (!(dt_coarse > 0) || nsteps < 0) return fail(FC_ERR_ARG, "bad step arguments");
-    if (ps->cfg.map_alpha != 0.0 && mode != FC_MODE_PER_LEVEL)
-        return fail(FC_ERR_ARG, "a mapped grid steps in FC_MODE_PER_LEVEL only");
+    if (ps->cfg.map_alpha != 0.0 && (mode == FC_MODE_FUSED || mode == FC_MODE_PERSISTENT_GRAPH))
+        return fail(FC_ERR_ARG, "a mapped grid has no persistent kernel: use FC_MODE_PER_LEVEL, FC_MODE_FUSED_LEVELS "
+                                "or FC_MODE_FUSED_GRAPH");
     const bool cfl = cfl_dev != nullptr;
     const double cmax = flag_cfl ? ps->cfg.cfl_max : 0.0;
     const int nleaf = (int)ps->mesh.lv.size();
