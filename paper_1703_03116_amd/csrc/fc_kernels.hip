@@ -1057,7 +1057,7 @@ __device__ void reduce_cfl_slot(double v, double *red, unsigned long long *slot,
 // and accumulators take 68 KB).
 template <int MX, int NT, int EQ>
 constexpr int min_waves() {
-    if (EQ == 0 && MX == 32) {
+    if ((EQ == 0 || EQ == 2) && MX == 32) {  // 2: the mapped grid's capacity form (30.4 KB)
         const int w = (5 * NT / 64 + 3) / 4;
         return w < 8 ? w : 8;
     }
@@ -1124,11 +1124,10 @@ __device__ __forceinline__ void msweep_side(MappedSmem<MX> &s, int line, int e0,
     const double *ve = DIR == 0 ? &s.ux[e0] : &s.vy[e0];
     const double vl = DIR == 0 ? s.uy[line + 1] : s.vx[line + 1];
     const double *lk = &s.dk[line + e0 - 1 + 2 * MB];  // lk[k]: cell e0 - 1 + k of the line
-    double q[SEG + 4], L[SEG + 2];
+    double q[SEG + 4];
 #pragma unroll
     for (int k = 0; k < SEG + 4; k++) q[k] = qp[k * STR];
-#pragma unroll
-    for (int k = 0; k < SEG + 2; k++) L[k] = lk[k];
+    const double *L = lk;  // read where used: held in registers they cost the fifth workgroup per CU
     double aprev = 0.0, cprev = 0.0;
 #pragma unroll
     for (int k = 0; k <= SEG; k++) {  // edge e0 + k, between cells e0+k-1 (q[k+1], L[k]) and e0+k (q[k+2], L[k+1])
@@ -1345,8 +1344,8 @@ __device__ void advance_mapped_patch(const Ctx &c, const View &w, MappedSmem<MX>
 }
 
 template <int MX, int NT, bool FUSED>
-__global__ void __launch_bounds__(NT) advance_mapped_kernel(Ctx c, int first, int count, int level, double t,
-                                                            double dt) {
+__global__ void __launch_bounds__(NT, (min_waves<MX, NT, 0>())) advance_mapped_kernel(Ctx c, int first, int count,
+                                                                                      int level, double t, double dt) {
     __shared__ MappedSmem<MX> s;
     const int p = first + xcd_remap(blockIdx.x, count);
     unsigned long long *slot = c.cflp ? c.cflp + p : nullptr;
