@@ -99,9 +99,8 @@ typedef struct {
                               |alpha| < 1/(2 pi); 0: Cartesian.  Non-zero needs
                               one periodic block and scalar advection; steps
                               then take the capacity form (cell areas kappa h^2)
-                              in the per-level and ghost-gathering forms (not the
-                              persistent kernel), and averages from fine to
-                              coarse cells are area-weighted                 */
+                              in every execution form, and averages from fine
+                              to coarse cells are area-weighted              */
 } fc_config;
 
 typedef struct fc_patchstore fc_patchstore;

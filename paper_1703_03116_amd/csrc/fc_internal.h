@@ -155,6 +155,8 @@ hipError_t launch_advance(const Ctx &c, LaunchCfg lc, int level, int first, int 
 hipError_t launch_persistent(const Ctx &c, LaunchCfg lc, const SchedEntry *sched, int nsched,
                              const LevelRange *ranges_dev, int ncoarse, DevState *state, int grid,
                              hipStream_t s);
+// eq: the kernel kind (0 scalar advection, 1 shallow water, 2 scalar
+// advection on a mapped grid)
 int persistent_max_grid(LaunchCfg lc, int eq);
 // one level-step (schedule entry e over slots [first, first+count), coarse
 // step cidx of a chunk of steps dt_coarse, buffer parities mask), ghosts

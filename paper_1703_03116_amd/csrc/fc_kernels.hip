@@ -1966,6 +1966,7 @@ __global__ void __launch_bounds__(NT, (min_waves<MX, NT, EQ>())) persistent_kern
             const int c0 = (int)((long long)count * x / NXC), c1 = (int)((long long)count * (x + 1) / NXC);
             for (int pi = c0 + r; pi < c1; pi += nbx) {
                 if constexpr (EQ == 0) advance_scalar_patch<MX, NT, true>(c, w, s, first + pi, e.level, t, dt, cfl);
+                else if constexpr (EQ == 2) advance_mapped_patch<MX, NT, true>(c, w, s, first + pi, e.level, t, dt, cfl);
                 else advance_swe_patch<MX, NT, true>(c, w, s, first + pi, dt, cfl);
                 __syncthreads();
             }
@@ -2510,6 +2511,8 @@ static const void *persistent_select(LaunchCfg lc, int eq) {
     if (lc.mx == MXV && lc.nt == NTV && eq == EQV) return reinterpret_cast<const void *>(&persistent_kernel<MXV, NTV, EQV>);
     PS(8, 64, 0) PS(8, 128, 0) PS(16, 64, 0) PS(16, 128, 0) PS(16, 256, 0) PS(32, 128, 0) PS(32, 256, 0) PS(32, 512, 0)
     PS(8, 64, 1) PS(8, 128, 1) PS(8, 192, 1) PS(16, 256, 1) PS(16, 384, 1) PS(16, 512, 1) PS(16, 640, 1)
+    // eq 2: scalar advection on a mapped grid (capacity form)
+    PS(8, 64, 2) PS(8, 128, 2) PS(16, 64, 2) PS(16, 128, 2) PS(16, 256, 2) PS(32, 128, 2) PS(32, 256, 2) PS(32, 512, 2)
 #undef PS
     return nullptr;
 }
@@ -2572,7 +2575,7 @@ hipError_t launch_finish_chunk(DevState *st, int ncoarse, uint32_t flip, hipStre
 
 hipError_t launch_persistent(const Ctx &c, LaunchCfg lc, const SchedEntry *sched, int nsched,
                              const LevelRange *ranges_dev, int ncoarse, DevState *state, int grid, hipStream_t s) {
-    const void *fn = persistent_select(lc, c.eq);
+    const void *fn = persistent_select(lc, c.mapped ? 2 : c.eq);
     if (!fn || grid <= 0 || ncoarse <= 0) return hipErrorInvalidValue;
     Ctx cc = c;
     void *args[] = {&cc, (void *)&sched, &nsched, (void *)&ranges_dev, &ncoarse, &state};

@@ -784,7 +784,7 @@ fc_status fc_patchstore_bind(fc_patchstore *ps, double *q0, double *q1, void *wo
     if (ps->cfg.map_alpha != 0.0)
         for (int l = ps->cfg.min_level; l <= ps->cfg.max_level; l++)
             HIPCHK(launch_init_capacity(ps->mx << l, ps->cfg.map_alpha, (double *)(ps->ws + ps->off_mk[l]), s));
-    ps->pgrid = persistent_max_grid(persistent_cfg(ps), ps->cfg.equation);
+    ps->pgrid = persistent_max_grid(persistent_cfg(ps), ps->cfg.map_alpha != 0.0 ? 2 : ps->cfg.equation);
     HIPCHK(hipStreamSynchronize(s));
     return FC_OK;
 }
@@ -959,9 +959,6 @@ fc_status fc_prepare_steps(fc_patchstore *ps, double dt_coarse, int32_t nsteps, 
     fc_status r = check_bound(ps);
     if (r != FC_OK) return r;
     if (!(dt_coarse > 0) || nsteps < 0) return fail(FC_ERR_ARG, "bad step arguments");
-    if (ps->cfg.map_alpha != 0.0 && (mode == FC_MODE_FUSED || mode == FC_MODE_PERSISTENT_GRAPH))
-        return fail(FC_ERR_ARG, "a mapped grid has no persistent kernel: use FC_MODE_PER_LEVEL, FC_MODE_FUSED_LEVELS "
-                                "or FC_MODE_FUSED_GRAPH");
     if (mode == FC_MODE_PER_LEVEL || mode == FC_MODE_FUSED_LEVELS || mode == FC_MODE_FUSED) return FC_OK;
     if (mode != FC_MODE_FUSED_GRAPH && mode != FC_MODE_PERSISTENT_GRAPH) return fail(FC_ERR_ARG, "unknown mode");
     if (ps->pgrid <= 0) return fail(FC_ERR_HIP, "persistent kernel has no resident blocks");
@@ -984,9 +981,6 @@ static fc_status advance_steps(fc_patchstore *ps, double dt_coarse, int32_t nste
     fc_status r = check_bound(ps);
     if (r != FC_OK) return r;
     if (!(dt_coarse > 0) || nsteps < 0) return fail(FC_ERR_ARG, "bad step arguments");
-    if (ps->cfg.map_alpha != 0.0 && (mode == FC_MODE_FUSED || mode == FC_MODE_PERSISTENT_GRAPH))
-        return fail(FC_ERR_ARG, "a mapped grid has no persistent kernel: use FC_MODE_PER_LEVEL, FC_MODE_FUSED_LEVELS "
-                                "or FC_MODE_FUSED_GRAPH");
     const bool cfl = cfl_dev != nullptr;
     const double cmax = flag_cfl ? ps->cfg.cfl_max : 0.0;
     const int nleaf = (int)ps->mesh.lv.size();
@@ -1407,7 +1401,7 @@ fc_status fc_set_variant(fc_patchstore *ps, int32_t threads_per_patch) {
         return fail(FC_ERR_ARG, "unsupported threads per patch for this mx");
     ps->nt = threads_per_patch;
     ps->seg = 0;
-    if (ps->ws) ps->pgrid = persistent_max_grid(persistent_cfg(ps), ps->cfg.equation);
+    if (ps->ws) ps->pgrid = persistent_max_grid(persistent_cfg(ps), ps->cfg.map_alpha != 0.0 ? 2 : ps->cfg.equation);
     drop_graph(ps);
     return FC_OK;
 }

@@ -224,13 +224,14 @@ def test_mapped_coarsening_is_area_weighted(B, O):
     assert abs(y.mean() - want) > 1e-6
 
 
-@pytest.mark.parametrize("mode", ["graph", "fused_levels"])
+@pytest.mark.parametrize("mode", ["graph", "fused_levels", "fused", "persistent_graph"])
 @pytest.mark.parametrize("mx,lmin,lmax", CASES)
 def test_mapped_gathering_forms_match_per_level(B, O, mode, mx, lmin, lmax):
-    """The ghost-gathering forms (one capacity-form kernel per level-step that
-    gathers its ghosts, area-weighted averages included; launched from the
-    host or replayed from a graph) give the per-level form's bits, and the
-    oracle's values, over multirate steps."""
+    """The ghost-gathering forms (a capacity-form kernel that gathers its
+    ghosts, area-weighted averages included: one per level-step, launched from
+    the host or replayed from a graph, or the persistent kernel walking the
+    schedule) give the per-level form's bits, and the oracle's values, over
+    multirate steps."""
     L = S.random_balanced_leaves(6, lmin, lmax) if lmin > 0 else \
         S.refine_leaves(S.refine_leaves(S.uniform_leaves(0), [0]), [0, 3])
     q = S.sample_on_leaves(hump, L, mx)
@@ -252,20 +253,13 @@ def test_mapped_gathering_forms_match_per_level(B, O, mode, mx, lmin, lmax):
 
 
 def test_mapped_store_rejects_other_forms(B, O):
-    """The capacity form has no persistent kernel: the persistent forms, the
-    uniform-level step and the adjoint refuse a mapped store with FC_ERR_ARG,
-    leaving the data untouched; the tuner picks one of the capacity-form
-    kernel's own variants."""
+    """The uniform-level step and the adjoint are Cartesian: they refuse a
+    mapped store with FC_ERR_ARG, leaving the data untouched; the tuner picks
+    one of the capacity-form kernel's own variants."""
     mx = 16
     L = S.uniform_leaves(1)
     q = np.random.default_rng(2).random((len(L), 1, mx, mx))
     ps, _ = mapped_pair(B, O, L, mx, q)
-    for mode in ("fused", "persistent_graph"):
-        with pytest.raises(B.FcError) as e:
-            ps.coarse_steps(0.01, 1, mode)
-        assert e.value.status == -1
-        with pytest.raises(B.FcError):
-            ps.prepare_steps(0.01, 1, "persistent_graph")
     qt = torch.as_tensor(q, device="cuda")
     with pytest.raises(B.FcError):
         ps.step_uniform(1, 0.0, 0.01, qt)
