@@ -636,6 +636,18 @@ fc_status capture_levels(fc_patchstore *ps, fc_patchstore::Graph &out, int ncoar
     int nall = 0;
     for (int l = 0; l < FC_MAXLEV; l++)
         if (ps->lr.count[l] > 0) { allmask |= 1u << l; nall += ps->lr.count[l]; }
+    // A level-step of at most four patches per CU runs in one round of
+    // workgroups, so its time is one workgroup's latency: scalar advection on
+    // 32x32 Cartesian patches takes it with 512 threads per patch (shorter
+    // segments, twice the waves; measured 7.1-9.5 us against 8.1-11.2 us
+    // for 256 threads over 1-1023 patches) and keeps the chosen variant for
+    // larger levels.  Every variant gives the same bits.
+    const LaunchCfg lc{ps->mx, ps->nt, ps->seg}, lc_small{ps->mx, 512, 0};
+    int cus = 0, dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 0;
+    const bool small_ok = ps->mx == 32 && ps->cfg.equation == FC_EQ_ADVECTION && ps->cfg.map_alpha == 0.0;
     HIPCHK(hipStreamBeginCapture(ps->cap_stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
     uint32_t flip = 0;
@@ -644,8 +656,9 @@ fc_status capture_levels(fc_patchstore *ps, fc_patchstore::Graph &out, int ncoar
             const SchedEntry &en = ps->sched[k];
             const int first = en.level < 0 ? 0 : ps->lr.start[en.level];
             const int cnt = en.level < 0 ? nall : ps->lr.count[en.level];
-            if (cnt > 0) e = launch_level_step(c, LaunchCfg{ps->mx, ps->nt, ps->seg}, en, first, cnt, cs, mask ^ flip, dtc,
-                                               dstate(ps), ps->cap_stream);
+            if (cnt > 0)
+                e = launch_level_step(c, (small_ok && cnt <= 4 * cus) ? lc_small : lc, en, first, cnt, cs, mask ^ flip,
+                                      dtc, dstate(ps), ps->cap_stream);
             flip ^= en.level < 0 ? allmask : (1u << en.level);
         }
     if (e == hipSuccess) e = launch_finish_chunk(dstate(ps), ncoarse, flip, ps->cap_stream);
