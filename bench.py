@@ -443,7 +443,7 @@ def amr_workload(args):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": (ratio * bpl) if ratio else None,
                      "kernel": level_step_name(32, nt, seg), "small_level_kernel": level_step_name(32, 512, 0),
-                     "small_level_patches": "at most 4 per CU", "launches": g["launches"],
+                     "small_level_patches": "at most 4 per CU, on levels that are not complete", "launches": g["launches"],
                      "bytes_per_launch": bpl, "avg_launch_ms": 1e3 * g["advance_s"] / g["launches"],
                      "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
         "per_level": per_level,

@@ -637,11 +637,15 @@ fc_status capture_levels(fc_patchstore *ps, fc_patchstore::Graph &out, int ncoar
     for (int l = 0; l < FC_MAXLEV; l++)
         if (ps->lr.count[l] > 0) { allmask |= 1u << l; nall += ps->lr.count[l]; }
     // A level-step of at most four patches per CU runs in one round of
-    // workgroups, so its time is one workgroup's latency: scalar advection on
-    // 32x32 Cartesian patches takes it with 512 threads per patch (shorter
-    // segments, twice the waves; measured 7.1-9.5 us against 8.1-11.2 us
-    // for 256 threads over 1-1023 patches) and keeps the chosen variant for
-    // larger levels.  Every variant gives the same bits.
+    // workgroups, so its time is one workgroup's latency.  On a level that is
+    // not complete (ghosts through neighbour records: two dependent loads,
+    // coarse-fine averages and interpolations) scalar advection on 32x32
+    // Cartesian patches takes it with 512 threads per patch (fewer ghost
+    // cells per thread, twice the waves; measured 7.1-9.5 us against
+    // 8.1-11.2 us for 256 threads over 1-1023 patches); a complete level
+    // (one round of loads) and larger levels keep the chosen variant (a
+    // complete level of 1024 patches: 9.8 us with 512 threads, 8.7 us with
+    // 256).  Every variant gives the same bits.
     const LaunchCfg lc{ps->mx, ps->nt, ps->seg}, lc_small{ps->mx, 512, 0};
     int cus = 0, dev = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -657,8 +661,10 @@ fc_status capture_levels(fc_patchstore *ps, fc_patchstore::Graph &out, int ncoar
             const int first = en.level < 0 ? 0 : ps->lr.start[en.level];
             const int cnt = en.level < 0 ? nall : ps->lr.count[en.level];
             if (cnt > 0)
-                e = launch_level_step(c, (small_ok && cnt <= 4 * cus) ? lc_small : lc, en, first, cnt, cs, mask ^ flip,
-                                      dtc, dstate(ps), ps->cap_stream);
+                e = launch_level_step(c,
+                                      (small_ok && cnt <= 4 * cus && !(en.level >= 0 && ((c.complete >> en.level) & 1u)))
+                                          ? lc_small : lc,
+                                      en, first, cnt, cs, mask ^ flip, dtc, dstate(ps), ps->cap_stream);
             flip ^= en.level < 0 ? allmask : (1u << en.level);
         }
     if (e == hipSuccess) e = launch_finish_chunk(dstate(ps), ncoarse, flip, ps->cap_stream);
