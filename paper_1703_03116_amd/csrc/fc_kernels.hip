@@ -1702,15 +1702,18 @@ struct AdjSmem {
     static constexpr int NQ = MX + 6, QP = NQ + 1;  // q, three ghost layers (corners unused)
     static constexpr int NL = MX + 4, LP = NL + 1;  // lambda_in, two ghost layers
     double q[NQ * QP];
-    double l[NL * LP];
-    double part[MX * (MX + 1)];  // L + row part of each interior cell
+    double l[NL * LP];  // after the sweeps, the interior takes L + the row part of each cell
     // velocity factors (the forward step's): x-edge e -> ue[e + 1], row j ->
     // uc[j + 2]; y-edge e -> ve[e + 1], column i -> vc[i + 2]
     double ue[MX + 3], uc[MX + 4], ve[MX + 3], vc[MX + 4];
 };
 
 // One segment of one line: cells e0 .. e0+SEG-1 of row `line` (DIR 0) or
-// column `line` (DIR 1).  Returns D(i) - D(i+1) of each cell.
+// column `line` (DIR 1).  Returns D(i) - D(i+1) of each cell.  The edges
+// e0-1 .. e0+SEG+1 are walked in order with a window of three differences W,
+// two cells (L, Tbar) and the last two edges' (g, h, upwind side), so that
+// few values are live at once: D of an edge is complete once the edge after
+// it has its h.
 template <int MX, int SEG, int LIM, int DIR>
 __device__ __forceinline__ void adjoint_line(const AdjSmem<MX> &s, int line, int e0, double lam, double (&R)[SEG]) {
     using A = AdjSmem<MX>;
@@ -1723,57 +1726,61 @@ __device__ __forceinline__ void adjoint_line(const AdjSmem<MX> &s, int line, int
     const double fup = DIR == 0 ? s.ve[line + 2] : s.ue[line + 2];  // transverse edge line + 1/2
     const double fdn = DIR == 0 ? s.ve[line + 1] : s.ue[line + 1];  // transverse edge line - 1/2
     const double hl = 0.5 * lam, hl2 = 0.5 * lam * lam;
-    // w[k] = W(e0 - 2 + k) from q(e0 - 3 .. e0 + SEG + 2)
-    double w[SEG + 5];
-    {
-        double q[SEG + 6];
-#pragma unroll
-        for (int k = 0; k < SEG + 6; k++) q[k] = qp[(e0 - 3 + k) * SQ];
-#pragma unroll
-        for (int k = 0; k < SEG + 5; k++) w[k] = q[k + 1] - q[k];
-    }
-    // L(i) and Tbar(i), i = e0 - 2 + k
-    double lv[SEG + 4], tb[SEG + 4];
-#pragma unroll
-    for (int k = 0; k < SEG + 4; k++) {
+    // window cell k is cell e0 - 2 + k: its L and Tbar
+    auto cell = [&](int k, double &L, double &T) {
         const double *lc = lp + (e0 - 2 + k) * SL;
-        const double L = lc[0], Lu = lc[XL], Ld = lc[-XL];
+        const double Lc = lc[0], Lu = lc[XL], Ld = lc[-XL];
         const double cf = ca[e0 - 2 + k];
-        lv[k] = L;
-        tb[k] = hl2 * (posp(fup * cf) * (L - Lu) + negp(fdn * cf) * (Ld - L)) - lam * L;
-    }
-    // edges e = e0 - 1 + m
-    double g[SEG + 3], h[SEG + 3];
-    bool up[SEG + 3];
+        L = Lc;
+        T = hl2 * (posp(fup * cf) * (Lc - Lu) + negp(fdn * cf) * (Ld - Lc)) - lam * Lc;
+    };
+    // q at cell e0 - 3 + k; W(k) = q(k + 1) - q(k) is the difference at edge e0 - 2 + k
+    auto qv = [&](int k) { return qp[(e0 - 3 + k) * SQ]; };
+    const double q0 = qv(0), q1 = qv(1);
+    double q2 = qv(2);
+    double wm = q1 - q0, w0 = q2 - q1;  // W at edges m - 1 and m (window edge m is edge e0 - 1 + m)
+    double L0, T0;
+    cell(0, L0, T0);
+    double g1 = 0.0, h1 = 0.0, h2 = 0.0, D1 = 0.0;  // the previous edge's g, h; the one before's h
+    bool up1 = false, up2 = false;
 #pragma unroll
     for (int m = 0; m < SEG + 3; m++) {
+        const double q3 = qv(m + 3);
+        const double wp = q3 - q2;  // W at edge m + 1
+        double L1, T1;
+        cell(m + 1, L1, T1);
+        // edge m: between window cells m and m + 1
         const double u = ea[e0 - 1 + m] * lf;
-        up[m] = u > 0.0;
-        const double W = w[m + 1];
-        const double Wu = up[m] ? w[m] : w[m + 2];
-        const double tr = tb[m + 1], tl = tb[m];
+        const bool up = u > 0.0;
+        const double W = w0;
+        const double Wu = up ? wm : wp;
+        const double tr = T1, tl = T0;
         const double au = fabs(u);
-        const double wb = (au * (1.0 - lam * au)) * (hl * (lv[m] - lv[m + 1]) - tr + tl);
+        const double wb = (au * (1.0 - lam * au)) * (hl * (L0 - L1) - tr + tl);
         double dW, dWu;
         limiter_partials<LIM>(W, Wu, dW, dWu);
-        g[m] = posp(u) * tr + negp(u) * tl + dW * wb;
-        h[m] = dWu * wb;
+        const double g = posp(u) * tr + negp(u) * tl + dW * wb;
+        const double h = dWu * wb;
+        if (m >= 2) {  // D of edge m - 1 (cell boundary e0 + m - 2)
+            const double D = g1 + (up ? h : 0.0) + (up2 ? 0.0 : h2);
+            if (m >= 3) R[m - 3] = D1 - D;
+            D1 = D;
+        }
+        h2 = h1; up2 = up1;
+        g1 = g; h1 = h; up1 = up;
+        wm = w0; w0 = wp; q2 = q3;
+        L0 = L1; T0 = T1;
     }
-    double D[SEG + 1];
-#pragma unroll
-    for (int k = 0; k <= SEG; k++) {  // edge e0 + k
-        const int m = k + 1;
-        D[k] = g[m] + (up[m + 1] ? h[m + 1] : 0.0) + (up[m - 1] ? 0.0 : h[m - 1]);
-    }
-#pragma unroll
-    for (int k = 0; k < SEG; k++) R[k] = D[k] - D[k + 1];
 }
 
 template <int MX, int NT>
 constexpr int adj_seg() { return (2 * MX * MX / NT) < 4 ? 4 : 2 * MX * MX / NT; }
 
+// mx = 32: the tiles of q and lambda_in (23.1 KB) admit six workgroups per CU,
+// and the register budget is set for all six (five for minmod, whose
+// partials take a few more registers)
 template <int MX, int NT, int LIM>
-__global__ void __launch_bounds__(NT, (MX == 32 ? 4 : 1)) adjoint_kernel(Ctx c, int level, int first, int count,
+__global__ void __launch_bounds__(NT, (MX == 32 ? (LIM == 3 ? 5 : 6) : 1)) adjoint_kernel(Ctx c, int level, int first, int count,
                                                                          double t, double dt,
                                                                          const int32_t *leaf_of_slot,
                                                                          const double *q_in, const double *lam_in,
@@ -1875,21 +1882,23 @@ __global__ void __launch_bounds__(NT, (MX == 32 ? 4 : 1)) adjoint_kernel(Ctx c, 
         if (tid + v * NT < NG2) s.l[(rj[v] + 2) * A::LP + ri[v] + 2] = rv[v];
     __syncthreads();
     double R[SEG];
-    if (tid < NI) {  // rows: L + row part into LDS
-        const int j = tid % MX, e0 = (tid / MX) * SEG;
-        adjoint_line<MX, SEG, LIM, 0>(s, j, e0, lam, R);
+    const int j = tid % MX, e0 = (tid / MX) * SEG;  // rows
+    const int k0 = tid - NI, i = k0 % MX, c0 = (k0 / MX) * SEG;  // columns
+    if (tid < NI) adjoint_line<MX, SEG, LIM, 0>(s, j, e0, lam, R);
+    else if (tid < 2 * NI) adjoint_line<MX, SEG, LIM, 1>(s, i, c0, lam, R);
+    __syncthreads();
+    // rows: L + row part into the interior of lambda_in's tile (no sweep reads
+    // it any more; one row item per cell), held in registers over the barrier
+    if (tid < NI) {
+        double *lr = &s.l[(j + 2) * A::LP + e0 + 2];
 #pragma unroll
-        for (int k = 0; k < SEG; k++) s.part[j * (MX + 1) + e0 + k] = s.l[(j + 2) * A::LP + e0 + k + 2] + R[k];
-    } else if (tid < 2 * NI) {
-        const int k0 = tid - NI;
-        adjoint_line<MX, SEG, LIM, 1>(s, k0 % MX, (k0 / MX) * SEG, lam, R);
+        for (int k = 0; k < SEG; k++) lr[k] = lr[k] + R[k];
     }
     __syncthreads();
     if (tid >= NI && tid < 2 * NI) {  // columns finish the cells (a row of lanes per store)
-        const int k0 = tid - NI, i = k0 % MX, e0 = (k0 / MX) * SEG;
         double *lo = lam_out + (size_t)leaf_of_slot[p] * PS;
 #pragma unroll
-        for (int k = 0; k < SEG; k++) lo[(e0 + k) * MX + i] = s.part[(e0 + k) * (MX + 1) + i] + R[k];
+        for (int k = 0; k < SEG; k++) lo[(c0 + k) * MX + i] = s.l[(c0 + k + 2) * A::LP + i + 2] + R[k];
     }
 }
 
