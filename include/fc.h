@@ -350,7 +350,11 @@ fc_status fc_autotune(fc_patchstore *ps, int32_t *threads_out, void *stream);
  * mx = 8; 64, 128 or 256 at mx = 16; 128, 256 or 512 at mx = 32.  Shallow
  * water: 64, 128 or 192 at mx = 8; 256, 384, 512 or 640 at mx = 16 (a
  * mapped grid: those of scalar advection).  FC_ERR_ARG otherwise.  Resets the
- * tile shape to the default.  Drops captured graphs. */
+ * tile shape to the default.  Drops captured graphs.  Whatever the variant,
+ * FC_MODE_FUSED_GRAPH steps a level of scalar advection on 32x32 Cartesian
+ * patches that is not complete and holds at most four patches per CU with
+ * 512 threads per patch (one round of workgroups, so one workgroup's latency
+ * decides; the same bits). */
 fc_status fc_set_variant(fc_patchstore *ps, int32_t threads_per_patch);
 /* Tile shape of the scalar edge sweeps (Cartesian grid): every interior
  * line is cut into segments of seg_cells cells, one per work item.  0 (or
