@@ -649,8 +649,10 @@ fc_status capture_levels(fc_patchstore *ps, fc_patchstore::Graph &out, int ncoar
     const LaunchCfg lc{ps->mx, ps->nt, ps->seg}, lc_small{ps->mx, 512, 0};
     int cus = 0, dev = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-        cus = 0;
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        cus = 0;  // no small-level variant
+        (void)hipGetLastError();
+    }
     const bool small_ok = ps->mx == 32 && ps->cfg.equation == FC_EQ_ADVECTION && ps->cfg.map_alpha == 0.0;
     HIPCHK(hipStreamBeginCapture(ps->cap_stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipSuccess;
